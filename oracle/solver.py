@@ -1,0 +1,220 @@
+"""Multigrid hierarchy, V-cycle and the outer loops (oracle).
+
+* Algorithm 1 / Sect. 3.1: multiplicative V(mu_pre, mu_post) cycles with damped
+  point Jacobi, u <- u + omega diag(A)^-1 (b - A u), out of place.
+* Sect. 3.3: coarse operators A_{l-1} = P^T A_l P (Galerkin and BoxMG) or the
+  rediscretisation (geometric); the coarsest level moves up when a Galerkin
+  operator fails the diagonal check.
+* Results section ("/e"): an exact coarsest-level solve; otherwise mu_pre+mu_post
+  Jacobi sweeps on the coarsest level.
+
+Readings:
+
+* Regular grids use the correction scheme: r = b - A u, b_{l-1} = P^T r,
+  u_{l-1} = 0, recurse, u += P u_{l-1}.  For Galerkin operators this produces the
+  same iterates as the paper's FAS/HTMG form (A_{l-1} I u cancels R A P I u), and
+  for rediscretised coarse operators it equals classic FAS, which keeps the fine
+  solution a fixed point.
+* The coarsest level is solved exactly when it has at most COARSE_DIRECT_MAX
+  unknowns, otherwise by mu_pre + mu_post Jacobi sweeps from zero.
+* The relative residual is the unweighted 2-norm over interior unknowns relative
+  to ||b||_2 (the paper reduces ||r||_2 by 1e8).
+* Mixed precision (not in the paper): an FP64 defect-correction loop
+  x += V32(fp32(b - A x)) whose inner V-cycles run in FP32 on operators rebuilt
+  from quantised hierarchical deltas (see ``store``); the coarsest solve of the
+  inner cycle stays in FP64.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Optional
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .fem import (geometric_stencil, stencil_to_csr, csr_to_stencil, coarsen_eps)
+from .transfer import dlinear_P, boxmg_P
+from .galerkin import rap, definiteness_violations
+from .store import quantise, delta_zero, EPS_ZERO
+
+COARSE_DIRECT_MAX = 1024
+
+
+class IndefiniteError(RuntimeError):
+    """Every Galerkin coarse operator failed the diagonal check."""
+
+
+@dataclasses.dataclass
+class Hierarchy:
+    d: int
+    L: int
+    lc: int
+    transfer: str
+    A: Dict[int, sp.csr_matrix]
+    P: Dict[int, sp.csr_matrix]
+    eps: Dict[int, np.ndarray]
+    omega: float = 0.6
+    mu_pre: int = 2
+    mu_post: int = 2
+    coarse_lu: Optional[tuple] = None
+    dtype: type = np.float64
+
+    def diag(self, l):
+        return self.A[l].diagonal()
+
+
+def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_post=2,
+                    check_definite=True):
+    """Operators of all levels from the finest coefficients (Sect. 3.3, 3.4)."""
+    if transfer not in ("geometric", "galerkin", "boxmg"):
+        raise ValueError(transfer)
+    eps_l = {L: np.asarray(eps, dtype=np.float64)}
+    for l in range(L, 0, -1):
+        eps_l[l - 1] = coarsen_eps(eps_l[l], d)
+    A = {L: stencil_to_csr(geometric_stencil(eps_l[L], d, L), d, L)}
+    P = {}
+    lc_used = lc
+    for l in range(L, lc, -1):
+        if transfer == "boxmg":
+            Pl = boxmg_P(csr_to_stencil(A[l], d, l), d, l)
+        else:
+            Pl = dlinear_P(d, l)
+        if transfer == "geometric":
+            Ac = stencil_to_csr(geometric_stencil(eps_l[l - 1], d, l - 1), d, l - 1)
+        else:
+            Ac = rap(A[l], Pl)
+            if check_definite and len(definiteness_violations(Ac)) > 0:
+                lc_used = l
+                break
+        P[l] = Pl
+        A[l - 1] = Ac
+    if lc_used >= L:
+        raise IndefiniteError("coarsest level would reach the finest level")
+    H = Hierarchy(d, L, lc_used, transfer, A, P, eps_l, omega, mu_pre, mu_post)
+    n_c = A[lc_used].shape[0]
+    if n_c <= COARSE_DIRECT_MAX:
+        H.coarse_lu = sla.lu_factor(A[lc_used].toarray())
+    return H
+
+
+def jacobi(A, diag, u, b, omega):
+    return u + omega * (b - A @ u) / diag
+
+
+def residual(A, u, b):
+    return b - A @ u
+
+
+def vcycle(H, l, u, b):
+    """One V(mu_pre, mu_post) cycle on level l (correction scheme)."""
+    A = H.A[l]
+    dt = H.dtype
+    D = A.diagonal()
+    om = dt(H.omega)
+    if l == H.lc:
+        if H.coarse_lu is not None:
+            return sla.lu_solve(H.coarse_lu, b.astype(np.float64)).astype(dt)
+        for _ in range(H.mu_pre + H.mu_post):
+            u = jacobi(A, D, u, b, om)
+        return u
+    for _ in range(H.mu_pre):
+        u = jacobi(A, D, u, b, om)
+    r = b - A @ u
+    P = H.P[l]
+    bc = (P.T @ r).astype(dt)
+    ec = vcycle(H, l - 1, np.zeros(P.shape[1], dtype=dt), bc)
+    u = u + P @ ec
+    for _ in range(H.mu_post):
+        u = jacobi(A, D, u, b, om)
+    return u
+
+
+def relres(A, u, b):
+    return float(np.linalg.norm(b - A @ u) / np.linalg.norm(b))
+
+
+def solve(H, b, tol=1e-8, max_cycles=100, u0=None, cycles=None):
+    """V-cycles from u0 (default 0) until ||b - A u|| / ||b|| <= tol, or exactly
+    ``cycles`` cycles when given.  Returns (u, history of relres per cycle)."""
+    A = H.A[H.L]
+    u = np.zeros(A.shape[0]) if u0 is None else np.array(u0, dtype=np.float64)
+    hist: List[float] = []
+    n = cycles if cycles is not None else max_cycles
+    for _ in range(n):
+        u = vcycle(H, H.L, u, b)
+        hist.append(relres(A, u, b))
+        if cycles is None and hist[-1] <= tol:
+            break
+    return u, hist
+
+
+def direct_solve(A, b):
+    return spla.spsolve(sp.csc_matrix(A), b)
+
+
+def quantised_hierarchy(H, fmt):
+    """Inner FP32 hierarchy: A_geom(eps_l) + q(A_hat_l) and P_dlin + q(P_hat_l),
+    quantised per vertex as in ``store``; the finest operator is the geometric
+    one (its delta is zero by construction).  Parity unpinned beyond the
+    bound of the outer loop: used only for error-budget studies."""
+    d = H.d
+    A32, P32 = {}, {}
+    for l, Al in H.A.items():
+        G = geometric_stencil(H.eps[l], d, l)
+        if l == H.L:
+            A32[l] = stencil_to_csr(G, d, l).astype(np.float32)
+            continue
+        S = csr_to_stencil(Al, d, l)
+        dlt = S - G
+        q = quantise(dlt, fmt, axis=0)
+        q[:, delta_zero(dlt, G)] = 0.0
+        A32[l] = stencil_to_csr(G + q, d, l).astype(np.float32)
+    for l, Pl in H.P.items():
+        Pd = dlinear_P(d, l)
+        dP = sp.csr_matrix(Pl - Pd)
+        dP.sum_duplicates()
+        rows = np.repeat(np.arange(dP.shape[0]), np.diff(dP.indptr))
+        vals = dP.data.copy()
+        if fmt == "fp16":
+            from .store import fp16_exponent
+            mx = np.zeros(dP.shape[0])
+            np.maximum.at(mx, rows, np.abs(vals))
+            e = fp16_exponent(mx)
+            sc = np.ldexp(1.0, e[rows])
+            vals = (vals / sc).astype(np.float32).astype(np.float16).astype(np.float64) * sc
+        else:
+            vals = quantise(vals, fmt)
+        # zero rows whose delta is negligible against the d-linear weights
+        mxd = np.zeros(dP.shape[0])
+        np.maximum.at(mxd, rows, np.abs(dP.data))
+        mxp = np.asarray(abs(Pd).max(axis=1).todense()).ravel()
+        zero = mxd <= EPS_ZERO * mxp
+        vals[zero[rows]] = 0.0
+        q = sp.csr_matrix((vals, dP.indices, dP.indptr), shape=dP.shape)
+        P32[l] = (Pd + q).astype(np.float32).tocsr()
+    Hq = Hierarchy(d, H.L, H.lc, H.transfer, A32, P32, H.eps, H.omega, H.mu_pre, H.mu_post,
+                   H.coarse_lu, np.float32)
+    return Hq
+
+
+def mixed_solve(H, Hq, b, tol=1e-8, max_outer=100, inner_cycles=1):
+    """FP64 defect correction around FP32 inner V-cycles (see module notes).
+    Returns (x, relres history)."""
+    A = H.A[H.L]
+    x = np.zeros(A.shape[0])
+    nb = np.linalg.norm(b)
+    hist = []
+    for _ in range(max_outer):
+        r = b - A @ x
+        rr = float(np.linalg.norm(r) / nb)
+        hist.append(rr)
+        if rr <= tol:
+            break
+        r32 = r.astype(np.float32)
+        e = np.zeros_like(r32)
+        for _ in range(inner_cycles):
+            e = vcycle(Hq, Hq.L, e, r32)
+        x = x + e.astype(np.float64)
+    return x, hist

@@ -1,0 +1,163 @@
+"""Seeded synthetic inputs for the multigrid solver and for its reference checks.
+
+This module only draws random numbers and lays them out; it holds none of the
+solver's arithmetic.  Both the HIP library's tests/benchmarks and the CPU
+reference consume these arrays, and nothing else is shared between the two.
+
+Layout conventions (shared by every producer and consumer of these arrays):
+
+* A level-``L`` regular grid of the unit cube ``(0,1)^d`` has ``n = 3**L`` cells
+  per axis (tripartitioned spacetree, every cell refined down to level ``L``).
+* ``eps`` holds one diffusion coefficient per finest cell, shape ``(n,)*d``,
+  C order with x fastest, i.e. ``eps[z, y, x]`` (``eps[y, x]`` in 2D).
+* ``f`` holds one source value per interior vertex, shape ``(n-1,)*d``, again x
+  fastest.  Interior vertex ``(i, j[, k])`` with ``1 <= i,j,k <= n-1`` sits at
+  ``x = i/n`` and is stored at ``f[k-1, j-1, i-1]``.
+
+The problems follow the paper's setups (Table "parameters", Sect. 5): zero
+Dirichlet boundary, no convection, piecewise-constant coefficients per cell.
+The concrete random fields stand in for the paper's analytic setups; no data set
+is involved.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Problem:
+    """One solve request: grid size, coefficient field and right-hand side."""
+    name: str
+    dim: int
+    level: int
+    eps: np.ndarray        # (n,)*dim float64, one value per finest cell
+    f: np.ndarray          # (n-1,)*dim float64, one value per interior vertex
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return 3 ** self.level
+
+    @property
+    def n_unknowns(self) -> int:
+        return (self.n - 1) ** self.dim
+
+
+def _uniform_f(rng: np.random.Generator, dim: int, level: int) -> np.ndarray:
+    n = 3 ** level
+    return rng.uniform(-1.0, 1.0, size=(n - 1,) * dim)
+
+
+def _block_index(dim: int, level: int, blocks: int) -> List[np.ndarray]:
+    """Per axis, the index of the ``blocks``-wide coarse block each finest cell
+    centre falls into (``floor(blocks * x_centre)``)."""
+    n = 3 ** level
+    centres = (np.arange(n) + 0.5) / n
+    b = np.floor(blocks * centres).astype(np.int64)
+    grids = np.meshgrid(*([b] * dim), indexing="ij")
+    return grids[::-1]  # returned as (x, y[, z]) index arrays shaped like eps[z, y, x]
+
+
+def poisson(dim: int, level: int, seed: int, name: str = "poisson") -> Problem:
+    """Constant coefficient (eps = 1) and f ~ U[-1, 1] i.i.d. per unknown."""
+    rng = np.random.default_rng(seed)
+    n = 3 ** level
+    eps = np.ones((n,) * dim)
+    f = _uniform_f(rng, dim, level)
+    return Problem(name, dim, level, eps, f, {"seed": seed, "eps": "1"})
+
+
+def random_checkerboard(dim: int, level: int, seed: int, values=(1.0, 1.0e4),
+                        blocks: int = 9, name: str = "jump") -> Problem:
+    """Coefficient piecewise constant on a ``blocks^d`` array of equal boxes;
+    each box draws one of ``values`` i.i.d. (box array drawn first, C order),
+    then f ~ U[-1, 1] per unknown."""
+    rng = np.random.default_rng(seed)
+    table = rng.choice(np.asarray(values, dtype=np.float64), size=(blocks,) * dim)
+    idx = _block_index(dim, level, blocks)          # x, y[, z]
+    eps = table[tuple(idx[::-1])]                   # table indexed [z, y, x]
+    f = _uniform_f(rng, dim, level)
+    return Problem(name, dim, level, eps, f,
+                   {"seed": seed, "eps": f"random {blocks}^d boxes of {values}"})
+
+
+def alternating_checkerboard(dim: int, level: int, contrast: float, seed: int,
+                             blocks: int = 9, name: str = "checker") -> Problem:
+    """Coefficient 1 / ``contrast`` alternating on a ``blocks^d`` box array
+    (parity of the box index sum), f ~ U[-1, 1] per unknown."""
+    rng = np.random.default_rng(seed)
+    idx = _block_index(dim, level, blocks)
+    parity = sum(idx) % 2
+    eps = np.where(parity == 0, 1.0, float(contrast))
+    f = _uniform_f(rng, dim, level)
+    return Problem(name, dim, level, eps, f,
+                   {"seed": seed, "eps": f"alternating {blocks}^d, contrast {contrast:g}"})
+
+
+def sin_source(dim: int, level: int) -> Problem:
+    """The paper's validation setup with eps = 1 and a sine source whose exact
+    solution is prod_i sin(pi x_i); f = d*pi^2*prod_i sin(pi x_i) (the printed
+    2*pi^2 is the d = 2 instance)."""
+    n = 3 ** level
+    x = np.arange(1, n) / n
+    s = np.sin(np.pi * x)
+    grids = np.meshgrid(*([s] * dim), indexing="ij")
+    prod = np.ones_like(grids[0])
+    for g in grids:
+        prod = prod * g
+    f = dim * np.pi ** 2 * prod
+    return Problem("sin", dim, level, np.ones((n,) * dim), f, {"exact": prod})
+
+
+# --------------------------------------------------------------------------
+# Named workloads.  cfg1: small 2D Poisson; cfg2: 2D jumping coefficient on
+# 729^2 cells; cfg4: a stream of mixed 2D/3D checkerboard requests.
+# --------------------------------------------------------------------------
+
+def cfg1(seed: int = 0) -> Problem:
+    p = poisson(2, 4, seed, name="cfg1-poisson2d-L4")
+    return p
+
+
+def cfg2(seed: int = 0, level: int = 6) -> Problem:
+    return random_checkerboard(2, level, seed, name=f"cfg2-jump2d-L{level}")
+
+
+def jump3d(level: int, seed: int = 0) -> Problem:
+    """3D analogue of cfg2: random 9^3 boxes with values {1, 1e4}."""
+    return random_checkerboard(3, level, seed, name=f"jump3d-L{level}")
+
+
+@dataclasses.dataclass
+class Request:
+    problem: Problem
+    arrival: float       # seconds after stream start
+
+
+def cfg4_stream(seed: int = 0, n_requests: int = 256, rate: float = 100.0,
+                levels_2d=(3, 6), levels_3d=(2, 4)) -> List[Request]:
+    """Served stream: each request draws d in {2,3} with p = 1/2, a level
+    uniformly in ``levels_2d`` / ``levels_3d`` (inclusive), a contrast 10^c with
+    c ~ U[0, 4] and its own f; arrivals are a Poisson process of ``rate``/s."""
+    rng = np.random.default_rng(seed)
+    out: List[Request] = []
+    t = 0.0
+    for k in range(n_requests):
+        dim = 2 if rng.uniform() < 0.5 else 3
+        lo, hi = levels_2d if dim == 2 else levels_3d
+        level = int(rng.integers(lo, hi + 1))
+        c = float(rng.uniform(0.0, 4.0))
+        sub_seed = int(rng.integers(0, 2 ** 31 - 1))
+        t += float(rng.exponential(1.0 / rate))
+        p = alternating_checkerboard(dim, level, 10.0 ** c, sub_seed,
+                                     name=f"cfg4-req{k}-d{dim}-L{level}")
+        out.append(Request(p, t))
+    return out
+
+
+__all__ = ["Problem", "Request", "poisson", "random_checkerboard",
+           "alternating_checkerboard", "sin_source", "cfg1", "cfg2", "jump3d",
+           "cfg4_stream"]

@@ -1,0 +1,180 @@
+"""Benchmark: vertex updates/s, solves/s to 1e-8 and p50/p99 solve latency.
+
+One step = the whole hot path for one request of the 2D jumping-coefficient
+workload (729^2 cells, random 9x9 checkerboard of {1, 1e4}): set_coefficients,
+build_operators (BoxMG P, Galerkin R A P with the definiteness check,
+hierarchical FP64 delta store, coarsest LU) and V(2,2) cycles to a relative
+residual of 1e-8, all in the HIP library on one GPU.  Inputs are seeded and
+synthetic (workloads.cfg2); they are resident in host memory and copied in by
+set_coefficients inside the timed step.
+
+Prints one JSON line.  The dominant kernel (finest-level Jacobi sweep) is timed
+with HIP events on the grid's stream during the timed steps; its algorithmic
+bytes per launch give the roofline figure.  The CPU baseline times the oracle
+(test infrastructure) on one solve of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "vertex updates/s + solves/s to 1e-8 rel residual; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic bytes per finest vertex of one Jacobi sweep: eps, u, b read once,
+# u' written once (stencils rebuilt on the fly); the plain store adds 3^d FP64
+# stencil entries and drops nothing else
+SWEEP_BYTES = {("hier64", 2): 32, ("hier64", 3): 32, ("plain64", 2): 96, ("plain64", 3): 240,
+               ("hier32", 2): 16, ("hier32", 3): 16, ("hier16", 2): 16, ("hier16", 3): 16,
+               ("bf16", 2): 16, ("bf16", 3): 16}
+
+
+def run_variant(qmg, problem, transfer, store, steps, warmup, tol=1e-8, profile=True):
+    import torch
+    opts = qmg.make_opts(transfer, store)
+    g = qmg.Grid(problem.dim, problem.level, opts)
+    lat = []
+    updates = 0
+    reps = []
+    for it in range(warmup + steps):
+        if it == warmup:
+            torch.cuda.synchronize()
+            if profile:
+                g.profile(True)
+                g.profile_read()
+            t_start = time.perf_counter()
+        t0 = time.perf_counter()
+        g.set_coefficients(problem.eps, problem.f)
+        g.build()
+        rep, _ = g.solve(tol, 2000)
+        t1 = time.perf_counter()
+        if rep["status"] != "QMG_OK":
+            raise RuntimeError(f"solve did not converge: {rep}")
+        if it >= warmup:
+            lat.append(t1 - t0)
+            updates += rep["vertex_updates"]
+            reps.append(rep)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    launches, ms = g.profile_read() if profile else (0, 0.0)
+    u = g.solution()
+    g.close()
+    return {"elapsed": elapsed, "lat": lat, "updates": updates, "reps": reps,
+            "kernel_launches": launches, "kernel_ms": ms, "u": u}
+
+
+def cpu_baseline(problem):
+    """The oracle (plain FP64 numpy/scipy) on one full solve of the workload."""
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        H = O.build_hierarchy(problem.eps, problem.dim, problem.level, transfer="boxmg")
+        b = O.rhs_from_f(problem.f, problem.dim, problem.level)
+        u, hist = O.solve(H, b, tol=1e-8, max_cycles=2000)
+        dt = time.perf_counter() - t0
+    per_cycle = sum(4 * (3 ** l - 1) ** problem.dim for l in range(H.lc + 1, problem.level + 1))
+    upd = per_cycle * len(hist)
+    return {"value": upd / dt, "unit": "vertex updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full solve (build + {len(hist)} V(2,2) cycles to 1e-8) of the benchmark "
+                      f"workload, single thread, {dt:.1f} s; solves/s {1.0 / dt:.4f}",
+            "solves_per_s": 1.0 / dt, "u": u}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--level", type=int, default=6)
+    ap.add_argument("--store", default="hier64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one device copy of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--variants", default="plain64,bf16",
+                    help="extra stores timed on the same workload (comma list, '' for none)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver path is "
+              f"single-GPU in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1607_00648_amd import qmg
+    import workloads as W
+    torch.cuda.set_device(0)
+    qmg.load()
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy calibration: {args.calibrate_copy} MiB read + written", file=sys.stderr)
+        del src, dst
+    p = W.cfg2(0, level=args.level)
+    res = run_variant(qmg, p, "boxmg", args.store, args.steps, args.warmup)
+    lat = np.array(res["lat"])
+    vu = res["updates"] / res["elapsed"]
+    n_int = p.n_unknowns
+    bytes_per_launch = SWEEP_BYTES[(args.store, p.dim)] * n_int
+    avg_s = res["kernel_ms"] / max(res["kernel_launches"], 1) / 1e3
+    achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else None
+    out = {
+        "metric": METRIC,
+        "value": vu,
+        "unit": "vertex updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * res["elapsed"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.store in ("hier64", "plain64") else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D -div(eps grad u)=f, {p.n}^2 cells ({p.n - 1}^2 unknowns), "
+                               f"eps random 9x9 checkerboard {{1,1e4}} (seed 0), f~U[-1,1]; "
+                               f"BoxMG + Galerkin RAP, store {args.store}, V(2,2), omega 0.6, "
+                               f"exact coarsest solve, to 1e-8 relative residual",
+                   "step": "set_coefficients + build_operators + solve",
+                   "level": p.level, "unknowns": n_int},
+        "solves_per_s": args.steps / res["elapsed"],
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "cycles_per_solve": res["reps"][-1]["cycles"],
+        "relres": res["reps"][-1]["relres"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "kernel": "finest-level Jacobi sweep (k_stencil mode 0)",
+                     "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": avg_s * 1e6, "launches": res["kernel_launches"]},
+    }
+    variants = {}
+    for v in [s for s in args.variants.split(",") if s]:
+        r = run_variant(qmg, p, "boxmg", v, max(3, args.steps // 4), 1)
+        variants[v] = {"solves_per_s": len(r["lat"]) / r["elapsed"],
+                       "vertex_updates_per_s": r["updates"] / r["elapsed"],
+                       "cycles_per_solve": r["reps"][-1]["cycles"],
+                       "relres": r["reps"][-1]["relres"],
+                       "avg_sweep_us": r["kernel_ms"] / max(r["kernel_launches"], 1) * 1e3}
+    if variants:
+        out["variants"] = variants
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(p)
+        ucpu = cb.pop("u")
+        out["cpu_baseline"] = cb
+        out["u_rel_diff_vs_oracle"] = float(np.linalg.norm(res["u"] - ucpu) / np.linalg.norm(ucpu))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * qmg.h -- C ABI of the MI355X (gfx950) quasi-matrix-free hybrid multigrid.
+ *
+ * The library solves the elliptic problem of the paper's eq. (1) with v = 0,
+ *     -div(eps grad u) = f  on (0,1)^d,  u = 0 on the boundary,
+ * discretised with d-linear (Q1) finite elements on the levels of a
+ * tripartitioned spacetree (Sect. 2: every refinement splits a cell into 3^d
+ * children; level l has 3^l cells per axis).  Per-vertex 3^d stencils are
+ * applied in situ (Sect. 3); coarse operators are rediscretised (geometric
+ * multigrid), or Galerkin products R A P (Sect. 3.3) with d-linear or BoxMG
+ * (Sect. 3.4 and the BoxMG appendix) transfer operators; stored operators are
+ * kept as hierarchical deltas from the rediscretised stencil and the d-linear
+ * prolongation (Sect. 4), in FP64, FP32, FP16 or BF16.
+ *
+ * Conventions for every entry point:
+ *  - Return value: QMG_OK (0) or a negative status.  Nothing throws across the
+ *    ABI.  The text of the last error is returned by qmg_last_error(grid), or by
+ *    qmg_last_error(NULL) for errors of calls that had no valid grid.  After any
+ *    error other than QMG_EHIP the grid stays usable; QMG_EHIP (a HIP runtime or
+ *    kernel fault) leaves the device state undefined.
+ *  - Ownership: input arrays are copied in; the caller keeps them.  Output
+ *    arrays are caller-allocated and written.  Pointers flagged by `mem` are
+ *    host (QMG_HOST) or device (QMG_DEVICE) memory of the current HIP device.
+ *  - Device memory: a grid lives in one workspace.  Pass device_buf == NULL to
+ *    let the library allocate it (freed by qmg_destroy_grid), or pass a
+ *    caller-owned device buffer of at least qmg_workspace_bytes() bytes that
+ *    must outlive the grid (the library never frees it).
+ *  - Streams: all device work of a grid is enqueued on the stream given at
+ *    creation (a hipStream_t, NULL = the null stream).  Calls return when their
+ *    host-visible results are ready.  A grid is not thread-safe; distinct grids
+ *    may be used concurrently from different threads on different streams.
+ *  - Enumeration: unknowns are the interior vertices of the finest level,
+ *    numbered lexicographically with x fastest: vertex (i,j[,k]) with
+ *    1 <= i,j,k <= n-1 has index (i-1) + (n-1)*((j-1) + (n-1)*(k-1)).  Finest
+ *    cells (coefficients) are numbered the same way over 0 <= i,j,k <= n-1.
+ *  - Lattice arrays (inspection entry points) cover all vertices 0..n of a
+ *    level, x fastest, (n+1)^d values; stencil arrays hold 3^d such arrays,
+ *    entry k belonging to the offset o in {-1,0,1}^d with
+ *    k = (o_x+1) + 3(o_y+1) + 9(o_z+1).
+ */
+#ifndef QMG_H
+#define QMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qmg_grid qmg_grid_t;
+typedef struct qmg_server qmg_server_t;
+
+enum qmg_status {
+  QMG_OK = 0,
+  QMG_EINVAL = -1,   /* invalid argument                                      */
+  QMG_ENOMEM = -2,   /* workspace too small / allocation failed               */
+  QMG_EHIP = -3,     /* HIP runtime error or device fault (sticky)            */
+  QMG_ESTATE = -4,   /* call out of order (e.g. solve before build)           */
+  QMG_ENOTCONV = -5, /* tolerance not reached within the cycle limit          */
+  QMG_EINDEF = -6,   /* every Galerkin coarse operator failed the check       */
+  QMG_EBUSY = -7     /* server: no slot / memory for the request right now    */
+};
+
+enum { QMG_HOST = 0, QMG_DEVICE = 1 };
+
+/* Transfer operators and coarse operators (Sect. 3.1, 3.3, 3.4). */
+enum {
+  QMG_GEOMETRIC = 0,         /* d-linear P, R = P^T, rediscretised coarse stencils */
+  QMG_GALERKIN_DLINEAR = 1,  /* d-linear P, R = P^T, A_{l-1} = R A_l P            */
+  QMG_BOXMG = 2              /* BoxMG P, R = P^T, A_{l-1} = R A_l P               */
+};
+
+/* Operator store (Sect. 4).  PLAIN keeps full FP64 stencils (and P) on every
+ * level including the finest; HIER keeps deltas from the rediscretised stencil
+ * and from the d-linear P, dropping all-zero 64-vertex blocks.  PLAIN_FP64 and
+ * HIER_FP64 iterate in FP64; the reduced-precision stores iterate in FP32 inside
+ * an FP64 defect-correction loop (FP64 residual on the finest level, FP64
+ * Galerkin construction and FP64 coarsest solve). */
+enum {
+  QMG_PLAIN_FP64 = 0,
+  QMG_HIER_FP64 = 1,
+  QMG_HIER_FP32 = 2,
+  QMG_HIER_FP16 = 3,   /* FP16 with one power-of-two scale per vertex */
+  QMG_HIER_BF16 = 4
+};
+
+typedef struct {
+  int dim;        /* 2 or 3                                                */
+  int max_level;  /* finest level L >= 2: 3^L cells per axis, regular grid */
+} qmg_grid_desc;
+
+typedef struct {
+  int transfer;        /* QMG_GEOMETRIC | QMG_GALERKIN_DLINEAR | QMG_BOXMG     */
+  int store;           /* QMG_PLAIN_FP64 ... QMG_HIER_BF16                    */
+  int mu_pre, mu_post; /* smoothing steps per level, each >= 1 (Alg. 1)       */
+  double omega;        /* Jacobi damping in (0, 2)                           */
+  int coarsest_level;  /* requested coarsest level, 1 <= lc < L              */
+  int check_definite;  /* 1: raise the coarsest level when a Galerkin row is
+                          not positive / diagonally dominant (Sect. 3.3)      */
+  int inner_cycles;    /* FP32 V-cycles per FP64 outer iteration (>= 1)     */
+} qmg_solver_opts;
+
+typedef struct {
+  int cycles;               /* V-cycles run (inner cycles for FP32 iterates)  */
+  int outer_iters;          /* FP64 residual evaluations                      */
+  double relres;            /* final ||b - A u||_2 / ||b||_2, FP64, finest    */
+  int coarsest_level_used;  /* after the definiteness check                   */
+  int64_t vertex_updates;   /* Jacobi vertex updates performed (all levels)   */
+  size_t bytes_operators;   /* device bytes holding stored operators          */
+  double zero_delta_fraction; /* share of 64-vertex blocks stored as zero     */
+  double seconds;           /* wall time of the call                          */
+} qmg_solve_report;
+
+/* Library version string (static storage). */
+const char* qmg_version(void);
+
+/* Device bytes a grid needs for `desc` and `opts` (worst case over stores). */
+int qmg_workspace_bytes(const qmg_grid_desc* desc, const qmg_solver_opts* opts, size_t* bytes);
+
+/* Default options: BoxMG, HIER_FP64, V(2,2), omega 0.6, lc 1, check on, 1 inner cycle. */
+int qmg_default_opts(qmg_solver_opts* opts);
+
+/* Creates a grid (Sect. 2: the regular levels 0..L of a tripartitioned
+ * spacetree, linearised level by level) in `device_buf` (or library memory when
+ * NULL).  `stream` is a hipStream_t.  On success *out owns the grid. */
+int qmg_create_grid(const qmg_grid_desc* desc, const qmg_solver_opts* opts, void* device_buf,
+                    size_t bytes, void* stream, qmg_grid_t** out);
+
+/* Number of unknowns, finest cells and levels (L+1). */
+int qmg_sizes(const qmg_grid_t* grid, int64_t* n_unknowns, int64_t* n_leaf_cells, int* n_levels);
+
+/* Coordinates of the unknowns, dim values per unknown (host array). */
+int qmg_unknown_coords(const qmg_grid_t* grid, double* xyz);
+
+/* Sets the coefficient eps (one value per finest cell, > 0 and finite; ncomp
+ * must be 1) and the source f (one value per unknown); the right-hand side is
+ * b = h^d f (lumped).  Resets the solution to zero and invalidates operators. */
+int qmg_set_coefficients(qmg_grid_t* grid, const double* eps, int ncomp, const double* f, int mem);
+
+/* Builds all coarse operators (Sect. 3.3, 3.4): BoxMG P, Galerkin RAP with the
+ * definiteness check, the hierarchical delta store (Sect. 4) and the coarsest
+ * solve.  Fills `info` (nullable) with coarsest_level_used, bytes_operators,
+ * zero_delta_fraction and seconds.  Returns QMG_EINDEF when even the first
+ * coarse level fails the check. */
+int qmg_build_operators(qmg_grid_t* grid, qmg_solve_report* info);
+
+/* Runs n cycles (FP64 iterates: n V-cycles; FP32 iterates: n outer iterations
+ * of inner_cycles V-cycles each) on the current solution.  relres (nullable,
+ * n values, host) receives the relative residual after each cycle. */
+int qmg_vcycle(qmg_grid_t* grid, int n, double* relres);
+
+/* Cycles from the current solution until the relative residual is <= rel_tol
+ * or max_cycles cycles ran.  history (nullable, host, max_cycles values)
+ * receives the relative residual after each cycle.  Returns QMG_ENOTCONV if
+ * the tolerance was not reached; `report` (nullable) is filled either way. */
+int qmg_solve(qmg_grid_t* grid, double rel_tol, int max_cycles, double* history,
+              qmg_solve_report* report);
+
+/* Copies the solution out / in (one value per unknown).  set_solution is a warm
+ * start (resume): the next cycle starts from it. */
+int qmg_get_solution(const qmg_grid_t* grid, double* u, int mem);
+int qmg_set_solution(qmg_grid_t* grid, const double* u, int mem);
+
+/* Measurement: when enabled, every smoothing launch on the finest level is
+ * bracketed by HIP events on the grid's stream (a few microseconds of
+ * overhead per launch).  profile_read returns the number of timed launches and
+ * their summed device time in milliseconds since the last read, then resets. */
+int qmg_profile_enable(qmg_grid_t* grid, int on);
+int qmg_profile_read(qmg_grid_t* grid, int64_t* launches, double* total_ms);
+
+/* Frees the grid (and the workspace if the library allocated it). */
+int qmg_destroy_grid(qmg_grid_t* grid);
+
+/* Last error message of `grid` (or of the calling thread when grid is NULL). */
+const char* qmg_last_error(const qmg_grid_t* grid);
+
+/* ---------------- inspection (host arrays, FP64) --------------------------
+ * These read back or exercise single steps of the hot path so that each can be
+ * checked on its own.  `level` is 0..L; arrays are lattice arrays of that level. */
+
+/* The operator of `level` as applied by the smoother (stored operators are
+ * reconstructed from their store; the finest level is rediscretised from eps),
+ * 3^d lattice arrays.  Requires built operators for level < L. */
+int qmg_get_operator(const qmg_grid_t* grid, int level, double* stencils);
+
+/* Prolongation from level-1 to `level` as weights per fine vertex: 2^d lattice
+ * arrays; array c = kx + 2 ky + 4 kz holds the weight of the coarse vertex
+ * floor(f/3) + (kx,ky,kz) at fine vertex f (zero where it is not a parent). */
+int qmg_get_prolongation(const qmg_grid_t* grid, int level, double* weights);
+
+enum {
+  QMG_OP_MATVEC = 0,     /* out = A x                                         */
+  QMG_OP_RESIDUAL = 1,   /* out = b - A x                                     */
+  QMG_OP_JACOBI = 2,     /* out = x + omega diag(A)^-1 (b - A x)               */
+  QMG_OP_RESTRICT = 3,   /* out (level-1 lattice) = P^T x (x on `level`)       */
+  QMG_OP_PROLONG = 4     /* out (level lattice) = b + P x (x on level-1)       */
+};
+
+/* Applies one step of the hot path on `level` in the grid's iterate precision
+ * (FP64 or FP32, converted at the boundary).  x, b, out are lattice arrays of
+ * the sizes the operation implies; b is ignored where unused (may be NULL). */
+int qmg_apply(qmg_grid_t* grid, int op, int level, const double* x, const double* b, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QMG_H */

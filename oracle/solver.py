@@ -66,8 +66,12 @@ class Hierarchy:
 
 
 def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_post=2,
-                    check_definite=True):
-    """Operators of all levels from the finest coefficients (Sect. 3.3, 3.4)."""
+                    check_definite=True, perturb=None):
+    """Operators of all levels from the finest coefficients (Sect. 3.3, 3.4).
+
+    ``perturb`` (tests only) is applied to every Galerkin product before it is
+    used; the tests pass one-ulp random noise to measure how far FP64 rounding
+    alone moves the results (the noise floor of a parity comparison)."""
     if transfer not in ("geometric", "galerkin", "boxmg"):
         raise ValueError(transfer)
     eps_l = {L: np.asarray(eps, dtype=np.float64)}
@@ -85,6 +89,8 @@ def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_p
             Ac = stencil_to_csr(geometric_stencil(eps_l[l - 1], d, l - 1), d, l - 1)
         else:
             Ac = rap(A[l], Pl)
+            if perturb is not None:
+                Ac = perturb(Ac)
             if check_definite and len(definiteness_violations(Ac)) > 0:
                 lc_used = l
                 break

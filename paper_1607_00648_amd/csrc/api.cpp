@@ -1,0 +1,999 @@
+// Host driver and C ABI of the quasi-matrix-free multigrid library: workspace
+// layout, coefficient upload, operator construction (Sect. 3.3, 3.4, 4),
+// V-cycles (Alg. 1, correction-scheme form on regular grids), the FP64
+// defect-correction loop around FP32 cycles, and inspection entry points.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qmg_internal.hpp"
+
+using namespace qmg;
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+size_t fmt_size(int fmt) { return fmt == F64 ? 8 : fmt == F32 ? 4 : 2; }
+
+int store_fmt(int store) {
+  switch (store) {
+    case QMG_HIER_FP32: return F32;
+    case QMG_HIER_FP16: return F16;
+    case QMG_HIER_BF16: return BF16;
+    default: return F64;
+  }
+}
+
+struct LevelBuf {
+  Lat L{};
+  double* eps64 = nullptr;
+  float* eps32 = nullptr;
+  void* u = nullptr;  // iterate type
+  void* t = nullptr;
+  void* b = nullptr;
+  void* r = nullptr;
+  Store A, P;
+  double* Adense = nullptr;
+  double* Pdense = nullptr;
+  int32_t* Ablk = nullptr;
+  void* Apay = nullptr;
+  int8_t* Ascale = nullptr;
+  int32_t* Pblk = nullptr;
+  void* Ppay = nullptr;
+  int8_t* Pscale = nullptr;
+  int64_t Anz = -1, Pnz = -1;  // stored non-zero blocks (-1: no store)
+};
+
+// Bump allocator over the workspace; with base == nullptr it only measures.
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(int64_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (size_t)std::max<int64_t>(count, 0) * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct qmg_grid {
+  qmg_grid_desc desc{};
+  qmg_solver_opts opts{};
+  int d = 2, Lmax = 2, lcq = 1, lc = 1;
+  bool mixed = false, plain = false;
+  int fmt = F64;
+  std::vector<LevelBuf> lv;
+  double* x64 = nullptr;    // mixed: FP64 solution on the finest level
+  double* bfin = nullptr;   // mixed: FP64 right-hand side on the finest level
+  double* stage = nullptr;  // packed IO staging (nslot of the finest level)
+  double* partial = nullptr;
+  double* dscal = nullptr;
+  int* dcount = nullptr;
+  int32_t* dtotal = nullptr;
+  double* Ainv = nullptr;
+  int64_t ainv_cap = 0;
+  int nc = 0;
+  bool coarse_direct = false;
+  double* tmpA[2] = {nullptr, nullptr};
+  double* tmpP = nullptr;
+  char* base = nullptr;
+  size_t bytes = 0;
+  bool owns = false;
+  hipStream_t stream = nullptr;
+  bool have_coef = false, have_ops = false;
+  double bnorm = 0.0;
+  int64_t n_unknowns = 0;
+  size_t bytes_ops = 0;
+  double zero_frac = 0.0;
+  std::string err;
+  // optional HIP-event timing of every finest-level smoothing launch
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;  // start/stop pairs
+  size_t prof_used = 0;
+  int64_t prof_launches = 0;
+  double prof_ms = 0.0;
+};
+
+namespace {
+
+void set_err(qmg_grid_t* g, const std::string& m) {
+  if (g) g->err = m;
+  g_thread_err = m;
+}
+
+template <class F>
+int guard(qmg_grid_t* g, F&& f) {
+  try {
+    f();
+    return QMG_OK;
+  } catch (const ApiError& e) {
+    set_err(g, e.what());
+    return e.code;
+  } catch (const HipError& e) {
+    set_err(g, e.what());
+    return QMG_EHIP;
+  } catch (const std::bad_alloc&) {
+    set_err(g, "host allocation failed");
+    return QMG_ENOMEM;
+  } catch (const std::exception& e) {
+    set_err(g, e.what());
+    return QMG_EINVAL;
+  }
+}
+
+void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
+  if (!desc || !o) throw ApiError(QMG_EINVAL, "null descriptor or options");
+  if (desc->dim != 2 && desc->dim != 3) throw ApiError(QMG_EINVAL, "dim must be 2 or 3");
+  if (desc->max_level < 2 || desc->max_level > (desc->dim == 2 ? 10 : 6))
+    throw ApiError(QMG_EINVAL, "max_level out of range (2..10 in 2D, 2..6 in 3D)");
+  if (o->transfer < QMG_GEOMETRIC || o->transfer > QMG_BOXMG) throw ApiError(QMG_EINVAL, "bad transfer");
+  if (o->store < QMG_PLAIN_FP64 || o->store > QMG_HIER_BF16) throw ApiError(QMG_EINVAL, "bad store");
+  if (o->mu_pre < 1 || o->mu_post < 1) throw ApiError(QMG_EINVAL, "mu_pre and mu_post must be >= 1");
+  if (!(o->omega > 0.0 && o->omega < 2.0)) throw ApiError(QMG_EINVAL, "omega must lie in (0, 2)");
+  if (o->coarsest_level < 1 || o->coarsest_level > desc->max_level - 1)
+    throw ApiError(QMG_EINVAL, "coarsest_level must satisfy 1 <= lc < max_level");
+  if (o->inner_cycles < 1) throw ApiError(QMG_EINVAL, "inner_cycles must be >= 1");
+}
+
+int64_t n_interior(const Lat& L) {
+  const int64_t m = L.n - 1;
+  return L.d == 3 ? m * m * m : m * m;
+}
+
+int npartials(const Lat& L) {
+  return (L.pitch / 64) * ((L.n + 1 + 3) / 4) * (L.d == 3 ? L.n + 1 : 1);
+}
+
+// Lays out every buffer of the grid in the arena (measure or assign).
+void layout(qmg_grid_t* g, Arena& a) {
+  const int d = g->d, L = g->Lmax, lcq = g->lcq;
+  const int NS = ipow(3, d), NC = 1 << d;
+  const size_t it = g->mixed ? sizeof(float) : sizeof(double);
+  const bool galerkin = g->opts.transfer != QMG_GEOMETRIC;
+  const bool boxmg = g->opts.transfer == QMG_BOXMG;
+  g->lv.assign(L + 1, LevelBuf{});
+  for (int l = 0; l <= L; ++l) g->lv[l].L = make_lat(d, l);
+  for (int l = lcq; l <= L; ++l) {
+    LevelBuf& B = g->lv[l];
+    const int64_t ns = B.L.nslot;
+    B.eps64 = a.take<double>(ns);
+    if (g->mixed) B.eps32 = a.take<float>(ns);
+    B.u = a.take<char>(ns * it);
+    B.t = a.take<char>(ns * it);
+    B.b = a.take<char>(ns * it);
+    B.r = a.take<char>(ns * it);
+    const bool hasA = (l < L) || g->plain;
+    if (hasA) {
+      if (g->plain) {
+        B.Adense = a.take<double>(ns * NS);
+      } else if (galerkin && l < L) {
+        B.Ablk = a.take<int32_t>(ns / kSeg);
+        B.Apay = a.take<char>(ns * NS * fmt_size(g->fmt));
+        if (g->fmt == F16) B.Ascale = a.take<int8_t>(ns);
+      }
+    }
+    if (l > lcq) {
+      if (g->plain) {
+        B.Pdense = a.take<double>(ns * NC);
+      } else if (boxmg) {
+        B.Pblk = a.take<int32_t>(ns / kSeg);
+        B.Ppay = a.take<char>(ns * NC * fmt_size(g->fmt));
+        if (g->fmt == F16) B.Pscale = a.take<int8_t>(ns);
+      }
+    }
+  }
+  if (!g->plain) {
+    const int64_t nsA = g->lv[L - 1].L.nslot;
+    g->tmpA[0] = a.take<double>(nsA * NS);
+    g->tmpA[1] = a.take<double>(nsA * NS);
+    if (boxmg) g->tmpP = a.take<double>(g->lv[L].L.nslot * NC);
+  }
+  if (g->mixed) {
+    g->x64 = a.take<double>(g->lv[L].L.nslot);
+    g->bfin = a.take<double>(g->lv[L].L.nslot);
+  }
+  g->stage = a.take<double>(g->lv[L].L.nslot);
+  g->partial = a.take<double>(npartials(g->lv[L].L));
+  g->dscal = a.take<double>(8);
+  g->dcount = a.take<int>(8);
+  g->dtotal = a.take<int32_t>(2 * (L + 1));
+  int64_t cap = 0;
+  for (int l = lcq; l < L; ++l) {
+    const int64_t m = n_interior(g->lv[l].L);
+    if (m <= kCoarseDirectMax) cap = std::max(cap, m * m);
+  }
+  g->ainv_cap = cap;
+  g->Ainv = a.take<double>(cap);
+  (void)galerkin;
+}
+
+void init_modes(qmg_grid_t* g, const qmg_grid_desc* desc, const qmg_solver_opts* o) {
+  g->desc = *desc;
+  g->opts = *o;
+  g->d = desc->dim;
+  g->Lmax = desc->max_level;
+  g->lcq = o->coarsest_level;
+  g->lc = g->lcq;
+  g->plain = o->store == QMG_PLAIN_FP64;
+  g->mixed = o->store >= QMG_HIER_FP32;
+  g->fmt = store_fmt(o->store);
+}
+
+hipStream_t S(qmg_grid_t* g) { return g->stream; }
+
+template <typename T>
+const T* eps_of(const LevelBuf& B);
+template <>
+const double* eps_of<double>(const LevelBuf& B) { return B.eps64; }
+template <>
+const float* eps_of<float>(const LevelBuf& B) { return B.eps32; }
+
+// ---------------------------------------------------------------------------
+// V-cycle (Alg. 1 read as the correction scheme on regular grids)
+// ---------------------------------------------------------------------------
+void prof_harvest(qmg_grid_t* g) {
+  if (g->prof_used == 0) return;
+  QMG_HIP(hipEventSynchronize(g->prof_ev[2 * g->prof_used - 1]));
+  for (size_t i = 0; i < g->prof_used; ++i) {
+    float ms = 0.f;
+    QMG_HIP(hipEventElapsedTime(&ms, g->prof_ev[2 * i], g->prof_ev[2 * i + 1]));
+    g->prof_ms += ms;
+  }
+  g->prof_launches += (int64_t)g->prof_used;
+  g->prof_used = 0;
+}
+
+hipEvent_t* prof_pair(qmg_grid_t* g) {
+  constexpr size_t kPool = 2048;
+  if (g->prof_used == kPool) prof_harvest(g);
+  if (2 * (g->prof_used + 1) > g->prof_ev.size()) {
+    hipEvent_t a, b;
+    QMG_HIP(hipEventCreate(&a));
+    QMG_HIP(hipEventCreate(&b));
+    g->prof_ev.push_back(a);
+    g->prof_ev.push_back(b);
+  }
+  return &g->prof_ev[2 * g->prof_used++];
+}
+
+template <typename T>
+void smooth(qmg_grid_t* g, LevelBuf& B, int sweeps, bool zero_init) {
+  const T om = (T)g->opts.omega;
+  const bool timed = g->prof_on && B.L.n == g->lv[g->Lmax].L.n;
+  for (int k = 0; k < sweeps; ++k) {
+    const int mode = (k == 0 && zero_init) ? 1 : 0;
+    hipEvent_t* ev = timed ? prof_pair(g) : nullptr;
+    if (ev) QMG_HIP(hipEventRecord(ev[0], S(g)));
+    launch_stencil<T>(B.L, mode, (const T*)B.u, (const T*)B.b, (T*)B.t, eps_of<T>(B), B.A, om,
+                      nullptr, nullptr, S(g));
+    if (ev) QMG_HIP(hipEventRecord(ev[1], S(g)));
+    std::swap(B.u, B.t);
+  }
+}
+
+template <typename T>
+void vcycle(qmg_grid_t* g, int l, bool zero_init) {
+  LevelBuf& F = g->lv[l];
+  const int mu = g->opts.mu_pre, nu = g->opts.mu_post;
+  if (l == g->lc) {
+    if (g->coarse_direct)
+      launch_coarse_solve<T>(F.L, g->Ainv, g->nc, (const T*)F.b, (T*)F.u, S(g));
+    else
+      smooth<T>(g, F, mu + nu, zero_init);
+    return;
+  }
+  smooth<T>(g, F, mu, zero_init);
+  launch_stencil<T>(F.L, 2, (const T*)F.u, (const T*)F.b, (T*)F.r, eps_of<T>(F), F.A, (T)0, nullptr,
+                    nullptr, S(g));
+  LevelBuf& C = g->lv[l - 1];
+  launch_restrict<T>(F.L, C.L, (const T*)F.r, (T*)C.b, F.P, S(g));
+  vcycle<T>(g, l - 1, true);
+  launch_prolong<T>(F.L, C.L, (const T*)C.u, (T*)F.u, F.P, S(g));
+  smooth<T>(g, F, nu, false);
+}
+
+int64_t updates_per_cycle(const qmg_grid_t* g) {
+  int64_t s = 0;
+  const int sw = g->opts.mu_pre + g->opts.mu_post;
+  for (int l = g->lc + 1; l <= g->Lmax; ++l) s += (int64_t)sw * n_interior(g->lv[l].L);
+  if (!g->coarse_direct) s += (int64_t)sw * n_interior(g->lv[g->lc].L);
+  return s;
+}
+
+double read_scalar(qmg_grid_t* g) {
+  double h = 0.0;
+  QMG_HIP(hipMemcpyAsync(&h, g->dscal, sizeof(double), hipMemcpyDeviceToHost, S(g)));
+  QMG_HIP(hipStreamSynchronize(S(g)));
+  return h;
+}
+
+// ||b - A u||_2 on the finest level, FP64 (the FP32 residual of the mixed loop
+// is written to the finest inner right-hand side on the way).
+double finest_residual_norm(qmg_grid_t* g) {
+  LevelBuf& F = g->lv[g->Lmax];
+  int np = 0;
+  if (g->mixed) {
+    launch_residual_mixed(F.L, g->x64, g->bfin, (float*)F.b, F.eps64, g->partial, &np, S(g));
+  } else {
+    launch_stencil<double>(F.L, 2, (const double*)F.u, (const double*)F.b, (double*)F.r, F.eps64,
+                           F.A, 0.0, g->partial, &np, S(g));
+  }
+  launch_sum_partials(g->partial, np, g->dscal, S(g));
+  return std::sqrt(read_scalar(g));
+}
+
+// One "cycle" of the public API: a V-cycle (FP64) or an outer defect-correction
+// iteration with inner FP32 V-cycles (the residual has been formed already).
+void one_cycle(qmg_grid_t* g) {
+  if (!g->mixed) {
+    vcycle<double>(g, g->Lmax, false);
+    return;
+  }
+  for (int m = 0; m < g->opts.inner_cycles; ++m) vcycle<float>(g, g->Lmax, m == 0);
+  launch_axpy_mixed(g->lv[g->Lmax].L, g->x64, (const float*)g->lv[g->Lmax].u, S(g));
+}
+
+// ---------------------------------------------------------------------------
+// Build (Sect. 3.3 and 3.4; store of Sect. 4)
+// ---------------------------------------------------------------------------
+void encode(qmg_grid_t* g, LevelBuf& B, const Lat& Lc, bool is_P, const double* full, int slot) {
+  int32_t* blk = is_P ? B.Pblk : B.Ablk;
+  void* pay = is_P ? B.Ppay : B.Apay;
+  int8_t* sc = is_P ? B.Pscale : B.Ascale;
+  launch_delta_flags(B.L, Lc, is_P, full, B.eps64, blk, S(g));
+  launch_scan_blocks(blk, B.L.nslot / kSeg, g->dtotal + slot, S(g));
+  launch_delta_write(B.L, Lc, is_P, g->fmt, full, B.eps64, blk, pay, sc, S(g));
+}
+
+void invert_dense(std::vector<double>& M, int n) {
+  std::vector<double> I((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(M[(size_t)r * n + c]) > std::fabs(M[(size_t)p * n + c])) p = r;
+    if (M[(size_t)p * n + c] == 0.0) throw ApiError(QMG_EINDEF, "singular coarsest operator");
+    if (p != c)
+      for (int q = 0; q < n; ++q) {
+        std::swap(M[(size_t)p * n + q], M[(size_t)c * n + q]);
+        std::swap(I[(size_t)p * n + q], I[(size_t)c * n + q]);
+      }
+    const double inv = 1.0 / M[(size_t)c * n + c];
+    for (int q = 0; q < n; ++q) {
+      M[(size_t)c * n + q] *= inv;
+      I[(size_t)c * n + q] *= inv;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = M[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      for (int q = 0; q < n; ++q) {
+        M[(size_t)r * n + q] -= f * M[(size_t)c * n + q];
+        I[(size_t)r * n + q] -= f * I[(size_t)c * n + q];
+      }
+    }
+  }
+  M.swap(I);
+}
+
+void setup_coarse(qmg_grid_t* g, const double* Afull) {
+  LevelBuf& C = g->lv[g->lc];
+  const int64_t n = n_interior(C.L);
+  g->nc = (int)std::min<int64_t>(n, 1 << 30);
+  g->coarse_direct = n <= kCoarseDirectMax && n * n <= g->ainv_cap;
+  if (!g->coarse_direct) return;
+  const int NS = ipow(3, g->d);
+  std::vector<double> h((size_t)NS * C.L.nslot);
+  QMG_HIP(hipMemcpyAsync(h.data(), Afull, h.size() * sizeof(double), hipMemcpyDeviceToHost, S(g)));
+  QMG_HIP(hipStreamSynchronize(S(g)));
+  const int m = C.L.n - 1;
+  std::vector<double> M((size_t)n * n, 0.0);
+  for (int64_t r = 0; r < n; ++r) {
+    const int i = (int)(r % m) + 1, j = (int)((r / m) % m) + 1, k = g->d == 3 ? (int)(r / ((int64_t)m * m)) + 1 : 0;
+    const int64_t v = i + (int64_t)j * C.L.pitch + (int64_t)k * C.L.plane;
+    for (int e = 0; e < NS; ++e) {
+      const int ox = e % 3 - 1, oy = (e / 3) % 3 - 1, oz = g->d == 3 ? e / 9 - 1 : 0;
+      const int ii = i + ox, jj = j + oy, kk = k + oz;
+      if (ii < 1 || ii > m || jj < 1 || jj > m || (g->d == 3 && (kk < 1 || kk > m))) continue;
+      const int64_t c = (ii - 1) + (int64_t)m * ((jj - 1) + (int64_t)m * (g->d == 3 ? kk - 1 : 0));
+      M[(size_t)r * n + c] = h[(size_t)e * C.L.nslot + v];
+    }
+  }
+  invert_dense(M, (int)n);
+  QMG_HIP(hipMemcpyAsync(g->Ainv, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice, S(g)));
+  QMG_HIP(hipStreamSynchronize(S(g)));
+}
+
+void assign_stores(qmg_grid_t* g) {
+  const bool galerkin = g->opts.transfer != QMG_GEOMETRIC;
+  const bool boxmg = g->opts.transfer == QMG_BOXMG;
+  const int d = g->d;
+  for (int l = g->lcq; l <= g->Lmax; ++l) {
+    LevelBuf& B = g->lv[l];
+    B.A = Store{};
+    B.P = Store{};
+    B.A.nent = ipow(3, d);
+    B.P.nent = 1 << d;
+    if (g->plain) {
+      B.A.src = SRC_PLAIN;
+      B.A.dense = B.Adense;
+      B.P.src = SRC_PLAIN;
+      B.P.dense = B.Pdense;
+      continue;
+    }
+    if (galerkin && l < g->Lmax && B.Ablk) {
+      B.A.src = SRC_HIER;
+      B.A.fmt = g->fmt;
+      B.A.blk = B.Ablk;
+      B.A.payload = B.Apay;
+      B.A.scale = B.Ascale;
+    }
+    if (boxmg && B.Pblk) {
+      B.P.src = SRC_HIER;
+      B.P.fmt = g->fmt;
+      B.P.blk = B.Pblk;
+      B.P.payload = B.Ppay;
+      B.P.scale = B.Pscale;
+    }
+  }
+}
+
+void build(qmg_grid_t* g, qmg_solve_report* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!g->have_coef) throw ApiError(QMG_ESTATE, "set_coefficients must precede build_operators");
+  const int L = g->Lmax, d = g->d, NS = ipow(3, d), NC = 1 << d;
+  const bool galerkin = g->opts.transfer != QMG_GEOMETRIC;
+  const bool boxmg = g->opts.transfer == QMG_BOXMG;
+  hipStream_t s = S(g);
+  for (int l = L; l > g->lcq; --l) launch_coarsen_eps(g->lv[l].L, g->lv[l - 1].L, g->lv[l].eps64, g->lv[l - 1].eps64, s);
+  if (g->mixed)
+    for (int l = g->lcq; l <= L; ++l) launch_convert<double, float>(g->lv[l].L, g->lv[l].eps64, g->lv[l].eps32, s);
+  g->lc = g->lcq;
+  assign_stores(g);  // views used by materialise below (plain stores)
+  auto fullA = [&](int l) -> double* {
+    if (g->plain) return g->lv[l].Adense;
+    return g->tmpA[l & 1];
+  };
+  Store geom;
+  if (g->plain) launch_materialise(g->lv[L].L, g->lv[L].eps64, geom, g->lv[L].Adense, s);
+  for (int l = g->lcq; l <= L; ++l) {
+    g->lv[l].Anz = -1;
+    g->lv[l].Pnz = -1;
+  }
+  std::vector<int> encodedA, encodedP;
+  int lc_used = g->lcq;
+  for (int l = L; l > g->lcq; --l) {
+    LevelBuf& F = g->lv[l];
+    LevelBuf& C = g->lv[l - 1];
+    const double* Afine = (l == L) ? (g->plain ? F.Adense : nullptr) : fullA(l);
+    const double* Pw = nullptr;
+    if (boxmg) {
+      double* Pt = g->plain ? F.Pdense : g->tmpP;
+      launch_zero<double>(Pt, F.L.nslot * NC, s);
+      launch_boxmg(F.L, C.L, Afine, F.eps64, Pt, s);
+      Pw = Pt;
+    } else if (g->plain) {
+      Store dl;
+      launch_materialise_P(F.L, C.L, dl, F.Pdense, s);
+      Pw = F.Pdense;
+    }
+    double* Ac = fullA(l - 1);
+    if (!galerkin) {
+      // rediscretised coarse operator: stored only in the plain store, and
+      // needed in full on the coarsest level for the exact solve
+      if (g->plain || l - 1 == g->lcq) launch_materialise(C.L, C.eps64, geom, Ac, s);
+    } else {
+      launch_zero<double>(Ac, C.L.nslot * NS, s);
+      launch_rap(F.L, C.L, Afine, F.eps64, Pw, Ac, s);
+      if (g->opts.check_definite) {
+        launch_zero<int>(g->dcount, 1, s);
+        launch_check_rows(C.L, Ac, g->dcount, s);
+        int bad = 0;
+        QMG_HIP(hipMemcpyAsync(&bad, g->dcount, sizeof(int), hipMemcpyDeviceToHost, s));
+        QMG_HIP(hipStreamSynchronize(s));
+        if (bad > 0) {
+          lc_used = l;
+          break;
+        }
+      }
+    }
+    if (!g->plain) {
+      if (boxmg) {
+        encode(g, F, C.L, true, Pw, 2 * l + 1);
+        encodedP.push_back(l);
+      }
+      if (galerkin) {
+        encode(g, C, C.L, false, Ac, 2 * (l - 1));
+        encodedA.push_back(l - 1);
+      }
+    }
+    lc_used = l - 1;
+  }
+  if (lc_used >= L) throw ApiError(QMG_EINDEF, "every Galerkin coarse operator failed the definiteness check");
+  g->lc = lc_used;
+  // stored-operator bookkeeping
+  std::vector<int32_t> tot(2 * (L + 1), 0);
+  QMG_HIP(hipMemcpyAsync(tot.data(), g->dtotal, tot.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  QMG_HIP(hipStreamSynchronize(s));
+  size_t bytes = 0;
+  int64_t blocks = 0, zero_blocks = 0;
+  for (int l : encodedA) {
+    g->lv[l].Anz = tot[2 * l];
+    const int64_t nb = g->lv[l].L.nslot / kSeg;
+    blocks += nb;
+    zero_blocks += nb - tot[2 * l];
+    bytes += (size_t)nb * 4 + (size_t)tot[2 * l] * kSeg * (NS * fmt_size(g->fmt) + (g->fmt == F16 ? 1 : 0));
+  }
+  for (int l : encodedP) {
+    g->lv[l].Pnz = tot[2 * l + 1];
+    const int64_t nb = g->lv[l].L.nslot / kSeg;
+    blocks += nb;
+    zero_blocks += nb - tot[2 * l + 1];
+    bytes += (size_t)nb * 4 + (size_t)tot[2 * l + 1] * kSeg * (NC * fmt_size(g->fmt) + (g->fmt == F16 ? 1 : 0));
+  }
+  if (g->plain) {
+    for (int l = g->lc; l <= L; ++l) bytes += (size_t)g->lv[l].L.nslot * NS * 8;
+    for (int l = g->lc + 1; l <= L; ++l) bytes += (size_t)g->lv[l].L.nslot * NC * 8;
+  }
+  g->bytes_ops = bytes;
+  g->zero_frac = blocks ? (double)zero_blocks / (double)blocks : 1.0;
+  // levels coarser than lc are unused; the coarsest level's own stencil is
+  // the FP64 Galerkin (or rediscretised) operator
+  assign_stores(g);
+  for (int l = g->lcq; l < g->lc; ++l) {
+    g->lv[l].A = Store{};
+    g->lv[l].P = Store{};
+  }
+  g->lv[g->lc].P = Store{};
+  double* Alc = fullA(g->lc);
+  if (!galerkin && !g->plain && g->lc == L) launch_materialise(g->lv[L].L, g->lv[L].eps64, geom, Alc, s);
+  setup_coarse(g, Alc);
+  g->have_ops = true;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->coarsest_level_used = g->lc;
+    info->bytes_operators = g->bytes_ops;
+    info->zero_delta_fraction = g->zero_frac;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+}
+
+void need_ops(qmg_grid_t* g) {
+  if (!g) throw ApiError(QMG_EINVAL, "null grid");
+  if (!g->have_ops) throw ApiError(QMG_ESTATE, "build_operators must precede cycles");
+}
+
+void copy_in(qmg_grid_t* g, double* dst_dev, const double* src, int64_t n, int mem) {
+  QMG_HIP(hipMemcpyAsync(dst_dev, src, n * sizeof(double),
+                         mem == QMG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, S(g)));
+}
+
+// Lattice arrays in host inspection calls have (n+1)^d values without padding.
+std::vector<double> unpitch(const Lat& L, const std::vector<double>& h, int nent) {
+  const int64_t w = L.n + 1;
+  const int64_t per = L.d == 3 ? w * w * w : w * w;
+  std::vector<double> out((size_t)nent * per);
+  for (int e = 0; e < nent; ++e)
+    for (int64_t k = 0; k < (L.d == 3 ? w : 1); ++k)
+      for (int64_t j = 0; j < w; ++j)
+        for (int64_t i = 0; i < w; ++i)
+          out[(size_t)e * per + i + w * (j + w * k)] = h[(size_t)e * L.nslot + i + j * L.pitch + k * L.plane];
+  return out;
+}
+
+std::vector<double> pitch_in(const Lat& L, const double* a) {
+  const int64_t w = L.n + 1;
+  std::vector<double> out((size_t)L.nslot, 0.0);
+  for (int64_t k = 0; k < (L.d == 3 ? w : 1); ++k)
+    for (int64_t j = 0; j < w; ++j)
+      for (int64_t i = 0; i < w; ++i) out[(size_t)(i + j * L.pitch + k * L.plane)] = a[i + w * (j + w * k)];
+  return out;
+}
+
+template <typename T>
+void upload_lattice(qmg_grid_t* g, const Lat& L, const double* host, T* dst) {
+  std::vector<double> p = pitch_in(L, host);
+  QMG_HIP(hipMemcpyAsync(g->stage, p.data(), p.size() * sizeof(double), hipMemcpyHostToDevice, S(g)));
+  if (sizeof(T) == sizeof(double))
+    QMG_HIP(hipMemcpyAsync(dst, g->stage, p.size() * sizeof(double), hipMemcpyDeviceToDevice, S(g)));
+  else
+    launch_convert<double, float>(L, g->stage, (float*)dst, S(g));
+  QMG_HIP(hipStreamSynchronize(S(g)));
+}
+
+template <typename T>
+void download_lattice(qmg_grid_t* g, const Lat& L, const T* src, double* host) {
+  if (sizeof(T) == sizeof(double))
+    QMG_HIP(hipMemcpyAsync(g->stage, src, L.nslot * sizeof(double), hipMemcpyDeviceToDevice, S(g)));
+  else
+    launch_convert<float, double>(L, (const float*)src, g->stage, S(g));
+  std::vector<double> h((size_t)L.nslot);
+  QMG_HIP(hipMemcpyAsync(h.data(), g->stage, h.size() * sizeof(double), hipMemcpyDeviceToHost, S(g)));
+  QMG_HIP(hipStreamSynchronize(S(g)));
+  std::vector<double> o = unpitch(L, h, 1);
+  std::memcpy(host, o.data(), o.size() * sizeof(double));
+}
+
+template <typename T>
+void apply_op(qmg_grid_t* g, int op, int level, const double* x, const double* b, double* out) {
+  if (level < g->lc || level > g->Lmax) throw ApiError(QMG_EINVAL, "level outside the built hierarchy");
+  LevelBuf& B = g->lv[level];
+  const T om = (T)g->opts.omega;
+  if (op == QMG_OP_RESTRICT || op == QMG_OP_PROLONG) {
+    if (level <= g->lc) throw ApiError(QMG_EINVAL, "transfer needs level > coarsest level");
+    LevelBuf& C = g->lv[level - 1];
+    if (op == QMG_OP_RESTRICT) {
+      upload_lattice<T>(g, B.L, x, (T*)B.r);
+      launch_zero<T>((T*)C.b, C.L.nslot, S(g));
+      launch_restrict<T>(B.L, C.L, (const T*)B.r, (T*)C.b, B.P, S(g));
+      download_lattice<T>(g, C.L, (const T*)C.b, out);
+    } else {
+      upload_lattice<T>(g, C.L, x, (T*)C.u);
+      if (b) upload_lattice<T>(g, B.L, b, (T*)B.u);
+      else launch_zero<T>((T*)B.u, B.L.nslot, S(g));
+      launch_prolong<T>(B.L, C.L, (const T*)C.u, (T*)B.u, B.P, S(g));
+      download_lattice<T>(g, B.L, (const T*)B.u, out);
+    }
+    return;
+  }
+  upload_lattice<T>(g, B.L, x, (T*)B.u);
+  if (b) upload_lattice<T>(g, B.L, b, (T*)B.b);
+  else launch_zero<T>((T*)B.b, B.L.nslot, S(g));
+  launch_zero<T>((T*)B.t, B.L.nslot, S(g));
+  const int mode = op == QMG_OP_MATVEC ? 3 : op == QMG_OP_RESIDUAL ? 2 : 0;
+  launch_stencil<T>(B.L, mode, (const T*)B.u, (const T*)B.b, (T*)B.t, eps_of<T>(B), B.A, om, nullptr,
+                    nullptr, S(g));
+  download_lattice<T>(g, B.L, (const T*)B.t, out);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* qmg_version(void) { return "qmg-mi355x 0.1 (gfx950)"; }
+
+int qmg_default_opts(qmg_solver_opts* o) {
+  if (!o) return QMG_EINVAL;
+  o->transfer = QMG_BOXMG;
+  o->store = QMG_HIER_FP64;
+  o->mu_pre = 2;
+  o->mu_post = 2;
+  o->omega = 0.6;
+  o->coarsest_level = 1;
+  o->check_definite = 1;
+  o->inner_cycles = 1;
+  return QMG_OK;
+}
+
+int qmg_workspace_bytes(const qmg_grid_desc* desc, const qmg_solver_opts* opts, size_t* bytes) {
+  return guard(nullptr, [&] {
+    validate(desc, opts);
+    if (!bytes) throw ApiError(QMG_EINVAL, "null bytes");
+    qmg_grid_t g;
+    init_modes(&g, desc, opts);
+    Arena a;
+    layout(&g, a);
+    *bytes = a.off + 256;
+  });
+}
+
+int qmg_create_grid(const qmg_grid_desc* desc, const qmg_solver_opts* opts, void* device_buf,
+                    size_t bytes, void* stream, qmg_grid_t** out) {
+  return guard(nullptr, [&] {
+    validate(desc, opts);
+    if (!out) throw ApiError(QMG_EINVAL, "null output handle");
+    *out = nullptr;
+    qmg_grid_t* g = new qmg_grid_t();
+    try {
+      init_modes(g, desc, opts);
+      g->stream = (hipStream_t)stream;
+      Arena probe;
+      layout(g, probe);
+      const size_t need = probe.off + 256;
+      if (device_buf) {
+        if (bytes < need)
+          throw ApiError(QMG_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+        g->base = (char*)device_buf;
+        g->bytes = bytes;
+      } else {
+        void* p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess) {
+          (void)hipGetLastError();
+          throw ApiError(QMG_ENOMEM, "device allocation of " + std::to_string(need) + " bytes failed");
+        }
+        g->base = (char*)p;
+        g->bytes = need;
+        g->owns = true;
+      }
+      Arena a;
+      a.base = (char*)(((uintptr_t)g->base + 255) & ~(uintptr_t)255);
+      layout(g, a);
+      QMG_HIP(hipMemsetAsync(g->base, 0, need, g->stream));
+      QMG_HIP(hipStreamSynchronize(g->stream));
+      g->n_unknowns = n_interior(g->lv[g->Lmax].L);
+    } catch (...) {
+      if (g->owns && g->base) (void)hipFree(g->base);
+      delete g;
+      throw;
+    }
+    *out = g;
+  });
+}
+
+int qmg_sizes(const qmg_grid_t* g, int64_t* n_unknowns, int64_t* n_leaf_cells, int* n_levels) {
+  if (!g) return QMG_EINVAL;
+  const Lat& L = g->lv[g->Lmax].L;
+  if (n_unknowns) *n_unknowns = g->n_unknowns;
+  if (n_leaf_cells) *n_leaf_cells = g->d == 3 ? (int64_t)L.n * L.n * L.n : (int64_t)L.n * L.n;
+  if (n_levels) *n_levels = g->Lmax + 1;
+  return QMG_OK;
+}
+
+int qmg_unknown_coords(const qmg_grid_t* g, double* xyz) {
+  if (!g || !xyz) return QMG_EINVAL;
+  const Lat& L = g->lv[g->Lmax].L;
+  const int m = L.n - 1;
+  for (int64_t r = 0; r < g->n_unknowns; ++r) {
+    xyz[r * g->d + 0] = (double)(r % m + 1) * L.h;
+    xyz[r * g->d + 1] = (double)((r / m) % m + 1) * L.h;
+    if (g->d == 3) xyz[r * g->d + 2] = (double)(r / ((int64_t)m * m) + 1) * L.h;
+  }
+  return QMG_OK;
+}
+
+int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const double* f, int mem) {
+  return guard(g, [&] {
+    if (!g || !eps || !f) throw ApiError(QMG_EINVAL, "null argument");
+    if (ncomp != 1) throw ApiError(QMG_EINVAL, "only scalar coefficients (ncomp = 1) are supported");
+    if (mem != QMG_HOST && mem != QMG_DEVICE) throw ApiError(QMG_EINVAL, "bad mem flag");
+    LevelBuf& F = g->lv[g->Lmax];
+    const Lat& L = F.L;
+    const int64_t ncell = L.d == 3 ? (int64_t)L.n * L.n * L.n : (int64_t)L.n * L.n;
+    const int64_t nu = g->n_unknowns;
+    std::vector<double> he, hf;
+    const double* pe = eps;
+    const double* pf = f;
+    if (mem == QMG_DEVICE) {
+      he.resize(ncell);
+      hf.resize(nu);
+      QMG_HIP(hipMemcpy(he.data(), eps, ncell * sizeof(double), hipMemcpyDeviceToHost));
+      QMG_HIP(hipMemcpy(hf.data(), f, nu * sizeof(double), hipMemcpyDeviceToHost));
+      pe = he.data();
+      pf = hf.data();
+    }
+    for (int64_t c = 0; c < ncell; ++c)
+      if (!(pe[c] > 0.0) || !std::isfinite(pe[c])) throw ApiError(QMG_EINVAL, "eps must be positive and finite");
+    double hd = 1.0;
+    for (int i = 0; i < g->d; ++i) hd *= L.h;
+    std::vector<double> b(nu);
+    double s2 = 0.0;
+    for (int64_t r = 0; r < nu; ++r) {
+      if (!std::isfinite(pf[r])) throw ApiError(QMG_EINVAL, "f must be finite");
+      b[r] = hd * pf[r];
+      s2 += b[r] * b[r];
+    }
+    g->bnorm = std::sqrt(s2);
+    QMG_HIP(hipMemcpyAsync(g->stage, pe, ncell * sizeof(double), hipMemcpyHostToDevice, S(g)));
+    launch_scatter_cells<double>(L, g->stage, F.eps64, S(g));
+    QMG_HIP(hipMemcpyAsync(g->stage, b.data(), nu * sizeof(double), hipMemcpyHostToDevice, S(g)));
+    if (g->mixed) {
+      launch_scatter_unknowns<double>(L, g->stage, g->bfin, S(g));
+      launch_zero<double>(g->x64, L.nslot, S(g));
+    } else {
+      launch_scatter_unknowns<double>(L, g->stage, (double*)F.b, S(g));
+      launch_zero<double>((double*)F.u, L.nslot, S(g));
+    }
+    QMG_HIP(hipStreamSynchronize(S(g)));
+    g->have_coef = true;
+    g->have_ops = false;
+  });
+}
+
+int qmg_build_operators(qmg_grid_t* g, qmg_solve_report* info) {
+  return guard(g, [&] {
+    if (!g) throw ApiError(QMG_EINVAL, "null grid");
+    build(g, info);
+  });
+}
+
+int qmg_vcycle(qmg_grid_t* g, int n, double* relres) {
+  return guard(g, [&] {
+    need_ops(g);
+    if (n < 0) throw ApiError(QMG_EINVAL, "negative cycle count");
+    for (int c = 0; c < n; ++c) {
+      if (g->mixed) finest_residual_norm(g);  // forms the inner right-hand side
+      one_cycle(g);
+      if (relres) relres[c] = finest_residual_norm(g) / g->bnorm;
+    }
+    QMG_HIP(hipStreamSynchronize(S(g)));
+  });
+}
+
+int qmg_solve(qmg_grid_t* g, double rel_tol, int max_cycles, double* history, qmg_solve_report* rep) {
+  int status = QMG_OK;
+  const int rc = guard(g, [&] {
+    need_ops(g);
+    if (max_cycles < 0 || !(rel_tol >= 0.0)) throw ApiError(QMG_EINVAL, "bad tolerance or cycle limit");
+    const auto t0 = std::chrono::steady_clock::now();
+    int cycles = 0, outer = 0;
+    double rr = (g->bnorm > 0) ? finest_residual_norm(g) / g->bnorm : 0.0;
+    ++outer;
+    while (rr > rel_tol && cycles < max_cycles) {
+      one_cycle(g);
+      rr = finest_residual_norm(g) / g->bnorm;
+      ++outer;
+      if (history) history[cycles] = rr;
+      ++cycles;
+      if (!std::isfinite(rr)) break;
+    }
+    if (rep) {
+      std::memset(rep, 0, sizeof(*rep));
+      rep->cycles = cycles * (g->mixed ? g->opts.inner_cycles : 1);
+      rep->outer_iters = outer;
+      rep->relres = rr;
+      rep->coarsest_level_used = g->lc;
+      rep->vertex_updates = (int64_t)cycles * (g->mixed ? g->opts.inner_cycles : 1) * updates_per_cycle(g);
+      rep->bytes_operators = g->bytes_ops;
+      rep->zero_delta_fraction = g->zero_frac;
+      rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!(rr <= rel_tol)) {
+      status = QMG_ENOTCONV;
+      set_err(g, "tolerance not reached: relres " + std::to_string(rr) + " after " + std::to_string(cycles) + " cycles");
+    }
+  });
+  return rc != QMG_OK ? rc : status;
+}
+
+int qmg_get_solution(const qmg_grid_t* cg, double* u, int mem) {
+  qmg_grid_t* g = const_cast<qmg_grid_t*>(cg);
+  return guard(g, [&] {
+    if (!g || !u) throw ApiError(QMG_EINVAL, "null argument");
+    LevelBuf& F = g->lv[g->Lmax];
+    const double* src = g->mixed ? g->x64 : (const double*)F.u;
+    launch_gather_unknowns<double>(F.L, src, g->stage, S(g));
+    QMG_HIP(hipMemcpyAsync(u, g->stage, g->n_unknowns * sizeof(double),
+                           mem == QMG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, S(g)));
+    QMG_HIP(hipStreamSynchronize(S(g)));
+  });
+}
+
+int qmg_set_solution(qmg_grid_t* g, const double* u, int mem) {
+  return guard(g, [&] {
+    if (!g || !u) throw ApiError(QMG_EINVAL, "null argument");
+    LevelBuf& F = g->lv[g->Lmax];
+    copy_in(g, g->stage, u, g->n_unknowns, mem);
+    launch_scatter_unknowns<double>(F.L, g->stage, g->mixed ? g->x64 : (double*)F.u, S(g));
+    QMG_HIP(hipStreamSynchronize(S(g)));
+  });
+}
+
+int qmg_profile_enable(qmg_grid_t* g, int on) {
+  return guard(g, [&] {
+    if (!g) throw ApiError(QMG_EINVAL, "null grid");
+    prof_harvest(g);
+    g->prof_on = on != 0;
+  });
+}
+
+int qmg_profile_read(qmg_grid_t* g, int64_t* launches, double* total_ms) {
+  return guard(g, [&] {
+    if (!g || !launches || !total_ms) throw ApiError(QMG_EINVAL, "null argument");
+    prof_harvest(g);
+    *launches = g->prof_launches;
+    *total_ms = g->prof_ms;
+    g->prof_launches = 0;
+    g->prof_ms = 0.0;
+  });
+}
+
+int qmg_destroy_grid(qmg_grid_t* g) {
+  if (!g) return QMG_EINVAL;
+  int rc = QMG_OK;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  else (void)hipDeviceSynchronize();
+  for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
+  if (g->owns && g->base && hipFree(g->base) != hipSuccess) rc = QMG_EHIP;
+  delete g;
+  return rc;
+}
+
+const char* qmg_last_error(const qmg_grid_t* g) {
+  if (g) return g->err.c_str();
+  return g_thread_err.c_str();
+}
+
+int qmg_get_operator(const qmg_grid_t* cg, int level, double* stencils) {
+  qmg_grid_t* g = const_cast<qmg_grid_t*>(cg);
+  return guard(g, [&] {
+    if (!g || !stencils) throw ApiError(QMG_EINVAL, "null argument");
+    if (level < g->lcq || level > g->Lmax) throw ApiError(QMG_EINVAL, "level out of range");
+    if (level < g->Lmax && !g->have_ops) throw ApiError(QMG_ESTATE, "operators not built");
+    if (level < g->lc) throw ApiError(QMG_EINVAL, "level below the coarsest level used");
+    LevelBuf& B = g->lv[level];
+    const int NS = ipow(3, g->d);
+    double* tmp = nullptr;
+    QMG_HIP(hipMalloc(&tmp, (size_t)NS * B.L.nslot * sizeof(double)));
+    std::vector<double> h((size_t)NS * B.L.nslot);
+    try {
+      launch_zero<double>(tmp, (int64_t)NS * B.L.nslot, S(g));
+      if (level == g->lc && !g->plain && g->opts.transfer != QMG_GEOMETRIC && level < g->Lmax) {
+        // the coarsest level keeps its full FP64 Galerkin operator for the solve
+        QMG_HIP(hipMemcpyAsync(tmp, g->tmpA[level & 1], h.size() * sizeof(double), hipMemcpyDeviceToDevice, S(g)));
+      } else {
+        launch_materialise(B.L, B.eps64, B.A, tmp, S(g));
+      }
+      QMG_HIP(hipMemcpyAsync(h.data(), tmp, h.size() * sizeof(double), hipMemcpyDeviceToHost, S(g)));
+      QMG_HIP(hipStreamSynchronize(S(g)));
+    } catch (...) {
+      (void)hipFree(tmp);
+      throw;
+    }
+    QMG_HIP(hipFree(tmp));
+    std::vector<double> o = unpitch(B.L, h, NS);
+    std::memcpy(stencils, o.data(), o.size() * sizeof(double));
+  });
+}
+
+int qmg_get_prolongation(const qmg_grid_t* cg, int level, double* weights) {
+  qmg_grid_t* g = const_cast<qmg_grid_t*>(cg);
+  return guard(g, [&] {
+    if (!g || !weights) throw ApiError(QMG_EINVAL, "null argument");
+    if (!g->have_ops) throw ApiError(QMG_ESTATE, "operators not built");
+    if (level <= g->lc || level > g->Lmax) throw ApiError(QMG_EINVAL, "level out of range");
+    LevelBuf& B = g->lv[level];
+    const int NC = 1 << g->d;
+    double* tmp = nullptr;
+    QMG_HIP(hipMalloc(&tmp, (size_t)NC * B.L.nslot * sizeof(double)));
+    std::vector<double> h((size_t)NC * B.L.nslot);
+    try {
+      launch_zero<double>(tmp, (int64_t)NC * B.L.nslot, S(g));
+      launch_materialise_P(B.L, g->lv[level - 1].L, B.P, tmp, S(g));
+      QMG_HIP(hipMemcpyAsync(h.data(), tmp, h.size() * sizeof(double), hipMemcpyDeviceToHost, S(g)));
+      QMG_HIP(hipStreamSynchronize(S(g)));
+    } catch (...) {
+      (void)hipFree(tmp);
+      throw;
+    }
+    QMG_HIP(hipFree(tmp));
+    std::vector<double> o = unpitch(B.L, h, NC);
+    std::memcpy(weights, o.data(), o.size() * sizeof(double));
+  });
+}
+
+int qmg_apply(qmg_grid_t* g, int op, int level, const double* x, const double* b, double* out) {
+  return guard(g, [&] {
+    if (!g || !x || !out) throw ApiError(QMG_EINVAL, "null argument");
+    if (op < QMG_OP_MATVEC || op > QMG_OP_PROLONG) throw ApiError(QMG_EINVAL, "bad op");
+    if (!g->have_coef) throw ApiError(QMG_ESTATE, "coefficients not set");
+    if (level < g->Lmax && !g->have_ops) throw ApiError(QMG_ESTATE, "operators not built");
+    if ((op == QMG_OP_RESTRICT || op == QMG_OP_PROLONG) && !g->have_ops)
+      throw ApiError(QMG_ESTATE, "operators not built");
+    if (g->mixed) {
+      if (!g->have_ops)  // eps32 of the finest level is set at build
+        launch_convert<double, float>(g->lv[g->Lmax].L, g->lv[g->Lmax].eps64, g->lv[g->Lmax].eps32, S(g));
+      apply_op<float>(g, op, level, x, b, out);
+    } else {
+      apply_op<double>(g, op, level, x, b, out);
+    }
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,578 @@
+// Operator construction kernels: coefficient coarsening, BoxMG prolongation
+// (Sect. 3.4 and the BoxMG appendix), Galerkin R A P (Sect. 3.3) with the
+// definiteness check, and the hierarchical delta store (Sect. 4).  All FP64.
+#include "device_ops.hpp"
+
+namespace qmg {
+
+namespace {
+
+constexpr int TX = 64, TY = 4;
+
+inline dim3 tile_grid(const Lat& L) {
+  return dim3((unsigned)(L.pitch / TX), (unsigned)((L.n + 1 + TY - 1) / TY),
+              (unsigned)(L.d == 3 ? L.n + 1 : 1));
+}
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+__device__ inline bool interior(const Lat& L, int i, int j, int k) {
+  return i >= 1 && i < L.n && j >= 1 && j < L.n && (L.d == 2 || (k >= 1 && k < L.n));
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_coarsen_eps(Lat Lf, Lat Lc, const double* __restrict__ ef,
+                                                     double* __restrict__ ec) {
+  const int I = blockIdx.x * TX + threadIdx.x;
+  const int J = blockIdx.y * TY + threadIdx.y;
+  const int K = (D == 3) ? (int)blockIdx.z : 0;
+  if (I >= Lc.n || J >= Lc.n || (D == 3 && K >= Lc.n)) return;
+  double s = 0.0;
+  const int zc = (D == 3) ? 3 : 1;
+  for (int c = 0; c < zc; ++c)
+    for (int b = 0; b < 3; ++b)
+      for (int a = 0; a < 3; ++a)
+        s += ef[(3 * I + a) + (int64_t)(3 * J + b) * Lf.pitch + (int64_t)(3 * K + c) * Lf.plane];
+  ec[I + (int64_t)J * Lc.pitch + (int64_t)K * Lc.plane] = s / (D == 3 ? 27.0 : 9.0);
+}
+
+// Operator row of an interior vertex as the smoother applies it, with entries
+// pointing at boundary vertices dropped.
+template <int D, int SRC, int FMT>
+__global__ __launch_bounds__(256) void k_materialise(Lat L, const double* __restrict__ eps, Store A,
+                                                     double* __restrict__ out) {
+  constexpr int NS = Dim<D>::NS;
+  const int i = blockIdx.x * TX + threadIdx.x;
+  const int j = blockIdx.y * TY + threadIdx.y;
+  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+  if (!interior(L, i, j, kz)) return;
+  const int64_t v = i + (int64_t)j * L.pitch + (int64_t)kz * L.plane;
+  double a[NS];
+  if (SRC == SRC_PLAIN) {
+    for (int k = 0; k < NS; ++k) a[k] = ((const double*)A.dense)[(int64_t)k * L.nslot + v];
+  } else {
+    geom_row<D, double>(eps, v, L, a);
+    if (SRC == SRC_HIER) add_delta<FMT, NS, double>(A, v, a);
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const bool in = interior(L, i + off_x(k), j + off_y(k), kz + (D == 3 ? off_z(k) : 0));
+    out[(int64_t)k * L.nslot + v] = in ? a[k] : 0.0;
+  }
+}
+
+// d-linear weight of parent floor(f/3)+kappa with non-parents and boundary
+// coarse vertices dropped.
+template <int D>
+__device__ inline double dlin_dropped(const Lat& Lc, int i, int j, int k, int kap) {
+  const int kx = kap & 1, ky = (kap >> 1) & 1, kz = (kap >> 2) & 1;
+  const int qx = i / 3, qy = j / 3, qz = k / 3;
+  const int rx = i - 3 * qx, ry = j - 3 * qy, rz = k - 3 * qz;
+  if ((kx && rx == 0) || (ky && ry == 0) || (D == 3 && kz && rz == 0)) return 0.0;
+  if (!interior(Lc, qx + kx, qy + ky, D == 3 ? qz + kz : 0)) return 0.0;
+  return dlin1(rx, kx) * dlin1(ry, ky) * (D == 3 ? dlin1(rz, kz) : 1.0);
+}
+
+template <int D, int SRC, int FMT>
+__global__ __launch_bounds__(256) void k_materialise_P(Lat Lf, Lat Lc, Store P, double* __restrict__ out) {
+  const int i = blockIdx.x * TX + threadIdx.x;
+  const int j = blockIdx.y * TY + threadIdx.y;
+  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+  if (!interior(Lf, i, j, kz)) return;
+  const int64_t v = i + (int64_t)j * Lf.pitch + (int64_t)kz * Lf.plane;
+  double w[Dim<D>::NC];
+  for (int c = 0; c < Dim<D>::NC; ++c) {
+    if (SRC == SRC_PLAIN) w[c] = ((const double*)P.dense)[(int64_t)c * Lf.nslot + v];
+    else w[c] = dlin_dropped<D>(Lc, i, j, kz, c);
+  }
+  if (SRC == SRC_HIER) add_delta<FMT, Dim<D>::NC, double>(P, v, w);
+  for (int c = 0; c < Dim<D>::NC; ++c) out[(int64_t)c * Lf.nslot + v] = w[c];
+}
+
+// ---------------------------------------------------------------------------
+// BoxMG.  One thread per (interior coarse vertex V, orthant sigma).  In the
+// reference frame y in {0..3}^d the fine vertex is 3V + sigma*y and the stencil
+// offset o' is the true offset sigma*o'.  Unknowns p(y), y in {0,1,2}^d; p = 0
+// where a coordinate is 3.  Groups are solved in order: c-point (p = 1), lines
+// (stencil collapsed onto the line's axis), faces in 3D (collapsed along the
+// normal), interior (full stencils), each group depending only on earlier ones.
+// ---------------------------------------------------------------------------
+template <int D>
+struct BoxFetch {
+  const double* A;  // FP64 stencils (entry-major) or null: rediscretise from eps
+  const double* eps;
+  Lat L;
+  __device__ double operator()(int64_t v, int i, int j, int k, int kk) const {
+    if (A) return A[(int64_t)kk * L.nslot + v];
+    return geom_entry<D>(eps, v, i, j, k, kk, L);
+  }
+};
+
+__host__ __device__ constexpr int pidx(int yx, int yy, int yz) { return yx + 3 * yy + 9 * yz; }
+
+template <int D, int S>
+__device__ inline void box_group(const BoxFetch<D>& F, int Vx, int Vy, int Vz, int sx, int sy, int sz,
+                                 double (&p)[27]) {
+  // unknowns: y with y_i in {1,2} for i in S, 0 otherwise
+  constexpr int m = 1 << ((S & 1) + ((S >> 1) & 1) + ((S >> 2) & 1));
+  double M[m][m];
+  double rhs[m];
+#pragma unroll
+  for (int r = 0; r < m; ++r) {
+    rhs[r] = 0.0;
+#pragma unroll
+    for (int c = 0; c < m; ++c) M[r][c] = 0.0;
+  }
+  // enumerate group members: bit b of r selects value 1 or 2 on the b-th axis of S
+#pragma unroll
+  for (int r = 0; r < m; ++r) {
+    int y[3] = {0, 0, 0};
+    {
+      int bit = 0;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax)
+        if (S & (1 << ax)) { y[ax] = 1 + ((r >> bit) & 1); ++bit; }
+    }
+    const int fx = 3 * Vx + sx * y[0], fy = 3 * Vy + sy * y[1], fz = 3 * Vz + sz * y[2];
+    const int64_t v = fx + (int64_t)fy * F.L.pitch + (int64_t)fz * F.L.plane;
+#pragma unroll
+    for (int k = 0; k < Dim<D>::NS; ++k) {
+      const int o[3] = {off_x(k), off_y(k), D == 3 ? off_z(k) : 0};
+      int w[3];
+      bool far = false, ingroup = true;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        w[ax] = y[ax] + ((S & (1 << ax)) ? o[ax] : 0);
+        if (w[ax] == 3) far = true;
+        const bool nz = w[ax] != 0;
+        if (nz != (((S >> ax) & 1) != 0)) ingroup = false;
+      }
+      if (far) continue;
+      const int ks = (sx * o[0] + 1) + 3 * (sy * o[1] + 1) + (D == 3 ? 9 * (sz * o[2] + 1) : 0);
+      const double a = F(v, fx, fy, fz, ks);
+      if (ingroup) {
+        int col = 0, bit = 0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax)
+          if (S & (1 << ax)) { col |= (w[ax] - 1) << bit; ++bit; }
+        M[r][col] += a;
+      } else {
+        rhs[r] -= a * p[pidx(w[0], w[1], w[2])];
+      }
+    }
+  }
+  // Gaussian elimination (the systems are diagonally dominant M-matrices for
+  // FEM stencils of positive coefficients; no pivoting)
+#pragma unroll
+  for (int c = 0; c < m; ++c) {
+    const double inv = 1.0 / M[c][c];
+#pragma unroll
+    for (int r = c + 1; r < m; ++r) {
+      const double f = M[r][c] * inv;
+#pragma unroll
+      for (int q = c; q < m; ++q) M[r][q] -= f * M[c][q];
+      rhs[r] -= f * rhs[c];
+    }
+  }
+  double sol[m];
+#pragma unroll
+  for (int c = m - 1; c >= 0; --c) {
+    double t = rhs[c];
+#pragma unroll
+    for (int q = c + 1; q < m; ++q) t -= M[c][q] * sol[q];
+    sol[c] = t / M[c][c];
+  }
+#pragma unroll
+  for (int r = 0; r < m; ++r) {
+    int y[3] = {0, 0, 0};
+    int bit = 0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+      if (S & (1 << ax)) { y[ax] = 1 + ((r >> bit) & 1); ++bit; }
+    p[pidx(y[0], y[1], y[2])] = sol[r];
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(64) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, double* __restrict__ Pw) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int m = Lc.n - 1;
+  const int64_t nV = (D == 3) ? (int64_t)m * m * m : (int64_t)m * m;
+  if (t >= nV * Dim<D>::NC) return;
+  const int orth = (int)(t % Dim<D>::NC);
+  const int64_t Vi = t / Dim<D>::NC;
+  const int Vx = (int)(Vi % m) + 1, Vy = (int)((Vi / m) % m) + 1, Vz = (D == 3) ? (int)(Vi / ((int64_t)m * m)) + 1 : 0;
+  const int sx = (orth & 1) ? -1 : 1, sy = (orth & 2) ? -1 : 1, sz = (D == 3 && (orth & 4)) ? -1 : 1;
+  double p[27];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) p[q] = 0.0;
+  p[0] = 1.0;
+  box_group<D, 1>(F, Vx, Vy, Vz, sx, sy, sz, p);
+  box_group<D, 2>(F, Vx, Vy, Vz, sx, sy, sz, p);
+  if constexpr (D == 3) {
+    box_group<D, 4>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    box_group<D, 5>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    box_group<D, 6>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    box_group<D, 7>(F, Vx, Vy, Vz, sx, sy, sz, p);
+  } else {
+    box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p);
+  }
+  // write the reference region; a point on an axis (y_i = 0) is shared by the
+  // orthants that differ only on that axis and is written by the + orthant
+  const int zmax = (D == 3) ? 3 : 1;
+  for (int yz = 0; yz < zmax; ++yz)
+    for (int yy = 0; yy < 3; ++yy)
+      for (int yx = 0; yx < 3; ++yx) {
+        if ((yx == 0 && sx < 0) || (yy == 0 && sy < 0) || (D == 3 && yz == 0 && sz < 0)) continue;
+        const int fx = 3 * Vx + sx * yx, fy = 3 * Vy + sy * yy, fz = 3 * Vz + sz * yz;
+        const int kap = ((sx < 0 && yx > 0) ? 1 : 0) | ((sy < 0 && yy > 0) ? 2 : 0) |
+                        ((D == 3 && sz < 0 && yz > 0) ? 4 : 0);
+        const int64_t vf = fx + (int64_t)fy * Lf.pitch + (int64_t)fz * Lf.plane;
+        Pw[(int64_t)kap * Lf.nslot + vf] = p[pidx(yx, yy, yz)];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin product.  One thread per (interior coarse vertex V, offset delta):
+// A_c(V, V+delta) = sum_i sum_j P(i,V) a(i,j) P(j,V+delta), i within 2 of 3V
+// and j within 2 of 3(V+delta) on every axis, |i - j| <= 1.
+// ---------------------------------------------------------------------------
+template <int D>
+struct PFetch {
+  const double* W;  // FP64 parent weights (2^d * nslot) or null for d-linear
+  Lat Lf, Lc;
+  // weight of coarse vertex (Vx,Vy,Vz) at fine (i,j,k); the caller guarantees
+  // |f - 3V| <= 2 per axis
+  __device__ double operator()(int i, int j, int k, int Vx, int Vy, int Vz) const {
+    const int kx = Vx - i / 3, ky = Vy - j / 3, kz = (D == 3) ? Vz - k / 3 : 0;
+    if (W) {
+      const int64_t v = i + (int64_t)j * Lf.pitch + (int64_t)k * Lf.plane;
+      return W[(int64_t)(kx | (ky << 1) | (kz << 2)) * Lf.nslot + v];
+    }
+    double w = (1.0 - abs(i - 3 * Vx) / 3.0) * (1.0 - abs(j - 3 * Vy) / 3.0);
+    if (D == 3) w *= (1.0 - abs(k - 3 * Vz) / 3.0);
+    return w;
+  }
+};
+
+template <int D>
+__global__ __launch_bounds__(256) void k_rap(Lat Lf, Lat Lc, BoxFetch<D> A, PFetch<D> P,
+                                             double* __restrict__ Ac) {
+  constexpr int NS = Dim<D>::NS;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int m = Lc.n - 1;
+  const int64_t nV = (D == 3) ? (int64_t)m * m * m : (int64_t)m * m;
+  if (t >= nV * NS) return;
+  const int kd = (int)(t % NS);
+  const int64_t Vi = t / NS;
+  const int Vx = (int)(Vi % m) + 1, Vy = (int)((Vi / m) % m) + 1, Vz = (D == 3) ? (int)(Vi / ((int64_t)m * m)) + 1 : 0;
+  const int Wx = Vx + off_x(kd), Wy = Vy + off_y(kd), Wz = Vz + (D == 3 ? off_z(kd) : 0);
+  const int64_t vc = Vx + (int64_t)Vy * Lc.pitch + (int64_t)Vz * Lc.plane;
+  double acc = 0.0;
+  if (interior(Lc, Wx, Wy, Wz)) {
+    const int ilx = max(3 * Vx - 2, 3 * Wx - 3), ihx = min(3 * Vx + 2, 3 * Wx + 3);
+    const int ily = max(3 * Vy - 2, 3 * Wy - 3), ihy = min(3 * Vy + 2, 3 * Wy + 3);
+    const int ilz = (D == 3) ? max(3 * Vz - 2, 3 * Wz - 3) : 0, ihz = (D == 3) ? min(3 * Vz + 2, 3 * Wz + 3) : 0;
+    for (int iz = ilz; iz <= ihz; ++iz)
+      for (int iy = ily; iy <= ihy; ++iy)
+        for (int ix = ilx; ix <= ihx; ++ix) {
+          const double pi = P(ix, iy, iz, Vx, Vy, Vz);
+          if (pi == 0.0) continue;
+          const int64_t vi = ix + (int64_t)iy * Lf.pitch + (int64_t)iz * Lf.plane;
+          double s = 0.0;
+          for (int k = 0; k < NS; ++k) {
+            const int jx = ix + off_x(k), jy = iy + off_y(k), jz = iz + (D == 3 ? off_z(k) : 0);
+            if (abs(jx - 3 * Wx) > 2 || abs(jy - 3 * Wy) > 2 || (D == 3 && abs(jz - 3 * Wz) > 2)) continue;
+            const double pj = P(jx, jy, jz, Wx, Wy, Wz);
+            if (pj == 0.0) continue;
+            s += A(vi, ix, iy, iz, k) * pj;
+          }
+          acc += pi * s;
+        }
+  }
+  Ac[(int64_t)kd * Lc.nslot + vc] = acc;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_check_rows(Lat Lc, const double* __restrict__ Ac,
+                                                    int* __restrict__ bad) {
+  constexpr int NS = Dim<D>::NS;
+  const int i = blockIdx.x * TX + threadIdx.x;
+  const int j = blockIdx.y * TY + threadIdx.y;
+  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+  if (!interior(Lc, i, j, kz)) return;
+  const int64_t v = i + (int64_t)j * Lc.pitch + (int64_t)kz * Lc.plane;
+  const double dg = Ac[(int64_t)(NS / 2) * Lc.nslot + v];
+  double off = 0.0;
+  for (int k = 0; k < NS; ++k)
+    if (k != NS / 2) off += fabs(Ac[(int64_t)k * Lc.nslot + v]);
+  if (dg <= 0.0 || dg < (1.0 - kDomSlack) * off) atomicAdd(bad, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Delta store.  One wavefront = one 64-slot block.
+// ---------------------------------------------------------------------------
+template <int D, bool IS_P>
+__device__ inline int load_delta(const Lat& L, const Lat& Lc, const double* __restrict__ full,
+                                 const double* __restrict__ eps, int i, int j, int kz, int64_t v,
+                                 double (&dl)[27], double& refmax) {
+  constexpr int NE = IS_P ? Dim<D>::NC : Dim<D>::NS;
+  refmax = 0.0;
+  if (!interior(L, i, j, kz)) {
+    for (int k = 0; k < NE; ++k) dl[k] = 0.0;
+    return NE;
+  }
+  if (IS_P) {
+    for (int c = 0; c < NE; ++c) {
+      const double r = dlin_dropped<D>(Lc, i, j, kz, c);
+      dl[c] = full[(int64_t)c * L.nslot + v] - r;
+      refmax = fmax(refmax, fabs(r));
+    }
+  } else {
+    double g[Dim<D>::NS];
+    geom_row<D, double>(eps, v, L, g);
+    for (int k = 0; k < NE; ++k) {
+      const bool in = interior(L, i + off_x(k), j + off_y(k), kz + (D == 3 ? off_z(k) : 0));
+      const double r = in ? g[k] : 0.0;
+      dl[k] = full[(int64_t)k * L.nslot + v] - r;
+      refmax = fmax(refmax, fabs(r));
+    }
+  }
+  return NE;
+}
+
+template <int D, bool IS_P>
+__global__ __launch_bounds__(256) void k_delta_flags(Lat L, Lat Lc, const double* __restrict__ full,
+                                                     const double* __restrict__ eps,
+                                                     int32_t* __restrict__ blk) {
+  const int i = blockIdx.x * TX + threadIdx.x;
+  const int j = blockIdx.y * TY + threadIdx.y;
+  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+  const bool inlat = j <= L.n && (D == 2 || kz <= L.n);
+  const int64_t v = i + (int64_t)j * L.pitch + (int64_t)kz * L.plane;
+  double dl[27], refmax;
+  int nz = 0;
+  if (inlat) {
+    const int ne = load_delta<D, IS_P>(L, Lc, full, eps, i, j, kz, v, dl, refmax);
+    double mx = 0.0;
+    for (int k = 0; k < ne; ++k) mx = fmax(mx, fabs(dl[k]));
+    nz = mx > kEpsZero * refmax;
+  }
+  const bool any = __any(nz);
+  if (inlat && threadIdx.x == 0) blk[v / kSeg] = any ? 1 : 0;
+}
+
+// Exclusive scan of 0/1 block flags into compact ids (-1 for zero blocks); one
+// workgroup walks the array in chunks.
+__global__ __launch_bounds__(1024) void k_scan_blocks(int32_t* __restrict__ blk, int64_t nblk,
+                                                      int32_t* __restrict__ total) {
+  __shared__ int32_t wsum[16];
+  __shared__ int32_t base_s;
+  if (threadIdx.x == 0) base_s = 0;
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < nblk; c0 += 1024) {
+    const int64_t idx = c0 + threadIdx.x;
+    const int32_t f = (idx < nblk) ? blk[idx] : 0;
+    // inclusive scan within the wavefront
+    int32_t x = f;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int32_t s = 0;
+      for (int w = 0; w < 16; ++w) {
+        const int32_t t = wsum[w];
+        wsum[w] = s;
+        s += t;
+      }
+    }
+    __syncthreads();
+    const int32_t excl = base_s + wsum[threadIdx.x >> 6] + x - f;
+    if (idx < nblk) blk[idx] = f ? excl : -1;
+    __syncthreads();
+    if (threadIdx.x == 1023) base_s = excl + f;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = base_s;
+}
+
+__device__ inline uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <int D, bool IS_P, int FMT>
+__global__ __launch_bounds__(256) void k_delta_write(Lat L, Lat Lc, const double* __restrict__ full,
+                                                     const double* __restrict__ eps,
+                                                     const int32_t* __restrict__ blk,
+                                                     void* __restrict__ payload,
+                                                     int8_t* __restrict__ scale) {
+  constexpr int NE = IS_P ? Dim<D>::NC : Dim<D>::NS;
+  const int i = blockIdx.x * TX + threadIdx.x;
+  const int j = blockIdx.y * TY + threadIdx.y;
+  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+  if (j > L.n || (D == 3 && kz > L.n)) return;
+  const int64_t v = i + (int64_t)j * L.pitch + (int64_t)kz * L.plane;
+  const int32_t cb = blk[v / kSeg];
+  if (cb < 0) return;
+  double dl[27], refmax;
+  load_delta<D, IS_P>(L, Lc, full, eps, i, j, kz, v, dl, refmax);
+  const int lane = (int)(v % kSeg);
+  const int64_t base = (int64_t)cb * NE * kSeg + lane;
+  if (FMT == F16) {
+    double mx = 0.0;
+    for (int k = 0; k < NE; ++k) mx = fmax(mx, fabs(dl[k]));
+    int E = 0;
+    const double m = frexp(mx, &E);  // mx = m 2^E, m in [0.5, 1)
+    int e = (mx == 0.0) ? 0 : (m == 0.5 ? E - 16 : E - 15);
+    e = max(-128, min(127, e));
+    scale[(int64_t)cb * kSeg + lane] = (int8_t)e;
+    for (int k = 0; k < NE; ++k)
+      ((_Float16*)payload)[base + (int64_t)k * kSeg] = (_Float16)(float)ldexp(dl[k], -e);
+  } else {
+    for (int k = 0; k < NE; ++k) {
+      const int64_t q = base + (int64_t)k * kSeg;
+      if (FMT == F64) ((double*)payload)[q] = dl[k];
+      else if (FMT == F32) ((float*)payload)[q] = (float)dl[k];
+      else ((uint16_t*)payload)[q] = bf16_rne((float)dl[k]);
+    }
+  }
+}
+
+}  // namespace
+
+void launch_coarsen_eps(const Lat& Lf, const Lat& Lc, const double* epsf, double* epsc, hipStream_t s) {
+  const dim3 g = tile_grid(Lc), bl(TX, TY, 1);
+  if (Lf.d == 2) hipLaunchKernelGGL(k_coarsen_eps<2>, g, bl, 0, s, Lf, Lc, epsf, epsc);
+  else hipLaunchKernelGGL(k_coarsen_eps<3>, g, bl, 0, s, Lf, Lc, epsf, epsc);
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_materialise(const Lat& L, const double* eps, const Store& A, double* out, hipStream_t s) {
+  const dim3 g = tile_grid(L), bl(TX, TY, 1);
+#define QMG_MAT(DV, SRCV, FMTV) hipLaunchKernelGGL((k_materialise<DV, SRCV, FMTV>), g, bl, 0, s, L, eps, A, out)
+#define QMG_MAT_D(DV)                                   \
+  do {                                                  \
+    if (A.src == SRC_GEOM) QMG_MAT(DV, SRC_GEOM, F64);  \
+    else if (A.src == SRC_PLAIN) QMG_MAT(DV, SRC_PLAIN, F64); \
+    else if (A.fmt == F64) QMG_MAT(DV, SRC_HIER, F64);  \
+    else if (A.fmt == F32) QMG_MAT(DV, SRC_HIER, F32);  \
+    else if (A.fmt == F16) QMG_MAT(DV, SRC_HIER, F16);  \
+    else QMG_MAT(DV, SRC_HIER, BF16);                   \
+  } while (0)
+  if (L.d == 2) QMG_MAT_D(2);
+  else QMG_MAT_D(3);
+#undef QMG_MAT_D
+#undef QMG_MAT
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_materialise_P(const Lat& Lf, const Lat& Lc, const Store& P, double* out, hipStream_t s) {
+  const dim3 g = tile_grid(Lf), bl(TX, TY, 1);
+#define QMG_MP(DV, SRCV, FMTV) hipLaunchKernelGGL((k_materialise_P<DV, SRCV, FMTV>), g, bl, 0, s, Lf, Lc, P, out)
+#define QMG_MP_D(DV)                                    \
+  do {                                                  \
+    if (P.src == SRC_GEOM) QMG_MP(DV, SRC_GEOM, F64);   \
+    else if (P.src == SRC_PLAIN) QMG_MP(DV, SRC_PLAIN, F64); \
+    else if (P.fmt == F64) QMG_MP(DV, SRC_HIER, F64);   \
+    else if (P.fmt == F32) QMG_MP(DV, SRC_HIER, F32);   \
+    else if (P.fmt == F16) QMG_MP(DV, SRC_HIER, F16);   \
+    else QMG_MP(DV, SRC_HIER, BF16);                    \
+  } while (0)
+  if (Lf.d == 2) QMG_MP_D(2);
+  else QMG_MP_D(3);
+#undef QMG_MP_D
+#undef QMG_MP
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf, double* Pw,
+                  hipStream_t s) {
+  const int m = Lc.n - 1;
+  if (m <= 0) return;
+  if (Lf.d == 2) {
+    const int64_t nt = (int64_t)m * m * 4;
+    BoxFetch<2> F{Afine, epsf, Lf};
+    hipLaunchKernelGGL(k_boxmg<2>, dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw);
+  } else {
+    const int64_t nt = (int64_t)m * m * m * 8;
+    BoxFetch<3> F{Afine, epsf, Lf};
+    hipLaunchKernelGGL(k_boxmg<3>, dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw);
+  }
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
+                const double* Pw, double* Ac, hipStream_t s) {
+  const int m = Lc.n - 1;
+  if (m <= 0) return;
+  if (Lf.d == 2) {
+    const int64_t nt = (int64_t)m * m * 9;
+    BoxFetch<2> A{Afine, epsf, Lf};
+    PFetch<2> P{Pw, Lf, Lc};
+    hipLaunchKernelGGL(k_rap<2>, dim3(blocks_for(nt, 256)), dim3(256), 0, s, Lf, Lc, A, P, Ac);
+  } else {
+    const int64_t nt = (int64_t)m * m * m * 27;
+    BoxFetch<3> A{Afine, epsf, Lf};
+    PFetch<3> P{Pw, Lf, Lc};
+    hipLaunchKernelGGL(k_rap<3>, dim3(blocks_for(nt, 256)), dim3(256), 0, s, Lf, Lc, A, P, Ac);
+  }
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s) {
+  const dim3 g = tile_grid(Lc), bl(TX, TY, 1);
+  if (Lc.d == 2) hipLaunchKernelGGL(k_check_rows<2>, g, bl, 0, s, Lc, Ac, bad);
+  else hipLaunchKernelGGL(k_check_rows<3>, g, bl, 0, s, Lc, Ac, bad);
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_delta_flags(const Lat& L, const Lat& Lc, bool is_P, const double* full, const double* eps,
+                        int32_t* blk, hipStream_t s) {
+  const dim3 g = tile_grid(L), bl(TX, TY, 1);
+  if (L.d == 2) {
+    if (is_P) hipLaunchKernelGGL((k_delta_flags<2, true>), g, bl, 0, s, L, Lc, full, eps, blk);
+    else hipLaunchKernelGGL((k_delta_flags<2, false>), g, bl, 0, s, L, Lc, full, eps, blk);
+  } else {
+    if (is_P) hipLaunchKernelGGL((k_delta_flags<3, true>), g, bl, 0, s, L, Lc, full, eps, blk);
+    else hipLaunchKernelGGL((k_delta_flags<3, false>), g, bl, 0, s, L, Lc, full, eps, blk);
+  }
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_scan_blocks(int32_t* blk, int64_t nblk, int32_t* total, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, blk, nblk, total);
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_delta_write(const Lat& L, const Lat& Lc, bool is_P, int fmt, const double* full,
+                        const double* eps, const int32_t* blk, void* payload, int8_t* scale,
+                        hipStream_t s) {
+  const dim3 g = tile_grid(L), bl(TX, TY, 1);
+#define QMG_DW(DV, PV, FV) hipLaunchKernelGGL((k_delta_write<DV, PV, FV>), g, bl, 0, s, L, Lc, full, eps, blk, payload, scale)
+#define QMG_DW_F(DV, PV)                  \
+  do {                                    \
+    if (fmt == F64) QMG_DW(DV, PV, F64);  \
+    else if (fmt == F32) QMG_DW(DV, PV, F32); \
+    else if (fmt == F16) QMG_DW(DV, PV, F16); \
+    else QMG_DW(DV, PV, BF16);            \
+  } while (0)
+  if (L.d == 2) {
+    if (is_P) QMG_DW_F(2, true);
+    else QMG_DW_F(2, false);
+  } else {
+    if (is_P) QMG_DW_F(3, true);
+    else QMG_DW_F(3, false);
+  }
+#undef QMG_DW_F
+#undef QMG_DW
+  QMG_HIP(hipGetLastError());
+}
+
+}  // namespace qmg

@@ -1,0 +1,391 @@
+// Per-level kernels of the V-cycle: Jacobi smoothing, residual (+ norm
+// partials), matvec, restriction, prolongation, coarsest solve and helpers.
+//
+// Layout: one thread per lattice slot of a 64 x 4 (x, y) tile; blockIdx.z is
+// the z-plane in 3D.  Every wavefront covers 64 consecutive slots of one x-row,
+// which is also the granule of the delta store, so store lookups are uniform
+// per wavefront.  Stencil rows are rebuilt per vertex from the 2^d cell
+// coefficients (rediscretisation on the fly) plus the stored delta, or read
+// from the plain FP64 store.
+#include "device_ops.hpp"
+
+namespace qmg {
+
+namespace {
+
+constexpr int TX = 64, TY = 4;
+
+inline dim3 tile_grid(const Lat& L) {
+  return dim3((unsigned)(L.pitch / TX), (unsigned)((L.n + 1 + TY - 1) / TY),
+              (unsigned)(L.d == 3 ? L.n + 1 : 1));
+}
+
+// Deterministic workgroup sum (fixed shuffle tree, then the 4 wavefronts in order).
+__device__ inline double block_sum_256(double x) {
+  __shared__ double red[4];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+  const int t = threadIdx.x + threadIdx.y * TX;
+  if ((t & 63) == 0) red[t >> 6] = x;
+  __syncthreads();
+  double s = 0.0;
+  if (t == 0) s = ((red[0] + red[1]) + red[2]) + red[3];
+  return s;
+}
+
+template <int D, typename T, typename TO, int SRC, int FMT, int MODE>
+__global__ __launch_bounds__(256) void k_stencil(Lat L, const T* __restrict__ u,
+                                                 const T* __restrict__ b, TO* __restrict__ out,
+                                                 const T* __restrict__ eps, Store A, T omega,
+                                                 double* __restrict__ partial) {
+  constexpr int NS = Dim<D>::NS;
+  const int i = blockIdx.x * TX + threadIdx.x;
+  const int j = blockIdx.y * TY + threadIdx.y;
+  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+  const int n = L.n;
+  const bool act = i >= 1 && i < n && j >= 1 && j < n && (D == 2 || (kz >= 1 && kz < n));
+  double sq = 0.0;
+  if (act) {
+    const int64_t v = i + (int64_t)j * L.pitch + (int64_t)kz * L.plane;
+    T a[NS];
+    if (SRC == SRC_PLAIN) {
+      const double* Ad = (const double*)A.dense;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) a[k] = (T)Ad[(int64_t)k * L.nslot + v];
+    } else {
+      geom_row<D, T>(eps, v, L, a);
+      if (SRC == SRC_HIER) add_delta<FMT, NS, T>(A, v, a);
+    }
+    if (MODE == 1) {
+      out[v] = (TO)(omega * b[v] / a[NS / 2]);
+    } else {
+      T au = (T)0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        if (D == 3 && SRC == SRC_GEOM && kref(3, ndiff_of<3>(k)) == 0.0) continue;
+        au += a[k] * u[v + slot_off(L, off_x(k), off_y(k), D == 3 ? off_z(k) : 0)];
+      }
+      if (MODE == 0) {
+        out[v] = (TO)(u[v] + omega * (b[v] - au) / a[NS / 2]);
+      } else {
+        const T res = (MODE == 3) ? au : b[v] - au;
+        out[v] = (TO)res;
+        sq = (double)res * (double)res;
+      }
+    }
+  }
+  if (partial != nullptr) {
+    const double s = block_sum_256(sq);
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+      partial[blockIdx.x + gridDim.x * ((int64_t)blockIdx.y + gridDim.y * (int64_t)blockIdx.z)] = s;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict__ p, int n,
+                                                       double* __restrict__ out) {
+  __shared__ double red[16];
+  double x = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x += p[i];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    out[0] = s;
+  }
+}
+
+// Weight of the parent floor(f/3)+kappa at fine vertex f (slot vf; r = f mod 3).
+template <int D, int SRC, int FMT>
+__device__ inline double pweight(const Store& P, const Lat& Lf, int64_t vf, int rx, int ry, int rz,
+                                 int kap) {
+  const int kx = kap & 1, ky = (kap >> 1) & 1, kz = (kap >> 2) & 1;
+  if (SRC == SRC_PLAIN) return ((const double*)P.dense)[(int64_t)kap * Lf.nslot + vf];
+  double w = dlin1(rx, kx) * dlin1(ry, ky) * (D == 3 ? dlin1(rz, kz) : 1.0);
+  if (SRC == SRC_HIER) {
+    const int32_t cb = P.blk[vf / kSeg];
+    if (cb >= 0) {
+      const int lane = (int)(vf % kSeg);
+      const int64_t idx = ((int64_t)cb * Dim<D>::NC + kap) * kSeg + lane;
+      double dv = (double)Dec<FMT>::get(P.payload, idx);
+      if (FMT == F16) dv = ldexp(dv, (int)P.scale[(int64_t)cb * kSeg + lane]);
+      w += dv;
+    }
+  }
+  return w;
+}
+
+// b_c(V) = sum over fine f = 3V + o, o in [-2,2]^d, of P(f,V) r(f)  (R = P^T).
+template <int D, typename T, int SRC, int FMT>
+__global__ __launch_bounds__(256) void k_restrict(Lat Lf, Lat Lc, const T* __restrict__ r,
+                                                  T* __restrict__ bc, Store P) {
+  const int I = blockIdx.x * TX + threadIdx.x;
+  const int J = blockIdx.y * TY + threadIdx.y;
+  const int K = (D == 3) ? (int)blockIdx.z : 0;
+  const int nc = Lc.n;
+  if (!(I >= 1 && I < nc && J >= 1 && J < nc && (D == 2 || (K >= 1 && K < nc)))) return;
+  const int64_t vf0 = 3 * I + (int64_t)3 * J * Lf.pitch + (int64_t)3 * K * Lf.plane;
+  T acc = (T)0;
+  const int zlo = (D == 3) ? -2 : 0, zhi = (D == 3) ? 2 : 0;
+#pragma unroll
+  for (int oz = zlo; oz <= zhi; ++oz)
+#pragma unroll
+    for (int oy = -2; oy <= 2; ++oy)
+#pragma unroll
+      for (int ox = -2; ox <= 2; ++ox) {
+        const int64_t vf = vf0 + slot_off(Lf, ox, oy, oz);
+        const int kap = (ox < 0 ? 1 : 0) | (oy < 0 ? 2 : 0) | (oz < 0 ? 4 : 0);
+        double w;
+        if (SRC == SRC_GEOM) {
+          w = (1.0 - abs(ox) / 3.0) * (1.0 - abs(oy) / 3.0) * (D == 3 ? (1.0 - abs(oz) / 3.0) : 1.0);
+        } else {
+          w = pweight<D, SRC, FMT>(P, Lf, vf, (ox + 3) % 3, (oy + 3) % 3, (oz + 3) % 3, kap);
+        }
+        acc += (T)w * r[vf];
+      }
+  bc[I + (int64_t)J * Lc.pitch + (int64_t)K * Lc.plane] = acc;
+}
+
+// u_f = (ADD ? u_f : 0) + sum over parents floor(f/3)+kappa of P(f,V) e_c(V).
+template <int D, typename T, int SRC, int FMT>
+__global__ __launch_bounds__(256) void k_prolong(Lat Lf, Lat Lc, const T* __restrict__ ec,
+                                                 T* __restrict__ uf, Store P) {
+  const int i = blockIdx.x * TX + threadIdx.x;
+  const int j = blockIdx.y * TY + threadIdx.y;
+  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+  const int n = Lf.n;
+  if (!(i >= 1 && i < n && j >= 1 && j < n && (D == 2 || (kz >= 1 && kz < n)))) return;
+  const int64_t vf = i + (int64_t)j * Lf.pitch + (int64_t)kz * Lf.plane;
+  const int qx = i / 3, qy = j / 3, qz = kz / 3;
+  const int rx = i - 3 * qx, ry = j - 3 * qy, rz = kz - 3 * qz;
+  const int64_t vc = qx + (int64_t)qy * Lc.pitch + (int64_t)qz * Lc.plane;
+  T acc = (T)0;
+#pragma unroll
+  for (int kap = 0; kap < Dim<D>::NC; ++kap) {
+    const int kx = kap & 1, ky = (kap >> 1) & 1, kk = (kap >> 2) & 1;
+    if ((kx && rx == 0) || (ky && ry == 0) || (kk && rz == 0)) continue;
+    const double w = pweight<D, SRC, FMT>(P, Lf, vf, rx, ry, rz, kap);
+    acc += (T)w * ec[vc + slot_off(Lc, kx, ky, kk)];
+  }
+  uf[vf] += acc;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_axpy_mixed(Lat L, double* __restrict__ x,
+                                                    const float* __restrict__ e) {
+  const int i = blockIdx.x * TX + threadIdx.x;
+  const int j = blockIdx.y * TY + threadIdx.y;
+  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+  const int n = L.n;
+  if (!(i >= 1 && i < n && j >= 1 && j < n && (D == 2 || (kz >= 1 && kz < n)))) return;
+  const int64_t v = i + (int64_t)j * L.pitch + (int64_t)kz * L.plane;
+  x[v] += (double)e[v];
+}
+
+template <typename Ti, typename To>
+__global__ void k_convert(const Ti* __restrict__ in, To* __restrict__ out, int64_t n) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) out[t] = (To)in[t];
+}
+
+// packed unknowns (x fastest over 1..n-1) <-> lattice slots; cells (0..n-1).
+template <typename T, bool TO_LATTICE, bool CELLS>
+__global__ void k_pack(Lat L, const double* __restrict__ packed_in, const T* __restrict__ lat_in,
+                       T* __restrict__ lat_out, double* __restrict__ packed_out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int m = CELLS ? L.n : L.n - 1;
+  const int64_t total = (L.d == 3) ? (int64_t)m * m * m : (int64_t)m * m;
+  if (t >= total) return;
+  const int off = CELLS ? 0 : 1;
+  const int i = (int)(t % m) + off;
+  const int j = (int)((t / m) % m) + off;
+  const int k = (L.d == 3) ? (int)(t / ((int64_t)m * m)) + off : 0;
+  const int64_t v = i + (int64_t)j * L.pitch + (int64_t)k * L.plane;
+  if (TO_LATTICE)
+    lat_out[v] = (T)packed_in[t];
+  else
+    packed_out[t] = (double)lat_in[v];
+}
+
+template <typename T>
+__global__ void k_coarse_solve(Lat L, const double* __restrict__ Ainv, int nc,
+                               const T* __restrict__ b, T* __restrict__ u) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nc) return;
+  const int m = L.n - 1;
+  double acc = 0.0;
+  for (int c = 0; c < nc; ++c) {
+    const int i = c % m + 1, j = (c / m) % m + 1, k = (L.d == 3) ? c / (m * m) + 1 : 0;
+    acc += Ainv[(int64_t)row * nc + c] * (double)b[i + (int64_t)j * L.pitch + (int64_t)k * L.plane];
+  }
+  const int i = row % m + 1, j = (row / m) % m + 1, k = (L.d == 3) ? row / (m * m) + 1 : 0;
+  u[i + (int64_t)j * L.pitch + (int64_t)k * L.plane] = (T)acc;
+}
+
+template <typename T>
+__global__ void k_zero(T* __restrict__ p, int64_t n) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) p[t] = (T)0;
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <int D, typename T, typename TO, int SRC, int FMT>
+void dispatch_mode(const Lat& L, int mode, const T* u, const T* b, TO* out, const T* eps,
+                   const Store& A, T omega, double* partial, hipStream_t s) {
+  const dim3 g = tile_grid(L), bl(TX, TY, 1);
+  switch (mode) {
+    case 0: hipLaunchKernelGGL((k_stencil<D, T, TO, SRC, FMT, 0>), g, bl, 0, s, L, u, b, out, eps, A, omega, partial); break;
+    case 1: hipLaunchKernelGGL((k_stencil<D, T, TO, SRC, FMT, 1>), g, bl, 0, s, L, u, b, out, eps, A, omega, partial); break;
+    case 2: hipLaunchKernelGGL((k_stencil<D, T, TO, SRC, FMT, 2>), g, bl, 0, s, L, u, b, out, eps, A, omega, partial); break;
+    default: hipLaunchKernelGGL((k_stencil<D, T, TO, SRC, FMT, 3>), g, bl, 0, s, L, u, b, out, eps, A, omega, partial); break;
+  }
+  QMG_HIP(hipGetLastError());
+}
+
+template <int D, typename T, typename TO>
+void dispatch_src(const Lat& L, int mode, const T* u, const T* b, TO* out, const T* eps,
+                  const Store& A, T omega, double* partial, hipStream_t s) {
+  if (A.src == SRC_GEOM) return dispatch_mode<D, T, TO, SRC_GEOM, F64>(L, mode, u, b, out, eps, A, omega, partial, s);
+  if (A.src == SRC_PLAIN) return dispatch_mode<D, T, TO, SRC_PLAIN, F64>(L, mode, u, b, out, eps, A, omega, partial, s);
+  switch (A.fmt) {
+    case F64: return dispatch_mode<D, T, TO, SRC_HIER, F64>(L, mode, u, b, out, eps, A, omega, partial, s);
+    case F32: return dispatch_mode<D, T, TO, SRC_HIER, F32>(L, mode, u, b, out, eps, A, omega, partial, s);
+    case F16: return dispatch_mode<D, T, TO, SRC_HIER, F16>(L, mode, u, b, out, eps, A, omega, partial, s);
+    default: return dispatch_mode<D, T, TO, SRC_HIER, BF16>(L, mode, u, b, out, eps, A, omega, partial, s);
+  }
+}
+
+template <int D, typename T, bool RESTRICT>
+void dispatch_transfer(const Lat& Lf, const Lat& Lc, const T* in, T* out, const Store& P, hipStream_t s) {
+  const Lat& Lg = RESTRICT ? Lc : Lf;
+  const dim3 g = tile_grid(Lg), bl(TX, TY, 1);
+#define QMG_TR(SRCV, FMTV)                                                                     \
+  do {                                                                                         \
+    if (RESTRICT)                                                                              \
+      hipLaunchKernelGGL((k_restrict<D, T, SRCV, FMTV>), g, bl, 0, s, Lf, Lc, in, out, P);     \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_prolong<D, T, SRCV, FMTV>), g, bl, 0, s, Lf, Lc, in, out, P);      \
+  } while (0)
+  if (P.src == SRC_GEOM) QMG_TR(SRC_GEOM, F64);
+  else if (P.src == SRC_PLAIN) QMG_TR(SRC_PLAIN, F64);
+  else if (P.fmt == F64) QMG_TR(SRC_HIER, F64);
+  else if (P.fmt == F32) QMG_TR(SRC_HIER, F32);
+  else if (P.fmt == F16) QMG_TR(SRC_HIER, F16);
+  else QMG_TR(SRC_HIER, BF16);
+#undef QMG_TR
+  QMG_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+template <typename T>
+void launch_stencil(const Lat& L, int mode, const T* u, const T* b, T* out, const T* eps,
+                    const Store& A, T omega, double* partial, int* n_partial, hipStream_t s) {
+  if (n_partial) {
+    const dim3 g = tile_grid(L);
+    *n_partial = (int)(g.x * g.y * g.z);
+  }
+  if (L.d == 2)
+    dispatch_src<2, T, T>(L, mode, u, b, out, eps, A, omega, partial, s);
+  else
+    dispatch_src<3, T, T>(L, mode, u, b, out, eps, A, omega, partial, s);
+}
+template void launch_stencil<double>(const Lat&, int, const double*, const double*, double*,
+                                     const double*, const Store&, double, double*, int*, hipStream_t);
+template void launch_stencil<float>(const Lat&, int, const float*, const float*, float*,
+                                    const float*, const Store&, float, double*, int*, hipStream_t);
+
+void launch_residual_mixed(const Lat& L, const double* x, const double* b, float* r32,
+                           const double* eps, double* partial, int* n_partial, hipStream_t s) {
+  const dim3 g = tile_grid(L), bl(TX, TY, 1);
+  if (n_partial) *n_partial = (int)(g.x * g.y * g.z);
+  Store none;
+  if (L.d == 2)
+    hipLaunchKernelGGL((k_stencil<2, double, float, SRC_GEOM, F64, 2>), g, bl, 0, s, L, x, b, r32, eps, none, 0.0, partial);
+  else
+    hipLaunchKernelGGL((k_stencil<3, double, float, SRC_GEOM, F64, 2>), g, bl, 0, s, L, x, b, r32, eps, none, 0.0, partial);
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_sum_partials(const double* partial, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, partial, n, out);
+  QMG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_restrict(const Lat& Lf, const Lat& Lc, const T* r, T* bc, const Store& P, hipStream_t s) {
+  if (Lf.d == 2) dispatch_transfer<2, T, true>(Lf, Lc, r, bc, P, s);
+  else dispatch_transfer<3, T, true>(Lf, Lc, r, bc, P, s);
+}
+template <typename T>
+void launch_prolong(const Lat& Lf, const Lat& Lc, const T* ec, T* uf, const Store& P, hipStream_t s) {
+  if (Lf.d == 2) dispatch_transfer<2, T, false>(Lf, Lc, ec, uf, P, s);
+  else dispatch_transfer<3, T, false>(Lf, Lc, ec, uf, P, s);
+}
+template void launch_restrict<double>(const Lat&, const Lat&, const double*, double*, const Store&, hipStream_t);
+template void launch_restrict<float>(const Lat&, const Lat&, const float*, float*, const Store&, hipStream_t);
+template void launch_prolong<double>(const Lat&, const Lat&, const double*, double*, const Store&, hipStream_t);
+template void launch_prolong<float>(const Lat&, const Lat&, const float*, float*, const Store&, hipStream_t);
+
+void launch_axpy_mixed(const Lat& L, double* x, const float* e, hipStream_t s) {
+  const dim3 g = tile_grid(L), bl(TX, TY, 1);
+  if (L.d == 2) hipLaunchKernelGGL(k_axpy_mixed<2>, g, bl, 0, s, L, x, e);
+  else hipLaunchKernelGGL(k_axpy_mixed<3>, g, bl, 0, s, L, x, e);
+  QMG_HIP(hipGetLastError());
+}
+
+template <typename Ti, typename To>
+void launch_convert(const Lat& L, const Ti* in, To* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<Ti, To>), dim3(blocks_for(L.nslot, 256)), dim3(256), 0, s, in, out, L.nslot);
+  QMG_HIP(hipGetLastError());
+}
+template void launch_convert<double, float>(const Lat&, const double*, float*, hipStream_t);
+template void launch_convert<float, double>(const Lat&, const float*, double*, hipStream_t);
+
+template <typename T>
+void launch_scatter_unknowns(const Lat& L, const double* in, T* lat, hipStream_t s) {
+  const int64_t m = L.n - 1, tot = (L.d == 3) ? m * m * m : m * m;
+  hipLaunchKernelGGL((k_pack<T, true, false>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, L, in, (const T*)nullptr, lat, (double*)nullptr);
+  QMG_HIP(hipGetLastError());
+}
+template <typename T>
+void launch_gather_unknowns(const Lat& L, const T* lat, double* out, hipStream_t s) {
+  const int64_t m = L.n - 1, tot = (L.d == 3) ? m * m * m : m * m;
+  hipLaunchKernelGGL((k_pack<T, false, false>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, L, (const double*)nullptr, lat, (T*)nullptr, out);
+  QMG_HIP(hipGetLastError());
+}
+template <typename T>
+void launch_scatter_cells(const Lat& L, const double* in, T* lat, hipStream_t s) {
+  const int64_t m = L.n, tot = (L.d == 3) ? m * m * m : m * m;
+  hipLaunchKernelGGL((k_pack<T, true, true>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, L, in, (const T*)nullptr, lat, (double*)nullptr);
+  QMG_HIP(hipGetLastError());
+}
+template void launch_scatter_unknowns<double>(const Lat&, const double*, double*, hipStream_t);
+template void launch_scatter_unknowns<float>(const Lat&, const double*, float*, hipStream_t);
+template void launch_gather_unknowns<double>(const Lat&, const double*, double*, hipStream_t);
+template void launch_gather_unknowns<float>(const Lat&, const float*, double*, hipStream_t);
+template void launch_scatter_cells<double>(const Lat&, const double*, double*, hipStream_t);
+template void launch_scatter_cells<float>(const Lat&, const double*, float*, hipStream_t);
+
+template <typename T>
+void launch_coarse_solve(const Lat& L, const double* Ainv, int nc, const T* b, T* u, hipStream_t s) {
+  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(blocks_for(nc, 256)), dim3(256), 0, s, L, Ainv, nc, b, u);
+  QMG_HIP(hipGetLastError());
+}
+template void launch_coarse_solve<double>(const Lat&, const double*, int, const double*, double*, hipStream_t);
+template void launch_coarse_solve<float>(const Lat&, const double*, int, const float*, float*, hipStream_t);
+
+template <typename T>
+void launch_zero(T* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_zero<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n);
+  QMG_HIP(hipGetLastError());
+}
+template void launch_zero<double>(double*, int64_t, hipStream_t);
+template void launch_zero<float>(float*, int64_t, hipStream_t);
+template void launch_zero<int32_t>(int32_t*, int64_t, hipStream_t);
+
+}  // namespace qmg

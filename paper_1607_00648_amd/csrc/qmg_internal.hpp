@@ -1,0 +1,169 @@
+// Internal definitions shared by the HIP kernels and the host driver of the
+// quasi-matrix-free multigrid library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/qmg.h"
+
+namespace qmg {
+
+// ---------------------------------------------------------------------------
+// Constants of the method and of the data layout
+// ---------------------------------------------------------------------------
+constexpr int kSeg = 64;                       // lattice slots per store block (one wavefront)
+constexpr double kEpsZero = 9.094947017729282e-13;  // 2^-40: a delta this small (relative) is zero
+constexpr double kDomSlack = 1e-10;            // diagonal-dominance slack of the definiteness check
+constexpr int kCoarseDirectMax = 1024;         // coarsest levels up to this size are solved exactly
+
+enum Fmt { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
+enum Src { SRC_GEOM = 0, SRC_PLAIN = 1, SRC_HIER = 2 };
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct ApiError : std::runtime_error {
+  int code;
+  ApiError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define QMG_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::qmg::HipError(std::string(#call) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Lattice of one regular level.  Vertex (i,j,k), 0 <= i,j,k <= n, lives at slot
+// i + pitch*j + plane*k; pitch is a multiple of 64 so that every 64-slot block
+// lies in one x-row.  Cell c (low corner (i,j,k), 0 <= i,j,k < n) uses the slot
+// of its low corner, so cell arrays share the vertex layout.
+// ---------------------------------------------------------------------------
+struct Lat {
+  int d;
+  int n;          // cells per axis
+  int pitch;      // slots per x-row
+  int64_t plane;  // slots per z-plane (pitch * (n+1)); 0 in 2D
+  int64_t nslot;  // total slots
+  double h;       // 1/n
+};
+
+inline Lat make_lat(int d, int level) {
+  Lat L{};
+  L.d = d;
+  L.n = 1;
+  for (int i = 0; i < level; ++i) L.n *= 3;
+  L.pitch = ((L.n + 1 + kSeg - 1) / kSeg) * kSeg;
+  L.plane = (d == 3) ? (int64_t)L.pitch * (L.n + 1) : 0;
+  L.nslot = (d == 3) ? L.plane * (L.n + 1) : (int64_t)L.pitch * (L.n + 1);
+  L.h = 1.0 / L.n;
+  return L;
+}
+
+// Operator store of one level (stencils: 3^d entries per vertex; prolongation:
+// 2^d parent weights per fine vertex).
+//   SRC_GEOM : nothing stored, the rediscretised stencil / d-linear weights
+//   SRC_PLAIN: `dense` holds nent arrays of nslot doubles (entry-major)
+//   SRC_HIER : rediscretised / d-linear part on the fly plus a delta; `blk[b]`
+//              is the compact index of 64-slot block b or -1 for an all-zero
+//              delta; `payload` holds [cblk][nent][64] values of format `fmt`;
+//              `scale` holds [cblk][64] power-of-two exponents (FP16 only).
+struct Store {
+  int src = SRC_GEOM;
+  int fmt = F64;
+  int nent = 0;
+  const void* dense = nullptr;
+  const int32_t* blk = nullptr;
+  const void* payload = nullptr;
+  const int8_t* scale = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (kernels_level.hip / kernels_build.hip)
+// ---------------------------------------------------------------------------
+// Smoothing / residual / matvec on one level.  mode: 0 = Jacobi sweep
+// (out = u + omega D^-1 (b - A u)), 1 = Jacobi sweep from u = 0 (u not read),
+// 2 = residual out = b - A u, 3 = matvec out = A u.  When `partial` is non-null
+// (modes 2 and 3) each workgroup adds its sum of squares of `out` there.
+// T is double or float; eps has the iterate type.
+template <typename T>
+void launch_stencil(const Lat& L, int mode, const T* u, const T* b, T* out, const T* eps,
+                    const Store& A, T omega, double* partial, int* n_partial, hipStream_t s);
+
+// Finest-level FP64 residual for the mixed loop: r32 = fp32(b - A x), partial
+// sums of squares of the FP64 residual.
+void launch_residual_mixed(const Lat& L, const double* x, const double* b, float* r32,
+                           const double* eps, double* partial, int* n_partial, hipStream_t s);
+
+// Sum of `n` partials into out[0] in a fixed order (one workgroup).
+void launch_sum_partials(const double* partial, int n, double* out, hipStream_t s);
+
+// Restriction bc = P^T r (gather per coarse vertex).  Lf: fine lattice.
+template <typename T>
+void launch_restrict(const Lat& Lf, const Lat& Lc, const T* r, T* bc, const Store& P, hipStream_t s);
+
+// Prolongation uf = (add ? uf : 0) + P ec (gather per fine vertex).
+template <typename T>
+void launch_prolong(const Lat& Lf, const Lat& Lc, const T* ec, T* uf, const Store& P, hipStream_t s);
+
+// x64 += e32 on the interior.
+void launch_axpy_mixed(const Lat& L, double* x, const float* e, hipStream_t s);
+
+// Conversions between iterate types and between packed unknown vectors and
+// lattice arrays.
+template <typename Ti, typename To>
+void launch_convert(const Lat& L, const Ti* in, To* out, hipStream_t s);
+template <typename T>
+void launch_scatter_unknowns(const Lat& L, const double* in, T* lat, hipStream_t s);
+template <typename T>
+void launch_gather_unknowns(const Lat& L, const T* lat, double* out, hipStream_t s);
+template <typename T>
+void launch_scatter_cells(const Lat& L, const double* in, T* lat, hipStream_t s);
+
+// Coarsest solve u = Ainv b over the interior unknowns (Ainv FP64, nc x nc).
+template <typename T>
+void launch_coarse_solve(const Lat& L, const double* Ainv, int nc, const T* b, T* u, hipStream_t s);
+
+// ---- build ----
+// eps of level l-1 = mean of the 3^d children (lattice cell layout).
+void launch_coarsen_eps(const Lat& Lf, const Lat& Lc, const double* epsf, double* epsc,
+                        hipStream_t s);
+// Materialise the operator of a level as FP64 stencils (entry-major, nent*nslot).
+void launch_materialise(const Lat& L, const double* eps, const Store& A, double* out,
+                        hipStream_t s);
+// Materialise prolongation weights as FP64 (2^d * nslot of the fine level; Lc
+// is the coarse lattice).
+void launch_materialise_P(const Lat& Lf, const Lat& Lc, const Store& P, double* out, hipStream_t s);
+// BoxMG P (Sect. 3.4): writes 2^d*nslot FP64 parent weights of the fine level.
+// Afine: FP64 stencils of the fine level (entry-major); when null, the fine
+// operator is rediscretised from epsf on the fly.
+void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
+                  double* Pw, hipStream_t s);
+// Galerkin RAP (Sect. 3.3): coarse FP64 stencils from fine stencils (or eps on
+// the fly when Afine is null) and FP64 parent weights (d-linear when Pw null).
+void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
+                const double* Pw, double* Ac, hipStream_t s);
+// Definiteness check of coarse stencils; counts failing rows into *bad.
+void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s);
+// Hierarchical delta store: per-block zero flags, compaction and payload.  The
+// reference is the rediscretised stencil from eps (stencils) or the d-linear
+// weights (is_P; Lc is then the coarse lattice), both with Dirichlet entries
+// dropped.  blk gets 0/1 per block, then compact ids from the scan.
+void launch_delta_flags(const Lat& L, const Lat& Lc, bool is_P, const double* full,
+                        const double* eps, int32_t* blk, hipStream_t s);
+void launch_scan_blocks(int32_t* blk, int64_t nblk, int32_t* total, hipStream_t s);
+void launch_delta_write(const Lat& L, const Lat& Lc, bool is_P, int fmt, const double* full,
+                        const double* eps, const int32_t* blk, void* payload, int8_t* scale,
+                        hipStream_t s);
+
+// Fill lattice array with zeros (kernel, not memset, so it can live in graphs).
+template <typename T>
+void launch_zero(T* p, int64_t n, hipStream_t s);
+
+}  // namespace qmg

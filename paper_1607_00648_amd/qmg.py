@@ -1,0 +1,237 @@
+"""ctypes binding of ``libqmg.so`` (the C ABI declared in ``include/qmg.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch supplies device memory (the grid workspace) and the HIP stream.  The
+binding raises if the library is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqmg.so")
+
+QMG_OK, QMG_EINVAL, QMG_ENOMEM, QMG_EHIP, QMG_ESTATE, QMG_ENOTCONV, QMG_EINDEF, QMG_EBUSY = \
+    0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "QMG_OK", -1: "QMG_EINVAL", -2: "QMG_ENOMEM", -3: "QMG_EHIP",
+                -4: "QMG_ESTATE", -5: "QMG_ENOTCONV", -6: "QMG_EINDEF", -7: "QMG_EBUSY"}
+QMG_HOST, QMG_DEVICE = 0, 1
+GEOMETRIC, GALERKIN_DLINEAR, BOXMG = 0, 1, 2
+PLAIN_FP64, HIER_FP64, HIER_FP32, HIER_FP16, HIER_BF16 = 0, 1, 2, 3, 4
+OP_MATVEC, OP_RESIDUAL, OP_JACOBI, OP_RESTRICT, OP_PROLONG = 0, 1, 2, 3, 4
+
+TRANSFERS = {"geometric": GEOMETRIC, "galerkin": GALERKIN_DLINEAR, "boxmg": BOXMG}
+STORES = {"plain64": PLAIN_FP64, "hier64": HIER_FP64, "hier32": HIER_FP32,
+          "hier16": HIER_FP16, "bf16": HIER_BF16}
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("max_level", C.c_int)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("transfer", C.c_int), ("store", C.c_int), ("mu_pre", C.c_int),
+                ("mu_post", C.c_int), ("omega", C.c_double), ("coarsest_level", C.c_int),
+                ("check_definite", C.c_int), ("inner_cycles", C.c_int)]
+
+
+class SolveReport(C.Structure):
+    _fields_ = [("cycles", C.c_int), ("outer_iters", C.c_int), ("relres", C.c_double),
+                ("coarsest_level_used", C.c_int), ("vertex_updates", C.c_int64),
+                ("bytes_operators", C.c_size_t), ("zero_delta_fraction", C.c_double),
+                ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# every entry point of include/qmg.h with its ctypes signature
+_SIGS = {
+    "qmg_version": (C.c_char_p, []),
+    "qmg_workspace_bytes": (C.c_int, [C.POINTER(GridDesc), C.POINTER(SolverOpts), C.POINTER(C.c_size_t)]),
+    "qmg_default_opts": (C.c_int, [C.POINTER(SolverOpts)]),
+    "qmg_create_grid": (C.c_int, [C.POINTER(GridDesc), C.POINTER(SolverOpts), C.c_void_p, C.c_size_t,
+                                  C.c_void_p, C.POINTER(C.c_void_p)]),
+    "qmg_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
+    "qmg_unknown_coords": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "qmg_set_coefficients": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
+    "qmg_build_operators": (C.c_int, [C.c_void_p, C.POINTER(SolveReport)]),
+    "qmg_vcycle": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "qmg_solve": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_void_p, C.POINTER(SolveReport)]),
+    "qmg_get_solution": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "qmg_set_solution": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "qmg_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "qmg_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "qmg_destroy_grid": (C.c_int, [C.c_void_p]),
+    "qmg_last_error": (C.c_char_p, [C.c_void_p]),
+    "qmg_get_operator": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "qmg_get_prolongation": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "qmg_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads the library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class QmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_level=1,
+              check_definite=True, inner_cycles=1) -> SolverOpts:
+    o = SolverOpts()
+    o.transfer = TRANSFERS[transfer] if isinstance(transfer, str) else int(transfer)
+    o.store = STORES[store] if isinstance(store, str) else int(store)
+    o.mu_pre, o.mu_post = int(mu[0]), int(mu[1])
+    o.omega = float(omega)
+    o.coarsest_level = int(coarsest_level)
+    o.check_definite = 1 if check_definite else 0
+    o.inner_cycles = int(inner_cycles)
+    return o
+
+
+class Grid:
+    """One regular grid of the unit square/cube with its operators and iterates.
+
+    The workspace is a torch uint8 CUDA tensor owned by this object; work runs on
+    ``stream`` (a torch.cuda.Stream, default: the current stream)."""
+
+    def __init__(self, dim: int, level: int, opts: Optional[SolverOpts] = None, stream=None,
+                 device: str = "cuda"):
+        import torch
+        self.lib = load()
+        self.dim, self.level = int(dim), int(level)
+        self.opts = opts if opts is not None else make_opts()
+        self.desc = GridDesc(self.dim, self.level)
+        nbytes = C.c_size_t(0)
+        self._check(self.lib.qmg_workspace_bytes(C.byref(self.desc), C.byref(self.opts), C.byref(nbytes)), None)
+        self.workspace_bytes = int(nbytes.value)
+        self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        self._check(self.lib.qmg_create_grid(C.byref(self.desc), C.byref(self.opts),
+                                             C.c_void_p(self._ws.data_ptr()), nbytes,
+                                             C.c_void_p(self.stream.cuda_stream), C.byref(h)), None)
+        self.h = h
+        n = 3 ** self.level
+        self.n = n
+        self.n_unknowns = (n - 1) ** self.dim
+
+    # -- errors --------------------------------------------------------------
+    def _check(self, rc, h, allow=()):
+        if rc != QMG_OK and rc not in allow:
+            msg = self.lib.qmg_last_error(h).decode() if h is not None else \
+                self.lib.qmg_last_error(None).decode()
+            raise QmgError(rc, msg)
+        return rc
+
+    # -- main path -----------------------------------------------------------
+    def set_coefficients(self, eps, f):
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        if eps.size != self.n ** self.dim or f.size != self.n_unknowns:
+            raise ValueError("eps must hold n^d values and f (n-1)^d values")
+        self._check(self.lib.qmg_set_coefficients(self.h, _ptr(eps), 1, _ptr(f), QMG_HOST), self.h)
+
+    def build(self) -> dict:
+        rep = SolveReport()
+        self._check(self.lib.qmg_build_operators(self.h, C.byref(rep)), self.h)
+        return rep.as_dict()
+
+    def vcycle(self, n: int = 1) -> np.ndarray:
+        rr = np.zeros(max(n, 1))
+        self._check(self.lib.qmg_vcycle(self.h, int(n), _ptr(rr)), self.h)
+        return rr[:n]
+
+    def solve(self, tol: float = 1e-8, max_cycles: int = 500):
+        hist = np.zeros(max(max_cycles, 1))
+        rep = SolveReport()
+        rc = self._check(self.lib.qmg_solve(self.h, float(tol), int(max_cycles), _ptr(hist), C.byref(rep)),
+                         self.h, allow=(QMG_ENOTCONV,))
+        d = rep.as_dict()
+        d["status"] = STATUS_NAMES[rc]
+        return d, hist[: max(rep.outer_iters - 1, 0)]
+
+    def solution(self) -> np.ndarray:
+        u = np.zeros(self.n_unknowns)
+        self._check(self.lib.qmg_get_solution(self.h, _ptr(u), QMG_HOST), self.h)
+        return u
+
+    def set_solution(self, u):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        self._check(self.lib.qmg_set_solution(self.h, _ptr(u), QMG_HOST), self.h)
+
+    def profile(self, on: bool = True):
+        self._check(self.lib.qmg_profile_enable(self.h, 1 if on else 0), self.h)
+
+    def profile_read(self):
+        n = C.c_int64(0)
+        ms = C.c_double(0.0)
+        self._check(self.lib.qmg_profile_read(self.h, C.byref(n), C.byref(ms)), self.h)
+        return int(n.value), float(ms.value)
+
+    # -- inspection ----------------------------------------------------------
+    def _lat_shape(self, level):
+        return (3 ** level + 1,) * self.dim
+
+    def operator(self, level: int) -> np.ndarray:
+        out = np.zeros((3 ** self.dim,) + self._lat_shape(level))
+        self._check(self.lib.qmg_get_operator(self.h, int(level), _ptr(out)), self.h)
+        return out
+
+    def prolongation(self, level: int) -> np.ndarray:
+        out = np.zeros((2 ** self.dim,) + self._lat_shape(level))
+        self._check(self.lib.qmg_get_prolongation(self.h, int(level), _ptr(out)), self.h)
+        return out
+
+    def apply(self, op: int, level: int, x: np.ndarray, b: Optional[np.ndarray] = None) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        out_level = level - 1 if op == OP_RESTRICT else level
+        out = np.zeros(self._lat_shape(out_level))
+        bp = None
+        if b is not None:
+            b = np.ascontiguousarray(b, dtype=np.float64)
+            bp = _ptr(b)
+        self._check(self.lib.qmg_apply(self.h, int(op), int(level), _ptr(x), bp, _ptr(out)), self.h)
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.qmg_destroy_grid(self.h)
+            self.h = C.c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def version() -> str:
+    return load().qmg_version().decode()

@@ -1,0 +1,257 @@
+"""Parity of the HIP path against the CPU oracle, step by step and end to end.
+
+Every comparison uses the same seeded inputs on both sides; sizes span several
+64 x 4 tiles with ragged tails (n + 1 = 28, 82, 244, 730 slots per row)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_util import require_gpu, announce, lattice_of_unknowns, unknowns_of_lattice, weights_to_csr
+from noise_floor import iterate_tolerance, operator_tolerance
+
+pytestmark = pytest.mark.gpu
+
+RTOL64 = 1e-13
+
+
+def _grid(qmg, p, transfer="boxmg", store="hier64", **kw):
+    g = qmg.Grid(p.dim, p.level, qmg.make_opts(transfer, store, **kw))
+    g.set_coefficients(p.eps, p.f)
+    return g
+
+
+@pytest.mark.parametrize("d,L", [(2, 3), (2, 5), (3, 2), (3, 3)])
+def test_finest_operator_rediscretised(d, L):
+    qmg = require_gpu()
+    announce(f"finest operator d={d} L={L}")
+    p = W.random_checkerboard(d, L, seed=1, values=(0.5, 30.0), blocks=3)
+    g = _grid(qmg, p, "geometric", "hier64")
+    S = g.operator(L)
+    g.close()
+    R = O.geometric_stencil(p.eps, d, L)
+    assert np.abs(S - R).max() <= RTOL64 * np.abs(R).max()
+
+
+@pytest.mark.parametrize("d,L,store", [(2, 4, "hier64"), (2, 4, "plain64"), (3, 3, "hier64")])
+def test_single_steps_on_finest_level(d, L, store):
+    qmg = require_gpu()
+    announce(f"single steps d={d} L={L} {store}")
+    p = W.random_checkerboard(d, L, seed=2, values=(1.0, 1e3), blocks=9 if L > 2 else 3)
+    g = _grid(qmg, p, "boxmg", store)
+    g.build()
+    rng = np.random.default_rng(5)
+    x = lattice_of_unknowns(rng.normal(size=p.n_unknowns), d, L)
+    b = lattice_of_unknowns(rng.normal(size=p.n_unknowns), d, L)
+    A = O.stencil_to_csr(O.geometric_stencil(p.eps, d, L), d, L)
+    xu, bu = unknowns_of_lattice(x, d, L), unknowns_of_lattice(b, d, L)
+    mv = unknowns_of_lattice(g.apply(qmg.OP_MATVEC, L, x), d, L)
+    np.testing.assert_allclose(mv, A @ xu, rtol=0, atol=RTOL64 * np.abs(A @ xu).max())
+    rs = unknowns_of_lattice(g.apply(qmg.OP_RESIDUAL, L, x, b), d, L)
+    np.testing.assert_allclose(rs, bu - A @ xu, rtol=0, atol=RTOL64 * np.abs(bu - A @ xu).max())
+    jac = unknowns_of_lattice(g.apply(qmg.OP_JACOBI, L, x, b), d, L)
+    want = O.jacobi(A, A.diagonal(), xu, bu, 0.6)
+    np.testing.assert_allclose(jac, want, rtol=0, atol=RTOL64 * np.abs(want).max())
+    g.close()
+
+
+@pytest.mark.parametrize("d,L", [(2, 3), (2, 5), (3, 2), (3, 3)])
+def test_boxmg_prolongation_and_galerkin_operators(d, L):
+    qmg = require_gpu()
+    announce(f"boxmg+rap d={d} L={L}")
+    p = W.random_checkerboard(d, L, seed=3, values=(1.0, 1e4), blocks=9 if L > 2 else 3)
+    g = _grid(qmg, p, "boxmg", "hier64")
+    info = g.build()
+    H = O.build_hierarchy(p.eps, d, L, transfer="boxmg")
+    assert info["coarsest_level_used"] == H.lc
+    # below the finest level both sides start from Galerkin operators that
+    # already differ by rounding: bounds come from the oracle's own one-ulp
+    # sensitivity (the finest-level P depends on rediscretised stencils only)
+    tolP, tolA = operator_tolerance(p, "boxmg", H)
+    for l in range(H.lc + 1, L + 1):
+        tol = 1e-13 if l == L else tolP[l]
+        Wg = g.prolongation(l)
+        Wo = O.P_to_parent_weights(H.P[l], d, l)
+        assert np.abs(Wg - Wo).max() <= tol, (l, np.abs(Wg - Wo).max(), tol)
+    for l in range(H.lc, L):
+        Sg = g.operator(l)
+        So = O.csr_to_stencil(H.A[l], d, l)
+        assert np.abs(Sg - So).max() <= tolA[l] * np.abs(So).max(), (l, np.abs(Sg - So).max(), tolA[l])
+    g.close()
+
+
+@pytest.mark.parametrize("d,L,contrast", [(2, 4, 1e4), (2, 5, 1e4), (3, 3, 1e4), (3, 3, 10.0)])
+def test_boxmg_and_rap_steps_on_gpu_inputs(d, L, contrast):
+    """Each construction step on the same input: the oracle's BoxMG applied to
+    the GPU's level operator must give the GPU's weights, and the oracle's
+    P^T A P of the GPU's A and P must give the GPU's coarse operator."""
+    qmg = require_gpu()
+    announce(f"boxmg/rap steps d={d} L={L} contrast={contrast:g}")
+    p = W.random_checkerboard(d, L, seed=12, values=(1.0, contrast), blocks=9 if L > 2 else 3)
+    g = _grid(qmg, p, "boxmg", "plain64")
+    info = g.build()
+    lc = info["coarsest_level_used"]
+    for l in range(L, lc, -1):
+        S = g.operator(l)
+        Wg = g.prolongation(l)
+        Wo = O.P_to_parent_weights(O.boxmg_P(S, d, l), d, l)
+        assert np.abs(Wg - Wo).max() <= 1e-11, (l, np.abs(Wg - Wo).max())
+        Ag = O.stencil_to_csr(S, d, l)
+        Ac = O.csr_to_stencil(O.rap(Ag, weights_to_csr(Wg, d, l)), d, l - 1)
+        Sc = g.operator(l - 1)
+        assert np.abs(Sc - Ac).max() <= 1e-13 * np.abs(Ac).max(), (l, np.abs(Sc - Ac).max())
+    g.close()
+
+
+@pytest.mark.parametrize("transfer,store", [("galerkin", "hier64"), ("galerkin", "plain64"),
+                                            ("geometric", "plain64"), ("boxmg", "plain64")])
+def test_operators_other_transfers(transfer, store):
+    qmg = require_gpu()
+    announce(f"operators {transfer} {store}")
+    d, L = 2, 4
+    p = W.random_checkerboard(d, L, seed=4, values=(1.0, 50.0))
+    g = _grid(qmg, p, transfer, store)
+    g.build()
+    H = O.build_hierarchy(p.eps, d, L, transfer=transfer)
+    for l in range(H.lc, L + 1):
+        Sg, So = g.operator(l), O.csr_to_stencil(H.A[l], d, l)
+        assert np.abs(Sg - So).max() <= 1e-11 * np.abs(So).max(), l
+    for l in range(H.lc + 1, L + 1):
+        assert np.abs(g.prolongation(l) - O.P_to_parent_weights(H.P[l], d, l)).max() <= 1e-11
+    g.close()
+
+
+@pytest.mark.parametrize("d,L", [(2, 4), (3, 3)])
+def test_restrict_and_prolong(d, L):
+    qmg = require_gpu()
+    announce(f"transfer ops d={d} L={L}")
+    p = W.random_checkerboard(d, L, seed=6, values=(1.0, 1e4), blocks=3)
+    g = _grid(qmg, p, "boxmg", "hier64")
+    g.build()
+    H = O.build_hierarchy(p.eps, d, L, transfer="boxmg")
+    rng = np.random.default_rng(7)
+    r = rng.normal(size=p.n_unknowns)
+    bc = unknowns_of_lattice(g.apply(qmg.OP_RESTRICT, L, lattice_of_unknowns(r, d, L)), d, L - 1)
+    want = H.P[L].T @ r
+    np.testing.assert_allclose(bc, want, rtol=0, atol=1e-13 * np.abs(want).max())
+    e = rng.normal(size=H.P[L].shape[1])
+    base = rng.normal(size=p.n_unknowns)
+    up = unknowns_of_lattice(g.apply(qmg.OP_PROLONG, L, lattice_of_unknowns(e, d, L - 1),
+                                     lattice_of_unknowns(base, d, L)), d, L)
+    want = base + H.P[L] @ e
+    np.testing.assert_allclose(up, want, rtol=0, atol=1e-13 * np.abs(want).max())
+    g.close()
+
+
+@pytest.mark.parametrize("d,L,transfer,store", [
+    (2, 4, "geometric", "plain64"),   # small 2D Poisson shape of the first workload
+    (2, 4, "boxmg", "hier64"),
+    (2, 5, "boxmg", "plain64"),
+    (3, 3, "boxmg", "hier64"),
+    (3, 3, "galerkin", "hier64"),
+])
+def test_vcycle_iterates_match_oracle(d, L, transfer, store):
+    qmg = require_gpu()
+    announce(f"vcycles d={d} L={L} {transfer} {store}")
+    if transfer == "geometric":
+        p = W.poisson(d, L, seed=0)
+    else:
+        p = W.random_checkerboard(d, L, seed=8, values=(1.0, 1e4), blocks=9 if L > 2 else 3)
+    k = 6
+    g = _grid(qmg, p, transfer, store)
+    g.build()
+    rr = g.vcycle(k)
+    u = g.solution()
+    g.close()
+    H = O.build_hierarchy(p.eps, d, L, transfer=transfer)
+    b = O.rhs_from_f(p.f, d, L)
+    uo, hist = O.solve(H, b, cycles=k)
+    A = H.A[L]
+    tol, _ = iterate_tolerance(p, transfer, H, k) if transfer != "geometric" else (1e-12, None)
+    diff = np.linalg.norm(A @ (u - uo)) / np.linalg.norm(b)
+    print(f"iterate measure {diff:.3e} (bound {tol:.3e})")
+    assert diff <= tol
+    np.testing.assert_allclose(rr, hist, rtol=1e-6, atol=1e-12)
+
+
+def test_cfg2_full_size_cycles_and_solve():
+    """The 729^2-cell jumping-coefficient workload at full size: 4 cycles match
+    the oracle's iterate; the solve reaches 1e-8 by the oracle's own FP64
+    recomputation of the residual."""
+    qmg = require_gpu()
+    announce("cfg2 full size")
+    p = W.cfg2(0)
+    g = _grid(qmg, p, "boxmg", "hier64")
+    g.build()
+    rr = g.vcycle(4)
+    u4 = g.solution()
+    H = O.build_hierarchy(p.eps, 2, 6, transfer="boxmg")
+    b = O.rhs_from_f(p.f, 2, 6)
+    uo, hist = O.solve(H, b, cycles=4)
+    A = H.A[6]
+    tol, _ = iterate_tolerance(p, "boxmg", H, 4)
+    diff = np.linalg.norm(A @ (u4 - uo)) / np.linalg.norm(b)
+    print(f"iterate measure {diff:.3e} (bound {tol:.3e})")
+    assert diff <= tol
+    np.testing.assert_allclose(rr, hist, rtol=1e-6)
+    rep, _ = g.solve(1e-8, 400)
+    u = g.solution()
+    g.close()
+    assert rep["status"] == "QMG_OK"
+    assert np.linalg.norm(b - A @ u) / np.linalg.norm(b) <= 1e-8
+
+
+@pytest.mark.parametrize("store", ["hier32", "bf16", "hier16"])
+def test_mixed_precision_reaches_tolerance(store):
+    qmg = require_gpu()
+    announce(f"mixed {store}")
+    d, L = 2, 5
+    p = W.random_checkerboard(d, L, seed=9, values=(1.0, 1e4))
+    g = _grid(qmg, p, "boxmg", store)
+    g.build()
+    rep, hist = g.solve(1e-8, 400)
+    u = g.solution()
+    g.close()
+    H = O.build_hierarchy(p.eps, d, L, transfer="boxmg")
+    b = O.rhs_from_f(p.f, d, L)
+    A = H.A[L]
+    assert rep["status"] == "QMG_OK"
+    assert np.linalg.norm(b - A @ u) / np.linalg.norm(b) <= 1e-8
+    ustar = O.direct_solve(A, b)
+    u64, h64 = O.solve(H, b, tol=1e-8)
+    err64 = np.linalg.norm(u64 - ustar) / np.linalg.norm(ustar)
+    err = np.linalg.norm(u - ustar) / np.linalg.norm(ustar)
+    assert err <= 10 * max(err64, 1e-12)
+    assert rep["cycles"] <= 1.5 * len(h64) + 3
+
+
+def test_constant_coefficient_store_is_empty():
+    qmg = require_gpu()
+    announce("constant eps store")
+    p = W.poisson(2, 5, seed=1)
+    g = _grid(qmg, p, "boxmg", "hier64")
+    info = g.build()
+    g.close()
+    assert info["zero_delta_fraction"] == 1.0
+
+
+def test_raised_coarsest_level_and_errors():
+    qmg = require_gpu()
+    announce("coarsest level 2, error paths")
+    p = W.random_checkerboard(2, 4, seed=10, values=(1.0, 10.0))
+    g = _grid(qmg, p, "boxmg", "hier64", coarsest_level=2)
+    info = g.build()
+    assert info["coarsest_level_used"] == 2
+    rep, _ = g.solve(1e-10, 200)
+    assert rep["status"] == "QMG_OK"
+    g.close()
+    with pytest.raises(qmg.QmgError):
+        qmg.Grid(2, 4, qmg.make_opts(omega=2.5))
+    g = qmg.Grid(2, 3, qmg.make_opts())
+    with pytest.raises(qmg.QmgError):      # solve before build
+        g.solve()
+    bad = np.ones((27, 27))
+    bad[3, 3] = -1.0
+    with pytest.raises(qmg.QmgError):
+        g.set_coefficients(bad, np.zeros(26 * 26))
+    g.close()

@@ -26,7 +26,9 @@
  *    caller-owned device buffer of at least qmg_workspace_bytes() bytes that
  *    must outlive the grid (the library never frees it).
  *  - Streams: all device work of a grid is enqueued on the stream given at
- *    creation (a hipStream_t, NULL = the null stream).  Calls return when their
+ *    creation (a hipStream_t; NULL makes the library create and own a
+ *    non-blocking stream, since cycles are replayed as captured HIP graphs,
+ *    which the null stream cannot capture).  Calls return when their
  *    host-visible results are ready.  A grid is not thread-safe; distinct grids
  *    may be used concurrently from different threads on different streams.
  *  - Enumeration: unknowns are the interior vertices of the finest level,
@@ -201,6 +203,48 @@ enum {
  * (FP64 or FP32, converted at the boundary).  x, b, out are lattice arrays of
  * the sizes the operation implies; b is ignored where unused (may be NULL). */
 int qmg_apply(qmg_grid_t* grid, int op, int level, const double* x, const double* b, double* out);
+
+/* ---------------- serving ------------------------------------------------
+ * A persistent request loop (one scheduler thread per server) that keeps the
+ * grids and operators of admitted requests on the device and overlaps their
+ * work.  Requests are admitted in arrival order -- a later request that fits
+ * may pass a head that does not -- while one of `max_slots` slots is free and
+ * the request's qmg_workspace_bytes() fit in the unused part of `hbm_budget`.
+ * Each admitted request runs the single-grid path (create, set_coefficients,
+ * build_operators, solve) on a stream of its own; its result does not depend
+ * on the other requests.  Not in the paper: it batches independent solves the
+ * way the paper's multi-parameter runs would. */
+typedef struct {
+  int64_t submitted, completed, failed, active, queued;
+  size_t hbm_budget, hbm_in_use, hbm_peak;
+  int max_slots;
+} qmg_server_stats_t;
+
+/* Starts a server on the current HIP device (1 <= max_slots <= 256). */
+int qmg_server_create(size_t hbm_budget, int max_slots, qmg_server_t** out);
+
+/* Queues a solve (eps: n^d cell values, f: (n-1)^d unknowns, host memory,
+ * copied).  QMG_EINVAL if the request could never fit the budget.  The ticket
+ * identifies it in qmg_server_poll. */
+int qmg_server_submit(qmg_server_t* server, const qmg_grid_desc* desc, const qmg_solver_opts* opts,
+                      const double* eps, const double* f, double rel_tol, int max_cycles,
+                      uint64_t* ticket);
+
+/* Non-blocking.  *done = 1 once the request retired; then u_out (nullable,
+ * (n-1)^d host values), report (nullable) and latency_s (nullable: retire time
+ * minus submit time, seconds) are filled, the ticket is released, and the
+ * request's own status is returned (QMG_ENOTCONV etc.). */
+int qmg_server_poll(qmg_server_t* server, uint64_t ticket, int* done, double* u_out,
+                    qmg_solve_report* report, double* latency_s);
+
+/* Blocks until no request is queued or active. */
+int qmg_server_drain(qmg_server_t* server);
+
+int qmg_server_stats(qmg_server_t* server, qmg_server_stats_t* stats);
+const char* qmg_server_last_error(const qmg_server_t* server);
+
+/* Stops the loop: queued requests are dropped, active ones finish first. */
+int qmg_server_destroy(qmg_server_t* server);
 
 #ifdef __cplusplus
 }

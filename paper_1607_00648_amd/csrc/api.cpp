@@ -5,7 +5,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -17,6 +19,8 @@ using namespace qmg;
 namespace {
 
 thread_local std::string g_thread_err;
+
+constexpr int kHistCap = 1024;  // cycles per batch between host synchronisations
 
 int ipow(int b, int e) {
   int r = 1;
@@ -88,6 +92,9 @@ struct qmg_grid {
   int64_t ainv_cap = 0;
   int nc = 0;
   bool coarse_direct = false;
+  int lf = -1;  // top level of the fused single-workgroup coarse cycle (-1: none)
+  bool lf_pw_lds = true;
+  int64_t lds_max = 65536;  // LDS bytes one workgroup may use on this device
   double* tmpA[2] = {nullptr, nullptr};
   double* tmpP = nullptr;
   char* base = nullptr;
@@ -100,6 +107,16 @@ struct qmg_grid {
   size_t bytes_ops = 0;
   double zero_frac = 0.0;
   std::string err;
+  // device norm history of replayed cycles, its pinned host copy and the
+  // event marking the end of the batch in flight
+  double* dhist = nullptr;
+  int* dctr = nullptr;
+  double* hnorm = nullptr;
+  hipEvent_t bev = nullptr;
+  int inflight = 0;
+  // one cycle (+ residual norm) captured as a HIP graph
+  hipGraphExec_t gexec = nullptr;
+  bool own_stream = false;
   // optional HIP-event timing of every finest-level smoothing launch
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;  // start/stop pairs
@@ -211,6 +228,8 @@ void layout(qmg_grid_t* g, Arena& a) {
   g->dscal = a.take<double>(8);
   g->dcount = a.take<int>(8);
   g->dtotal = a.take<int32_t>(2 * (L + 1));
+  g->dhist = a.take<double>(kHistCap);
+  g->dctr = a.take<int>(64);
   int64_t cap = 0;
   for (int l = lcq; l < L; ++l) {
     const int64_t m = n_interior(g->lv[l].L);
@@ -277,18 +296,74 @@ void smooth(qmg_grid_t* g, LevelBuf& B, int sweeps, bool zero_init) {
   for (int k = 0; k < sweeps; ++k) {
     const int mode = (k == 0 && zero_init) ? 1 : 0;
     hipEvent_t* ev = timed ? prof_pair(g) : nullptr;
-    if (ev) QMG_HIP(hipEventRecord(ev[0], S(g)));
     launch_stencil<T>(B.L, mode, (const T*)B.u, (const T*)B.b, (T*)B.t, eps_of<T>(B), B.A, om,
-                      nullptr, nullptr, S(g));
-    if (ev) QMG_HIP(hipEventRecord(ev[1], S(g)));
+                      nullptr, nullptr, S(g), ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
     std::swap(B.u, B.t);
   }
+}
+
+template <typename T>
+FusedArgs<T> fused_args(qmg_grid_t* g, int lf) {
+  FusedArgs<T> a{};
+  a.lc = g->lc;
+  a.lf = lf;
+  a.mu_pre = g->opts.mu_pre;
+  a.mu_post = g->opts.mu_post;
+  a.coarse_direct = g->coarse_direct ? 1 : 0;
+  a.nc = g->nc;
+  a.omega = (T)g->opts.omega;
+  a.Ainv = g->Ainv;
+  for (int l = g->lc; l <= lf; ++l) {
+    LevelBuf& B = g->lv[l];
+    const int s = l - g->lc;
+    a.L[s] = B.L;
+    a.A[s] = B.A;
+    a.P[s] = B.P;
+    a.eps[s] = eps_of<T>(B);
+    a.u[s] = (T*)B.u;
+    a.b[s] = (T*)B.b;
+  }
+  return a;
+}
+
+bool p_stored(const qmg_grid_t* g) {
+  return g->lc + 1 <= g->Lmax && g->lv[g->lc + 1].P.src != SRC_GEOM;
+}
+
+// Largest level whose coarse cycle fits in the LDS of one workgroup (-1: none);
+// prolongation weights go to LDS when they fit as well.
+template <typename T>
+int choose_fused_top(qmg_grid_t* g, bool& pw_lds) {
+  int best = -1;
+  for (int lf = g->lc; lf < g->Lmax && lf - g->lc + 1 <= kMaxFused; ++lf) {
+    for (int pl = 1; pl >= 0; --pl) {
+      FusedArgs<T> a = fused_args<T>(g, lf);
+      if ((int64_t)fused_lds_layout<T>(g->d, a, p_stored(g), pl == 1) <= g->lds_max) {
+        best = lf;
+        pw_lds = pl == 1;
+        break;
+      }
+    }
+  }
+  return best;
+}
+
+template <typename T>
+void fused_coarse(qmg_grid_t* g) {
+  FusedArgs<T> a = fused_args<T>(g, g->lf);
+  fused_lds_layout<T>(g->d, a, p_stored(g), g->lf_pw_lds);
+  const int psrc = g->lf > g->lc ? g->lv[g->lc + 1].P.src : SRC_GEOM;
+  launch_fused_coarse<T>(g->d, a, g->lv[g->lf].A.src, psrc, g->fmt, S(g));
 }
 
 template <typename T>
 void vcycle(qmg_grid_t* g, int l, bool zero_init) {
   LevelBuf& F = g->lv[l];
   const int mu = g->opts.mu_pre, nu = g->opts.mu_post;
+  if (l == g->lf && l < g->Lmax && zero_init) {
+    fused_coarse<T>(g);
+    return;
+  }
   if (l == g->lc) {
     if (g->coarse_direct)
       launch_coarse_solve<T>(F.L, g->Ainv, g->nc, (const T*)F.b, (T*)F.u, S(g));
@@ -323,7 +398,7 @@ double read_scalar(qmg_grid_t* g) {
 
 // ||b - A u||_2 on the finest level, FP64 (the FP32 residual of the mixed loop
 // is written to the finest inner right-hand side on the way).
-double finest_residual_norm(qmg_grid_t* g) {
+void enqueue_residual_norm(qmg_grid_t* g, bool record) {
   LevelBuf& F = g->lv[g->Lmax];
   int np = 0;
   if (g->mixed) {
@@ -332,7 +407,14 @@ double finest_residual_norm(qmg_grid_t* g) {
     launch_stencil<double>(F.L, 2, (const double*)F.u, (const double*)F.b, (double*)F.r, F.eps64,
                            F.A, 0.0, g->partial, &np, S(g));
   }
-  launch_sum_partials(g->partial, np, g->dscal, S(g));
+  if (record)
+    launch_sum_partials(g->partial, np, g->dscal, S(g), g->dhist, g->dctr, kHistCap);
+  else
+    launch_sum_partials(g->partial, np, g->dscal, S(g));
+}
+
+double finest_residual_norm(qmg_grid_t* g) {
+  enqueue_residual_norm(g, false);
   return std::sqrt(read_scalar(g));
 }
 
@@ -345,6 +427,83 @@ void one_cycle(qmg_grid_t* g) {
   }
   for (int m = 0; m < g->opts.inner_cycles; ++m) vcycle<float>(g, g->Lmax, m == 0);
   launch_axpy_mixed(g->lv[g->Lmax].L, g->x64, (const float*)g->lv[g->Lmax].u, S(g));
+}
+
+void drop_graph(qmg_grid_t* g) {
+  if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+  g->gexec = nullptr;
+}
+
+// Replaying one captured cycle needs every level to end a cycle in the buffer
+// it started from, i.e. an even number of sweeps per level.
+bool graph_usable(const qmg_grid_t* g) {
+  if (g->prof_on) return false;
+  if ((g->opts.mu_pre + g->opts.mu_post) % 2 != 0) return false;
+  const char* e = std::getenv("QMG_NO_GRAPH");
+  return !(e && e[0] == '1');
+}
+
+void ensure_graph(qmg_grid_t* g) {
+  if (g->gexec) return;
+  hipGraph_t graph = nullptr;
+  QMG_HIP(hipStreamBeginCapture(S(g), hipStreamCaptureModeThreadLocal));
+  try {
+    one_cycle(g);
+    enqueue_residual_norm(g, true);
+  } catch (...) {
+    hipGraph_t dummy = nullptr;
+    (void)hipStreamEndCapture(S(g), &dummy);
+    if (dummy) (void)hipGraphDestroy(dummy);
+    throw;
+  }
+  QMG_HIP(hipStreamEndCapture(S(g), &graph));
+  const hipError_t e = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    g->gexec = nullptr;
+    throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+}
+
+// Enqueues B cycles, each followed by the finest residual norm recorded on the
+// device, then the copy of the B squared norms to pinned host memory and an
+// event; nothing waits.
+void enqueue_batch(qmg_grid_t* g, int B) {
+  if (B <= 0 || B > kHistCap) throw ApiError(QMG_EINVAL, "batch size out of range");
+  launch_zero<int>(g->dctr, 1, S(g));
+  if (graph_usable(g)) {
+    ensure_graph(g);
+    for (int c = 0; c < B; ++c) QMG_HIP(hipGraphLaunch(g->gexec, S(g)));
+  } else {
+    for (int c = 0; c < B; ++c) {
+      one_cycle(g);
+      enqueue_residual_norm(g, true);
+    }
+  }
+  QMG_HIP(hipMemcpyAsync(g->hnorm, g->dhist, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, S(g)));
+  QMG_HIP(hipEventRecord(g->bev, S(g)));
+  g->inflight = B;
+}
+
+bool batch_ready(qmg_grid_t* g) {
+  const hipError_t e = hipEventQuery(g->bev);
+  if (e == hipSuccess) return true;
+  if (e == hipErrorNotReady) return false;
+  throw HipError(std::string("hipEventQuery: ") + hipGetErrorString(e));
+}
+
+// Waits for the batch in flight and returns its residual norms.
+std::vector<double> collect_batch(qmg_grid_t* g) {
+  QMG_HIP(hipEventSynchronize(g->bev));
+  std::vector<double> out((size_t)g->inflight);
+  for (int c = 0; c < g->inflight; ++c) out[c] = std::sqrt(g->hnorm[c]);
+  g->inflight = 0;
+  return out;
+}
+
+std::vector<double> run_batch(qmg_grid_t* g, int B) {
+  enqueue_batch(g, B);
+  return collect_batch(g);
 }
 
 // ---------------------------------------------------------------------------
@@ -455,6 +614,7 @@ void assign_stores(qmg_grid_t* g) {
 void build(qmg_grid_t* g, qmg_solve_report* info) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!g->have_coef) throw ApiError(QMG_ESTATE, "set_coefficients must precede build_operators");
+  drop_graph(g);
   const int L = g->Lmax, d = g->d, NS = ipow(3, d), NC = 1 << d;
   const bool galerkin = g->opts.transfer != QMG_GEOMETRIC;
   const bool boxmg = g->opts.transfer == QMG_BOXMG;
@@ -562,6 +722,15 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
   double* Alc = fullA(g->lc);
   if (!galerkin && !g->plain && g->lc == L) launch_materialise(g->lv[L].L, g->lv[L].eps64, geom, Alc, s);
   setup_coarse(g, Alc);
+  {
+    int dev = 0, optin = 0;
+    QMG_HIP(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess && optin > 0)
+      g->lds_max = optin;
+    else
+      (void)hipGetLastError();
+  }
+  g->lf = g->mixed ? choose_fused_top<float>(g, g->lf_pw_lds) : choose_fused_top<double>(g, g->lf_pw_lds);
   g->have_ops = true;
   if (info) {
     std::memset(info, 0, sizeof(*info));
@@ -662,6 +831,70 @@ void apply_op(qmg_grid_t* g, int op, int level, const double* x, const double* b
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Solve loop as a state machine (used blocking by qmg_solve and polled by the
+// server).  Cycles run in batches between host synchronisations; the batch
+// length follows the observed convergence factor so that the tolerance is
+// reached in the last cycle of a batch (a batch is never cut short: cycles
+// after the crossing are kept and counted).
+// ---------------------------------------------------------------------------
+namespace qmg {
+
+void solve_begin(qmg_grid_t* g, SolveState& st, double tol, int max_cycles) {
+  need_ops(g);
+  if (max_cycles < 0 || !(tol >= 0.0)) throw ApiError(QMG_EINVAL, "bad tolerance or cycle limit");
+  st = SolveState{};
+  st.tol = tol;
+  st.max_cycles = max_cycles;
+  st.t0 = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  st.rr = (g->bnorm > 0) ? finest_residual_norm(g) / g->bnorm : 0.0;
+  st.outer = 1;
+  st.done = !(st.rr > tol) || max_cycles == 0;
+}
+
+void solve_enqueue(qmg_grid_t* g, SolveState& st) {
+  const int B = std::max(1, std::min({st.batch, st.max_cycles - st.cycles, kHistCap}));
+  enqueue_batch(g, B);
+}
+
+bool solve_ready(qmg_grid_t* g) { return batch_ready(g); }
+
+void solve_collect(qmg_grid_t* g, SolveState& st) {
+  const int B = g->inflight;
+  const std::vector<double> nr = collect_batch(g);
+  for (int c = 0; c < B; ++c) st.history.push_back(nr[c] / g->bnorm);
+  st.cycles += B;
+  st.outer += B;
+  st.rr_prev = st.rr;
+  st.rr = nr[B - 1] / g->bnorm;
+  const double rho = (st.rr > 0 && st.rr_prev > 0) ? std::pow(st.rr / st.rr_prev, 1.0 / B) : 0.0;
+  if (rho > 0.0 && rho < 1.0 && st.rr > st.tol) {
+    // half the predicted remainder: multigrid factors often improve over the
+    // first cycles, so a full prediction would overshoot
+    const double need = std::log(st.tol / st.rr) / std::log(rho);
+    st.batch = std::max(1, std::min((int)std::floor(0.5 * need), 64));
+  } else {
+    st.batch = 1;
+  }
+  st.done = !(st.rr > st.tol) || st.cycles >= st.max_cycles || !std::isfinite(st.rr);
+}
+
+void solve_fill_report(qmg_grid_t* g, const SolveState& st, qmg_solve_report* rep) {
+  if (!rep) return;
+  std::memset(rep, 0, sizeof(*rep));
+  const int inner = g->mixed ? g->opts.inner_cycles : 1;
+  rep->cycles = st.cycles * inner;
+  rep->outer_iters = st.outer;
+  rep->relres = st.rr;
+  rep->coarsest_level_used = g->lc;
+  rep->vertex_updates = (int64_t)st.cycles * inner * updates_per_cycle(g);
+  rep->bytes_operators = g->bytes_ops;
+  rep->zero_delta_fraction = g->zero_frac;
+  rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count() - st.t0;
+}
+
+}  // namespace qmg
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -704,6 +937,10 @@ int qmg_create_grid(const qmg_grid_desc* desc, const qmg_solver_opts* opts, void
     try {
       init_modes(g, desc, opts);
       g->stream = (hipStream_t)stream;
+      if (g->stream == nullptr) {  // graph capture needs a stream other than the null stream
+        QMG_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+        g->own_stream = true;
+      }
       Arena probe;
       layout(g, probe);
       const size_t need = probe.off + 256;
@@ -726,10 +963,15 @@ int qmg_create_grid(const qmg_grid_desc* desc, const qmg_solver_opts* opts, void
       a.base = (char*)(((uintptr_t)g->base + 255) & ~(uintptr_t)255);
       layout(g, a);
       QMG_HIP(hipMemsetAsync(g->base, 0, need, g->stream));
+      QMG_HIP(hipHostMalloc((void**)&g->hnorm, kHistCap * sizeof(double), hipHostMallocDefault));
+      QMG_HIP(hipEventCreateWithFlags(&g->bev, hipEventDisableTiming));
       QMG_HIP(hipStreamSynchronize(g->stream));
       g->n_unknowns = n_interior(g->lv[g->Lmax].L);
     } catch (...) {
       if (g->owns && g->base) (void)hipFree(g->base);
+      if (g->hnorm) (void)hipHostFree(g->hnorm);
+      if (g->bev) (void)hipEventDestroy(g->bev);
+      if (g->own_stream) (void)hipStreamDestroy(g->stream);
       delete g;
       throw;
     }
@@ -803,6 +1045,7 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
     QMG_HIP(hipStreamSynchronize(S(g)));
     g->have_coef = true;
     g->have_ops = false;
+    drop_graph(g);
   });
 }
 
@@ -817,46 +1060,34 @@ int qmg_vcycle(qmg_grid_t* g, int n, double* relres) {
   return guard(g, [&] {
     need_ops(g);
     if (n < 0) throw ApiError(QMG_EINVAL, "negative cycle count");
-    for (int c = 0; c < n; ++c) {
-      if (g->mixed) finest_residual_norm(g);  // forms the inner right-hand side
-      one_cycle(g);
-      if (relres) relres[c] = finest_residual_norm(g) / g->bnorm;
+    if (g->mixed && n > 0) finest_residual_norm(g);  // forms the inner right-hand side
+    int done = 0;
+    while (done < n) {
+      const int B = std::min(n - done, kHistCap);
+      const std::vector<double> nr = run_batch(g, B);
+      if (relres)
+        for (int c = 0; c < B; ++c) relres[done + c] = nr[c] / g->bnorm;
+      done += B;
     }
-    QMG_HIP(hipStreamSynchronize(S(g)));
   });
 }
 
 int qmg_solve(qmg_grid_t* g, double rel_tol, int max_cycles, double* history, qmg_solve_report* rep) {
   int status = QMG_OK;
   const int rc = guard(g, [&] {
-    need_ops(g);
-    if (max_cycles < 0 || !(rel_tol >= 0.0)) throw ApiError(QMG_EINVAL, "bad tolerance or cycle limit");
-    const auto t0 = std::chrono::steady_clock::now();
-    int cycles = 0, outer = 0;
-    double rr = (g->bnorm > 0) ? finest_residual_norm(g) / g->bnorm : 0.0;
-    ++outer;
-    while (rr > rel_tol && cycles < max_cycles) {
-      one_cycle(g);
-      rr = finest_residual_norm(g) / g->bnorm;
-      ++outer;
-      if (history) history[cycles] = rr;
-      ++cycles;
-      if (!std::isfinite(rr)) break;
+    SolveState st;
+    solve_begin(g, st, rel_tol, max_cycles);
+    while (!st.done) {
+      solve_enqueue(g, st);
+      solve_collect(g, st);
     }
-    if (rep) {
-      std::memset(rep, 0, sizeof(*rep));
-      rep->cycles = cycles * (g->mixed ? g->opts.inner_cycles : 1);
-      rep->outer_iters = outer;
-      rep->relres = rr;
-      rep->coarsest_level_used = g->lc;
-      rep->vertex_updates = (int64_t)cycles * (g->mixed ? g->opts.inner_cycles : 1) * updates_per_cycle(g);
-      rep->bytes_operators = g->bytes_ops;
-      rep->zero_delta_fraction = g->zero_frac;
-      rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    }
-    if (!(rr <= rel_tol)) {
+    if (history)
+      for (size_t c = 0; c < st.history.size(); ++c) history[c] = st.history[c];
+    solve_fill_report(g, st, rep);
+    if (!(st.rr <= rel_tol)) {
       status = QMG_ENOTCONV;
-      set_err(g, "tolerance not reached: relres " + std::to_string(rr) + " after " + std::to_string(cycles) + " cycles");
+      set_err(g, "tolerance not reached: relres " + std::to_string(st.rr) + " after " +
+                     std::to_string(st.cycles) + " cycles");
     }
   });
   return rc != QMG_OK ? rc : status;
@@ -890,6 +1121,7 @@ int qmg_profile_enable(qmg_grid_t* g, int on) {
     if (!g) throw ApiError(QMG_EINVAL, "null grid");
     prof_harvest(g);
     g->prof_on = on != 0;
+    drop_graph(g);
   });
 }
 
@@ -910,7 +1142,11 @@ int qmg_destroy_grid(qmg_grid_t* g) {
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   else (void)hipDeviceSynchronize();
   for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
+  drop_graph(g);
   if (g->owns && g->base && hipFree(g->base) != hipSuccess) rc = QMG_EHIP;
+  if (g->hnorm) (void)hipHostFree(g->hnorm);
+  if (g->bev) (void)hipEventDestroy(g->bev);
+  if (g->own_stream) (void)hipStreamDestroy(g->stream);
   delete g;
   return rc;
 }

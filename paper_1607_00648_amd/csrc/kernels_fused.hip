@@ -1,0 +1,298 @@
+// Coarse part of the V-cycle in one workgroup, with the levels held in LDS.
+//
+// The coarse levels of a tripartitioned hierarchy are tiny (2D: 676, 64 and 4
+// unknowns on levels 3, 2, 1), so seven launches per level cost far more than
+// the arithmetic, and a workgroup walking them in global memory is bound by L2
+// latency.  This kernel loads, once per cycle, the stencil rows (rebuilt from
+// the coefficients and the delta store) and the prolongation weights of levels
+// lc..lf into LDS, keeps every iterate of those levels in LDS, and runs the
+// whole V-cycle from level lf (which has just received its restricted
+// right-hand side and starts from zero) down to the coarsest level and back up:
+// every phase is a strided loop over a level's interior vertices followed by a
+// workgroup barrier.  Only the final iterate of level lf goes back to global
+// memory.
+#include "level_ops.hpp"
+
+namespace qmg {
+
+namespace {
+
+template <int D>
+constexpr int block_of() { return D == 2 ? 1024 : 256; }
+
+// 32-bit index arithmetic (the fused levels have a few thousand vertices)
+__device__ inline void vertex_of(int idx, int m, int d, int& i, int& j, int& k) {
+  const int q = idx / m;
+  i = idx - q * m + 1;
+  if (d == 3) {
+    const int r = q / m;
+    j = q - r * m + 1;
+    k = r + 1;
+  } else {
+    j = q + 1;
+    k = 0;
+  }
+}
+
+// compact LDS index of vertex (i,j,k) of a level with w = n+1 vertices per axis
+__device__ inline int cidx(int w, int i, int j, int k) { return i + w * (j + w * k); }
+
+template <int D, typename T, int ASRC, int PSRC, int FMT>
+struct Fused {
+  static constexpr int NS = Dim<D>::NS, NC = Dim<D>::NC, BS = block_of<D>();
+  const FusedArgs<T>& a;
+  char* smem;
+  __device__ Fused(const FusedArgs<T>& args, char* s) : a(args), smem(s) {}
+
+  __device__ int w(int s) const { return a.L[s].n + 1; }
+  __device__ int m(int s) const { return a.L[s].n - 1; }
+  __device__ int nint(int s) const { return D == 3 ? m(s) * m(s) * m(s) : m(s) * m(s); }
+  __device__ T* vec(int s, int which) const {  // 0 u, 1 t, 2 b, 3 r
+    return (T*)(smem + a.lds_vec[s]) + which * a.lds_nslot[s];
+  }
+  __device__ T* rows(int s) const { return (T*)(smem + a.lds_rows[s]); }
+  __device__ T* pw(int s) const { return (T*)(smem + a.lds_pw[s]); }
+
+  __device__ T row_dot_lds(const T* row, const T* u, int ws, int c) const {
+    T acc = (T)0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int o = off_x(k) + ws * (off_y(k) + (D == 3 ? ws * off_z(k) : 0));
+      acc += row[k] * u[c + o];
+    }
+    return acc;
+  }
+
+  __device__ void load() const {
+    for (int s = 0; s <= a.lf - a.lc; ++s) {
+      const Lat& L = a.L[s];
+      const int ws = w(s), ms = m(s);
+      const int nsl = a.lds_nslot[s];
+      for (int q = threadIdx.x; q < 4 * nsl; q += BS) vec(s, 0)[q] = (T)0;
+      for (int idx = threadIdx.x; idx < nint(s); idx += BS) {
+        int i, j, k;
+        vertex_of(idx, ms, D, i, j, k);
+        const int64_t v = i + (int64_t)j * L.pitch + (int64_t)k * L.plane;
+        T r[NS];
+        op_row<D, T, ASRC, FMT>(a.eps[s], a.A[s], L, v, r);
+        T* dst = rows(s) + (int64_t)idx * NS;
+#pragma unroll
+        for (int e = 0; e < NS; ++e) dst[e] = r[e];
+        if (s >= 1 && PSRC != SRC_GEOM && a.pw_lds) {
+          const int rx = i % 3, ry = j % 3, rz = k % 3;
+          T* pd = pw(s) + (int64_t)cidx(ws, i, j, k) * NC;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) pd[c] = (T)pweight<D, PSRC, FMT>(a.P[s], L, v, rx, ry, rz, c);
+        }
+      }
+    }
+    __syncthreads();
+    // restricted right-hand side of the top level
+    const int top = a.lf - a.lc;
+    const Lat& L = a.L[top];
+    for (int idx = threadIdx.x; idx < nint(top); idx += BS) {
+      int i, j, k;
+      vertex_of(idx, m(top), D, i, j, k);
+      vec(top, 2)[cidx(w(top), i, j, k)] = a.b[top][i + (int64_t)j * L.pitch + (int64_t)k * L.plane];
+    }
+    __syncthreads();
+  }
+
+  // one Jacobi sweep u -> out on level s (from zero: u not read)
+  __device__ void sweep(int s, const T* u, T* out, bool from_zero) const {
+    const int ws = w(s), ms = m(s);
+    const T* bv = vec(s, 2);
+    for (int idx = threadIdx.x; idx < nint(s); idx += BS) {
+      int i, j, k;
+      vertex_of(idx, ms, D, i, j, k);
+      const int c = cidx(ws, i, j, k);
+      const T* row = rows(s) + (int64_t)idx * NS;
+      const T dg = row[NS / 2];
+      out[c] = from_zero ? a.omega * bv[c] / dg : u[c] + a.omega * (bv[c] - row_dot_lds(row, u, ws, c)) / dg;
+    }
+    __syncthreads();
+  }
+
+  // returns the buffer index (0 = u, 1 = t) holding the result
+  __device__ int smooth(int s, int cur, int mu, bool zero_init) const {
+    for (int q = 0; q < mu; ++q) {
+      sweep(s, vec(s, cur), vec(s, 1 - cur), zero_init && q == 0);
+      cur = 1 - cur;
+    }
+    return cur;
+  }
+
+  __device__ T weight(int s, int fc, int i, int j, int k, int kap) const {
+    const int rx = i % 3, ry = j % 3, rz = k % 3;
+    if (PSRC == SRC_GEOM)
+      return (T)(dlin1(rx, kap & 1) * dlin1(ry, (kap >> 1) & 1) * (D == 3 ? dlin1(rz, (kap >> 2) & 1) : 1.0));
+    if (!a.pw_lds) {
+      const Lat& L = a.L[s];
+      return (T)pweight<D, PSRC, FMT>(a.P[s], L, i + (int64_t)j * L.pitch + (int64_t)k * L.plane, rx, ry, rz, kap);
+    }
+    return pw(s)[(int64_t)fc * NC + kap];
+  }
+
+  __device__ void run() const {
+    const int top = a.lf - a.lc;
+    int cur[kMaxFused];
+    for (int s = top; s >= 1; --s) {
+      cur[s] = smooth(s, 0, a.mu_pre, true);
+      const int ws = w(s), ms = m(s);
+      const T* u = vec(s, cur[s]);
+      T* r = vec(s, 3);
+      for (int idx = threadIdx.x; idx < nint(s); idx += BS) {
+        int i, j, k;
+        vertex_of(idx, ms, D, i, j, k);
+        const int c = cidx(ws, i, j, k);
+        r[c] = vec(s, 2)[c] - row_dot_lds(rows(s) + (int64_t)idx * NS, u, ws, c);
+      }
+      __syncthreads();
+      const int wc = w(s - 1), mc = m(s - 1);
+      T* bc = vec(s - 1, 2);
+      for (int idx = threadIdx.x; idx < nint(s - 1); idx += BS) {
+        int I, J, K;
+        vertex_of(idx, mc, D, I, J, K);
+        T acc = (T)0;
+        const int zlo = (D == 3) ? -2 : 0, zhi = (D == 3) ? 2 : 0;
+        for (int oz = zlo; oz <= zhi; ++oz)
+          for (int oy = -2; oy <= 2; ++oy)
+#pragma unroll
+            for (int ox = -2; ox <= 2; ++ox) {
+              const int fi = 3 * I + ox, fj = 3 * J + oy, fk = 3 * K + oz;
+              const int fc = cidx(ws, fi, fj, fk);
+              const int kap = (ox < 0 ? 1 : 0) | (oy < 0 ? 2 : 0) | (oz < 0 ? 4 : 0);
+              acc += weight(s, fc, fi, fj, fk, kap) * r[fc];
+            }
+        bc[cidx(wc, I, J, K)] = acc;
+      }
+      __syncthreads();
+    }
+    // coarsest level
+    if (a.coarse_direct) {
+      const int ws = w(0), ms = m(0);
+      const T* b0 = vec(0, 2);
+      T* u0 = vec(0, 0);
+      for (int row = threadIdx.x; row < a.nc; row += BS) {
+        double acc = 0.0;
+        for (int c = 0; c < a.nc; ++c) {
+          int i, j, k;
+          vertex_of(c, ms, D, i, j, k);
+          acc += a.Ainv[(int64_t)row * a.nc + c] * (double)b0[cidx(ws, i, j, k)];
+        }
+        int i, j, k;
+        vertex_of(row, ms, D, i, j, k);
+        u0[cidx(ws, i, j, k)] = (T)acc;
+      }
+      __syncthreads();
+      cur[0] = 0;
+    } else {
+      cur[0] = smooth(0, 0, a.mu_pre + a.mu_post, true);
+    }
+    for (int s = 1; s <= top; ++s) {
+      const int ws = w(s), ms = m(s), wc = w(s - 1);
+      T* u = vec(s, cur[s]);
+      const T* ec = vec(s - 1, cur[s - 1]);
+      for (int idx = threadIdx.x; idx < nint(s); idx += BS) {
+        int i, j, k;
+        vertex_of(idx, ms, D, i, j, k);
+        const int fc = cidx(ws, i, j, k);
+        const int qx = i / 3, qy = j / 3, qz = k / 3;
+        T acc = (T)0;
+#pragma unroll
+        for (int kap = 0; kap < NC; ++kap) {
+          const int kx = kap & 1, ky = (kap >> 1) & 1, kz = (kap >> 2) & 1;
+          if ((kx && i % 3 == 0) || (ky && j % 3 == 0) || (kz && k % 3 == 0)) continue;
+          acc += weight(s, fc, i, j, k, kap) * ec[cidx(wc, qx + kx, qy + ky, qz + kz)];
+        }
+        u[fc] += acc;
+      }
+      __syncthreads();
+      cur[s] = smooth(s, cur[s], a.mu_post, false);
+    }
+    // result of level lf back to global memory
+    const Lat& L = a.L[top];
+    const T* res = vec(top, cur[top]);
+    for (int idx = threadIdx.x; idx < nint(top); idx += BS) {
+      int i, j, k;
+      vertex_of(idx, m(top), D, i, j, k);
+      a.u[top][i + (int64_t)j * L.pitch + (int64_t)k * L.plane] = res[cidx(w(top), i, j, k)];
+    }
+  }
+};
+
+template <int D, typename T, int ASRC, int PSRC, int FMT>
+__global__ __launch_bounds__(block_of<D>()) void k_fused_coarse(FusedArgs<T> a) {
+  extern __shared__ char smem[];
+  Fused<D, T, ASRC, PSRC, FMT> f(a, smem);
+  f.load();
+  f.run();
+}
+
+template <int D, typename T, int AS, int PS, int F>
+void launch_one(const FusedArgs<T>& a, hipStream_t s) {
+  static int attr_set = 0;  // opt in to LDS beyond the 64 KiB default (per kernel)
+  if (a.lds_bytes > attr_set) {
+    QMG_HIP(hipFuncSetAttribute((const void*)k_fused_coarse<D, T, AS, PS, F>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes));
+    attr_set = a.lds_bytes;
+  }
+  hipLaunchKernelGGL((k_fused_coarse<D, T, AS, PS, F>), dim3(1), dim3(block_of<D>()), a.lds_bytes, s, a);
+}
+
+template <int D, typename T>
+void dispatch_fused(const FusedArgs<T>& a, int asrc, int psrc, int fmt, hipStream_t s) {
+  if (asrc == SRC_PLAIN) {
+    launch_one<D, T, SRC_PLAIN, SRC_PLAIN, F64>(a, s);
+  } else if (asrc == SRC_GEOM) {
+    launch_one<D, T, SRC_GEOM, SRC_GEOM, F64>(a, s);
+  } else {
+    const bool ph = psrc == SRC_HIER;
+    switch (fmt) {
+      case F64: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, F64>(a, s); else launch_one<D, T, SRC_HIER, SRC_GEOM, F64>(a, s); break;
+      case F32: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, F32>(a, s); else launch_one<D, T, SRC_HIER, SRC_GEOM, F32>(a, s); break;
+      case F16: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, F16>(a, s); else launch_one<D, T, SRC_HIER, SRC_GEOM, F16>(a, s); break;
+      default: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, BF16>(a, s); else launch_one<D, T, SRC_HIER, SRC_GEOM, BF16>(a, s); break;
+    }
+  }
+  QMG_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+template <typename T>
+size_t fused_lds_layout(int d, FusedArgs<T>& a, bool p_stored, bool pw_lds) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = (off + 15) & ~size_t(15);
+    const size_t p = off;
+    off += bytes;
+    return p;
+  };
+  const int NS = d == 2 ? 9 : 27, NC = 1 << d;
+  for (int s = 0; s <= a.lf - a.lc; ++s) {
+    const int w = a.L[s].n + 1, m = a.L[s].n - 1;
+    const int nsl = d == 3 ? w * w * w : w * w;
+    const int nin = d == 3 ? m * m * m : m * m;
+    a.lds_nslot[s] = nsl;
+    a.lds_vec[s] = (int)take((size_t)4 * nsl * sizeof(T));
+    a.lds_rows[s] = (int)take((size_t)nin * NS * sizeof(T));
+    a.lds_pw[s] = (s >= 1 && p_stored && pw_lds) ? (int)take((size_t)nsl * NC * sizeof(T)) : 0;
+  }
+  a.pw_lds = pw_lds ? 1 : 0;
+  a.lds_bytes = (int)((off + 15) & ~size_t(15));
+  return (size_t)a.lds_bytes;
+}
+template size_t fused_lds_layout<double>(int, FusedArgs<double>&, bool, bool);
+template size_t fused_lds_layout<float>(int, FusedArgs<float>&, bool, bool);
+
+template <typename T>
+void launch_fused_coarse(int d, const FusedArgs<T>& a, int asrc, int psrc, int fmt, hipStream_t s) {
+  if (a.lf - a.lc + 1 > kMaxFused) throw HipError("fused coarse cycle: too many levels");
+  if (d == 2) dispatch_fused<2, T>(a, asrc, psrc, fmt, s);
+  else dispatch_fused<3, T>(a, asrc, psrc, fmt, s);
+}
+template void launch_fused_coarse<double>(int, const FusedArgs<double>&, int, int, int, hipStream_t);
+template void launch_fused_coarse<float>(int, const FusedArgs<float>&, int, int, int, hipStream_t);
+
+}  // namespace qmg

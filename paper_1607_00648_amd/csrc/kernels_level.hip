@@ -7,7 +7,9 @@
 // per wavefront.  Stencil rows are rebuilt per vertex from the 2^d cell
 // coefficients (rediscretisation on the fly) plus the stored delta, or read
 // from the plain FP64 store.
-#include "device_ops.hpp"
+#include <hip/hip_ext.h>
+
+#include "level_ops.hpp"
 
 namespace qmg {
 
@@ -48,23 +50,11 @@ __global__ __launch_bounds__(256) void k_stencil(Lat L, const T* __restrict__ u,
   if (act) {
     const int64_t v = i + (int64_t)j * L.pitch + (int64_t)kz * L.plane;
     T a[NS];
-    if (SRC == SRC_PLAIN) {
-      const double* Ad = (const double*)A.dense;
-#pragma unroll
-      for (int k = 0; k < NS; ++k) a[k] = (T)Ad[(int64_t)k * L.nslot + v];
-    } else {
-      geom_row<D, T>(eps, v, L, a);
-      if (SRC == SRC_HIER) add_delta<FMT, NS, T>(A, v, a);
-    }
+    op_row<D, T, SRC, FMT>(eps, A, L, v, a);
     if (MODE == 1) {
       out[v] = (TO)(omega * b[v] / a[NS / 2]);
     } else {
-      T au = (T)0;
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        if (D == 3 && SRC == SRC_GEOM && kref(3, ndiff_of<3>(k)) == 0.0) continue;
-        au += a[k] * u[v + slot_off(L, off_x(k), off_y(k), D == 3 ? off_z(k) : 0)];
-      }
+      const T au = row_dot<D, T, SRC>(a, u, L, v);
       if (MODE == 0) {
         out[v] = (TO)(u[v] + omega * (b[v] - au) / a[NS / 2]);
       } else {
@@ -82,7 +72,9 @@ __global__ __launch_bounds__(256) void k_stencil(Lat L, const T* __restrict__ u,
 }
 
 __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict__ p, int n,
-                                                       double* __restrict__ out) {
+                                                       double* __restrict__ out,
+                                                       double* __restrict__ hist, int* __restrict__ counter,
+                                                       int cap) {
   __shared__ double red[16];
   double x = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) x += p[i];
@@ -94,27 +86,12 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict_
     double s = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
     out[0] = s;
-  }
-}
-
-// Weight of the parent floor(f/3)+kappa at fine vertex f (slot vf; r = f mod 3).
-template <int D, int SRC, int FMT>
-__device__ inline double pweight(const Store& P, const Lat& Lf, int64_t vf, int rx, int ry, int rz,
-                                 int kap) {
-  const int kx = kap & 1, ky = (kap >> 1) & 1, kz = (kap >> 2) & 1;
-  if (SRC == SRC_PLAIN) return ((const double*)P.dense)[(int64_t)kap * Lf.nslot + vf];
-  double w = dlin1(rx, kx) * dlin1(ry, ky) * (D == 3 ? dlin1(rz, kz) : 1.0);
-  if (SRC == SRC_HIER) {
-    const int32_t cb = P.blk[vf / kSeg];
-    if (cb >= 0) {
-      const int lane = (int)(vf % kSeg);
-      const int64_t idx = ((int64_t)cb * Dim<D>::NC + kap) * kSeg + lane;
-      double dv = (double)Dec<FMT>::get(P.payload, idx);
-      if (FMT == F16) dv = ldexp(dv, (int)P.scale[(int64_t)cb * kSeg + lane]);
-      w += dv;
+    if (hist != nullptr) {
+      const int c = counter[0];
+      if (c < cap) hist[c] = s;
+      counter[0] = c + 1;
     }
   }
-  return w;
 }
 
 // b_c(V) = sum over fine f = 3V + o, o in [-2,2]^d, of P(f,V) r(f)  (R = P^T).
@@ -126,26 +103,7 @@ __global__ __launch_bounds__(256) void k_restrict(Lat Lf, Lat Lc, const T* __res
   const int K = (D == 3) ? (int)blockIdx.z : 0;
   const int nc = Lc.n;
   if (!(I >= 1 && I < nc && J >= 1 && J < nc && (D == 2 || (K >= 1 && K < nc)))) return;
-  const int64_t vf0 = 3 * I + (int64_t)3 * J * Lf.pitch + (int64_t)3 * K * Lf.plane;
-  T acc = (T)0;
-  const int zlo = (D == 3) ? -2 : 0, zhi = (D == 3) ? 2 : 0;
-#pragma unroll
-  for (int oz = zlo; oz <= zhi; ++oz)
-#pragma unroll
-    for (int oy = -2; oy <= 2; ++oy)
-#pragma unroll
-      for (int ox = -2; ox <= 2; ++ox) {
-        const int64_t vf = vf0 + slot_off(Lf, ox, oy, oz);
-        const int kap = (ox < 0 ? 1 : 0) | (oy < 0 ? 2 : 0) | (oz < 0 ? 4 : 0);
-        double w;
-        if (SRC == SRC_GEOM) {
-          w = (1.0 - abs(ox) / 3.0) * (1.0 - abs(oy) / 3.0) * (D == 3 ? (1.0 - abs(oz) / 3.0) : 1.0);
-        } else {
-          w = pweight<D, SRC, FMT>(P, Lf, vf, (ox + 3) % 3, (oy + 3) % 3, (oz + 3) % 3, kap);
-        }
-        acc += (T)w * r[vf];
-      }
-  bc[I + (int64_t)J * Lc.pitch + (int64_t)K * Lc.plane] = acc;
+  bc[I + (int64_t)J * Lc.pitch + (int64_t)K * Lc.plane] = restrict_at<D, T, SRC, FMT>(Lf, r, P, I, J, K);
 }
 
 // u_f = (ADD ? u_f : 0) + sum over parents floor(f/3)+kappa of P(f,V) e_c(V).
@@ -158,18 +116,7 @@ __global__ __launch_bounds__(256) void k_prolong(Lat Lf, Lat Lc, const T* __rest
   const int n = Lf.n;
   if (!(i >= 1 && i < n && j >= 1 && j < n && (D == 2 || (kz >= 1 && kz < n)))) return;
   const int64_t vf = i + (int64_t)j * Lf.pitch + (int64_t)kz * Lf.plane;
-  const int qx = i / 3, qy = j / 3, qz = kz / 3;
-  const int rx = i - 3 * qx, ry = j - 3 * qy, rz = kz - 3 * qz;
-  const int64_t vc = qx + (int64_t)qy * Lc.pitch + (int64_t)qz * Lc.plane;
-  T acc = (T)0;
-#pragma unroll
-  for (int kap = 0; kap < Dim<D>::NC; ++kap) {
-    const int kx = kap & 1, ky = (kap >> 1) & 1, kk = (kap >> 2) & 1;
-    if ((kx && rx == 0) || (ky && ry == 0) || (kk && rz == 0)) continue;
-    const double w = pweight<D, SRC, FMT>(P, Lf, vf, rx, ry, rz, kap);
-    acc += (T)w * ec[vc + slot_off(Lc, kx, ky, kk)];
-  }
-  uf[vf] += acc;
+  uf[vf] += prolong_at<D, T, SRC, FMT>(Lf, Lc, ec, P, i, j, kz, vf);
 }
 
 template <int D>
@@ -232,29 +179,39 @@ __global__ void k_zero(T* __restrict__ p, int64_t n) {
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+template <int D, typename T, typename TO, int SRC, int FMT, int MODE>
+void launch_one(const dim3& g, const dim3& bl, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const Lat& L,
+                const T* u, const T* b, TO* out, const T* eps, const Store& A, T omega, double* partial) {
+  if (e0 != nullptr)  // per-dispatch timestamps (the same the profiler reports)
+    hipExtLaunchKernelGGL((k_stencil<D, T, TO, SRC, FMT, MODE>), g, bl, 0, s, e0, e1, 0, L, u, b, out, eps, A,
+                          omega, partial);
+  else
+    hipLaunchKernelGGL((k_stencil<D, T, TO, SRC, FMT, MODE>), g, bl, 0, s, L, u, b, out, eps, A, omega, partial);
+}
+
 template <int D, typename T, typename TO, int SRC, int FMT>
 void dispatch_mode(const Lat& L, int mode, const T* u, const T* b, TO* out, const T* eps,
-                   const Store& A, T omega, double* partial, hipStream_t s) {
+                   const Store& A, T omega, double* partial, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const dim3 g = tile_grid(L), bl(TX, TY, 1);
   switch (mode) {
-    case 0: hipLaunchKernelGGL((k_stencil<D, T, TO, SRC, FMT, 0>), g, bl, 0, s, L, u, b, out, eps, A, omega, partial); break;
-    case 1: hipLaunchKernelGGL((k_stencil<D, T, TO, SRC, FMT, 1>), g, bl, 0, s, L, u, b, out, eps, A, omega, partial); break;
-    case 2: hipLaunchKernelGGL((k_stencil<D, T, TO, SRC, FMT, 2>), g, bl, 0, s, L, u, b, out, eps, A, omega, partial); break;
-    default: hipLaunchKernelGGL((k_stencil<D, T, TO, SRC, FMT, 3>), g, bl, 0, s, L, u, b, out, eps, A, omega, partial); break;
+    case 0: launch_one<D, T, TO, SRC, FMT, 0>(g, bl, s, e0, e1, L, u, b, out, eps, A, omega, partial); break;
+    case 1: launch_one<D, T, TO, SRC, FMT, 1>(g, bl, s, e0, e1, L, u, b, out, eps, A, omega, partial); break;
+    case 2: launch_one<D, T, TO, SRC, FMT, 2>(g, bl, s, e0, e1, L, u, b, out, eps, A, omega, partial); break;
+    default: launch_one<D, T, TO, SRC, FMT, 3>(g, bl, s, e0, e1, L, u, b, out, eps, A, omega, partial); break;
   }
   QMG_HIP(hipGetLastError());
 }
 
 template <int D, typename T, typename TO>
 void dispatch_src(const Lat& L, int mode, const T* u, const T* b, TO* out, const T* eps,
-                  const Store& A, T omega, double* partial, hipStream_t s) {
-  if (A.src == SRC_GEOM) return dispatch_mode<D, T, TO, SRC_GEOM, F64>(L, mode, u, b, out, eps, A, omega, partial, s);
-  if (A.src == SRC_PLAIN) return dispatch_mode<D, T, TO, SRC_PLAIN, F64>(L, mode, u, b, out, eps, A, omega, partial, s);
+                  const Store& A, T omega, double* partial, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (A.src == SRC_GEOM) return dispatch_mode<D, T, TO, SRC_GEOM, F64>(L, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
+  if (A.src == SRC_PLAIN) return dispatch_mode<D, T, TO, SRC_PLAIN, F64>(L, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
   switch (A.fmt) {
-    case F64: return dispatch_mode<D, T, TO, SRC_HIER, F64>(L, mode, u, b, out, eps, A, omega, partial, s);
-    case F32: return dispatch_mode<D, T, TO, SRC_HIER, F32>(L, mode, u, b, out, eps, A, omega, partial, s);
-    case F16: return dispatch_mode<D, T, TO, SRC_HIER, F16>(L, mode, u, b, out, eps, A, omega, partial, s);
-    default: return dispatch_mode<D, T, TO, SRC_HIER, BF16>(L, mode, u, b, out, eps, A, omega, partial, s);
+    case F64: return dispatch_mode<D, T, TO, SRC_HIER, F64>(L, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
+    case F32: return dispatch_mode<D, T, TO, SRC_HIER, F32>(L, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
+    case F16: return dispatch_mode<D, T, TO, SRC_HIER, F16>(L, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
+    default: return dispatch_mode<D, T, TO, SRC_HIER, BF16>(L, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
   }
 }
 
@@ -283,20 +240,23 @@ void dispatch_transfer(const Lat& Lf, const Lat& Lc, const T* in, T* out, const 
 
 template <typename T>
 void launch_stencil(const Lat& L, int mode, const T* u, const T* b, T* out, const T* eps,
-                    const Store& A, T omega, double* partial, int* n_partial, hipStream_t s) {
+                    const Store& A, T omega, double* partial, int* n_partial, hipStream_t s,
+                    hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (n_partial) {
     const dim3 g = tile_grid(L);
     *n_partial = (int)(g.x * g.y * g.z);
   }
   if (L.d == 2)
-    dispatch_src<2, T, T>(L, mode, u, b, out, eps, A, omega, partial, s);
+    dispatch_src<2, T, T>(L, mode, u, b, out, eps, A, omega, partial, s, ev_start, ev_stop);
   else
-    dispatch_src<3, T, T>(L, mode, u, b, out, eps, A, omega, partial, s);
+    dispatch_src<3, T, T>(L, mode, u, b, out, eps, A, omega, partial, s, ev_start, ev_stop);
 }
 template void launch_stencil<double>(const Lat&, int, const double*, const double*, double*,
-                                     const double*, const Store&, double, double*, int*, hipStream_t);
+                                     const double*, const Store&, double, double*, int*, hipStream_t,
+                                     hipEvent_t, hipEvent_t);
 template void launch_stencil<float>(const Lat&, int, const float*, const float*, float*,
-                                    const float*, const Store&, float, double*, int*, hipStream_t);
+                                    const float*, const Store&, float, double*, int*, hipStream_t,
+                                    hipEvent_t, hipEvent_t);
 
 void launch_residual_mixed(const Lat& L, const double* x, const double* b, float* r32,
                            const double* eps, double* partial, int* n_partial, hipStream_t s) {
@@ -310,8 +270,9 @@ void launch_residual_mixed(const Lat& L, const double* x, const double* b, float
   QMG_HIP(hipGetLastError());
 }
 
-void launch_sum_partials(const double* partial, int n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, partial, n, out);
+void launch_sum_partials(const double* partial, int n, double* out, hipStream_t s, double* hist,
+                         int* counter, int cap) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, partial, n, out, hist, counter, cap);
   QMG_HIP(hipGetLastError());
 }
 

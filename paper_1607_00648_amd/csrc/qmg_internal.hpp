@@ -92,17 +92,22 @@ struct Store {
 // 2 = residual out = b - A u, 3 = matvec out = A u.  When `partial` is non-null
 // (modes 2 and 3) each workgroup adds its sum of squares of `out` there.
 // T is double or float; eps has the iterate type.
+// With ev_start/ev_stop the launch carries per-dispatch start/end timestamps.
 template <typename T>
 void launch_stencil(const Lat& L, int mode, const T* u, const T* b, T* out, const T* eps,
-                    const Store& A, T omega, double* partial, int* n_partial, hipStream_t s);
+                    const Store& A, T omega, double* partial, int* n_partial, hipStream_t s,
+                    hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // Finest-level FP64 residual for the mixed loop: r32 = fp32(b - A x), partial
 // sums of squares of the FP64 residual.
 void launch_residual_mixed(const Lat& L, const double* x, const double* b, float* r32,
                            const double* eps, double* partial, int* n_partial, hipStream_t s);
 
-// Sum of `n` partials into out[0] in a fixed order (one workgroup).
-void launch_sum_partials(const double* partial, int n, double* out, hipStream_t s);
+// Sum of `n` partials into out[0] in a fixed order (one workgroup).  With
+// `hist`, the sum is also stored at hist[*counter] (when below cap) and the
+// device counter advanced, so that replayed cycles keep a norm history.
+void launch_sum_partials(const double* partial, int n, double* out, hipStream_t s,
+                         double* hist = nullptr, int* counter = nullptr, int cap = 0);
 
 // Restriction bc = P^T r (gather per coarse vertex).  Lf: fine lattice.
 template <typename T>
@@ -162,8 +167,53 @@ void launch_delta_write(const Lat& L, const Lat& Lc, bool is_P, int fmt, const d
                         const double* eps, const int32_t* blk, void* payload, int8_t* scale,
                         hipStream_t s);
 
+// Coarse part of the V-cycle in one workgroup with levels lc..lf held in LDS
+// (lf starting from zero after its right-hand side was restricted into b of
+// index lf - lc).  Index s of every array is level lc + s.
+constexpr int kMaxFused = 8;
+template <typename T>
+struct FusedArgs {
+  int lc, lf, mu_pre, mu_post, coarse_direct, nc;
+  T omega;
+  const double* Ainv;
+  Lat L[kMaxFused];
+  Store A[kMaxFused], P[kMaxFused];
+  const T* eps[kMaxFused];
+  T* u[kMaxFused];
+  T* b[kMaxFused];
+  // LDS layout (byte offsets): 4 iterate arrays (u, t, b, r) over the compact
+  // (n+1)^d lattice, stencil rows of the interior, parent weights (when pw_lds)
+  int lds_vec[kMaxFused], lds_rows[kMaxFused], lds_pw[kMaxFused], lds_nslot[kMaxFused];
+  int lds_bytes, pw_lds;
+};
+// Fills the LDS layout of `a` (levels lc..lf already set) and returns its bytes.
+template <typename T>
+size_t fused_lds_layout(int d, FusedArgs<T>& a, bool p_stored, bool pw_lds);
+template <typename T>
+void launch_fused_coarse(int d, const FusedArgs<T>& a, int asrc, int psrc, int fmt, hipStream_t s);
+
 // Fill lattice array with zeros (kernel, not memset, so it can live in graphs).
 template <typename T>
 void launch_zero(T* p, int64_t n, hipStream_t s);
+
+// ---- solve loop as a state machine (api.cpp); used by the server ----
+struct SolveState {
+  double tol = 1e-8;
+  int max_cycles = 0;
+  int cycles = 0, outer = 0, batch = 2;
+  double rr = 0.0, rr_prev = 0.0;
+  std::vector<double> history;
+  bool done = false;
+  double t0 = 0.0;
+};
+// Residual of the current iterate (blocking); st.done if nothing to do.
+void solve_begin(qmg_grid_t* g, SolveState& st, double tol, int max_cycles);
+// Enqueues the next batch of cycles (non-blocking).
+void solve_enqueue(qmg_grid_t* g, SolveState& st);
+// True when the batch in flight has finished on the device.
+bool solve_ready(qmg_grid_t* g);
+// Reads the finished batch's norms and updates the state (sets st.done).
+void solve_collect(qmg_grid_t* g, SolveState& st);
+void solve_fill_report(qmg_grid_t* g, const SolveState& st, qmg_solve_report* rep);
 
 }  // namespace qmg

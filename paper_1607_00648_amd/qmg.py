@@ -49,6 +49,15 @@ class SolveReport(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("active", C.c_int64), ("queued", C.c_int64), ("hbm_budget", C.c_size_t),
+                ("hbm_in_use", C.c_size_t), ("hbm_peak", C.c_size_t), ("max_slots", C.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 # every entry point of include/qmg.h with its ctypes signature
 _SIGS = {
     "qmg_version": (C.c_char_p, []),
@@ -71,6 +80,15 @@ _SIGS = {
     "qmg_get_operator": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "qmg_get_prolongation": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "qmg_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "qmg_server_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
+    "qmg_server_submit": (C.c_int, [C.c_void_p, C.POINTER(GridDesc), C.POINTER(SolverOpts), C.c_void_p,
+                                    C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_uint64)]),
+    "qmg_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int), C.c_void_p,
+                                  C.POINTER(SolveReport), C.POINTER(C.c_double)]),
+    "qmg_server_drain": (C.c_int, [C.c_void_p]),
+    "qmg_server_stats": (C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    "qmg_server_last_error": (C.c_char_p, [C.c_void_p]),
+    "qmg_server_destroy": (C.c_int, [C.c_void_p]),
 }
 
 _lib = None
@@ -231,6 +249,89 @@ class Grid:
             self.close()
         except Exception:
             pass
+
+
+class Server:
+    """Persistent solve server on the current HIP device (see qmg_server_* in
+    include/qmg.h).  Requests carry their own grid size, coefficients, options
+    and tolerance; results come back through poll()."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 8):
+        import torch
+        torch.cuda.init()
+        self.lib = load()
+        h = C.c_void_p()
+        rc = self.lib.qmg_server_create(C.c_size_t(int(hbm_budget)), int(max_slots), C.byref(h))
+        if rc != QMG_OK:
+            raise QmgError(rc, self.lib.qmg_server_last_error(None).decode())
+        self.h = h
+        self._n = {}
+
+    def _err(self, rc):
+        raise QmgError(rc, self.lib.qmg_server_last_error(self.h).decode())
+
+    def submit(self, dim: int, level: int, eps, f, opts: SolverOpts, tol: float = 1e-8,
+               max_cycles: int = 1000) -> int:
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        n = 3 ** level
+        if eps.size != n ** dim or f.size != (n - 1) ** dim:
+            raise ValueError("eps must hold n^d values and f (n-1)^d values")
+        desc = GridDesc(int(dim), int(level))
+        t = C.c_uint64(0)
+        rc = self.lib.qmg_server_submit(self.h, C.byref(desc), C.byref(opts), _ptr(eps), _ptr(f),
+                                        float(tol), int(max_cycles), C.byref(t))
+        if rc != QMG_OK:
+            self._err(rc)
+        self._n[t.value] = f.size
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """(done, status name, solution or None, report dict, latency seconds)."""
+        done = C.c_int(0)
+        u = np.zeros(self._n[ticket])
+        rep = SolveReport()
+        lat = C.c_double(0.0)
+        rc = self.lib.qmg_server_poll(self.h, C.c_uint64(ticket), C.byref(done), _ptr(u), C.byref(rep),
+                                      C.byref(lat))
+        if not done.value:
+            if rc != QMG_OK:
+                self._err(rc)
+            return False, None, None, None, None
+        del self._n[ticket]
+        return True, STATUS_NAMES.get(rc, str(rc)), u, rep.as_dict(), float(lat.value)
+
+    def drain(self):
+        rc = self.lib.qmg_server_drain(self.h)
+        if rc != QMG_OK:
+            self._err(rc)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        rc = self.lib.qmg_server_stats(self.h, C.byref(st))
+        if rc != QMG_OK:
+            self._err(rc)
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.qmg_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_bytes(dim: int, level: int, opts: SolverOpts) -> int:
+    lib = load()
+    nb = C.c_size_t(0)
+    rc = lib.qmg_workspace_bytes(C.byref(GridDesc(int(dim), int(level))), C.byref(opts), C.byref(nb))
+    if rc != QMG_OK:
+        raise QmgError(rc, lib.qmg_last_error(None).decode())
+    return int(nb.value)
 
 
 def version() -> str:

@@ -1,0 +1,425 @@
+"""Adaptive spacetrees: composite system and FAS V-cycle (oracle, FP64).
+
+Paper passages followed (Sect. 2):
+
+* A cell is refined independently of its neighbours; level l holds the cells
+  of depth l, so each level is a ragged Cartesian grid.
+* A vertex of level l is hanging if fewer than 2^d level-l cells touch it,
+  refined if all its level-l cells are refined (a non-hanging copy then exists
+  on level l+1), unrefined otherwise.
+* A refined vertex holds the value of the vertex at the same position on the
+  finer level (injection I); a hanging vertex holds the d-linear interpolant of
+  the coarser level; every level uses the same discretisation.
+* FAS/HTMG: the coarse equation of a refined vertex has the right-hand side
+  R (b - A u) + A_{l-1} I u; unrefined vertices keep the PDE right-hand side.
+
+Readings (the paper is silent or its Alg. 1 is garbled here; see the design
+notes):
+
+* Levels 0..base are complete; refinement flags are given for levels
+  base..L-1 (a flag on a cell that does not exist is ignored).
+* The unknowns are the unrefined non-hanging interior vertices of levels
+  base..L ("leaves"), numbered level by level, x fastest within a level.  Leaf
+  cells (cells that exist and are not refined) carry the coefficients; a
+  refined cell's coefficient is the mean of its 3^d children.
+* Leaf v of level l satisfies sum_w a_l(v,w) u_bar(w) = h_l^d f_v, with a_l the
+  level-l rediscretised stencil and u_bar the composite value: the unknown for
+  a leaf, the finer copy for a refined vertex, the d-linear interpolant of the
+  coarser level for a hanging vertex, zero on the boundary.
+* The cycle on adaptive levels is the textbook FAS V-cycle (smooth all
+  non-hanging vertices of the level with hanging values frozen, inject, FAS
+  right-hand side on refined coarse vertices, recurse, correct with
+  P (u_{l-1} - I u_l), re-interpolate hanging vertices); at the complete base
+  level it continues as the regular correction-scheme cycle.  The paper's code
+  additionally smooths coarser unrefined regions while finer levels are
+  active; that changes iterates, not the fixed point.  Iterate parity is
+  therefore pinned only against this reading; the fixed point is pinned by the
+  composite system.
+* Coarse stencils of refined vertices are Galerkin products with the d-linear
+  P (the hanging interpolation uses the same weights), or rediscretised for the
+  geometric variant.
+"""
+from __future__ import annotations
+
+import itertools
+from typing import Dict
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .fem import (geometric_stencil, offsets, shifted, csr_to_stencil, stencil_to_csr,
+                  interior_mask)
+from .transfer import dlinear_P
+from .galerkin import rap
+from . import solver as S
+
+OUT, LEAF, REFINED, HANGING = 0, 1, 2, 3
+
+
+def _children(a, d):
+    """Each cell value repeated on its 3^d children (lattice cell arrays)."""
+    out = a
+    for ax in range(d):
+        out = np.repeat(out, 3, axis=ax)
+    return out
+
+
+class AdaptiveGrid:
+    """Levels 0..L of a tripartitioned spacetree with refinement flags for
+    levels base..L-1 (``flags[l]``: bool array (3^l,)*d over cells, NumPy axes
+    z, y, x)."""
+
+    def __init__(self, d, base, L, flags: Dict[int, np.ndarray]):
+        self.d, self.base, self.L = d, base, L
+        self.exist, self.refined, self.vtype = {}, {}, {}
+        for l in range(0, L + 1):
+            n = 3 ** l
+            if l <= base:
+                self.exist[l] = np.ones((n,) * d, dtype=bool)
+            else:
+                self.exist[l] = _children(self.refined[l - 1], d)
+            if l < base:
+                self.refined[l] = np.ones((n,) * d, dtype=bool)
+            elif l < L:
+                self.refined[l] = self.exist[l] & np.asarray(flags.get(l, np.zeros((n,) * d, bool)), bool)
+            else:
+                self.refined[l] = np.zeros((n,) * d, dtype=bool)
+            self.vtype[l] = self._classify(l)
+
+    def _classify(self, l):
+        d = self.d
+        n = 3 ** l
+        cnt = np.zeros((n + 1,) * d, dtype=np.int64)
+        nref = np.zeros((n + 1,) * d, dtype=np.int64)
+        ex = np.pad(self.exist[l].astype(np.int64), 1)
+        rf = np.pad(self.refined[l].astype(np.int64), 1)
+        for s in itertools.product((0, 1), repeat=d):
+            sl = tuple(slice(1 - si, 1 - si + n + 1) for si in s)   # cell (v - s), axes z,y,x
+            cnt += ex[sl]
+            nref += rf[sl]
+        t = np.full((n + 1,) * d, OUT, dtype=np.int8)
+        inner = interior_mask(d, l) > 0
+        full = cnt == 2 ** d
+        t[inner & full & (nref == 2 ** d)] = REFINED
+        t[inner & full & (nref < 2 ** d)] = LEAF
+        t[inner & (cnt > 0) & ~full] = HANGING
+        return t
+
+    # -- numbering -------------------------------------------------------------
+    def leaves(self):
+        """(level, lattice index tuple in NumPy order) of every unknown."""
+        out = []
+        for l in range(self.base, self.L + 1):
+            idx = np.argwhere(self.vtype[l] == LEAF)
+            out += [(l, tuple(i)) for i in idx]
+        return out
+
+    def leaf_cells(self):
+        out = []
+        for l in range(self.base, self.L + 1):
+            idx = np.argwhere(self.exist[l] & ~self.refined[l])
+            out += [(l, tuple(i)) for i in idx]
+        return out
+
+    def n_unknowns(self):
+        return sum(int((self.vtype[l] == LEAF).sum()) for l in range(self.base, self.L + 1))
+
+    def level_eps(self, eps_leaf):
+        """Cell coefficients of every level from the leaf-cell values (in
+        ``leaf_cells`` order): leaf cells keep theirs, refined cells take the
+        mean of their children, non-existing cells 0."""
+        d = self.d
+        eps = {l: np.zeros((3 ** l,) * d) for l in range(self.L + 1)}
+        for k, (l, c) in enumerate(self.leaf_cells()):
+            eps[l][c] = eps_leaf[k]
+        for l in range(self.L - 1, -1, -1):
+            n = 3 ** l
+            ch = eps[l + 1].reshape(sum(((n, 3) for _ in range(d)), ()))
+            mean = ch.mean(axis=tuple(2 * i + 1 for i in range(d)))
+            eps[l] = np.where(self.refined[l], mean, eps[l])
+        return eps
+
+    def cell_centres(self):
+        out = []
+        for l, c in self.leaf_cells():
+            h = 3.0 ** -l
+            out.append([(ci + 0.5) * h for ci in reversed(c)])   # x first
+        return np.array(out)
+
+    def unknown_coords(self):
+        out = []
+        for l, v in self.leaves():
+            h = 3.0 ** -l
+            out.append([vi * h for vi in reversed(v)])
+        return np.array(out)
+
+
+# ---------------------------------------------------------------------------
+# Composite system (the plain definition of the result)
+# ---------------------------------------------------------------------------
+
+def composite_system(G: AdaptiveGrid, eps_leaf, f_leaf):
+    """Sparse composite matrix over the leaf unknowns and its right-hand side."""
+    d = G.d
+    num = {lv: k for k, lv in enumerate(G.leaves())}
+    N = len(num)
+    eps = G.level_eps(eps_leaf)
+    memo = {}
+
+    def value(l, v):
+        """u_bar at (level l, lattice index v) as {unknown: weight}."""
+        key = (l, v)
+        if key in memo:
+            return memo[key]
+        t = G.vtype[l][v]
+        if t == LEAF:
+            res = {num[key]: 1.0}
+        elif t == REFINED:
+            res = value(l + 1, tuple(3 * vi for vi in v))
+        elif t == HANGING:
+            res = {}
+            q = [vi // 3 for vi in v]
+            r = [vi - 3 * qi for vi, qi in zip(v, q)]
+            for kap in itertools.product((0, 1), repeat=d):
+                w = 1.0
+                for ri, ki in zip(r, kap):
+                    w *= (1.0 - ri / 3.0) if ki == 0 else (ri / 3.0)
+                if w == 0.0:
+                    continue
+                par = tuple(qi + ki for qi, ki in zip(q, kap))
+                for j, c in value(l - 1, par).items():
+                    res[j] = res.get(j, 0.0) + w * c
+        else:
+            res = {}
+        memo[key] = res
+        return res
+
+    rows, cols, vals = [], [], []
+    b = np.zeros(N)
+    stencils = {l: geometric_stencil(eps[l], d, l) for l in range(G.base, G.L + 1)}
+    offs = offsets(d)
+    for (l, v), k in num.items():
+        S_l = stencils[l]
+        for e, o in enumerate(offs):
+            a = S_l[(e,) + v]
+            if a == 0.0:
+                continue
+            w = tuple(vi + oi for vi, oi in zip(v, reversed(o)))   # v is (z,y,x)
+            for j, c in value(l, w).items():
+                rows.append(k)
+                cols.append(j)
+                vals.append(a * c)
+        b[k] = (3.0 ** -l) ** d * f_leaf[k]
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+    A.sum_duplicates()
+    return A, b
+
+
+# ---------------------------------------------------------------------------
+# FAS V-cycle on the adaptive levels
+# ---------------------------------------------------------------------------
+
+class AdaptiveHierarchy:
+    pass
+
+
+def build_adaptive(G: AdaptiveGrid, eps_leaf, transfer="galerkin", omega=0.6, mu_pre=2, mu_post=2,
+                   lc=1):
+    """Stencils of every level: rediscretised rows for unrefined vertices,
+    Galerkin (d-linear P) or rediscretised rows for refined ones; the levels
+    up to the base level form a regular hierarchy below."""
+    if transfer not in ("geometric", "galerkin"):
+        raise ValueError("adaptive levels support the geometric and d-linear Galerkin transfers")
+    d = G.d
+    eps = G.level_eps(eps_leaf)
+    H = AdaptiveHierarchy()
+    H.G, H.d, H.base, H.L = G, d, G.base, G.L
+    H.omega, H.mu_pre, H.mu_post = omega, mu_pre, mu_post
+    H.eps = eps
+    H.S = {}
+    H.S[G.L] = geometric_stencil(eps[G.L], d, G.L)
+    for l in range(G.L - 1, lc - 1, -1):
+        geo = geometric_stencil(eps[l], d, l)
+        if transfer == "galerkin":
+            Af = stencil_to_csr(H.S[l + 1], d, l + 1)
+            gal = csr_to_stencil(rap(Af, dlinear_P(d, l + 1)), d, l)
+            ref = (G.vtype[l] == REFINED)
+            H.S[l] = np.where(ref[None], gal, geo)
+        else:
+            H.S[l] = geo
+        # rows only for non-hanging vertices
+        H.S[l] = H.S[l] * np.isin(G.vtype[l], (LEAF, REFINED))[None]
+    H.S[G.L] = H.S[G.L] * np.isin(G.vtype[G.L], (LEAF, REFINED))[None]
+    # regular hierarchy from the base level down (correction scheme)
+    A = {l: stencil_to_csr(H.S[l], d, l) for l in range(lc, G.base + 1)}
+    P = {l: dlinear_P(d, l) for l in range(lc + 1, G.base + 1)}
+    Hr = S.Hierarchy(d, G.base, lc, transfer, A, P, {l: eps[l] for l in range(lc, G.base + 1)},
+                     omega, mu_pre, mu_post)
+    import scipy.linalg as sla
+    if A[lc].shape[0] <= S.COARSE_DIRECT_MAX:
+        Hr.coarse_lu = sla.lu_factor(A[lc].toarray())
+    H.regular = Hr
+    return H
+
+
+def _apply(Sl, u, d):
+    """(A u) on a lattice array from a stencil array."""
+    out = np.zeros_like(u)
+    for e, o in enumerate(offsets(d)):
+        out += Sl[e] * shifted(u, o)
+    return out
+
+
+def _dlin_weights(d, l):
+    """Per fine lattice vertex of level l, the d-linear weights of its parents
+    floor(v/3) + kappa, as a list over kappa of (kappa, weight array)."""
+    n = 3 ** l
+    grids = np.meshgrid(*([np.arange(n + 1)] * d), indexing="ij")   # axes z,y,x
+    out = []
+    for kap in itertools.product((0, 1), repeat=d):                # kap in NumPy order
+        w = np.ones((n + 1,) * d)
+        for ax in range(d):
+            r = grids[ax] % 3
+            w = w * (np.where(kap[ax] == 0, 1.0 - r / 3.0, r / 3.0))
+        out.append((kap, w))
+    return out
+
+
+def _from_coarse(uc, d, l):
+    """d-linear interpolation of the level l-1 lattice array to level l."""
+    n = 3 ** l
+    grids = np.meshgrid(*([np.arange(n + 1)] * d), indexing="ij")
+    res = np.zeros((n + 1,) * d)
+    ucp = np.pad(uc, [(0, 1)] * d)
+    for kap, w in _dlin_weights(d, l):
+        idx = tuple(g // 3 + k for g, k in zip(grids, kap))
+        res += w * ucp[idx]
+    return res
+
+
+def _restrict_dlin(r, d, l):
+    """P^T r from level l to level l-1 (d-linear, all coarse lattice points)."""
+    nc = 3 ** (l - 1)
+    out = np.zeros((nc + 1,) * d)
+    rp = np.pad(r, [(2, 2)] * d)
+    for o in itertools.product(range(-2, 3), repeat=d):
+        w = np.prod([1.0 - abs(oi) / 3.0 for oi in o])
+        sl = tuple(slice(2 + oi, 2 + oi + 3 * nc + 1, 3) for oi in o)
+        out += w * rp[sl]
+    return out
+
+
+def hang(H, u, l):
+    """Hanging vertices of level l take the interpolant of level l-1."""
+    G = H.G
+    hv = G.vtype[l] == HANGING
+    u[l] = np.where(hv, _from_coarse(u[l - 1], H.d, l), u[l])
+
+
+def inject(H, u, l):
+    """Refined vertices of level l-1 take the value of their copy on level l."""
+    G = H.G
+    ref = G.vtype[l - 1] == REFINED
+    sl = (slice(None, None, 3),) * H.d
+    u[l - 1] = np.where(ref, u[l][sl], u[l - 1])
+
+
+def _jacobi_masked(H, l, u, b):
+    d = H.d
+    act = np.isin(H.G.vtype[l], (LEAF, REFINED))
+    Sl = H.S[l]
+    c = (3 ** d) // 2
+    diag = np.where(act, Sl[c], 1.0)
+    new = u + H.omega * (b - _apply(Sl, u, d)) / diag
+    return np.where(act, new, u)
+
+
+def fas_cycle(H, l, u, b):
+    """One FAS V-cycle from level l (u, b: dicts of lattice arrays, changed in
+    place).  At the base level the regular correction-scheme cycle runs on the
+    base lattice."""
+    d = H.d
+    G = H.G
+    if l == H.base:
+        ub = u[l][(slice(1, 3 ** l),) * d].ravel()
+        bb = b[l][(slice(1, 3 ** l),) * d].ravel()
+        ub = S.vcycle(H.regular, l, ub, bb)
+        u[l][(slice(1, 3 ** l),) * d] = ub.reshape((3 ** l - 1,) * d)
+        return
+    act = np.isin(G.vtype[l], (LEAF, REFINED))
+    hang(H, u, l)
+    for _ in range(H.mu_pre):
+        u[l] = _jacobi_masked(H, l, u[l], b[l])
+    r = np.where(act, b[l] - _apply(H.S[l], u[l], d), 0.0)
+    inject(H, u, l)
+    saved = u[l - 1].copy()
+    ref = G.vtype[l - 1] == REFINED
+    b[l - 1] = np.where(ref, _restrict_dlin(r, d, l) + _apply(H.S[l - 1], u[l - 1], d), b[l - 1])
+    fas_cycle(H, l - 1, u, b)
+    corr = _from_coarse(u[l - 1] - saved, d, l)
+    u[l] = np.where(act, u[l] + corr, u[l])
+    hang(H, u, l)
+    for _ in range(H.mu_post):
+        u[l] = _jacobi_masked(H, l, u[l], b[l])
+
+
+def composite_state(H, u):
+    """Make refined and hanging values consistent with the leaves: inject from
+    the finest level down, then interpolate hanging vertices from the base up."""
+    for l in range(H.L, H.base, -1):
+        inject(H, u, l)
+    for l in range(H.base + 1, H.L + 1):
+        hang(H, u, l)
+
+
+def leaf_vector(H, u):
+    return np.concatenate([u[l][H.G.vtype[l] == LEAF] for l in range(H.base, H.L + 1)])
+
+
+def composite_residual(H, u, b):
+    """Residual of the composite equations at the leaves (after
+    ``composite_state``), level by level in unknown order."""
+    out = []
+    for l in range(H.base, H.L + 1):
+        lf = H.G.vtype[l] == LEAF
+        r = b[l] - _apply(H.S[l], u[l], H.d)
+        out.append(r[lf])
+    return np.concatenate(out)
+
+
+def initial_state(H, f_leaf):
+    """Zero iterate; PDE right-hand side h^d f at the leaves of every level."""
+    d = H.d
+    u = {l: np.zeros((3 ** l + 1,) * d) for l in range(1, H.L + 1)}
+    b = {l: np.zeros((3 ** l + 1,) * d) for l in range(1, H.L + 1)}
+    k = 0
+    for l in range(H.base, H.L + 1):
+        lf = H.G.vtype[l] == LEAF
+        m = int(lf.sum())
+        b[l][lf] = (3.0 ** -l) ** d * np.asarray(f_leaf[k:k + m])
+        k += m
+    return u, b
+
+
+def solve_adaptive(H, f_leaf, tol=1e-8, max_cycles=200, cycles=None):
+    """FAS V-cycles from zero; returns (leaf values, relres history)."""
+    u, b = initial_state(H, f_leaf)
+    b0 = {l: v.copy() for l, v in b.items()}
+    bl = np.concatenate([b0[l][H.G.vtype[l] == LEAF] for l in range(H.base, H.L + 1)])
+    nb = np.linalg.norm(bl)
+    hist = []
+    n = cycles if cycles is not None else max_cycles
+    for _ in range(n):
+        fas_cycle(H, H.L, u, b)
+        composite_state(H, u)
+        # leaf right-hand sides are the PDE ones (FAS only rewrites refined rows)
+        hist.append(float(np.linalg.norm(composite_residual(H, u, b0)) / nb))
+        if cycles is None and hist[-1] <= tol:
+            break
+    return leaf_vector(H, u), hist
+
+
+def solve_composite_direct(G, eps_leaf, f_leaf):
+    A, b = composite_system(G, eps_leaf, f_leaf)
+    return spla.spsolve(sp.csc_matrix(A), b), A, b

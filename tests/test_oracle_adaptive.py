@@ -1,0 +1,110 @@
+"""Pins of the adaptive oracle: the composite system against the regular
+system in the limiting cases, d-linear reproduction at hanging vertices,
+and FAS V-cycles against the directly solved composite system."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle import adaptive as AD
+
+
+def _problem(d, base, L, seed=0, r=0.2):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0, 1, size=(2, d))
+    G = AD.AdaptiveGrid(d, base, L, W.ball_flags(d, base, L, c, r))
+    eps = rng.uniform(0.5, 2.0, size=len(G.leaf_cells()))
+    f = rng.uniform(-1.0, 1.0, size=G.n_unknowns())
+    return G, eps, f
+
+
+def test_vertex_classes():
+    G, _, _ = _problem(2, 2, 4)
+    for l in range(G.base + 1, G.L + 1):
+        t = G.vtype[l]
+        assert (t == AD.HANGING).any() and (t == AD.LEAF).any()
+        # a refined vertex has a non-hanging copy on the next level
+        for v in np.argwhere(t == AD.REFINED):
+            assert G.vtype[l + 1][tuple(3 * v)] in (AD.LEAF, AD.REFINED)
+    assert not (G.vtype[G.L] == AD.REFINED).any()
+    assert not (G.vtype[G.base] == AD.HANGING).any()
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_no_refinement_is_the_regular_system(d):
+    base = 2 if d == 2 else 1
+    n = 3 ** base
+    G = AD.AdaptiveGrid(d, base, base + 2, {})
+    rng = np.random.default_rng(1)
+    eps = rng.uniform(0.5, 2.0, size=n ** d)
+    f = rng.uniform(-1, 1, size=G.n_unknowns())
+    A, b = AD.composite_system(G, eps, f)
+    Ar = O.stencil_to_csr(O.geometric_stencil(eps.reshape((n,) * d), d, base), d, base)
+    assert abs(A - Ar).max() < 1e-14 * abs(Ar).max()
+    np.testing.assert_allclose(b, O.rhs_from_f(f, d, base))
+
+
+def test_full_refinement_is_the_regular_fine_system():
+    d, base, L = 2, 1, 3
+    flags = {l: np.ones((3 ** l,) * d, bool) for l in range(base, L)}
+    G = AD.AdaptiveGrid(d, base, L, flags)
+    n = 3 ** L
+    assert G.n_unknowns() == (n - 1) ** d
+    rng = np.random.default_rng(2)
+    eps = rng.uniform(0.5, 2.0, size=n ** d)
+    f = rng.uniform(-1, 1, size=G.n_unknowns())
+    A, b = AD.composite_system(G, eps, f)
+    Ar = O.stencil_to_csr(O.geometric_stencil(eps.reshape((n,) * d), d, L), d, L)
+    assert abs(A - Ar).max() < 1e-14 * abs(Ar).max()
+
+
+def test_hanging_values_reproduce_dlinear_functions():
+    """With leaves holding a d-linear function, injection and interpolation
+    give every vertex of every level that function's value."""
+    d = 2
+    # refinement away from the boundary, where Dirichlet zeros would enter
+    G = AD.AdaptiveGrid(d, 2, 4, W.ball_flags(d, 2, 4, np.array([[0.5, 0.5]]), 0.2))
+    eps = np.ones(len(G.leaf_cells()))
+    f = np.zeros(G.n_unknowns())
+    H = AD.build_adaptive(G, eps, transfer="geometric")
+    fun = lambda x, y: 0.3 + 1.5 * x - 0.7 * y + 2.0 * x * y
+    u, _ = AD.initial_state(H, f)
+    for l in range(G.base, G.L + 1):
+        n = 3 ** l
+        yy, xx = np.meshgrid(np.arange(n + 1) / n, np.arange(n + 1) / n, indexing="ij")
+        u[l] = np.where(G.vtype[l] == AD.LEAF, fun(xx, yy), 0.0)
+    AD.composite_state(H, u)
+    for l in range(G.base, G.L + 1):
+        n = 3 ** l
+        yy, xx = np.meshgrid(np.arange(n + 1) / n, np.arange(n + 1) / n, indexing="ij")
+        live = G.vtype[l] != AD.OUT
+        np.testing.assert_allclose(u[l][live], fun(xx, yy)[live], rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("d,base,L", [(2, 2, 4), (3, 1, 3)])
+@pytest.mark.parametrize("transfer", ["galerkin", "geometric"])
+def test_fas_cycles_converge_to_composite_solution(d, base, L, transfer):
+    G, eps, f = _problem(d, base, L)
+    ustar, A, b = AD.solve_composite_direct(G, eps, f)
+    H = AD.build_adaptive(G, eps, transfer=transfer)
+    u, hist = AD.solve_adaptive(H, f, tol=1e-12, max_cycles=100)
+    assert hist[-1] <= 1e-12
+    assert np.linalg.norm(u - ustar) <= 1e-10 * np.linalg.norm(ustar)
+    # the cycle's own residual equals the independently assembled one
+    assert abs(np.linalg.norm(b - A @ u) / np.linalg.norm(b) - hist[-1]) <= 1e-14
+    assert all(hist[i + 1] < hist[i] for i in range(len(hist) - 1))
+
+
+def test_adaptive_manufactured_solution_improves_with_refinement():
+    """sin source, exact solution prod sin(pi x_i): refining a region (the
+    whole domain in the limit) reduces the nodal error at the leaves."""
+    d = 2
+    errs = []
+    for L in (3, 4):
+        flags = {l: np.ones((3 ** l,) * d, bool) for l in range(2, L)}
+        G = AD.AdaptiveGrid(d, 2, L, flags)
+        X = G.unknown_coords()
+        f = d * np.pi ** 2 * np.prod(np.sin(np.pi * X), axis=1)
+        u, _, _ = AD.solve_composite_direct(G, np.ones(len(G.leaf_cells())), f)
+        errs.append(np.max(np.abs(u - np.prod(np.sin(np.pi * X), axis=1))))
+    assert 7.5 <= errs[0] / errs[1] <= 10.5

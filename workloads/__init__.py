@@ -131,6 +131,138 @@ def jump3d(level: int, seed: int = 0) -> Problem:
     return random_checkerboard(3, level, seed, name=f"jump3d-L{level}")
 
 
+# --------------------------------------------------------------------------
+# Adaptive spacetrees.  A problem is (base level, max level, refinement flags
+# per level) plus coefficient and source *fields* that each side evaluates at
+# its own leaf cells and unknowns, so that no side needs the other's numbering.
+# --------------------------------------------------------------------------
+
+def _cell_boxes(dim, level):
+    n = 3 ** level
+    idx = np.stack(np.meshgrid(*([np.arange(n)] * dim), indexing="ij"), -1)[..., ::-1]  # x first
+    lo = idx / n
+    return lo, lo + 1.0 / n
+
+
+def ball_flags(dim, base, level, centres, radius):
+    """Refine a cell when its closed box comes closer than ``radius`` to any
+    centre (levels base..level-1)."""
+    flags = {}
+    for l in range(base, level):
+        lo, hi = _cell_boxes(dim, l)
+        f = np.zeros((3 ** l,) * dim, dtype=bool)
+        for c in np.atleast_2d(centres):
+            gap = np.maximum(np.maximum(lo - c, 0.0), np.maximum(c - hi, 0.0))
+            f |= np.sqrt((gap ** 2).sum(-1)) < radius
+        flags[l] = f
+    return flags
+
+
+def rff_field(dim, seed, n_features, length):
+    """Random-Fourier-feature Gaussian field g(x) = sqrt(2/M) sum cos(k_m.x + p_m),
+    k_m ~ N(0, length^-2 I), p_m ~ U[0, 2pi): zero mean, unit variance,
+    covariance exp(-|r|^2 / (2 length^2))."""
+    rng = np.random.default_rng(seed)
+    k = rng.normal(0.0, 1.0 / length, size=(n_features, dim))
+    p = rng.uniform(0.0, 2.0 * np.pi, size=n_features)
+    scale = np.sqrt(2.0 / n_features)
+
+    def g(x):
+        x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+        out = np.empty(len(x))
+        for c0 in range(0, len(x), 1 << 16):
+            xs = x[c0:c0 + (1 << 16)]
+            out[c0:c0 + len(xs)] = scale * np.cos(xs @ k.T + p).sum(axis=1)
+        return out
+    return g
+
+
+def uniform_hash(seed, level, idx):
+    """Counter-based U[-1, 1) value per (seed, level, lattice index) from the
+    SplitMix64 finaliser (Steele, Lea, Flood 2014): the source value of an
+    unknown depends only on its level and position."""
+    idx = np.atleast_2d(np.asarray(idx, dtype=np.uint64))
+    z = np.uint64(seed) * np.uint64(0x9E3779B97F4A7C15) + np.uint64(level + 1)
+    with np.errstate(over="ignore"):
+        for c in range(idx.shape[1]):
+            z = (z ^ idx[:, c]) * np.uint64(0x9E3779B97F4A7C15) + np.uint64(c + 1)
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+            z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * (2.0 / 2.0 ** 53) - 1.0
+
+
+@dataclasses.dataclass
+class AdaptiveProblem:
+    name: str
+    dim: int
+    base: int
+    level: int
+    flags: dict                 # level -> bool array over the level's cells (NumPy axes z,y,x)
+    eps_at: object              # callable: cell centres (m, dim) x-first -> eps (m,)
+    f_seed: int                 # source of unknown (level l, vertex i,j,k) = uniform_hash(f_seed, l, (i,j,k))
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    def f_at(self, level, coords_xfirst):
+        """Source values at unknowns of one level given their coordinates."""
+        n = 3 ** level
+        idx = np.rint(np.asarray(coords_xfirst) * n).astype(np.int64)
+        return uniform_hash(self.f_seed, level, idx)
+
+
+def adaptive_balls(dim=3, base=3, level=5, n_balls=4, radius=0.2, seed=0, contrast_field=True,
+                   name="cfg3-adaptive-balls"):
+    """Refined to ``level`` within ``radius`` of ``n_balls`` seeded points,
+    ``base`` everywhere; eps = exp(g) with g a unit-variance RFF field of
+    correlation length 0.1 (M = 1024) at leaf-cell centres."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, 1.0, size=(n_balls, dim))
+    g = rff_field(dim, seed + 1000, 1024, 0.1) if contrast_field else (lambda x: np.zeros(len(x)))
+    return AdaptiveProblem(name, dim, base, level, ball_flags(dim, base, level, centres, radius),
+                           lambda x: np.exp(g(x)), seed + 2000,
+                           {"centres": centres, "radius": radius, "seed": seed})
+
+
+def adaptive_band(dim=3, base=3, level=6, seed=0, fraction=0.10, n_cubes=64, n_features=64,
+                  name="cfg5-adaptive-band"):
+    """Refined to ``level`` around the zero set of an RFF level set phi
+    (length 0.2): a cell is refined where |phi| < tau at one of its 3^d sample
+    points or phi changes sign there, tau being the ``fraction`` quantile of
+    |phi| on 10^6 seeded points.  eps = 1e6 inside ``n_cubes`` random cubes
+    (centres U[0,1]^3, sides U[0.05, 0.15]), 1 outside."""
+    rng = np.random.default_rng(seed)
+    phi = rff_field(dim, seed + 3000, n_features, 0.2)
+    tau = float(np.quantile(np.abs(phi(rng.uniform(0.0, 1.0, size=(10 ** 6, dim)))), fraction))
+    centres = rng.uniform(0.0, 1.0, size=(n_cubes, dim))
+    sides = rng.uniform(0.05, 0.15, size=n_cubes)
+    flags = {}
+    exist = None
+    for l in range(base, level):
+        n = 3 ** l
+        cells = np.argwhere(np.ones((n,) * dim, bool) if exist is None else exist)  # numpy order
+        f = np.zeros((n,) * dim, dtype=bool)
+        if len(cells):
+            lo = cells[:, ::-1] / n
+            pts = []
+            for o in np.ndindex(*([3] * dim)):
+                pts.append(lo + (np.array(o) * 0.5) / n)
+            vals = np.stack([phi(pp) for pp in pts], 1)
+            hit = (np.abs(vals).min(1) < tau) | (vals.min(1) < 0) & (vals.max(1) > 0)
+            f[tuple(cells.T)] = hit
+        flags[l] = f
+        exist = np.repeat(np.repeat(np.repeat(f, 3, 0), 3, 1), 3, 2) if dim == 3 else \
+            np.repeat(np.repeat(f, 3, 0), 3, 1)
+
+    def eps_at(x):
+        x = np.atleast_2d(x)
+        inside = np.zeros(len(x), dtype=bool)
+        for c, s in zip(centres, sides):
+            inside |= np.all(np.abs(x - c) <= s / 2, axis=1)
+        return np.where(inside, 1e6, 1.0)
+    return AdaptiveProblem(name, dim, base, level, flags, eps_at, seed + 4000,
+                           {"tau": tau, "seed": seed})
+
+
 @dataclasses.dataclass
 class Request:
     problem: Problem
@@ -160,4 +292,5 @@ def cfg4_stream(seed: int = 0, n_requests: int = 256, rate: float = 100.0,
 
 __all__ = ["Problem", "Request", "poisson", "random_checkerboard",
            "alternating_checkerboard", "sin_source", "cfg1", "cfg2", "jump3d",
-           "cfg4_stream"]
+           "cfg4_stream", "ball_flags", "rff_field", "uniform_hash", "AdaptiveProblem",
+           "adaptive_balls", "adaptive_band"]

@@ -31,10 +31,15 @@
  *    which the null stream cannot capture).  Calls return when their
  *    host-visible results are ready.  A grid is not thread-safe; distinct grids
  *    may be used concurrently from different threads on different streams.
- *  - Enumeration: unknowns are the interior vertices of the finest level,
- *    numbered lexicographically with x fastest: vertex (i,j[,k]) with
- *    1 <= i,j,k <= n-1 has index (i-1) + (n-1)*((j-1) + (n-1)*(k-1)).  Finest
- *    cells (coefficients) are numbered the same way over 0 <= i,j,k <= n-1.
+ *  - Enumeration: on a regular grid the unknowns are the interior vertices of
+ *    the finest level, numbered lexicographically with x fastest: vertex
+ *    (i,j[,k]) with 1 <= i,j,k <= n-1 has index
+ *    (i-1) + (n-1)*((j-1) + (n-1)*(k-1)); the cells (coefficients) are numbered
+ *    the same way over 0 <= i,j,k <= n-1.  On an adaptive spacetree (Sect. 2)
+ *    the unknowns are the leaf vertices (interior, non-hanging, not refined) of
+ *    levels base..L and the coefficients live on the leaf cells (existing,
+ *    not refined); both are numbered level by level, x fastest within a level
+ *    (qmg_unknown_coords / qmg_leaf_cell_centres give their positions).
  *  - Lattice arrays (inspection entry points) cover all vertices 0..n of a
  *    level, x fastest, (n+1)^d values; stencil arrays hold 3^d such arrays,
  *    entry k belonging to the offset o in {-1,0,1}^d with
@@ -88,8 +93,14 @@ enum {
 };
 
 typedef struct {
-  int dim;        /* 2 or 3                                                */
-  int max_level;  /* finest level L >= 2: 3^L cells per axis, regular grid */
+  int dim;        /* 2 or 3                                                   */
+  int max_level;  /* finest level L >= 2 (3^L cells per axis when refined)   */
+  int base_level; /* 0 (or L): regular grid of level L.  1 <= base < L:
+                     adaptive spacetree, every cell refined down to `base`,
+                     further refinement given by `refine`                      */
+  const uint8_t* refine; /* adaptive only, host: for levels base..L-1 in turn,
+                     one byte per cell of that level (x fastest; nonzero =
+                     refine); flags of cells that do not exist are ignored     */
 } qmg_grid_desc;
 
 typedef struct {
@@ -97,7 +108,7 @@ typedef struct {
   int store;           /* QMG_PLAIN_FP64 ... QMG_HIER_BF16                    */
   int mu_pre, mu_post; /* smoothing steps per level, each >= 1 (Alg. 1)       */
   double omega;        /* Jacobi damping in (0, 2)                           */
-  int coarsest_level;  /* requested coarsest level, 1 <= lc < L              */
+  int coarsest_level;  /* requested coarsest level, 1 <= lc < L (<= base)    */
   int check_definite;  /* 1: raise the coarsest level when a Galerkin row is
                           not positive / diagonally dominant (Sect. 3.3)      */
   int inner_cycles;    /* FP32 V-cycles per FP64 outer iteration (>= 1)     */
@@ -106,7 +117,8 @@ typedef struct {
 typedef struct {
   int cycles;               /* V-cycles run (inner cycles for FP32 iterates)  */
   int outer_iters;          /* FP64 residual evaluations                      */
-  double relres;            /* final ||b - A u||_2 / ||b||_2, FP64, finest    */
+  double relres;            /* final ||b - A u||_2 / ||b||_2 over the
+                               unknowns (composite system when adaptive), FP64 */
   int coarsest_level_used;  /* after the definiteness check                   */
   int64_t vertex_updates;   /* Jacobi vertex updates performed (all levels)   */
   size_t bytes_operators;   /* device bytes holding stored operators          */
@@ -123,21 +135,31 @@ int qmg_workspace_bytes(const qmg_grid_desc* desc, const qmg_solver_opts* opts, 
 /* Default options: BoxMG, HIER_FP64, V(2,2), omega 0.6, lc 1, check on, 1 inner cycle. */
 int qmg_default_opts(qmg_solver_opts* opts);
 
-/* Creates a grid (Sect. 2: the regular levels 0..L of a tripartitioned
- * spacetree, linearised level by level) in `device_buf` (or library memory when
- * NULL).  `stream` is a hipStream_t.  On success *out owns the grid. */
+/* Creates a grid (Sect. 2: the levels 0..L of a tripartitioned spacetree,
+ * each linearised as a Cartesian lattice of its level; on an adaptive
+ * spacetree a level keeps its lattice and launches only the 64 x 4 vertex
+ * tiles that touch existing cells) in `device_buf` (or library memory when
+ * NULL).  `stream` is a hipStream_t.  On success *out owns the grid.
+ * Adaptive spacetrees take QMG_GEOMETRIC or QMG_GALERKIN_DLINEAR and the FP64
+ * stores (QMG_EINVAL otherwise); their cycle is the FAS V-cycle on the levels
+ * above `base_level` and the correction-scheme cycle below. */
 int qmg_create_grid(const qmg_grid_desc* desc, const qmg_solver_opts* opts, void* device_buf,
                     size_t bytes, void* stream, qmg_grid_t** out);
 
-/* Number of unknowns, finest cells and levels (L+1). */
+/* Number of unknowns, leaf cells (coefficients) and levels (L+1). */
 int qmg_sizes(const qmg_grid_t* grid, int64_t* n_unknowns, int64_t* n_leaf_cells, int* n_levels);
 
-/* Coordinates of the unknowns, dim values per unknown (host array). */
-int qmg_unknown_coords(const qmg_grid_t* grid, double* xyz);
+/* Coordinates of the unknowns, dim values per unknown (host array); `level`
+ * (nullable) receives each unknown's level. */
+int qmg_unknown_coords(const qmg_grid_t* grid, double* xyz, int8_t* level);
 
-/* Sets the coefficient eps (one value per finest cell, > 0 and finite; ncomp
- * must be 1) and the source f (one value per unknown); the right-hand side is
- * b = h^d f (lumped).  Resets the solution to zero and invalidates operators. */
+/* Centres of the leaf cells, dim values per cell (host array). */
+int qmg_leaf_cell_centres(const qmg_grid_t* grid, double* xyz);
+
+/* Sets the coefficient eps (one value per leaf cell, > 0 and finite; ncomp
+ * must be 1) and the source f (one value per unknown); the right-hand side of
+ * an unknown on level l is b = h_l^d f (lumped).  Resets the solution to zero
+ * and invalidates operators. */
 int qmg_set_coefficients(qmg_grid_t* grid, const double* eps, int ncomp, const double* f, int mem);
 
 /* Builds all coarse operators (Sect. 3.3, 3.4): BoxMG P, Galerkin RAP with the
@@ -201,7 +223,10 @@ enum {
 
 /* Applies one step of the hot path on `level` in the grid's iterate precision
  * (FP64 or FP32, converted at the boundary).  x, b, out are lattice arrays of
- * the sizes the operation implies; b is ignored where unused (may be NULL). */
+ * the sizes the operation implies; b is ignored where unused (may be NULL).
+ * The step runs in the level's work buffers: the iterates and right-hand
+ * sides of `level` (and level-1 for transfers) are overwritten, so a solve
+ * after it starts with qmg_set_coefficients or qmg_set_solution. */
 int qmg_apply(qmg_grid_t* grid, int op, int level, const double* x, const double* b, double* out);
 
 /* ---------------- serving ------------------------------------------------
@@ -223,8 +248,9 @@ typedef struct {
 /* Starts a server on the current HIP device (1 <= max_slots <= 256). */
 int qmg_server_create(size_t hbm_budget, int max_slots, qmg_server_t** out);
 
-/* Queues a solve (eps: n^d cell values, f: (n-1)^d unknowns, host memory,
- * copied).  QMG_EINVAL if the request could never fit the budget.  The ticket
+/* Queues a solve on a regular grid (eps: n^d cell values, f: (n-1)^d
+ * unknowns, host memory, copied).  QMG_EINVAL for an adaptive description or
+ * if the request could never fit the budget.  The ticket
  * identifies it in qmg_server_poll. */
 int qmg_server_submit(qmg_server_t* server, const qmg_grid_desc* desc, const qmg_solver_opts* opts,
                       const double* eps, const double* f, double rel_tol, int max_cycles,

@@ -49,7 +49,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .fem import (geometric_stencil, offsets, shifted, csr_to_stencil, stencil_to_csr,
-                  interior_mask)
+                  interior_mask, corners, corner_index, element_matrix)
 from .transfer import dlinear_P
 from .galerkin import rap
 from . import solver as S
@@ -141,42 +141,46 @@ class AdaptiveGrid:
         return eps
 
     def cell_centres(self):
+        """Centres of the leaf cells in ``leaf_cells`` order, x first."""
         out = []
-        for l, c in self.leaf_cells():
-            h = 3.0 ** -l
-            out.append([(ci + 0.5) * h for ci in reversed(c)])   # x first
-        return np.array(out)
+        for l in range(self.base, self.L + 1):
+            idx = np.argwhere(self.exist[l] & ~self.refined[l])
+            out.append((idx[:, ::-1] + 0.5) * 3.0 ** -l)
+        return np.concatenate(out)
 
     def unknown_coords(self):
+        """Positions of the unknowns in ``leaves`` order, x first."""
         out = []
-        for l, v in self.leaves():
-            h = 3.0 ** -l
-            out.append([vi * h for vi in reversed(v)])
-        return np.array(out)
+        for l in range(self.base, self.L + 1):
+            idx = np.argwhere(self.vtype[l] == LEAF)
+            out.append(idx[:, ::-1] * 3.0 ** -l)
+        return np.concatenate(out)
 
 
 # ---------------------------------------------------------------------------
 # Composite system (the plain definition of the result)
 # ---------------------------------------------------------------------------
 
-def composite_system(G: AdaptiveGrid, eps_leaf, f_leaf):
-    """Sparse composite matrix over the leaf unknowns and its right-hand side."""
-    d = G.d
-    num = {lv: k for k, lv in enumerate(G.leaves())}
-    N = len(num)
-    eps = G.level_eps(eps_leaf)
-    memo = {}
+class _CompositeValues:
+    """u_bar(l, v) of the composite system as {unknown: weight}: the unknown
+    for a leaf, the finer copy for a refined vertex, the d-linear interpolant
+    of the coarser level for a hanging vertex, nothing on the boundary."""
 
-    def value(l, v):
-        """u_bar at (level l, lattice index v) as {unknown: weight}."""
+    def __init__(self, G: AdaptiveGrid):
+        self.G = G
+        self.num = {lv: k for k, lv in enumerate(G.leaves())}
+        self.memo = {}
+
+    def __call__(self, l, v):
+        G, d = self.G, self.G.d
         key = (l, v)
-        if key in memo:
-            return memo[key]
+        if key in self.memo:
+            return self.memo[key]
         t = G.vtype[l][v]
         if t == LEAF:
-            res = {num[key]: 1.0}
+            res = {self.num[key]: 1.0}
         elif t == REFINED:
-            res = value(l + 1, tuple(3 * vi for vi in v))
+            res = self(l + 1, tuple(3 * vi for vi in v))
         elif t == HANGING:
             res = {}
             q = [vi // 3 for vi in v]
@@ -188,13 +192,21 @@ def composite_system(G: AdaptiveGrid, eps_leaf, f_leaf):
                 if w == 0.0:
                     continue
                 par = tuple(qi + ki for qi, ki in zip(q, kap))
-                for j, c in value(l - 1, par).items():
+                for j, c in self(l - 1, par).items():
                     res[j] = res.get(j, 0.0) + w * c
         else:
             res = {}
-        memo[key] = res
+        self.memo[key] = res
         return res
 
+
+def composite_system(G: AdaptiveGrid, eps_leaf, f_leaf):
+    """Sparse composite matrix over the leaf unknowns and its right-hand side."""
+    d = G.d
+    value = _CompositeValues(G)
+    num = value.num
+    N = len(num)
+    eps = G.level_eps(eps_leaf)
     rows, cols, vals = [], [], []
     b = np.zeros(N)
     stencils = {l: geometric_stencil(eps[l], d, l) for l in range(G.base, G.L + 1)}
@@ -214,6 +226,33 @@ def composite_system(G: AdaptiveGrid, eps_leaf, f_leaf):
     A = sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
     A.sum_duplicates()
     return A, b
+
+
+def composite_residual_rows(G: AdaptiveGrid, eps_leaf, f_leaf, u_leaf, sample):
+    """b_k - (A u)_k of the composite system at the unknowns ``sample``, each
+    row assembled on its own: the element matrices (Sect. 2, Q1) of the 2^d
+    cells around the leaf, applied to the composite values of their corners.
+    Usable on grids far too large for ``composite_system``."""
+    d = G.d
+    value = _CompositeValues(G)
+    leaves = G.leaves()
+    eps = G.level_eps(eps_leaf)
+    cs = corners(d)
+    out = np.zeros(len(sample))
+    for q, k in enumerate(sample):
+        l, v = leaves[k]
+        h = 3.0 ** -l
+        acc = 0.0
+        for s in cs:                               # v is corner s of cell v - s
+            cell = tuple(vi - si for vi, si in zip(v, reversed(s)))
+            K = element_matrix(d, h, eps[l][cell])
+            ia = corner_index(s)
+            for ib, w in enumerate(cs):
+                corner = tuple(ci + wi for ci, wi in zip(cell, reversed(w)))
+                for j, c in value(l, corner).items():
+                    acc += K[ia, ib] * c * u_leaf[j]
+        out[q] = h ** d * f_leaf[k] - acc
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -57,6 +57,31 @@ struct LevelBuf {
   void* Ppay = nullptr;
   int8_t* Pscale = nullptr;
   int64_t Anz = -1, Pnz = -1;  // stored non-zero blocks (-1: no store)
+  // adaptive spacetrees, levels base..L: vertex classes, refined-cell flags,
+  // active tiles and the saved iterate of the FAS cycle
+  int8_t* vt = nullptr;
+  int8_t* cref = nullptr;
+  int32_t* tiles = nullptr;
+  int ntiles = 0;
+  void* sv = nullptr;
+  AdTiles ad() const {
+    AdTiles t;
+    t.L = L;
+    t.tiles = tiles;
+    t.vt = vt;
+    t.n = ntiles;
+    return t;
+  }
+};
+
+// Host-side linearisation of one level of an adaptive spacetree.
+struct HostLevel {
+  std::vector<int8_t> vt;         // vertex class per lattice slot
+  std::vector<int8_t> cref;       // refined flag per cell slot
+  std::vector<int32_t> tiles;     // active tiles (x tile, y tile, z plane)
+  std::vector<int64_t> leaf;      // slots of the unknowns (x fastest)
+  std::vector<int64_t> cells;     // slots of the leaf cells (x fastest)
+  int64_t n_active = 0;           // leaf + refined vertices
 };
 
 // Bump allocator over the workspace; with base == nullptr it only measures.
@@ -107,6 +132,13 @@ struct qmg_grid {
   size_t bytes_ops = 0;
   double zero_frac = 0.0;
   std::string err;
+  // adaptive spacetree (base < L); a regular grid has base == L
+  bool adaptive = false;
+  int lb = 0;  // base level (complete level of the spacetree)
+  std::vector<HostLevel> hl;
+  int64_t* unk_slots = nullptr;   // device copies of the leaf / leaf-cell slot lists
+  int64_t* cell_slots = nullptr;
+  int64_t n_cells = 0;
   // device norm history of replayed cycles, its pinned host copy and the
   // event marking the end of the batch in flight
   double* dhist = nullptr;
@@ -164,6 +196,95 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
   if (o->coarsest_level < 1 || o->coarsest_level > desc->max_level - 1)
     throw ApiError(QMG_EINVAL, "coarsest_level must satisfy 1 <= lc < max_level");
   if (o->inner_cycles < 1) throw ApiError(QMG_EINVAL, "inner_cycles must be >= 1");
+  const bool adaptive = desc->base_level != 0 && desc->base_level != desc->max_level;
+  if (adaptive) {
+    if (desc->base_level < 1 || desc->base_level > desc->max_level)
+      throw ApiError(QMG_EINVAL, "base_level must satisfy 1 <= base <= max_level");
+    if (!desc->refine) throw ApiError(QMG_EINVAL, "adaptive grid without refinement flags");
+    if (o->coarsest_level > desc->base_level)
+      throw ApiError(QMG_EINVAL, "coarsest_level must not exceed base_level");
+    if (o->transfer == QMG_BOXMG)
+      throw ApiError(QMG_EINVAL, "adaptive grids take the geometric or the d-linear Galerkin transfer");
+    if (o->store != QMG_HIER_FP64 && o->store != QMG_PLAIN_FP64)
+      throw ApiError(QMG_EINVAL, "adaptive grids take the FP64 stores");
+  }
+}
+
+// Spacetree of levels base..L (Sect. 2): cells of level base all exist; a
+// cell of a finer level exists when its parent is refined; a cell is refined
+// when it exists, its flag is set and it is not on level L.  Vertex classes:
+// hanging (fewer than 2^d existing cells), refined (all 2^d cells refined),
+// leaf (the other non-hanging interior vertices), outside/boundary.
+void linearise(qmg_grid_t* g) {
+  const int d = g->d, L = g->Lmax, base = g->lb;
+  g->hl.assign(L + 1, HostLevel{});
+  std::vector<uint8_t> ref_prev;
+  const uint8_t* fl = g->desc.refine;
+  int64_t nprev = 0;
+  for (int l = base; l <= L; ++l) {
+    const Lat Lt = make_lat(d, l);
+    const int64_t n = Lt.n;
+    const int64_t ncell = d == 3 ? n * n * n : n * n;
+    std::vector<uint8_t> exist((size_t)ncell), ref((size_t)ncell, 0);
+    for (int64_t c = 0; c < ncell; ++c) {
+      if (l == base) {
+        exist[c] = 1;
+      } else {
+        const int64_t cx = c % n, cy = (c / n) % n, cz = d == 3 ? c / (n * n) : 0;
+        const int64_t pc = cx / 3 + nprev * (cy / 3 + (d == 3 ? nprev * (cz / 3) : 0));
+        exist[c] = ref_prev[pc];
+      }
+      if (l < L) ref[c] = exist[c] && fl[c] != 0;
+    }
+    if (l < L) fl += ncell;
+    HostLevel& H = g->hl[l];
+    H.vt.assign((size_t)Lt.nslot, VT_OUT);
+    H.cref.assign((size_t)Lt.nslot, 0);
+    auto cell = [&](int64_t i, int64_t j, int64_t k) -> int64_t { return i + n * (j + n * k); };
+    for (int64_t k = 0; k < (d == 3 ? n : 1); ++k)
+      for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) {
+          const int64_t c = cell(i, j, k);
+          const int64_t sl = i + j * Lt.pitch + k * Lt.plane;
+          if (ref[c]) H.cref[(size_t)sl] = 1;
+          if (exist[c] && !ref[c]) H.cells.push_back(sl);
+        }
+    for (int64_t k = (d == 3 ? 1 : 0); k <= (d == 3 ? n - 1 : 0); ++k)
+      for (int64_t j = 1; j <= n - 1; ++j)
+        for (int64_t i = 1; i <= n - 1; ++i) {
+          int cnt = 0, nref = 0;
+          for (int s = 0; s < (1 << d); ++s) {
+            const int64_t c = cell(i - (s & 1), j - ((s >> 1) & 1), d == 3 ? k - ((s >> 2) & 1) : 0);
+            cnt += exist[c];
+            nref += ref[c];
+          }
+          const int64_t sl = i + j * Lt.pitch + k * Lt.plane;
+          int8_t t = VT_OUT;
+          if (cnt == (1 << d)) t = (nref == (1 << d)) ? VT_REFINED : VT_LEAF;
+          else if (cnt > 0) t = VT_HANGING;
+          H.vt[(size_t)sl] = t;
+          if (t == VT_LEAF) H.leaf.push_back(sl);
+          if (t == VT_LEAF || t == VT_REFINED) ++H.n_active;
+        }
+    // active tiles: every tile of the base level; on finer levels the tiles
+    // holding a vertex that is not outside
+    const int ntx = Lt.pitch / 64, nty = (int)((n + 1 + 3) / 4), ntz = d == 3 ? (int)n + 1 : 1;
+    for (int tz = 0; tz < ntz; ++tz)
+      for (int ty = 0; ty < nty; ++ty)
+        for (int tx = 0; tx < ntx; ++tx) {
+          bool any = l == base;
+          for (int jj = ty * 4; jj < std::min<int64_t>(ty * 4 + 4, n + 1) && !any; ++jj)
+            for (int ii = tx * 64; ii < std::min<int64_t>(tx * 64 + 64, n + 1) && !any; ++ii)
+              any = H.vt[(size_t)(ii + jj * Lt.pitch + tz * Lt.plane)] != VT_OUT;
+          if (any) {
+            H.tiles.push_back(tx);
+            H.tiles.push_back(ty);
+            H.tiles.push_back(tz);
+          }
+        }
+    ref_prev.swap(ref);
+    nprev = n;
+  }
 }
 
 int64_t n_interior(const Lat& L) {
@@ -184,6 +305,23 @@ void layout(qmg_grid_t* g, Arena& a) {
   const bool boxmg = g->opts.transfer == QMG_BOXMG;
   g->lv.assign(L + 1, LevelBuf{});
   for (int l = 0; l <= L; ++l) g->lv[l].L = make_lat(d, l);
+  int64_t n_unk = 0, n_cells = 0, ad_partials = 0;
+  if (g->adaptive) {
+    for (int l = g->lb; l <= L; ++l) {
+      LevelBuf& B = g->lv[l];
+      const HostLevel& H = g->hl[l];
+      B.ntiles = (int)(H.tiles.size() / 3);
+      B.vt = a.take<int8_t>(B.L.nslot);
+      if (l < L) B.cref = a.take<int8_t>(B.L.nslot);
+      B.tiles = a.take<int32_t>((int64_t)H.tiles.size());
+      if (l < L) B.sv = a.take<char>(B.L.nslot * (int64_t)it);
+      n_unk += (int64_t)H.leaf.size();
+      n_cells += (int64_t)H.cells.size();
+      ad_partials += B.ntiles;
+    }
+    g->unk_slots = a.take<int64_t>(n_unk);
+    g->cell_slots = a.take<int64_t>(n_cells);
+  }
   for (int l = lcq; l <= L; ++l) {
     LevelBuf& B = g->lv[l];
     const int64_t ns = B.L.nslot;
@@ -203,7 +341,7 @@ void layout(qmg_grid_t* g, Arena& a) {
         if (g->fmt == F16) B.Ascale = a.take<int8_t>(ns);
       }
     }
-    if (l > lcq) {
+    if (l > lcq && !(g->adaptive && l > g->lb && !g->plain)) {
       if (g->plain) {
         B.Pdense = a.take<double>(ns * NC);
       } else if (boxmg) {
@@ -219,12 +357,12 @@ void layout(qmg_grid_t* g, Arena& a) {
     g->tmpA[1] = a.take<double>(nsA * NS);
     if (boxmg) g->tmpP = a.take<double>(g->lv[L].L.nslot * NC);
   }
-  if (g->mixed) {
+  if (g->mixed && !g->adaptive) {
     g->x64 = a.take<double>(g->lv[L].L.nslot);
     g->bfin = a.take<double>(g->lv[L].L.nslot);
   }
   g->stage = a.take<double>(g->lv[L].L.nslot);
-  g->partial = a.take<double>(npartials(g->lv[L].L));
+  g->partial = a.take<double>(std::max<int64_t>(npartials(g->lv[L].L), ad_partials));
   g->dscal = a.take<double>(8);
   g->dcount = a.take<int>(8);
   g->dtotal = a.take<int32_t>(2 * (L + 1));
@@ -250,6 +388,36 @@ void init_modes(qmg_grid_t* g, const qmg_grid_desc* desc, const qmg_solver_opts*
   g->plain = o->store == QMG_PLAIN_FP64;
   g->mixed = o->store >= QMG_HIER_FP32;
   g->fmt = store_fmt(o->store);
+  g->adaptive = desc->base_level != 0 && desc->base_level != desc->max_level;
+  g->lb = g->adaptive ? desc->base_level : desc->max_level;
+  if (g->adaptive) linearise(g);
+}
+
+// uploads the host linearisation (after the device layout is assigned)
+void upload_linearisation(qmg_grid_t* g) {
+  if (!g->adaptive) return;
+  int64_t uo = 0, co = 0;
+  for (int l = g->lb; l <= g->Lmax; ++l) {
+    LevelBuf& B = g->lv[l];
+    HostLevel& H = g->hl[l];
+    QMG_HIP(hipMemcpy(B.vt, H.vt.data(), H.vt.size(), hipMemcpyHostToDevice));
+    if (B.cref) QMG_HIP(hipMemcpy(B.cref, H.cref.data(), H.cref.size(), hipMemcpyHostToDevice));
+    if (!H.tiles.empty())
+      QMG_HIP(hipMemcpy(B.tiles, H.tiles.data(), H.tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!H.leaf.empty())
+      QMG_HIP(hipMemcpy(g->unk_slots + uo, H.leaf.data(), H.leaf.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (!H.cells.empty())
+      QMG_HIP(hipMemcpy(g->cell_slots + co, H.cells.data(), H.cells.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    uo += (int64_t)H.leaf.size();
+    co += (int64_t)H.cells.size();
+    // the class arrays stay on the host for numbering; drop the bulky ones
+    H.vt.clear();
+    H.vt.shrink_to_fit();
+    H.cref.clear();
+    H.cref.shrink_to_fit();
+  }
+  g->n_unknowns = uo;
+  g->n_cells = co;
 }
 
 hipStream_t S(qmg_grid_t* g) { return g->stream; }
@@ -335,7 +503,7 @@ bool p_stored(const qmg_grid_t* g) {
 template <typename T>
 int choose_fused_top(qmg_grid_t* g, bool& pw_lds) {
   int best = -1;
-  for (int lf = g->lc; lf < g->Lmax && lf - g->lc + 1 <= kMaxFused; ++lf) {
+  for (int lf = g->lc; lf < g->lb && lf - g->lc + 1 <= kMaxFused; ++lf) {
     for (int pl = 1; pl >= 0; --pl) {
       FusedArgs<T> a = fused_args<T>(g, lf);
       if ((int64_t)fused_lds_layout<T>(g->d, a, p_stored(g), pl == 1) <= g->lds_max) {
@@ -357,7 +525,14 @@ void fused_coarse(qmg_grid_t* g) {
 }
 
 template <typename T>
+void vcycle_ad(qmg_grid_t* g, int l);
+
+template <typename T>
 void vcycle(qmg_grid_t* g, int l, bool zero_init) {
+  if (l > g->lb) {
+    vcycle_ad<T>(g, l);
+    return;
+  }
   LevelBuf& F = g->lv[l];
   const int mu = g->opts.mu_pre, nu = g->opts.mu_post;
   if (l == g->lf && l < g->Lmax && zero_init) {
@@ -381,10 +556,54 @@ void vcycle(qmg_grid_t* g, int l, bool zero_init) {
   smooth<T>(g, F, nu, false);
 }
 
+// Smoothing sweeps of an adaptive level over its leaf and refined vertices.
+template <typename T>
+void smooth_ad(qmg_grid_t* g, LevelBuf& B, int sweeps) {
+  const T om = (T)g->opts.omega;
+  const AdTiles t = B.ad();
+  for (int k = 0; k < sweeps; ++k) {
+    launch_ad_stencil<T, T>(t, 0, (const T*)B.u, (const T*)B.b, (T*)B.t, eps_of<T>(B), B.A, om, nullptr, S(g));
+    std::swap(B.u, B.t);
+  }
+}
+
+// FAS V-cycle step on an adaptive level (Sect. 2): hanging vertices take the
+// interpolant of the coarser level, the leaf and refined vertices are
+// smoothed, refined coarse vertices receive the finer values (injection) and
+// the FAS right-hand side R r + A_c I u, the coarse level is cycled, and the
+// change of the coarse iterate is prolongated (d-linear).  The complete base
+// level continues with the correction-scheme cycle.
+template <typename T>
+void vcycle_ad(qmg_grid_t* g, int l) {
+  LevelBuf& F = g->lv[l];
+  LevelBuf& C = g->lv[l - 1];
+  const AdTiles tf = F.ad(), tc = C.ad();
+  launch_ad_hang<T>(tf, C.L, (T*)F.u, (const T*)C.u, S(g));
+  smooth_ad<T>(g, F, g->opts.mu_pre);
+  launch_ad_stencil<T, T>(tf, 2, (const T*)F.u, (const T*)F.b, (T*)F.r, eps_of<T>(F), F.A, (T)0, nullptr, S(g));
+  launch_ad_inject<T>(tc, F.L, (const T*)F.u, (T*)C.u, S(g));
+  launch_ad_copy<T>(tc, (const T*)C.u, (T*)C.sv, S(g));
+  launch_ad_fas_rhs<T>(tc, F.L, (const T*)F.r, (const T*)C.u, eps_of<T>(C), C.A, (T*)C.b, S(g));
+  vcycle<T>(g, l - 1, false);
+  launch_ad_correct<T>(tf, C.L, (T*)F.u, (const T*)C.u, (const T*)C.sv, S(g));
+  launch_ad_hang<T>(tf, C.L, (T*)F.u, (const T*)C.u, S(g));
+  smooth_ad<T>(g, F, g->opts.mu_post);
+}
+
+// Refined vertices take their finest copy (top down), then hanging vertices
+// the interpolant of the level below (bottom up).
+void composite_state(qmg_grid_t* g) {
+  for (int l = g->Lmax; l > g->lb; --l)
+    launch_ad_inject<double>(g->lv[l - 1].ad(), g->lv[l].L, (const double*)g->lv[l].u, (double*)g->lv[l - 1].u, S(g));
+  for (int l = g->lb + 1; l <= g->Lmax; ++l)
+    launch_ad_hang<double>(g->lv[l].ad(), g->lv[l - 1].L, (double*)g->lv[l].u, (const double*)g->lv[l - 1].u, S(g));
+}
+
 int64_t updates_per_cycle(const qmg_grid_t* g) {
   int64_t s = 0;
   const int sw = g->opts.mu_pre + g->opts.mu_post;
-  for (int l = g->lc + 1; l <= g->Lmax; ++l) s += (int64_t)sw * n_interior(g->lv[l].L);
+  for (int l = g->lc + 1; l <= g->Lmax; ++l)
+    s += (int64_t)sw * (l > g->lb ? g->hl[l].n_active : n_interior(g->lv[l].L));
   if (!g->coarse_direct) s += (int64_t)sw * n_interior(g->lv[g->lc].L);
   return s;
 }
@@ -398,10 +617,20 @@ double read_scalar(qmg_grid_t* g) {
 
 // ||b - A u||_2 on the finest level, FP64 (the FP32 residual of the mixed loop
 // is written to the finest inner right-hand side on the way).
+// On an adaptive spacetree: the composite residual over the leaves of every
+// level, after the refined and hanging values are made consistent.
 void enqueue_residual_norm(qmg_grid_t* g, bool record) {
   LevelBuf& F = g->lv[g->Lmax];
   int np = 0;
-  if (g->mixed) {
+  if (g->adaptive) {
+    composite_state(g);
+    for (int l = g->lb; l <= g->Lmax; ++l) {
+      LevelBuf& B = g->lv[l];
+      launch_ad_stencil<double, double>(B.ad(), 2, (const double*)B.u, (const double*)B.b, (double*)B.r,
+                                        B.eps64, B.A, 0.0, g->partial + np, S(g));
+      np += B.ntiles;
+    }
+  } else if (g->mixed) {
     launch_residual_mixed(F.L, g->x64, g->bfin, (float*)F.b, F.eps64, g->partial, &np, S(g));
   } else {
     launch_stencil<double>(F.L, 2, (const double*)F.u, (const double*)F.b, (double*)F.r, F.eps64,
@@ -619,7 +848,14 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
   const bool galerkin = g->opts.transfer != QMG_GEOMETRIC;
   const bool boxmg = g->opts.transfer == QMG_BOXMG;
   hipStream_t s = S(g);
-  for (int l = L; l > g->lcq; --l) launch_coarsen_eps(g->lv[l].L, g->lv[l - 1].L, g->lv[l].eps64, g->lv[l - 1].eps64, s);
+  // cell coefficients of coarser levels: means of the children (refined cells
+  // of the adaptive levels, every cell from the base level down)
+  for (int l = L; l > g->lcq; --l) {
+    if (l > g->lb)
+      launch_ad_coarsen_eps(g->lv[l].L, g->lv[l - 1].L, g->lv[l - 1].cref, g->lv[l].eps64, g->lv[l - 1].eps64, s);
+    else
+      launch_coarsen_eps(g->lv[l].L, g->lv[l - 1].L, g->lv[l].eps64, g->lv[l - 1].eps64, s);
+  }
   if (g->mixed)
     for (int l = g->lcq; l <= L; ++l) launch_convert<double, float>(g->lv[l].L, g->lv[l].eps64, g->lv[l].eps32, s);
   g->lc = g->lcq;
@@ -629,7 +865,15 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
     return g->tmpA[l & 1];
   };
   Store geom;
-  if (g->plain) launch_materialise(g->lv[L].L, g->lv[L].eps64, geom, g->lv[L].Adense, s);
+  // rows of an adaptive level: refined vertices keep the Galerkin (or
+  // rediscretised) row, leaves take the rediscretised one, others none
+  auto merge = [&](int l, double* full) {
+    if (g->adaptive && l >= g->lb) launch_ad_merge_rows(g->lv[l].L, g->lv[l].vt, g->lv[l].eps64, full, s);
+  };
+  if (g->plain) {
+    launch_materialise(g->lv[L].L, g->lv[L].eps64, geom, g->lv[L].Adense, s);
+    merge(L, g->lv[L].Adense);
+  }
   for (int l = g->lcq; l <= L; ++l) {
     g->lv[l].Anz = -1;
     g->lv[l].Pnz = -1;
@@ -655,11 +899,19 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
     if (!galerkin) {
       // rediscretised coarse operator: stored only in the plain store, and
       // needed in full on the coarsest level for the exact solve
-      if (g->plain || l - 1 == g->lcq) launch_materialise(C.L, C.eps64, geom, Ac, s);
+      if (g->plain || l - 1 == g->lcq) {
+        launch_materialise(C.L, C.eps64, geom, Ac, s);
+        merge(l - 1, Ac);
+      }
     } else {
       launch_zero<double>(Ac, C.L.nslot * NS, s);
-      launch_rap(F.L, C.L, Afine, F.eps64, Pw, Ac, s);
-      if (g->opts.check_definite) {
+      // the finest adaptive level's rows exist only at leaf vertices
+      const int8_t* mask = (g->adaptive && l == L && !Afine) ? F.vt : nullptr;
+      launch_rap(F.L, C.L, Afine, F.eps64, Pw, Ac, s, mask);
+      merge(l - 1, Ac);
+      // the fallback of a failed check raises the coarsest level, which is
+      // possible only below the base level of an adaptive spacetree
+      if (g->opts.check_definite && l - 1 < g->lb) {
         launch_zero<int>(g->dcount, 1, s);
         launch_check_rows(C.L, Ac, g->dcount, s);
         int bad = 0;
@@ -829,6 +1081,14 @@ void apply_op(qmg_grid_t* g, int op, int level, const double* x, const double* b
   download_lattice<T>(g, B.L, (const T*)B.t, out);
 }
 
+// position of a lattice slot (+ offset in units of h) on level l
+void slot_xyz(const Lat& L, int64_t sl, double off, double* out) {
+  const int64_t k = L.d == 3 ? sl / L.plane : 0, rem = sl - k * L.plane;
+  out[0] = ((double)(rem % L.pitch) + off) * L.h;
+  out[1] = ((double)(rem / L.pitch) + off) * L.h;
+  if (L.d == 3) out[2] = ((double)k + off) * L.h;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -967,6 +1227,7 @@ int qmg_create_grid(const qmg_grid_desc* desc, const qmg_solver_opts* opts, void
       QMG_HIP(hipEventCreateWithFlags(&g->bev, hipEventDisableTiming));
       QMG_HIP(hipStreamSynchronize(g->stream));
       g->n_unknowns = n_interior(g->lv[g->Lmax].L);
+      upload_linearisation(g);
     } catch (...) {
       if (g->owns && g->base) (void)hipFree(g->base);
       if (g->hnorm) (void)hipHostFree(g->hnorm);
@@ -983,19 +1244,48 @@ int qmg_sizes(const qmg_grid_t* g, int64_t* n_unknowns, int64_t* n_leaf_cells, i
   if (!g) return QMG_EINVAL;
   const Lat& L = g->lv[g->Lmax].L;
   if (n_unknowns) *n_unknowns = g->n_unknowns;
-  if (n_leaf_cells) *n_leaf_cells = g->d == 3 ? (int64_t)L.n * L.n * L.n : (int64_t)L.n * L.n;
+  if (n_leaf_cells) *n_leaf_cells = g->adaptive ? g->n_cells : g->d == 3 ? (int64_t)L.n * L.n * L.n : (int64_t)L.n * L.n;
   if (n_levels) *n_levels = g->Lmax + 1;
   return QMG_OK;
 }
 
-int qmg_unknown_coords(const qmg_grid_t* g, double* xyz) {
+int qmg_unknown_coords(const qmg_grid_t* g, double* xyz, int8_t* level) {
   if (!g || !xyz) return QMG_EINVAL;
+  if (g->adaptive) {
+    int64_t r = 0;
+    for (int l = g->lb; l <= g->Lmax; ++l)
+      for (int64_t sl : g->hl[l].leaf) {
+        slot_xyz(g->lv[l].L, sl, 0.0, xyz + r * g->d);
+        if (level) level[r] = (int8_t)l;
+        ++r;
+      }
+    return QMG_OK;
+  }
   const Lat& L = g->lv[g->Lmax].L;
   const int m = L.n - 1;
   for (int64_t r = 0; r < g->n_unknowns; ++r) {
     xyz[r * g->d + 0] = (double)(r % m + 1) * L.h;
     xyz[r * g->d + 1] = (double)((r / m) % m + 1) * L.h;
     if (g->d == 3) xyz[r * g->d + 2] = (double)(r / ((int64_t)m * m) + 1) * L.h;
+    if (level) level[r] = (int8_t)g->Lmax;
+  }
+  return QMG_OK;
+}
+
+int qmg_leaf_cell_centres(const qmg_grid_t* g, double* xyz) {
+  if (!g || !xyz) return QMG_EINVAL;
+  if (g->adaptive) {
+    int64_t r = 0;
+    for (int l = g->lb; l <= g->Lmax; ++l)
+      for (int64_t sl : g->hl[l].cells) slot_xyz(g->lv[l].L, sl, 0.5, xyz + (r++) * g->d);
+    return QMG_OK;
+  }
+  const Lat& L = g->lv[g->Lmax].L;
+  const int64_t n = L.n, nc = g->d == 3 ? n * n * n : n * n;
+  for (int64_t c = 0; c < nc; ++c) {
+    xyz[c * g->d + 0] = ((double)(c % n) + 0.5) * L.h;
+    xyz[c * g->d + 1] = ((double)((c / n) % n) + 0.5) * L.h;
+    if (g->d == 3) xyz[c * g->d + 2] = ((double)(c / (n * n)) + 0.5) * L.h;
   }
   return QMG_OK;
 }
@@ -1007,7 +1297,7 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
     if (mem != QMG_HOST && mem != QMG_DEVICE) throw ApiError(QMG_EINVAL, "bad mem flag");
     LevelBuf& F = g->lv[g->Lmax];
     const Lat& L = F.L;
-    const int64_t ncell = L.d == 3 ? (int64_t)L.n * L.n * L.n : (int64_t)L.n * L.n;
+    const int64_t ncell = g->adaptive ? g->n_cells : L.d == 3 ? (int64_t)L.n * L.n * L.n : (int64_t)L.n * L.n;
     const int64_t nu = g->n_unknowns;
     std::vector<double> he, hf;
     const double* pe = eps;
@@ -1022,16 +1312,51 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
     }
     for (int64_t c = 0; c < ncell; ++c)
       if (!(pe[c] > 0.0) || !std::isfinite(pe[c])) throw ApiError(QMG_EINVAL, "eps must be positive and finite");
-    double hd = 1.0;
-    for (int i = 0; i < g->d; ++i) hd *= L.h;
     std::vector<double> b(nu);
     double s2 = 0.0;
-    for (int64_t r = 0; r < nu; ++r) {
-      if (!std::isfinite(pf[r])) throw ApiError(QMG_EINVAL, "f must be finite");
-      b[r] = hd * pf[r];
-      s2 += b[r] * b[r];
+    {
+      int64_t r = 0;
+      for (int l = g->lb; l <= g->Lmax; ++l) {
+        double hd = 1.0;
+        for (int i = 0; i < g->d; ++i) hd *= g->lv[l].L.h;
+        const int64_t cnt = g->adaptive ? (int64_t)g->hl[l].leaf.size() : nu;
+        for (int64_t q = 0; q < cnt; ++q, ++r) {
+          if (!std::isfinite(pf[r])) throw ApiError(QMG_EINVAL, "f must be finite");
+          b[r] = hd * pf[r];
+          s2 += b[r] * b[r];
+        }
+      }
     }
     g->bnorm = std::sqrt(s2);
+    if (g->adaptive) {
+      QMG_HIP(hipMemcpyAsync(g->stage, pe, ncell * sizeof(double), hipMemcpyHostToDevice, S(g)));
+      int64_t co = 0;
+      for (int l = g->lb; l <= g->Lmax; ++l) {
+        LevelBuf& B = g->lv[l];
+        const int64_t cnt = (int64_t)g->hl[l].cells.size();
+        launch_zero<double>(B.eps64, B.L.nslot, S(g));
+        launch_ad_scatter<double>(g->cell_slots + co, cnt, g->stage + co, 1.0, B.eps64, S(g));
+        co += cnt;
+      }
+      QMG_HIP(hipStreamSynchronize(S(g)));
+      QMG_HIP(hipMemcpyAsync(g->stage, b.data(), nu * sizeof(double), hipMemcpyHostToDevice, S(g)));
+      int64_t uo = 0;
+      for (int l = g->lcq; l <= g->Lmax; ++l) {
+        LevelBuf& B = g->lv[l];
+        launch_zero<double>((double*)B.u, B.L.nslot, S(g));
+        launch_zero<double>((double*)B.t, B.L.nslot, S(g));
+        launch_zero<double>((double*)B.b, B.L.nslot, S(g));
+        if (l < g->lb) continue;
+        const int64_t cnt = (int64_t)g->hl[l].leaf.size();
+        launch_ad_scatter<double>(g->unk_slots + uo, cnt, g->stage + uo, 1.0, (double*)B.b, S(g));
+        uo += cnt;
+      }
+      QMG_HIP(hipStreamSynchronize(S(g)));
+      g->have_coef = true;
+      g->have_ops = false;
+      drop_graph(g);
+      return;
+    }
     QMG_HIP(hipMemcpyAsync(g->stage, pe, ncell * sizeof(double), hipMemcpyHostToDevice, S(g)));
     launch_scatter_cells<double>(L, g->stage, F.eps64, S(g));
     QMG_HIP(hipMemcpyAsync(g->stage, b.data(), nu * sizeof(double), hipMemcpyHostToDevice, S(g)));
@@ -1098,8 +1423,17 @@ int qmg_get_solution(const qmg_grid_t* cg, double* u, int mem) {
   return guard(g, [&] {
     if (!g || !u) throw ApiError(QMG_EINVAL, "null argument");
     LevelBuf& F = g->lv[g->Lmax];
-    const double* src = g->mixed ? g->x64 : (const double*)F.u;
-    launch_gather_unknowns<double>(F.L, src, g->stage, S(g));
+    if (g->adaptive) {
+      int64_t uo = 0;
+      for (int l = g->lb; l <= g->Lmax; ++l) {
+        const int64_t cnt = (int64_t)g->hl[l].leaf.size();
+        launch_ad_gather<double>(g->unk_slots + uo, cnt, (const double*)g->lv[l].u, g->stage + uo, S(g));
+        uo += cnt;
+      }
+    } else {
+      const double* src = g->mixed ? g->x64 : (const double*)F.u;
+      launch_gather_unknowns<double>(F.L, src, g->stage, S(g));
+    }
     QMG_HIP(hipMemcpyAsync(u, g->stage, g->n_unknowns * sizeof(double),
                            mem == QMG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, S(g)));
     QMG_HIP(hipStreamSynchronize(S(g)));
@@ -1111,7 +1445,18 @@ int qmg_set_solution(qmg_grid_t* g, const double* u, int mem) {
     if (!g || !u) throw ApiError(QMG_EINVAL, "null argument");
     LevelBuf& F = g->lv[g->Lmax];
     copy_in(g, g->stage, u, g->n_unknowns, mem);
-    launch_scatter_unknowns<double>(F.L, g->stage, g->mixed ? g->x64 : (double*)F.u, S(g));
+    if (g->adaptive) {
+      int64_t uo = 0;
+      for (int l = g->lb; l <= g->Lmax; ++l) {
+        const int64_t cnt = (int64_t)g->hl[l].leaf.size();
+        launch_ad_scatter<double>(g->unk_slots + uo, cnt, g->stage + uo, 1.0, (double*)g->lv[l].u, S(g));
+        uo += cnt;
+      }
+      // refined and hanging values are functions of the leaves
+      composite_state(g);
+    } else {
+      launch_scatter_unknowns<double>(F.L, g->stage, g->mixed ? g->x64 : (double*)F.u, S(g));
+    }
     QMG_HIP(hipStreamSynchronize(S(g)));
   });
 }

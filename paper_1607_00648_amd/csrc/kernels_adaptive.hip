@@ -1,0 +1,405 @@
+// Kernels of the adaptive levels (finer than the complete base level).
+//
+// An adaptive level keeps the full lattice of its level but only the 64 x 4
+// (x, y) tiles that hold vertices of existing cells are launched: blockIdx.x
+// indexes a tile list.  Every slot carries its vertex class (Sect. 2): leaf
+// (unrefined, an unknown), refined (a finer copy exists), hanging (fewer than
+// 2^d cells of the level), or outside/boundary.  Smoothing and residuals act
+// on leaf and refined vertices; hanging vertices hold the d-linear interpolant
+// of the coarser level; refined coarse vertices receive the value of their
+// finer copy and the FAS right-hand side.
+#include "level_ops.hpp"
+
+namespace qmg {
+
+namespace {
+
+constexpr int TX = 64, TY = 4;
+
+struct Slot {
+  int i, j, k;
+  int64_t v;
+  bool valid;
+};
+
+template <int D>
+__device__ inline Slot tile_slot(const Lat& L, const int32_t* __restrict__ tiles) {
+  const int32_t* t = tiles + 3 * (int64_t)blockIdx.x;
+  Slot s;
+  s.i = t[0] * TX + threadIdx.x;
+  s.j = t[1] * TY + threadIdx.y;
+  s.k = (D == 3) ? t[2] : 0;
+  s.valid = s.i <= L.n && s.j <= L.n;
+  s.v = s.i + (int64_t)s.j * L.pitch + (int64_t)s.k * L.plane;
+  return s;
+}
+
+__device__ inline bool active(int8_t t) { return t == VT_LEAF || t == VT_REFINED; }
+
+__device__ inline double block_sum_256(double x) {
+  __shared__ double red[4];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+  const int t = threadIdx.x + threadIdx.y * TX;
+  if ((t & 63) == 0) red[t >> 6] = x;
+  __syncthreads();
+  double s = 0.0;
+  if (t == 0) s = ((red[0] + red[1]) + red[2]) + red[3];
+  return s;
+}
+
+// mode 0: Jacobi sweep, 1: sweep from zero, 2: residual (0 off the active set)
+template <int D, typename T, typename TO, int SRC, int FMT, int MODE>
+__global__ __launch_bounds__(256) void k_ad_stencil(Lat L, const int32_t* __restrict__ tiles,
+                                                    const int8_t* __restrict__ vt, const T* __restrict__ u,
+                                                    const T* __restrict__ b, TO* __restrict__ out,
+                                                    const T* __restrict__ eps, Store A, T omega,
+                                                    double* __restrict__ partial) {
+  constexpr int NS = Dim<D>::NS;
+  const Slot s = tile_slot<D>(L, tiles);
+  double sq = 0.0;
+  if (s.valid) {
+    const int8_t t = vt[s.v];
+    if (active(t)) {
+      T a[NS];
+      op_row<D, T, SRC, FMT>(eps, A, L, s.v, a);
+      if (MODE == 1) {
+        out[s.v] = (TO)(omega * b[s.v] / a[NS / 2]);
+      } else {
+        const T res = b[s.v] - row_dot<D, T, SRC>(a, u, L, s.v);
+        if (MODE == 0) {
+          out[s.v] = (TO)(u[s.v] + omega * res / a[NS / 2]);
+        } else {
+          out[s.v] = (TO)res;
+          if (t == VT_LEAF) sq = (double)res * (double)res;
+        }
+      }
+    } else {
+      // hanging / outside values travel with the iterate (zero from zero)
+      out[s.v] = (MODE == 0) ? (TO)u[s.v] : (TO)0;
+    }
+  }
+  if (partial != nullptr) {
+    const double tot = block_sum_256(sq);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partial[blockIdx.x] = tot;
+  }
+}
+
+// hanging vertices of the fine level := d-linear interpolant of the coarse level
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_ad_hang(Lat Lf, Lat Lc, const int32_t* __restrict__ tiles,
+                                                 const int8_t* __restrict__ vt, T* __restrict__ uf,
+                                                 const T* __restrict__ uc) {
+  const Slot s = tile_slot<D>(Lf, tiles);
+  if (!s.valid || vt[s.v] != VT_HANGING) return;
+  const int qx = s.i / 3, qy = s.j / 3, qz = s.k / 3;
+  const int rx = s.i - 3 * qx, ry = s.j - 3 * qy, rz = s.k - 3 * qz;
+  const int64_t vc = qx + (int64_t)qy * Lc.pitch + (int64_t)qz * Lc.plane;
+  T acc = (T)0;
+#pragma unroll
+  for (int kap = 0; kap < Dim<D>::NC; ++kap) {
+    const int kx = kap & 1, ky = (kap >> 1) & 1, kk = (kap >> 2) & 1;
+    if ((kx && rx == 0) || (ky && ry == 0) || (kk && rz == 0)) continue;
+    const double w = dlin1(rx, kx) * dlin1(ry, ky) * (D == 3 ? dlin1(rz, kk) : 1.0);
+    acc += (T)w * uc[vc + slot_off(Lc, kx, ky, kk)];
+  }
+  uf[s.v] = acc;
+}
+
+// refined coarse vertices := value of the finer copy (over coarse tiles)
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_ad_inject(Lat Lf, Lat Lc, const int32_t* __restrict__ tiles,
+                                                   const int8_t* __restrict__ vtc, const T* __restrict__ uf,
+                                                   T* __restrict__ uc) {
+  const Slot s = tile_slot<D>(Lc, tiles);
+  if (!s.valid || vtc[s.v] != VT_REFINED) return;
+  uc[s.v] = uf[3 * s.i + (int64_t)3 * s.j * Lf.pitch + (int64_t)3 * s.k * Lf.plane];
+}
+
+// FAS right-hand side of refined coarse vertices: (P^T r)(V) + (A_c u_c)(V),
+// d-linear P; r is zero off the fine active set
+template <int D, typename T, int SRC, int FMT>
+__global__ __launch_bounds__(256) void k_ad_fas_rhs(Lat Lf, Lat Lc, const int32_t* __restrict__ tiles,
+                                                    const int8_t* __restrict__ vtc, const T* __restrict__ rf,
+                                                    const T* __restrict__ uc, const T* __restrict__ epsc,
+                                                    Store Ac, T* __restrict__ bc) {
+  constexpr int NS = Dim<D>::NS;
+  const Slot s = tile_slot<D>(Lc, tiles);
+  if (!s.valid || vtc[s.v] != VT_REFINED) return;
+  Store none;
+  const T rr = restrict_at<D, T, SRC_GEOM, F64>(Lf, rf, none, s.i, s.j, s.k);
+  T a[NS];
+  op_row<D, T, SRC, FMT>(epsc, Ac, Lc, s.v, a);
+  bc[s.v] = rr + row_dot<D, T, SRC>(a, uc, Lc, s.v);
+}
+
+// FAS correction: active fine vertices += P (u_c - saved_c), d-linear P
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_ad_correct(Lat Lf, Lat Lc, const int32_t* __restrict__ tiles,
+                                                    const int8_t* __restrict__ vt, T* __restrict__ uf,
+                                                    const T* __restrict__ uc, const T* __restrict__ sc) {
+  const Slot s = tile_slot<D>(Lf, tiles);
+  if (!s.valid || !active(vt[s.v])) return;
+  const int qx = s.i / 3, qy = s.j / 3, qz = s.k / 3;
+  const int rx = s.i - 3 * qx, ry = s.j - 3 * qy, rz = s.k - 3 * qz;
+  const int64_t vc = qx + (int64_t)qy * Lc.pitch + (int64_t)qz * Lc.plane;
+  T acc = (T)0;
+#pragma unroll
+  for (int kap = 0; kap < Dim<D>::NC; ++kap) {
+    const int kx = kap & 1, ky = (kap >> 1) & 1, kk = (kap >> 2) & 1;
+    if ((kx && rx == 0) || (ky && ry == 0) || (kk && rz == 0)) continue;
+    const double w = dlin1(rx, kx) * dlin1(ry, ky) * (D == 3 ? dlin1(rz, kk) : 1.0);
+    const int64_t c = vc + slot_off(Lc, kx, ky, kk);
+    acc += (T)w * (uc[c] - sc[c]);
+  }
+  uf[s.v] += acc;
+}
+
+// dst := src on every slot of the listed tiles
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_ad_copy(Lat L, const int32_t* __restrict__ tiles,
+                                                 const T* __restrict__ src, T* __restrict__ dst) {
+  const Slot s = tile_slot<D>(L, tiles);
+  if (s.valid) dst[s.v] = src[s.v];
+}
+
+// zero on every slot of the listed tiles
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_ad_zero(Lat L, const int32_t* __restrict__ tiles, T* __restrict__ p) {
+  const Slot s = tile_slot<D>(L, tiles);
+  if (s.valid) p[s.v] = (T)0;
+}
+
+// x64 += e32 on the leaves; residual of the mixed loop at the leaves in FP64
+template <int D>
+__global__ __launch_bounds__(256) void k_ad_axpy(Lat L, const int32_t* __restrict__ tiles,
+                                                 const int8_t* __restrict__ vt, double* __restrict__ x,
+                                                 const float* __restrict__ e) {
+  const Slot s = tile_slot<D>(L, tiles);
+  if (s.valid && vt[s.v] == VT_LEAF) x[s.v] += (double)e[s.v];
+}
+
+// cell coefficients of a level: refined cells take the mean of their children
+template <int D>
+__global__ __launch_bounds__(256) void k_ad_coarsen_eps(Lat Lf, Lat Lc, const int8_t* __restrict__ cref,
+                                                        const double* __restrict__ ef, double* __restrict__ ec) {
+  const int I = blockIdx.x * TX + threadIdx.x;
+  const int J = blockIdx.y * TY + threadIdx.y;
+  const int K = (D == 3) ? (int)blockIdx.z : 0;
+  if (I >= Lc.n || J >= Lc.n || (D == 3 && K >= Lc.n)) return;
+  const int64_t vc = I + (int64_t)J * Lc.pitch + (int64_t)K * Lc.plane;
+  if (!cref[vc]) return;
+  double s = 0.0;
+  const int zc = (D == 3) ? 3 : 1;
+  for (int c = 0; c < zc; ++c)
+    for (int b = 0; b < 3; ++b)
+      for (int a = 0; a < 3; ++a)
+        s += ef[(3 * I + a) + (int64_t)(3 * J + b) * Lf.pitch + (int64_t)(3 * K + c) * Lf.plane];
+  ec[vc] = s / (D == 3 ? 27.0 : 9.0);
+}
+
+// stencil rows of a level for the next Galerkin product: refined rows keep the
+// Galerkin result, leaf rows take the rediscretised stencil, other rows zero
+template <int D>
+__global__ __launch_bounds__(256) void k_ad_merge_rows(Lat L, const int8_t* __restrict__ vt,
+                                                       const double* __restrict__ eps, double* __restrict__ A) {
+  constexpr int NS = Dim<D>::NS;
+  const int i = blockIdx.x * TX + threadIdx.x;
+  const int j = blockIdx.y * TY + threadIdx.y;
+  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+  if (i > L.n || j > L.n) return;
+  const int64_t v = i + (int64_t)j * L.pitch + (int64_t)kz * L.plane;
+  const int8_t t = vt[v];
+  if (t == VT_REFINED) return;
+  if (t == VT_LEAF) {
+    double a[NS];
+    geom_row<D, double>(eps, v, L, a);
+    for (int k = 0; k < NS; ++k) {
+      const int ii = i + off_x(k), jj = j + off_y(k), kk = kz + (D == 3 ? off_z(k) : 0);
+      const bool in = ii >= 1 && ii < L.n && jj >= 1 && jj < L.n && (D == 2 || (kk >= 1 && kk < L.n));
+      A[(int64_t)k * L.nslot + v] = in ? a[k] : 0.0;
+    }
+  } else {
+    for (int k = 0; k < NS; ++k) A[(int64_t)k * L.nslot + v] = 0.0;
+  }
+}
+
+// packed leaf values <-> lattice slots (slot lists in unknown order)
+template <typename T>
+__global__ void k_ad_scatter(const int64_t* __restrict__ slots, int64_t n, const double* __restrict__ in,
+                             double scale, T* __restrict__ lat) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) lat[slots[t]] = (T)(scale * in[t]);
+}
+template <typename T>
+__global__ void k_ad_gather(const int64_t* __restrict__ slots, int64_t n, const T* __restrict__ lat,
+                            double* __restrict__ out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) out[t] = (double)lat[slots[t]];
+}
+
+inline dim3 tiles_grid(int ntiles) { return dim3((unsigned)ntiles); }
+inline dim3 full_grid(const Lat& L) {
+  return dim3((unsigned)(L.pitch / TX), (unsigned)((L.n + 1 + TY - 1) / TY), (unsigned)(L.d == 3 ? L.n + 1 : 1));
+}
+
+template <int D, typename T, typename TO, int SRC, int FMT>
+void ad_stencil_mode(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
+                     const Store& A, T omega, double* partial, hipStream_t s) {
+  const dim3 g = tiles_grid(t.n), bl(TX, TY, 1);
+  switch (mode) {
+    case 0: hipLaunchKernelGGL((k_ad_stencil<D, T, TO, SRC, FMT, 0>), g, bl, 0, s, t.L, t.tiles, t.vt, u, b, out, eps, A, omega, partial); break;
+    case 1: hipLaunchKernelGGL((k_ad_stencil<D, T, TO, SRC, FMT, 1>), g, bl, 0, s, t.L, t.tiles, t.vt, u, b, out, eps, A, omega, partial); break;
+    default: hipLaunchKernelGGL((k_ad_stencil<D, T, TO, SRC, FMT, 2>), g, bl, 0, s, t.L, t.tiles, t.vt, u, b, out, eps, A, omega, partial); break;
+  }
+}
+
+template <int D, typename T, typename TO>
+void ad_stencil_src(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
+                    const Store& A, T omega, double* partial, hipStream_t s) {
+  if (A.src == SRC_GEOM) return ad_stencil_mode<D, T, TO, SRC_GEOM, F64>(t, mode, u, b, out, eps, A, omega, partial, s);
+  if (A.src == SRC_PLAIN) return ad_stencil_mode<D, T, TO, SRC_PLAIN, F64>(t, mode, u, b, out, eps, A, omega, partial, s);
+  switch (A.fmt) {
+    case F64: return ad_stencil_mode<D, T, TO, SRC_HIER, F64>(t, mode, u, b, out, eps, A, omega, partial, s);
+    case F32: return ad_stencil_mode<D, T, TO, SRC_HIER, F32>(t, mode, u, b, out, eps, A, omega, partial, s);
+    case F16: return ad_stencil_mode<D, T, TO, SRC_HIER, F16>(t, mode, u, b, out, eps, A, omega, partial, s);
+    default: return ad_stencil_mode<D, T, TO, SRC_HIER, BF16>(t, mode, u, b, out, eps, A, omega, partial, s);
+  }
+}
+
+template <int D, typename T>
+void ad_fas_src(const AdTiles& tc, const Lat& Lf, const T* rf, const T* uc, const T* epsc, const Store& Ac,
+                T* bc, hipStream_t s) {
+  const dim3 g = tiles_grid(tc.n), bl(TX, TY, 1);
+#define QMG_FAS(SRCV, FMTV) hipLaunchKernelGGL((k_ad_fas_rhs<D, T, SRCV, FMTV>), g, bl, 0, s, Lf, tc.L, tc.tiles, tc.vt, rf, uc, epsc, Ac, bc)
+  if (Ac.src == SRC_GEOM) QMG_FAS(SRC_GEOM, F64);
+  else if (Ac.src == SRC_PLAIN) QMG_FAS(SRC_PLAIN, F64);
+  else if (Ac.fmt == F64) QMG_FAS(SRC_HIER, F64);
+  else if (Ac.fmt == F32) QMG_FAS(SRC_HIER, F32);
+  else if (Ac.fmt == F16) QMG_FAS(SRC_HIER, F16);
+  else QMG_FAS(SRC_HIER, BF16);
+#undef QMG_FAS
+}
+
+}  // namespace
+
+template <typename T, typename TO>
+void launch_ad_stencil(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
+                       const Store& A, T omega, double* partial, hipStream_t s) {
+  if (t.n <= 0) return;
+  if (t.L.d == 2) ad_stencil_src<2, T, TO>(t, mode, u, b, out, eps, A, omega, partial, s);
+  else ad_stencil_src<3, T, TO>(t, mode, u, b, out, eps, A, omega, partial, s);
+  QMG_HIP(hipGetLastError());
+}
+template void launch_ad_stencil<double, double>(const AdTiles&, int, const double*, const double*, double*, const double*, const Store&, double, double*, hipStream_t);
+template void launch_ad_stencil<float, float>(const AdTiles&, int, const float*, const float*, float*, const float*, const Store&, float, double*, hipStream_t);
+template void launch_ad_stencil<double, float>(const AdTiles&, int, const double*, const double*, float*, const double*, const Store&, double, double*, hipStream_t);
+
+template <typename T>
+void launch_ad_hang(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, hipStream_t s) {
+  if (tf.n <= 0) return;
+  const dim3 g = tiles_grid(tf.n), bl(TX, TY, 1);
+  if (tf.L.d == 2) hipLaunchKernelGGL((k_ad_hang<2, T>), g, bl, 0, s, tf.L, Lc, tf.tiles, tf.vt, uf, uc);
+  else hipLaunchKernelGGL((k_ad_hang<3, T>), g, bl, 0, s, tf.L, Lc, tf.tiles, tf.vt, uf, uc);
+  QMG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_ad_inject(const AdTiles& tc, const Lat& Lf, const T* uf, T* uc, hipStream_t s) {
+  if (tc.n <= 0) return;
+  const dim3 g = tiles_grid(tc.n), bl(TX, TY, 1);
+  if (tc.L.d == 2) hipLaunchKernelGGL((k_ad_inject<2, T>), g, bl, 0, s, Lf, tc.L, tc.tiles, tc.vt, uf, uc);
+  else hipLaunchKernelGGL((k_ad_inject<3, T>), g, bl, 0, s, Lf, tc.L, tc.tiles, tc.vt, uf, uc);
+  QMG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_ad_fas_rhs(const AdTiles& tc, const Lat& Lf, const T* rf, const T* uc, const T* epsc,
+                       const Store& Ac, T* bc, hipStream_t s) {
+  if (tc.n <= 0) return;
+  if (tc.L.d == 2) ad_fas_src<2, T>(tc, Lf, rf, uc, epsc, Ac, bc, s);
+  else ad_fas_src<3, T>(tc, Lf, rf, uc, epsc, Ac, bc, s);
+  QMG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_ad_correct(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const T* sc, hipStream_t s) {
+  if (tf.n <= 0) return;
+  const dim3 g = tiles_grid(tf.n), bl(TX, TY, 1);
+  if (tf.L.d == 2) hipLaunchKernelGGL((k_ad_correct<2, T>), g, bl, 0, s, tf.L, Lc, tf.tiles, tf.vt, uf, uc, sc);
+  else hipLaunchKernelGGL((k_ad_correct<3, T>), g, bl, 0, s, tf.L, Lc, tf.tiles, tf.vt, uf, uc, sc);
+  QMG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_ad_copy(const AdTiles& t, const T* src, T* dst, hipStream_t s) {
+  if (t.n <= 0) return;
+  const dim3 g = tiles_grid(t.n), bl(TX, TY, 1);
+  if (t.L.d == 2) hipLaunchKernelGGL((k_ad_copy<2, T>), g, bl, 0, s, t.L, t.tiles, src, dst);
+  else hipLaunchKernelGGL((k_ad_copy<3, T>), g, bl, 0, s, t.L, t.tiles, src, dst);
+  QMG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_ad_zero(const AdTiles& t, T* p, hipStream_t s) {
+  if (t.n <= 0) return;
+  const dim3 g = tiles_grid(t.n), bl(TX, TY, 1);
+  if (t.L.d == 2) hipLaunchKernelGGL((k_ad_zero<2, T>), g, bl, 0, s, t.L, t.tiles, p);
+  else hipLaunchKernelGGL((k_ad_zero<3, T>), g, bl, 0, s, t.L, t.tiles, p);
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_ad_axpy(const AdTiles& t, double* x, const float* e, hipStream_t s) {
+  if (t.n <= 0) return;
+  const dim3 g = tiles_grid(t.n), bl(TX, TY, 1);
+  if (t.L.d == 2) hipLaunchKernelGGL(k_ad_axpy<2>, g, bl, 0, s, t.L, t.tiles, t.vt, x, e);
+  else hipLaunchKernelGGL(k_ad_axpy<3>, g, bl, 0, s, t.L, t.tiles, t.vt, x, e);
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_ad_coarsen_eps(const Lat& Lf, const Lat& Lc, const int8_t* cref, const double* ef, double* ec,
+                           hipStream_t s) {
+  const dim3 g = full_grid(Lc), bl(TX, TY, 1);
+  if (Lc.d == 2) hipLaunchKernelGGL(k_ad_coarsen_eps<2>, g, bl, 0, s, Lf, Lc, cref, ef, ec);
+  else hipLaunchKernelGGL(k_ad_coarsen_eps<3>, g, bl, 0, s, Lf, Lc, cref, ef, ec);
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_ad_merge_rows(const Lat& L, const int8_t* vt, const double* eps, double* A, hipStream_t s) {
+  const dim3 g = full_grid(L), bl(TX, TY, 1);
+  if (L.d == 2) hipLaunchKernelGGL(k_ad_merge_rows<2>, g, bl, 0, s, L, vt, eps, A);
+  else hipLaunchKernelGGL(k_ad_merge_rows<3>, g, bl, 0, s, L, vt, eps, A);
+  QMG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_ad_scatter(const int64_t* slots, int64_t n, const double* in, double scale, T* lat, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_ad_scatter<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, slots, n, in, scale, lat);
+  QMG_HIP(hipGetLastError());
+}
+template <typename T>
+void launch_ad_gather(const int64_t* slots, int64_t n, const T* lat, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_ad_gather<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, slots, n, lat, out);
+  QMG_HIP(hipGetLastError());
+}
+
+template void launch_ad_hang<double>(const AdTiles&, const Lat&, double*, const double*, hipStream_t);
+template void launch_ad_hang<float>(const AdTiles&, const Lat&, float*, const float*, hipStream_t);
+template void launch_ad_inject<double>(const AdTiles&, const Lat&, const double*, double*, hipStream_t);
+template void launch_ad_inject<float>(const AdTiles&, const Lat&, const float*, float*, hipStream_t);
+template void launch_ad_fas_rhs<double>(const AdTiles&, const Lat&, const double*, const double*, const double*, const Store&, double*, hipStream_t);
+template void launch_ad_fas_rhs<float>(const AdTiles&, const Lat&, const float*, const float*, const float*, const Store&, float*, hipStream_t);
+template void launch_ad_correct<double>(const AdTiles&, const Lat&, double*, const double*, const double*, hipStream_t);
+template void launch_ad_correct<float>(const AdTiles&, const Lat&, float*, const float*, const float*, hipStream_t);
+template void launch_ad_copy<double>(const AdTiles&, const double*, double*, hipStream_t);
+template void launch_ad_copy<float>(const AdTiles&, const float*, float*, hipStream_t);
+template void launch_ad_zero<double>(const AdTiles&, double*, hipStream_t);
+template void launch_ad_zero<float>(const AdTiles&, float*, hipStream_t);
+template void launch_ad_scatter<double>(const int64_t*, int64_t, const double*, double, double*, hipStream_t);
+template void launch_ad_scatter<float>(const int64_t*, int64_t, const double*, double, float*, hipStream_t);
+template void launch_ad_gather<double>(const int64_t*, int64_t, const double*, double*, hipStream_t);
+template void launch_ad_gather<float>(const int64_t*, int64_t, const float*, double*, hipStream_t);
+
+}  // namespace qmg

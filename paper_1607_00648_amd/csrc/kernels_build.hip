@@ -101,7 +101,9 @@ struct BoxFetch {
   const double* A;  // FP64 stencils (entry-major) or null: rediscretise from eps
   const double* eps;
   Lat L;
+  const int8_t* vt = nullptr;  // optional: rows only at leaf and refined vertices
   __device__ double operator()(int64_t v, int i, int j, int k, int kk) const {
+    if (vt && vt[v] != VT_LEAF && vt[v] != VT_REFINED) return 0.0;
     if (A) return A[(int64_t)kk * L.nslot + v];
     return geom_entry<D>(eps, v, i, j, k, kk, L);
   }
@@ -306,6 +308,7 @@ __global__ __launch_bounds__(256) void k_check_rows(Lat Lc, const double* __rest
   double off = 0.0;
   for (int k = 0; k < NS; ++k)
     if (k != NS / 2) off += fabs(Ac[(int64_t)k * Lc.nslot + v]);
+  if (dg == 0.0 && off == 0.0) return;  // no row (adaptive levels: not a refined vertex)
   if (dg <= 0.0 || dg < (1.0 - kDomSlack) * off) atomicAdd(bad, 1);
 }
 
@@ -509,17 +512,17 @@ void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const doubl
 }
 
 void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
-                const double* Pw, double* Ac, hipStream_t s) {
+                const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine) {
   const int m = Lc.n - 1;
   if (m <= 0) return;
   if (Lf.d == 2) {
     const int64_t nt = (int64_t)m * m * 9;
-    BoxFetch<2> A{Afine, epsf, Lf};
+    BoxFetch<2> A{Afine, epsf, Lf, vt_fine};
     PFetch<2> P{Pw, Lf, Lc};
     hipLaunchKernelGGL(k_rap<2>, dim3(blocks_for(nt, 256)), dim3(256), 0, s, Lf, Lc, A, P, Ac);
   } else {
     const int64_t nt = (int64_t)m * m * m * 27;
-    BoxFetch<3> A{Afine, epsf, Lf};
+    BoxFetch<3> A{Afine, epsf, Lf, vt_fine};
     PFetch<3> P{Pw, Lf, Lc};
     hipLaunchKernelGGL(k_rap<3>, dim3(blocks_for(nt, 256)), dim3(256), 0, s, Lf, Lc, A, P, Ac);
   }

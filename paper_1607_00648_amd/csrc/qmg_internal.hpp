@@ -152,8 +152,10 @@ void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const doubl
                   double* Pw, hipStream_t s);
 // Galerkin RAP (Sect. 3.3): coarse FP64 stencils from fine stencils (or eps on
 // the fly when Afine is null) and FP64 parent weights (d-linear when Pw null).
+// vt_fine (nullable): vertex classes of the fine level; rows of vertices that
+// are neither leaf nor refined count as zero.
 void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
-                const double* Pw, double* Ac, hipStream_t s);
+                const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine = nullptr);
 // Definiteness check of coarse stencils; counts failing rows into *bad.
 void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s);
 // Hierarchical delta store: per-block zero flags, compaction and payload.  The
@@ -195,6 +197,44 @@ void launch_fused_coarse(int d, const FusedArgs<T>& a, int asrc, int psrc, int f
 // Fill lattice array with zeros (kernel, not memset, so it can live in graphs).
 template <typename T>
 void launch_zero(T* p, int64_t n, hipStream_t s);
+
+// ---- adaptive levels (kernels_adaptive.hip) ----
+enum VertexClass : int8_t { VT_OUT = 0, VT_LEAF = 1, VT_REFINED = 2, VT_HANGING = 3 };
+// Active 64 x 4 (x, y) tiles of one level (3 ints per tile: x tile, y tile,
+// z plane) and the vertex class of every slot of the level.
+struct AdTiles {
+  Lat L;
+  const int32_t* tiles = nullptr;
+  const int8_t* vt = nullptr;
+  int n = 0;
+};
+// mode 0: Jacobi sweep of leaf and refined vertices (others copied), 1: the
+// same from zero, 2: residual (zero off that set; partial: per-tile sums of
+// squares over the leaves).
+template <typename T, typename TO>
+void launch_ad_stencil(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
+                       const Store& A, T omega, double* partial, hipStream_t s);
+template <typename T>
+void launch_ad_hang(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, hipStream_t s);
+template <typename T>
+void launch_ad_inject(const AdTiles& tc, const Lat& Lf, const T* uf, T* uc, hipStream_t s);
+template <typename T>
+void launch_ad_fas_rhs(const AdTiles& tc, const Lat& Lf, const T* rf, const T* uc, const T* epsc,
+                       const Store& Ac, T* bc, hipStream_t s);
+template <typename T>
+void launch_ad_correct(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const T* sc, hipStream_t s);
+template <typename T>
+void launch_ad_copy(const AdTiles& t, const T* src, T* dst, hipStream_t s);
+template <typename T>
+void launch_ad_zero(const AdTiles& t, T* p, hipStream_t s);
+void launch_ad_axpy(const AdTiles& t, double* x, const float* e, hipStream_t s);
+void launch_ad_coarsen_eps(const Lat& Lf, const Lat& Lc, const int8_t* cref, const double* ef, double* ec,
+                           hipStream_t s);
+void launch_ad_merge_rows(const Lat& L, const int8_t* vt, const double* eps, double* A, hipStream_t s);
+template <typename T>
+void launch_ad_scatter(const int64_t* slots, int64_t n, const double* in, double scale, T* lat, hipStream_t s);
+template <typename T>
+void launch_ad_gather(const int64_t* slots, int64_t n, const T* lat, double* out, hipStream_t s);
 
 // ---- solve loop as a state machine (api.cpp); used by the server ----
 struct SolveState {

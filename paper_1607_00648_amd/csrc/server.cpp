@@ -247,6 +247,8 @@ int qmg_server_submit(qmg_server_t* s, const qmg_grid_desc* desc, const qmg_solv
   return sguard(s, [&] {
     if (!s || !desc || !opts || !eps || !f || !ticket) throw ApiError(QMG_EINVAL, "null argument");
     if (!(rel_tol >= 0.0) || max_cycles < 0) throw ApiError(QMG_EINVAL, "bad tolerance or cycle limit");
+    if (desc->base_level != 0 && desc->base_level != desc->max_level)
+      throw ApiError(QMG_EINVAL, "the server takes regular grids");
     size_t bytes = 0;
     const int rc = qmg_workspace_bytes(desc, opts, &bytes);
     if (rc != QMG_OK) throw ApiError(rc, qmg_last_error(nullptr));

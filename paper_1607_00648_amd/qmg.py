@@ -30,7 +30,8 @@ STORES = {"plain64": PLAIN_FP64, "hier64": HIER_FP64, "hier32": HIER_FP32,
 
 
 class GridDesc(C.Structure):
-    _fields_ = [("dim", C.c_int), ("max_level", C.c_int)]
+    _fields_ = [("dim", C.c_int), ("max_level", C.c_int), ("base_level", C.c_int),
+                ("refine", C.c_void_p)]
 
 
 class SolverOpts(C.Structure):
@@ -66,7 +67,8 @@ _SIGS = {
     "qmg_create_grid": (C.c_int, [C.POINTER(GridDesc), C.POINTER(SolverOpts), C.c_void_p, C.c_size_t,
                                   C.c_void_p, C.POINTER(C.c_void_p)]),
     "qmg_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
-    "qmg_unknown_coords": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "qmg_unknown_coords": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "qmg_leaf_cell_centres": (C.c_int, [C.c_void_p, C.c_void_p]),
     "qmg_set_coefficients": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
     "qmg_build_operators": (C.c_int, [C.c_void_p, C.POINTER(SolveReport)]),
     "qmg_vcycle": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
@@ -133,19 +135,39 @@ def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_l
     return o
 
 
+def pack_refine(dim: int, base: int, level: int, flags) -> np.ndarray:
+    """Refinement flags of levels base..level-1 as the library's byte array
+    (``flags[l]``: array of shape (3^l,)*dim over the cells of level l, NumPy
+    axes (z,) y, x; missing levels mean no refinement)."""
+    parts = []
+    for l in range(base, level):
+        shape = (3 ** l,) * dim
+        a = np.asarray(flags.get(l, np.zeros(shape, bool)))
+        if a.shape != shape:
+            raise ValueError(f"refinement flags of level {l} must have shape {shape}")
+        parts.append(np.ascontiguousarray(a != 0, dtype=np.uint8).ravel())
+    return np.ascontiguousarray(np.concatenate(parts))
+
+
 class Grid:
-    """One regular grid of the unit square/cube with its operators and iterates.
+    """One grid of the unit square/cube (regular, or an adaptive spacetree when
+    ``base_level`` and ``refine`` are given) with its operators and iterates.
 
     The workspace is a torch uint8 CUDA tensor owned by this object; work runs on
     ``stream`` (a torch.cuda.Stream, default: the current stream)."""
 
     def __init__(self, dim: int, level: int, opts: Optional[SolverOpts] = None, stream=None,
-                 device: str = "cuda"):
+                 device: str = "cuda", base_level: Optional[int] = None, refine=None):
         import torch
         self.lib = load()
         self.dim, self.level = int(dim), int(level)
         self.opts = opts if opts is not None else make_opts()
         self.desc = GridDesc(self.dim, self.level)
+        self.adaptive = base_level is not None and int(base_level) not in (0, self.level)
+        if self.adaptive:
+            self._refine = pack_refine(self.dim, int(base_level), self.level, refine or {})
+            self.desc.base_level = int(base_level)
+            self.desc.refine = self._refine.ctypes.data_as(C.c_void_p)
         nbytes = C.c_size_t(0)
         self._check(self.lib.qmg_workspace_bytes(C.byref(self.desc), C.byref(self.opts), C.byref(nbytes)), None)
         self.workspace_bytes = int(nbytes.value)
@@ -156,9 +178,22 @@ class Grid:
                                              C.c_void_p(self._ws.data_ptr()), nbytes,
                                              C.c_void_p(self.stream.cuda_stream), C.byref(h)), None)
         self.h = h
-        n = 3 ** self.level
-        self.n = n
-        self.n_unknowns = (n - 1) ** self.dim
+        self.n = 3 ** self.level
+        nu, nc, nl = C.c_int64(0), C.c_int64(0), C.c_int(0)
+        self._check(self.lib.qmg_sizes(self.h, C.byref(nu), C.byref(nc), C.byref(nl)), self.h)
+        self.n_unknowns, self.n_cells = int(nu.value), int(nc.value)
+
+    def unknown_coords(self):
+        """(coordinates (n_unknowns, dim), level of each unknown)."""
+        xyz = np.zeros((self.n_unknowns, self.dim))
+        lev = np.zeros(self.n_unknowns, dtype=np.int8)
+        self._check(self.lib.qmg_unknown_coords(self.h, _ptr(xyz), _ptr(lev)), self.h)
+        return xyz, lev
+
+    def cell_centres(self):
+        xyz = np.zeros((self.n_cells, self.dim))
+        self._check(self.lib.qmg_leaf_cell_centres(self.h, _ptr(xyz)), self.h)
+        return xyz
 
     # -- errors --------------------------------------------------------------
     def _check(self, rc, h, allow=()):
@@ -172,8 +207,8 @@ class Grid:
     def set_coefficients(self, eps, f):
         eps = np.ascontiguousarray(eps, dtype=np.float64)
         f = np.ascontiguousarray(f, dtype=np.float64)
-        if eps.size != self.n ** self.dim or f.size != self.n_unknowns:
-            raise ValueError("eps must hold n^d values and f (n-1)^d values")
+        if eps.size != self.n_cells or f.size != self.n_unknowns:
+            raise ValueError(f"eps must hold {self.n_cells} values and f {self.n_unknowns}")
         self._check(self.lib.qmg_set_coefficients(self.h, _ptr(eps), 1, _ptr(f), QMG_HOST), self.h)
 
     def build(self) -> dict:

@@ -1,0 +1,239 @@
+"""Adaptive spacetrees on the GPU against the adaptive oracle: numbering of
+unknowns and leaf cells, the operators of every level, FAS V-cycle iterates
+and residual histories, and the composite fixed point."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adaptive as AD
+from gpu_util import announce, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(d, base, L, seed=0, r=0.2, n_balls=2):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0, 1, size=(n_balls, d))
+    flags = W.ball_flags(d, base, L, c, r)
+    G = AD.AdaptiveGrid(d, base, L, flags)
+    eps = rng.uniform(0.5, 2.0, size=len(G.leaf_cells()))
+    f = rng.uniform(-1.0, 1.0, size=G.n_unknowns())
+    return flags, G, eps, f
+
+
+def _grid(qmg, d, base, L, flags, transfer="galerkin", store="hier64", **kw):
+    return qmg.Grid(d, L, qmg.make_opts(transfer=transfer, store=store, **kw), base_level=base,
+                    refine=flags)
+
+
+@pytest.mark.parametrize("d,base,L", [(2, 2, 4), (2, 1, 5), (3, 1, 3)])
+def test_numbering_matches_oracle(d, base, L):
+    qmg = require_gpu()
+    announce(f"adaptive numbering d={d} base={base} L={L}")
+    flags, G, _, _ = _problem(d, base, L)
+    g = _grid(qmg, d, base, L, flags)
+    assert g.n_unknowns == G.n_unknowns()
+    assert g.n_cells == len(G.leaf_cells())
+    xyz, lev = g.unknown_coords()
+    np.testing.assert_allclose(xyz, G.unknown_coords(), rtol=0, atol=1e-14)
+    assert lev.tolist() == [l for l, _ in G.leaves()]
+    np.testing.assert_allclose(g.cell_centres(), G.cell_centres(), rtol=0, atol=1e-14)
+    g.close()
+
+
+@pytest.mark.parametrize("d,base,L,transfer", [(2, 2, 4, "galerkin"), (2, 1, 4, "galerkin"),
+                                               (3, 1, 3, "galerkin"), (2, 2, 4, "geometric")])
+def test_level_operators_match_oracle(d, base, L, transfer):
+    """Rows of leaf and refined vertices of every adaptive level (and the full
+    rows of the complete levels below) equal the oracle's stencils."""
+    qmg = require_gpu()
+    announce(f"adaptive operators d={d} base={base} L={L} {transfer}")
+    flags, G, eps, f = _problem(d, base, L)
+    H = AD.build_adaptive(G, eps, transfer=transfer)
+    g = _grid(qmg, d, base, L, flags, transfer=transfer)
+    g.set_coefficients(eps, f)
+    rep = g.build()
+    assert rep["coarsest_level_used"] == 1
+    for l in range(2, L + 1):
+        S_gpu = g.operator(l)
+        act = np.isin(G.vtype[l], (AD.LEAF, AD.REFINED))
+        ref = H.S[l]
+        scale = np.abs(ref).max()
+        diff = np.abs(S_gpu[:, act] - ref[:, act]).max()
+        assert diff <= 1e-13 * scale, (l, diff / scale)
+    g.close()
+
+
+CYCLE_CASES = [
+    (2, 2, 4, "galerkin", "hier64"),
+    (2, 2, 4, "geometric", "hier64"),
+    (2, 2, 4, "galerkin", "plain64"),
+    (2, 1, 5, "galerkin", "hier64"),
+    (3, 1, 3, "galerkin", "hier64"),
+    (3, 1, 3, "geometric", "plain64"),
+]
+
+
+@pytest.mark.parametrize("d,base,L,transfer,store", CYCLE_CASES)
+def test_fas_cycles_match_oracle(d, base, L, transfer, store):
+    """Iterates and residual histories of the first cycles agree with the
+    oracle's FAS V-cycle (same composite state after every cycle)."""
+    qmg = require_gpu()
+    announce(f"adaptive cycles d={d} base={base} L={L} {transfer} {store}")
+    flags, G, eps, f = _problem(d, base, L)
+    H = AD.build_adaptive(G, eps, transfer=transfer)
+    k = 6
+    u_o, hist_o = AD.solve_adaptive(H, f, cycles=k)
+    g = _grid(qmg, d, base, L, flags, transfer=transfer, store=store)
+    g.set_coefficients(eps, f)
+    g.build()
+    rr = g.vcycle(k)
+    u = g.solution()
+    np.testing.assert_allclose(rr, hist_o, rtol=1e-9, atol=1e-14)
+    assert np.abs(u - u_o).max() <= 1e-11 * np.abs(u_o).max()
+    g.close()
+
+
+@pytest.mark.parametrize("d,base,L,transfer", [(2, 2, 4, "galerkin"), (3, 1, 3, "galerkin"),
+                                               (2, 1, 5, "geometric")])
+def test_solve_reaches_composite_solution(d, base, L, transfer):
+    qmg = require_gpu()
+    announce(f"adaptive solve d={d} base={base} L={L} {transfer}")
+    flags, G, eps, f = _problem(d, base, L)
+    ustar, A, b = AD.solve_composite_direct(G, eps, f)
+    g = _grid(qmg, d, base, L, flags, transfer=transfer)
+    g.set_coefficients(eps, f)
+    g.build()
+    rep, hist = g.solve(tol=1e-11, max_cycles=200)
+    assert rep["status"] == "QMG_OK", rep
+    u = g.solution()
+    # the reported residual is the composite residual of the returned solution
+    rr = np.linalg.norm(b - A @ u) / np.linalg.norm(b)
+    assert rr <= 1e-11 * (1 + 1e-6)
+    assert abs(rr - rep["relres"]) <= 1e-14 + 1e-6 * rr
+    assert np.linalg.norm(u - ustar) <= 1e-9 * np.linalg.norm(ustar)
+    g.close()
+
+
+def test_warm_start_resumes_the_cycle():
+    """set_solution of the oracle's k-cycle iterate, then one GPU cycle, equals
+    k+1 oracle cycles."""
+    qmg = require_gpu()
+    d, base, L = 2, 2, 4
+    announce("adaptive warm start")
+    flags, G, eps, f = _problem(d, base, L)
+    H = AD.build_adaptive(G, eps, transfer="galerkin")
+    u3, _ = AD.solve_adaptive(H, f, cycles=3)
+    u4, h4 = AD.solve_adaptive(H, f, cycles=4)
+    g = _grid(qmg, d, base, L, flags)
+    g.set_coefficients(eps, f)
+    g.build()
+    g.set_solution(u3)
+    rr = g.vcycle(1)
+    np.testing.assert_allclose(rr[0], h4[-1], rtol=1e-9)
+    assert np.abs(g.solution() - u4).max() <= 1e-11 * np.abs(u4).max()
+    g.close()
+
+
+def test_no_refinement_equals_regular_grid():
+    """Flags that refine nothing beyond the base level give the regular grid of
+    the base level on the finest lattice (no adaptive level has a leaf)."""
+    qmg = require_gpu()
+    announce("adaptive without refinement")
+    d, base, L = 2, 3, 4
+    flags = {3: np.zeros((27, 27), bool)}
+    G = AD.AdaptiveGrid(d, base, L, flags)
+    rng = np.random.default_rng(5)
+    eps = rng.uniform(0.5, 2.0, size=len(G.leaf_cells()))
+    f = rng.uniform(-1, 1, size=G.n_unknowns())
+    ustar, A, b = AD.solve_composite_direct(G, eps, f)
+    g = _grid(qmg, d, base, L, flags)
+    assert g.n_unknowns == 26 * 26
+    g.set_coefficients(eps, f)
+    g.build()
+    rep, _ = g.solve(tol=1e-11, max_cycles=100)
+    assert rep["status"] == "QMG_OK"
+    assert np.linalg.norm(g.solution() - ustar) <= 1e-9 * np.linalg.norm(ustar)
+    g.close()
+
+
+def test_adaptive_rejected_by_server_and_boxmg():
+    qmg = require_gpu()
+    flags, G, eps, f = _problem(2, 2, 4)
+    with pytest.raises(qmg.QmgError):
+        _grid(qmg, 2, 2, 4, flags, transfer="boxmg")
+    with pytest.raises(qmg.QmgError):
+        _grid(qmg, 2, 2, 4, flags, store="bf16")
+
+
+def _workload_inputs(P, G):
+    eps = P.eps_at(G.cell_centres())
+    X = G.unknown_coords()
+    levels = np.concatenate([np.full(int((G.vtype[l] == AD.LEAF).sum()), l)
+                             for l in range(G.base, G.L + 1)])
+    f = np.empty(len(X))
+    for l in range(G.base, G.L + 1):
+        m = levels == l
+        f[m] = P.f_at(l, X[m])
+    return eps, f
+
+
+def test_balls_midsize_cycles_match_oracle():
+    """The 3D four-ball workload (smooth log-normal eps) at base 2, level 4:
+    FAS cycle iterates against the oracle."""
+    qmg = require_gpu()
+    announce("adaptive balls 3D base2 L4 cycles")
+    P = W.adaptive_balls(dim=3, base=2, level=4)
+    G = AD.AdaptiveGrid(P.dim, P.base, P.level, P.flags)
+    eps, f = _workload_inputs(P, G)
+    H = AD.build_adaptive(G, eps, transfer="galerkin")
+    k = 4
+    u_o, hist_o = AD.solve_adaptive(H, f, cycles=k)
+    g = _grid(qmg, 3, P.base, P.level, P.flags)
+    g.set_coefficients(eps, f)
+    g.build()
+    rr = g.vcycle(k)
+    u = g.solution()
+    np.testing.assert_allclose(rr, hist_o, rtol=1e-9)
+    assert np.abs(u - u_o).max() <= 1e-11 * np.abs(u_o).max()
+    g.close()
+
+
+def test_balls_full_size_solve_sampled_rows():
+    """The 3D four-ball workload at full size (base 3, level 5, about 1.3e6
+    unknowns): the GPU reaches 1e-8 and the composite residual of its solution,
+    assembled row by row by the oracle at sampled unknowns of every level,
+    agrees with that."""
+    qmg = require_gpu()
+    announce("adaptive balls 3D base3 L5 full size")
+    P = W.adaptive_balls()
+    G = AD.AdaptiveGrid(P.dim, P.base, P.level, P.flags)
+    eps, f = _workload_inputs(P, G)
+    # 3D Galerkin coarse stencils of a variable scalar eps carry small positive
+    # face entries: SPD, but not diagonally dominant, so the check would raise
+    # the coarsest level to the base level (Jacobi there); it is off here, as
+    # in the oracle's adaptive hierarchy
+    g = _grid(qmg, 3, P.base, P.level, P.flags, check_definite=False)
+    assert g.n_unknowns == G.n_unknowns()
+    g.set_coefficients(eps, f)
+    info = g.build()
+    assert info["coarsest_level_used"] == 1
+    rep, hist = g.solve(tol=1e-8, max_cycles=100)
+    assert rep["status"] == "QMG_OK", rep
+    u = g.solution()
+    levels = np.concatenate([np.full(int((G.vtype[l] == AD.LEAF).sum()), l)
+                             for l in range(G.base, G.L + 1)])
+    b = f * (3.0 ** -levels.astype(float)) ** 3
+    nb = np.linalg.norm(b)
+    rng = np.random.default_rng(11)
+    sample = np.concatenate([rng.choice(np.flatnonzero(levels == l), 100, replace=False)
+                             for l in range(G.base, G.L + 1)])
+    r = AD.composite_residual_rows(G, eps, f, u, sample)
+    assert np.abs(r).max() <= 1e-8 * nb * (1 + 1e-6)
+    # the sampled rows estimate the full residual norm (level-stratified)
+    est = 0.0
+    for l in range(G.base, G.L + 1):
+        m = levels[sample] == l
+        est += (levels == l).sum() * np.mean(r[m] ** 2)
+    assert np.sqrt(est) <= 10 * rep["relres"] * nb
+    g.close()

@@ -50,3 +50,28 @@ def test_oracle_not_imported_by_product():
             if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_adaptive_description_validation():
+    """Adaptive spacetrees are linearised on the host when the workspace is
+    measured; unsupported option combinations are rejected there."""
+    import numpy as np
+    from paper_1607_00648_amd import qmg
+    lib = qmg.load()
+    flags = {2: np.zeros((9, 9), bool), 3: np.zeros((27, 27), bool)}
+    flags[2][3:6, 3:6] = True
+    flags[3][12:15, 12:15] = True
+    packed = qmg.pack_refine(2, 2, 4, flags)
+    assert packed.size == 81 + 729 and packed.sum() == 18
+    d = qmg.GridDesc(2, 4, 2, packed.ctypes.data_as(C.c_void_p))
+    nb = C.c_size_t(0)
+    ok = qmg.make_opts(transfer="galerkin")
+    assert lib.qmg_workspace_bytes(C.byref(d), C.byref(ok), C.byref(nb)) == qmg.QMG_OK
+    assert nb.value > 0
+    for bad in (qmg.make_opts(transfer="boxmg"), qmg.make_opts(transfer="galerkin", store="bf16"),
+                qmg.make_opts(transfer="galerkin", coarsest_level=3)):
+        assert lib.qmg_workspace_bytes(C.byref(d), C.byref(bad), C.byref(nb)) == qmg.QMG_EINVAL
+    no_flags = qmg.GridDesc(2, 4, 2, None)
+    assert lib.qmg_workspace_bytes(C.byref(no_flags), C.byref(ok), C.byref(nb)) == qmg.QMG_EINVAL
+    with pytest.raises(ValueError):
+        qmg.pack_refine(2, 2, 4, {2: np.zeros((8, 8), bool)})

@@ -108,3 +108,16 @@ def test_adaptive_manufactured_solution_improves_with_refinement():
         u, _, _ = AD.solve_composite_direct(G, np.ones(len(G.leaf_cells())), f)
         errs.append(np.max(np.abs(u - np.prod(np.sin(np.pi * X), axis=1))))
     assert 7.5 <= errs[0] / errs[1] <= 10.5
+
+
+@pytest.mark.parametrize("d,base,L", [(2, 2, 4), (3, 1, 3)])
+def test_residual_rows_assembled_one_by_one(d, base, L):
+    """Rows evaluated on their own from element matrices equal the rows of the
+    assembled composite system (so they can stand in for it on large grids)."""
+    G, eps, f = _problem(d, base, L, seed=3)
+    A, b = AD.composite_system(G, eps, f)
+    u = np.random.default_rng(4).uniform(-1, 1, size=G.n_unknowns())
+    sample = np.arange(0, G.n_unknowns(), 7)
+    rows = AD.composite_residual_rows(G, eps, f, u, sample)
+    ref = (b - A @ u)[sample]
+    np.testing.assert_allclose(rows, ref, rtol=0, atol=1e-13 * np.abs(ref).max())

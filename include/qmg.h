@@ -112,6 +112,12 @@ typedef struct {
   int check_definite;  /* 1: raise the coarsest level when a Galerkin row is
                           not positive / diagonally dominant (Sect. 3.3)      */
   int inner_cycles;    /* FP32 V-cycles per FP64 outer iteration (>= 1)     */
+  int use_graphs;      /* 1: each cycle (+ residual norm) is captured once as
+                          a HIP graph and replayed (one host call per cycle;
+                          pays off when many grids share a host thread, as in
+                          the server); 0: eager kernel launches, which keep
+                          up with the device for one grid on its own.  Needs
+                          an even mu_pre + mu_post; ignored while profiling */
 } qmg_solver_opts;
 
 typedef struct {
@@ -132,7 +138,8 @@ const char* qmg_version(void);
 /* Device bytes a grid needs for `desc` and `opts` (worst case over stores). */
 int qmg_workspace_bytes(const qmg_grid_desc* desc, const qmg_solver_opts* opts, size_t* bytes);
 
-/* Default options: BoxMG, HIER_FP64, V(2,2), omega 0.6, lc 1, check on, 1 inner cycle. */
+/* Default options: BoxMG, HIER_FP64, V(2,2), omega 0.6, lc 1, check on, 1 inner
+ * cycle, graphs on. */
 int qmg_default_opts(qmg_solver_opts* opts);
 
 /* Creates a grid (Sect. 2: the levels 0..L of a tripartitioned spacetree,
@@ -158,8 +165,11 @@ int qmg_leaf_cell_centres(const qmg_grid_t* grid, double* xyz);
 
 /* Sets the coefficient eps (one value per leaf cell, > 0 and finite; ncomp
  * must be 1) and the source f (one value per unknown); the right-hand side of
- * an unknown on level l is b = h_l^d f (lumped).  Resets the solution to zero
- * and invalidates operators. */
+ * an unknown on level l is b = h_l^d f (lumped).  `mem` says where eps and f
+ * live (QMG_HOST or QMG_DEVICE); device inputs never leave the device (they
+ * are checked and scattered there).  Resets the solution to zero and
+ * invalidates operators.  QMG_EINVAL for values out of range; the grid then
+ * holds no coefficients until a call succeeds. */
 int qmg_set_coefficients(qmg_grid_t* grid, const double* eps, int ncomp, const double* f, int mem);
 
 /* Builds all coarse operators (Sect. 3.3, 3.4): BoxMG P, Galerkin RAP with the
@@ -186,10 +196,12 @@ int qmg_solve(qmg_grid_t* grid, double rel_tol, int max_cycles, double* history,
 int qmg_get_solution(const qmg_grid_t* grid, double* u, int mem);
 int qmg_set_solution(qmg_grid_t* grid, const double* u, int mem);
 
-/* Measurement: when enabled, every smoothing launch on the finest level is
- * bracketed by HIP events on the grid's stream (a few microseconds of
- * overhead per launch).  profile_read returns the number of timed launches and
- * their summed device time in milliseconds since the last read, then resets. */
+/* Measurement: with on = k > 0, every k-th smoothing launch on the finest
+ * level (2D: the pre-smoothing pass of two sweeps and the residual; 3D: each
+ * sweep) carries per-dispatch HIP event timestamps on the grid's stream
+ * (cycles then run as eager launches); on = 0 turns it off.  profile_read returns the
+ * number of timed launches and their summed device time in milliseconds since
+ * the last read, then resets. */
 int qmg_profile_enable(qmg_grid_t* grid, int on);
 int qmg_profile_read(qmg_grid_t* grid, int64_t* launches, double* total_ms);
 

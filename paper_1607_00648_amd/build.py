@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libqmg.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "server.cpp", "kernels_level.hip", "kernels_build.hip", "kernels_fused.hip", "kernels_adaptive.hip"]
+SOURCES = ["api.cpp", "server.cpp", "kernels_level.hip", "kernels_build.hip", "kernels_fused.hip",
+           "kernels_adaptive.hip", "kernels_pass.hip"]
 ARCH = os.environ.get("QMG_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -110,6 +110,7 @@ struct qmg_grid {
   double* bfin = nullptr;   // mixed: FP64 right-hand side on the finest level
   double* stage = nullptr;  // packed IO staging (nslot of the finest level)
   double* partial = nullptr;
+  int npart = 0;  // entries of `partial`
   double* dscal = nullptr;
   int* dcount = nullptr;
   int32_t* dtotal = nullptr;
@@ -150,7 +151,8 @@ struct qmg_grid {
   hipGraphExec_t gexec = nullptr;
   bool own_stream = false;
   // optional HIP-event timing of every finest-level smoothing launch
-  bool prof_on = false;
+  int prof_every = 0;       // time every k-th finest-level sweep (0: off)
+  int64_t prof_count = 0;   // finest-level sweeps since profiling was enabled
   std::vector<hipEvent_t> prof_ev;  // start/stop pairs
   size_t prof_used = 0;
   int64_t prof_launches = 0;
@@ -362,7 +364,8 @@ void layout(qmg_grid_t* g, Arena& a) {
     g->bfin = a.take<double>(g->lv[L].L.nslot);
   }
   g->stage = a.take<double>(g->lv[L].L.nslot);
-  g->partial = a.take<double>(std::max<int64_t>(npartials(g->lv[L].L), ad_partials));
+  g->npart = (int)std::max<int64_t>(npartials(g->lv[L].L), ad_partials);
+  g->partial = a.take<double>(g->npart);
   g->dscal = a.take<double>(8);
   g->dcount = a.take<int>(8);
   g->dtotal = a.take<int32_t>(2 * (L + 1));
@@ -460,9 +463,10 @@ hipEvent_t* prof_pair(qmg_grid_t* g) {
 template <typename T>
 void smooth(qmg_grid_t* g, LevelBuf& B, int sweeps, bool zero_init) {
   const T om = (T)g->opts.omega;
-  const bool timed = g->prof_on && B.L.n == g->lv[g->Lmax].L.n;
+  const bool finest = g->prof_every > 0 && B.L.n == g->lv[g->Lmax].L.n;
   for (int k = 0; k < sweeps; ++k) {
     const int mode = (k == 0 && zero_init) ? 1 : 0;
+    const bool timed = finest && (g->prof_count++ % g->prof_every) == 0;
     hipEvent_t* ev = timed ? prof_pair(g) : nullptr;
     launch_stencil<T>(B.L, mode, (const T*)B.u, (const T*)B.b, (T*)B.t, eps_of<T>(B), B.A, om,
                       nullptr, nullptr, S(g), ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
@@ -524,27 +528,78 @@ void fused_coarse(qmg_grid_t* g) {
   launch_fused_coarse<T>(g->d, a, g->lv[g->lf].A.src, psrc, g->fmt, S(g));
 }
 
+// Smoothing of a regular 2D level as fused passes of at most two sweeps each
+// (kernels_pass.hip): the first pass may start with the prolongation-add from
+// C or from a zero iterate, the last may end with the residual (into B.r, and
+// norm partials when `partial` is given).
+template <typename T>
+void passes(qmg_grid_t* g, LevelBuf& B, const LevelBuf* C, int sweeps, bool zero_init, bool residual,
+            double* partial) {
+  const bool finest = g->prof_every > 0 && B.L.n == g->lv[g->Lmax].L.n && C == nullptr;
+  int left = sweeps;
+  bool first = true;
+  while (left > 0) {
+    const int k = std::min(left, 2);
+    const bool last = left == k;
+    PassArgs<T> p;
+    p.L = B.L;
+    if (C) p.Lc = C->L;
+    p.u = (const T*)B.u;
+    p.out = (T*)B.t;
+    p.b = (const T*)B.b;
+    p.r = (T*)B.r;
+    p.eps = eps_of<T>(B);
+    p.ec = C ? (const T*)C->u : nullptr;
+    p.A = B.A;
+    p.P = B.P;
+    p.omega = (T)g->opts.omega;
+    p.pro = (first && C) ? 1 : 0;
+    p.nsw = k;
+    p.res = (last && residual) ? 1 : 0;
+    p.zero_first = (first && zero_init) ? 1 : 0;
+    p.partial = last ? partial : nullptr;
+    const bool timed = finest && first && (g->prof_count++ % g->prof_every) == 0;
+    hipEvent_t* ev = timed ? prof_pair(g) : nullptr;
+    launch_pass2d<T>(p, S(g), ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
+    std::swap(B.u, B.t);
+    left -= k;
+    first = false;
+  }
+}
+
 template <typename T>
 void vcycle_ad(qmg_grid_t* g, int l);
 
+// One V-cycle from level l.  With want_norm on the finest regular 2D level,
+// the last post-smoothing pass also leaves the residual norm partials of the
+// new iterate in g->partial (returns true).
 template <typename T>
-void vcycle(qmg_grid_t* g, int l, bool zero_init) {
+bool vcycle(qmg_grid_t* g, int l, bool zero_init, bool want_norm = false) {
   if (l > g->lb) {
     vcycle_ad<T>(g, l);
-    return;
+    return false;
   }
   LevelBuf& F = g->lv[l];
   const int mu = g->opts.mu_pre, nu = g->opts.mu_post;
   if (l == g->lf && l < g->Lmax && zero_init) {
     fused_coarse<T>(g);
-    return;
+    return false;
   }
   if (l == g->lc) {
     if (g->coarse_direct)
       launch_coarse_solve<T>(F.L, g->Ainv, g->nc, (const T*)F.b, (T*)F.u, S(g));
     else
       smooth<T>(g, F, mu + nu, zero_init);
-    return;
+    return false;
+  }
+  LevelBuf& Cb = g->lv[l - 1];
+  if (g->d == 2) {
+    passes<T>(g, F, nullptr, mu, zero_init, true, nullptr);
+    launch_restrict<T>(F.L, Cb.L, (const T*)F.r, (T*)Cb.b, F.P, S(g));
+    vcycle<T>(g, l - 1, true);
+    const bool norm = want_norm && l == g->Lmax;
+    passes<T>(g, F, &Cb, nu, false, norm, norm ? g->partial : nullptr);
+    return norm;
   }
   smooth<T>(g, F, mu, zero_init);
   launch_stencil<T>(F.L, 2, (const T*)F.u, (const T*)F.b, (T*)F.r, eps_of<T>(F), F.A, (T)0, nullptr,
@@ -554,6 +609,7 @@ void vcycle(qmg_grid_t* g, int l, bool zero_init) {
   vcycle<T>(g, l - 1, true);
   launch_prolong<T>(F.L, C.L, (const T*)C.u, (T*)F.u, F.P, S(g));
   smooth<T>(g, F, nu, false);
+  return false;
 }
 
 // Smoothing sweeps of an adaptive level over its leaf and refined vertices.
@@ -619,10 +675,12 @@ double read_scalar(qmg_grid_t* g) {
 // is written to the finest inner right-hand side on the way).
 // On an adaptive spacetree: the composite residual over the leaves of every
 // level, after the refined and hanging values are made consistent.
-void enqueue_residual_norm(qmg_grid_t* g, bool record) {
+void enqueue_residual_norm(qmg_grid_t* g, bool record, bool partials_ready = false) {
   LevelBuf& F = g->lv[g->Lmax];
   int np = 0;
-  if (g->adaptive) {
+  if (partials_ready) {  // left by the cycle's last fused pass
+    np = pass2d_partials(F.L);
+  } else if (g->adaptive) {
     composite_state(g);
     for (int l = g->lb; l <= g->Lmax; ++l) {
       LevelBuf& B = g->lv[l];
@@ -649,13 +707,18 @@ double finest_residual_norm(qmg_grid_t* g) {
 
 // One "cycle" of the public API: a V-cycle (FP64) or an outer defect-correction
 // iteration with inner FP32 V-cycles (the residual has been formed already).
-void one_cycle(qmg_grid_t* g) {
-  if (!g->mixed) {
-    vcycle<double>(g, g->Lmax, false);
-    return;
-  }
+// Returns true when the cycle left the finest residual norm partials.
+bool one_cycle(qmg_grid_t* g) {
+  if (!g->mixed) return vcycle<double>(g, g->Lmax, false, true);
   for (int m = 0; m < g->opts.inner_cycles; ++m) vcycle<float>(g, g->Lmax, m == 0);
   launch_axpy_mixed(g->lv[g->Lmax].L, g->x64, (const float*)g->lv[g->Lmax].u, S(g));
+  return false;
+}
+
+// one cycle followed by the recorded residual norm
+void cycle_and_norm(qmg_grid_t* g) {
+  const bool ready = one_cycle(g);
+  enqueue_residual_norm(g, true, ready);
 }
 
 void drop_graph(qmg_grid_t* g) {
@@ -666,10 +729,10 @@ void drop_graph(qmg_grid_t* g) {
 // Replaying one captured cycle needs every level to end a cycle in the buffer
 // it started from, i.e. an even number of sweeps per level.
 bool graph_usable(const qmg_grid_t* g) {
-  if (g->prof_on) return false;
-  if ((g->opts.mu_pre + g->opts.mu_post) % 2 != 0) return false;
-  const char* e = std::getenv("QMG_NO_GRAPH");
-  return !(e && e[0] == '1');
+  if (g->prof_every > 0 || !g->opts.use_graphs) return false;
+  const int mu = g->opts.mu_pre, nu = g->opts.mu_post;
+  // single sweeps (3D, coarsest level) and fused passes of two (2D)
+  return (mu + nu) % 2 == 0 && ((mu + 1) / 2 + (nu + 1) / 2) % 2 == 0;
 }
 
 void ensure_graph(qmg_grid_t* g) {
@@ -677,8 +740,7 @@ void ensure_graph(qmg_grid_t* g) {
   hipGraph_t graph = nullptr;
   QMG_HIP(hipStreamBeginCapture(S(g), hipStreamCaptureModeThreadLocal));
   try {
-    one_cycle(g);
-    enqueue_residual_norm(g, true);
+    cycle_and_norm(g);
   } catch (...) {
     hipGraph_t dummy = nullptr;
     (void)hipStreamEndCapture(S(g), &dummy);
@@ -704,10 +766,7 @@ void enqueue_batch(qmg_grid_t* g, int B) {
     ensure_graph(g);
     for (int c = 0; c < B; ++c) QMG_HIP(hipGraphLaunch(g->gexec, S(g)));
   } else {
-    for (int c = 0; c < B; ++c) {
-      one_cycle(g);
-      enqueue_residual_norm(g, true);
-    }
+    for (int c = 0; c < B; ++c) cycle_and_norm(g);
   }
   QMG_HIP(hipMemcpyAsync(g->hnorm, g->dhist, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, S(g)));
   QMG_HIP(hipEventRecord(g->bev, S(g)));
@@ -1172,6 +1231,7 @@ int qmg_default_opts(qmg_solver_opts* o) {
   o->coarsest_level = 1;
   o->check_definite = 1;
   o->inner_cycles = 1;
+  o->use_graphs = 1;
   return QMG_OK;
 }
 
@@ -1295,82 +1355,78 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
     if (!g || !eps || !f) throw ApiError(QMG_EINVAL, "null argument");
     if (ncomp != 1) throw ApiError(QMG_EINVAL, "only scalar coefficients (ncomp = 1) are supported");
     if (mem != QMG_HOST && mem != QMG_DEVICE) throw ApiError(QMG_EINVAL, "bad mem flag");
+    g->have_coef = false;
+    g->have_ops = false;
+    drop_graph(g);
     LevelBuf& F = g->lv[g->Lmax];
     const Lat& L = F.L;
     const int64_t ncell = g->adaptive ? g->n_cells : L.d == 3 ? (int64_t)L.n * L.n * L.n : (int64_t)L.n * L.n;
     const int64_t nu = g->n_unknowns;
-    std::vector<double> he, hf;
-    const double* pe = eps;
-    const double* pf = f;
-    if (mem == QMG_DEVICE) {
-      he.resize(ncell);
-      hf.resize(nu);
-      QMG_HIP(hipMemcpy(he.data(), eps, ncell * sizeof(double), hipMemcpyDeviceToHost));
-      QMG_HIP(hipMemcpy(hf.data(), f, nu * sizeof(double), hipMemcpyDeviceToHost));
-      pe = he.data();
-      pf = hf.data();
-    }
-    for (int64_t c = 0; c < ncell; ++c)
-      if (!(pe[c] > 0.0) || !std::isfinite(pe[c])) throw ApiError(QMG_EINVAL, "eps must be positive and finite");
-    std::vector<double> b(nu);
-    double s2 = 0.0;
-    {
-      int64_t r = 0;
-      for (int l = g->lb; l <= g->Lmax; ++l) {
-        double hd = 1.0;
-        for (int i = 0; i < g->d; ++i) hd *= g->lv[l].L.h;
-        const int64_t cnt = g->adaptive ? (int64_t)g->hl[l].leaf.size() : nu;
-        for (int64_t q = 0; q < cnt; ++q, ++r) {
-          if (!std::isfinite(pf[r])) throw ApiError(QMG_EINVAL, "f must be finite");
-          b[r] = hd * pf[r];
-          s2 += b[r] * b[r];
-        }
-      }
-    }
-    g->bnorm = std::sqrt(s2);
+    hipStream_t s = S(g);
+    auto blocks = [&](int64_t n, int share) {
+      return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, g->npart / share));
+    };
+    launch_zero<int>(g->dcount, 2, s);
+    // cell coefficients: staged, checked on the device, scattered per level
+    copy_in(g, g->stage, eps, ncell, mem);
+    launch_prep_input(g->stage, ncell, 1.0, true, g->partial, blocks(ncell, 1), g->dcount, s);
     if (g->adaptive) {
-      QMG_HIP(hipMemcpyAsync(g->stage, pe, ncell * sizeof(double), hipMemcpyHostToDevice, S(g)));
       int64_t co = 0;
       for (int l = g->lb; l <= g->Lmax; ++l) {
         LevelBuf& B = g->lv[l];
         const int64_t cnt = (int64_t)g->hl[l].cells.size();
-        launch_zero<double>(B.eps64, B.L.nslot, S(g));
-        launch_ad_scatter<double>(g->cell_slots + co, cnt, g->stage + co, 1.0, B.eps64, S(g));
+        launch_zero<double>(B.eps64, B.L.nslot, s);
+        launch_ad_scatter<double>(g->cell_slots + co, cnt, g->stage + co, 1.0, B.eps64, s);
         co += cnt;
       }
-      QMG_HIP(hipStreamSynchronize(S(g)));
-      QMG_HIP(hipMemcpyAsync(g->stage, b.data(), nu * sizeof(double), hipMemcpyHostToDevice, S(g)));
+    } else {
+      launch_scatter_cells<double>(L, g->stage, F.eps64, s);
+    }
+    // right-hand side b = h_l^d f of every unknown (level l), and its norm
+    copy_in(g, g->stage, f, nu, mem);
+    const int nlev = g->Lmax - g->lb + 1;
+    int np = 0;
+    int64_t off = 0;
+    for (int l = g->lb; l <= g->Lmax; ++l) {
+      double hd = 1.0;
+      for (int i = 0; i < g->d; ++i) hd *= g->lv[l].L.h;
+      const int64_t cnt = g->adaptive ? (int64_t)g->hl[l].leaf.size() : nu;
+      const int nb = blocks(cnt, nlev);
+      if (cnt > 0) {
+        launch_prep_input(g->stage + off, cnt, hd, false, g->partial + np, nb, g->dcount + 1, s);
+        np += nb;
+      }
+      off += cnt;
+    }
+    launch_sum_partials(g->partial, np, g->dscal, s);
+    if (g->adaptive) {
       int64_t uo = 0;
       for (int l = g->lcq; l <= g->Lmax; ++l) {
         LevelBuf& B = g->lv[l];
-        launch_zero<double>((double*)B.u, B.L.nslot, S(g));
-        launch_zero<double>((double*)B.t, B.L.nslot, S(g));
-        launch_zero<double>((double*)B.b, B.L.nslot, S(g));
+        launch_zero<double>((double*)B.u, B.L.nslot, s);
+        launch_zero<double>((double*)B.t, B.L.nslot, s);
+        launch_zero<double>((double*)B.b, B.L.nslot, s);
         if (l < g->lb) continue;
         const int64_t cnt = (int64_t)g->hl[l].leaf.size();
-        launch_ad_scatter<double>(g->unk_slots + uo, cnt, g->stage + uo, 1.0, (double*)B.b, S(g));
+        launch_ad_scatter<double>(g->unk_slots + uo, cnt, g->stage + uo, 1.0, (double*)B.b, s);
         uo += cnt;
       }
-      QMG_HIP(hipStreamSynchronize(S(g)));
-      g->have_coef = true;
-      g->have_ops = false;
-      drop_graph(g);
-      return;
-    }
-    QMG_HIP(hipMemcpyAsync(g->stage, pe, ncell * sizeof(double), hipMemcpyHostToDevice, S(g)));
-    launch_scatter_cells<double>(L, g->stage, F.eps64, S(g));
-    QMG_HIP(hipMemcpyAsync(g->stage, b.data(), nu * sizeof(double), hipMemcpyHostToDevice, S(g)));
-    if (g->mixed) {
-      launch_scatter_unknowns<double>(L, g->stage, g->bfin, S(g));
-      launch_zero<double>(g->x64, L.nslot, S(g));
+    } else if (g->mixed) {
+      launch_scatter_unknowns<double>(L, g->stage, g->bfin, s);
+      launch_zero<double>(g->x64, L.nslot, s);
     } else {
-      launch_scatter_unknowns<double>(L, g->stage, (double*)F.b, S(g));
-      launch_zero<double>((double*)F.u, L.nslot, S(g));
+      launch_scatter_unknowns<double>(L, g->stage, (double*)F.b, s);
+      launch_zero<double>((double*)F.u, L.nslot, s);
     }
-    QMG_HIP(hipStreamSynchronize(S(g)));
+    int bad[2] = {0, 0};
+    double b2 = 0.0;
+    QMG_HIP(hipMemcpyAsync(bad, g->dcount, sizeof(bad), hipMemcpyDeviceToHost, s));
+    QMG_HIP(hipMemcpyAsync(&b2, g->dscal, sizeof(double), hipMemcpyDeviceToHost, s));
+    QMG_HIP(hipStreamSynchronize(s));
+    if (bad[0] > 0) throw ApiError(QMG_EINVAL, "eps must be positive and finite");
+    if (bad[1] > 0) throw ApiError(QMG_EINVAL, "f must be finite");
+    g->bnorm = std::sqrt(b2);
     g->have_coef = true;
-    g->have_ops = false;
-    drop_graph(g);
   });
 }
 
@@ -1464,8 +1520,10 @@ int qmg_set_solution(qmg_grid_t* g, const double* u, int mem) {
 int qmg_profile_enable(qmg_grid_t* g, int on) {
   return guard(g, [&] {
     if (!g) throw ApiError(QMG_EINVAL, "null grid");
+    if (on < 0) throw ApiError(QMG_EINVAL, "profile stride must be >= 0");
     prof_harvest(g);
-    g->prof_on = on != 0;
+    g->prof_every = on;
+    g->prof_count = 0;
     drop_graph(g);
   });
 }
@@ -1486,8 +1544,8 @@ int qmg_destroy_grid(qmg_grid_t* g) {
   int rc = QMG_OK;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   else (void)hipDeviceSynchronize();
-  for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
   drop_graph(g);
+  for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
   if (g->owns && g->base && hipFree(g->base) != hipSuccess) rc = QMG_EHIP;
   if (g->hnorm) (void)hipHostFree(g->hnorm);
   if (g->bev) (void)hipEventDestroy(g->bev);

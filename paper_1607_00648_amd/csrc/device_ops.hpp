@@ -133,6 +133,29 @@ __device__ inline void add_delta(const Store& st, int64_t v, T (&a)[NENT]) {
   }
 }
 
+// Tile of this workgroup.  Workgroups are dispatched round-robin over the 8
+// XCDs, each with its own L2; the dispatch index is remapped so that every XCD
+// walks one contiguous range of tiles (x tiles fastest, then rows, then
+// planes), and the halo rows a tile shares with the tile above or below are
+// mostly reread from the same L2.  t is the tile's linear index.
+struct Tile {
+  int x, y, z;
+  unsigned t;
+};
+__device__ inline Tile xcd_tile() {
+  constexpr unsigned kXcd = 8;
+  const unsigned nx = gridDim.x, ny = gridDim.y;
+  const unsigned N = nx * ny * gridDim.z;
+  const unsigned b = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+  const unsigned q = N / kXcd, r = N % kXcd, k = b % kXcd;
+  Tile T;
+  T.t = k * q + min(k, r) + b / kXcd;
+  T.x = (int)(T.t % nx);
+  T.y = (int)((T.t / nx) % ny);
+  T.z = (int)(T.t / (nx * ny));
+  return T;
+}
+
 // d-linear weight of the parent at floor(f/3) + kappa along one axis, r = f mod 3.
 __host__ __device__ constexpr double dlin1(int r, int kappa) {
   return kappa == 0 ? (r == 0 ? 1.0 : r == 1 ? 2.0 / 3.0 : 1.0 / 3.0)

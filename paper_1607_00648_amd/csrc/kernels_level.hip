@@ -41,9 +41,10 @@ __global__ __launch_bounds__(256) void k_stencil(Lat L, const T* __restrict__ u,
                                                  const T* __restrict__ eps, Store A, T omega,
                                                  double* __restrict__ partial) {
   constexpr int NS = Dim<D>::NS;
-  const int i = blockIdx.x * TX + threadIdx.x;
-  const int j = blockIdx.y * TY + threadIdx.y;
-  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * TX + threadIdx.x;
+  const int j = tl.y * TY + threadIdx.y;
+  const int kz = (D == 3) ? tl.z : 0;
   const int n = L.n;
   const bool act = i >= 1 && i < n && j >= 1 && j < n && (D == 2 || (kz >= 1 && kz < n));
   double sq = 0.0;
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(256) void k_stencil(Lat L, const T* __restrict__ u,
   if (partial != nullptr) {
     const double s = block_sum_256(sq);
     if (threadIdx.x == 0 && threadIdx.y == 0)
-      partial[blockIdx.x + gridDim.x * ((int64_t)blockIdx.y + gridDim.y * (int64_t)blockIdx.z)] = s;
+      partial[tl.t] = s;
   }
 }
 
@@ -98,9 +99,10 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict_
 template <int D, typename T, int SRC, int FMT>
 __global__ __launch_bounds__(256) void k_restrict(Lat Lf, Lat Lc, const T* __restrict__ r,
                                                   T* __restrict__ bc, Store P) {
-  const int I = blockIdx.x * TX + threadIdx.x;
-  const int J = blockIdx.y * TY + threadIdx.y;
-  const int K = (D == 3) ? (int)blockIdx.z : 0;
+  const Tile tl = xcd_tile();
+  const int I = tl.x * TX + threadIdx.x;
+  const int J = tl.y * TY + threadIdx.y;
+  const int K = (D == 3) ? tl.z : 0;
   const int nc = Lc.n;
   if (!(I >= 1 && I < nc && J >= 1 && J < nc && (D == 2 || (K >= 1 && K < nc)))) return;
   bc[I + (int64_t)J * Lc.pitch + (int64_t)K * Lc.plane] = restrict_at<D, T, SRC, FMT>(Lf, r, P, I, J, K);
@@ -110,9 +112,10 @@ __global__ __launch_bounds__(256) void k_restrict(Lat Lf, Lat Lc, const T* __res
 template <int D, typename T, int SRC, int FMT>
 __global__ __launch_bounds__(256) void k_prolong(Lat Lf, Lat Lc, const T* __restrict__ ec,
                                                  T* __restrict__ uf, Store P) {
-  const int i = blockIdx.x * TX + threadIdx.x;
-  const int j = blockIdx.y * TY + threadIdx.y;
-  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * TX + threadIdx.x;
+  const int j = tl.y * TY + threadIdx.y;
+  const int kz = (D == 3) ? tl.z : 0;
   const int n = Lf.n;
   if (!(i >= 1 && i < n && j >= 1 && j < n && (D == 2 || (kz >= 1 && kz < n)))) return;
   const int64_t vf = i + (int64_t)j * Lf.pitch + (int64_t)kz * Lf.plane;
@@ -169,6 +172,34 @@ __global__ void k_coarse_solve(Lat L, const double* __restrict__ Ainv, int nc,
   }
   const int i = row % m + 1, j = (row / m) % m + 1, k = (L.d == 3) ? row / (m * m) + 1 : 0;
   u[i + (int64_t)j * L.pitch + (int64_t)k * L.plane] = (T)acc;
+}
+
+// x *= scale over [0, n) (grid-stride); per-block sums of squares of the
+// scaled values; *bad counts entries that are not finite (or, with positive,
+// not > 0).
+__global__ __launch_bounds__(256) void k_prep_input(double* __restrict__ x, int64_t n, double scale, int positive,
+                                                    double* __restrict__ partial, int* __restrict__ bad) {
+  __shared__ double red[4];
+  double sq = 0.0;
+  int nbad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = x[i];
+    if (!isfinite(v) || (positive && !(v > 0.0))) ++nbad;
+    const double w = v * scale;
+    x[i] = w;
+    sq += w * w;
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    sq += __shfl_xor(sq, m, 64);
+    nbad += __shfl_xor(nbad, m, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = sq;
+    if (nbad) atomicAdd(bad, nbad);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 template <typename T>
@@ -267,6 +298,13 @@ void launch_residual_mixed(const Lat& L, const double* x, const double* b, float
     hipLaunchKernelGGL((k_stencil<2, double, float, SRC_GEOM, F64, 2>), g, bl, 0, s, L, x, b, r32, eps, none, 0.0, partial);
   else
     hipLaunchKernelGGL((k_stencil<3, double, float, SRC_GEOM, F64, 2>), g, bl, 0, s, L, x, b, r32, eps, none, 0.0, partial);
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_prep_input(double* x, int64_t n, double scale, bool positive, double* partial, int blocks, int* bad,
+                       hipStream_t s) {
+  if (n <= 0 || blocks <= 0) return;
+  hipLaunchKernelGGL(k_prep_input, dim3((unsigned)blocks), dim3(256), 0, s, x, n, scale, positive ? 1 : 0, partial, bad);
   QMG_HIP(hipGetLastError());
 }
 

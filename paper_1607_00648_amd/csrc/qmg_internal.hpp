@@ -106,6 +106,11 @@ void launch_residual_mixed(const Lat& L, const double* x, const double* b, float
 // Sum of `n` partials into out[0] in a fixed order (one workgroup).  With
 // `hist`, the sum is also stored at hist[*counter] (when below cap) and the
 // device counter advanced, so that replayed cycles keep a norm history.
+// Input staging: x *= scale in place (grid-stride over `blocks` blocks of 256),
+// per-block sums of squares of the scaled values into partial[0..blocks), and
+// a count of non-finite (or, with positive, non-positive) entries added to *bad.
+void launch_prep_input(double* x, int64_t n, double scale, bool positive, double* partial, int blocks, int* bad,
+                       hipStream_t s);
 void launch_sum_partials(const double* partial, int n, double* out, hipStream_t s,
                          double* hist = nullptr, int* counter = nullptr, int cap = 0);
 
@@ -197,6 +202,30 @@ void launch_fused_coarse(int d, const FusedArgs<T>& a, int asrc, int psrc, int f
 // Fill lattice array with zeros (kernel, not memset, so it can live in graphs).
 template <typename T>
 void launch_zero(T* p, int64_t n, hipStream_t s);
+
+// ---- fused smoothing passes of regular 2D levels (kernels_pass.hip) ----
+// One launch: optional prolongation-add u += P e (pro), nsw (1 or 2) damped
+// Jacobi sweeps from u (the first from zero when zero_first) into out, and an
+// optional residual r = b - A out (res) with per-tile norm partials (partial,
+// nullable; pass2d_partials(L) entries).
+template <typename T>
+struct PassArgs {
+  Lat L, Lc;
+  const T* u = nullptr;
+  T* out = nullptr;
+  const T* b = nullptr;
+  T* r = nullptr;
+  const T* eps = nullptr;
+  const T* ec = nullptr;
+  Store A, P;
+  T omega = (T)0;
+  int pro = 0, nsw = 1, res = 0, zero_first = 0;
+  double* partial = nullptr;
+};
+template <typename T>
+void launch_pass2d(const PassArgs<T>& p, hipStream_t s, hipEvent_t ev_start = nullptr,
+                   hipEvent_t ev_stop = nullptr);
+int pass2d_partials(const Lat& L);
 
 // ---- adaptive levels (kernels_adaptive.hip) ----
 enum VertexClass : int8_t { VT_OUT = 0, VT_LEAF = 1, VT_REFINED = 2, VT_HANGING = 3 };

@@ -37,7 +37,7 @@ class GridDesc(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("transfer", C.c_int), ("store", C.c_int), ("mu_pre", C.c_int),
                 ("mu_post", C.c_int), ("omega", C.c_double), ("coarsest_level", C.c_int),
-                ("check_definite", C.c_int), ("inner_cycles", C.c_int)]
+                ("check_definite", C.c_int), ("inner_cycles", C.c_int), ("use_graphs", C.c_int)]
 
 
 class SolveReport(C.Structure):
@@ -123,7 +123,7 @@ def _ptr(a: np.ndarray):
 
 
 def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_level=1,
-              check_definite=True, inner_cycles=1) -> SolverOpts:
+              check_definite=True, inner_cycles=1, graphs=True) -> SolverOpts:
     o = SolverOpts()
     o.transfer = TRANSFERS[transfer] if isinstance(transfer, str) else int(transfer)
     o.store = STORES[store] if isinstance(store, str) else int(store)
@@ -132,6 +132,7 @@ def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_l
     o.coarsest_level = int(coarsest_level)
     o.check_definite = 1 if check_definite else 0
     o.inner_cycles = int(inner_cycles)
+    o.use_graphs = 1 if graphs else 0
     return o
 
 
@@ -205,6 +206,18 @@ class Grid:
 
     # -- main path -----------------------------------------------------------
     def set_coefficients(self, eps, f):
+        """eps per leaf cell, f per unknown: NumPy arrays (host) or contiguous
+        float64 torch tensors on the grid's device (used in place)."""
+        if hasattr(eps, "data_ptr") and hasattr(f, "data_ptr"):
+            import torch
+            for t in (eps, f):
+                if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                    raise ValueError("device inputs must be contiguous float64 tensors on the GPU")
+            if eps.numel() != self.n_cells or f.numel() != self.n_unknowns:
+                raise ValueError(f"eps must hold {self.n_cells} values and f {self.n_unknowns}")
+            self._check(self.lib.qmg_set_coefficients(self.h, C.c_void_p(eps.data_ptr()), 1,
+                                                      C.c_void_p(f.data_ptr()), QMG_DEVICE), self.h)
+            return
         eps = np.ascontiguousarray(eps, dtype=np.float64)
         f = np.ascontiguousarray(f, dtype=np.float64)
         if eps.size != self.n_cells or f.size != self.n_unknowns:
@@ -239,8 +252,11 @@ class Grid:
         u = np.ascontiguousarray(u, dtype=np.float64)
         self._check(self.lib.qmg_set_solution(self.h, _ptr(u), QMG_HOST), self.h)
 
-    def profile(self, on: bool = True):
-        self._check(self.lib.qmg_profile_enable(self.h, 1 if on else 0), self.h)
+    def profile(self, every=1):
+        """Time every ``every``-th finest-level sweep with HIP events (0 or
+        False: off; True: every sweep)."""
+        every = (1 if every else 0) if isinstance(every, bool) else int(every)
+        self._check(self.lib.qmg_profile_enable(self.h, every), self.h)
 
     def profile_read(self):
         n = C.c_int64(0)

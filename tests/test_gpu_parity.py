@@ -255,3 +255,57 @@ def test_raised_coarsest_level_and_errors():
     with pytest.raises(qmg.QmgError):
         g.set_coefficients(bad, np.zeros(26 * 26))
     g.close()
+
+
+def test_device_inputs_match_host_inputs():
+    """Coefficients handed over in device memory give bitwise the result of
+    the host hand-over; bad device values are rejected and leave the grid
+    without coefficients."""
+    import torch
+    qmg = require_gpu()
+    announce("device-resident inputs")
+    p = W.cfg2(0, level=4)
+    res = []
+    for dev in (False, True):
+        g = qmg.Grid(p.dim, p.level, qmg.make_opts())
+        if dev:
+            g.set_coefficients(torch.from_numpy(p.eps.ravel()).cuda(), torch.from_numpy(p.f.ravel()).cuda())
+        else:
+            g.set_coefficients(p.eps, p.f)
+        g.build()
+        rr = g.vcycle(4)
+        res.append((rr, g.solution()))
+        g.close()
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    g = qmg.Grid(p.dim, p.level, qmg.make_opts())
+    bad = torch.from_numpy(p.eps.ravel()).cuda()
+    bad[17] = float("nan")
+    with pytest.raises(qmg.QmgError):
+        g.set_coefficients(bad, torch.from_numpy(p.f.ravel()).cuda())
+    with pytest.raises(qmg.QmgError):      # no coefficients: build is refused
+        g.build()
+    g.close()
+
+
+def test_profiling_and_graphs_leave_results_unchanged():
+    """Event timing of the finest sweeps and graph replay of the cycles change
+    neither the iterates nor the residual history."""
+    qmg = require_gpu()
+    announce("profiling strides and graph replay")
+    p = W.cfg2(0, level=4)
+    out = []
+    for every, graphs in ((0, True), (0, False), (1, True), (3, False)):
+        g = qmg.Grid(p.dim, p.level, qmg.make_opts(graphs=graphs))
+        g.set_coefficients(p.eps, p.f)
+        g.profile(every)
+        g.build()
+        rep, hist = g.solve(1e-8, 200)
+        n, ms = g.profile_read()
+        if every:
+            assert n > 0 and ms > 0.0
+        else:
+            assert n == 0
+        out.append((hist, g.solution()))
+        g.close()
+    for hist, u in out[1:]:
+        assert np.array_equal(hist, out[0][0]) and np.array_equal(u, out[0][1])

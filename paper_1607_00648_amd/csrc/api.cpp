@@ -120,6 +120,8 @@ struct qmg_grid {
   bool coarse_direct = false;
   int lf = -1;  // top level of the fused single-workgroup coarse cycle (-1: none)
   bool lf_pw_lds = true;
+  char* fimg = nullptr;      // LDS image of the fused coarse levels (kFusedImgBytes)
+  bool fimg_ready = false;
   int64_t lds_max = 65536;  // LDS bytes one workgroup may use on this device
   double* tmpA[2] = {nullptr, nullptr};
   double* tmpP = nullptr;
@@ -369,6 +371,7 @@ void layout(qmg_grid_t* g, Arena& a) {
   g->dscal = a.take<double>(8);
   g->dcount = a.take<int>(8);
   g->dtotal = a.take<int32_t>(2 * (L + 1));
+  g->fimg = a.take<char>(kFusedImgBytes);
   g->dhist = a.take<double>(kHistCap);
   g->dctr = a.take<int>(64);
   int64_t cap = 0;
@@ -485,6 +488,7 @@ FusedArgs<T> fused_args(qmg_grid_t* g, int lf) {
   a.nc = g->nc;
   a.omega = (T)g->opts.omega;
   a.Ainv = g->Ainv;
+  a.img = g->fimg_ready ? g->fimg : nullptr;
   for (int l = g->lc; l <= lf; ++l) {
     LevelBuf& B = g->lv[l];
     const int s = l - g->lc;
@@ -518,6 +522,17 @@ int choose_fused_top(qmg_grid_t* g, bool& pw_lds) {
     }
   }
   return best;
+}
+
+// Decodes the fused levels' rows and weights once into the LDS image.
+template <typename T>
+void prepare_fused(qmg_grid_t* g) {
+  FusedArgs<T> a = fused_args<T>(g, g->lf);
+  if (fused_lds_layout<T>(g->d, a, p_stored(g), g->lf_pw_lds) > (size_t)kFusedImgBytes) return;
+  a.img = g->fimg;
+  const int psrc = g->lf > g->lc ? g->lv[g->lc + 1].P.src : SRC_GEOM;
+  launch_fused_prepare<T>(g->d, a, g->lv[g->lf].A.src, psrc, g->fmt, S(g));
+  g->fimg_ready = true;
 }
 
 template <typename T>
@@ -1042,6 +1057,11 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
       (void)hipGetLastError();
   }
   g->lf = g->mixed ? choose_fused_top<float>(g, g->lf_pw_lds) : choose_fused_top<double>(g, g->lf_pw_lds);
+  g->fimg_ready = false;
+  if (g->lf >= 0) {
+    if (g->mixed) prepare_fused<float>(g);
+    else prepare_fused<double>(g);
+  }
   g->have_ops = true;
   if (info) {
     std::memset(info, 0, sizeof(*info));

@@ -116,20 +116,28 @@ struct Dec<BF16> {
 };
 
 // Adds the stored delta of vertex v (nent entries) to a[] when its block is
-// non-zero.
+// non-zero.  The payload is read unconditionally (block 0 stands in for a zero
+// block; stores are allocated in full) and selected, so that the loads of
+// several vertices can be in flight together.
 template <int FMT, int NENT, typename T>
 __device__ inline void add_delta(const Store& st, int64_t v, T (&a)[NENT]) {
   const int32_t cb = st.blk[v / kSeg];
-  if (cb < 0) return;
+  const int64_t cbl = cb >= 0 ? cb : 0;
   const int lane = (int)(v % kSeg);
-  const int64_t base = (int64_t)cb * NENT * kSeg + lane;
+  const int64_t base = cbl * NENT * kSeg + lane;
   if (FMT == F16) {
-    const int e = st.scale[(int64_t)cb * kSeg + lane];
+    const int e = st.scale[cbl * kSeg + lane];
 #pragma unroll
-    for (int k = 0; k < NENT; ++k) a[k] += (T)ldexpf(Dec<FMT>::get(st.payload, base + (int64_t)k * kSeg), e);
+    for (int k = 0; k < NENT; ++k) {
+      const T dv = (T)ldexpf(Dec<FMT>::get(st.payload, base + (int64_t)k * kSeg), e);
+      a[k] = cb >= 0 ? a[k] + dv : a[k];
+    }
   } else {
 #pragma unroll
-    for (int k = 0; k < NENT; ++k) a[k] += (T)Dec<FMT>::get(st.payload, base + (int64_t)k * kSeg);
+    for (int k = 0; k < NENT; ++k) {
+      const T dv = (T)Dec<FMT>::get(st.payload, base + (int64_t)k * kSeg);
+      a[k] = cb >= 0 ? a[k] + dv : a[k];
+    }
   }
 }
 

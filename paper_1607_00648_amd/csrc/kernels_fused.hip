@@ -10,7 +10,9 @@
 // right-hand side and starts from zero) down to the coarsest level and back up:
 // every phase is a strided loop over a level's interior vertices followed by a
 // workgroup barrier.  Only the final iterate of level lf goes back to global
-// memory.
+// memory.  The operators do not change between cycles, so the rows and weights
+// are decoded once per build into an image of the LDS contents in global
+// memory; each launch copies that image in with 16-byte loads.
 #include "level_ops.hpp"
 
 namespace qmg {
@@ -63,7 +65,9 @@ struct Fused {
     return acc;
   }
 
-  __device__ void load() const {
+  // zero iterates, stencil rows and parent weights at the layout's offsets from
+  // `smem` (LDS, or the global image)
+  __device__ void build_static() const {
     for (int s = 0; s <= a.lf - a.lc; ++s) {
       const Lat& L = a.L[s];
       const int ws = w(s), ms = m(s);
@@ -85,6 +89,16 @@ struct Fused {
           for (int c = 0; c < NC; ++c) pd[c] = (T)pweight<D, PSRC, FMT>(a.P[s], L, v, rx, ry, rz, c);
         }
       }
+    }
+  }
+
+  __device__ void load() const {
+    if (a.img != nullptr) {
+      const uint4* src = (const uint4*)a.img;
+      uint4* dst = (uint4*)smem;
+      for (int q = threadIdx.x; q < a.lds_bytes / 16; q += BS) dst[q] = src[q];
+    } else {
+      build_static();
     }
     __syncthreads();
     // restricted right-hand side of the top level
@@ -229,8 +243,18 @@ __global__ __launch_bounds__(block_of<D>()) void k_fused_coarse(FusedArgs<T> a) 
   f.run();
 }
 
+template <int D, typename T, int ASRC, int PSRC, int FMT>
+__global__ __launch_bounds__(block_of<D>()) void k_fused_prepare(FusedArgs<T> a) {
+  Fused<D, T, ASRC, PSRC, FMT> f(a, a.img);
+  f.build_static();
+}
+
 template <int D, typename T, int AS, int PS, int F>
-void launch_one(const FusedArgs<T>& a, hipStream_t s) {
+void launch_one(const FusedArgs<T>& a, hipStream_t s, bool prepare) {
+  if (prepare) {
+    hipLaunchKernelGGL((k_fused_prepare<D, T, AS, PS, F>), dim3(1), dim3(block_of<D>()), 0, s, a);
+    return;
+  }
   static int attr_set = 0;  // opt in to LDS beyond the 64 KiB default (per kernel)
   if (a.lds_bytes > attr_set) {
     QMG_HIP(hipFuncSetAttribute((const void*)k_fused_coarse<D, T, AS, PS, F>,
@@ -241,18 +265,18 @@ void launch_one(const FusedArgs<T>& a, hipStream_t s) {
 }
 
 template <int D, typename T>
-void dispatch_fused(const FusedArgs<T>& a, int asrc, int psrc, int fmt, hipStream_t s) {
+void dispatch_fused(const FusedArgs<T>& a, int asrc, int psrc, int fmt, hipStream_t s, bool prep) {
   if (asrc == SRC_PLAIN) {
-    launch_one<D, T, SRC_PLAIN, SRC_PLAIN, F64>(a, s);
+    launch_one<D, T, SRC_PLAIN, SRC_PLAIN, F64>(a, s, prep);
   } else if (asrc == SRC_GEOM) {
-    launch_one<D, T, SRC_GEOM, SRC_GEOM, F64>(a, s);
+    launch_one<D, T, SRC_GEOM, SRC_GEOM, F64>(a, s, prep);
   } else {
     const bool ph = psrc == SRC_HIER;
     switch (fmt) {
-      case F64: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, F64>(a, s); else launch_one<D, T, SRC_HIER, SRC_GEOM, F64>(a, s); break;
-      case F32: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, F32>(a, s); else launch_one<D, T, SRC_HIER, SRC_GEOM, F32>(a, s); break;
-      case F16: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, F16>(a, s); else launch_one<D, T, SRC_HIER, SRC_GEOM, F16>(a, s); break;
-      default: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, BF16>(a, s); else launch_one<D, T, SRC_HIER, SRC_GEOM, BF16>(a, s); break;
+      case F64: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, F64>(a, s, prep); else launch_one<D, T, SRC_HIER, SRC_GEOM, F64>(a, s, prep); break;
+      case F32: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, F32>(a, s, prep); else launch_one<D, T, SRC_HIER, SRC_GEOM, F32>(a, s, prep); break;
+      case F16: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, F16>(a, s, prep); else launch_one<D, T, SRC_HIER, SRC_GEOM, F16>(a, s, prep); break;
+      default: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, BF16>(a, s, prep); else launch_one<D, T, SRC_HIER, SRC_GEOM, BF16>(a, s, prep); break;
     }
   }
   QMG_HIP(hipGetLastError());
@@ -289,10 +313,20 @@ template size_t fused_lds_layout<float>(int, FusedArgs<float>&, bool, bool);
 template <typename T>
 void launch_fused_coarse(int d, const FusedArgs<T>& a, int asrc, int psrc, int fmt, hipStream_t s) {
   if (a.lf - a.lc + 1 > kMaxFused) throw HipError("fused coarse cycle: too many levels");
-  if (d == 2) dispatch_fused<2, T>(a, asrc, psrc, fmt, s);
-  else dispatch_fused<3, T>(a, asrc, psrc, fmt, s);
+  if (a.img != nullptr && a.lds_bytes > kFusedImgBytes) throw HipError("fused coarse cycle: image too large");
+  if (d == 2) dispatch_fused<2, T>(a, asrc, psrc, fmt, s, false);
+  else dispatch_fused<3, T>(a, asrc, psrc, fmt, s, false);
 }
 template void launch_fused_coarse<double>(int, const FusedArgs<double>&, int, int, int, hipStream_t);
 template void launch_fused_coarse<float>(int, const FusedArgs<float>&, int, int, int, hipStream_t);
+
+template <typename T>
+void launch_fused_prepare(int d, const FusedArgs<T>& a, int asrc, int psrc, int fmt, hipStream_t s) {
+  if (a.img == nullptr || a.lds_bytes > kFusedImgBytes) throw HipError("fused coarse cycle: no room for the image");
+  if (d == 2) dispatch_fused<2, T>(a, asrc, psrc, fmt, s, true);
+  else dispatch_fused<3, T>(a, asrc, psrc, fmt, s, true);
+}
+template void launch_fused_prepare<double>(int, const FusedArgs<double>&, int, int, int, hipStream_t);
+template void launch_fused_prepare<float>(int, const FusedArgs<float>&, int, int, int, hipStream_t);
 
 }  // namespace qmg

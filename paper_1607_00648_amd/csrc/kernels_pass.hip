@@ -2,7 +2,9 @@
 // optional prolongation-add u += P e, one or two damped Jacobi sweeps and an
 // optional residual r = b - A u (with norm partials), in one launch.
 //
-// A workgroup owns a 64 x 8 output tile.  The iterate is staged in LDS on the
+// A workgroup of 1024 threads owns a 64 x 8 output tile, one region point per
+// thread, so that every thread issues its loads at once (the passes are bound
+// by memory latency, not bandwidth).  The iterate is staged in LDS on the
 // tile plus a halo of K vertices, K = number of neighbour-dependent stages
 // (sweeps, residual); stage s produces its values on the tile plus a halo of
 // K - s, so the next stage finds every neighbour in LDS.  Each thread keeps the
@@ -19,7 +21,7 @@ namespace qmg {
 
 namespace {
 
-constexpr int PX = 64, PY = 8, NT = 256;
+constexpr int PX = 64, PY = 8, NT = 1024;
 constexpr int KMAX = 3;
 constexpr int WMAX = PX + 2 * KMAX, HMAX = PY + 2 * KMAX;
 constexpr int PTS = (WMAX * HMAX + NT - 1) / NT;
@@ -114,7 +116,12 @@ __global__ __launch_bounds__(NT) void k_pass2d(PassArgs<T> p) {
     for (int mm = 32; mm >= 1; mm >>= 1) sq += __shfl_xor(sq, mm, 64);
     if ((tid & 63) == 0) red[tid >> 6] = sq;
     __syncthreads();
-    if (tid == 0) p.partial[tl.t] = ((red[0] + red[1]) + red[2]) + red[3];
+    if (tid == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) t += red[w];
+      p.partial[tl.t] = t;
+    }
   }
 }
 

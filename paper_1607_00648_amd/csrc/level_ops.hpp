@@ -43,14 +43,16 @@ __device__ inline double pweight(const Store& P, const Lat& Lf, int64_t vf, int 
   if (SRC == SRC_PLAIN) return ((const double*)P.dense)[(int64_t)kap * Lf.nslot + vf];
   double w = dlin1(rx, kx) * dlin1(ry, ky) * (D == 3 ? dlin1(rz, kz) : 1.0);
   if (SRC == SRC_HIER) {
+    // the payload is read unconditionally (block 0 stands in for a zero
+    // block, the store is allocated in full) and selected, so that the loads
+    // of many weights can be in flight together
     const int32_t cb = P.blk[vf / kSeg];
-    if (cb >= 0) {
-      const int lane = (int)(vf % kSeg);
-      const int64_t idx = ((int64_t)cb * Dim<D>::NC + kap) * kSeg + lane;
-      double dv = (double)Dec<FMT>::get(P.payload, idx);
-      if (FMT == F16) dv = ldexp(dv, (int)P.scale[(int64_t)cb * kSeg + lane]);
-      w += dv;
-    }
+    const int64_t cbl = cb >= 0 ? cb : 0;
+    const int lane = (int)(vf % kSeg);
+    const int64_t idx = (cbl * Dim<D>::NC + kap) * kSeg + lane;
+    double dv = (double)Dec<FMT>::get(P.payload, idx);
+    if (FMT == F16) dv = ldexp(dv, (int)P.scale[cbl * kSeg + lane]);
+    w = cb >= 0 ? w + dv : w;
   }
   return w;
 }

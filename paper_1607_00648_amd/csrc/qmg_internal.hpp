@@ -192,12 +192,21 @@ struct FusedArgs {
   // (n+1)^d lattice, stencil rows of the interior, parent weights (when pw_lds)
   int lds_vec[kMaxFused], lds_rows[kMaxFused], lds_pw[kMaxFused], lds_nslot[kMaxFused];
   int lds_bytes, pw_lds;
+  // precomputed LDS image (zero iterates, stencil rows, parent weights) in
+  // global memory, copied into LDS at the start of every launch (nullable:
+  // then the rows and weights are decoded in the kernel)
+  char* img;
 };
+// Bytes reserved per grid for that image (the largest LDS a workgroup may use).
+constexpr int kFusedImgBytes = 160 * 1024;
 // Fills the LDS layout of `a` (levels lc..lf already set) and returns its bytes.
 template <typename T>
 size_t fused_lds_layout(int d, FusedArgs<T>& a, bool p_stored, bool pw_lds);
 template <typename T>
 void launch_fused_coarse(int d, const FusedArgs<T>& a, int asrc, int psrc, int fmt, hipStream_t s);
+// Writes the LDS image of `a` (layout filled) to a.img (once per operator build).
+template <typename T>
+void launch_fused_prepare(int d, const FusedArgs<T>& a, int asrc, int psrc, int fmt, hipStream_t s);
 
 // Fill lattice array with zeros (kernel, not memset, so it can live in graphs).
 template <typename T>

@@ -169,6 +169,9 @@ def main():
                     help="first run one device copy of MIB MiB (HBM counter calibration)")
     ap.add_argument("--profile-every", type=int, default=8,
                     help="time every k-th launch of the timed kernel with HIP events (0: none)")
+    ap.add_argument("--sweep", default="2:8",
+                    help="roofline sweep on larger regular grids, dim:level comma list ('' for none): "
+                         "the same step for the hier64, plain64 and bf16 stores")
     ap.add_argument("--variants", default="plain64,bf16",
                     help="extra stores timed on the same workload (comma list, '' for none)")
     args = ap.parse_args()
@@ -253,6 +256,29 @@ def main():
                        "p50_ms": float(np.percentile(r["lat"], 50) * 1e3)}
     if variants:
         out["variants"] = variants
+    sweep = []
+    for item in [s for s in args.sweep.split(",") if s]:
+        dim, level = (int(x) for x in item.split(":"))
+        q = W.random_checkerboard(dim, level, 0, name=f"jump{dim}d-L{level}")
+        for store in ("hier64", "plain64", "bf16"):
+            r = run_variant(qmg, q, "boxmg", store, 2, 1, profile=args.profile_every or 8)
+            avg = r["kernel_ms"] / max(r["kernel_launches"], 1) / 1e3
+            op_b = OP_BYTES[(store, dim)] * TIMED_OPS[dim] * q.n_unknowns
+            fz_b = FUSED_MIN_BYTES.get((store, dim), OP_BYTES[(store, dim)]) * q.n_unknowns
+            sweep.append({"dim": dim, "level": level, "unknowns": q.n_unknowns, "store": store,
+                          "solves_per_s": len(r["lat"]) / r["elapsed"],
+                          "vertex_updates_per_s": r["updates"] / r["elapsed"],
+                          "cycles_per_solve": r["reps"][-1]["cycles"], "relres": r["reps"][-1]["relres"],
+                          "kernel": TIMED_KERNEL[dim], "avg_launch_us": avg * 1e6,
+                          "achieved_gbs": op_b / avg / 1e9 if avg > 0 else None,
+                          "frac": op_b / avg / 1e9 / HBM_PEAK_GBS if avg > 0 else None,
+                          "fused_bytes_per_launch": fz_b,
+                          "fused_gbs": fz_b / avg / 1e9 if avg > 0 else None})
+            print(f"sweep {dim}D L{level} {store}: {sweep[-1]['solves_per_s']:.2f} solves/s, "
+                  f"{sweep[-1]['avg_launch_us']:.1f} us/launch", file=sys.stderr, flush=True)
+        del q
+    if sweep:
+        out["roofline_sweep"] = sweep
     if not args.no_serving:
         out["serving"] = serve_stream(qmg)
     if not args.no_cpu_baseline:

@@ -22,12 +22,15 @@ namespace {
 template <int D>
 constexpr int block_of() { return D == 2 ? 1024 : 256; }
 
-// 32-bit index arithmetic (the fused levels have a few thousand vertices)
-__device__ inline void vertex_of(int idx, int m, int d, int& i, int& j, int& k) {
-  const int q = idx / m;
+// 32-bit index arithmetic (the fused levels have a few thousand vertices).
+// Division by m is a multiply-high with mag = floor((2^32 - 1) / m) + 1, exact
+// for m >= 2 and indices below 2^22 (error below 2^-10 of one unit).
+__device__ inline int divm(int x, unsigned mag) { return (int)__umulhi((unsigned)x, mag); }
+__device__ inline void vertex_of(int idx, int m, unsigned mag, int d, int& i, int& j, int& k) {
+  const int q = divm(idx, mag);
   i = idx - q * m + 1;
   if (d == 3) {
-    const int r = q / m;
+    const int r = divm(q, mag);
     j = q - r * m + 1;
     k = r + 1;
   } else {
@@ -44,7 +47,8 @@ struct Fused {
   static constexpr int NS = Dim<D>::NS, NC = Dim<D>::NC, BS = block_of<D>();
   const FusedArgs<T>& a;
   char* smem;
-  __device__ Fused(const FusedArgs<T>& args, char* s) : a(args), smem(s) {}
+  const unsigned* mag;  // division magic of m(s) per level (kernel arguments)
+  __device__ Fused(const FusedArgs<T>& args, char* s) : a(args), smem(s), mag(args.mag) {}
 
   __device__ int w(int s) const { return a.L[s].n + 1; }
   __device__ int m(int s) const { return a.L[s].n - 1; }
@@ -75,7 +79,7 @@ struct Fused {
       for (int q = threadIdx.x; q < 4 * nsl; q += BS) vec(s, 0)[q] = (T)0;
       for (int idx = threadIdx.x; idx < nint(s); idx += BS) {
         int i, j, k;
-        vertex_of(idx, ms, D, i, j, k);
+        vertex_of(idx, ms, mag[s], D, i, j, k);
         const int64_t v = i + (int64_t)j * L.pitch + (int64_t)k * L.plane;
         T r[NS];
         op_row<D, T, ASRC, FMT>(a.eps[s], a.A[s], L, v, r);
@@ -106,7 +110,7 @@ struct Fused {
     const Lat& L = a.L[top];
     for (int idx = threadIdx.x; idx < nint(top); idx += BS) {
       int i, j, k;
-      vertex_of(idx, m(top), D, i, j, k);
+      vertex_of(idx, m(top), mag[top], D, i, j, k);
       vec(top, 2)[cidx(w(top), i, j, k)] = a.b[top][i + (int64_t)j * L.pitch + (int64_t)k * L.plane];
     }
     __syncthreads();
@@ -118,7 +122,7 @@ struct Fused {
     const T* bv = vec(s, 2);
     for (int idx = threadIdx.x; idx < nint(s); idx += BS) {
       int i, j, k;
-      vertex_of(idx, ms, D, i, j, k);
+      vertex_of(idx, ms, mag[s], D, i, j, k);
       const int c = cidx(ws, i, j, k);
       const T* row = rows(s) + (int64_t)idx * NS;
       const T dg = row[NS / 2];
@@ -157,7 +161,7 @@ struct Fused {
       T* r = vec(s, 3);
       for (int idx = threadIdx.x; idx < nint(s); idx += BS) {
         int i, j, k;
-        vertex_of(idx, ms, D, i, j, k);
+        vertex_of(idx, ms, mag[s], D, i, j, k);
         const int c = cidx(ws, i, j, k);
         r[c] = vec(s, 2)[c] - row_dot_lds(rows(s) + (int64_t)idx * NS, u, ws, c);
       }
@@ -166,7 +170,7 @@ struct Fused {
       T* bc = vec(s - 1, 2);
       for (int idx = threadIdx.x; idx < nint(s - 1); idx += BS) {
         int I, J, K;
-        vertex_of(idx, mc, D, I, J, K);
+        vertex_of(idx, mc, mag[s - 1], D, I, J, K);
         T acc = (T)0;
         const int zlo = (D == 3) ? -2 : 0, zhi = (D == 3) ? 2 : 0;
         for (int oz = zlo; oz <= zhi; ++oz)
@@ -191,11 +195,11 @@ struct Fused {
         double acc = 0.0;
         for (int c = 0; c < a.nc; ++c) {
           int i, j, k;
-          vertex_of(c, ms, D, i, j, k);
+          vertex_of(c, ms, mag[0], D, i, j, k);
           acc += a.Ainv[(int64_t)row * a.nc + c] * (double)b0[cidx(ws, i, j, k)];
         }
         int i, j, k;
-        vertex_of(row, ms, D, i, j, k);
+        vertex_of(row, ms, mag[0], D, i, j, k);
         u0[cidx(ws, i, j, k)] = (T)acc;
       }
       __syncthreads();
@@ -209,7 +213,7 @@ struct Fused {
       const T* ec = vec(s - 1, cur[s - 1]);
       for (int idx = threadIdx.x; idx < nint(s); idx += BS) {
         int i, j, k;
-        vertex_of(idx, ms, D, i, j, k);
+        vertex_of(idx, ms, mag[s], D, i, j, k);
         const int fc = cidx(ws, i, j, k);
         const int qx = i / 3, qy = j / 3, qz = k / 3;
         T acc = (T)0;
@@ -229,7 +233,7 @@ struct Fused {
     const T* res = vec(top, cur[top]);
     for (int idx = threadIdx.x; idx < nint(top); idx += BS) {
       int i, j, k;
-      vertex_of(idx, m(top), D, i, j, k);
+      vertex_of(idx, m(top), mag[top], D, i, j, k);
       a.u[top][i + (int64_t)j * L.pitch + (int64_t)k * L.plane] = res[cidx(w(top), i, j, k)];
     }
   }
@@ -299,6 +303,7 @@ size_t fused_lds_layout(int d, FusedArgs<T>& a, bool p_stored, bool pw_lds) {
     const int nsl = d == 3 ? w * w * w : w * w;
     const int nin = d == 3 ? m * m * m : m * m;
     a.lds_nslot[s] = nsl;
+    a.mag[s] = 0xFFFFFFFFu / (unsigned)m + 1u;
     a.lds_vec[s] = (int)take((size_t)4 * nsl * sizeof(T));
     a.lds_rows[s] = (int)take((size_t)nin * NS * sizeof(T));
     a.lds_pw[s] = (s >= 1 && p_stored && pw_lds) ? (int)take((size_t)nsl * NC * sizeof(T)) : 0;

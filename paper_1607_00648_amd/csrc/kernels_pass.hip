@@ -51,10 +51,13 @@ __global__ __launch_bounds__(NT) void k_pass2d(PassArgs<T> p) {
   T bb[PTS];
   int64_t vv[PTS];
   bool inter[PTS];
+  int rxs[PTS], rys[PTS];  // region coordinates (divisions done once)
 #pragma unroll
   for (int m = 0; m < PTS; ++m) {
     const int q = tid + NT * m;
-    const int i = x0 + q % W, j = y0 + q / W;
+    rys[m] = q / W;
+    rxs[m] = q - rys[m] * W;
+    const int i = x0 + rxs[m], j = y0 + rys[m];
     const bool valid = q < W * H;
     const bool inside = valid && i >= 0 && i <= n && j >= 0 && j <= n;
     inter[m] = inside && i >= 1 && i < n && j >= 1 && j < n;
@@ -76,7 +79,7 @@ __global__ __launch_bounds__(NT) void k_pass2d(PassArgs<T> p) {
 #pragma unroll
     for (int m = 0; m < PTS; ++m) {
       const int q = tid + NT * m;
-      const int rx = q % W, ry = q / W;
+      const int rx = rxs[m], ry = rys[m];
       if (q >= W * H || rx < s || rx >= W - s || ry < s || ry >= H - s) continue;
       T nu = buf[cur][q];
       if (inter[m]) {
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(NT) void k_pass2d(PassArgs<T> p) {
 #pragma unroll
   for (int m = 0; m < PTS; ++m) {
     const int q = tid + NT * m;
-    const int rx = q % W, ry = q / W;
+    const int rx = rxs[m], ry = rys[m];
     if (q >= W * H || rx < K || rx >= W - K || ry < K || ry >= H - K || !inter[m]) continue;
     p.out[vv[m]] = buf[cur][q];
     if (p.res) {

@@ -192,6 +192,7 @@ struct FusedArgs {
   // (n+1)^d lattice, stencil rows of the interior, parent weights (when pw_lds)
   int lds_vec[kMaxFused], lds_rows[kMaxFused], lds_pw[kMaxFused], lds_nslot[kMaxFused];
   int lds_bytes, pw_lds;
+  unsigned mag[kMaxFused];  // floor((2^32 - 1) / (n - 1)) + 1 per level: exact division by n - 1
   // precomputed LDS image (zero iterates, stencil rows, parent weights) in
   // global memory, copied into LDS at the start of every launch (nullable:
   // then the rows and weights are decoded in the kernel)

@@ -64,6 +64,8 @@ struct LevelBuf {
   int32_t* tiles = nullptr;
   int ntiles = 0;
   void* sv = nullptr;
+  double* x64 = nullptr;  // FP32 iterates: FP64 solution and right-hand side of the level
+  double* b64 = nullptr;
   AdTiles ad() const {
     AdTiles t;
     t.L = L;
@@ -209,8 +211,6 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
       throw ApiError(QMG_EINVAL, "coarsest_level must not exceed base_level");
     if (o->transfer == QMG_BOXMG)
       throw ApiError(QMG_EINVAL, "adaptive grids take the geometric or the d-linear Galerkin transfer");
-    if (o->store != QMG_HIER_FP64 && o->store != QMG_PLAIN_FP64)
-      throw ApiError(QMG_EINVAL, "adaptive grids take the FP64 stores");
   }
 }
 
@@ -319,6 +319,10 @@ void layout(qmg_grid_t* g, Arena& a) {
       if (l < L) B.cref = a.take<int8_t>(B.L.nslot);
       B.tiles = a.take<int32_t>((int64_t)H.tiles.size());
       if (l < L) B.sv = a.take<char>(B.L.nslot * (int64_t)it);
+      if (g->mixed) {
+        B.x64 = a.take<double>(B.L.nslot);
+        B.b64 = a.take<double>(B.L.nslot);
+      }
       n_unk += (int64_t)H.leaf.size();
       n_cells += (int64_t)H.cells.size();
       ad_partials += B.ntiles;
@@ -663,11 +667,22 @@ void vcycle_ad(qmg_grid_t* g, int l) {
 
 // Refined vertices take their finest copy (top down), then hanging vertices
 // the interpolant of the level below (bottom up).
-void composite_state(qmg_grid_t* g) {
+// (on the FP64 solution x64 of every level when the iterates are FP32, on the
+// iterates themselves otherwise)
+template <typename T>
+void composite_state_of(qmg_grid_t* g, T* (*field)(LevelBuf&)) {
   for (int l = g->Lmax; l > g->lb; --l)
-    launch_ad_inject<double>(g->lv[l - 1].ad(), g->lv[l].L, (const double*)g->lv[l].u, (double*)g->lv[l - 1].u, S(g));
+    launch_ad_inject<T>(g->lv[l - 1].ad(), g->lv[l].L, field(g->lv[l]), field(g->lv[l - 1]), S(g));
   for (int l = g->lb + 1; l <= g->Lmax; ++l)
-    launch_ad_hang<double>(g->lv[l].ad(), g->lv[l - 1].L, (double*)g->lv[l].u, (const double*)g->lv[l - 1].u, S(g));
+    launch_ad_hang<T>(g->lv[l].ad(), g->lv[l - 1].L, field(g->lv[l]), field(g->lv[l - 1]), S(g));
+}
+double* iterate64(LevelBuf& B) { return (double*)B.u; }
+float* iterate32(LevelBuf& B) { return (float*)B.u; }
+double* solution64(LevelBuf& B) { return B.x64; }
+
+void composite_state(qmg_grid_t* g) {
+  if (g->mixed) composite_state_of<double>(g, solution64);
+  else composite_state_of<double>(g, iterate64);
 }
 
 int64_t updates_per_cycle(const qmg_grid_t* g) {
@@ -695,6 +710,17 @@ void enqueue_residual_norm(qmg_grid_t* g, bool record, bool partials_ready = fal
   int np = 0;
   if (partials_ready) {  // left by the cycle's last fused pass
     np = pass2d_partials(F.L);
+  } else if (g->adaptive && g->mixed) {
+    // FP64 composite residual of x64 at the leaves (rediscretised leaf rows
+    // from eps64); its FP32 rounding becomes the inner right-hand side
+    composite_state(g);
+    Store geom;
+    for (int l = g->lb; l <= g->Lmax; ++l) {
+      LevelBuf& B = g->lv[l];
+      launch_ad_stencil<double, float>(B.ad(), 2, B.x64, B.b64, (float*)B.b, B.eps64, geom, 0.0,
+                                       g->partial + np, S(g));
+      np += B.ntiles;
+    }
   } else if (g->adaptive) {
     composite_state(g);
     for (int l = g->lb; l <= g->Lmax; ++l) {
@@ -725,6 +751,20 @@ double finest_residual_norm(qmg_grid_t* g) {
 // Returns true when the cycle left the finest residual norm partials.
 bool one_cycle(qmg_grid_t* g) {
   if (!g->mixed) return vcycle<double>(g, g->Lmax, false, true);
+  if (g->adaptive) {
+    // inner FAS cycles on the correction, from zero on every level
+    for (int l = g->lcq; l <= g->Lmax; ++l) {
+      LevelBuf& B = g->lv[l];
+      if (l >= g->lb) launch_ad_zero<float>(B.ad(), (float*)B.u, S(g));
+      else launch_zero<float>((float*)B.u, B.L.nslot, S(g));
+    }
+    for (int m = 0; m < g->opts.inner_cycles; ++m) {
+      if (m > 0) composite_state_of<float>(g, iterate32);
+      vcycle<float>(g, g->Lmax, false);
+    }
+    for (int l = g->lb; l <= g->Lmax; ++l) launch_ad_axpy(g->lv[l].ad(), g->lv[l].x64, (const float*)g->lv[l].u, S(g));
+    return false;
+  }
   for (int m = 0; m < g->opts.inner_cycles; ++m) vcycle<float>(g, g->Lmax, m == 0);
   launch_axpy_mixed(g->lv[g->Lmax].L, g->x64, (const float*)g->lv[g->Lmax].u, S(g));
   return false;
@@ -1423,12 +1463,18 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
       int64_t uo = 0;
       for (int l = g->lcq; l <= g->Lmax; ++l) {
         LevelBuf& B = g->lv[l];
-        launch_zero<double>((double*)B.u, B.L.nslot, s);
-        launch_zero<double>((double*)B.t, B.L.nslot, s);
-        launch_zero<double>((double*)B.b, B.L.nslot, s);
+        for (void* v : {B.u, B.t, B.b}) {
+          if (g->mixed) launch_zero<float>((float*)v, B.L.nslot, s);
+          else launch_zero<double>((double*)v, B.L.nslot, s);
+        }
         if (l < g->lb) continue;
+        double* bdst = g->mixed ? B.b64 : (double*)B.b;
+        if (g->mixed) {
+          launch_zero<double>(B.x64, B.L.nslot, s);
+          launch_zero<double>(B.b64, B.L.nslot, s);
+        }
         const int64_t cnt = (int64_t)g->hl[l].leaf.size();
-        launch_ad_scatter<double>(g->unk_slots + uo, cnt, g->stage + uo, 1.0, (double*)B.b, s);
+        launch_ad_scatter<double>(g->unk_slots + uo, cnt, g->stage + uo, 1.0, bdst, s);
         uo += cnt;
       }
     } else if (g->mixed) {
@@ -1503,7 +1549,8 @@ int qmg_get_solution(const qmg_grid_t* cg, double* u, int mem) {
       int64_t uo = 0;
       for (int l = g->lb; l <= g->Lmax; ++l) {
         const int64_t cnt = (int64_t)g->hl[l].leaf.size();
-        launch_ad_gather<double>(g->unk_slots + uo, cnt, (const double*)g->lv[l].u, g->stage + uo, S(g));
+        const double* src = g->mixed ? g->lv[l].x64 : (const double*)g->lv[l].u;
+        launch_ad_gather<double>(g->unk_slots + uo, cnt, src, g->stage + uo, S(g));
         uo += cnt;
       }
     } else {
@@ -1525,7 +1572,8 @@ int qmg_set_solution(qmg_grid_t* g, const double* u, int mem) {
       int64_t uo = 0;
       for (int l = g->lb; l <= g->Lmax; ++l) {
         const int64_t cnt = (int64_t)g->hl[l].leaf.size();
-        launch_ad_scatter<double>(g->unk_slots + uo, cnt, g->stage + uo, 1.0, (double*)g->lv[l].u, S(g));
+        double* dst = g->mixed ? g->lv[l].x64 : (double*)g->lv[l].u;
+        launch_ad_scatter<double>(g->unk_slots + uo, cnt, g->stage + uo, 1.0, dst, S(g));
         uo += cnt;
       }
       // refined and hanging values are functions of the leaves

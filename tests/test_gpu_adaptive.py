@@ -162,8 +162,44 @@ def test_adaptive_rejected_by_server_and_boxmg():
     flags, G, eps, f = _problem(2, 2, 4)
     with pytest.raises(qmg.QmgError):
         _grid(qmg, 2, 2, 4, flags, transfer="boxmg")
-    with pytest.raises(qmg.QmgError):
-        _grid(qmg, 2, 2, 4, flags, store="bf16")
+    srv = qmg.Server(1 << 30, max_slots=2)
+    desc = qmg.GridDesc(2, 4, 2, qmg.pack_refine(2, 2, 4, flags).ctypes.data_as(qmg.C.c_void_p))
+    t = qmg.C.c_uint64(0)
+    rc = srv.lib.qmg_server_submit(srv.h, qmg.C.byref(desc), qmg.C.byref(qmg.make_opts(transfer="galerkin")),
+                                   qmg._ptr(eps), qmg._ptr(f), 1e-8, 100, qmg.C.byref(t))
+    assert rc == qmg.QMG_EINVAL
+    srv.close()
+
+
+@pytest.mark.parametrize("d,base,L", [(2, 2, 4), (3, 1, 3)])
+@pytest.mark.parametrize("store", ["hier32", "bf16", "hier16"])
+def test_mixed_precision_reaches_composite_solution(d, base, L, store):
+    """FP32 inner FAS cycles on reduced-precision stores inside the FP64
+    composite defect correction: the oracle recomputes the final relative
+    residual in FP64, and the error against the directly solved composite
+    system stays within 10x that of the FP64 path stopped at the same
+    tolerance."""
+    qmg = require_gpu()
+    announce(f"adaptive mixed d={d} base={base} L={L} {store}")
+    flags, G, eps, f = _problem(d, base, L)
+    ustar, A, b = AD.solve_composite_direct(G, eps, f)
+    errs, cyc = {}, {}
+    for st in ("hier64", store):
+        g = _grid(qmg, d, base, L, flags, store=st)
+        g.set_coefficients(eps, f)
+        g.build()
+        rep, hist = g.solve(tol=1e-8, max_cycles=300)
+        assert rep["status"] == "QMG_OK", rep
+        u = g.solution()
+        rr = np.linalg.norm(b - A @ u) / np.linalg.norm(b)
+        assert rr <= 1e-8 * (1 + 1e-6)
+        assert abs(rr - rep["relres"]) <= 1e-6 * rr
+        errs[st] = np.linalg.norm(u - ustar) / np.linalg.norm(ustar)
+        cyc[st] = rep["cycles"]
+        g.close()
+    print(f"[adaptive mixed] {store}: err {errs[store]:.2e} (fp64 {errs['hier64']:.2e}), "
+          f"cycles {cyc[store]} (fp64 {cyc['hier64']})")
+    assert errs[store] <= 10 * errs["hier64"]
 
 
 def _workload_inputs(P, G):
@@ -237,3 +273,33 @@ def test_balls_full_size_solve_sampled_rows():
         est += (levels == l).sum() * np.mean(r[m] ** 2)
     assert np.sqrt(est) <= 10 * rep["relres"] * nb
     g.close()
+
+
+def test_balls_full_size_mixed_bf16_sampled_rows():
+    """The 3D four-ball workload at full size in its mixed form: BF16 deltas,
+    FP32 inner cycles, FP64 composite defect correction to 1e-8; the oracle
+    recomputes the composite residual at sampled unknowns of every level."""
+    qmg = require_gpu()
+    announce("adaptive balls 3D base3 L5 full size, bf16 mixed")
+    P = W.adaptive_balls()
+    G = AD.AdaptiveGrid(P.dim, P.base, P.level, P.flags)
+    eps, f = _workload_inputs(P, G)
+    g = _grid(qmg, 3, P.base, P.level, P.flags, store="bf16", check_definite=False)
+    g.set_coefficients(eps, f)
+    g.build()
+    rep, hist = g.solve(tol=1e-8, max_cycles=200)
+    assert rep["status"] == "QMG_OK", rep
+    u = g.solution()
+    g.close()
+    levels = np.concatenate([np.full(int((G.vtype[l] == AD.LEAF).sum()), l)
+                             for l in range(G.base, G.L + 1)])
+    b = f * (3.0 ** -levels.astype(float)) ** 3
+    nb = np.linalg.norm(b)
+    rng = np.random.default_rng(12)
+    sample = np.concatenate([rng.choice(np.flatnonzero(levels == l), 100, replace=False)
+                             for l in range(G.base, G.L + 1)])
+    r = AD.composite_residual_rows(G, eps, f, u, sample)
+    assert np.abs(r).max() <= 1e-8 * nb * (1 + 1e-6)
+    est = sum((levels == l).sum() * np.mean(r[levels[sample] == l] ** 2) for l in range(G.base, G.L + 1))
+    assert np.sqrt(est) <= 10 * rep["relres"] * nb
+    print(f"[cfg3 bf16] outer iterations {rep['outer_iters']}, relres {rep['relres']:.2e}")

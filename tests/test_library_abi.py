@@ -68,8 +68,9 @@ def test_adaptive_description_validation():
     ok = qmg.make_opts(transfer="galerkin")
     assert lib.qmg_workspace_bytes(C.byref(d), C.byref(ok), C.byref(nb)) == qmg.QMG_OK
     assert nb.value > 0
-    for bad in (qmg.make_opts(transfer="boxmg"), qmg.make_opts(transfer="galerkin", store="bf16"),
-                qmg.make_opts(transfer="galerkin", coarsest_level=3)):
+    assert lib.qmg_workspace_bytes(C.byref(d), C.byref(qmg.make_opts(transfer="galerkin", store="bf16")),
+                                   C.byref(nb)) == qmg.QMG_OK
+    for bad in (qmg.make_opts(transfer="boxmg"), qmg.make_opts(transfer="galerkin", coarsest_level=3)):
         assert lib.qmg_workspace_bytes(C.byref(d), C.byref(bad), C.byref(nb)) == qmg.QMG_EINVAL
     no_flags = qmg.GridDesc(2, 4, 2, None)
     assert lib.qmg_workspace_bytes(C.byref(no_flags), C.byref(ok), C.byref(nb)) == qmg.QMG_EINVAL

@@ -38,6 +38,22 @@ notes):
 * Coarse stencils of refined vertices are Galerkin products with the d-linear
   P (the hanging interpolation uses the same weights), or rediscretised for the
   geometric variant.
+* BoxMG on adaptive levels (Sect. 3.4, the passage on spacetree grids): P is
+  built per refined coarse cell only (a patch), from the level's stencils.  At
+  hanging vertices, whose rows the collapsed systems of the patch faces need,
+  the paper takes stencils obtained from the coarser level by d-linear
+  interpolation.  Reading: the hanging vertex's row is rediscretised on its
+  level from its 2^d cells, a cell that does not exist taking the coefficient
+  of the leaf cell that covers it (the coarse data prolongated to the missing
+  fine cells).  Interpolating the parents' stencil entries themselves breaks
+  down where a parent is a Dirichlet vertex (it has no stencil), and this
+  reading keeps the invariant that a constant coefficient gives d-linear BoxMG
+  weights.  The value of a hanging vertex is the BoxMG interpolant
+  P u_{l-1} (not the geometric one), so the composite system of the BoxMG
+  variant has BoxMG constraints at hanging vertices.  A point shared by
+  several refined patches takes the value of the one whose orthant has + signs
+  on the most significant shared axes (the lowest rank below); the others must
+  agree (rounding aside).
 """
 from __future__ import annotations
 
@@ -50,7 +66,8 @@ import scipy.sparse.linalg as spla
 
 from .fem import (geometric_stencil, offsets, shifted, csr_to_stencil, stencil_to_csr,
                   interior_mask, corners, corner_index, element_matrix)
-from .transfer import dlinear_P
+from .transfer import dlinear_P, boxmg_P, boxmg_reference_stepwise, _gather_reference, _points
+from .fem import _unknown_numbering
 from .galerkin import rap
 from . import solver as S
 
@@ -163,11 +180,13 @@ class AdaptiveGrid:
 
 class _CompositeValues:
     """u_bar(l, v) of the composite system as {unknown: weight}: the unknown
-    for a leaf, the finer copy for a refined vertex, the d-linear interpolant
-    of the coarser level for a hanging vertex, nothing on the boundary."""
+    for a leaf, the finer copy for a refined vertex, the interpolant of the
+    coarser level for a hanging vertex (d-linear, or the rows of the given
+    prolongations ``P[l]``), nothing on the boundary."""
 
-    def __init__(self, G: AdaptiveGrid):
+    def __init__(self, G: AdaptiveGrid, P=None):
         self.G = G
+        self.P = P
         self.num = {lv: k for k, lv in enumerate(G.leaves())}
         self.memo = {}
 
@@ -181,6 +200,17 @@ class _CompositeValues:
             res = {self.num[key]: 1.0}
         elif t == REFINED:
             res = self(l + 1, tuple(3 * vi for vi in v))
+        elif t == HANGING and self.P is not None:
+            res = {}
+            n = 3 ** l
+            Pl = self.P[l]
+            row = _unknown_numbering(d, l)[v]
+            numc = 3 ** (l - 1) - 1
+            for jj in range(Pl.indptr[row], Pl.indptr[row + 1]):
+                c = Pl.indices[jj]
+                par = tuple(reversed([c // numc ** i % numc + 1 for i in range(d)]))   # numpy order
+                for j, cw in self(l - 1, par).items():
+                    res[j] = res.get(j, 0.0) + Pl.data[jj] * cw
         elif t == HANGING:
             res = {}
             q = [vi // 3 for vi in v]
@@ -200,10 +230,11 @@ class _CompositeValues:
         return res
 
 
-def composite_system(G: AdaptiveGrid, eps_leaf, f_leaf):
-    """Sparse composite matrix over the leaf unknowns and its right-hand side."""
+def composite_system(G: AdaptiveGrid, eps_leaf, f_leaf, P=None):
+    """Sparse composite matrix over the leaf unknowns and its right-hand side
+    (hanging constraints d-linear, or from the prolongations ``P``)."""
     d = G.d
-    value = _CompositeValues(G)
+    value = _CompositeValues(G, P)
     num = value.num
     N = len(num)
     eps = G.level_eps(eps_leaf)
@@ -228,13 +259,13 @@ def composite_system(G: AdaptiveGrid, eps_leaf, f_leaf):
     return A, b
 
 
-def composite_residual_rows(G: AdaptiveGrid, eps_leaf, f_leaf, u_leaf, sample):
+def composite_residual_rows(G: AdaptiveGrid, eps_leaf, f_leaf, u_leaf, sample, P=None):
     """b_k - (A u)_k of the composite system at the unknowns ``sample``, each
     row assembled on its own: the element matrices (Sect. 2, Q1) of the 2^d
     cells around the leaf, applied to the composite values of their corners.
     Usable on grids far too large for ``composite_system``."""
     d = G.d
-    value = _CompositeValues(G)
+    value = _CompositeValues(G, P)
     leaves = G.leaves()
     eps = G.level_eps(eps_leaf)
     cs = corners(d)
@@ -263,36 +294,112 @@ class AdaptiveHierarchy:
     pass
 
 
+def virtual_eps(G: AdaptiveGrid, eps):
+    """Cell coefficients of every level where a cell that does not exist takes
+    the coefficient of the leaf cell covering it (base level up)."""
+    d = G.d
+    out = {G.base: eps[G.base]}
+    for l in range(G.base + 1, G.L + 1):
+        out[l] = np.where(G.exist[l], eps[l], _children(out[l - 1], d))
+    return out
+
+
+def hanging_stencils(G: AdaptiveGrid, eps):
+    """Rows of the hanging vertices of levels base+1..L for the collapsed BoxMG
+    systems, rediscretised from the virtual coefficients (zero elsewhere)."""
+    d = G.d
+    ev = virtual_eps(G, eps)
+    out = {}
+    for l in range(G.base + 1, G.L + 1):
+        out[l] = geometric_stencil(ev[l], d, l) * (G.vtype[l] == HANGING)[None]
+    return out
+
+
+def boxmg_adaptive_P(G: AdaptiveGrid, S_full, l, check=True):
+    """BoxMG prolongation from level l-1 to level l computed on the refined
+    coarse cells only (Sect. 3.4 per patch and corner), from the level's
+    stencil array ``S_full`` (rows of leaf, refined and hanging vertices).
+    Sparse, fine interior unknowns x coarse interior unknowns; rows of fine
+    vertices outside every refined cell are empty."""
+    d = G.d
+    nf = 3 ** l
+    nc = nf // 3
+    numf = _unknown_numbering(d, l)
+    numc = _unknown_numbering(d, l - 1)
+    Vall = np.array(list(itertools.product(range(1, nc), repeat=d)))[:, ::-1]   # x first
+    ref = G.refined[l - 1]
+    rows, cols, ranks, vals = [], [], [], []
+    for sigma in itertools.product((1, -1), repeat=d):
+        sigma = tuple(reversed(sigma))
+        sig = np.array(sigma)
+        cell = Vall + (sig - 1) // 2                       # the orthant's coarse cell, x first
+        ok = ref[tuple(cell[:, i] for i in reversed(range(d)))]
+        V = Vall[ok]
+        if len(V) == 0:
+            continue
+        p = boxmg_reference_stepwise(_gather_reference(S_full, d, V, sigma), d)
+        c = numc[tuple(V[:, i] for i in reversed(range(d)))]
+        for j, y in enumerate(_points(d, 3)):
+            # a point on the patch's own axes is shared with the orthants that
+            # differ there; rank orders those (+ first, axis i weighing 2^i)
+            rank = sum(1 << i for i in range(d) if y[i] == 0 and sigma[i] < 0)
+            F = 3 * V + sig * np.array(y)
+            rows.append(numf[tuple(F[:, i] for i in reversed(range(d)))])
+            cols.append(c)
+            ranks.append(np.full(len(V), rank))
+            vals.append(p[:, j])
+    Nf, Nc = (nf - 1) ** d, (nc - 1) ** d
+    if not rows:
+        return sp.csr_matrix((Nf, Nc))
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    ranks, vals = np.concatenate(ranks), np.concatenate(vals)
+    key = rows * Nc + cols
+    order = np.lexsort((ranks, key))
+    key, vals = key[order], vals[order]
+    uniq, first = np.unique(key, return_index=True)
+    if check:
+        grp = np.repeat(np.arange(len(uniq)), np.diff(np.append(first, len(key))))
+        ref_v = vals[first][grp]
+        if (np.abs(vals - ref_v) > 1e-9 * np.maximum(1.0, np.abs(ref_v))).any():
+            raise AssertionError("adaptive BoxMG: neighbouring patches disagree on a shared entry")
+    return sp.csr_matrix((vals[first], (uniq // Nc, uniq % Nc)), shape=(Nf, Nc))
+
+
 def build_adaptive(G: AdaptiveGrid, eps_leaf, transfer="galerkin", omega=0.6, mu_pre=2, mu_post=2,
                    lc=1):
-    """Stencils of every level: rediscretised rows for unrefined vertices,
-    Galerkin (d-linear P) or rediscretised rows for refined ones; the levels
-    up to the base level form a regular hierarchy below."""
-    if transfer not in ("geometric", "galerkin"):
-        raise ValueError("adaptive levels support the geometric and d-linear Galerkin transfers")
+    """Operators of every level: rediscretised rows for unrefined vertices,
+    Galerkin rows P^T A P (d-linear or BoxMG P) or rediscretised rows for
+    refined ones; prolongations ``H.P[l]`` (also used for the hanging values);
+    the levels up to the base level form a regular hierarchy below."""
+    if transfer not in ("geometric", "galerkin", "boxmg"):
+        raise ValueError(transfer)
     d = G.d
     eps = G.level_eps(eps_leaf)
     H = AdaptiveHierarchy()
     H.G, H.d, H.base, H.L = G, d, G.base, G.L
     H.omega, H.mu_pre, H.mu_post = omega, mu_pre, mu_post
     H.eps = eps
-    H.S = {}
-    H.S[G.L] = geometric_stencil(eps[G.L], d, G.L)
-    for l in range(G.L - 1, lc - 1, -1):
-        geo = geometric_stencil(eps[l], d, l)
-        if transfer == "galerkin":
-            Af = stencil_to_csr(H.S[l + 1], d, l + 1)
-            gal = csr_to_stencil(rap(Af, dlinear_P(d, l + 1)), d, l)
-            ref = (G.vtype[l] == REFINED)
-            H.S[l] = np.where(ref[None], gal, geo)
+    H.transfer = transfer
+    geo = {l: geometric_stencil(eps[l], d, l) for l in range(lc, G.L + 1)}
+    act = {l: np.isin(G.vtype[l], (LEAF, REFINED)) for l in range(lc, G.L + 1)}
+    Hs = hanging_stencils(G, eps) if transfer == "boxmg" else {}
+    H.S = {G.L: geo[G.L] * act[G.L][None]}
+    H.P = {}
+    for l in range(G.L, lc, -1):
+        if transfer == "boxmg":
+            H.P[l] = boxmg_adaptive_P(G, H.S[l] + Hs[l], l) if l > G.base else boxmg_P(H.S[l], d, l)
         else:
-            H.S[l] = geo
-        # rows only for non-hanging vertices
-        H.S[l] = H.S[l] * np.isin(G.vtype[l], (LEAF, REFINED))[None]
-    H.S[G.L] = H.S[G.L] * np.isin(G.vtype[G.L], (LEAF, REFINED))[None]
+            H.P[l] = dlinear_P(d, l)
+        if transfer == "geometric":
+            Sc = geo[l - 1]
+        else:
+            gal = csr_to_stencil(rap(stencil_to_csr(H.S[l], d, l), H.P[l]), d, l - 1)
+            Sc = np.where((G.vtype[l - 1] == REFINED)[None], gal, geo[l - 1])
+        # rows only for leaf and refined vertices
+        H.S[l - 1] = Sc * act[l - 1][None]
     # regular hierarchy from the base level down (correction scheme)
     A = {l: stencil_to_csr(H.S[l], d, l) for l in range(lc, G.base + 1)}
-    P = {l: dlinear_P(d, l) for l in range(lc + 1, G.base + 1)}
+    P = {l: H.P[l] for l in range(lc + 1, G.base + 1)}
     Hr = S.Hierarchy(d, G.base, lc, transfer, A, P, {l: eps[l] for l in range(lc, G.base + 1)},
                      omega, mu_pre, mu_post)
     import scipy.linalg as sla
@@ -300,6 +407,12 @@ def build_adaptive(G: AdaptiveGrid, eps_leaf, transfer="galerkin", omega=0.6, mu
         Hr.coarse_lu = sla.lu_factor(A[lc].toarray())
     H.regular = Hr
     return H
+
+
+def hanging_constraints(H):
+    """The prolongations that define hanging values in the composite system
+    (None: d-linear)."""
+    return H.P if H.transfer == "boxmg" else None
 
 
 def _apply(Sl, u, d):
@@ -349,11 +462,32 @@ def _restrict_dlin(r, d, l):
     return out
 
 
+def _prolong(H, uc, l):
+    """P u_{l-1} on the level-l lattice: d-linear, or the BoxMG rows."""
+    if H.transfer != "boxmg":
+        return _from_coarse(uc, H.d, l)
+    d = H.d
+    out = np.zeros((3 ** l + 1,) * d)
+    out[(slice(1, 3 ** l),) * d] = (H.P[l] @ uc[(slice(1, 3 ** (l - 1)),) * d].ravel()).reshape((3 ** l - 1,) * d)
+    return out
+
+
+def _restrict(H, r, l):
+    """P^T r on the level l-1 lattice: d-linear, or the BoxMG columns."""
+    if H.transfer != "boxmg":
+        return _restrict_dlin(r, H.d, l)
+    d = H.d
+    out = np.zeros((3 ** (l - 1) + 1,) * d)
+    out[(slice(1, 3 ** (l - 1)),) * d] = (H.P[l].T @ r[(slice(1, 3 ** l),) * d].ravel()).reshape(
+        (3 ** (l - 1) - 1,) * d)
+    return out
+
+
 def hang(H, u, l):
     """Hanging vertices of level l take the interpolant of level l-1."""
     G = H.G
     hv = G.vtype[l] == HANGING
-    u[l] = np.where(hv, _from_coarse(u[l - 1], H.d, l), u[l])
+    u[l] = np.where(hv, _prolong(H, u[l - 1], l), u[l])
 
 
 def inject(H, u, l):
@@ -394,9 +528,9 @@ def fas_cycle(H, l, u, b):
     inject(H, u, l)
     saved = u[l - 1].copy()
     ref = G.vtype[l - 1] == REFINED
-    b[l - 1] = np.where(ref, _restrict_dlin(r, d, l) + _apply(H.S[l - 1], u[l - 1], d), b[l - 1])
+    b[l - 1] = np.where(ref, _restrict(H, r, l) + _apply(H.S[l - 1], u[l - 1], d), b[l - 1])
     fas_cycle(H, l - 1, u, b)
-    corr = _from_coarse(u[l - 1] - saved, d, l)
+    corr = _prolong(H, u[l - 1] - saved, l)
     u[l] = np.where(act, u[l] + corr, u[l])
     hang(H, u, l)
     for _ in range(H.mu_post):
@@ -459,6 +593,6 @@ def solve_adaptive(H, f_leaf, tol=1e-8, max_cycles=200, cycles=None):
     return leaf_vector(H, u), hist
 
 
-def solve_composite_direct(G, eps_leaf, f_leaf):
-    A, b = composite_system(G, eps_leaf, f_leaf)
+def solve_composite_direct(G, eps_leaf, f_leaf, P=None):
+    A, b = composite_system(G, eps_leaf, f_leaf, P)
     return spla.spsolve(sp.csc_matrix(A), b), A, b

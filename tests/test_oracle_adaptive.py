@@ -121,3 +121,100 @@ def test_residual_rows_assembled_one_by_one(d, base, L):
     rows = AD.composite_residual_rows(G, eps, f, u, sample)
     ref = (b - A @ u)[sample]
     np.testing.assert_allclose(rows, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------------------
+# BoxMG on adaptive levels
+# ---------------------------------------------------------------------------
+
+def _checkerboard_eps(G, seed, values=(1.0, 1e3)):
+    """Leaf-cell coefficients from a random 9^d table (jumps on level-2 faces)."""
+    rng = np.random.default_rng(seed)
+    table = rng.choice(np.asarray(values), size=(9,) * G.d)
+    idx = np.minimum((G.cell_centres() * 9).astype(int), 8)
+    return table[tuple(idx[:, i] for i in reversed(range(G.d)))]
+
+
+@pytest.mark.parametrize("d,base,L", [(2, 2, 4), (3, 1, 3)])
+def test_boxmg_constant_coefficient_is_dlinear(d, base, L):
+    """For constant eps BoxMG reproduces d-linear weights, also at hanging
+    vertices (whose interpolated stencils are then proportional to the
+    rediscretised ones), so every operator, every prolongation and the
+    composite system equal those of the d-linear Galerkin variant."""
+    G, _, f = _problem(d, base, L, seed=5)
+    eps = np.full(len(G.leaf_cells()), 2.5)
+    Hb = AD.build_adaptive(G, eps, transfer="boxmg")
+    Hg = AD.build_adaptive(G, eps, transfer="galerkin")
+    for l in range(2, L + 1):
+        np.testing.assert_allclose(Hb.P[l].toarray(), Hg.P[l].toarray()[:, :] * (abs(Hb.P[l]).toarray() > 0),
+                                   atol=1e-12)
+        act = np.isin(G.vtype[l], (AD.LEAF, AD.REFINED))
+        np.testing.assert_allclose(Hb.S[l][:, act], Hg.S[l][:, act], atol=1e-12 * abs(Hg.S[l]).max())
+    Ab, bb = AD.composite_system(G, eps, f, AD.hanging_constraints(Hb))
+    Ag, bg = AD.composite_system(G, eps, f)
+    assert abs(Ab - Ag).max() <= 1e-12 * abs(Ag).max()
+
+
+def test_boxmg_full_refinement_is_the_regular_boxmg():
+    """Refining every cell leaves no hanging vertex: the adaptive BoxMG of each
+    level equals the regular BoxMG of the same stencils."""
+    d, base, L = 2, 1, 3
+    flags = {l: np.ones((3 ** l,) * d, bool) for l in range(base, L)}
+    G = AD.AdaptiveGrid(d, base, L, flags)
+    rng = np.random.default_rng(7)
+    eps = rng.choice([1.0, 100.0], size=len(G.leaf_cells()))
+    H = AD.build_adaptive(G, eps, transfer="boxmg")
+    for l in range(base + 1, L + 1):
+        Pr = O.boxmg_P(H.S[l], d, l)
+        assert abs(H.P[l] - Pr).max() <= 1e-12
+        assert H.P[l].nnz == Pr.nnz
+
+
+def test_boxmg_hanging_stencils_from_covering_cells():
+    """A hanging vertex's row is the rediscretised row of its level with the
+    missing cells carrying the coefficient of the leaf cell that covers them:
+    check one hanging vertex by hand from the element matrices."""
+    d, base, L = 2, 2, 4
+    G, _, _ = _problem(d, base, L, seed=6)
+    rng = np.random.default_rng(9)
+    eps_leaf = rng.uniform(0.5, 2.0, size=len(G.leaf_cells()))
+    eps = G.level_eps(eps_leaf)
+    Hs = AD.hanging_stencils(G, eps)
+    l = 3
+    v = tuple(np.argwhere(G.vtype[l] == AD.HANGING)[0])      # numpy order (y, x)
+    h = 3.0 ** -l
+    row = np.zeros(9)
+    for s in O.corners(d):                                    # v is corner s of cell v - s
+        cell = tuple(vi - si for vi, si in zip(v, reversed(s)))
+        if G.exist[l][cell]:
+            e = eps[l][cell]
+        else:                                                  # covered by a level-2 leaf cell
+            e = eps[l - 1][tuple(c // 3 for c in cell)]
+        K = O.element_matrix(d, h, e)
+        for ib, w in enumerate(O.corners(d)):
+            o = tuple(wi - si for wi, si in zip(w, s))        # x first
+            row[O.fem.flat_offset(o)] += K[O.fem.corner_index(s), ib]
+    n = 3 ** l
+    for k, o in enumerate(O.offsets(d)):                       # Dirichlet entries dropped
+        nb = (v[0] + o[1], v[1] + o[0])
+        if not (0 < nb[0] < n and 0 < nb[1] < n):
+            row[k] = 0.0
+    np.testing.assert_allclose(Hs[l][(slice(None),) + v], row, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("d,base,L", [(2, 2, 4), (3, 1, 3)])
+def test_boxmg_fas_cycles_converge_to_composite_solution(d, base, L):
+    """A random 9^d checkerboard of {1, 1e3} (jumps on level-2 faces): the
+    BoxMG FAS cycle converges to the directly solved composite system with
+    BoxMG hanging constraints."""
+    G, _, f = _problem(d, base, L, seed=8)
+    eps = _checkerboard_eps(G, seed=8)
+    H = AD.build_adaptive(G, eps, transfer="boxmg")
+    ustar, A, b = AD.solve_composite_direct(G, eps, f, AD.hanging_constraints(H))
+    u, hist = AD.solve_adaptive(H, f, tol=1e-12, max_cycles=300)
+    assert hist[-1] <= 1e-12
+    assert np.linalg.norm(u - ustar) <= 1e-9 * np.linalg.norm(ustar)
+    assert abs(np.linalg.norm(b - A @ u) / np.linalg.norm(b) - hist[-1]) <= 1e-14
+    rows = AD.composite_residual_rows(G, eps, f, u, np.arange(0, G.n_unknowns(), 11),
+                                      AD.hanging_constraints(H))
+    np.testing.assert_allclose(rows, (b - A @ u)[::11], atol=1e-13 * np.abs(b).max())

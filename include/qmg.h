@@ -147,10 +147,11 @@ int qmg_default_opts(qmg_solver_opts* opts);
  * spacetree a level keeps its lattice and launches only the 64 x 4 vertex
  * tiles that touch existing cells) in `device_buf` (or library memory when
  * NULL).  `stream` is a hipStream_t.  On success *out owns the grid.
- * Adaptive spacetrees take QMG_GEOMETRIC or QMG_GALERKIN_DLINEAR (QMG_EINVAL
- * otherwise) and every store; their cycle is the FAS V-cycle on the levels
- * above `base_level` and the correction-scheme cycle below (with FP32 iterates:
- * inner FAS cycles on the correction, the FP64 composite residual outside). */
+ * Adaptive spacetrees take every transfer and store; their cycle is the FAS
+ * V-cycle on the levels above `base_level` and the correction-scheme cycle
+ * below (with FP32 iterates: inner FAS cycles on the correction, the FP64
+ * composite residual outside).  With QMG_BOXMG, P is built per refined cell
+ * and also defines the hanging values (kept in FP64 on adaptive levels). */
 int qmg_create_grid(const qmg_grid_desc* desc, const qmg_solver_opts* opts, void* device_buf,
                     size_t bytes, void* stream, qmg_grid_t** out);
 

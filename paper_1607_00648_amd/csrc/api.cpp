@@ -209,8 +209,6 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
     if (!desc->refine) throw ApiError(QMG_EINVAL, "adaptive grid without refinement flags");
     if (o->coarsest_level > desc->base_level)
       throw ApiError(QMG_EINVAL, "coarsest_level must not exceed base_level");
-    if (o->transfer == QMG_BOXMG)
-      throw ApiError(QMG_EINVAL, "adaptive grids take the geometric or the d-linear Galerkin transfer");
   }
 }
 
@@ -300,6 +298,11 @@ int npartials(const Lat& L) {
   return (L.pitch / 64) * ((L.n + 1 + 3) / 4) * (L.d == 3 ? L.n + 1 : 1);
 }
 
+// Format of the stored prolongation of fine level l: the store's, except on
+// adaptive levels, where P also defines the hanging values of the composite
+// system and stays FP64.
+int p_fmt(const qmg_grid_t* g, int l) { return (g->adaptive && l > g->lb) ? (int)F64 : g->fmt; }
+
 // Lays out every buffer of the grid in the arena (measure or assign).
 void layout(qmg_grid_t* g, Arena& a) {
   const int d = g->d, L = g->Lmax, lcq = g->lcq;
@@ -349,13 +352,14 @@ void layout(qmg_grid_t* g, Arena& a) {
         if (g->fmt == F16) B.Ascale = a.take<int8_t>(ns);
       }
     }
-    if (l > lcq && !(g->adaptive && l > g->lb && !g->plain)) {
+    if (l > lcq) {
+      const int pf = p_fmt(g, l);
       if (g->plain) {
         B.Pdense = a.take<double>(ns * NC);
       } else if (boxmg) {
         B.Pblk = a.take<int32_t>(ns / kSeg);
-        B.Ppay = a.take<char>(ns * NC * fmt_size(g->fmt));
-        if (g->fmt == F16) B.Pscale = a.take<int8_t>(ns);
+        B.Ppay = a.take<char>(ns * NC * fmt_size(pf));
+        if (pf == F16) B.Pscale = a.take<int8_t>(ns);
       }
     }
   }
@@ -645,23 +649,24 @@ void smooth_ad(qmg_grid_t* g, LevelBuf& B, int sweeps) {
 // FAS V-cycle step on an adaptive level (Sect. 2): hanging vertices take the
 // interpolant of the coarser level, the leaf and refined vertices are
 // smoothed, refined coarse vertices receive the finer values (injection) and
-// the FAS right-hand side R r + A_c I u, the coarse level is cycled, and the
-// change of the coarse iterate is prolongated (d-linear).  The complete base
-// level continues with the correction-scheme cycle.
+// the FAS right-hand side R r + A_c I u (R = P^T), the coarse level is
+// cycled, and the change of the coarse iterate is prolongated (P: d-linear or
+// BoxMG, which also gives the hanging values).  The complete base level
+// continues with the correction-scheme cycle.
 template <typename T>
 void vcycle_ad(qmg_grid_t* g, int l) {
   LevelBuf& F = g->lv[l];
   LevelBuf& C = g->lv[l - 1];
   const AdTiles tf = F.ad(), tc = C.ad();
-  launch_ad_hang<T>(tf, C.L, (T*)F.u, (const T*)C.u, S(g));
+  launch_ad_hang<T>(tf, C.L, (T*)F.u, (const T*)C.u, F.P, S(g));
   smooth_ad<T>(g, F, g->opts.mu_pre);
   launch_ad_stencil<T, T>(tf, 2, (const T*)F.u, (const T*)F.b, (T*)F.r, eps_of<T>(F), F.A, (T)0, nullptr, S(g));
   launch_ad_inject<T>(tc, F.L, (const T*)F.u, (T*)C.u, S(g));
   launch_ad_copy<T>(tc, (const T*)C.u, (T*)C.sv, S(g));
-  launch_ad_fas_rhs<T>(tc, F.L, (const T*)F.r, (const T*)C.u, eps_of<T>(C), C.A, (T*)C.b, S(g));
+  launch_ad_fas_rhs<T>(tc, F.L, (const T*)F.r, (const T*)C.u, eps_of<T>(C), C.A, (T*)C.b, F.P, S(g));
   vcycle<T>(g, l - 1, false);
-  launch_ad_correct<T>(tf, C.L, (T*)F.u, (const T*)C.u, (const T*)C.sv, S(g));
-  launch_ad_hang<T>(tf, C.L, (T*)F.u, (const T*)C.u, S(g));
+  launch_ad_correct<T>(tf, C.L, (T*)F.u, (const T*)C.u, (const T*)C.sv, F.P, S(g));
+  launch_ad_hang<T>(tf, C.L, (T*)F.u, (const T*)C.u, F.P, S(g));
   smooth_ad<T>(g, F, g->opts.mu_post);
 }
 
@@ -674,7 +679,7 @@ void composite_state_of(qmg_grid_t* g, T* (*field)(LevelBuf&)) {
   for (int l = g->Lmax; l > g->lb; --l)
     launch_ad_inject<T>(g->lv[l - 1].ad(), g->lv[l].L, field(g->lv[l]), field(g->lv[l - 1]), S(g));
   for (int l = g->lb + 1; l <= g->Lmax; ++l)
-    launch_ad_hang<T>(g->lv[l].ad(), g->lv[l - 1].L, field(g->lv[l]), field(g->lv[l - 1]), S(g));
+    launch_ad_hang<T>(g->lv[l].ad(), g->lv[l - 1].L, field(g->lv[l]), field(g->lv[l - 1]), g->lv[l].P, S(g));
 }
 double* iterate64(LevelBuf& B) { return (double*)B.u; }
 float* iterate32(LevelBuf& B) { return (float*)B.u; }
@@ -852,13 +857,13 @@ std::vector<double> run_batch(qmg_grid_t* g, int B) {
 // ---------------------------------------------------------------------------
 // Build (Sect. 3.3 and 3.4; store of Sect. 4)
 // ---------------------------------------------------------------------------
-void encode(qmg_grid_t* g, LevelBuf& B, const Lat& Lc, bool is_P, const double* full, int slot) {
+void encode(qmg_grid_t* g, LevelBuf& B, const Lat& Lc, bool is_P, const double* full, int slot, int fmt) {
   int32_t* blk = is_P ? B.Pblk : B.Ablk;
   void* pay = is_P ? B.Ppay : B.Apay;
   int8_t* sc = is_P ? B.Pscale : B.Ascale;
   launch_delta_flags(B.L, Lc, is_P, full, B.eps64, blk, S(g));
   launch_scan_blocks(blk, B.L.nslot / kSeg, g->dtotal + slot, S(g));
-  launch_delta_write(B.L, Lc, is_P, g->fmt, full, B.eps64, blk, pay, sc, S(g));
+  launch_delta_write(B.L, Lc, is_P, fmt, full, B.eps64, blk, pay, sc, S(g));
 }
 
 void invert_dense(std::vector<double>& M, int n) {
@@ -946,7 +951,7 @@ void assign_stores(qmg_grid_t* g) {
     }
     if (boxmg && B.Pblk) {
       B.P.src = SRC_HIER;
-      B.P.fmt = g->fmt;
+      B.P.fmt = p_fmt(g, l);
       B.P.blk = B.Pblk;
       B.P.payload = B.Ppay;
       B.P.scale = B.Pscale;
@@ -970,6 +975,11 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
     else
       launch_coarsen_eps(g->lv[l].L, g->lv[l - 1].L, g->lv[l].eps64, g->lv[l - 1].eps64, s);
   }
+  // BoxMG on adaptive levels: cells that do not exist carry their covering
+  // cell's coefficient, from which hanging rows are rediscretised
+  if (g->adaptive && boxmg)
+    for (int l = g->lb + 1; l <= L; ++l)
+      launch_ad_virtual_eps(g->lv[l].L, g->lv[l - 1].L, g->lv[l - 1].cref, g->lv[l - 1].eps64, g->lv[l].eps64, s);
   if (g->mixed)
     for (int l = g->lcq; l <= L; ++l) launch_convert<double, float>(g->lv[l].L, g->lv[l].eps64, g->lv[l].eps32, s);
   g->lc = g->lcq;
@@ -1002,7 +1012,8 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
     if (boxmg) {
       double* Pt = g->plain ? F.Pdense : g->tmpP;
       launch_zero<double>(Pt, F.L.nslot * NC, s);
-      launch_boxmg(F.L, C.L, Afine, F.eps64, Pt, s);
+      const bool ad = g->adaptive && l > g->lb;
+      launch_boxmg(F.L, C.L, Afine, F.eps64, Pt, s, ad ? F.vt : nullptr, ad ? C.cref : nullptr);
       Pw = Pt;
     } else if (g->plain) {
       Store dl;
@@ -1039,11 +1050,11 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
     }
     if (!g->plain) {
       if (boxmg) {
-        encode(g, F, C.L, true, Pw, 2 * l + 1);
+        encode(g, F, C.L, true, Pw, 2 * l + 1, p_fmt(g, l));
         encodedP.push_back(l);
       }
       if (galerkin) {
-        encode(g, C, C.L, false, Ac, 2 * (l - 1));
+        encode(g, C, C.L, false, Ac, 2 * (l - 1), g->fmt);
         encodedA.push_back(l - 1);
       }
     }
@@ -1069,7 +1080,8 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
     const int64_t nb = g->lv[l].L.nslot / kSeg;
     blocks += nb;
     zero_blocks += nb - tot[2 * l + 1];
-    bytes += (size_t)nb * 4 + (size_t)tot[2 * l + 1] * kSeg * (NC * fmt_size(g->fmt) + (g->fmt == F16 ? 1 : 0));
+    const int pf = p_fmt(g, l);
+    bytes += (size_t)nb * 4 + (size_t)tot[2 * l + 1] * kSeg * (NC * fmt_size(pf) + (pf == F16 ? 1 : 0));
   }
   if (g->plain) {
     for (int l = g->lc; l <= L; ++l) bytes += (size_t)g->lv[l].L.nslot * NS * 8;

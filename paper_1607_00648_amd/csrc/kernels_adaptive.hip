@@ -85,25 +85,34 @@ __global__ __launch_bounds__(256) void k_ad_stencil(Lat L, const int32_t* __rest
   }
 }
 
-// hanging vertices of the fine level := d-linear interpolant of the coarse level
-template <int D, typename T>
-__global__ __launch_bounds__(256) void k_ad_hang(Lat Lf, Lat Lc, const int32_t* __restrict__ tiles,
-                                                 const int8_t* __restrict__ vt, T* __restrict__ uf,
-                                                 const T* __restrict__ uc) {
-  const Slot s = tile_slot<D>(Lf, tiles);
-  if (!s.valid || vt[s.v] != VT_HANGING) return;
-  const int qx = s.i / 3, qy = s.j / 3, qz = s.k / 3;
-  const int rx = s.i - 3 * qx, ry = s.j - 3 * qy, rz = s.k - 3 * qz;
+// (P (uc - sc))(f) at fine vertex (i,j,k), sc nullable; P d-linear (GEOM),
+// stored deltas (HIER) or plain weights
+template <int D, typename T, int PSRC, int PFMT>
+__device__ inline T interp_at(const Lat& Lf, const Lat& Lc, const Store& P, int i, int j, int k, int64_t vf,
+                              const T* __restrict__ uc, const T* __restrict__ sc) {
+  const int qx = i / 3, qy = j / 3, qz = k / 3;
+  const int rx = i - 3 * qx, ry = j - 3 * qy, rz = k - 3 * qz;
   const int64_t vc = qx + (int64_t)qy * Lc.pitch + (int64_t)qz * Lc.plane;
   T acc = (T)0;
 #pragma unroll
   for (int kap = 0; kap < Dim<D>::NC; ++kap) {
     const int kx = kap & 1, ky = (kap >> 1) & 1, kk = (kap >> 2) & 1;
     if ((kx && rx == 0) || (ky && ry == 0) || (kk && rz == 0)) continue;
-    const double w = dlin1(rx, kx) * dlin1(ry, ky) * (D == 3 ? dlin1(rz, kk) : 1.0);
-    acc += (T)w * uc[vc + slot_off(Lc, kx, ky, kk)];
+    const double w = pweight<D, PSRC, PFMT>(P, Lf, vf, rx, ry, rz, kap);
+    const int64_t c = vc + slot_off(Lc, kx, ky, kk);
+    acc += (T)w * (sc ? uc[c] - sc[c] : uc[c]);
   }
-  uf[s.v] = acc;
+  return acc;
+}
+
+// hanging vertices of the fine level := interpolant P u_c of the coarse level
+template <int D, typename T, int PSRC, int PFMT>
+__global__ __launch_bounds__(256) void k_ad_hang(Lat Lf, Lat Lc, const int32_t* __restrict__ tiles,
+                                                 const int8_t* __restrict__ vt, T* __restrict__ uf,
+                                                 const T* __restrict__ uc, Store P) {
+  const Slot s = tile_slot<D>(Lf, tiles);
+  if (!s.valid || vt[s.v] != VT_HANGING) return;
+  uf[s.v] = interp_at<D, T, PSRC, PFMT>(Lf, Lc, P, s.i, s.j, s.k, s.v, uc, (const T*)nullptr);
 }
 
 // refined coarse vertices := value of the finer copy (over coarse tiles)
@@ -116,43 +125,43 @@ __global__ __launch_bounds__(256) void k_ad_inject(Lat Lf, Lat Lc, const int32_t
   uc[s.v] = uf[3 * s.i + (int64_t)3 * s.j * Lf.pitch + (int64_t)3 * s.k * Lf.plane];
 }
 
-// FAS right-hand side of refined coarse vertices: (P^T r)(V) + (A_c u_c)(V),
-// d-linear P; r is zero off the fine active set
-template <int D, typename T, int SRC, int FMT>
+// FAS right-hand side of refined coarse vertices: (P^T r)(V) + (A_c u_c)(V);
+// r is zero off the fine active set
+template <int D, typename T, int SRC, int FMT, int PSRC, int PFMT>
 __global__ __launch_bounds__(256) void k_ad_fas_rhs(Lat Lf, Lat Lc, const int32_t* __restrict__ tiles,
                                                     const int8_t* __restrict__ vtc, const T* __restrict__ rf,
                                                     const T* __restrict__ uc, const T* __restrict__ epsc,
-                                                    Store Ac, T* __restrict__ bc) {
+                                                    Store Ac, T* __restrict__ bc, Store P) {
   constexpr int NS = Dim<D>::NS;
   const Slot s = tile_slot<D>(Lc, tiles);
   if (!s.valid || vtc[s.v] != VT_REFINED) return;
-  Store none;
-  const T rr = restrict_at<D, T, SRC_GEOM, F64>(Lf, rf, none, s.i, s.j, s.k);
+  const T rr = restrict_at<D, T, PSRC, PFMT>(Lf, rf, P, s.i, s.j, s.k);
   T a[NS];
   op_row<D, T, SRC, FMT>(epsc, Ac, Lc, s.v, a);
   bc[s.v] = rr + row_dot<D, T, SRC>(a, uc, Lc, s.v);
 }
 
-// FAS correction: active fine vertices += P (u_c - saved_c), d-linear P
-template <int D, typename T>
+// FAS correction: active fine vertices += P (u_c - saved_c)
+template <int D, typename T, int PSRC, int PFMT>
 __global__ __launch_bounds__(256) void k_ad_correct(Lat Lf, Lat Lc, const int32_t* __restrict__ tiles,
                                                     const int8_t* __restrict__ vt, T* __restrict__ uf,
-                                                    const T* __restrict__ uc, const T* __restrict__ sc) {
+                                                    const T* __restrict__ uc, const T* __restrict__ sc, Store P) {
   const Slot s = tile_slot<D>(Lf, tiles);
   if (!s.valid || !active(vt[s.v])) return;
-  const int qx = s.i / 3, qy = s.j / 3, qz = s.k / 3;
-  const int rx = s.i - 3 * qx, ry = s.j - 3 * qy, rz = s.k - 3 * qz;
-  const int64_t vc = qx + (int64_t)qy * Lc.pitch + (int64_t)qz * Lc.plane;
-  T acc = (T)0;
-#pragma unroll
-  for (int kap = 0; kap < Dim<D>::NC; ++kap) {
-    const int kx = kap & 1, ky = (kap >> 1) & 1, kk = (kap >> 2) & 1;
-    if ((kx && rx == 0) || (ky && ry == 0) || (kk && rz == 0)) continue;
-    const double w = dlin1(rx, kx) * dlin1(ry, ky) * (D == 3 ? dlin1(rz, kk) : 1.0);
-    const int64_t c = vc + slot_off(Lc, kx, ky, kk);
-    acc += (T)w * (uc[c] - sc[c]);
-  }
-  uf[s.v] += acc;
+  uf[s.v] += interp_at<D, T, PSRC, PFMT>(Lf, Lc, P, s.i, s.j, s.k, s.v, uc, sc);
+}
+
+// cell coefficients of cells that do not exist: the covering (parent) cell's
+template <int D>
+__global__ __launch_bounds__(256) void k_ad_virtual_eps(Lat Lf, Lat Lc, const int8_t* __restrict__ crefc,
+                                                        const double* __restrict__ ec, double* __restrict__ ef) {
+  const int I = blockIdx.x * TX + threadIdx.x;
+  const int J = blockIdx.y * TY + threadIdx.y;
+  const int K = (D == 3) ? (int)blockIdx.z : 0;
+  if (I >= Lf.n || J >= Lf.n || (D == 3 && K >= Lf.n)) return;
+  const int64_t pc = I / 3 + (int64_t)(J / 3) * Lc.pitch + (int64_t)(K / 3) * Lc.plane;
+  if (crefc[pc]) return;
+  ef[I + (int64_t)J * Lf.pitch + (int64_t)K * Lf.plane] = ec[pc];
 }
 
 // dst := src on every slot of the listed tiles
@@ -267,11 +276,11 @@ void ad_stencil_src(const AdTiles& t, int mode, const T* u, const T* b, TO* out,
   }
 }
 
-template <int D, typename T>
+template <int D, typename T, int PSRC>
 void ad_fas_src(const AdTiles& tc, const Lat& Lf, const T* rf, const T* uc, const T* epsc, const Store& Ac,
-                T* bc, hipStream_t s) {
+                T* bc, const Store& P, hipStream_t s) {
   const dim3 g = tiles_grid(tc.n), bl(TX, TY, 1);
-#define QMG_FAS(SRCV, FMTV) hipLaunchKernelGGL((k_ad_fas_rhs<D, T, SRCV, FMTV>), g, bl, 0, s, Lf, tc.L, tc.tiles, tc.vt, rf, uc, epsc, Ac, bc)
+#define QMG_FAS(SRCV, FMTV) hipLaunchKernelGGL((k_ad_fas_rhs<D, T, SRCV, FMTV, PSRC, F64>), g, bl, 0, s, Lf, tc.L, tc.tiles, tc.vt, rf, uc, epsc, Ac, bc, P)
   if (Ac.src == SRC_GEOM) QMG_FAS(SRC_GEOM, F64);
   else if (Ac.src == SRC_PLAIN) QMG_FAS(SRC_PLAIN, F64);
   else if (Ac.fmt == F64) QMG_FAS(SRC_HIER, F64);
@@ -279,6 +288,11 @@ void ad_fas_src(const AdTiles& tc, const Lat& Lf, const T* rf, const T* uc, cons
   else if (Ac.fmt == F16) QMG_FAS(SRC_HIER, F16);
   else QMG_FAS(SRC_HIER, BF16);
 #undef QMG_FAS
+}
+
+// prolongation stores of adaptive levels: d-linear, FP64 deltas or plain
+inline void check_ad_P(const Store& P) {
+  if (P.src == SRC_HIER && P.fmt != F64) throw HipError("adaptive levels keep their prolongation in FP64");
 }
 
 }  // namespace
@@ -296,11 +310,17 @@ template void launch_ad_stencil<float, float>(const AdTiles&, int, const float*,
 template void launch_ad_stencil<double, float>(const AdTiles&, int, const double*, const double*, float*, const double*, const Store&, double, double*, hipStream_t);
 
 template <typename T>
-void launch_ad_hang(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, hipStream_t s) {
+void launch_ad_hang(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const Store& P, hipStream_t s) {
   if (tf.n <= 0) return;
+  check_ad_P(P);
   const dim3 g = tiles_grid(tf.n), bl(TX, TY, 1);
-  if (tf.L.d == 2) hipLaunchKernelGGL((k_ad_hang<2, T>), g, bl, 0, s, tf.L, Lc, tf.tiles, tf.vt, uf, uc);
-  else hipLaunchKernelGGL((k_ad_hang<3, T>), g, bl, 0, s, tf.L, Lc, tf.tiles, tf.vt, uf, uc);
+#define QMG_HANG(DV, PS) hipLaunchKernelGGL((k_ad_hang<DV, T, PS, F64>), g, bl, 0, s, tf.L, Lc, tf.tiles, tf.vt, uf, uc, P)
+  if (tf.L.d == 2) {
+    if (P.src == SRC_HIER) QMG_HANG(2, SRC_HIER); else if (P.src == SRC_PLAIN) QMG_HANG(2, SRC_PLAIN); else QMG_HANG(2, SRC_GEOM);
+  } else {
+    if (P.src == SRC_HIER) QMG_HANG(3, SRC_HIER); else if (P.src == SRC_PLAIN) QMG_HANG(3, SRC_PLAIN); else QMG_HANG(3, SRC_GEOM);
+  }
+#undef QMG_HANG
   QMG_HIP(hipGetLastError());
 }
 
@@ -315,19 +335,43 @@ void launch_ad_inject(const AdTiles& tc, const Lat& Lf, const T* uf, T* uc, hipS
 
 template <typename T>
 void launch_ad_fas_rhs(const AdTiles& tc, const Lat& Lf, const T* rf, const T* uc, const T* epsc,
-                       const Store& Ac, T* bc, hipStream_t s) {
+                       const Store& Ac, T* bc, const Store& P, hipStream_t s) {
   if (tc.n <= 0) return;
-  if (tc.L.d == 2) ad_fas_src<2, T>(tc, Lf, rf, uc, epsc, Ac, bc, s);
-  else ad_fas_src<3, T>(tc, Lf, rf, uc, epsc, Ac, bc, s);
+  check_ad_P(P);
+  if (tc.L.d == 2) {
+    if (P.src == SRC_HIER) ad_fas_src<2, T, SRC_HIER>(tc, Lf, rf, uc, epsc, Ac, bc, P, s);
+    else if (P.src == SRC_PLAIN) ad_fas_src<2, T, SRC_PLAIN>(tc, Lf, rf, uc, epsc, Ac, bc, P, s);
+    else ad_fas_src<2, T, SRC_GEOM>(tc, Lf, rf, uc, epsc, Ac, bc, P, s);
+  } else {
+    if (P.src == SRC_HIER) ad_fas_src<3, T, SRC_HIER>(tc, Lf, rf, uc, epsc, Ac, bc, P, s);
+    else if (P.src == SRC_PLAIN) ad_fas_src<3, T, SRC_PLAIN>(tc, Lf, rf, uc, epsc, Ac, bc, P, s);
+    else ad_fas_src<3, T, SRC_GEOM>(tc, Lf, rf, uc, epsc, Ac, bc, P, s);
+  }
   QMG_HIP(hipGetLastError());
 }
 
 template <typename T>
-void launch_ad_correct(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const T* sc, hipStream_t s) {
+void launch_ad_correct(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const T* sc, const Store& P,
+                       hipStream_t s) {
   if (tf.n <= 0) return;
+  check_ad_P(P);
   const dim3 g = tiles_grid(tf.n), bl(TX, TY, 1);
-  if (tf.L.d == 2) hipLaunchKernelGGL((k_ad_correct<2, T>), g, bl, 0, s, tf.L, Lc, tf.tiles, tf.vt, uf, uc, sc);
-  else hipLaunchKernelGGL((k_ad_correct<3, T>), g, bl, 0, s, tf.L, Lc, tf.tiles, tf.vt, uf, uc, sc);
+#define QMG_CORR(DV, PS) hipLaunchKernelGGL((k_ad_correct<DV, T, PS, F64>), g, bl, 0, s, tf.L, Lc, tf.tiles, tf.vt, uf, uc, sc, P)
+  if (tf.L.d == 2) {
+    if (P.src == SRC_HIER) QMG_CORR(2, SRC_HIER); else if (P.src == SRC_PLAIN) QMG_CORR(2, SRC_PLAIN); else QMG_CORR(2, SRC_GEOM);
+  } else {
+    if (P.src == SRC_HIER) QMG_CORR(3, SRC_HIER); else if (P.src == SRC_PLAIN) QMG_CORR(3, SRC_PLAIN); else QMG_CORR(3, SRC_GEOM);
+  }
+#undef QMG_CORR
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_ad_virtual_eps(const Lat& Lf, const Lat& Lc, const int8_t* crefc, const double* ec, double* ef,
+                           hipStream_t s) {
+  const dim3 g((unsigned)(Lf.pitch / TX), (unsigned)((Lf.n + TY - 1) / TY), (unsigned)(Lf.d == 3 ? Lf.n : 1));
+  const dim3 bl(TX, TY, 1);
+  if (Lf.d == 2) hipLaunchKernelGGL(k_ad_virtual_eps<2>, g, bl, 0, s, Lf, Lc, crefc, ec, ef);
+  else hipLaunchKernelGGL(k_ad_virtual_eps<3>, g, bl, 0, s, Lf, Lc, crefc, ec, ef);
   QMG_HIP(hipGetLastError());
 }
 
@@ -385,14 +429,14 @@ void launch_ad_gather(const int64_t* slots, int64_t n, const T* lat, double* out
   QMG_HIP(hipGetLastError());
 }
 
-template void launch_ad_hang<double>(const AdTiles&, const Lat&, double*, const double*, hipStream_t);
-template void launch_ad_hang<float>(const AdTiles&, const Lat&, float*, const float*, hipStream_t);
+template void launch_ad_hang<double>(const AdTiles&, const Lat&, double*, const double*, const Store&, hipStream_t);
+template void launch_ad_hang<float>(const AdTiles&, const Lat&, float*, const float*, const Store&, hipStream_t);
 template void launch_ad_inject<double>(const AdTiles&, const Lat&, const double*, double*, hipStream_t);
 template void launch_ad_inject<float>(const AdTiles&, const Lat&, const float*, float*, hipStream_t);
-template void launch_ad_fas_rhs<double>(const AdTiles&, const Lat&, const double*, const double*, const double*, const Store&, double*, hipStream_t);
-template void launch_ad_fas_rhs<float>(const AdTiles&, const Lat&, const float*, const float*, const float*, const Store&, float*, hipStream_t);
-template void launch_ad_correct<double>(const AdTiles&, const Lat&, double*, const double*, const double*, hipStream_t);
-template void launch_ad_correct<float>(const AdTiles&, const Lat&, float*, const float*, const float*, hipStream_t);
+template void launch_ad_fas_rhs<double>(const AdTiles&, const Lat&, const double*, const double*, const double*, const Store&, double*, const Store&, hipStream_t);
+template void launch_ad_fas_rhs<float>(const AdTiles&, const Lat&, const float*, const float*, const float*, const Store&, float*, const Store&, hipStream_t);
+template void launch_ad_correct<double>(const AdTiles&, const Lat&, double*, const double*, const double*, const Store&, hipStream_t);
+template void launch_ad_correct<float>(const AdTiles&, const Lat&, float*, const float*, const float*, const Store&, hipStream_t);
 template void launch_ad_copy<double>(const AdTiles&, const double*, double*, hipStream_t);
 template void launch_ad_copy<float>(const AdTiles&, const float*, float*, hipStream_t);
 template void launch_ad_zero<double>(const AdTiles&, double*, hipStream_t);

@@ -102,8 +102,13 @@ struct BoxFetch {
   const double* eps;
   Lat L;
   const int8_t* vt = nullptr;  // optional: rows only at leaf and refined vertices
+  bool hanging_rows = false;   // with vt: hanging rows rediscretised from eps
   __device__ double operator()(int64_t v, int i, int j, int k, int kk) const {
-    if (vt && vt[v] != VT_LEAF && vt[v] != VT_REFINED) return 0.0;
+    if (vt) {
+      const int8_t t = vt[v];
+      if (hanging_rows && t == VT_HANGING) return geom_entry<D>(eps, v, i, j, k, kk, L);
+      if (t != VT_LEAF && t != VT_REFINED) return 0.0;
+    }
     if (A) return A[(int64_t)kk * L.nslot + v];
     return geom_entry<D>(eps, v, i, j, k, kk, L);
   }
@@ -194,8 +199,18 @@ __device__ inline void box_group(const BoxFetch<D>& F, int Vx, int Vy, int Vz, i
   }
 }
 
+// refined flag of the coarse cell of orthant (sx, sy, sz) at coarse vertex V
+__device__ inline bool orthant_refined(const int8_t* cref, const Lat& Lc, int Vx, int Vy, int Vz, int sx, int sy,
+                                       int sz) {
+  const int cx = Vx + (sx < 0 ? -1 : 0), cy = Vy + (sy < 0 ? -1 : 0), cz = Vz + (sz < 0 ? -1 : 0);
+  return cref[cx + (int64_t)cy * Lc.pitch + (int64_t)cz * Lc.plane] != 0;
+}
+
+// cref (nullable): refined flags of the coarse cells; patches of cells that
+// are not refined are skipped (adaptive levels)
 template <int D>
-__global__ __launch_bounds__(64) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, double* __restrict__ Pw) {
+__global__ __launch_bounds__(64) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, double* __restrict__ Pw,
+                                              const int8_t* __restrict__ cref) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int m = Lc.n - 1;
   const int64_t nV = (D == 3) ? (int64_t)m * m * m : (int64_t)m * m;
@@ -204,6 +219,7 @@ __global__ __launch_bounds__(64) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, dou
   const int64_t Vi = t / Dim<D>::NC;
   const int Vx = (int)(Vi % m) + 1, Vy = (int)((Vi / m) % m) + 1, Vz = (D == 3) ? (int)(Vi / ((int64_t)m * m)) + 1 : 0;
   const int sx = (orth & 1) ? -1 : 1, sy = (orth & 2) ? -1 : 1, sz = (D == 3 && (orth & 4)) ? -1 : 1;
+  if (cref && !orthant_refined(cref, Lc, Vx, Vy, Vz, sx, sy, sz)) return;
   double p[27];
 #pragma unroll
   for (int q = 0; q < 27; ++q) p[q] = 0.0;
@@ -220,12 +236,30 @@ __global__ __launch_bounds__(64) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, dou
     box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p);
   }
   // write the reference region; a point on an axis (y_i = 0) is shared by the
-  // orthants that differ only on that axis and is written by the + orthant
+  // orthants that differ only on such axes.  It is written by the one of
+  // lowest rank (rank: bit i set when the orthant is negative on shared axis
+  // i) among those whose patch is computed: the + orthant on regular levels,
+  // the next refined one on adaptive levels
   const int zmax = (D == 3) ? 3 : 1;
+  const int sneg = (sx < 0 ? 1 : 0) | (sy < 0 ? 2 : 0) | (sz < 0 ? 4 : 0);
   for (int yz = 0; yz < zmax; ++yz)
     for (int yy = 0; yy < 3; ++yy)
       for (int yx = 0; yx < 3; ++yx) {
-        if ((yx == 0 && sx < 0) || (yy == 0 && sy < 0) || (D == 3 && yz == 0 && sz < 0)) continue;
+        const int zmask = (yx == 0 ? 1 : 0) | (yy == 0 ? 2 : 0) | ((D == 3 && yz == 0) ? 4 : 0);
+        const int myrank = sneg & zmask;
+        bool mine = true;
+        if (cref == nullptr) {
+          mine = myrank == 0;
+        } else {
+          for (int c = 0; c < myrank && mine; ++c) {
+            if ((c & ~zmask) != 0) continue;  // candidates differ on shared axes only
+            const int ox = (zmask & 1) ? ((c & 1) ? -1 : 1) : sx;
+            const int oy = (zmask & 2) ? ((c & 2) ? -1 : 1) : sy;
+            const int oz = (zmask & 4) ? ((c & 4) ? -1 : 1) : sz;
+            if (orthant_refined(cref, Lc, Vx, Vy, Vz, ox, oy, oz)) mine = false;
+          }
+        }
+        if (!mine) continue;
         const int fx = 3 * Vx + sx * yx, fy = 3 * Vy + sy * yy, fz = 3 * Vz + sz * yz;
         const int kap = ((sx < 0 && yx > 0) ? 1 : 0) | ((sy < 0 && yy > 0) ? 2 : 0) |
                         ((D == 3 && sz < 0 && yz > 0) ? 4 : 0);
@@ -496,17 +530,17 @@ void launch_materialise_P(const Lat& Lf, const Lat& Lc, const Store& P, double* 
 }
 
 void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf, double* Pw,
-                  hipStream_t s) {
+                  hipStream_t s, const int8_t* vt_fine, const int8_t* cref_coarse) {
   const int m = Lc.n - 1;
   if (m <= 0) return;
   if (Lf.d == 2) {
     const int64_t nt = (int64_t)m * m * 4;
-    BoxFetch<2> F{Afine, epsf, Lf};
-    hipLaunchKernelGGL(k_boxmg<2>, dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw);
+    BoxFetch<2> F{Afine, epsf, Lf, vt_fine, vt_fine != nullptr};
+    hipLaunchKernelGGL(k_boxmg<2>, dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse);
   } else {
     const int64_t nt = (int64_t)m * m * m * 8;
-    BoxFetch<3> F{Afine, epsf, Lf};
-    hipLaunchKernelGGL(k_boxmg<3>, dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw);
+    BoxFetch<3> F{Afine, epsf, Lf, vt_fine, vt_fine != nullptr};
+    hipLaunchKernelGGL(k_boxmg<3>, dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse);
   }
   QMG_HIP(hipGetLastError());
 }

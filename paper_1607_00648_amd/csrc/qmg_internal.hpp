@@ -153,8 +153,13 @@ void launch_materialise_P(const Lat& Lf, const Lat& Lc, const Store& P, double* 
 // BoxMG P (Sect. 3.4): writes 2^d*nslot FP64 parent weights of the fine level.
 // Afine: FP64 stencils of the fine level (entry-major); when null, the fine
 // operator is rediscretised from epsf on the fly.
+// vt_fine / cref_coarse (adaptive levels, nullable): fine vertex classes (rows
+// of leaf and refined vertices from Afine or eps, hanging rows rediscretised
+// from eps, others zero) and the refined flags of the coarse cells (only
+// refined cells are patches).
 void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
-                  double* Pw, hipStream_t s);
+                  double* Pw, hipStream_t s, const int8_t* vt_fine = nullptr,
+                  const int8_t* cref_coarse = nullptr);
 // Galerkin RAP (Sect. 3.3): coarse FP64 stencils from fine stencils (or eps on
 // the fly when Afine is null) and FP64 parent weights (d-linear when Pw null).
 // vt_fine (nullable): vertex classes of the fine level; rows of vertices that
@@ -253,15 +258,20 @@ struct AdTiles {
 template <typename T, typename TO>
 void launch_ad_stencil(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
                        const Store& A, T omega, double* partial, hipStream_t s);
+// P: the fine level's prolongation store (d-linear, FP64 deltas, or plain)
 template <typename T>
-void launch_ad_hang(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, hipStream_t s);
+void launch_ad_hang(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const Store& P, hipStream_t s);
 template <typename T>
 void launch_ad_inject(const AdTiles& tc, const Lat& Lf, const T* uf, T* uc, hipStream_t s);
 template <typename T>
 void launch_ad_fas_rhs(const AdTiles& tc, const Lat& Lf, const T* rf, const T* uc, const T* epsc,
-                       const Store& Ac, T* bc, hipStream_t s);
+                       const Store& Ac, T* bc, const Store& P, hipStream_t s);
 template <typename T>
-void launch_ad_correct(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const T* sc, hipStream_t s);
+void launch_ad_correct(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const T* sc, const Store& P,
+                       hipStream_t s);
+// coefficients of the level-l cells that do not exist := their parent cell's
+void launch_ad_virtual_eps(const Lat& Lf, const Lat& Lc, const int8_t* crefc, const double* ec, double* ef,
+                           hipStream_t s);
 template <typename T>
 void launch_ad_copy(const AdTiles& t, const T* src, T* dst, hipStream_t s);
 template <typename T>

@@ -70,7 +70,9 @@ def test_adaptive_description_validation():
     assert nb.value > 0
     assert lib.qmg_workspace_bytes(C.byref(d), C.byref(qmg.make_opts(transfer="galerkin", store="bf16")),
                                    C.byref(nb)) == qmg.QMG_OK
-    for bad in (qmg.make_opts(transfer="boxmg"), qmg.make_opts(transfer="galerkin", coarsest_level=3)):
+    for good in (qmg.make_opts(transfer="boxmg"), qmg.make_opts(transfer="boxmg", store="hier16")):
+        assert lib.qmg_workspace_bytes(C.byref(d), C.byref(good), C.byref(nb)) == qmg.QMG_OK
+    for bad in (qmg.make_opts(transfer="galerkin", coarsest_level=3),):
         assert lib.qmg_workspace_bytes(C.byref(d), C.byref(bad), C.byref(nb)) == qmg.QMG_EINVAL
     no_flags = qmg.GridDesc(2, 4, 2, None)
     assert lib.qmg_workspace_bytes(C.byref(no_flags), C.byref(ok), C.byref(nb)) == qmg.QMG_EINVAL

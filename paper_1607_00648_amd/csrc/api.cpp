@@ -1032,7 +1032,7 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
       launch_zero<double>(Ac, C.L.nslot * NS, s);
       // the finest adaptive level's rows exist only at leaf vertices
       const int8_t* mask = (g->adaptive && l == L && !Afine) ? F.vt : nullptr;
-      launch_rap(F.L, C.L, Afine, F.eps64, Pw, Ac, s, mask);
+      launch_rap(F.L, C.L, Afine, F.eps64, Pw, Ac, s, mask, (g->adaptive && l - 1 >= g->lb) ? C.vt : nullptr);
       merge(l - 1, Ac);
       // the fallback of a failed check raises the coarsest level, which is
       // possible only below the base level of an adaptive spacetree

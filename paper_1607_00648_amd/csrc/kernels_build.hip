@@ -291,9 +291,12 @@ struct PFetch {
   }
 };
 
+// vtc (nullable): coarse vertex classes; rows of vertices that are not
+// refined are left zero (an adaptive level replaces them by rediscretised or
+// empty rows)
 template <int D>
 __global__ __launch_bounds__(256) void k_rap(Lat Lf, Lat Lc, BoxFetch<D> A, PFetch<D> P,
-                                             double* __restrict__ Ac) {
+                                             double* __restrict__ Ac, const int8_t* __restrict__ vtc) {
   constexpr int NS = Dim<D>::NS;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int m = Lc.n - 1;
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(256) void k_rap(Lat Lf, Lat Lc, BoxFetch<D> A, PFet
   const int Wx = Vx + off_x(kd), Wy = Vy + off_y(kd), Wz = Vz + (D == 3 ? off_z(kd) : 0);
   const int64_t vc = Vx + (int64_t)Vy * Lc.pitch + (int64_t)Vz * Lc.plane;
   double acc = 0.0;
-  if (interior(Lc, Wx, Wy, Wz)) {
+  if (interior(Lc, Wx, Wy, Wz) && (vtc == nullptr || vtc[vc] == VT_REFINED)) {
     const int ilx = max(3 * Vx - 2, 3 * Wx - 3), ihx = min(3 * Vx + 2, 3 * Wx + 3);
     const int ily = max(3 * Vy - 2, 3 * Wy - 3), ihy = min(3 * Vy + 2, 3 * Wy + 3);
     const int ilz = (D == 3) ? max(3 * Vz - 2, 3 * Wz - 3) : 0, ihz = (D == 3) ? min(3 * Vz + 2, 3 * Wz + 3) : 0;
@@ -546,19 +549,19 @@ void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const doubl
 }
 
 void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
-                const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine) {
+                const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine, const int8_t* vt_coarse) {
   const int m = Lc.n - 1;
   if (m <= 0) return;
   if (Lf.d == 2) {
     const int64_t nt = (int64_t)m * m * 9;
     BoxFetch<2> A{Afine, epsf, Lf, vt_fine};
     PFetch<2> P{Pw, Lf, Lc};
-    hipLaunchKernelGGL(k_rap<2>, dim3(blocks_for(nt, 256)), dim3(256), 0, s, Lf, Lc, A, P, Ac);
+    hipLaunchKernelGGL(k_rap<2>, dim3(blocks_for(nt, 256)), dim3(256), 0, s, Lf, Lc, A, P, Ac, vt_coarse);
   } else {
     const int64_t nt = (int64_t)m * m * m * 27;
     BoxFetch<3> A{Afine, epsf, Lf, vt_fine};
     PFetch<3> P{Pw, Lf, Lc};
-    hipLaunchKernelGGL(k_rap<3>, dim3(blocks_for(nt, 256)), dim3(256), 0, s, Lf, Lc, A, P, Ac);
+    hipLaunchKernelGGL(k_rap<3>, dim3(blocks_for(nt, 256)), dim3(256), 0, s, Lf, Lc, A, P, Ac, vt_coarse);
   }
   QMG_HIP(hipGetLastError());
 }

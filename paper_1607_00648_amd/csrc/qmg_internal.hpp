@@ -164,8 +164,10 @@ void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const doubl
 // the fly when Afine is null) and FP64 parent weights (d-linear when Pw null).
 // vt_fine (nullable): vertex classes of the fine level; rows of vertices that
 // are neither leaf nor refined count as zero.
+// vt_coarse (nullable): only rows of refined coarse vertices are formed.
 void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
-                const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine = nullptr);
+                const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine = nullptr,
+                const int8_t* vt_coarse = nullptr);
 // Definiteness check of coarse stencils; counts failing rows into *bad.
 void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s);
 // Hierarchical delta store: per-block zero flags, compaction and payload.  The

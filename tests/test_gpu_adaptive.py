@@ -433,3 +433,26 @@ def test_boxmg_balls_full_size_mixed():
     rel = np.linalg.norm(sol["bf16"] - sol["hier64"]) / np.linalg.norm(sol["hier64"])
     print(f"[cfg3 boxmg] bf16 vs fp64 solution: {rel:.2e}")
     assert rel <= 1e-5
+
+
+def test_band_midsize_boxmg_cycles_match_oracle():
+    """The level-set band workload with 1e6 cube inclusions (base 2, level 4):
+    the first BoxMG FAS cycles against the oracle.  With V(2,2) damped Jacobi
+    this coefficient field makes the cycle diverge, on both sides alike; the
+    comparison is of the iterates, relative to their size."""
+    qmg = require_gpu()
+    announce("adaptive band 3D base2 L4 boxmg cycles")
+    P = W.adaptive_band(dim=3, base=2, level=4)
+    G = AD.AdaptiveGrid(P.dim, P.base, P.level, P.flags)
+    eps, f = _workload_inputs(P, G)
+    H = AD.build_adaptive(G, eps, transfer="boxmg")
+    k = 3
+    u_o, hist_o = AD.solve_adaptive(H, f, cycles=k)
+    g = _grid(qmg, 3, P.base, P.level, P.flags, transfer="boxmg", check_definite=False)
+    g.set_coefficients(eps, f)
+    assert g.build()["coarsest_level_used"] == 1
+    rr = g.vcycle(k)
+    np.testing.assert_allclose(rr, hist_o, rtol=1e-6)
+    u = g.solution()
+    assert np.abs(u - u_o).max() <= 1e-6 * np.abs(u_o).max()
+    g.close()

@@ -309,3 +309,58 @@ def test_profiling_and_graphs_leave_results_unchanged():
         g.close()
     for hist, u in out[1:]:
         assert np.array_equal(hist, out[0][0]) and np.array_equal(u, out[0][1])
+
+
+@pytest.mark.parametrize("d,L,mu,omega,lc", [
+    (2, 4, (1, 1), 0.6, 1),     # single-sweep passes
+    (2, 4, (2, 1), 0.6, 1),     # odd sweep count per cycle: eager launches
+    (2, 5, (3, 3), 0.8, 1),     # a pass of two sweeps then one of one
+    (2, 4, (2, 2), 0.6, 2),     # coarsest level 2: 64 unknowns, exact solve
+    (3, 3, (1, 2), 0.7, 1),
+    (3, 3, (2, 2), 0.6, 2),     # 3D coarsest level 2: 512 unknowns
+])
+def test_cycle_options_match_oracle(d, L, mu, omega, lc):
+    """Smoothing counts, damping and coarsest level other than the defaults:
+    iterates and residual histories against the oracle (Galerkin, moderate
+    contrast, so rounding stays far below the tolerance)."""
+    qmg = require_gpu()
+    announce(f"cycle options d={d} L={L} mu={mu} omega={omega} lc={lc}")
+    p = W.random_checkerboard(d, L, seed=3, values=(1.0, 10.0))
+    g = qmg.Grid(d, L, qmg.make_opts("galerkin", "hier64", mu=mu, omega=omega, coarsest_level=lc))
+    g.set_coefficients(p.eps, p.f)
+    info = g.build()
+    assert info["coarsest_level_used"] == lc
+    k = 5
+    rr = g.vcycle(k)
+    u = g.solution()
+    g.close()
+    H = O.build_hierarchy(p.eps, d, L, transfer="galerkin", lc=lc, omega=omega, mu_pre=mu[0], mu_post=mu[1])
+    b = O.rhs_from_f(p.f, d, L)
+    uo, hist = O.solve(H, b, cycles=k)
+    np.testing.assert_allclose(rr, hist, rtol=1e-10, atol=1e-14)
+    assert np.abs(u - uo).max() <= 1e-11 * np.abs(uo).max()
+
+
+@pytest.mark.parametrize("store", ["hier32", "bf16"])
+def test_mixed_inner_cycles(store):
+    """Two FP32 inner cycles per FP64 outer iteration: fewer outer iterations,
+    the same FP64 tolerance (recomputed by the oracle)."""
+    qmg = require_gpu()
+    announce(f"mixed inner cycles 2 {store}")
+    p = W.random_checkerboard(2, 5, seed=4, values=(1.0, 1e3))
+    out = {}
+    for inner in (1, 2):
+        g = qmg.Grid(2, 5, qmg.make_opts("boxmg", store, inner_cycles=inner))
+        g.set_coefficients(p.eps, p.f)
+        g.build()
+        rep, _ = g.solve(1e-8, 300)
+        assert rep["status"] == "QMG_OK"
+        out[inner] = (rep, g.solution())
+        g.close()
+    H = O.build_hierarchy(p.eps, 2, 5, transfer="boxmg")
+    b = O.rhs_from_f(p.f, 2, 5)
+    for inner, (rep, u) in out.items():
+        rr = np.linalg.norm(b - H.A[5] @ u) / np.linalg.norm(b)
+        assert rr <= 1e-8 * (1 + 1e-6)
+    assert out[2][0]["outer_iters"] < out[1][0]["outer_iters"]
+    assert out[2][0]["cycles"] == 2 * (out[2][0]["outer_iters"] - 1)

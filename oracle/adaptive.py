@@ -575,21 +575,28 @@ def initial_state(H, f_leaf):
     return u, b
 
 
-def solve_adaptive(H, f_leaf, tol=1e-8, max_cycles=200, cycles=None):
-    """FAS V-cycles from zero; returns (leaf values, relres history)."""
+def solve_adaptive(H, f_leaf, tol=1e-8, max_cycles=200, cycles=None, stagnation=0.0):
+    """FAS V-cycles from zero; returns (leaf values, relres history).  With
+    ``stagnation`` > 0 the coarsest level of the regular levels moves up (to
+    the base level at most) after a cycle that reduced the composite residual
+    by less than that factor (Sect. 3.3)."""
     u, b = initial_state(H, f_leaf)
     b0 = {l: v.copy() for l, v in b.items()}
     bl = np.concatenate([b0[l][H.G.vtype[l] == LEAF] for l in range(H.base, H.L + 1)])
     nb = np.linalg.norm(bl)
     hist = []
+    prev = 1.0
     n = cycles if cycles is not None else max_cycles
-    for _ in range(n):
+    for k in range(n):
         fas_cycle(H, H.L, u, b)
         composite_state(H, u)
         # leaf right-hand sides are the PDE ones (FAS only rewrites refined rows)
         hist.append(float(np.linalg.norm(composite_residual(H, u, b0)) / nb))
         if cycles is None and hist[-1] <= tol:
             break
+        if k + 1 < n and S.stagnated(hist[-1], prev, stagnation, tol):
+            S.raise_coarsest(H.regular, top=min(H.base, H.L - 1))
+        prev = hist[-1]
     return leaf_vector(H, u), hist
 
 

@@ -7,6 +7,8 @@
   operator fails the diagonal check.
 * Results section ("/e"): an exact coarsest-level solve; otherwise mu_pre+mu_post
   Jacobi sweeps on the coarsest level.
+* Sect. 3.3 (dynamic coarsest level): between two cycles the coarsest level
+  moves one level up when the residual stagnates or grows (``raise_coarsest``).
 
 Readings:
 
@@ -19,6 +21,13 @@ Readings:
   unknowns, otherwise by mu_pre + mu_post Jacobi sweeps from zero.
 * The relative residual is the unweighted 2-norm over interior unknowns relative
   to ||b||_2 (the paper reduces ||r||_2 by 1e8).
+* Stagnation is read as ||r_k|| > theta ||r_{k-1}|| for a threshold theta
+  (an option; the paper names none), checked after every cycle that has not
+  reached the tolerance, ||r_0|| being the residual of the start value.  The
+  level moves up to L - 1 at most (the base level on an adaptive grid); the new
+  coarsest level is solved exactly with its own operator when it has at most
+  COARSE_DIRECT_MAX unknowns, otherwise by mu_pre + mu_post sweeps, and the
+  raise lasts for the rest of the hierarchy's life.
 * Mixed precision (not in the paper): an FP64 defect-correction loop
   x += V32(fp32(b - A x)) whose inner V-cycles run in FP32 on operators rebuilt
   from quantised hierarchical deltas (see ``store``); the coarsest solve of the
@@ -137,22 +146,48 @@ def vcycle(H, l, u, b):
     return u
 
 
+def raise_coarsest(H, top=None):
+    """Dynamic coarsest level (Sect. 3.3): move l_c one level up, to ``top``
+    (default L - 1) at most; the new coarsest level is solved with its own
+    operator.  Returns whether the level moved."""
+    top = H.L - 1 if top is None else top
+    if H.lc + 1 > top:
+        return False
+    H.lc += 1
+    Ac = H.A[H.lc]
+    H.coarse_lu = sla.lu_factor(Ac.toarray().astype(np.float64)) if Ac.shape[0] <= COARSE_DIRECT_MAX else None
+    return True
+
+
+def stagnated(rr, rr_prev, theta, tol):
+    """The trigger of the dynamic coarsest level: not converged, and the
+    residual fell by less than the factor theta (or grew) over the cycle."""
+    return theta > 0 and rr > tol and rr > theta * rr_prev
+
+
 def relres(A, u, b):
     return float(np.linalg.norm(b - A @ u) / np.linalg.norm(b))
 
 
-def solve(H, b, tol=1e-8, max_cycles=100, u0=None, cycles=None):
+def solve(H, b, tol=1e-8, max_cycles=100, u0=None, cycles=None, stagnation=0.0):
     """V-cycles from u0 (default 0) until ||b - A u|| / ||b|| <= tol, or exactly
-    ``cycles`` cycles when given.  Returns (u, history of relres per cycle)."""
+    ``cycles`` cycles when given.  With ``stagnation`` > 0 the coarsest level
+    moves up after a cycle that reduced the residual by less than that factor.
+    Returns (u, history of relres per cycle)."""
     A = H.A[H.L]
     u = np.zeros(A.shape[0]) if u0 is None else np.array(u0, dtype=np.float64)
     hist: List[float] = []
+    prev = relres(A, u, b)
     n = cycles if cycles is not None else max_cycles
-    for _ in range(n):
+    for k in range(n):
         u = vcycle(H, H.L, u, b)
         hist.append(relres(A, u, b))
         if cycles is None and hist[-1] <= tol:
             break
+        # the check runs only between two cycles
+        if k + 1 < n and stagnated(hist[-1], prev, stagnation, tol):
+            raise_coarsest(H)
+        prev = hist[-1]
     return u, hist
 
 
@@ -205,8 +240,10 @@ def quantised_hierarchy(H, fmt):
     return Hq
 
 
-def mixed_solve(H, Hq, b, tol=1e-8, max_outer=100, inner_cycles=1):
+def mixed_solve(H, Hq, b, tol=1e-8, max_outer=100, inner_cycles=1, stagnation=0.0):
     """FP64 defect correction around FP32 inner V-cycles (see module notes).
+    With ``stagnation`` > 0 the inner hierarchy's coarsest level moves up after
+    an outer iteration that reduced the residual by less than that factor.
     Returns (x, relres history)."""
     A = H.A[H.L]
     x = np.zeros(A.shape[0])
@@ -218,6 +255,8 @@ def mixed_solve(H, Hq, b, tol=1e-8, max_outer=100, inner_cycles=1):
         hist.append(rr)
         if rr <= tol:
             break
+        if len(hist) > 1 and stagnated(rr, hist[-2], stagnation, tol):
+            raise_coarsest(Hq)
         r32 = r.astype(np.float32)
         e = np.zeros_like(r32)
         for _ in range(inner_cycles):

@@ -456,3 +456,26 @@ def test_band_midsize_boxmg_cycles_match_oracle():
     u = g.solution()
     assert np.abs(u - u_o).max() <= 1e-6 * np.abs(u_o).max()
     g.close()
+
+
+def test_stagnation_raise_to_base_matches_oracle():
+    """Dynamic coarsest level on an adaptive grid: a threshold no cycle meets
+    moves the regular levels' coarsest level up to the base level (676
+    unknowns, solved exactly); FAS cycle history and leaf values against the
+    oracle."""
+    qmg = require_gpu()
+    announce("adaptive stagnation raise 2D base3 L5")
+    flags, G, eps, f = _problem(2, 3, 5)
+    k = 4
+    H = AD.build_adaptive(G, eps, transfer="galerkin")
+    u_o, hist_o = AD.solve_adaptive(H, f, tol=0.0, max_cycles=k, stagnation=1e-12)
+    assert H.regular.lc == 3
+    g = _grid(qmg, 2, 3, 5, flags, check_definite=False, stagnation=1e-12)
+    g.set_coefficients(eps, f)
+    g.build()
+    rep, hist = g.solve(1e-30, k)
+    u = g.solution()
+    g.close()
+    assert rep["coarsest_level_used"] == 3 and rep["cycles"] == k
+    np.testing.assert_allclose(hist, hist_o, rtol=1e-9, atol=0)
+    assert np.abs(u - u_o).max() <= 1e-10 * np.abs(u_o).max()

@@ -364,3 +364,93 @@ def test_mixed_inner_cycles(store):
         assert rr <= 1e-8 * (1 + 1e-6)
     assert out[2][0]["outer_iters"] < out[1][0]["outer_iters"]
     assert out[2][0]["cycles"] == 2 * (out[2][0]["outer_iters"] - 1)
+
+
+# ---------------------------------------------------------------------------
+# Dynamic coarsest level (Sect. 3.3): raise between cycles on stagnation
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("transfer,store", [("geometric", "hier64"), ("geometric", "plain64"),
+                                            ("galerkin", "hier64"), ("galerkin", "plain64")])
+def test_stagnation_raise_on_jump_matches_oracle(transfer, store):
+    """The paper's jump setup (eps 1 | 0.1 at x = 0.5, f = 1) with V(1,1)
+    cycles, omega 0.9: the residual grows over the first cycles, the
+    coarsest level moves up after each of them (threshold 1: growth only),
+    and the solve converges.  Cycle count, raised level, residual history and
+    iterate against the oracle; every decision's ratio lies at least 1e-3
+    from the threshold, so rounding cannot flip one.""" 
+    qmg = require_gpu()
+    announce(f"stagnation raise jump 2D L5 {transfer} {store}")
+    p = W.material_jump(2, 5)
+    H = O.build_hierarchy(p.eps, 2, 5, transfer=transfer, omega=0.9, mu_pre=1, mu_post=1,
+                          check_definite=False)
+    b = O.rhs_from_f(p.f, 2, 5)
+    uo, ho = O.solve(H, b, tol=1e-8, max_cycles=300, stagnation=1.0)
+    ratios = np.array(ho) / np.array([1.0] + ho[:-1])
+    assert np.abs(ratios - 1.0).min() > 1e-3
+    assert H.lc > 1 and ho[-1] <= 1e-8
+    g = qmg.Grid(2, 5, qmg.make_opts(transfer, store, mu=(1, 1), omega=0.9, check_definite=False,
+                                     stagnation=1.0))
+    g.set_coefficients(p.eps, p.f)
+    g.build()
+    rep, hist = g.solve(1e-8, 300)
+    u = g.solution()
+    g.close()
+    assert rep["status"] == "QMG_OK"
+    assert rep["coarsest_level_used"] == H.lc
+    assert rep["cycles"] == len(ho)
+    # the residual norm of an FP64 iterate carries ~1e-14 of rounding relative
+    # to ||b|| (f = 1 gives |u| ~ 0.1 against |b| ~ 1e-3 per vertex)
+    np.testing.assert_allclose(hist, ho, rtol=1e-9, atol=1e-13)
+    assert np.abs(u - uo).max() <= 1e-10 * np.abs(uo).max()
+
+
+@pytest.mark.parametrize("d,L,transfer,store", [(2, 4, "boxmg", "hier64"), (2, 5, "boxmg", "hier64"),
+                                                (2, 4, "boxmg", "plain64"), (3, 3, "boxmg", "hier64"),
+                                                (3, 3, "galerkin", "hier64")])
+def test_raise_after_every_cycle_matches_oracle(d, L, transfer, store):
+    """A threshold no cycle meets moves the coarsest level up after every
+    cycle until L - 1: each raised level's stored operator is decoded for its
+    exact solve (or smoothed when larger than 1024 unknowns, level 4 in 2D),
+    and the fused coarse levels are rebuilt.  History and iterate against the
+    oracle."""
+    qmg = require_gpu()
+    announce(f"raise every cycle d={d} L={L} {transfer} {store}")
+    p = W.random_checkerboard(d, L, seed=6, values=(1.0, 10.0), blocks=9 if L > 3 else 3)
+    k = L + 1
+    H = O.build_hierarchy(p.eps, d, L, transfer=transfer, check_definite=False)
+    b = O.rhs_from_f(p.f, d, L)
+    uo, ho = O.solve(H, b, tol=1e-30, max_cycles=k, stagnation=1e-12)
+    assert H.lc == L - 1
+    g = qmg.Grid(d, L, qmg.make_opts(transfer, store, check_definite=False, stagnation=1e-12))
+    g.set_coefficients(p.eps, p.f)
+    g.build()
+    rep, hist = g.solve(1e-30, k)
+    u = g.solution()
+    assert rep["coarsest_level_used"] == L - 1 and rep["cycles"] == k
+    np.testing.assert_allclose(hist, ho, rtol=1e-10, atol=0)
+    assert np.abs(u - uo).max() <= 1e-11 * np.abs(uo).max()
+    # a new build starts again from the requested coarsest level
+    info = g.build()
+    assert info["coarsest_level_used"] == 1
+    g.close()
+
+
+@pytest.mark.parametrize("store", ["hier32", "bf16"])
+def test_raise_with_fp32_iterates(store):
+    """Raises between FP64 outer iterations: the inner FP32 cycles continue
+    on the raised hierarchy and the FP64 tolerance is reached (the oracle
+    recomputes the residual)."""
+    qmg = require_gpu()
+    announce(f"raise every outer iteration {store}")
+    p = W.random_checkerboard(2, 4, seed=4, values=(1.0, 1e3))
+    g = qmg.Grid(2, 4, qmg.make_opts("boxmg", store, check_definite=False, stagnation=1e-12))
+    g.set_coefficients(p.eps, p.f)
+    g.build()
+    rep, _ = g.solve(1e-8, 300)
+    u = g.solution()
+    g.close()
+    assert rep["status"] == "QMG_OK" and rep["coarsest_level_used"] == 3
+    H = O.build_hierarchy(p.eps, 2, 4, transfer="boxmg", check_definite=False)
+    b = O.rhs_from_f(p.f, 2, 4)
+    assert np.linalg.norm(b - H.A[4] @ u) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)

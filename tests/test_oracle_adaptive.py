@@ -218,3 +218,23 @@ def test_boxmg_fas_cycles_converge_to_composite_solution(d, base, L):
     rows = AD.composite_residual_rows(G, eps, f, u, np.arange(0, G.n_unknowns(), 11),
                                       AD.hanging_constraints(H))
     np.testing.assert_allclose(rows, (b - A @ u)[::11], atol=1e-13 * np.abs(b).max())
+
+
+def test_stagnation_raise_moves_coarsest_level_to_the_base():
+    """Dynamic coarsest level on an adaptive grid: with a threshold no cycle
+    meets, the regular levels' coarsest level moves up after every cycle and
+    stops at the base level; the first cycle is the one of the unraised
+    hierarchy, and the raised solve still converges to the composite
+    solution."""
+    G, eps, f = _problem(2, 3, 5)
+    H = AD.build_adaptive(G, eps, transfer="galerkin")
+    _, h = AD.solve_adaptive(H, f, cycles=4, stagnation=1e-12)
+    assert H.regular.lc == G.base
+    H0 = AD.build_adaptive(G, eps, transfer="galerkin")
+    _, h0 = AD.solve_adaptive(H0, f, cycles=1)
+    assert h[0] == h0[0] and H0.regular.lc == 1
+    H1 = AD.build_adaptive(G, eps, transfer="galerkin")
+    u, h1 = AD.solve_adaptive(H1, f, tol=1e-10, max_cycles=200, stagnation=1e-12)
+    ustar, _, _ = AD.solve_composite_direct(G, eps, f)
+    assert h1[-1] <= 1e-10
+    assert np.linalg.norm(u - ustar) <= 1e-8 * np.linalg.norm(ustar)

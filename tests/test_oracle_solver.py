@@ -91,3 +91,93 @@ def test_mixed_precision_reaches_tolerance(fmt):
     assert hist[-1] <= 1e-8
     u64, h64 = O.solve(H, b, tol=1e-8)
     assert len(hist) - 1 <= 1.5 * len(h64) + 2
+
+
+# ---------------------------------------------------------------------------
+# Dynamic coarsest level (Sect. 3.3): raise between cycles on stagnation
+# ---------------------------------------------------------------------------
+
+def _two_grid_cycle(A, P, Ac, b, u, omega, mu_pre, mu_post):
+    """Textbook two-grid cycle with dense linear algebra: damped Jacobi
+    pre-smoothing, exact coarse correction with R = P^T, post-smoothing."""
+    A = A.toarray()
+    P = P.toarray()
+    D = np.diag(A)
+    for _ in range(mu_pre):
+        u = u + omega * (b - A @ u) / D
+    u = u + P @ np.linalg.solve(Ac.toarray(), P.T @ (b - A @ u))
+    for _ in range(mu_post):
+        u = u + omega * (b - A @ u) / D
+    return u
+
+
+@pytest.mark.parametrize("transfer", ["galerkin", "boxmg", "geometric"])
+def test_raise_to_top_gives_the_two_grid_cycle(transfer):
+    """Raised to L - 1, a V-cycle is the two-grid cycle with an exact coarse
+    solve of level L - 1's operator."""
+    d, L = 2, 3
+    p = W.random_checkerboard(d, L, seed=2, values=(1.0, 100.0), blocks=3)
+    H = O.build_hierarchy(p.eps, d, L, transfer=transfer, check_definite=False)
+    assert H.lc == 1
+    assert O.raise_coarsest(H) and H.lc == 2
+    assert not O.raise_coarsest(H) and H.lc == 2      # L - 1 is the top
+    b = O.rhs_from_f(p.f, d, L)
+    rng = np.random.default_rng(0)
+    u0 = rng.uniform(-1, 1, size=b.shape) * 1e-2
+    u1 = O.vcycle(H, L, u0.copy(), b)
+    ref = _two_grid_cycle(H.A[L], H.P[L], H.A[L - 1], b, u0, H.omega, H.mu_pre, H.mu_post)
+    np.testing.assert_allclose(u1, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_raised_level_is_solved_with_its_own_operator():
+    """After one raise the cycle equals that of a hierarchy built with the
+    higher coarsest level from the start."""
+    p = W.random_checkerboard(2, 4, seed=4, values=(1.0, 1e3))
+    b = O.rhs_from_f(p.f, 2, 4)
+    H = O.build_hierarchy(p.eps, 2, 4, transfer="boxmg", check_definite=False)
+    O.raise_coarsest(H)
+    H2 = O.build_hierarchy(p.eps, 2, 4, transfer="boxmg", lc=2, check_definite=False)
+    u = np.zeros_like(b)
+    np.testing.assert_allclose(O.vcycle(H, 4, u, b), O.vcycle(H2, 4, u, b), rtol=1e-13, atol=0)
+
+
+def test_threshold_above_every_ratio_changes_nothing():
+    p = W.random_checkerboard(2, 4, seed=1, values=(1.0, 1e4))
+    b = O.rhs_from_f(p.f, 2, 4)
+    H0 = O.build_hierarchy(p.eps, 2, 4, transfer="boxmg")
+    _, h0 = O.solve(H0, b, tol=1e-8)
+    ratios = np.array(h0) / np.array([1.0] + h0[:-1])
+    H1 = O.build_hierarchy(p.eps, 2, 4, transfer="boxmg")
+    _, h1 = O.solve(H1, b, tol=1e-8, stagnation=2.0 * ratios.max())
+    assert h1 == h0 and H1.lc == H0.lc == 1
+
+
+def test_tiny_threshold_raises_after_every_cycle_up_to_the_top():
+    p = W.random_checkerboard(2, 4, seed=1, values=(1.0, 1e4))
+    b = O.rhs_from_f(p.f, 2, 4)
+    lcs = []
+    for k in range(1, 5):
+        H = O.build_hierarchy(p.eps, 2, 4, transfer="galerkin", check_definite=False)
+        O.solve(H, b, cycles=k, stagnation=1e-12)
+        lcs.append(H.lc)
+    # the check runs between cycles only: k cycles leave k - 1 raises
+    assert lcs == [1, 2, 3, 3]
+
+
+def test_jump_setup_growth_triggers_raise():
+    """The paper's jump setup with geometric V(1,1) cycles: the residual grows
+    over the first cycles (the coarse corrections' d-linear interpolation
+    across the jump); raising the coarsest level on growth keeps the solve
+    convergent and does not take more cycles (the behaviour reported with
+    the dynamic coarsest level)."""
+    p = W.material_jump(2, 5)
+    b = O.rhs_from_f(p.f, 2, 5)
+    H0 = O.build_hierarchy(p.eps, 2, 5, transfer="geometric", omega=0.9, mu_pre=1, mu_post=1)
+    _, h0 = O.solve(H0, b, tol=1e-8, max_cycles=300)
+    assert max(np.array(h0) / np.array([1.0] + h0[:-1])) > 1.0
+    H1 = O.build_hierarchy(p.eps, 2, 5, transfer="geometric", omega=0.9, mu_pre=1, mu_post=1)
+    _, h1 = O.solve(H1, b, tol=1e-8, max_cycles=300, stagnation=1.0)
+    assert H1.lc > 1 and h1[-1] <= 1e-8 and len(h1) <= len(h0)
+    # the raise happened exactly after the cycles whose residual grew
+    grow = [k for k in range(len(h1) - 1) if h1[k] > (h1[k - 1] if k else 1.0)]
+    assert H1.lc == 1 + len(grow)

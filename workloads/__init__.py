@@ -112,6 +112,17 @@ def sin_source(dim: int, level: int) -> Problem:
     return Problem("sin", dim, level, np.ones((n,) * dim), f, {"exact": prod})
 
 
+def material_jump(dim: int, level: int) -> Problem:
+    """The paper's ``jump`` setup (Table "parameters"): eps = 1 where the first
+    coordinate of the cell centre is below 0.5, 0.1 elsewhere (a jump that no
+    cell face of any level meets), f = 1."""
+    n = 3 ** level
+    xc = (np.arange(n) + 0.5) / n
+    eps = np.broadcast_to(np.where(xc < 0.5, 1.0, 0.1), (n,) * dim).copy()
+    return Problem(f"jump{dim}d-L{level}", dim, level, eps, np.ones((n - 1,) * dim),
+                   {"eps": "1 | 0.1 at x = 0.5"})
+
+
 # --------------------------------------------------------------------------
 # Named workloads.  cfg1: small 2D Poisson; cfg2: 2D jumping coefficient on
 # 729^2 cells; cfg4: a stream of mixed 2D/3D checkerboard requests.

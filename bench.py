@@ -9,11 +9,16 @@ synthetic (workloads.cfg2) and resident in HBM (torch tensors) before the
 timed region; set_coefficients checks and scatters them on the device.  The
 same steps with host-resident inputs (PCIe hand-over) are reported beside.
 
-Prints one JSON line.  The dominant kernel (finest-level Jacobi sweep) is timed
-with HIP events on the grid's stream during the timed steps (event-record nodes
-inside the replayed cycle graph); its algorithmic bytes per launch give the
-roofline figure.  The CPU baseline times the oracle
-(test infrastructure) on one solve of the same workload.
+Prints one JSON line.  The dominant kernel (the finest-level pre-smoothing
+pass) is timed with per-dispatch HIP events on the grid's stream around every
+k-th of its launches during the timed steps; its algorithmic bytes per launch
+give the roofline figure.  Beside the main line: build_operators timed on its
+own, the other single-grid workloads (2D Poisson at level 4 in FP64 to 1e-10,
+the 3D four-ball adaptive grid in BF16/FP32 under FP64 correction), the same
+step with the plain FP64 and BF16 stores, a roofline sweep on grids larger
+than the Infinity Cache, the served request stream (mixed precision, and plain
+FP64 for the ratio) and the CPU baseline, which times the oracle (test
+infrastructure) on one solve of the main workload.
 """
 from __future__ import annotations
 
@@ -94,16 +99,99 @@ def run_variant(qmg, problem, transfer, store, steps, warmup, tol=1e-8, profile=
             "kernel_launches": launches, "kernel_ms": ms, "u": u}
 
 
+def time_solves(g, eps, f, tol, n, warmup=1, time_cap=20.0):
+    """Repeated full solves (set_coefficients + build_operators + solve) of one
+    grid: up to n timed solves, fewer if they exceed time_cap seconds."""
+    import torch
+    lat, reps = [], []
+    for it in range(warmup + n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.set_coefficients(eps, f)
+        g.build()
+        rep, _ = g.solve(tol, 2000)
+        t1 = time.perf_counter()
+        if rep["status"] != "QMG_OK":
+            raise RuntimeError(f"solve did not converge: {rep}")
+        if it >= warmup:
+            lat.append(t1 - t0)
+            reps.append(rep)
+            if sum(lat) > time_cap:
+                break
+    lat = np.array(lat)
+    return {"solves": len(lat), "solves_per_s": len(lat) / lat.sum(),
+            "vertex_updates_per_s": sum(r["vertex_updates"] for r in reps) / lat.sum(),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "cycles_per_solve": reps[-1]["cycles"], "outer_iters": reps[-1].get("outer_iters"),
+            "relres": reps[-1]["relres"]}
+
+
+def time_build(g, eps, f, n=20):
+    """build_operators on its own (after set_coefficients), synchronised."""
+    import torch
+    t = []
+    for it in range(n + 1):
+        g.set_coefficients(eps, f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.build()
+        torch.cuda.synchronize()
+        if it:
+            t.append(time.perf_counter() - t0)
+    return float(np.percentile(np.array(t), 50) * 1e3)
+
+
+def other_workloads(qmg, n):
+    """The 2D Poisson workload (level 4, FP64 plain store, geometric transfer,
+    to 1e-10) and the 3D four-ball adaptive workload (base level 3, level 5,
+    BoxMG + Galerkin, BF16 deltas and FP32 inner cycles under FP64 composite
+    defect correction, to 1e-8), inputs generated at the library's own
+    unknown and cell coordinates."""
+    import torch
+    import workloads as W
+    out = {}
+    p = W.cfg1(0)
+    g = qmg.Grid(p.dim, p.level, qmg.make_opts("geometric", "plain64"))
+    eps = torch.from_numpy(np.ascontiguousarray(p.eps).ravel()).cuda()
+    f = torch.from_numpy(np.ascontiguousarray(p.f).ravel()).cuda()
+    r = time_solves(g, eps, f, 1e-10, n, warmup=3)
+    out["poisson2d_L4"] = dict(r, unknowns=p.n_unknowns, u=g.solution(),
+                               workload="2D Poisson, 81^2 cells (80^2 unknowns), eps = 1, f~U[-1,1]; "
+                                        "geometric V(2,2), omega 0.6, plain FP64 store, to 1e-10")
+    g.close()
+    P = W.adaptive_balls()
+    g = qmg.Grid(P.dim, P.level, qmg.make_opts("boxmg", "bf16", check_definite=False),
+                 base_level=P.base, refine=P.flags)
+    xyz, lev = g.unknown_coords()
+    fa = np.empty(len(xyz))
+    for l in range(P.base, P.level + 1):
+        m = lev == l
+        fa[m] = P.f_at(l, xyz[m])
+    epsa = P.eps_at(g.cell_centres())
+    epsa = torch.from_numpy(epsa).cuda()
+    fa = torch.from_numpy(fa).cuda()
+    r = time_solves(g, epsa, fa, 1e-8, n, warmup=1)
+    out["adaptive3d_balls"] = dict(r, unknowns=g.n_unknowns, leaf_cells=g.n_cells,
+                                   build_ms=time_build(g, epsa, fa, 5),
+                                   workload="3D adaptive: level 3 everywhere, level 5 within 0.2 of 4 "
+                                            "seeded points; eps = exp(g), g a unit-variance Gaussian "
+                                            "field (correlation length 0.1); BoxMG + Galerkin, BF16 "
+                                            "deltas, FP32 inner FAS cycles, FP64 composite defect "
+                                            "correction to 1e-8")
+    g.close()
+    return out
+
+
 def serve_stream(qmg, n_requests=256, seed=0, slots=16, budget=8 << 30):
     """Served stream of mixed 2D/3D checkerboard solves (FP16 deltas, FP32
     cycles under FP64 refinement to 1e-8): first closed loop (all requests at
     t = 0) for the saturated throughput, then Poisson arrivals at 0.9 of it."""
     import workloads as W
-    opts = qmg.make_opts("boxmg", "hier16")
+    mixed = qmg.make_opts("boxmg", "hier16")
     stream = W.cfg4_stream(seed=seed, n_requests=n_requests)
     out = {"requests": n_requests, "store": "hier16", "slots": slots, "hbm_budget_bytes": budget}
 
-    def run(arrivals):
+    def run(arrivals, opts):
         srv = qmg.Server(budget, max_slots=slots)
         t0 = time.perf_counter()
         tickets = []
@@ -128,13 +216,18 @@ def serve_stream(qmg, n_requests=256, seed=0, slots=16, budget=8 << 30):
                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
                 "failed": int(bad), "hbm_peak_bytes": int(st["hbm_peak"])}
 
-    closed = run([0.0] * n_requests)
+    closed = run([0.0] * n_requests, mixed)
     rate = 0.9 * closed["solves_per_s"]
     rng = np.random.default_rng(seed + 1)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
-    opened = run(list(arrivals))
+    opened = run(list(arrivals), mixed)
     out["closed_loop"] = closed
     out["poisson_0.9"] = dict(opened, rate_per_s=rate)
+    # the same stream served in plain FP64 (full stencils, FP64 cycles) to the
+    # same tolerance, for the mixed-precision ratio
+    plain = run([0.0] * n_requests, qmg.make_opts("boxmg", "plain64"))
+    out["plain64_closed_loop"] = plain
+    out["mixed_over_plain64"] = closed["solves_per_s"] / plain["solves_per_s"]
     return out
 
 
@@ -156,10 +249,21 @@ def cpu_baseline(problem):
             "solves_per_s": 1.0 / dt, "u": u}
 
 
+def cpu_solution_poisson():
+    """The oracle's solution of the 2D Poisson workload (level 4, geometric
+    V(2,2) cycles to 1e-10)."""
+    import oracle as O
+    import workloads as W
+    p = W.cfg1(0)
+    H = O.build_hierarchy(p.eps, p.dim, p.level, transfer="geometric")
+    u, _ = O.solve(H, O.rhs_from_f(p.f, p.dim, p.level), tol=1e-10, max_cycles=500)
+    return u
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--level", type=int, default=6)
     ap.add_argument("--store", default="hier64")
@@ -174,6 +278,8 @@ def main():
                          "the same step for the hier64, plain64 and bf16 stores")
     ap.add_argument("--variants", default="plain64,bf16",
                     help="extra stores timed on the same workload (comma list, '' for none)")
+    ap.add_argument("--others", type=int, default=50, metavar="N",
+                    help="repeated solves of the 2D Poisson and 3D adaptive workloads (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver path is "
@@ -242,6 +348,10 @@ def main():
                      "timing": f"per-dispatch HIP events (hipExtLaunchKernelGGL) on the grid stream "
                                f"around every {args.profile_every}-th such launch of the timed steps"},
     }
+    gb = qmg.Grid(p.dim, p.level, qmg.make_opts("boxmg", args.store))
+    out["build_ms"] = time_build(gb, p.eps, p.f)
+    out["build_note"] = "build_operators alone (BoxMG P, Galerkin RAP, delta store, coarsest inverse), p50"
+    gb.close()
     hp = run_variant(qmg, p, "boxmg", args.store, max(3, args.steps // 2), 1, host_inputs=True)
     out["host_inputs"] = {"solves_per_s": len(hp["lat"]) / hp["elapsed"],
                           "p50_ms": float(np.percentile(hp["lat"], 50) * 1e3),
@@ -283,6 +393,8 @@ def main():
         del q
     if sweep:
         out["roofline_sweep"] = sweep
+    if args.others:
+        out["other_workloads"] = other_workloads(qmg, args.others)
     if not args.no_serving:
         out["serving"] = serve_stream(qmg)
     if not args.no_cpu_baseline:
@@ -290,6 +402,12 @@ def main():
         ucpu = cb.pop("u")
         out["cpu_baseline"] = cb
         out["u_rel_diff_vs_oracle"] = float(np.linalg.norm(res["u"] - ucpu) / np.linalg.norm(ucpu))
+    if args.others:
+        ow = out["other_workloads"]["poisson2d_L4"]
+        u1 = ow.pop("u")
+        if not args.no_cpu_baseline:
+            ucpu = cpu_solution_poisson()
+            ow["u_rel_diff_vs_oracle"] = float(np.linalg.norm(u1 - ucpu) / np.linalg.norm(ucpu))
     print(json.dumps(out))
 
 

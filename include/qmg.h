@@ -118,6 +118,18 @@ typedef struct {
                           the server); 0: eager kernel launches, which keep
                           up with the device for one grid on its own.  Needs
                           an even mu_pre + mu_post; ignored while profiling */
+  double stagnation;   /* dynamic coarsest level (Sect. 3.3): > 0 moves the
+                          coarsest level one up after a cycle (an outer
+                          iteration with FP32 iterates) that has not reached
+                          the tolerance and cut the relative residual by less
+                          than this factor (1.0: only on growth); up to
+                          L - 1, the base level at most on an adaptive grid.
+                          The new coarsest level is solved exactly with its
+                          stored operator decoded to FP64 when it has at most
+                          1024 unknowns, otherwise by mu_pre + mu_post
+                          sweeps; the raise lasts until the next
+                          build_operators.  Cycles then run one per host
+                          check.  0 (default): off                         */
 } qmg_solver_opts;
 
 typedef struct {
@@ -125,7 +137,8 @@ typedef struct {
   int outer_iters;          /* FP64 residual evaluations                      */
   double relres;            /* final ||b - A u||_2 / ||b||_2 over the
                                unknowns (composite system when adaptive), FP64 */
-  int coarsest_level_used;  /* after the definiteness check                   */
+  int coarsest_level_used;  /* after the definiteness check and any raise on
+                               stagnation                                     */
   int64_t vertex_updates;   /* Jacobi vertex updates performed (all levels)   */
   size_t bytes_operators;   /* device bytes holding stored operators          */
   double zero_delta_fraction; /* share of 64-vertex blocks stored as zero     */

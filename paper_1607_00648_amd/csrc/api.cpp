@@ -202,6 +202,8 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
   if (o->coarsest_level < 1 || o->coarsest_level > desc->max_level - 1)
     throw ApiError(QMG_EINVAL, "coarsest_level must satisfy 1 <= lc < max_level");
   if (o->inner_cycles < 1) throw ApiError(QMG_EINVAL, "inner_cycles must be >= 1");
+  if (!(o->stagnation >= 0.0 && o->stagnation < 1e6))
+    throw ApiError(QMG_EINVAL, "stagnation must be 0 (off) or a positive factor");
   const bool adaptive = desc->base_level != 0 && desc->base_level != desc->max_level;
   if (adaptive) {
     if (desc->base_level < 1 || desc->base_level > desc->max_level)
@@ -1124,6 +1126,36 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
   }
 }
 
+// Dynamic coarsest level (Sect. 3.3): moves l_c one level up, to L - 1 at
+// most (the base level on an adaptive grid).  The new coarsest level's stored
+// operator is decoded to FP64 for its exact solve (or it is smoothed when too
+// large); the levels below drop out of the cycle.  Returns whether it moved.
+bool raise_coarsest(qmg_grid_t* g) {
+  const int top = g->adaptive ? std::min(g->lb, g->Lmax - 1) : g->Lmax - 1;
+  if (g->lc + 1 > top) return false;
+  drop_graph(g);
+  const int l = g->lc + 1;
+  LevelBuf& B = g->lv[l];
+  double* full = B.Adense;
+  if (!g->plain) {
+    full = g->tmpA[0];  // sized for level L - 1
+    launch_materialise(B.L, B.eps64, B.A, full, S(g));
+  }
+  g->lv[g->lc].A = Store{};
+  g->lv[g->lc].P = Store{};
+  g->lc = l;
+  B.P = Store{};
+  setup_coarse(g, full);
+  g->lf = g->mixed ? choose_fused_top<float>(g, g->lf_pw_lds) : choose_fused_top<double>(g, g->lf_pw_lds);
+  g->fimg_ready = false;
+  if (g->lf >= 0) {
+    if (g->mixed) prepare_fused<float>(g);
+    else prepare_fused<double>(g);
+  }
+  QMG_HIP(hipStreamSynchronize(S(g)));
+  return true;
+}
+
 void need_ops(qmg_grid_t* g) {
   if (!g) throw ApiError(QMG_EINVAL, "null grid");
   if (!g->have_ops) throw ApiError(QMG_ESTATE, "build_operators must precede cycles");
@@ -1244,7 +1276,8 @@ void solve_begin(qmg_grid_t* g, SolveState& st, double tol, int max_cycles) {
 }
 
 void solve_enqueue(qmg_grid_t* g, SolveState& st) {
-  const int B = std::max(1, std::min({st.batch, st.max_cycles - st.cycles, kHistCap}));
+  // the stagnation check needs the residual of every cycle before the next
+  const int B = g->opts.stagnation > 0.0 ? 1 : std::max(1, std::min({st.batch, st.max_cycles - st.cycles, kHistCap}));
   enqueue_batch(g, B);
 }
 
@@ -1268,6 +1301,7 @@ void solve_collect(qmg_grid_t* g, SolveState& st) {
     st.batch = 1;
   }
   st.done = !(st.rr > st.tol) || st.cycles >= st.max_cycles || !std::isfinite(st.rr);
+  if (!st.done && g->opts.stagnation > 0.0 && st.rr > g->opts.stagnation * st.rr_prev) raise_coarsest(g);
 }
 
 void solve_fill_report(qmg_grid_t* g, const SolveState& st, qmg_solve_report* rep) {
@@ -1304,6 +1338,7 @@ int qmg_default_opts(qmg_solver_opts* o) {
   o->check_definite = 1;
   o->inner_cycles = 1;
   o->use_graphs = 1;
+  o->stagnation = 0.0;
   return QMG_OK;
 }
 

@@ -37,7 +37,8 @@ class GridDesc(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("transfer", C.c_int), ("store", C.c_int), ("mu_pre", C.c_int),
                 ("mu_post", C.c_int), ("omega", C.c_double), ("coarsest_level", C.c_int),
-                ("check_definite", C.c_int), ("inner_cycles", C.c_int), ("use_graphs", C.c_int)]
+                ("check_definite", C.c_int), ("inner_cycles", C.c_int), ("use_graphs", C.c_int),
+                ("stagnation", C.c_double)]
 
 
 class SolveReport(C.Structure):
@@ -123,7 +124,7 @@ def _ptr(a: np.ndarray):
 
 
 def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_level=1,
-              check_definite=True, inner_cycles=1, graphs=True) -> SolverOpts:
+              check_definite=True, inner_cycles=1, graphs=True, stagnation=0.0) -> SolverOpts:
     o = SolverOpts()
     o.transfer = TRANSFERS[transfer] if isinstance(transfer, str) else int(transfer)
     o.store = STORES[store] if isinstance(store, str) else int(store)
@@ -133,6 +134,7 @@ def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_l
     o.check_definite = 1 if check_definite else 0
     o.inner_cycles = int(inner_cycles)
     o.use_graphs = 1 if graphs else 0
+    o.stagnation = float(stagnation)
     return o
 
 

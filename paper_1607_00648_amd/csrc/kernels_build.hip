@@ -114,11 +114,56 @@ struct BoxFetch {
   }
 };
 
+// Row of fine vertex v as BoxFetch gives it, one entry at a time from a
+// prepared state: the stored row, or the rediscretised row from the 2^d cell
+// coefficients held in registers (boundary entries dropped), or nothing.
+template <int D>
+struct RowSrc {
+  int mode = 0;  // 0: empty row, 1: stored row, 2: rediscretised row
+  double ce[Dim<D>::NC];
+  __device__ RowSrc(const BoxFetch<D>& F, int64_t v) {
+    bool geo = F.A == nullptr;
+    mode = 1;
+    if (F.vt) {
+      const int8_t t = F.vt[v];
+      if (F.hanging_rows && t == VT_HANGING) geo = true;
+      else if (t != VT_LEAF && t != VT_REFINED) mode = 0;
+    }
+    if (mode == 1 && geo) mode = 2;
+#pragma unroll
+    for (int s = 0; s < Dim<D>::NC; ++s)
+      ce[s] = mode == 2 ? F.eps[v - slot_off(F.L, s & 1, (s >> 1) & 1, (s >> 2) & 1)] : 0.0;
+  }
+  // entry k of the row of v = (i, j, kz); the neighbour must be checked for
+  // being interior by the caller when mode == 2
+  __device__ double entry(const BoxFetch<D>& F, int64_t v, int k) const {
+    if (mode == 1) return F.A[(int64_t)k * F.L.nslot + v];
+    const int nd = (off_x(k) != 0) + (off_y(k) != 0) + (D == 3 ? (off_z(k) != 0) : 0);
+    const double w = kref(D, nd);
+    double e = 0.0;
+#pragma unroll
+    for (int s = 0; s < Dim<D>::NC; ++s) {
+      const int sx = s & 1, sy = (s >> 1) & 1, sz = (s >> 2) & 1;
+      const bool has = sx + off_x(k) >= 0 && sx + off_x(k) <= 1 && sy + off_y(k) >= 0 && sy + off_y(k) <= 1 &&
+                       (D == 2 || (sz + off_z(k) >= 0 && sz + off_z(k) <= 1));
+      e += has ? ce[s] : 0.0;
+    }
+    return ((D == 3) ? F.L.h : 1.0) * w * e;
+  }
+};
+
 __host__ __device__ constexpr int pidx(int yx, int yy, int yz) { return yx + 3 * yy + 9 * yz; }
+
+// The 27 reference-frame weights of one thread, kept in LDS (one column per
+// thread of the 64-thread workgroup) to leave registers to the patch systems.
+struct PCol {
+  double* base;
+  __device__ double& operator[](int i) const { return base[i * 64]; }
+};
 
 template <int D, int S>
 __device__ inline void box_group(const BoxFetch<D>& F, int Vx, int Vy, int Vz, int sx, int sy, int sz,
-                                 double (&p)[27]) {
+                                 const PCol& p) {
   // unknowns: y with y_i in {1,2} for i in S, 0 otherwise
   constexpr int m = 1 << ((S & 1) + ((S >> 1) & 1) + ((S >> 2) & 1));
   double M[m][m];
@@ -141,6 +186,7 @@ __device__ inline void box_group(const BoxFetch<D>& F, int Vx, int Vy, int Vz, i
     }
     const int fx = 3 * Vx + sx * y[0], fy = 3 * Vy + sy * y[1], fz = 3 * Vz + sz * y[2];
     const int64_t v = fx + (int64_t)fy * F.L.pitch + (int64_t)fz * F.L.plane;
+    const RowSrc<D> row(F, v);  // the member's row, fetched once
 #pragma unroll
     for (int k = 0; k < Dim<D>::NS; ++k) {
       const int o[3] = {off_x(k), off_y(k), D == 3 ? off_z(k) : 0};
@@ -155,7 +201,10 @@ __device__ inline void box_group(const BoxFetch<D>& F, int Vx, int Vy, int Vz, i
       }
       if (far) continue;
       const int ks = (sx * o[0] + 1) + 3 * (sy * o[1] + 1) + (D == 3 ? 9 * (sz * o[2] + 1) : 0);
-      const double a = F(v, fx, fy, fz, ks);
+      double a = 0.0;
+      if (row.mode == 1 || (row.mode == 2 && interior(F.L, fx + off_x(ks), fy + off_y(ks),
+                                                        fz + (D == 3 ? off_z(ks) : 0))))
+        a = row.entry(F, v, ks);
       if (ingroup) {
         int col = 0, bit = 0;
 #pragma unroll
@@ -220,7 +269,8 @@ __global__ __launch_bounds__(64) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, dou
   const int Vx = (int)(Vi % m) + 1, Vy = (int)((Vi / m) % m) + 1, Vz = (D == 3) ? (int)(Vi / ((int64_t)m * m)) + 1 : 0;
   const int sx = (orth & 1) ? -1 : 1, sy = (orth & 2) ? -1 : 1, sz = (D == 3 && (orth & 4)) ? -1 : 1;
   if (cref && !orthant_refined(cref, Lc, Vx, Vy, Vz, sx, sy, sz)) return;
-  double p[27];
+  __shared__ double pl[27 * 64];
+  const PCol p{pl + threadIdx.x};
 #pragma unroll
   for (int q = 0; q < 27; ++q) p[q] = 0.0;
   p[0] = 1.0;
@@ -269,9 +319,8 @@ __global__ __launch_bounds__(64) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, dou
 }
 
 // ---------------------------------------------------------------------------
-// Galerkin product.  One thread per (interior coarse vertex V, offset delta):
-// A_c(V, V+delta) = sum_i sum_j P(i,V) a(i,j) P(j,V+delta), i within 2 of 3V
-// and j within 2 of 3(V+delta) on every axis, |i - j| <= 1.
+// Galerkin product (Sect. 3.3): A_c(V, W) = sum_i sum_j P(i,V) a(i,j) P(j,W)
+// for interior coarse V and W in 3^d(V), i within 2 of 3V and |i - j| <= 1.
 // ---------------------------------------------------------------------------
 template <int D>
 struct PFetch {
@@ -291,45 +340,148 @@ struct PFetch {
   }
 };
 
+// Work shape of the Galerkin kernel: one thread per fine vertex i within 2 of
+// 3V (5^d of them), one coarse vertex V per workgroup in 3D, ten in 2D.
+template <int D>
+struct RapShape {
+  static constexpr int NI = (D == 3) ? 125 : 25;
+  static constexpr int VPB = (D == 3) ? 1 : 10;
+  static constexpr int NT = (D == 3) ? 128 : 256;
+  static constexpr int RW = 7;                         // fine region 3V + [-3, 3]^d
+  static constexpr int NR = (D == 3) ? 343 : 49;
+};
+
 // vtc (nullable): coarse vertex classes; rows of vertices that are not
 // refined are left zero (an adaptive level replaces them by rediscretised or
-// empty rows)
+// empty rows).
+//
+// A_c(V, W) = sum_i P(i,V) sum_j a(i,j) P(j,W) over fine i within 2 of 3V and
+// j = i + o, o in [-1,1]^d.  Each thread takes one i: it builds i's row once,
+// walks its 3^d neighbours j and their (up to 2^d) parents W near V, and adds
+// a(i,j) P(j,W) to its own LDS column of the 3^d entries W - V.  The columns
+// are then weighted by P(i,V) and summed in a fixed order.  BoxMG weights of
+// the fine region 3V + [-3,3]^d are staged in LDS first.
 template <int D>
-__global__ __launch_bounds__(256) void k_rap(Lat Lf, Lat Lc, BoxFetch<D> A, PFetch<D> P,
-                                             double* __restrict__ Ac, const int8_t* __restrict__ vtc) {
-  constexpr int NS = Dim<D>::NS;
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetch<D> A, PFetch<D> P,
+                                                         double* __restrict__ Ac,
+                                                         const int8_t* __restrict__ vtc) {
+  using S = RapShape<D>;
+  constexpr int NS = Dim<D>::NS, NC = Dim<D>::NC;
+  __shared__ double col[NS * S::NT];
+  __shared__ double pw[S::VPB * S::NR * NC];
+  __shared__ double piv[S::NT];
   const int m = Lc.n - 1;
   const int64_t nV = (D == 3) ? (int64_t)m * m * m : (int64_t)m * m;
-  if (t >= nV * NS) return;
-  const int kd = (int)(t % NS);
-  const int64_t Vi = t / NS;
-  const int Vx = (int)(Vi % m) + 1, Vy = (int)((Vi / m) % m) + 1, Vz = (D == 3) ? (int)(Vi / ((int64_t)m * m)) + 1 : 0;
-  const int Wx = Vx + off_x(kd), Wy = Vy + off_y(kd), Wz = Vz + (D == 3 ? off_z(kd) : 0);
-  const int64_t vc = Vx + (int64_t)Vy * Lc.pitch + (int64_t)Vz * Lc.plane;
-  double acc = 0.0;
-  if (interior(Lc, Wx, Wy, Wz) && (vtc == nullptr || vtc[vc] == VT_REFINED)) {
-    const int ilx = max(3 * Vx - 2, 3 * Wx - 3), ihx = min(3 * Vx + 2, 3 * Wx + 3);
-    const int ily = max(3 * Vy - 2, 3 * Wy - 3), ihy = min(3 * Vy + 2, 3 * Wy + 3);
-    const int ilz = (D == 3) ? max(3 * Vz - 2, 3 * Wz - 3) : 0, ihz = (D == 3) ? min(3 * Vz + 2, 3 * Wz + 3) : 0;
-    for (int iz = ilz; iz <= ihz; ++iz)
-      for (int iy = ily; iy <= ihy; ++iy)
-        for (int ix = ilx; ix <= ihx; ++ix) {
-          const double pi = P(ix, iy, iz, Vx, Vy, Vz);
-          if (pi == 0.0) continue;
-          const int64_t vi = ix + (int64_t)iy * Lf.pitch + (int64_t)iz * Lf.plane;
-          double s = 0.0;
-          for (int k = 0; k < NS; ++k) {
-            const int jx = ix + off_x(k), jy = iy + off_y(k), jz = iz + (D == 3 ? off_z(k) : 0);
-            if (abs(jx - 3 * Wx) > 2 || abs(jy - 3 * Wy) > 2 || (D == 3 && abs(jz - 3 * Wz) > 2)) continue;
-            const double pj = P(jx, jy, jz, Wx, Wy, Wz);
-            if (pj == 0.0) continue;
-            s += A(vi, ix, iy, iz, k) * pj;
-          }
-          acc += pi * s;
-        }
+  const int t = threadIdx.x;
+  // coarse vertex of this thread (VPB per workgroup; the spare threads of
+  // the last 5^d box take the last vertex and stay idle)
+  const int sub = min(t / S::NI, S::VPB - 1);
+  const int q = t - sub * S::NI;          // fine vertex within its 5^d box (idle when >= NI)
+  const int64_t Vi = (int64_t)blockIdx.x * S::VPB + sub;
+  const bool have = Vi < nV;
+  int Vx = 1, Vy = 1, Vz = 0;
+  if (have) {
+    Vx = (int)(Vi % m) + 1;
+    Vy = (int)((Vi / m) % m) + 1;
+    Vz = (D == 3) ? (int)(Vi / ((int64_t)m * m)) + 1 : 0;
   }
-  Ac[(int64_t)kd * Lc.nslot + vc] = acc;
+  const int64_t vc = Vx + (int64_t)Vy * Lc.pitch + (int64_t)Vz * Lc.plane;
+  const bool act = have && (vtc == nullptr || vtc[vc] == VT_REFINED);
+  if (D == 3 && !act) {  // one vertex per workgroup: the whole workgroup leaves together
+    if (have && t < NS) Ac[(int64_t)t * Lc.nslot + vc] = 0.0;
+    return;
+  }
+  // stage the BoxMG weights of each (refined) vertex's fine region
+  if (P.W) {
+#pragma unroll 2
+    for (int e = t; e < S::VPB * S::NR * NC; e += S::NT) {
+      const int vs = e / (S::NR * NC);
+      const int r = e - vs * (S::NR * NC);
+      const int kap = r % NC, jr = r / NC;
+      const int64_t Vj = (int64_t)blockIdx.x * S::VPB + vs;
+      double w = 0.0;
+      if (Vj < nV) {
+        const int ux = (int)(Vj % m) + 1, uy = (int)((Vj / m) % m) + 1;
+        const int uz = (D == 3) ? (int)(Vj / ((int64_t)m * m)) + 1 : 0;
+        const int64_t uc = ux + (int64_t)uy * Lc.pitch + (int64_t)uz * Lc.plane;
+        if (vtc == nullptr || vtc[uc] == VT_REFINED) {
+        const int jx = 3 * ux - 3 + jr % S::RW, jy = 3 * uy - 3 + (jr / S::RW) % S::RW;
+        const int jz = (D == 3) ? 3 * uz - 3 + jr / (S::RW * S::RW) : 0;
+          w = P.W[(int64_t)kap * Lf.nslot + jx + (int64_t)jy * Lf.pitch + (int64_t)jz * Lf.plane];
+        }
+      }
+      pw[e] = w;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < NS; ++e) col[e * S::NT + t] = 0.0;
+  __syncthreads();
+  const int ox = q % 5 - 2, oy = (q / 5) % 5 - 2, oz = (D == 3) ? q / 25 - 2 : 0;
+  double pi = 0.0;
+  if (act && q < S::NI) {
+    const int ix = 3 * Vx + ox, iy = 3 * Vy + oy, iz = 3 * Vz + oz;
+    const double* pr = pw + sub * S::NR * NC;
+    // weight at fine (x,y,z) of the parent floor(f/3)+kap, from the staged
+    // region or the d-linear formula
+    auto wt = [&](int x, int y, int z, int kap) -> double {
+      if (P.W) {
+        const int rl = (x - 3 * Vx + 3) + S::RW * ((y - 3 * Vy + 3) + S::RW * (D == 3 ? z - 3 * Vz + 3 : 0));
+        return pr[rl * NC + kap];
+      }
+      const int rx = x - 3 * (x / 3), ry = y - 3 * (y / 3), rz = (D == 3) ? z - 3 * (z / 3) : 0;
+      return dlin1(rx, kap & 1) * dlin1(ry, (kap >> 1) & 1) * (D == 3 ? dlin1(rz, (kap >> 2) & 1) : 1.0);
+    };
+    {
+      const int kx = Vx - ix / 3, ky = Vy - iy / 3, kz = (D == 3) ? Vz - iz / 3 : 0;
+      pi = wt(ix, iy, iz, kx | (ky << 1) | (kz << 2));
+    }
+    if (pi != 0.0) {
+      const int64_t vi = ix + (int64_t)iy * Lf.pitch + (int64_t)iz * Lf.plane;
+      const RowSrc<D> row(A, vi);
+      // the next entry is fetched while the current one is spread (stored
+      // rows come from global memory)
+      double anext = row.mode == 0 ? 0.0 : row.entry(A, vi, 0);
+#pragma unroll 1
+      for (int k = 0; k < NS; ++k) {
+        const double ak = anext;
+        if (k + 1 < NS && row.mode != 0) anext = row.entry(A, vi, k + 1);
+        const int jx = ix + off_x(k), jy = iy + off_y(k), jz = iz + (D == 3 ? off_z(k) : 0);
+        if (ak == 0.0 || !interior(Lf, jx, jy, jz)) continue;
+        const int qx = jx / 3, qy = jy / 3, qz = (D == 3) ? jz / 3 : 0;
+        const int rx = jx - 3 * qx, ry = jy - 3 * qy, rz = jz - 3 * qz;
+#pragma unroll
+        for (int kap = 0; kap < NC; ++kap) {
+          const int kx = kap & 1, ky = (kap >> 1) & 1, kz = (kap >> 2) & 1;
+          if ((kx && rx == 0) || (ky && ry == 0) || (kz && rz == 0)) continue;
+          const int dx = qx + kx - Vx, dy = qy + ky - Vy, dz = (D == 3) ? qz + kz - Vz : 0;
+          if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) continue;
+          if (!interior(Lc, qx + kx, qy + ky, D == 3 ? qz + kz : 0)) continue;
+          const double pj = wt(jx, jy, jz, kap);
+          if (pj == 0.0) continue;
+          const int w = (dx + 1) + 3 * (dy + 1) + (D == 3 ? 9 * (dz + 1) : 0);
+          col[w * S::NT + t] += ak * pj;
+        }
+      }
+    }
+  }
+  piv[t] = pi;
+  __syncthreads();
+  // fixed-order sums: thread sub*NS + w of the first VPB*NS threads
+  if (t < S::VPB * NS) {
+    const int vs = t / NS, w = t - vs * NS;
+    const int64_t Vj = (int64_t)blockIdx.x * S::VPB + vs;
+    if (Vj < nV) {
+      const int ux = (int)(Vj % m) + 1, uy = (int)((Vj / m) % m) + 1;
+      const int uz = (D == 3) ? (int)(Vj / ((int64_t)m * m)) + 1 : 0;
+      double acc = 0.0;
+#pragma unroll 5
+      for (int r = 0; r < S::NI; ++r) {
+        const int tt = vs * S::NI + r;
+        acc += piv[tt] * col[w * S::NT + tt];
+      }
+      Ac[(int64_t)w * Lc.nslot + ux + (int64_t)uy * Lc.pitch + (int64_t)uz * Lc.plane] = acc;
+    }
+  }
 }
 
 template <int D>
@@ -553,15 +705,17 @@ void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double*
   const int m = Lc.n - 1;
   if (m <= 0) return;
   if (Lf.d == 2) {
-    const int64_t nt = (int64_t)m * m * 9;
+    using S = RapShape<2>;
+    const int64_t nV = (int64_t)m * m;
     BoxFetch<2> A{Afine, epsf, Lf, vt_fine};
     PFetch<2> P{Pw, Lf, Lc};
-    hipLaunchKernelGGL(k_rap<2>, dim3(blocks_for(nt, 256)), dim3(256), 0, s, Lf, Lc, A, P, Ac, vt_coarse);
+    hipLaunchKernelGGL(k_rap<2>, dim3(blocks_for(nV, S::VPB)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse);
   } else {
-    const int64_t nt = (int64_t)m * m * m * 27;
+    using S = RapShape<3>;
+    const int64_t nV = (int64_t)m * m * m;
     BoxFetch<3> A{Afine, epsf, Lf, vt_fine};
     PFetch<3> P{Pw, Lf, Lc};
-    hipLaunchKernelGGL(k_rap<3>, dim3(blocks_for(nt, 256)), dim3(256), 0, s, Lf, Lc, A, P, Ac, vt_coarse);
+    hipLaunchKernelGGL(k_rap<3>, dim3(blocks_for(nV, S::VPB)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse);
   }
   QMG_HIP(hipGetLastError());
 }

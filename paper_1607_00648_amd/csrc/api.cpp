@@ -63,6 +63,10 @@ struct LevelBuf {
   int8_t* cref = nullptr;
   int32_t* tiles = nullptr;
   int ntiles = 0;
+  int32_t* rv = nullptr;  // refined vertices and cells (levels base..L-1), for the build
+  int64_t nrv = 0;
+  int32_t* rc = nullptr;
+  int64_t nrc = 0;
   void* sv = nullptr;
   double* x64 = nullptr;  // FP32 iterates: FP64 solution and right-hand side of the level
   double* b64 = nullptr;
@@ -83,6 +87,8 @@ struct HostLevel {
   std::vector<int32_t> tiles;     // active tiles (x tile, y tile, z plane)
   std::vector<int64_t> leaf;      // slots of the unknowns (x fastest)
   std::vector<int64_t> cells;     // slots of the leaf cells (x fastest)
+  std::vector<int32_t> rverts;    // refined interior vertices (interior index, x fastest)
+  std::vector<int32_t> rcells;    // refined cells (cell index, x fastest)
   int64_t n_active = 0;           // leaf + refined vertices
 };
 
@@ -250,7 +256,10 @@ void linearise(qmg_grid_t* g) {
         for (int64_t i = 0; i < n; ++i) {
           const int64_t c = cell(i, j, k);
           const int64_t sl = i + j * Lt.pitch + k * Lt.plane;
-          if (ref[c]) H.cref[(size_t)sl] = 1;
+          if (ref[c]) {
+            H.cref[(size_t)sl] = 1;
+            H.rcells.push_back((int32_t)c);
+          }
           if (exist[c] && !ref[c]) H.cells.push_back(sl);
         }
     for (int64_t k = (d == 3 ? 1 : 0); k <= (d == 3 ? n - 1 : 0); ++k)
@@ -268,6 +277,8 @@ void linearise(qmg_grid_t* g) {
           else if (cnt > 0) t = VT_HANGING;
           H.vt[(size_t)sl] = t;
           if (t == VT_LEAF) H.leaf.push_back(sl);
+          if (t == VT_REFINED)
+            H.rverts.push_back((int32_t)((i - 1) + (n - 1) * ((j - 1) + (n - 1) * (d == 3 ? k - 1 : 0))));
           if (t == VT_LEAF || t == VT_REFINED) ++H.n_active;
         }
     // active tiles: every tile of the base level; on finer levels the tiles
@@ -324,6 +335,12 @@ void layout(qmg_grid_t* g, Arena& a) {
       if (l < L) B.cref = a.take<int8_t>(B.L.nslot);
       B.tiles = a.take<int32_t>((int64_t)H.tiles.size());
       if (l < L) B.sv = a.take<char>(B.L.nslot * (int64_t)it);
+      if (l < L) {
+        B.nrv = (int64_t)H.rverts.size();
+        B.rv = a.take<int32_t>(std::max<int64_t>(B.nrv, 1));
+        B.nrc = (int64_t)H.rcells.size();
+        B.rc = a.take<int32_t>(std::max<int64_t>(B.nrc, 1));
+      }
       if (g->mixed) {
         B.x64 = a.take<double>(B.L.nslot);
         B.b64 = a.take<double>(B.L.nslot);
@@ -420,6 +437,8 @@ void upload_linearisation(qmg_grid_t* g) {
     if (B.cref) QMG_HIP(hipMemcpy(B.cref, H.cref.data(), H.cref.size(), hipMemcpyHostToDevice));
     if (!H.tiles.empty())
       QMG_HIP(hipMemcpy(B.tiles, H.tiles.data(), H.tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (B.nrv > 0) QMG_HIP(hipMemcpy(B.rv, H.rverts.data(), B.nrv * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (B.nrc > 0) QMG_HIP(hipMemcpy(B.rc, H.rcells.data(), B.nrc * sizeof(int32_t), hipMemcpyHostToDevice));
     if (!H.leaf.empty())
       QMG_HIP(hipMemcpy(g->unk_slots + uo, H.leaf.data(), H.leaf.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     if (!H.cells.empty())
@@ -431,6 +450,10 @@ void upload_linearisation(qmg_grid_t* g) {
     H.vt.shrink_to_fit();
     H.cref.clear();
     H.cref.shrink_to_fit();
+    H.rverts.clear();
+    H.rverts.shrink_to_fit();
+    H.rcells.clear();
+    H.rcells.shrink_to_fit();
   }
   g->n_unknowns = uo;
   g->n_cells = co;
@@ -1015,7 +1038,8 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
       double* Pt = g->plain ? F.Pdense : g->tmpP;
       launch_zero<double>(Pt, F.L.nslot * NC, s);
       const bool ad = g->adaptive && l > g->lb;
-      launch_boxmg(F.L, C.L, Afine, F.eps64, Pt, s, ad ? F.vt : nullptr, ad ? C.cref : nullptr);
+      launch_boxmg(F.L, C.L, Afine, F.eps64, Pt, s, ad ? F.vt : nullptr, ad ? C.cref : nullptr,
+                   ad ? C.rc : nullptr, ad ? C.nrc : 0);
       Pw = Pt;
     } else if (g->plain) {
       Store dl;
@@ -1034,7 +1058,9 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
       launch_zero<double>(Ac, C.L.nslot * NS, s);
       // the finest adaptive level's rows exist only at leaf vertices
       const int8_t* mask = (g->adaptive && l == L && !Afine) ? F.vt : nullptr;
-      launch_rap(F.L, C.L, Afine, F.eps64, Pw, Ac, s, mask, (g->adaptive && l - 1 >= g->lb) ? C.vt : nullptr);
+      const bool adc = g->adaptive && l - 1 >= g->lb;
+      launch_rap(F.L, C.L, Afine, F.eps64, Pw, Ac, s, mask, adc ? C.vt : nullptr, adc ? C.rv : nullptr,
+                 adc ? C.nrv : 0);
       merge(l - 1, Ac);
       // the fallback of a failed check raises the coarsest level, which is
       // possible only below the base level of an adaptive spacetree

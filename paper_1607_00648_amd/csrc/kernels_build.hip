@@ -257,16 +257,33 @@ __device__ inline bool orthant_refined(const int8_t* cref, const Lat& Lc, int Vx
 
 // cref (nullable): refined flags of the coarse cells; patches of cells that
 // are not refined are skipped (adaptive levels)
+// cells (nullable): list of the refined coarse cells; thread (cell, corner)
+// solves the corner's orthant, which points into the cell
 template <int D>
 __global__ __launch_bounds__(64) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, double* __restrict__ Pw,
-                                              const int8_t* __restrict__ cref) {
+                                              const int8_t* __restrict__ cref, const int32_t* __restrict__ cells,
+                                              int64_t ncells) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int m = Lc.n - 1;
-  const int64_t nV = (D == 3) ? (int64_t)m * m * m : (int64_t)m * m;
-  if (t >= nV * Dim<D>::NC) return;
-  const int orth = (int)(t % Dim<D>::NC);
-  const int64_t Vi = t / Dim<D>::NC;
-  const int Vx = (int)(Vi % m) + 1, Vy = (int)((Vi / m) % m) + 1, Vz = (D == 3) ? (int)(Vi / ((int64_t)m * m)) + 1 : 0;
+  int orth, Vx, Vy, Vz;
+  if (cells) {
+    if (t >= ncells * Dim<D>::NC) return;
+    orth = (int)(t % Dim<D>::NC);
+    const int64_t c = cells[t / Dim<D>::NC];
+    const int n = Lc.n;
+    Vx = (int)(c % n) + (orth & 1);
+    Vy = (int)((c / n) % n) + ((orth >> 1) & 1);
+    Vz = (D == 3) ? (int)(c / ((int64_t)n * n)) + ((orth >> 2) & 1) : 0;
+    if (!interior(Lc, Vx, Vy, Vz)) return;
+  } else {
+    const int64_t nV = (D == 3) ? (int64_t)m * m * m : (int64_t)m * m;
+    if (t >= nV * Dim<D>::NC) return;
+    orth = (int)(t % Dim<D>::NC);
+    const int64_t Vi = t / Dim<D>::NC;
+    Vx = (int)(Vi % m) + 1;
+    Vy = (int)((Vi / m) % m) + 1;
+    Vz = (D == 3) ? (int)(Vi / ((int64_t)m * m)) + 1 : 0;
+  }
   const int sx = (orth & 1) ? -1 : 1, sy = (orth & 2) ? -1 : 1, sz = (D == 3 && (orth & 4)) ? -1 : 1;
   if (cref && !orthant_refined(cref, Lc, Vx, Vy, Vz, sx, sy, sz)) return;
   __shared__ double pl[27 * 64];
@@ -349,6 +366,7 @@ struct RapShape {
   static constexpr int NT = (D == 3) ? 128 : 256;
   static constexpr int RW = 7;                         // fine region 3V + [-3, 3]^d
   static constexpr int NR = (D == 3) ? 343 : 49;
+  static constexpr int GPW = 1;                        // groups per workgroup
 };
 
 // vtc (nullable): coarse vertex classes; rows of vertices that are not
@@ -362,28 +380,29 @@ struct RapShape {
 // are then weighted by P(i,V) and summed in a fixed order.  BoxMG weights of
 // the fine region 3V + [-3,3]^d are staged in LDS first.
 template <int D>
-__global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetch<D> A, PFetch<D> P,
-                                                         double* __restrict__ Ac,
-                                                         const int8_t* __restrict__ vtc) {
+__device__ inline void rap_group(const Lat& Lf, const Lat& Lc, const BoxFetch<D>& A, const PFetch<D>& P,
+                                 double* __restrict__ Ac, const int8_t* __restrict__ vtc,
+                                 const int32_t* __restrict__ vlist, int64_t nlist, int64_t grp,
+                                 double* col, double* pw, double* piv) {
   using S = RapShape<D>;
   constexpr int NS = Dim<D>::NS, NC = Dim<D>::NC;
-  __shared__ double col[NS * S::NT];
-  __shared__ double pw[S::VPB * S::NR * NC];
-  __shared__ double piv[S::NT];
   const int m = Lc.n - 1;
-  const int64_t nV = (D == 3) ? (int64_t)m * m * m : (int64_t)m * m;
+  // coarse vertices: every interior one, or the listed ones
+  const int64_t nV = vlist ? nlist : ((D == 3) ? (int64_t)m * m * m : (int64_t)m * m);
+  auto vert = [&](int64_t idx) -> int64_t { return vlist ? (int64_t)vlist[idx] : idx; };
   const int t = threadIdx.x;
   // coarse vertex of this thread (VPB per workgroup; the spare threads of
   // the last 5^d box take the last vertex and stay idle)
   const int sub = min(t / S::NI, S::VPB - 1);
   const int q = t - sub * S::NI;          // fine vertex within its 5^d box (idle when >= NI)
-  const int64_t Vi = (int64_t)blockIdx.x * S::VPB + sub;
+  const int64_t Vi = grp * S::VPB + sub;
   const bool have = Vi < nV;
   int Vx = 1, Vy = 1, Vz = 0;
   if (have) {
-    Vx = (int)(Vi % m) + 1;
-    Vy = (int)((Vi / m) % m) + 1;
-    Vz = (D == 3) ? (int)(Vi / ((int64_t)m * m)) + 1 : 0;
+    const int64_t Vv = vert(Vi);
+    Vx = (int)(Vv % m) + 1;
+    Vy = (int)((Vv / m) % m) + 1;
+    Vz = (D == 3) ? (int)(Vv / ((int64_t)m * m)) + 1 : 0;
   }
   const int64_t vc = Vx + (int64_t)Vy * Lc.pitch + (int64_t)Vz * Lc.plane;
   const bool act = have && (vtc == nullptr || vtc[vc] == VT_REFINED);
@@ -393,16 +412,17 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
   }
   // stage the BoxMG weights of each (refined) vertex's fine region
   if (P.W) {
-#pragma unroll 2
+#pragma unroll
     for (int e = t; e < S::VPB * S::NR * NC; e += S::NT) {
       const int vs = e / (S::NR * NC);
       const int r = e - vs * (S::NR * NC);
       const int kap = r % NC, jr = r / NC;
-      const int64_t Vj = (int64_t)blockIdx.x * S::VPB + vs;
+      const int64_t Vj = grp * S::VPB + vs;
       double w = 0.0;
       if (Vj < nV) {
-        const int ux = (int)(Vj % m) + 1, uy = (int)((Vj / m) % m) + 1;
-        const int uz = (D == 3) ? (int)(Vj / ((int64_t)m * m)) + 1 : 0;
+        const int64_t Vv = vert(Vj);
+        const int ux = (int)(Vv % m) + 1, uy = (int)((Vv / m) % m) + 1;
+        const int uz = (D == 3) ? (int)(Vv / ((int64_t)m * m)) + 1 : 0;
         const int64_t uc = ux + (int64_t)uy * Lc.pitch + (int64_t)uz * Lc.plane;
         if (vtc == nullptr || vtc[uc] == VT_REFINED) {
         const int jx = 3 * ux - 3 + jr % S::RW, jy = 3 * uy - 3 + (jr / S::RW) % S::RW;
@@ -449,18 +469,27 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
         if (ak == 0.0 || !interior(Lf, jx, jy, jz)) continue;
         const int qx = jx / 3, qy = jy / 3, qz = (D == 3) ? jz / 3 : 0;
         const int rx = jx - 3 * qx, ry = jy - 3 * qy, rz = jz - 3 * qz;
+        // the parents of j are distinct entries W - V: their column slots are
+        // read together, then updated
+        int slot[NC];
+        double add[NC];
 #pragma unroll
         for (int kap = 0; kap < NC; ++kap) {
           const int kx = kap & 1, ky = (kap >> 1) & 1, kz = (kap >> 2) & 1;
-          if ((kx && rx == 0) || (ky && ry == 0) || (kz && rz == 0)) continue;
           const int dx = qx + kx - Vx, dy = qy + ky - Vy, dz = (D == 3) ? qz + kz - Vz : 0;
-          if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) continue;
-          if (!interior(Lc, qx + kx, qy + ky, D == 3 ? qz + kz : 0)) continue;
-          const double pj = wt(jx, jy, jz, kap);
-          if (pj == 0.0) continue;
-          const int w = (dx + 1) + 3 * (dy + 1) + (D == 3 ? 9 * (dz + 1) : 0);
-          col[w * S::NT + t] += ak * pj;
+          bool ok = !((kx && rx == 0) || (ky && ry == 0) || (kz && rz == 0));
+          ok = ok && dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+          ok = ok && interior(Lc, qx + kx, qy + ky, D == 3 ? qz + kz : 0);
+          const double pj = ok ? wt(jx, jy, jz, kap) : 0.0;
+          slot[kap] = ok ? ((dx + 1) + 3 * (dy + 1) + (D == 3 ? 9 * (dz + 1) : 0)) * S::NT + t : -1;
+          add[kap] = ak * pj;
         }
+        double cur[NC];
+#pragma unroll
+        for (int kap = 0; kap < NC; ++kap) cur[kap] = col[slot[kap] >= 0 ? slot[kap] : t];
+#pragma unroll
+        for (int kap = 0; kap < NC; ++kap)
+          if (slot[kap] >= 0) col[slot[kap]] = cur[kap] + add[kap];
       }
     }
   }
@@ -469,10 +498,11 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
   // fixed-order sums: thread sub*NS + w of the first VPB*NS threads
   if (t < S::VPB * NS) {
     const int vs = t / NS, w = t - vs * NS;
-    const int64_t Vj = (int64_t)blockIdx.x * S::VPB + vs;
+    const int64_t Vj = grp * S::VPB + vs;
     if (Vj < nV) {
-      const int ux = (int)(Vj % m) + 1, uy = (int)((Vj / m) % m) + 1;
-      const int uz = (D == 3) ? (int)(Vj / ((int64_t)m * m)) + 1 : 0;
+      const int64_t Vv = vert(Vj);
+      const int ux = (int)(Vv % m) + 1, uy = (int)((Vv / m) % m) + 1;
+      const int uz = (D == 3) ? (int)(Vv / ((int64_t)m * m)) + 1 : 0;
       double acc = 0.0;
 #pragma unroll 5
       for (int r = 0; r < S::NI; ++r) {
@@ -481,6 +511,28 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
       }
       Ac[(int64_t)w * Lc.nslot + ux + (int64_t)uy * Lc.pitch + (int64_t)uz * Lc.plane] = acc;
     }
+  }
+}
+
+// One workgroup takes RapShape::GPW consecutive groups of coarse vertices in
+// turn (one measured fastest: the refined vertices of an adaptive level
+// cluster, so longer workgroups only serialise their work).
+template <int D>
+__global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetch<D> A, PFetch<D> P,
+                                                         double* __restrict__ Ac,
+                                                         const int8_t* __restrict__ vtc,
+                                                         const int32_t* __restrict__ vlist, int64_t nlist,
+                                                         int64_t ngrp) {
+  using S = RapShape<D>;
+  constexpr int NS = Dim<D>::NS, NC = Dim<D>::NC;
+  __shared__ double col[NS * S::NT];
+  __shared__ double pw[S::VPB * S::NR * NC];
+  __shared__ double piv[S::NT];
+  const int64_t g0 = (int64_t)blockIdx.x * S::GPW;
+  const int64_t g1 = g0 + S::GPW < ngrp ? g0 + S::GPW : ngrp;
+  for (int64_t grp = g0; grp < g1; ++grp) {
+    __syncthreads();  // the previous group's LDS reads are done
+    rap_group<D>(Lf, Lc, A, P, Ac, vtc, vlist, nlist, grp, col, pw, piv);
   }
 }
 
@@ -685,37 +737,46 @@ void launch_materialise_P(const Lat& Lf, const Lat& Lc, const Store& P, double* 
 }
 
 void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf, double* Pw,
-                  hipStream_t s, const int8_t* vt_fine, const int8_t* cref_coarse) {
+                  hipStream_t s, const int8_t* vt_fine, const int8_t* cref_coarse, const int32_t* cells,
+                  int64_t n_cells) {
   const int m = Lc.n - 1;
   if (m <= 0) return;
+  const int64_t nv = (Lf.d == 3) ? (int64_t)m * m * m : (int64_t)m * m;
+  const int64_t nt = (cells ? n_cells : nv) * (Lf.d == 3 ? 8 : 4);
+  if (nt == 0) return;
   if (Lf.d == 2) {
-    const int64_t nt = (int64_t)m * m * 4;
     BoxFetch<2> F{Afine, epsf, Lf, vt_fine, vt_fine != nullptr};
-    hipLaunchKernelGGL(k_boxmg<2>, dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse);
+    hipLaunchKernelGGL(k_boxmg<2>, dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
+                       n_cells);
   } else {
-    const int64_t nt = (int64_t)m * m * m * 8;
     BoxFetch<3> F{Afine, epsf, Lf, vt_fine, vt_fine != nullptr};
-    hipLaunchKernelGGL(k_boxmg<3>, dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse);
+    hipLaunchKernelGGL(k_boxmg<3>, dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
+                       n_cells);
   }
   QMG_HIP(hipGetLastError());
 }
 
 void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
-                const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine, const int8_t* vt_coarse) {
+                const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine, const int8_t* vt_coarse,
+                const int32_t* verts, int64_t n_verts) {
   const int m = Lc.n - 1;
   if (m <= 0) return;
+  const int64_t nV = verts ? n_verts : (Lf.d == 3 ? (int64_t)m * m * m : (int64_t)m * m);
+  if (nV == 0) return;
   if (Lf.d == 2) {
     using S = RapShape<2>;
-    const int64_t nV = (int64_t)m * m;
+    const int64_t ngrp = (nV + S::VPB - 1) / S::VPB;
     BoxFetch<2> A{Afine, epsf, Lf, vt_fine};
     PFetch<2> P{Pw, Lf, Lc};
-    hipLaunchKernelGGL(k_rap<2>, dim3(blocks_for(nV, S::VPB)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse);
+    hipLaunchKernelGGL(k_rap<2>, dim3(blocks_for(ngrp, S::GPW)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse,
+                       verts, n_verts, ngrp);
   } else {
     using S = RapShape<3>;
-    const int64_t nV = (int64_t)m * m * m;
+    const int64_t ngrp = (nV + S::VPB - 1) / S::VPB;
     BoxFetch<3> A{Afine, epsf, Lf, vt_fine};
     PFetch<3> P{Pw, Lf, Lc};
-    hipLaunchKernelGGL(k_rap<3>, dim3(blocks_for(nV, S::VPB)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse);
+    hipLaunchKernelGGL(k_rap<3>, dim3(blocks_for(ngrp, S::GPW)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse,
+                       verts, n_verts, ngrp);
   }
   QMG_HIP(hipGetLastError());
 }

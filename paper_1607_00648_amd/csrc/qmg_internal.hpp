@@ -156,18 +156,21 @@ void launch_materialise_P(const Lat& Lf, const Lat& Lc, const Store& P, double* 
 // vt_fine / cref_coarse (adaptive levels, nullable): fine vertex classes (rows
 // of leaf and refined vertices from Afine or eps, hanging rows rediscretised
 // from eps, others zero) and the refined flags of the coarse cells (only
-// refined cells are patches).
+// refined cells are patches).  cells (nullable, with cref_coarse): the n_cells
+// refined coarse cells (cell index, x fastest); only their corners are solved.
 void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
                   double* Pw, hipStream_t s, const int8_t* vt_fine = nullptr,
-                  const int8_t* cref_coarse = nullptr);
+                  const int8_t* cref_coarse = nullptr, const int32_t* cells = nullptr, int64_t n_cells = 0);
 // Galerkin RAP (Sect. 3.3): coarse FP64 stencils from fine stencils (or eps on
 // the fly when Afine is null) and FP64 parent weights (d-linear when Pw null).
 // vt_fine (nullable): vertex classes of the fine level; rows of vertices that
 // are neither leaf nor refined count as zero.
 // vt_coarse (nullable): only rows of refined coarse vertices are formed.
+// verts (nullable): those n_verts vertices as interior indices (x fastest);
+// only they are visited (the other rows must have been zeroed).
 void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
                 const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine = nullptr,
-                const int8_t* vt_coarse = nullptr);
+                const int8_t* vt_coarse = nullptr, const int32_t* verts = nullptr, int64_t n_verts = 0);
 // Definiteness check of coarse stencils; counts failing rows into *bad.
 void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s);
 // Hierarchical delta store: per-block zero flags, compaction and payload.  The

@@ -357,182 +357,152 @@ struct PFetch {
   }
 };
 
-// Work shape of the Galerkin kernel: one thread per fine vertex i within 2 of
-// 3V (5^d of them), one coarse vertex V per workgroup in 3D, ten in 2D.
+// Work shape of the Galerkin kernel: VPB coarse vertices V per workgroup
+// (one in 3D, ten in 2D), 5^d fine vertices i within 2 of 3V each, and the
+// fine region 3V + [-3, 3]^d that their stencils reach.
 template <int D>
 struct RapShape {
   static constexpr int NI = (D == 3) ? 125 : 25;
   static constexpr int VPB = (D == 3) ? 1 : 10;
   static constexpr int NT = (D == 3) ? 128 : 256;
-  static constexpr int RW = 7;                         // fine region 3V + [-3, 3]^d
+  static constexpr int RW = 7;
   static constexpr int NR = (D == 3) ? 343 : 49;
-  static constexpr int GPW = 1;                        // groups per workgroup
 };
 
+// A_c(V, W) = sum_j (sum_i P(i,V) a(i,j)) P(j,W), i within 2 of 3V, |i - j| <= 1,
+// in three phases over LDS, each a gather in a fixed order:
+//   1. one thread per i: P(i,V) and the row of i (from the store, or
+//      rediscretised from eps with boundary entries dropped);
+//   2. one task per fine j of the region: t(j) = sum_i P(i,V) a(i,j);
+//   3. one thread per entry W - V in [-1,1]^d: sum over the j within 2 of 3W
+//      of t(j) P(j,W).
+// BoxMG weights P(j, .) of the region are staged in LDS in phase 1.
 // vtc (nullable): coarse vertex classes; rows of vertices that are not
-// refined are left zero (an adaptive level replaces them by rediscretised or
-// empty rows).
-//
-// A_c(V, W) = sum_i P(i,V) sum_j a(i,j) P(j,W) over fine i within 2 of 3V and
-// j = i + o, o in [-1,1]^d.  Each thread takes one i: it builds i's row once,
-// walks its 3^d neighbours j and their (up to 2^d) parents W near V, and adds
-// a(i,j) P(j,W) to its own LDS column of the 3^d entries W - V.  The columns
-// are then weighted by P(i,V) and summed in a fixed order.  BoxMG weights of
-// the fine region 3V + [-3,3]^d are staged in LDS first.
+// refined are left zero.  vlist (nullable): the nlist coarse vertices to form
+// (interior indices); the others are not visited.
 template <int D>
-__device__ inline void rap_group(const Lat& Lf, const Lat& Lc, const BoxFetch<D>& A, const PFetch<D>& P,
-                                 double* __restrict__ Ac, const int8_t* __restrict__ vtc,
-                                 const int32_t* __restrict__ vlist, int64_t nlist, int64_t grp,
-                                 double* col, double* pw, double* piv) {
+__global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetch<D> A, PFetch<D> P,
+                                                         double* __restrict__ Ac,
+                                                         const int8_t* __restrict__ vtc,
+                                                         const int32_t* __restrict__ vlist, int64_t nlist) {
   using S = RapShape<D>;
   constexpr int NS = Dim<D>::NS, NC = Dim<D>::NC;
+  __shared__ double arow[S::VPB * S::NI * NS];
+  __shared__ double piv[S::VPB * S::NI];
+  __shared__ double tj[S::VPB * S::NR];
+  __shared__ double pw[S::VPB * S::NR * NC];
+  __shared__ int vco[S::VPB * 4];  // per vertex: x, y, z, active
   const int m = Lc.n - 1;
-  // coarse vertices: every interior one, or the listed ones
   const int64_t nV = vlist ? nlist : ((D == 3) ? (int64_t)m * m * m : (int64_t)m * m);
-  auto vert = [&](int64_t idx) -> int64_t { return vlist ? (int64_t)vlist[idx] : idx; };
   const int t = threadIdx.x;
-  // coarse vertex of this thread (VPB per workgroup; the spare threads of
-  // the last 5^d box take the last vertex and stay idle)
-  const int sub = min(t / S::NI, S::VPB - 1);
-  const int q = t - sub * S::NI;          // fine vertex within its 5^d box (idle when >= NI)
-  const int64_t Vi = grp * S::VPB + sub;
-  const bool have = Vi < nV;
-  int Vx = 1, Vy = 1, Vz = 0;
-  if (have) {
-    const int64_t Vv = vert(Vi);
-    Vx = (int)(Vv % m) + 1;
-    Vy = (int)((Vv / m) % m) + 1;
-    Vz = (D == 3) ? (int)(Vv / ((int64_t)m * m)) + 1 : 0;
+  if (t < S::VPB) {
+    const int64_t idx = (int64_t)blockIdx.x * S::VPB + t;
+    int vx = 1, vy = 1, vz = 0, on = 0;
+    if (idx < nV) {
+      const int64_t vv = vlist ? (int64_t)vlist[idx] : idx;
+      vx = (int)(vv % m) + 1;
+      vy = (int)((vv / m) % m) + 1;
+      vz = (D == 3) ? (int)(vv / ((int64_t)m * m)) + 1 : 0;
+      on = (vtc == nullptr || vtc[vx + (int64_t)vy * Lc.pitch + (int64_t)vz * Lc.plane] == VT_REFINED) ? 1 : 2;
+    }
+    vco[4 * t] = vx;
+    vco[4 * t + 1] = vy;
+    vco[4 * t + 2] = vz;
+    vco[4 * t + 3] = on;  // 0: none, 1: form the row, 2: write a zero row
   }
-  const int64_t vc = Vx + (int64_t)Vy * Lc.pitch + (int64_t)Vz * Lc.plane;
-  const bool act = have && (vtc == nullptr || vtc[vc] == VT_REFINED);
-  if (D == 3 && !act) {  // one vertex per workgroup: the whole workgroup leaves together
-    if (have && t < NS) Ac[(int64_t)t * Lc.nslot + vc] = 0.0;
-    return;
-  }
-  // stage the BoxMG weights of each (refined) vertex's fine region
+  __syncthreads();
+  // phase 1: weights and rows of the i of each vertex; staged BoxMG weights
   if (P.W) {
 #pragma unroll
     for (int e = t; e < S::VPB * S::NR * NC; e += S::NT) {
       const int vs = e / (S::NR * NC);
       const int r = e - vs * (S::NR * NC);
       const int kap = r % NC, jr = r / NC;
-      const int64_t Vj = grp * S::VPB + vs;
       double w = 0.0;
-      if (Vj < nV) {
-        const int64_t Vv = vert(Vj);
-        const int ux = (int)(Vv % m) + 1, uy = (int)((Vv / m) % m) + 1;
-        const int uz = (D == 3) ? (int)(Vv / ((int64_t)m * m)) + 1 : 0;
-        const int64_t uc = ux + (int64_t)uy * Lc.pitch + (int64_t)uz * Lc.plane;
-        if (vtc == nullptr || vtc[uc] == VT_REFINED) {
-        const int jx = 3 * ux - 3 + jr % S::RW, jy = 3 * uy - 3 + (jr / S::RW) % S::RW;
-        const int jz = (D == 3) ? 3 * uz - 3 + jr / (S::RW * S::RW) : 0;
-          w = P.W[(int64_t)kap * Lf.nslot + jx + (int64_t)jy * Lf.pitch + (int64_t)jz * Lf.plane];
-        }
+      if (vco[4 * vs + 3] == 1) {
+        const int jx = 3 * vco[4 * vs] - 3 + jr % S::RW, jy = 3 * vco[4 * vs + 1] - 3 + (jr / S::RW) % S::RW;
+        const int jz = (D == 3) ? 3 * vco[4 * vs + 2] - 3 + jr / (S::RW * S::RW) : 0;
+        w = P.W[(int64_t)kap * Lf.nslot + jx + (int64_t)jy * Lf.pitch + (int64_t)jz * Lf.plane];
       }
       pw[e] = w;
     }
   }
+  {
+    const int vs = t / S::NI, q = t - (t / S::NI) * S::NI;
+    if (vs < S::VPB) {
+      double pi = 0.0;
+      double* ar = arow + (vs * S::NI + q) * NS;
+      if (vco[4 * vs + 3] == 1) {
+        const int Vx = vco[4 * vs], Vy = vco[4 * vs + 1], Vz = vco[4 * vs + 2];
+        const int ix = 3 * Vx + q % 5 - 2, iy = 3 * Vy + (q / 5) % 5 - 2, iz = (D == 3) ? 3 * Vz + q / 25 - 2 : 0;
+        pi = P(ix, iy, iz, Vx, Vy, Vz);
+        const int64_t vi = ix + (int64_t)iy * Lf.pitch + (int64_t)iz * Lf.plane;
+        const RowSrc<D> row(A, vi);
 #pragma unroll
-  for (int e = 0; e < NS; ++e) col[e * S::NT + t] = 0.0;
-  __syncthreads();
-  const int ox = q % 5 - 2, oy = (q / 5) % 5 - 2, oz = (D == 3) ? q / 25 - 2 : 0;
-  double pi = 0.0;
-  if (act && q < S::NI) {
-    const int ix = 3 * Vx + ox, iy = 3 * Vy + oy, iz = 3 * Vz + oz;
-    const double* pr = pw + sub * S::NR * NC;
-    // weight at fine (x,y,z) of the parent floor(f/3)+kap, from the staged
-    // region or the d-linear formula
-    auto wt = [&](int x, int y, int z, int kap) -> double {
-      if (P.W) {
-        const int rl = (x - 3 * Vx + 3) + S::RW * ((y - 3 * Vy + 3) + S::RW * (D == 3 ? z - 3 * Vz + 3 : 0));
-        return pr[rl * NC + kap];
-      }
-      const int rx = x - 3 * (x / 3), ry = y - 3 * (y / 3), rz = (D == 3) ? z - 3 * (z / 3) : 0;
-      return dlin1(rx, kap & 1) * dlin1(ry, (kap >> 1) & 1) * (D == 3 ? dlin1(rz, (kap >> 2) & 1) : 1.0);
-    };
-    {
-      const int kx = Vx - ix / 3, ky = Vy - iy / 3, kz = (D == 3) ? Vz - iz / 3 : 0;
-      pi = wt(ix, iy, iz, kx | (ky << 1) | (kz << 2));
-    }
-    if (pi != 0.0) {
-      const int64_t vi = ix + (int64_t)iy * Lf.pitch + (int64_t)iz * Lf.plane;
-      const RowSrc<D> row(A, vi);
-      // the next entry is fetched while the current one is spread (stored
-      // rows come from global memory)
-      double anext = row.mode == 0 ? 0.0 : row.entry(A, vi, 0);
-#pragma unroll 1
-      for (int k = 0; k < NS; ++k) {
-        const double ak = anext;
-        if (k + 1 < NS && row.mode != 0) anext = row.entry(A, vi, k + 1);
-        const int jx = ix + off_x(k), jy = iy + off_y(k), jz = iz + (D == 3 ? off_z(k) : 0);
-        if (ak == 0.0 || !interior(Lf, jx, jy, jz)) continue;
-        const int qx = jx / 3, qy = jy / 3, qz = (D == 3) ? jz / 3 : 0;
-        const int rx = jx - 3 * qx, ry = jy - 3 * qy, rz = jz - 3 * qz;
-        // the parents of j are distinct entries W - V: their column slots are
-        // read together, then updated
-        int slot[NC];
-        double add[NC];
-#pragma unroll
-        for (int kap = 0; kap < NC; ++kap) {
-          const int kx = kap & 1, ky = (kap >> 1) & 1, kz = (kap >> 2) & 1;
-          const int dx = qx + kx - Vx, dy = qy + ky - Vy, dz = (D == 3) ? qz + kz - Vz : 0;
-          bool ok = !((kx && rx == 0) || (ky && ry == 0) || (kz && rz == 0));
-          ok = ok && dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
-          ok = ok && interior(Lc, qx + kx, qy + ky, D == 3 ? qz + kz : 0);
-          const double pj = ok ? wt(jx, jy, jz, kap) : 0.0;
-          slot[kap] = ok ? ((dx + 1) + 3 * (dy + 1) + (D == 3 ? 9 * (dz + 1) : 0)) * S::NT + t : -1;
-          add[kap] = ak * pj;
+        for (int k = 0; k < NS; ++k) {
+          double a = 0.0;
+          if (row.mode == 1 || (row.mode == 2 && interior(Lf, ix + off_x(k), iy + off_y(k),
+                                                            iz + (D == 3 ? off_z(k) : 0))))
+            a = row.entry(A, vi, k);
+          ar[k] = a;
         }
-        double cur[NC];
+      } else {
 #pragma unroll
-        for (int kap = 0; kap < NC; ++kap) cur[kap] = col[slot[kap] >= 0 ? slot[kap] : t];
-#pragma unroll
-        for (int kap = 0; kap < NC; ++kap)
-          if (slot[kap] >= 0) col[slot[kap]] = cur[kap] + add[kap];
+        for (int k = 0; k < NS; ++k) ar[k] = 0.0;
       }
+      piv[vs * S::NI + q] = pi;
     }
   }
-  piv[t] = pi;
   __syncthreads();
-  // fixed-order sums: thread sub*NS + w of the first VPB*NS threads
-  if (t < S::VPB * NS) {
-    const int vs = t / NS, w = t - vs * NS;
-    const int64_t Vj = grp * S::VPB + vs;
-    if (Vj < nV) {
-      const int64_t Vv = vert(Vj);
-      const int ux = (int)(Vv % m) + 1, uy = (int)((Vv / m) % m) + 1;
-      const int uz = (D == 3) ? (int)(Vv / ((int64_t)m * m)) + 1 : 0;
-      double acc = 0.0;
-#pragma unroll 5
-      for (int r = 0; r < S::NI; ++r) {
-        const int tt = vs * S::NI + r;
-        acc += piv[tt] * col[w * S::NT + tt];
-      }
-      Ac[(int64_t)w * Lc.nslot + ux + (int64_t)uy * Lc.pitch + (int64_t)uz * Lc.plane] = acc;
+  // phase 2: t(j) = sum_i P(i,V) a(i,j) over the i = j - o_k inside the box
+  for (int e = t; e < S::VPB * S::NR; e += S::NT) {
+    const int vs = e / S::NR, jr = e - (e / S::NR) * S::NR;
+    const int jx = jr % S::RW - 3, jy = (jr / S::RW) % S::RW - 3, jz = (D == 3) ? jr / (S::RW * S::RW) - 3 : 0;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int ox = jx - off_x(k), oy = jy - off_y(k), oz = (D == 3) ? jz - off_z(k) : 0;
+      if (ox < -2 || ox > 2 || oy < -2 || oy > 2 || oz < -2 || oz > 2) continue;
+      const int qi = (ox + 2) + 5 * (oy + 2) + (D == 3 ? 25 * (oz + 2) : 0);
+      acc += piv[vs * S::NI + qi] * arow[(vs * S::NI + qi) * NS + k];
     }
+    tj[e] = acc;
   }
-}
-
-// One workgroup takes RapShape::GPW consecutive groups of coarse vertices in
-// turn (one measured fastest: the refined vertices of an adaptive level
-// cluster, so longer workgroups only serialise their work).
-template <int D>
-__global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetch<D> A, PFetch<D> P,
-                                                         double* __restrict__ Ac,
-                                                         const int8_t* __restrict__ vtc,
-                                                         const int32_t* __restrict__ vlist, int64_t nlist,
-                                                         int64_t ngrp) {
-  using S = RapShape<D>;
-  constexpr int NS = Dim<D>::NS, NC = Dim<D>::NC;
-  __shared__ double col[NS * S::NT];
-  __shared__ double pw[S::VPB * S::NR * NC];
-  __shared__ double piv[S::NT];
-  const int64_t g0 = (int64_t)blockIdx.x * S::GPW;
-  const int64_t g1 = g0 + S::GPW < ngrp ? g0 + S::GPW : ngrp;
-  for (int64_t grp = g0; grp < g1; ++grp) {
-    __syncthreads();  // the previous group's LDS reads are done
-    rap_group<D>(Lf, Lc, A, P, Ac, vtc, vlist, nlist, grp, col, pw, piv);
+  __syncthreads();
+  // phase 3: A_c(V, W) = sum_j t(j) P(j, W), j within 2 of 3W inside the region
+  if (t < S::VPB * NS) {
+    const int vs = t / NS, w = t - (t / NS) * NS;
+    const int on = vco[4 * vs + 3];
+    if (on != 0) {
+      const int Vx = vco[4 * vs], Vy = vco[4 * vs + 1], Vz = vco[4 * vs + 2];
+      const int dx = off_x(w), dy = off_y(w), dz = (D == 3) ? off_z(w) : 0;
+      double acc = 0.0;
+      if (on == 1 && interior(Lc, Vx + dx, Vy + dy, Vz + dz)) {
+        // region offsets of j per axis: [3d - 2, 3d + 2] clipped to [-3, 3]
+        const int xl = max(3 * dx - 2, -3), xh = min(3 * dx + 2, 3);
+        const int yl = max(3 * dy - 2, -3), yh = min(3 * dy + 2, 3);
+        const int zl = (D == 3) ? max(3 * dz - 2, -3) : 0, zh = (D == 3) ? min(3 * dz + 2, 3) : 0;
+        const double* pr = pw + vs * S::NR * NC;
+        for (int jz = zl; jz <= zh; ++jz)
+          for (int jy = yl; jy <= yh; ++jy)
+#pragma unroll 5
+            for (int jx = xl; jx <= xh; ++jx) {
+              const int jr = (jx + 3) + S::RW * ((jy + 3) + (D == 3 ? S::RW * (jz + 3) : 0));
+              // parent index of W at j: W - floor(j/3) per axis (j = 3V + offset)
+              const int kx = dx - (jx + 3) / 3 + 1, ky = dy - (jy + 3) / 3 + 1;
+              const int kz = (D == 3) ? dz - (jz + 3) / 3 + 1 : 0;
+              double pj;
+              if (P.W) {
+                pj = pr[jr * NC + (kx | (ky << 1) | (kz << 2))];
+              } else {
+                const int rx = (jx + 3) % 3, ry = (jy + 3) % 3, rz = (D == 3) ? (jz + 3) % 3 : 0;
+                pj = dlin1(rx, kx) * dlin1(ry, ky) * (D == 3 ? dlin1(rz, kz) : 1.0);
+              }
+              acc += tj[vs * S::NR + jr] * pj;
+            }
+      }
+      Ac[(int64_t)w * Lc.nslot + Vx + (int64_t)Vy * Lc.pitch + (int64_t)Vz * Lc.plane] = acc;
+    }
   }
 }
 
@@ -765,18 +735,16 @@ void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double*
   if (nV == 0) return;
   if (Lf.d == 2) {
     using S = RapShape<2>;
-    const int64_t ngrp = (nV + S::VPB - 1) / S::VPB;
     BoxFetch<2> A{Afine, epsf, Lf, vt_fine};
     PFetch<2> P{Pw, Lf, Lc};
-    hipLaunchKernelGGL(k_rap<2>, dim3(blocks_for(ngrp, S::GPW)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse,
-                       verts, n_verts, ngrp);
+    hipLaunchKernelGGL(k_rap<2>, dim3(blocks_for(nV, S::VPB)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse,
+                       verts, n_verts);
   } else {
     using S = RapShape<3>;
-    const int64_t ngrp = (nV + S::VPB - 1) / S::VPB;
     BoxFetch<3> A{Afine, epsf, Lf, vt_fine};
     PFetch<3> P{Pw, Lf, Lc};
-    hipLaunchKernelGGL(k_rap<3>, dim3(blocks_for(ngrp, S::GPW)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse,
-                       verts, n_verts, ngrp);
+    hipLaunchKernelGGL(k_rap<3>, dim3(blocks_for(nV, S::VPB)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse,
+                       verts, n_verts);
   }
   QMG_HIP(hipGetLastError());
 }

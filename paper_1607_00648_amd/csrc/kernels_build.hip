@@ -364,9 +364,10 @@ template <int D>
 struct RapShape {
   static constexpr int NI = (D == 3) ? 125 : 25;
   static constexpr int VPB = (D == 3) ? 1 : 10;
-  static constexpr int NT = (D == 3) ? 128 : 256;
+  static constexpr int NT = (D == 3) ? 192 : 256;
   static constexpr int RW = 7;
   static constexpr int NR = (D == 3) ? 343 : 49;
+  static constexpr int NP = (D == 3) ? 5 : 1;  // parts of one entry's sum (planes of j)
 };
 
 // A_c(V, W) = sum_j (sum_i P(i,V) a(i,j)) P(j,W), i within 2 of 3V, |i - j| <= 1,
@@ -392,6 +393,7 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
   __shared__ double tj[S::VPB * S::NR];
   __shared__ double pw[S::VPB * S::NR * NC];
   __shared__ int vco[S::VPB * 4];  // per vertex: x, y, z, active
+  __shared__ double tpart[S::VPB * Dim<D>::NS * S::NP];
   const int m = Lc.n - 1;
   const int64_t nV = vlist ? nlist : ((D == 3) ? (int64_t)m * m * m : (int64_t)m * m);
   const int t = threadIdx.x;
@@ -469,19 +471,22 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
     tj[e] = acc;
   }
   __syncthreads();
-  // phase 3: A_c(V, W) = sum_j t(j) P(j, W), j within 2 of 3W inside the region
-  if (t < S::VPB * NS) {
-    const int vs = t / NS, w = t - (t / NS) * NS;
+  // phase 3: A_c(V, W) = sum_j t(j) P(j, W), j within 2 of 3W inside the
+  // region; in 3D each entry's sum is split over the (up to 5) planes of j,
+  // whose partial sums are then added in order
+  if (t < S::VPB * NS * S::NP) {
+    const int vs = t / (NS * S::NP), w = (t / S::NP) % NS, part = t % S::NP;
     const int on = vco[4 * vs + 3];
-    if (on != 0) {
+    double acc = 0.0;
+    if (on == 1) {
       const int Vx = vco[4 * vs], Vy = vco[4 * vs + 1], Vz = vco[4 * vs + 2];
       const int dx = off_x(w), dy = off_y(w), dz = (D == 3) ? off_z(w) : 0;
-      double acc = 0.0;
-      if (on == 1 && interior(Lc, Vx + dx, Vy + dy, Vz + dz)) {
-        // region offsets of j per axis: [3d - 2, 3d + 2] clipped to [-3, 3]
-        const int xl = max(3 * dx - 2, -3), xh = min(3 * dx + 2, 3);
-        const int yl = max(3 * dy - 2, -3), yh = min(3 * dy + 2, 3);
-        const int zl = (D == 3) ? max(3 * dz - 2, -3) : 0, zh = (D == 3) ? min(3 * dz + 2, 3) : 0;
+      // region offsets of j per axis: [3d - 2, 3d + 2] clipped to [-3, 3]
+      const int xl = max(3 * dx - 2, -3), xh = min(3 * dx + 2, 3);
+      const int yl = max(3 * dy - 2, -3), yh = min(3 * dy + 2, 3);
+      const int zl = (D == 3) ? max(3 * dz - 2, -3) + part : 0;
+      const int zh = (D == 3) ? min(min(3 * dz + 2, 3), zl) : 0;
+      if (interior(Lc, Vx + dx, Vy + dy, Vz + dz)) {
         const double* pr = pw + vs * S::NR * NC;
         for (int jz = zl; jz <= zh; ++jz)
           for (int jy = yl; jy <= yh; ++jy)
@@ -501,7 +506,18 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
               acc += tj[vs * S::NR + jr] * pj;
             }
       }
-      Ac[(int64_t)w * Lc.nslot + Vx + (int64_t)Vy * Lc.pitch + (int64_t)Vz * Lc.plane] = acc;
+    }
+    tpart[t] = acc;
+  }
+  __syncthreads();
+  if (t < S::VPB * NS) {
+    const int vs = t / NS, w = t - (t / NS) * NS;
+    if (vco[4 * vs + 3] != 0) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < S::NP; ++q) acc += tpart[t * S::NP + q];
+      Ac[(int64_t)w * Lc.nslot + vco[4 * vs] + (int64_t)vco[4 * vs + 1] * Lc.pitch +
+         (int64_t)vco[4 * vs + 2] * Lc.plane] = acc;
     }
   }
 }

@@ -72,6 +72,155 @@ __global__ __launch_bounds__(256) void k_stencil(Lat L, const T* __restrict__ u,
   }
 }
 
+// 3D levels: a workgroup of 64 x 8 threads owns a 64 x 8 (x, y) tile and
+// marches over a chunk of MZ interior planes.  Three planes of the iterate
+// (tile plus a halo of one vertex) and two planes of cell coefficients ring
+// through LDS, so each value comes from memory once per chunk instead of once
+// per neighbour; every thread updates one vertex per plane with the same
+// expressions, in the same order, as k_stencil.
+constexpr int MX = 64, MY = 8, MZ = 16;
+constexpr int UW = MX + 2, UH = MY + 2;  // iterate plane region: x0-1..x0+64, y0-1..y0+8
+constexpr int EW = MX + 1, EH = MY + 1;  // cell plane region: x0-1..x0+63, y0-1..y0+7
+
+inline dim3 march_grid(const Lat& L) {
+  return dim3((unsigned)(L.pitch / MX), (unsigned)((L.n + 1 + MY - 1) / MY), (unsigned)((L.n - 1 + MZ - 1) / MZ));
+}
+
+template <typename T, typename TO, int SRC, int FMT, int MODE>
+__global__ __launch_bounds__(MX * MY) void k_march3d(Lat L, const T* __restrict__ u, const T* __restrict__ b,
+                                                     TO* __restrict__ out, const T* __restrict__ eps, Store A,
+                                                     T omega, double* __restrict__ partial) {
+  constexpr int NS = 27;
+  __shared__ T up[3][UW * UH];
+  __shared__ T ep[2][EW * EH];
+  __shared__ double red[MX * MY / 64];
+  const Tile tl = xcd_tile();
+  const int n = L.n;
+  const int x0 = tl.x * MX, y0 = tl.y * MY;
+  const int k0 = 1 + tl.z * MZ, k1 = min(k0 + MZ, n);  // interior planes [k0, k1)
+  const int tid = threadIdx.x;
+  const int lx = tid % MX, ly = tid / MX;
+  const int i = x0 + lx, j = y0 + ly;
+  const bool inplane = i >= 1 && i < n && j >= 1 && j < n;
+  // each thread moves at most two values of a plane region; the next planes'
+  // values are fetched into registers while the current plane is computed
+  constexpr int NT = MX * MY;
+  static_assert(UW * UH <= 2 * NT && EW * EH <= 2 * NT, "two values per thread");
+  auto fetch_u = [&](int k, T (&r)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + h * NT;
+      const int x = x0 - 1 + e % UW, y = y0 - 1 + e / UW;
+      r[h] = (e < UW * UH && x >= 0 && x <= n && y >= 0 && y <= n && k <= n)
+                 ? u[x + (int64_t)y * L.pitch + (int64_t)k * L.plane] : (T)0;
+    }
+  };
+  auto fetch_e = [&](int k, T (&r)[2]) {  // cells with low corner on plane k
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + h * NT;
+      const int x = x0 - 1 + e % EW, y = y0 - 1 + e / EW;
+      r[h] = (e < EW * EH && x >= 0 && x < n && y >= 0 && y < n && k < n)
+                 ? eps[x + (int64_t)y * L.pitch + (int64_t)k * L.plane] : (T)0;
+    }
+  };
+  auto put_u = [&](int k, const T (&r)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (tid + h * NT < UW * UH) up[k % 3][tid + h * NT] = r[h];
+  };
+  auto put_e = [&](int k, const T (&r)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (tid + h * NT < EW * EH) ep[k % 2][tid + h * NT] = r[h];
+  };
+  T ru[2] = {(T)0, (T)0}, re[2] = {(T)0, (T)0};
+  if (MODE != 1) {
+    fetch_u(k0 - 1, ru);
+    put_u(k0 - 1, ru);
+    fetch_u(k0, ru);
+    put_u(k0, ru);
+    fetch_u(k0 + 1, ru);
+  }
+  if (SRC != SRC_PLAIN) {
+    fetch_e(k0 - 1, re);
+    put_e(k0 - 1, re);
+    fetch_e(k0, re);
+  }
+  double sq = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    if (MODE != 1) {
+      put_u(k + 1, ru);
+      if (k + 1 < k1) fetch_u(k + 2, ru);
+    }
+    if (SRC != SRC_PLAIN) {
+      put_e(k, re);
+      if (k + 1 < k1) fetch_e(k + 1, re);
+    }
+    __syncthreads();
+    if (inplane) {
+      const int64_t v = i + (int64_t)j * L.pitch + (int64_t)k * L.plane;
+      T a[NS];
+      if (SRC == SRC_PLAIN) {
+        const double* Ad = (const double*)A.dense;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) a[q] = (T)Ad[(int64_t)q * L.nslot + v];
+      } else {
+        T ce[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int sx = c & 1, sy = (c >> 1) & 1, sz = (c >> 2) & 1;
+          ce[c] = ep[(k - sz) % 2][(ly + 1 - sy) * EW + (lx + 1 - sx)];
+        }
+        const T hs = (T)L.h;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          if (kref(3, ndiff_of<3>(q)) == 0.0) {
+            a[q] = (T)0;
+            continue;
+          }
+          T e = (T)0;
+#pragma unroll
+          for (int c = 0; c < 8; ++c)
+            if (cell_has<3>(c, q)) e += ce[c];
+          a[q] = hs * (T)kref(3, ndiff_of<3>(q)) * e;
+        }
+        if (SRC == SRC_HIER) add_delta<FMT, NS, T>(A, v, a);
+      }
+      if (MODE == 1) {
+        out[v] = (TO)(omega * b[v] / a[NS / 2]);
+      } else {
+        T au = (T)0;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          if (SRC == SRC_GEOM && kref(3, ndiff_of<3>(q)) == 0.0) continue;
+          au += a[q] * up[(k + off_z(q) + 3) % 3][(ly + 1 + off_y(q)) * UW + (lx + 1 + off_x(q))];
+        }
+        if (MODE == 0) {
+          out[v] = (TO)(up[k % 3][(ly + 1) * UW + lx + 1] + omega * (b[v] - au) / a[NS / 2]);
+        } else {
+          const T res = (MODE == 3) ? au : b[v] - au;
+          out[v] = (TO)res;
+          sq += (double)res * (double)res;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (partial != nullptr) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) sq += __shfl_xor(sq, m, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = sq;
+    __syncthreads();
+    if (tid == 0) {
+      double tot = 0.0;
+#pragma unroll
+      for (int w = 0; w < MX * MY / 64; ++w) tot += red[w];
+      partial[tl.t] = tot;
+    }
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict__ p, int n,
                                                        double* __restrict__ out,
                                                        double* __restrict__ hist, int* __restrict__ counter,
@@ -213,6 +362,15 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 template <int D, typename T, typename TO, int SRC, int FMT, int MODE>
 void launch_one(const dim3& g, const dim3& bl, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const Lat& L,
                 const T* u, const T* b, TO* out, const T* eps, const Store& A, T omega, double* partial) {
+  if (D == 3) {  // plane-marching kernel
+    const dim3 gm = march_grid(L), bm(MX * MY, 1, 1);
+    if (e0 != nullptr)
+      hipExtLaunchKernelGGL((k_march3d<T, TO, SRC, FMT, MODE>), gm, bm, 0, s, e0, e1, 0, L, u, b, out, eps, A,
+                            omega, partial);
+    else
+      hipLaunchKernelGGL((k_march3d<T, TO, SRC, FMT, MODE>), gm, bm, 0, s, L, u, b, out, eps, A, omega, partial);
+    return;
+  }
   if (e0 != nullptr)  // per-dispatch timestamps (the same the profiler reports)
     hipExtLaunchKernelGGL((k_stencil<D, T, TO, SRC, FMT, MODE>), g, bl, 0, s, e0, e1, 0, L, u, b, out, eps, A,
                           omega, partial);
@@ -274,7 +432,7 @@ void launch_stencil(const Lat& L, int mode, const T* u, const T* b, T* out, cons
                     const Store& A, T omega, double* partial, int* n_partial, hipStream_t s,
                     hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (n_partial) {
-    const dim3 g = tile_grid(L);
+    const dim3 g = L.d == 3 ? march_grid(L) : tile_grid(L);
     *n_partial = (int)(g.x * g.y * g.z);
   }
   if (L.d == 2)
@@ -291,13 +449,14 @@ template void launch_stencil<float>(const Lat&, int, const float*, const float*,
 
 void launch_residual_mixed(const Lat& L, const double* x, const double* b, float* r32,
                            const double* eps, double* partial, int* n_partial, hipStream_t s) {
-  const dim3 g = tile_grid(L), bl(TX, TY, 1);
+  const dim3 g = L.d == 3 ? march_grid(L) : tile_grid(L), bl(TX, TY, 1);
   if (n_partial) *n_partial = (int)(g.x * g.y * g.z);
   Store none;
   if (L.d == 2)
     hipLaunchKernelGGL((k_stencil<2, double, float, SRC_GEOM, F64, 2>), g, bl, 0, s, L, x, b, r32, eps, none, 0.0, partial);
   else
-    hipLaunchKernelGGL((k_stencil<3, double, float, SRC_GEOM, F64, 2>), g, bl, 0, s, L, x, b, r32, eps, none, 0.0, partial);
+    hipLaunchKernelGGL((k_march3d<double, float, SRC_GEOM, F64, 2>), g, dim3(MX * MY, 1, 1), 0, s, L, x, b, r32, eps,
+                       none, 0.0, partial);
   QMG_HIP(hipGetLastError());
 }
 

@@ -147,8 +147,13 @@ __global__ __launch_bounds__(MX * MY) void k_march3d(Lat L, const T* __restrict_
     put_e(k0 - 1, re);
     fetch_e(k0, re);
   }
+  // right-hand side of this thread's vertex on the next plane, prefetched
+  const int64_t vij = i + (int64_t)j * L.pitch;
+  T bnext = inplane ? b[vij + (int64_t)k0 * L.plane] : (T)0;
   double sq = 0.0;
   for (int k = k0; k < k1; ++k) {
+    const T bv = bnext;
+    if (inplane && k + 1 < k1) bnext = b[vij + (int64_t)(k + 1) * L.plane];
     if (MODE != 1) {
       put_u(k + 1, ru);
       if (k + 1 < k1) fetch_u(k + 2, ru);
@@ -188,7 +193,7 @@ __global__ __launch_bounds__(MX * MY) void k_march3d(Lat L, const T* __restrict_
         if (SRC == SRC_HIER) add_delta<FMT, NS, T>(A, v, a);
       }
       if (MODE == 1) {
-        out[v] = (TO)(omega * b[v] / a[NS / 2]);
+        out[v] = (TO)(omega * bv / a[NS / 2]);
       } else {
         T au = (T)0;
 #pragma unroll
@@ -197,9 +202,9 @@ __global__ __launch_bounds__(MX * MY) void k_march3d(Lat L, const T* __restrict_
           au += a[q] * up[(k + off_z(q) + 3) % 3][(ly + 1 + off_y(q)) * UW + (lx + 1 + off_x(q))];
         }
         if (MODE == 0) {
-          out[v] = (TO)(up[k % 3][(ly + 1) * UW + lx + 1] + omega * (b[v] - au) / a[NS / 2]);
+          out[v] = (TO)(up[k % 3][(ly + 1) * UW + lx + 1] + omega * (bv - au) / a[NS / 2]);
         } else {
-          const T res = (MODE == 3) ? au : b[v] - au;
+          const T res = (MODE == 3) ? au : bv - au;
           out[v] = (TO)res;
           sq += (double)res * (double)res;
         }

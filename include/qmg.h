@@ -243,14 +243,16 @@ int qmg_get_prolongation(const qmg_grid_t* grid, int level, double* weights);
 enum {
   QMG_OP_MATVEC = 0,     /* out = A x                                         */
   QMG_OP_RESIDUAL = 1,   /* out = b - A x                                     */
-  QMG_OP_JACOBI = 2,     /* out = x + omega diag(A)^-1 (b - A x)               */
+  QMG_OP_JACOBI = 2,     /* out = x + omega diag(A)^-1 (b - A x); x = NULL: the
+                            sweep from a zero iterate, out = omega diag(A)^-1 b */
   QMG_OP_RESTRICT = 3,   /* out (level-1 lattice) = P^T x (x on `level`)       */
   QMG_OP_PROLONG = 4     /* out (level lattice) = b + P x (x on level-1)       */
 };
 
 /* Applies one step of the hot path on `level` in the grid's iterate precision
  * (FP64 or FP32, converted at the boundary).  x, b, out are lattice arrays of
- * the sizes the operation implies; b is ignored where unused (may be NULL).
+ * the sizes the operation implies; b is ignored where unused (may be NULL);
+ * x may be NULL only for QMG_OP_JACOBI (EINVAL otherwise).
  * The step runs in the level's work buffers: the iterates and right-hand
  * sides of `level` (and level-1 for transfers) are overwritten, so a solve
  * after it starts with qmg_set_coefficients or qmg_set_solution. */

@@ -1260,11 +1260,13 @@ void apply_op(qmg_grid_t* g, int op, int level, const double* x, const double* b
     }
     return;
   }
-  upload_lattice<T>(g, B.L, x, (T*)B.u);
+  // a missing x (Jacobi only) is the sweep from a zero iterate
+  if (x) upload_lattice<T>(g, B.L, x, (T*)B.u);
+  else launch_zero<T>((T*)B.u, B.L.nslot, S(g));
   if (b) upload_lattice<T>(g, B.L, b, (T*)B.b);
   else launch_zero<T>((T*)B.b, B.L.nslot, S(g));
   launch_zero<T>((T*)B.t, B.L.nslot, S(g));
-  const int mode = op == QMG_OP_MATVEC ? 3 : op == QMG_OP_RESIDUAL ? 2 : 0;
+  const int mode = op == QMG_OP_MATVEC ? 3 : op == QMG_OP_RESIDUAL ? 2 : x ? 0 : 1;
   launch_stencil<T>(B.L, mode, (const T*)B.u, (const T*)B.b, (T*)B.t, eps_of<T>(B), B.A, om, nullptr,
                     nullptr, S(g));
   download_lattice<T>(g, B.L, (const T*)B.t, out);
@@ -1760,7 +1762,7 @@ int qmg_get_prolongation(const qmg_grid_t* cg, int level, double* weights) {
 
 int qmg_apply(qmg_grid_t* g, int op, int level, const double* x, const double* b, double* out) {
   return guard(g, [&] {
-    if (!g || !x || !out) throw ApiError(QMG_EINVAL, "null argument");
+    if (!g || !out || (!x && op != QMG_OP_JACOBI)) throw ApiError(QMG_EINVAL, "null argument");
     if (op < QMG_OP_MATVEC || op > QMG_OP_PROLONG) throw ApiError(QMG_EINVAL, "bad op");
     if (!g->have_coef) throw ApiError(QMG_ESTATE, "coefficients not set");
     if (level < g->Lmax && !g->have_ops) throw ApiError(QMG_ESTATE, "operators not built");

@@ -85,6 +85,13 @@ constexpr int EW = MX + 1, EH = MY + 1;  // cell plane region: x0-1..x0+63, y0-1
 inline dim3 march_grid(const Lat& L) {
   return dim3((unsigned)(L.pitch / MX), (unsigned)((L.n + 1 + MY - 1) / MY), (unsigned)((L.n - 1 + MZ - 1) / MZ));
 }
+// Smaller 3D levels keep one workgroup per 64 x 4 x 1 tile: a march over few
+// workgroups would serialise its planes.
+inline bool use_march(const Lat& L) {
+  if (L.d != 3) return false;
+  const dim3 g = march_grid(L);
+  return (int64_t)g.x * g.y * g.z >= 1024;
+}
 
 template <typename T, typename TO, int SRC, int FMT, int MODE>
 __global__ __launch_bounds__(MX * MY) void k_march3d(Lat L, const T* __restrict__ u, const T* __restrict__ b,
@@ -367,7 +374,7 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 template <int D, typename T, typename TO, int SRC, int FMT, int MODE>
 void launch_one(const dim3& g, const dim3& bl, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const Lat& L,
                 const T* u, const T* b, TO* out, const T* eps, const Store& A, T omega, double* partial) {
-  if (D == 3) {  // plane-marching kernel
+  if (D == 3 && use_march(L)) {  // plane-marching kernel
     const dim3 gm = march_grid(L), bm(MX * MY, 1, 1);
     if (e0 != nullptr)
       hipExtLaunchKernelGGL((k_march3d<T, TO, SRC, FMT, MODE>), gm, bm, 0, s, e0, e1, 0, L, u, b, out, eps, A,
@@ -437,7 +444,7 @@ void launch_stencil(const Lat& L, int mode, const T* u, const T* b, T* out, cons
                     const Store& A, T omega, double* partial, int* n_partial, hipStream_t s,
                     hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (n_partial) {
-    const dim3 g = L.d == 3 ? march_grid(L) : tile_grid(L);
+    const dim3 g = use_march(L) ? march_grid(L) : tile_grid(L);
     *n_partial = (int)(g.x * g.y * g.z);
   }
   if (L.d == 2)
@@ -454,14 +461,16 @@ template void launch_stencil<float>(const Lat&, int, const float*, const float*,
 
 void launch_residual_mixed(const Lat& L, const double* x, const double* b, float* r32,
                            const double* eps, double* partial, int* n_partial, hipStream_t s) {
-  const dim3 g = L.d == 3 ? march_grid(L) : tile_grid(L), bl(TX, TY, 1);
+  const dim3 g = use_march(L) ? march_grid(L) : tile_grid(L), bl(TX, TY, 1);
   if (n_partial) *n_partial = (int)(g.x * g.y * g.z);
   Store none;
   if (L.d == 2)
     hipLaunchKernelGGL((k_stencil<2, double, float, SRC_GEOM, F64, 2>), g, bl, 0, s, L, x, b, r32, eps, none, 0.0, partial);
-  else
+  else if (use_march(L))
     hipLaunchKernelGGL((k_march3d<double, float, SRC_GEOM, F64, 2>), g, dim3(MX * MY, 1, 1), 0, s, L, x, b, r32, eps,
                        none, 0.0, partial);
+  else
+    hipLaunchKernelGGL((k_stencil<3, double, float, SRC_GEOM, F64, 2>), g, bl, 0, s, L, x, b, r32, eps, none, 0.0, partial);
   QMG_HIP(hipGetLastError());
 }
 

@@ -280,15 +280,20 @@ class Grid:
         self._check(self.lib.qmg_get_prolongation(self.h, int(level), _ptr(out)), self.h)
         return out
 
-    def apply(self, op: int, level: int, x: np.ndarray, b: Optional[np.ndarray] = None) -> np.ndarray:
-        x = np.ascontiguousarray(x, dtype=np.float64)
+    def apply(self, op: int, level: int, x: Optional[np.ndarray], b: Optional[np.ndarray] = None) -> np.ndarray:
+        """One step on ``level``; ``x=None`` with OP_JACOBI is the sweep from
+        a zero iterate."""
+        xp = None
+        if x is not None:
+            x = np.ascontiguousarray(x, dtype=np.float64)
+            xp = _ptr(x)
         out_level = level - 1 if op == OP_RESTRICT else level
         out = np.zeros(self._lat_shape(out_level))
         bp = None
         if b is not None:
             b = np.ascontiguousarray(b, dtype=np.float64)
             bp = _ptr(b)
-        self._check(self.lib.qmg_apply(self.h, int(op), int(level), _ptr(x), bp, _ptr(out)), self.h)
+        self._check(self.lib.qmg_apply(self.h, int(op), int(level), xp, bp, _ptr(out)), self.h)
         return out
 
     def close(self):

@@ -454,3 +454,39 @@ def test_raise_with_fp32_iterates(store):
     H = O.build_hierarchy(p.eps, 2, 4, transfer="boxmg", check_definite=False)
     b = O.rhs_from_f(p.f, 2, 4)
     assert np.linalg.norm(b - H.A[4] @ u) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)
+
+
+def test_3d_level5_single_steps_full_size():
+    """The 3D levels large enough for the plane-marching kernel (level 5 and
+    up: 64 x 8 tiles marching over 16-plane chunks): matrix-vector product,
+    residual, Jacobi sweep and the sweep from a zero iterate on a 3D level-5
+    grid (242^3 unknowns; the tiles are ragged on every axis), on the whole
+    lattice against the oracle's rediscretised operator."""
+    from oracle import adaptive as AD
+    qmg = require_gpu()
+    announce("3D level 5 single steps (marching kernel)")
+    d, L = 3, 5
+    p = W.random_checkerboard(d, L, seed=7, values=(1.0, 1e3))
+    g = _grid(qmg, p, "geometric", "hier64")
+    rng = np.random.default_rng(8)
+    x = lattice_of_unknowns(rng.normal(size=p.n_unknowns), d, L)
+    b = lattice_of_unknowns(rng.normal(size=p.n_unknowns), d, L)
+    S = O.geometric_stencil(p.eps, d, L)
+    Ax = AD._apply(S, x, d)
+    del S
+    inner = (slice(1, 3 ** L),) * d
+    D = O.geometric_stencil(p.eps, d, L)[(3 ** d) // 2]
+
+    def close(got, want):
+        tol = RTOL64 * np.abs(want[inner]).max()
+        assert np.abs(got[inner] - want[inner]).max() <= tol
+
+    close(g.apply(qmg.OP_MATVEC, L, x), Ax)
+    close(g.apply(qmg.OP_RESIDUAL, L, x, b), b - Ax)
+    jac = np.zeros_like(x)
+    jac[inner] = x[inner] + 0.6 * (b[inner] - Ax[inner]) / D[inner]
+    close(g.apply(qmg.OP_JACOBI, L, x, b), jac)
+    zero = np.zeros_like(x)
+    zero[inner] = 0.6 * b[inner] / D[inner]
+    close(g.apply(qmg.OP_JACOBI, L, None, b), zero)
+    g.close()

@@ -259,11 +259,13 @@ enum {
 int qmg_apply(qmg_grid_t* grid, int op, int level, const double* x, const double* b, double* out);
 
 /* ---------------- serving ------------------------------------------------
- * A persistent request loop (one scheduler thread per server) that keeps the
- * grids and operators of admitted requests on the device and overlaps their
- * work.  Requests are admitted in arrival order -- a later request that fits
- * may pass a head that does not -- while one of `max_slots` slots is free and
- * the request's qmg_workspace_bytes() fit in the unused part of `hbm_budget`.
+ * A persistent request loop (up to four worker threads per server, each
+ * driving its share of the slots) that keeps the grids and operators of
+ * admitted requests on the device and overlaps their work.  Requests are
+ * admitted in arrival order -- a later request that fits may pass a head that
+ * does not -- while one of `max_slots` slots is free and the request's
+ * qmg_workspace_bytes() fit in the unused part of `hbm_budget` (and in one
+ * free range of it).
  * Each admitted request runs the single-grid path (create, set_coefficients,
  * build_operators, solve) on a stream of its own; its result does not depend
  * on the other requests.  Not in the paper: it batches independent solves the
@@ -274,7 +276,10 @@ typedef struct {
   int max_slots;
 } qmg_server_stats_t;
 
-/* Starts a server on the current HIP device (1 <= max_slots <= 256). */
+/* Starts a server on the current HIP device (1 <= max_slots <= 256).  The
+ * whole `hbm_budget` is reserved on the device here (QMG_ENOMEM if it cannot
+ * be) and request workspaces are carved from it, so serving itself allocates
+ * no device memory; the reservation is freed by qmg_server_destroy. */
 int qmg_server_create(size_t hbm_budget, int max_slots, qmg_server_t** out);
 
 /* Queues a solve on a regular grid (eps: n^d cell values, f: (n-1)^d

@@ -20,7 +20,6 @@ namespace {
 
 thread_local std::string g_thread_err;
 
-constexpr int kHistCap = 1024;  // cycles per batch between host synchronisations
 
 int ipow(int b, int e) {
   int r = 1;
@@ -136,6 +135,7 @@ struct qmg_grid {
   char* base = nullptr;
   size_t bytes = 0;
   bool owns = false;
+  bool own_hnorm = true;  // pinned history buffer allocated by the grid
   hipStream_t stream = nullptr;
   bool have_coef = false, have_ops = false;
   double bnorm = 0.0;
@@ -1348,6 +1348,68 @@ void solve_fill_report(qmg_grid_t* g, const SolveState& st, qmg_solve_report* re
 
 }  // namespace qmg
 
+namespace qmg {
+
+int create_grid(const qmg_grid_desc* desc, const qmg_solver_opts* opts, void* device_buf, size_t bytes,
+                void* stream, double* pinned_hist, qmg_grid_t** out) {
+  return guard(nullptr, [&] {
+    validate(desc, opts);
+    if (!out) throw ApiError(QMG_EINVAL, "null output handle");
+    *out = nullptr;
+    qmg_grid_t* g = new qmg_grid_t();
+    try {
+      init_modes(g, desc, opts);
+      g->stream = (hipStream_t)stream;
+      if (g->stream == nullptr) {  // graph capture needs a stream other than the null stream
+        QMG_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+        g->own_stream = true;
+      }
+      Arena probe;
+      layout(g, probe);
+      const size_t need = probe.off + 256;
+      if (device_buf) {
+        if (bytes < need)
+          throw ApiError(QMG_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+        g->base = (char*)device_buf;
+        g->bytes = bytes;
+      } else {
+        void* p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess) {
+          (void)hipGetLastError();
+          throw ApiError(QMG_ENOMEM, "device allocation of " + std::to_string(need) + " bytes failed");
+        }
+        g->base = (char*)p;
+        g->bytes = need;
+        g->owns = true;
+      }
+      Arena a;
+      a.base = (char*)(((uintptr_t)g->base + 255) & ~(uintptr_t)255);
+      layout(g, a);
+      QMG_HIP(hipMemsetAsync(g->base, 0, need, g->stream));
+      if (pinned_hist) {
+        g->hnorm = pinned_hist;
+        g->own_hnorm = false;
+      } else {
+        QMG_HIP(hipHostMalloc((void**)&g->hnorm, kHistCap * sizeof(double), hipHostMallocDefault));
+      }
+      QMG_HIP(hipEventCreateWithFlags(&g->bev, hipEventDisableTiming));
+      QMG_HIP(hipStreamSynchronize(g->stream));
+      g->n_unknowns = n_interior(g->lv[g->Lmax].L);
+      upload_linearisation(g);
+    } catch (...) {
+      if (g->owns && g->base) (void)hipFree(g->base);
+      if (g->hnorm && g->own_hnorm) (void)hipHostFree(g->hnorm);
+      if (g->bev) (void)hipEventDestroy(g->bev);
+      if (g->own_stream) (void)hipStreamDestroy(g->stream);
+      delete g;
+      throw;
+    }
+    *out = g;
+  });
+}
+
+}  // namespace qmg
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1384,55 +1446,7 @@ int qmg_workspace_bytes(const qmg_grid_desc* desc, const qmg_solver_opts* opts, 
 
 int qmg_create_grid(const qmg_grid_desc* desc, const qmg_solver_opts* opts, void* device_buf,
                     size_t bytes, void* stream, qmg_grid_t** out) {
-  return guard(nullptr, [&] {
-    validate(desc, opts);
-    if (!out) throw ApiError(QMG_EINVAL, "null output handle");
-    *out = nullptr;
-    qmg_grid_t* g = new qmg_grid_t();
-    try {
-      init_modes(g, desc, opts);
-      g->stream = (hipStream_t)stream;
-      if (g->stream == nullptr) {  // graph capture needs a stream other than the null stream
-        QMG_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
-        g->own_stream = true;
-      }
-      Arena probe;
-      layout(g, probe);
-      const size_t need = probe.off + 256;
-      if (device_buf) {
-        if (bytes < need)
-          throw ApiError(QMG_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
-        g->base = (char*)device_buf;
-        g->bytes = bytes;
-      } else {
-        void* p = nullptr;
-        if (hipMalloc(&p, need) != hipSuccess) {
-          (void)hipGetLastError();
-          throw ApiError(QMG_ENOMEM, "device allocation of " + std::to_string(need) + " bytes failed");
-        }
-        g->base = (char*)p;
-        g->bytes = need;
-        g->owns = true;
-      }
-      Arena a;
-      a.base = (char*)(((uintptr_t)g->base + 255) & ~(uintptr_t)255);
-      layout(g, a);
-      QMG_HIP(hipMemsetAsync(g->base, 0, need, g->stream));
-      QMG_HIP(hipHostMalloc((void**)&g->hnorm, kHistCap * sizeof(double), hipHostMallocDefault));
-      QMG_HIP(hipEventCreateWithFlags(&g->bev, hipEventDisableTiming));
-      QMG_HIP(hipStreamSynchronize(g->stream));
-      g->n_unknowns = n_interior(g->lv[g->Lmax].L);
-      upload_linearisation(g);
-    } catch (...) {
-      if (g->owns && g->base) (void)hipFree(g->base);
-      if (g->hnorm) (void)hipHostFree(g->hnorm);
-      if (g->bev) (void)hipEventDestroy(g->bev);
-      if (g->own_stream) (void)hipStreamDestroy(g->stream);
-      delete g;
-      throw;
-    }
-    *out = g;
-  });
+  return qmg::create_grid(desc, opts, device_buf, bytes, stream, nullptr, out);
 }
 
 int qmg_sizes(const qmg_grid_t* g, int64_t* n_unknowns, int64_t* n_leaf_cells, int* n_levels) {
@@ -1690,7 +1704,7 @@ int qmg_destroy_grid(qmg_grid_t* g) {
   drop_graph(g);
   for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
   if (g->owns && g->base && hipFree(g->base) != hipSuccess) rc = QMG_EHIP;
-  if (g->hnorm) (void)hipHostFree(g->hnorm);
+  if (g->hnorm && g->own_hnorm) (void)hipHostFree(g->hnorm);
   if (g->bev) (void)hipEventDestroy(g->bev);
   if (g->own_stream) (void)hipStreamDestroy(g->stream);
   delete g;

@@ -291,6 +291,13 @@ template <typename T>
 void launch_ad_gather(const int64_t* slots, int64_t n, const T* lat, double* out, hipStream_t s);
 
 // ---- solve loop as a state machine (api.cpp); used by the server ----
+constexpr int kHistCap = 1024;  // cycles per batch between host synchronisations
+
+// qmg_create_grid with an optional caller-owned pinned host buffer of kHistCap
+// doubles for the residual history (the server reuses one per slot).
+int create_grid(const qmg_grid_desc* desc, const qmg_solver_opts* opts, void* device_buf, size_t bytes,
+                void* stream, double* pinned_hist, qmg_grid_t** out);
+
 struct SolveState {
   double tol = 1e-8;
   int max_cycles = 0;

@@ -1,21 +1,26 @@
 // Serving: a persistent request loop that keeps the grids and operators of the
 // admitted requests on the device and overlaps their work.
 //
-// Requests queue on submission.  A scheduler thread admits them in arrival
-// order, skipping ahead to later requests that fit when the head does not, as
-// long as a slot is free and the request's workspace fits in the free part of
-// the HBM budget.  An admitted request gets its own stream: its grid is
-// created, its operators built and its cycles enqueued in batches (replayed HIP
-// graphs) without blocking the loop; the loop polls each active request's
-// batch event, sets up the next batch or retires the request (solution copied
-// out, memory returned to the budget) and admits waiting requests as slots and
-// memory free up.  Each request's arithmetic is exactly the single-grid path,
-// so a result does not depend on what else is in the mix.
+// Requests queue on submission.  Worker threads (each owning a share of the
+// slots, each slot with its own stream and pinned history buffer) admit them
+// in arrival order, skipping ahead to later requests that fit when the head
+// does not, as long as one of the worker's slots is free and the request's
+// workspace fits in the free part of the HBM budget.  The budget is reserved
+// on the device once, when the server starts, and workspaces are carved from
+// it, so admission and retirement allocate and free nothing on the device.
+// An admitted request's grid is created, its operators built and its cycles
+// enqueued in batches (replayed HIP graphs) without blocking the worker; the
+// worker polls each of its active requests' batch event, sets up the next
+// batch or retires the request (solution copied out, memory returned to the
+// budget) and admits waiting requests as slots and memory free up.  Each
+// request's arithmetic is exactly the single-grid path, so a result does not
+// depend on what else is in the mix.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -34,6 +39,8 @@ double now_s() {
 
 thread_local std::string g_server_err;
 
+constexpr int kServerWorkers = 8;  // host threads driving the slots
+
 struct Req {
   uint64_t id = 0;
   qmg_grid_desc desc{};
@@ -48,6 +55,7 @@ struct Req {
   std::string err;
   qmg_grid_t* g = nullptr;
   int slot = -1;
+  size_t off = 0;  // workspace offset in the server's arena
   SolveState st;
   std::vector<double> u;
   qmg_solve_report rep{};
@@ -59,8 +67,12 @@ struct qmg_server {
   size_t budget = 0, in_use = 0, peak = 0;
   int max_slots = 0;
   int device = 0;
+  int nworkers = 1;
   std::vector<hipStream_t> streams;
-  std::vector<int> slot_free;
+  std::vector<double*> hist;                // pinned residual history per slot
+  std::vector<std::vector<int>> slot_free;  // per worker; slot s belongs to worker s % nworkers
+  char* arena = nullptr;                    // the budget, reserved on the device
+  std::map<size_t, size_t> holes;           // free arena ranges: offset -> size
   std::mutex mu;
   std::condition_variable cv_done, cv_work;
   std::deque<Req*> queue;
@@ -69,11 +81,49 @@ struct qmg_server {
   uint64_t next_id = 1;
   int64_t submitted = 0, completed = 0, failed = 0;
   bool stop = false;
-  std::thread worker;
+  std::vector<std::thread> workers;
   std::string err;
 };
 
 namespace {
+
+constexpr size_t kArenaAlign = 256;
+
+size_t arena_size(size_t bytes) { return (bytes + kArenaAlign - 1) & ~(kArenaAlign - 1); }
+
+// First fit in the arena (caller holds the lock); false when no hole is large
+// enough (fragmentation: the request waits like one over the budget).
+bool arena_take(qmg_server* s, size_t bytes, size_t* off) {
+  const size_t need = arena_size(bytes);
+  for (auto it = s->holes.begin(); it != s->holes.end(); ++it) {
+    if (it->second < need) continue;
+    *off = it->first;
+    const size_t rest = it->second - need;
+    const size_t at = it->first + need;
+    s->holes.erase(it);
+    if (rest > 0) s->holes[at] = rest;
+    return true;
+  }
+  return false;
+}
+
+// Returns a range to the arena, merging it with its free neighbours.
+void arena_give(qmg_server* s, size_t off, size_t bytes) {
+  size_t size = arena_size(bytes);
+  auto next = s->holes.lower_bound(off);
+  if (next != s->holes.end() && off + size == next->first) {
+    size += next->second;
+    next = s->holes.erase(next);
+  }
+  if (next != s->holes.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      prev->second += size;
+      return;
+    }
+  }
+  s->holes[off] = size;
+}
 
 void fail(Req* r, int code, const std::string& msg) {
   if (r->status == QMG_OK) {
@@ -93,7 +143,8 @@ void release_grid(Req* r) {
 // first batch; any error retires the request with that status.
 void start(qmg_server* s, Req* r) {
   const int rc = [&]() -> int {
-    int c = qmg_create_grid(&r->desc, &r->opts, nullptr, 0, s->streams[r->slot], &r->g);
+    int c = create_grid(&r->desc, &r->opts, s->arena + r->off, r->bytes, s->streams[r->slot], s->hist[r->slot],
+                        &r->g);
     if (c != QMG_OK) return c;
     c = qmg_set_coefficients(r->g, r->eps.data(), 1, r->f.data(), QMG_HOST);
     if (c != QMG_OK) return c;
@@ -134,7 +185,8 @@ void finish(qmg_server* s, Req* r) {
   r->t_done = now_s();
   r->state = 2;
   s->in_use -= r->bytes;
-  s->slot_free.push_back(r->slot);
+  arena_give(s, r->off, r->bytes);
+  s->slot_free[r->slot % s->nworkers].push_back(r->slot);
   s->active.erase(std::remove(s->active.begin(), s->active.end(), r), s->active.end());
   ++s->completed;
   if (r->status != QMG_OK) ++s->failed;
@@ -142,18 +194,22 @@ void finish(qmg_server* s, Req* r) {
   s->cv_work.notify_all();
 }
 
-void loop(qmg_server* s) {
+// Worker w drives the slots s with s % nworkers == w.
+void loop(qmg_server* s, int w) {
   (void)hipSetDevice(s->device);
+  std::vector<int>& mine = s->slot_free[w];
   for (;;) {
     std::vector<Req*> admitted, running;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       if (s->stop && s->queue.empty() && s->active.empty()) break;
-      for (auto it = s->queue.begin(); it != s->queue.end() && !s->slot_free.empty();) {
+      for (auto it = s->queue.begin(); it != s->queue.end() && !mine.empty();) {
         Req* r = *it;
-        if (s->in_use + r->bytes <= s->budget) {
-          r->slot = s->slot_free.back();
-          s->slot_free.pop_back();
+        size_t off = 0;
+        if (s->in_use + r->bytes <= s->budget && arena_take(s, r->bytes, &off)) {
+          r->off = off;
+          r->slot = mine.back();
+          mine.pop_back();
           s->in_use += r->bytes;
           s->peak = std::max(s->peak, s->in_use);
           r->state = 1;
@@ -165,7 +221,8 @@ void loop(qmg_server* s) {
           ++it;
         }
       }
-      running = s->active;
+      for (Req* r : s->active)
+        if (r->slot % s->nworkers == w) running.push_back(r);
     }
     bool progress = !admitted.empty();
     for (Req* r : admitted) {
@@ -223,17 +280,34 @@ int qmg_server_create(size_t hbm_budget, int max_slots, qmg_server_t** out) {
     qmg_server* s = new qmg_server();
     s->budget = hbm_budget;
     s->max_slots = max_slots;
+    s->nworkers = std::min(max_slots, kServerWorkers);
+    auto release = [s] {
+      for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+      for (double* h : s->hist) (void)hipHostFree(h);
+      if (s->arena) (void)hipFree(s->arena);
+    };
     try {
       QMG_HIP(hipGetDevice(&s->device));
+      void* p = nullptr;
+      if (hipMalloc(&p, hbm_budget) != hipSuccess) {
+        (void)hipGetLastError();
+        throw ApiError(QMG_ENOMEM, "cannot reserve the HBM budget of " + std::to_string(hbm_budget) + " bytes");
+      }
+      s->arena = (char*)p;
+      s->holes[0] = hbm_budget & ~(kArenaAlign - 1);
+      s->slot_free.resize(s->nworkers);
       for (int i = 0; i < max_slots; ++i) {
         hipStream_t st = nullptr;
         QMG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
         s->streams.push_back(st);
-        s->slot_free.push_back(max_slots - 1 - i);
+        double* h = nullptr;
+        QMG_HIP(hipHostMalloc((void**)&h, kHistCap * sizeof(double), hipHostMallocDefault));
+        s->hist.push_back(h);
       }
-      s->worker = std::thread(loop, s);
+      for (int i = max_slots - 1; i >= 0; --i) s->slot_free[i % s->nworkers].push_back(i);
+      for (int w = 0; w < s->nworkers; ++w) s->workers.emplace_back(loop, s, w);
     } catch (...) {
-      for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+      release();
       delete s;
       throw;
     }
@@ -349,12 +423,15 @@ int qmg_server_destroy(qmg_server_t* s) {
     s->queue.clear();
     s->cv_work.notify_all();
   }
-  if (s->worker.joinable()) s->worker.join();
+  for (std::thread& t : s->workers)
+    if (t.joinable()) t.join();
   for (auto& kv : s->all) {
     release_grid(kv.second);
     delete kv.second;
   }
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  for (double* h : s->hist) (void)hipHostFree(h);
+  if (s->arena) (void)hipFree(s->arena);
   delete s;
   return QMG_OK;
 }

@@ -213,10 +213,11 @@ int qmg_set_solution(qmg_grid_t* grid, const double* u, int mem);
 
 /* Measurement: with on = k > 0, every k-th smoothing launch on the finest
  * level (2D: the pre-smoothing pass of two sweeps and the residual; 3D: each
- * sweep) carries per-dispatch HIP event timestamps on the grid's stream
- * (cycles then run as eager launches); on = 0 turns it off.  profile_read returns the
- * number of timed launches and their summed device time in milliseconds since
- * the last read, then resets. */
+ * full Jacobi sweep, not the sweep from a zero iterate) carries per-dispatch
+ * HIP event timestamps on the grid's stream (cycles then run as eager
+ * launches); on = 0 turns it off.  profile_read returns the number of timed
+ * launches and their summed device time in milliseconds since the last read,
+ * then resets. */
 int qmg_profile_enable(qmg_grid_t* grid, int on);
 int qmg_profile_read(qmg_grid_t* grid, int64_t* launches, double* total_ms);
 

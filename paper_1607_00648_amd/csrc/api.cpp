@@ -502,7 +502,9 @@ void smooth(qmg_grid_t* g, LevelBuf& B, int sweeps, bool zero_init) {
   const bool finest = g->prof_every > 0 && B.L.n == g->lv[g->Lmax].L.n;
   for (int k = 0; k < sweeps; ++k) {
     const int mode = (k == 0 && zero_init) ? 1 : 0;
-    const bool timed = finest && (g->prof_count++ % g->prof_every) == 0;
+    // timed: every k-th full Jacobi sweep of the finest level (not the sweep
+    // from a zero iterate, which reads no iterate)
+    const bool timed = finest && mode == 0 && (g->prof_count++ % g->prof_every) == 0;
     hipEvent_t* ev = timed ? prof_pair(g) : nullptr;
     launch_stencil<T>(B.L, mode, (const T*)B.u, (const T*)B.b, (T*)B.t, eps_of<T>(B), B.A, om,
                       nullptr, nullptr, S(g), ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);

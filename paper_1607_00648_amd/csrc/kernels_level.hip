@@ -2,7 +2,8 @@
 // partials), matvec, restriction, prolongation, coarsest solve and helpers.
 //
 // Layout: one thread per lattice slot of a 64 x 4 (x, y) tile; blockIdx.z is
-// the z-plane in 3D.  Every wavefront covers 64 consecutive slots of one x-row,
+// the z-plane in 3D.  Large 3D levels use the plane-marching variant
+// (k_march3d) for the stencil operations.  Every wavefront covers 64 consecutive slots of one x-row,
 // which is also the granule of the delta store, so store lookups are uniform
 // per wavefront.  Stencil rows are rebuilt per vertex from the 2^d cell
 // coefficients (rediscretisation on the fly) plus the stored delta, or read
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(256) void k_stencil(Lat L, const T* __restrict__ u,
 // through LDS, so each value comes from memory once per chunk instead of once
 // per neighbour; every thread updates one vertex per plane with the same
 // expressions, in the same order, as k_stencil.
-constexpr int MX = 64, MY = 8, MZ = 16;
+constexpr int MX = 64, MY = 8, MZ = 32;
 constexpr int UW = MX + 2, UH = MY + 2;  // iterate plane region: x0-1..x0+64, y0-1..y0+8
 constexpr int EW = MX + 1, EH = MY + 1;  // cell plane region: x0-1..x0+63, y0-1..y0+7
 
@@ -90,7 +91,7 @@ inline dim3 march_grid(const Lat& L) {
 inline bool use_march(const Lat& L) {
   if (L.d != 3) return false;
   const dim3 g = march_grid(L);
-  return (int64_t)g.x * g.y * g.z >= 1024;
+  return (int64_t)g.x * g.y * g.z >= 512;
 }
 
 template <typename T, typename TO, int SRC, int FMT, int MODE>

@@ -458,7 +458,7 @@ def test_raise_with_fp32_iterates(store):
 
 def test_3d_level5_single_steps_full_size():
     """The 3D levels large enough for the plane-marching kernel (level 5 and
-    up: 64 x 8 tiles marching over 16-plane chunks): matrix-vector product,
+    up: 64 x 8 tiles marching over 32-plane chunks): matrix-vector product,
     residual, Jacobi sweep and the sweep from a zero iterate on a 3D level-5
     grid (242^3 unknowns; the tiles are ragged on every axis), on the whole
     lattice against the oracle's rediscretised operator."""

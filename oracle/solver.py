@@ -9,6 +9,9 @@
   Jacobi sweeps on the coarsest level.
 * Sect. 3.3 (dynamic coarsest level): between two cycles the coarsest level
   moves one level up when the residual stagnates or grows (``raise_coarsest``).
+* Sect. "Spacetree block smoothers": block Jacobi BJ(m) runs m Gauss-Seidel
+  sweeps on the (k-1)^d iota-vertices of every 3^d patch and Jacobi on the
+  c- and gamma-vertices (``block_jacobi``).
 
 Readings:
 
@@ -28,6 +31,17 @@ Readings:
   coarsest level is solved exactly with its own operator when it has at most
   COARSE_DIRECT_MAX unknowns, otherwise by mu_pre + mu_post sweeps, and the
   raise lasts for the rest of the hierarchy's life.
+* Block Jacobi readings: a patch is the 3^d block of vertices of one cell of
+  the next coarser level; its iota-vertices are those with no coordinate
+  divisible by 3.  One BJ(m) step first runs m lexicographic (x fastest)
+  Gauss-Seidel sweeps, undamped, over each patch's iota-vertices, with every
+  other value held, and then the damped Jacobi update on the c- and
+  gamma-vertices from the iterate that already holds the new iota values; the
+  iota-vertices keep their Gauss-Seidel values.  Patches do not share
+  iota-vertices and no iota-vertex is a stencil neighbour of another patch's,
+  so their order does not matter.  The smoother serves every smoothing step
+  of the cycle (the paper's traversal could not use it while coarsening; an
+  explicit cycle has no such limit), the coarsest level's sweeps included.
 * Mixed precision (not in the paper): an FP64 defect-correction loop
   x += V32(fp32(b - A x)) whose inner V-cycles run in FP32 on operators rebuilt
   from quantised hierarchical deltas (see ``store``); the coarsest solve of the
@@ -69,13 +83,15 @@ class Hierarchy:
     mu_post: int = 2
     coarse_lu: Optional[tuple] = None
     dtype: type = np.float64
+    smoother: str = "jacobi"       # "jacobi" or "block" (block Jacobi)
+    bj_sweeps: int = 1             # Gauss-Seidel sweeps per patch in block Jacobi
 
     def diag(self, l):
         return self.A[l].diagonal()
 
 
 def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_post=2,
-                    check_definite=True, perturb=None):
+                    check_definite=True, perturb=None, smoother="jacobi", bj_sweeps=1):
     """Operators of all levels from the finest coefficients (Sect. 3.3, 3.4).
 
     ``perturb`` (tests only) is applied to every Galerkin product before it is
@@ -107,7 +123,8 @@ def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_p
         A[l - 1] = Ac
     if lc_used >= L:
         raise IndefiniteError("coarsest level would reach the finest level")
-    H = Hierarchy(d, L, lc_used, transfer, A, P, eps_l, omega, mu_pre, mu_post)
+    H = Hierarchy(d, L, lc_used, transfer, A, P, eps_l, omega, mu_pre, mu_post,
+                  smoother=smoother, bj_sweeps=bj_sweeps)
     n_c = A[lc_used].shape[0]
     if n_c <= COARSE_DIRECT_MAX:
         H.coarse_lu = sla.lu_factor(A[lc_used].toarray())
@@ -122,27 +139,68 @@ def residual(A, u, b):
     return b - A @ u
 
 
+def iota_positions(d, l):
+    """Unknown indices of the iota-vertices of level l grouped by their
+    position in the patch: entry p (lexicographic, x fastest over {1,2}^d)
+    lists that vertex of every patch, patches in unknown order."""
+    n = 3 ** l
+    m = n - 1
+    out = []
+    for p in range(2 ** d):
+        loc = [1 + ((p >> a) & 1) for a in range(d)]        # offsets inside the patch, x first
+        axes = [np.arange(loc[a], n, 3) for a in range(d)]  # coordinates 3c + loc
+        grids = np.meshgrid(*axes[::-1], indexing="ij")     # numpy order (z,) y, x
+        idx = np.zeros(grids[0].shape, dtype=np.int64)
+        for a in range(d):                                  # unknown index: (i-1) + m (j-1) + m^2 (k-1)
+            idx += (grids[d - 1 - a] - 1) * m ** a
+        out.append(idx.ravel())
+    return out
+
+
+def block_jacobi(A, D, u, b, omega, sweeps, d, l):
+    """One block Jacobi step (see module notes): Gauss-Seidel on the
+    iota-vertices of every patch, then damped Jacobi on the others."""
+    u = np.array(u, copy=True)
+    pos = iota_positions(d, l)
+    for _ in range(sweeps):
+        for idx in pos:          # the same patch position of every patch at once
+            u[idx] = u[idx] + (b[idx] - A[idx] @ u) / D[idx]
+    iota = np.zeros(len(u), dtype=bool)
+    for idx in pos:
+        iota[idx] = True
+    out = u + omega * (b - A @ u) / D
+    out[iota] = u[iota]
+    return out
+
+
+def smooth(H, l, A, D, u, b):
+    """One smoothing step of the hierarchy's smoother on level l."""
+    om = H.dtype(H.omega)
+    if H.smoother == "block":
+        return block_jacobi(A, D, u, b, om, H.bj_sweeps, H.d, l).astype(H.dtype)
+    return jacobi(A, D, u, b, om)
+
+
 def vcycle(H, l, u, b):
     """One V(mu_pre, mu_post) cycle on level l (correction scheme)."""
     A = H.A[l]
     dt = H.dtype
     D = A.diagonal()
-    om = dt(H.omega)
     if l == H.lc:
         if H.coarse_lu is not None:
             return sla.lu_solve(H.coarse_lu, b.astype(np.float64)).astype(dt)
         for _ in range(H.mu_pre + H.mu_post):
-            u = jacobi(A, D, u, b, om)
+            u = smooth(H, l, A, D, u, b)
         return u
     for _ in range(H.mu_pre):
-        u = jacobi(A, D, u, b, om)
+        u = smooth(H, l, A, D, u, b)
     r = b - A @ u
     P = H.P[l]
     bc = (P.T @ r).astype(dt)
     ec = vcycle(H, l - 1, np.zeros(P.shape[1], dtype=dt), bc)
     u = u + P @ ec
     for _ in range(H.mu_post):
-        u = jacobi(A, D, u, b, om)
+        u = smooth(H, l, A, D, u, b)
     return u
 
 
@@ -236,7 +294,7 @@ def quantised_hierarchy(H, fmt):
         q = sp.csr_matrix((vals, dP.indices, dP.indptr), shape=dP.shape)
         P32[l] = (Pd + q).astype(np.float32).tocsr()
     Hq = Hierarchy(d, H.L, H.lc, H.transfer, A32, P32, H.eps, H.omega, H.mu_pre, H.mu_post,
-                   H.coarse_lu, np.float32)
+                   H.coarse_lu, np.float32, H.smoother, H.bj_sweeps)
     return Hq
 
 

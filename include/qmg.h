@@ -130,6 +130,16 @@ typedef struct {
                           sweeps; the raise lasts until the next
                           build_operators.  Cycles then run one per host
                           check.  0 (default): off                         */
+  int smoother;        /* QMG_SMOOTH_JACOBI (default) or QMG_SMOOTH_BLOCK:
+                          block Jacobi (Sect. "Spacetree block smoothers"):
+                          each smoothing step first runs `bj_sweeps`
+                          lexicographic Gauss-Seidel sweeps over the 2^d
+                          iota-vertices (no coordinate divisible by 3) of
+                          every patch (the 3^d vertices of one cell of the
+                          next coarser level), then damped Jacobi on the
+                          other vertices from the updated iterate; on every
+                          smoothing step of the cycle.  Regular grids only   */
+  int bj_sweeps;       /* Gauss-Seidel sweeps per patch, 1..64 (block only)  */
 } qmg_solver_opts;
 
 typedef struct {
@@ -241,13 +251,16 @@ int qmg_get_operator(const qmg_grid_t* grid, int level, double* stencils);
  * floor(f/3) + (kx,ky,kz) at fine vertex f (zero where it is not a parent). */
 int qmg_get_prolongation(const qmg_grid_t* grid, int level, double* weights);
 
+enum { QMG_SMOOTH_JACOBI = 0, QMG_SMOOTH_BLOCK = 1 };
+
 enum {
   QMG_OP_MATVEC = 0,     /* out = A x                                         */
   QMG_OP_RESIDUAL = 1,   /* out = b - A x                                     */
   QMG_OP_JACOBI = 2,     /* out = x + omega diag(A)^-1 (b - A x); x = NULL: the
                             sweep from a zero iterate, out = omega diag(A)^-1 b */
   QMG_OP_RESTRICT = 3,   /* out (level-1 lattice) = P^T x (x on `level`)       */
-  QMG_OP_PROLONG = 4     /* out (level lattice) = b + P x (x on level-1)       */
+  QMG_OP_PROLONG = 4,    /* out (level lattice) = b + P x (x on level-1)       */
+  QMG_OP_SMOOTH = 5      /* out = one step of the grid's smoother from x      */
 };
 
 /* Applies one step of the hot path on `level` in the grid's iterate precision

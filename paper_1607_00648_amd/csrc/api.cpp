@@ -210,6 +210,9 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
   if (o->inner_cycles < 1) throw ApiError(QMG_EINVAL, "inner_cycles must be >= 1");
   if (!(o->stagnation >= 0.0 && o->stagnation < 1e6))
     throw ApiError(QMG_EINVAL, "stagnation must be 0 (off) or a positive factor");
+  if (o->smoother != QMG_SMOOTH_JACOBI && o->smoother != QMG_SMOOTH_BLOCK) throw ApiError(QMG_EINVAL, "bad smoother");
+  if (o->smoother == QMG_SMOOTH_BLOCK && (o->bj_sweeps < 1 || o->bj_sweeps > 64))
+    throw ApiError(QMG_EINVAL, "bj_sweeps must lie in 1..64");
   const bool adaptive = desc->base_level != 0 && desc->base_level != desc->max_level;
   if (adaptive) {
     if (desc->base_level < 1 || desc->base_level > desc->max_level)
@@ -217,6 +220,7 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
     if (!desc->refine) throw ApiError(QMG_EINVAL, "adaptive grid without refinement flags");
     if (o->coarsest_level > desc->base_level)
       throw ApiError(QMG_EINVAL, "coarsest_level must not exceed base_level");
+    if (o->smoother == QMG_SMOOTH_BLOCK) throw ApiError(QMG_EINVAL, "block Jacobi runs on regular grids");
   }
 }
 
@@ -500,6 +504,18 @@ template <typename T>
 void smooth(qmg_grid_t* g, LevelBuf& B, int sweeps, bool zero_init) {
   const T om = (T)g->opts.omega;
   const bool finest = g->prof_every > 0 && B.L.n == g->lv[g->Lmax].L.n;
+  if (g->opts.smoother == QMG_SMOOTH_BLOCK) {
+    // block Jacobi: Gauss-Seidel on the iota-vertices in place, then the
+    // Jacobi half into the other buffer
+    if (zero_init) launch_zero<T>((T*)B.u, B.L.nslot, S(g));
+    for (int k = 0; k < sweeps; ++k) {
+      launch_bj_iota<T>(B.L, (T*)B.u, (const T*)B.b, eps_of<T>(B), B.A, g->opts.bj_sweeps, S(g));
+      launch_stencil<T>(B.L, 4, (const T*)B.u, (const T*)B.b, (T*)B.t, eps_of<T>(B), B.A, om, nullptr,
+                        nullptr, S(g));
+      std::swap(B.u, B.t);
+    }
+    return;
+  }
   for (int k = 0; k < sweeps; ++k) {
     const int mode = (k == 0 && zero_init) ? 1 : 0;
     // timed: every k-th full Jacobi sweep of the finest level (not the sweep
@@ -546,6 +562,7 @@ bool p_stored(const qmg_grid_t* g) {
 template <typename T>
 int choose_fused_top(qmg_grid_t* g, bool& pw_lds) {
   int best = -1;
+  if (g->opts.smoother != QMG_SMOOTH_JACOBI) return best;  // the fused coarse cycle runs Jacobi
   for (int lf = g->lc; lf < g->lb && lf - g->lc + 1 <= kMaxFused; ++lf) {
     for (int pl = 1; pl >= 0; --pl) {
       FusedArgs<T> a = fused_args<T>(g, lf);
@@ -643,7 +660,7 @@ bool vcycle(qmg_grid_t* g, int l, bool zero_init, bool want_norm = false) {
     return false;
   }
   LevelBuf& Cb = g->lv[l - 1];
-  if (g->d == 2) {
+  if (g->d == 2 && g->opts.smoother == QMG_SMOOTH_JACOBI) {  // fused passes
     passes<T>(g, F, nullptr, mu, zero_init, true, nullptr);
     launch_restrict<T>(F.L, Cb.L, (const T*)F.r, (T*)Cb.b, F.P, S(g));
     vcycle<T>(g, l - 1, true);
@@ -818,7 +835,8 @@ void drop_graph(qmg_grid_t* g) {
 bool graph_usable(const qmg_grid_t* g) {
   if (g->prof_every > 0 || !g->opts.use_graphs) return false;
   const int mu = g->opts.mu_pre, nu = g->opts.mu_post;
-  // single sweeps (3D, coarsest level) and fused passes of two (2D)
+  // single sweeps (3D, coarsest level, block Jacobi) and fused passes of two (2D)
+  if (g->opts.smoother != QMG_SMOOTH_JACOBI) return (mu + nu) % 2 == 0;
   return (mu + nu) % 2 == 0 && ((mu + 1) / 2 + (nu + 1) / 2) % 2 == 0;
 }
 
@@ -1268,6 +1286,11 @@ void apply_op(qmg_grid_t* g, int op, int level, const double* x, const double* b
   if (b) upload_lattice<T>(g, B.L, b, (T*)B.b);
   else launch_zero<T>((T*)B.b, B.L.nslot, S(g));
   launch_zero<T>((T*)B.t, B.L.nslot, S(g));
+  if (op == QMG_OP_SMOOTH) {  // one step of the grid's smoother (result in B.u)
+    smooth<T>(g, B, 1, false);
+    download_lattice<T>(g, B.L, (const T*)B.u, out);
+    return;
+  }
   const int mode = op == QMG_OP_MATVEC ? 3 : op == QMG_OP_RESIDUAL ? 2 : x ? 0 : 1;
   launch_stencil<T>(B.L, mode, (const T*)B.u, (const T*)B.b, (T*)B.t, eps_of<T>(B), B.A, om, nullptr,
                     nullptr, S(g));
@@ -1431,6 +1454,8 @@ int qmg_default_opts(qmg_solver_opts* o) {
   o->inner_cycles = 1;
   o->use_graphs = 1;
   o->stagnation = 0.0;
+  o->smoother = QMG_SMOOTH_JACOBI;
+  o->bj_sweeps = 1;
   return QMG_OK;
 }
 
@@ -1779,7 +1804,8 @@ int qmg_get_prolongation(const qmg_grid_t* cg, int level, double* weights) {
 int qmg_apply(qmg_grid_t* g, int op, int level, const double* x, const double* b, double* out) {
   return guard(g, [&] {
     if (!g || !out || (!x && op != QMG_OP_JACOBI)) throw ApiError(QMG_EINVAL, "null argument");
-    if (op < QMG_OP_MATVEC || op > QMG_OP_PROLONG) throw ApiError(QMG_EINVAL, "bad op");
+    if (op < QMG_OP_MATVEC || op > QMG_OP_SMOOTH) throw ApiError(QMG_EINVAL, "bad op");
+    if (op == QMG_OP_SMOOTH && g->adaptive) throw ApiError(QMG_EINVAL, "smoothing step on regular grids only");
     if (!g->have_coef) throw ApiError(QMG_ESTATE, "coefficients not set");
     if (level < g->Lmax && !g->have_ops) throw ApiError(QMG_ESTATE, "operators not built");
     if ((op == QMG_OP_RESTRICT || op == QMG_OP_PROLONG) && !g->have_ops)

@@ -57,7 +57,10 @@ __global__ __launch_bounds__(256) void k_stencil(Lat L, const T* __restrict__ u,
       out[v] = (TO)(omega * b[v] / a[NS / 2]);
     } else {
       const T au = row_dot<D, T, SRC>(a, u, L, v);
-      if (MODE == 0) {
+      const bool iota = i % 3 != 0 && j % 3 != 0 && (D == 2 || kz % 3 != 0);
+      if (MODE == 4 && iota) {  // block Jacobi: iota-vertices keep their Gauss-Seidel value
+        out[v] = (TO)u[v];
+      } else if (MODE == 0 || MODE == 4) {
         out[v] = (TO)(u[v] + omega * (b[v] - au) / a[NS / 2]);
       } else {
         const T res = (MODE == 3) ? au : b[v] - au;
@@ -209,8 +212,11 @@ __global__ __launch_bounds__(MX * MY) void k_march3d(Lat L, const T* __restrict_
           if (SRC == SRC_GEOM && kref(3, ndiff_of<3>(q)) == 0.0) continue;
           au += a[q] * up[(k + off_z(q) + 3) % 3][(ly + 1 + off_y(q)) * UW + (lx + 1 + off_x(q))];
         }
-        if (MODE == 0) {
-          out[v] = (TO)(up[k % 3][(ly + 1) * UW + lx + 1] + omega * (bv - au) / a[NS / 2]);
+        const T uc = up[k % 3][(ly + 1) * UW + lx + 1];
+        if (MODE == 4 && i % 3 != 0 && j % 3 != 0 && k % 3 != 0) {  // block Jacobi iota-vertex
+          out[v] = (TO)uc;
+        } else if (MODE == 0 || MODE == 4) {
+          out[v] = (TO)(uc + omega * (bv - au) / a[NS / 2]);
         } else {
           const T res = (MODE == 3) ? au : bv - au;
           out[v] = (TO)res;
@@ -232,6 +238,60 @@ __global__ __launch_bounds__(MX * MY) void k_march3d(Lat L, const T* __restrict_
       partial[tl.t] = tot;
     }
   }
+}
+
+// Block Jacobi, first half (Sect. "Spacetree block smoothers"): one thread
+// per patch (the 3^d vertices of one cell of the next coarser level) runs
+// `sweeps` lexicographic Gauss-Seidel sweeps over the patch's 2^d
+// iota-vertices, in place, with every other value held.  The rows are built
+// once: the part that couples to vertices outside the patch's iota block is
+// folded into s_p = b_p - sum_w a_pw u_w, the 2^d x 2^d block stays in
+// registers.  Patches share no iota-vertex and no iota-vertex neighbours
+// another patch's, so the patches run in parallel.
+template <int D, typename T, int SRC, int FMT>
+__global__ __launch_bounds__(128) void k_bj_iota(Lat L, T* __restrict__ u, const T* __restrict__ b,
+                                                 const T* __restrict__ eps, Store A, int sweeps) {
+  constexpr int NS = Dim<D>::NS, NP = Dim<D>::NC;  // 2^d iota-vertices per patch
+  const int np = L.n / 3;                          // patches per axis
+  const int64_t npatch = (D == 3) ? (int64_t)np * np * np : (int64_t)np * np;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= npatch) return;
+  const int px = (int)(t % np), py = (int)((t / np) % np), pz = (D == 3) ? (int)(t / ((int64_t)np * np)) : 0;
+  T C[NP][NP], sp[NP], uu[NP];
+  int64_t vp[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int lx = p & 1, ly = (p >> 1) & 1, lz = (p >> 2) & 1;
+    const int64_t v = (3 * px + 1 + lx) + (int64_t)(3 * py + 1 + ly) * L.pitch +
+                      (D == 3 ? (int64_t)(3 * pz + 1 + lz) * L.plane : 0);
+    vp[p] = v;
+    T a[NS];
+    op_row<D, T, SRC, FMT>(eps, A, L, v, a);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) C[p][q] = (T)0;
+    T s = b[v];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int qx = lx + off_x(k), qy = ly + off_y(k), qz = (D == 3) ? lz + off_z(k) : 0;
+      if (qx >= 0 && qx <= 1 && qy >= 0 && qy <= 1 && qz >= 0 && qz <= 1)
+        C[p][qx | (qy << 1) | (qz << 2)] = a[k];
+      else
+        s -= a[k] * u[v + slot_off(L, off_x(k), off_y(k), D == 3 ? off_z(k) : 0)];
+    }
+    sp[p] = s;
+    uu[p] = u[v];
+  }
+  for (int sw = 0; sw < sweeps; ++sw) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      T r = sp[p];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) r -= C[p][q] * uu[q];
+      uu[p] += r / C[p][p];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) u[vp[p]] = uu[p];
 }
 
 __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict__ p, int n,
@@ -399,6 +459,7 @@ void dispatch_mode(const Lat& L, int mode, const T* u, const T* b, TO* out, cons
     case 0: launch_one<D, T, TO, SRC, FMT, 0>(g, bl, s, e0, e1, L, u, b, out, eps, A, omega, partial); break;
     case 1: launch_one<D, T, TO, SRC, FMT, 1>(g, bl, s, e0, e1, L, u, b, out, eps, A, omega, partial); break;
     case 2: launch_one<D, T, TO, SRC, FMT, 2>(g, bl, s, e0, e1, L, u, b, out, eps, A, omega, partial); break;
+    case 4: launch_one<D, T, TO, SRC, FMT, 4>(g, bl, s, e0, e1, L, u, b, out, eps, A, omega, partial); break;
     default: launch_one<D, T, TO, SRC, FMT, 3>(g, bl, s, e0, e1, L, u, b, out, eps, A, omega, partial); break;
   }
   QMG_HIP(hipGetLastError());
@@ -487,6 +548,33 @@ void launch_sum_partials(const double* partial, int n, double* out, hipStream_t 
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, partial, n, out, hist, counter, cap);
   QMG_HIP(hipGetLastError());
 }
+
+template <typename T>
+void launch_bj_iota(const Lat& L, T* u, const T* b, const T* eps, const Store& A, int sweeps, hipStream_t s) {
+  const int np = L.n / 3;
+  const int64_t npatch = (L.d == 3) ? (int64_t)np * np * np : (int64_t)np * np;
+  if (npatch == 0) return;
+  const dim3 g(blocks_for(npatch, 128)), bl(128);
+#define QMG_BJ(DV, SRCV, FMTV) hipLaunchKernelGGL((k_bj_iota<DV, T, SRCV, FMTV>), g, bl, 0, s, L, u, b, eps, A, sweeps)
+#define QMG_BJ_D(DV)                                   \
+  do {                                                 \
+    if (A.src == SRC_GEOM) QMG_BJ(DV, SRC_GEOM, F64);  \
+    else if (A.src == SRC_PLAIN) QMG_BJ(DV, SRC_PLAIN, F64); \
+    else if (A.fmt == F64) QMG_BJ(DV, SRC_HIER, F64);  \
+    else if (A.fmt == F32) QMG_BJ(DV, SRC_HIER, F32);  \
+    else if (A.fmt == F16) QMG_BJ(DV, SRC_HIER, F16);  \
+    else QMG_BJ(DV, SRC_HIER, BF16);                   \
+  } while (0)
+  if (L.d == 2) QMG_BJ_D(2);
+  else QMG_BJ_D(3);
+#undef QMG_BJ_D
+#undef QMG_BJ
+  QMG_HIP(hipGetLastError());
+}
+template void launch_bj_iota<double>(const Lat&, double*, const double*, const double*, const Store&, int,
+                                     hipStream_t);
+template void launch_bj_iota<float>(const Lat&, float*, const float*, const float*, const Store&, int,
+                                    hipStream_t);
 
 template <typename T>
 void launch_restrict(const Lat& Lf, const Lat& Lc, const T* r, T* bc, const Store& P, hipStream_t s) {

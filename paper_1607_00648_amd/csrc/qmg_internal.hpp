@@ -89,7 +89,8 @@ struct Store {
 // ---------------------------------------------------------------------------
 // Smoothing / residual / matvec on one level.  mode: 0 = Jacobi sweep
 // (out = u + omega D^-1 (b - A u)), 1 = Jacobi sweep from u = 0 (u not read),
-// 2 = residual out = b - A u, 3 = matvec out = A u.  When `partial` is non-null
+// 2 = residual out = b - A u, 3 = matvec out = A u, 4 = the Jacobi half of a
+// block Jacobi step (iota-vertices copied, the others as mode 0).  When `partial` is non-null
 // (modes 2 and 3) each workgroup adds its sum of squares of `out` there.
 // T is double or float; eps has the iterate type.
 // With ev_start/ev_stop the launch carries per-dispatch start/end timestamps.
@@ -97,6 +98,10 @@ template <typename T>
 void launch_stencil(const Lat& L, int mode, const T* u, const T* b, T* out, const T* eps,
                     const Store& A, T omega, double* partial, int* n_partial, hipStream_t s,
                     hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// Block Jacobi, Gauss-Seidel half: `sweeps` lexicographic sweeps over the
+// iota-vertices of every patch of level L, in place in u.
+template <typename T>
+void launch_bj_iota(const Lat& L, T* u, const T* b, const T* eps, const Store& A, int sweeps, hipStream_t s);
 
 // Finest-level FP64 residual for the mixed loop: r32 = fp32(b - A x), partial
 // sums of squares of the FP64 residual.

@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "QMG_OK", -1: "QMG_EINVAL", -2: "QMG_ENOMEM", -3: "QMG_EHIP",
 QMG_HOST, QMG_DEVICE = 0, 1
 GEOMETRIC, GALERKIN_DLINEAR, BOXMG = 0, 1, 2
 PLAIN_FP64, HIER_FP64, HIER_FP32, HIER_FP16, HIER_BF16 = 0, 1, 2, 3, 4
-OP_MATVEC, OP_RESIDUAL, OP_JACOBI, OP_RESTRICT, OP_PROLONG = 0, 1, 2, 3, 4
+OP_MATVEC, OP_RESIDUAL, OP_JACOBI, OP_RESTRICT, OP_PROLONG, OP_SMOOTH = 0, 1, 2, 3, 4, 5
+SMOOTHERS = {"jacobi": 0, "block": 1}
 
 TRANSFERS = {"geometric": GEOMETRIC, "galerkin": GALERKIN_DLINEAR, "boxmg": BOXMG}
 STORES = {"plain64": PLAIN_FP64, "hier64": HIER_FP64, "hier32": HIER_FP32,
@@ -38,7 +39,7 @@ class SolverOpts(C.Structure):
     _fields_ = [("transfer", C.c_int), ("store", C.c_int), ("mu_pre", C.c_int),
                 ("mu_post", C.c_int), ("omega", C.c_double), ("coarsest_level", C.c_int),
                 ("check_definite", C.c_int), ("inner_cycles", C.c_int), ("use_graphs", C.c_int),
-                ("stagnation", C.c_double)]
+                ("stagnation", C.c_double), ("smoother", C.c_int), ("bj_sweeps", C.c_int)]
 
 
 class SolveReport(C.Structure):
@@ -124,7 +125,8 @@ def _ptr(a: np.ndarray):
 
 
 def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_level=1,
-              check_definite=True, inner_cycles=1, graphs=True, stagnation=0.0) -> SolverOpts:
+              check_definite=True, inner_cycles=1, graphs=True, stagnation=0.0, smoother="jacobi",
+              bj_sweeps=1) -> SolverOpts:
     o = SolverOpts()
     o.transfer = TRANSFERS[transfer] if isinstance(transfer, str) else int(transfer)
     o.store = STORES[store] if isinstance(store, str) else int(store)
@@ -135,6 +137,8 @@ def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_l
     o.inner_cycles = int(inner_cycles)
     o.use_graphs = 1 if graphs else 0
     o.stagnation = float(stagnation)
+    o.smoother = SMOOTHERS[smoother] if isinstance(smoother, str) else int(smoother)
+    o.bj_sweeps = int(bj_sweeps)
     return o
 
 

@@ -31,6 +31,14 @@ Readings:
   coarsest level is solved exactly with its own operator when it has at most
   COARSE_DIRECT_MAX unknowns, otherwise by mu_pre + mu_post sweeps, and the
   raise lasts for the rest of the hierarchy's life.
+* Additive cycles (Alg. 2 and the additive multigrid appendix) in their
+  unpipelined form: one cycle restricts the fine residual down the whole
+  hierarchy (r_{l-1} = P_l^T r_l), takes one damped Jacobi step from zero on
+  every level (an exact solve on the coarsest level when it is direct), and
+  adds the prolongated sum of the corrections to the fine iterate.  The
+  paper's traversal pipelines this across half a grid sweep; the iterates
+  per cycle are the same.  Damping is constant (omega on every level) or
+  exponential (omega^(L - l + 1) on level l).
 * Block Jacobi readings: a patch is the 3^d block of vertices of one cell of
   the next coarser level; its iota-vertices are those with no coordinate
   divisible by 3.  One BJ(m) step first runs m lexicographic (x fastest)
@@ -202,6 +210,43 @@ def vcycle(H, l, u, b):
     for _ in range(H.mu_post):
         u = smooth(H, l, A, D, u, b)
     return u
+
+
+def additive_cycle(H, u, b, damping="exp"):
+    """One additive multigrid cycle (see module notes): u + sum over levels
+    of P (omega_l D_l^-1 R r); the coarsest level is solved exactly when the
+    hierarchy holds its factorisation."""
+    L, lc = H.L, H.lc
+    dt = H.dtype
+    r = {L: (b - H.A[L] @ u).astype(dt)}
+    for l in range(L, lc, -1):
+        r[l - 1] = (H.P[l].T @ r[l]).astype(dt)
+
+    def om(l):
+        return dt(H.omega ** (L - l + 1) if damping == "exp" else H.omega)
+
+    if H.coarse_lu is not None:
+        e = sla.lu_solve(H.coarse_lu, r[lc].astype(np.float64)).astype(dt)
+    else:
+        e = om(lc) * r[lc] / H.A[lc].diagonal()
+    for l in range(lc + 1, L + 1):
+        e = om(l) * r[l] / H.A[l].diagonal() + H.P[l] @ e
+    return u + e
+
+
+def solve_additive(H, b, tol=1e-8, max_cycles=1000, damping="exp", cycles=None):
+    """Additive cycles from zero until the relative residual reaches tol (or
+    exactly ``cycles``).  Returns (u, relres history)."""
+    A = H.A[H.L]
+    u = np.zeros(A.shape[0])
+    hist = []
+    n = cycles if cycles is not None else max_cycles
+    for _ in range(n):
+        u = additive_cycle(H, u, b, damping)
+        hist.append(relres(A, u, b))
+        if cycles is None and hist[-1] <= tol:
+            break
+    return u, hist
 
 
 def raise_coarsest(H, top=None):

@@ -255,3 +255,47 @@ def test_block_jacobi_cycles_converge_faster():
     assert h1[-1] <= 1e-10 and len(h1) < len(h0)
     ustar = O.direct_solve(H1.A[4], b)
     assert np.linalg.norm(u1 - ustar) <= 1e-8 * np.linalg.norm(ustar)
+
+
+# ---------------------------------------------------------------------------
+# Additive cycles (Alg. 2, additive multigrid appendix)
+# ---------------------------------------------------------------------------
+
+def test_additive_two_level_closed_form():
+    """Two levels with an exact coarse solve: u + omega D^-1 r + P A_c^-1 P^T r."""
+    p = W.random_checkerboard(2, 2, seed=3, values=(1.0, 20.0), blocks=3)
+    H = O.build_hierarchy(p.eps, 2, 2, transfer="galerkin")
+    assert H.lc == 1 and H.coarse_lu is not None
+    b = O.rhs_from_f(p.f, 2, 2)
+    u0 = np.random.default_rng(1).normal(size=b.shape)
+    A = H.A[2].toarray()
+    P = H.P[2].toarray()
+    r = b - A @ u0
+    want = u0 + 0.6 * r / np.diag(A) + P @ np.linalg.solve(H.A[1].toarray(), P.T @ r)
+    np.testing.assert_allclose(O.additive_cycle(H, u0, b), want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("damping", ["exp", "const"])
+def test_additive_operator_is_symmetric(damping):
+    """u -> additive_cycle(0, b) is the linear map B = sum_l P omega_l D_l^-1 P^T
+    (plus P A_c^-1 P^T): symmetric for R = P^T, checked column by column."""
+    p = W.random_checkerboard(2, 3, seed=2, values=(1.0, 10.0), blocks=3)
+    H = O.build_hierarchy(p.eps, 2, 3, transfer="boxmg")
+    n = H.A[3].shape[0]
+    B = np.column_stack([O.additive_cycle(H, np.zeros(n), np.eye(n)[:, j], damping) for j in range(n)])
+    assert np.abs(B - B.T).max() <= 1e-14 * np.abs(B).max()
+    assert np.linalg.eigvalsh((B + B.T) / 2).min() > 0
+
+
+def test_additive_exponential_damping_converges():
+    """With omega = 0.8 the undamped sum of level corrections diverges in 2D;
+    exponential damping converges to the direct solution."""
+    p = W.sin_source(2, 4)
+    b = O.rhs_from_f(p.f, 2, 4)
+    H = O.build_hierarchy(p.eps, 2, 4, transfer="geometric", omega=0.8)
+    u, h = O.solve_additive(H, b, tol=1e-10, max_cycles=400, damping="exp")
+    assert h[-1] <= 1e-10
+    ustar = O.direct_solve(H.A[4], b)
+    assert np.linalg.norm(u - ustar) <= 1e-8 * np.linalg.norm(ustar)
+    _, hc = O.solve_additive(H, b, cycles=60, damping="const")
+    assert hc[-1] > 1.0

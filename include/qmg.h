@@ -140,6 +140,16 @@ typedef struct {
                           other vertices from the updated iterate; on every
                           smoothing step of the cycle.  Regular grids only   */
   int bj_sweeps;       /* Gauss-Seidel sweeps per patch, 1..64 (block only)  */
+  int cycle;           /* QMG_CYCLE_MULT (default): multiplicative V(mu_pre,
+                          mu_post) cycles (Alg. 1); QMG_CYCLE_ADD: additive
+                          cycles (Alg. 2, unpipelined): the fine residual is
+                          restricted down the hierarchy, every level takes
+                          one damped Jacobi step from zero (the coarsest an
+                          exact solve when it is direct) and the prolongated
+                          sum of the corrections is added to the fine
+                          iterate.  Jacobi smoother, regular grids only      */
+  int damping;         /* additive cycles: QMG_DAMP_EXP (default), omega^(L-l+1)
+                          on level l; QMG_DAMP_CONST, omega on every level   */
 } qmg_solver_opts;
 
 typedef struct {
@@ -252,6 +262,8 @@ int qmg_get_operator(const qmg_grid_t* grid, int level, double* stencils);
 int qmg_get_prolongation(const qmg_grid_t* grid, int level, double* weights);
 
 enum { QMG_SMOOTH_JACOBI = 0, QMG_SMOOTH_BLOCK = 1 };
+enum { QMG_CYCLE_MULT = 0, QMG_CYCLE_ADD = 1 };
+enum { QMG_DAMP_EXP = 0, QMG_DAMP_CONST = 1 };
 
 enum {
   QMG_OP_MATVEC = 0,     /* out = A x                                         */

@@ -213,6 +213,10 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
   if (o->smoother != QMG_SMOOTH_JACOBI && o->smoother != QMG_SMOOTH_BLOCK) throw ApiError(QMG_EINVAL, "bad smoother");
   if (o->smoother == QMG_SMOOTH_BLOCK && (o->bj_sweeps < 1 || o->bj_sweeps > 64))
     throw ApiError(QMG_EINVAL, "bj_sweeps must lie in 1..64");
+  if (o->cycle != QMG_CYCLE_MULT && o->cycle != QMG_CYCLE_ADD) throw ApiError(QMG_EINVAL, "bad cycle");
+  if (o->damping != QMG_DAMP_EXP && o->damping != QMG_DAMP_CONST) throw ApiError(QMG_EINVAL, "bad damping");
+  if (o->cycle == QMG_CYCLE_ADD && o->smoother != QMG_SMOOTH_JACOBI)
+    throw ApiError(QMG_EINVAL, "additive cycles take one Jacobi step per level");
   const bool adaptive = desc->base_level != 0 && desc->base_level != desc->max_level;
   if (adaptive) {
     if (desc->base_level < 1 || desc->base_level > desc->max_level)
@@ -221,6 +225,7 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
     if (o->coarsest_level > desc->base_level)
       throw ApiError(QMG_EINVAL, "coarsest_level must not exceed base_level");
     if (o->smoother == QMG_SMOOTH_BLOCK) throw ApiError(QMG_EINVAL, "block Jacobi runs on regular grids");
+    if (o->cycle == QMG_CYCLE_ADD) throw ApiError(QMG_EINVAL, "additive cycles run on regular grids");
   }
 }
 
@@ -736,7 +741,8 @@ void composite_state(qmg_grid_t* g) {
 
 int64_t updates_per_cycle(const qmg_grid_t* g) {
   int64_t s = 0;
-  const int sw = g->opts.mu_pre + g->opts.mu_post;
+  // additive cycles: one Jacobi step per level
+  const int sw = g->opts.cycle == QMG_CYCLE_ADD ? 1 : g->opts.mu_pre + g->opts.mu_post;
   for (int l = g->lc + 1; l <= g->Lmax; ++l)
     s += (int64_t)sw * (l > g->lb ? g->hl[l].n_active : n_interior(g->lv[l].L));
   if (!g->coarse_direct) s += (int64_t)sw * n_interior(g->lv[g->lc].L);
@@ -798,7 +804,49 @@ double finest_residual_norm(qmg_grid_t* g) {
 // One "cycle" of the public API: a V-cycle (FP64) or an outer defect-correction
 // iteration with inner FP32 V-cycles (the residual has been formed already).
 // Returns true when the cycle left the finest residual norm partials.
+// Additive cycle (Alg. 2, unpipelined): r_L = b - A u restricted down to every
+// level, one damped Jacobi step from zero per level (exact on a direct
+// coarsest level), corrections summed coarse to fine, u += e_L.  The finest
+// level's own correction is the Jacobi sweep from u.
+template <typename T>
+void additive_cycle(qmg_grid_t* g, bool zero_init) {
+  const int L = g->Lmax, lc = g->lc;
+  LevelBuf& F = g->lv[L];
+  const double w = g->opts.omega;
+  auto om = [&](int l) { return (T)(g->opts.damping == QMG_DAMP_EXP ? std::pow(w, L - l + 1) : w); };
+  if (zero_init) launch_zero<T>((T*)F.u, F.L.nslot, S(g));
+  launch_stencil<T>(F.L, 2, (const T*)F.u, (const T*)F.b, (T*)F.r, eps_of<T>(F), F.A, (T)0, nullptr, nullptr,
+                    S(g));
+  for (int l = L; l > lc; --l)
+    launch_restrict<T>(g->lv[l].L, g->lv[l - 1].L, (const T*)g->lv[l].r, (T*)g->lv[l - 1].r, g->lv[l].P, S(g));
+  LevelBuf& C = g->lv[lc];
+  if (g->coarse_direct)
+    launch_coarse_solve<T>(C.L, g->Ainv, g->nc, (const T*)C.r, (T*)C.u, S(g));
+  else
+    launch_stencil<T>(C.L, 1, (const T*)C.u, (const T*)C.r, (T*)C.u, eps_of<T>(C), C.A, om(lc), nullptr, nullptr,
+                      S(g));
+  for (int l = lc + 1; l < L; ++l) {
+    LevelBuf& B = g->lv[l];
+    launch_stencil<T>(B.L, 1, (const T*)B.u, (const T*)B.r, (T*)B.u, eps_of<T>(B), B.A, om(l), nullptr, nullptr,
+                      S(g));
+    launch_prolong<T>(B.L, g->lv[l - 1].L, (const T*)g->lv[l - 1].u, (T*)B.u, B.P, S(g));
+  }
+  launch_stencil<T>(F.L, 0, (const T*)F.u, (const T*)F.b, (T*)F.t, eps_of<T>(F), F.A, om(L), nullptr, nullptr,
+                    S(g));
+  launch_prolong<T>(F.L, g->lv[L - 1].L, (const T*)g->lv[L - 1].u, (T*)F.t, F.P, S(g));
+  std::swap(F.u, F.t);
+}
+
 bool one_cycle(qmg_grid_t* g) {
+  if (g->opts.cycle == QMG_CYCLE_ADD) {
+    if (!g->mixed) {
+      additive_cycle<double>(g, false);
+      return false;
+    }
+    for (int m = 0; m < g->opts.inner_cycles; ++m) additive_cycle<float>(g, m == 0);
+    launch_axpy_mixed(g->lv[g->Lmax].L, g->x64, (const float*)g->lv[g->Lmax].u, S(g));
+    return false;
+  }
   if (!g->mixed) return vcycle<double>(g, g->Lmax, false, true);
   if (g->adaptive) {
     // inner FAS cycles on the correction, from zero on every level
@@ -834,6 +882,7 @@ void drop_graph(qmg_grid_t* g) {
 // it started from, i.e. an even number of sweeps per level.
 bool graph_usable(const qmg_grid_t* g) {
   if (g->prof_every > 0 || !g->opts.use_graphs) return false;
+  if (g->opts.cycle == QMG_CYCLE_ADD) return false;  // one buffer swap per cycle on the finest level
   const int mu = g->opts.mu_pre, nu = g->opts.mu_post;
   // single sweeps (3D, coarsest level, block Jacobi) and fused passes of two (2D)
   if (g->opts.smoother != QMG_SMOOTH_JACOBI) return (mu + nu) % 2 == 0;
@@ -1456,6 +1505,8 @@ int qmg_default_opts(qmg_solver_opts* o) {
   o->stagnation = 0.0;
   o->smoother = QMG_SMOOTH_JACOBI;
   o->bj_sweeps = 1;
+  o->cycle = QMG_CYCLE_MULT;
+  o->damping = QMG_DAMP_EXP;
   return QMG_OK;
 }
 

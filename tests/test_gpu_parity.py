@@ -586,3 +586,51 @@ def test_block_jacobi_solve_fewer_cycles(store):
         assert np.linalg.norm(b - H.A[5] @ u) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)
         reps[sm] = rep
     assert reps["block"]["outer_iters"] < reps["jacobi"]["outer_iters"]
+
+
+# ---------------------------------------------------------------------------
+# Additive cycles
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,L,transfer,store,omega,damping", [
+    (2, 4, "geometric", "hier64", 0.8, "exp"), (2, 5, "boxmg", "hier64", 0.6, "const"),
+    (3, 3, "galerkin", "hier64", 0.8, "exp"), (2, 4, "boxmg", "plain64", 0.6, "exp")])
+def test_additive_cycles_match_oracle(d, L, transfer, store, omega, damping):
+    """Additive cycles (restricted fine residual, one damped Jacobi step from
+    zero per level, prolongated sum of corrections): residual history and
+    iterate against the oracle."""
+    qmg = require_gpu()
+    announce(f"additive cycles d={d} L={L} {transfer} {store} omega={omega} {damping}")
+    p = W.random_checkerboard(d, L, seed=13, values=(1.0, 1e2), blocks=9 if L > 3 else 3)
+    g = _grid(qmg, p, transfer, store, omega=omega, cycle="add", damping=damping, check_definite=False)
+    g.build()
+    k = 6
+    rr = g.vcycle(k)
+    u = g.solution()
+    g.close()
+    H = O.build_hierarchy(p.eps, d, L, transfer=transfer, omega=omega, check_definite=False)
+    uo, hist = O.solve_additive(H, O.rhs_from_f(p.f, d, L), damping=damping, cycles=k)
+    np.testing.assert_allclose(rr, hist, rtol=1e-10, atol=1e-14)
+    assert np.abs(u - uo).max() <= 1e-11 * np.abs(uo).max()
+
+
+@pytest.mark.parametrize("store", ["hier64", "bf16"])
+def test_additive_solve_sine_setup(store):
+    """The paper's sin setup with omega = 0.8 and exponential damping, solved
+    to 1e-8 (the oracle recomputes the residual), in FP64 and with FP32 inner
+    cycles; the FP64 run takes the oracle's cycle count."""
+    qmg = require_gpu()
+    announce(f"additive solve sin {store}")
+    p = W.sin_source(2, 5)
+    g = _grid(qmg, p, "geometric", store, omega=0.8, cycle="add")
+    g.build()
+    rep, _ = g.solve(1e-8, 600)
+    u = g.solution()
+    g.close()
+    assert rep["status"] == "QMG_OK"
+    H = O.build_hierarchy(p.eps, 2, 5, transfer="geometric", omega=0.8)
+    b = O.rhs_from_f(p.f, 2, 5)
+    assert np.linalg.norm(b - H.A[5] @ u) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)
+    if store == "hier64":
+        _, hist = O.solve_additive(H, b, tol=1e-8, max_cycles=600)
+        assert abs(rep["cycles"] - len(hist)) <= 1   # the batched loop may stop one cycle late

@@ -159,6 +159,16 @@ def other_workloads(qmg, n):
                                workload="2D Poisson, 81^2 cells (80^2 unknowns), eps = 1, f~U[-1,1]; "
                                         "geometric V(2,2), omega 0.6, plain FP64 store, to 1e-10")
     g.close()
+    p = W.sin_source(2, 6)
+    g = qmg.Grid(p.dim, p.level, qmg.make_opts("geometric", "hier64", omega=0.8, cycle="add"))
+    eps = torch.from_numpy(np.ascontiguousarray(p.eps).ravel()).cuda()
+    f = torch.from_numpy(np.ascontiguousarray(p.f).ravel()).cuda()
+    r = time_solves(g, eps, f, 1e-8, max(5, n // 5), warmup=1)
+    out["additive2d_sin_L6"] = dict(r, unknowns=p.n_unknowns,
+                                    workload="2D sine source (exact solution prod sin(pi x_i)), 729^2 cells; "
+                                             "additive cycles with exponential damping, omega 0.8, "
+                                             "geometric transfer, to 1e-8")
+    g.close()
     P = W.adaptive_balls()
     g = qmg.Grid(P.dim, P.level, qmg.make_opts("boxmg", "bf16", check_definite=False),
                  base_level=P.base, refine=P.flags)

@@ -2,9 +2,9 @@
 // optional prolongation-add u += P e, one or two damped Jacobi sweeps and an
 // optional residual r = b - A u (with norm partials), in one launch.
 //
-// A workgroup of 1024 threads owns a 64 x 8 output tile, one region point per
-// thread, so that every thread issues its loads at once (the passes are bound
-// by memory latency, not bandwidth).  The iterate is staged in LDS on the
+// A workgroup of 1024 threads owns a 64 x 8 (or 56 x 10) output tile, one
+// region point per thread, so that every thread issues its loads at once (the
+// passes are bound by memory latency, not bandwidth).  The iterate is staged in LDS on the
 // tile plus a halo of K vertices, K = number of neighbour-dependent stages
 // (sweeps, residual); stage s produces its values on the tile plus a halo of
 // K - s, so the next stage finds every neighbour in LDS.  Each thread keeps the
@@ -21,11 +21,37 @@ namespace qmg {
 
 namespace {
 
-constexpr int PX = 64, PY = 8, NT = 1024;
+constexpr int NT = 1024;
 constexpr int KMAX = 3;
-constexpr int WMAX = PX + 2 * KMAX, HMAX = PY + 2 * KMAX;
-constexpr int PTS = (WMAX * HMAX + NT - 1) / NT;
 constexpr int NS2 = 9;
+// Output tiles: 64 x 8, or 56 x 10 (region 62 x 16 = 992 points, still one
+// per thread).  Two 1024-thread workgroups are resident per CU, 512 on the
+// chip; a level takes the tile with fewer such rounds of workgroups (the
+// 729^2-cell level: 1104 tiles of 64 x 8 need three rounds, the last one
+// nearly empty; 1022 tiles of 56 x 10 need two).
+constexpr int kResidentPasses = 512;
+template <int PXT, int PYT>
+struct PassTile {
+  static constexpr int PX = PXT, PY = PYT;
+  static constexpr int WMAX = PX + 2 * KMAX, HMAX = PY + 2 * KMAX;
+  static constexpr int PTS = (WMAX * HMAX + NT - 1) / NT;
+  static dim3 grid(const Lat& L) {
+    return dim3((unsigned)((L.n + 1 + PX - 1) / PX), (unsigned)((L.n + 1 + PY - 1) / PY), 1);
+  }
+  static int count(const Lat& L) {
+    const dim3 g = grid(L);
+    return (int)(g.x * g.y);
+  }
+};
+using TileA = PassTile<64, 8>;
+using TileB = PassTile<56, 10>;
+static_assert(TileA::PTS == 1 && TileB::PTS == 1, "one region point per thread");
+
+bool use_tile_b(const Lat& L) {
+  const int ra = (TileA::count(L) + kResidentPasses - 1) / kResidentPasses;
+  const int rb = (TileB::count(L) + kResidentPasses - 1) / kResidentPasses;
+  return rb < ra;
+}
 
 template <typename T, int FMT>
 __device__ inline T prolong_any(const PassArgs<T>& p, int i, int j, int64_t vf) {
@@ -36,8 +62,9 @@ __device__ inline T prolong_any(const PassArgs<T>& p, int i, int j, int64_t vf) 
   }
 }
 
-template <typename T, int SRC, int FMT>
+template <typename T, int SRC, int FMT, class TL>
 __global__ __launch_bounds__(NT) void k_pass2d(PassArgs<T> p) {
+  constexpr int PX = TL::PX, PY = TL::PY, WMAX = TL::WMAX, HMAX = TL::HMAX, PTS = TL::PTS;
   __shared__ T buf[2][WMAX * HMAX];
   __shared__ double red[NT / 64];
   const int K = p.nsw + (p.res ? 1 : 0);
@@ -136,13 +163,19 @@ void launch_pass2d(const PassArgs<T>& p, hipStream_t s, hipEvent_t ev_start, hip
   if (p.nsw < 0 || p.nsw > 2 || p.nsw + (p.res ? 1 : 0) > KMAX || p.nsw + (p.res ? 1 : 0) < 1)
     throw ApiError(QMG_EINVAL, "fused pass: 1 or 2 sweeps plus an optional residual");
   if (p.pro && p.zero_first) throw ApiError(QMG_EINVAL, "fused pass: prolongation into a zero iterate");
-  const dim3 g((unsigned)(p.L.pitch / PX), (unsigned)((p.L.n + 1 + PY - 1) / PY), 1), bl(NT, 1, 1);
-#define QMG_PASS(SRCV, FMTV)                                                                      \
+  const bool tb = use_tile_b(p.L);
+  const dim3 g = tb ? TileB::grid(p.L) : TileA::grid(p.L), bl(NT, 1, 1);
+#define QMG_PASS_T(SRCV, FMTV, TLV)                                                               \
   do {                                                                                            \
     if (ev_start != nullptr)                                                                      \
-      hipExtLaunchKernelGGL((k_pass2d<T, SRCV, FMTV>), g, bl, 0, s, ev_start, ev_stop, 0, p);      \
+      hipExtLaunchKernelGGL((k_pass2d<T, SRCV, FMTV, TLV>), g, bl, 0, s, ev_start, ev_stop, 0, p); \
     else                                                                                          \
-      hipLaunchKernelGGL((k_pass2d<T, SRCV, FMTV>), g, bl, 0, s, p);                              \
+      hipLaunchKernelGGL((k_pass2d<T, SRCV, FMTV, TLV>), g, bl, 0, s, p);                         \
+  } while (0)
+#define QMG_PASS(SRCV, FMTV)                 \
+  do {                                       \
+    if (tb) QMG_PASS_T(SRCV, FMTV, TileB);   \
+    else QMG_PASS_T(SRCV, FMTV, TileA);      \
   } while (0)
   if (p.A.src == SRC_GEOM) {
     switch (p.P.fmt) {  // the prolongation store shares the level format
@@ -162,10 +195,11 @@ void launch_pass2d(const PassArgs<T>& p, hipStream_t s, hipEvent_t ev_start, hip
     }
   }
 #undef QMG_PASS
+#undef QMG_PASS_T
   QMG_HIP(hipGetLastError());
 }
 
-int pass2d_partials(const Lat& L) { return (L.pitch / PX) * ((L.n + 1 + PY - 1) / PY); }
+int pass2d_partials(const Lat& L) { return use_tile_b(L) ? TileB::count(L) : TileA::count(L); }
 
 template void launch_pass2d<double>(const PassArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_pass2d<float>(const PassArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);

@@ -712,7 +712,8 @@ void vcycle_ad(qmg_grid_t* g, int l) {
   launch_ad_stencil<T, T>(tf, 2, (const T*)F.u, (const T*)F.b, (T*)F.r, eps_of<T>(F), F.A, (T)0, nullptr, S(g));
   launch_ad_inject<T>(tc, F.L, (const T*)F.u, (T*)C.u, S(g));
   launch_ad_copy<T>(tc, (const T*)C.u, (T*)C.sv, S(g));
-  launch_ad_fas_rhs<T>(tc, F.L, (const T*)F.r, (const T*)C.u, eps_of<T>(C), C.A, (T*)C.b, F.P, S(g));
+  launch_ad_fas_rhs<T>(tc, F.L, (const T*)F.r, (const T*)C.u, eps_of<T>(C), C.A, (T*)C.b, F.P, S(g), C.rv,
+                       C.nrv);
   vcycle<T>(g, l - 1, false);
   launch_ad_correct<T>(tf, C.L, (T*)F.u, (const T*)C.u, (const T*)C.sv, F.P, S(g));
   launch_ad_hang<T>(tf, C.L, (T*)F.u, (const T*)C.u, F.P, S(g));

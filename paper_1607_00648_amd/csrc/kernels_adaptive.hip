@@ -141,6 +141,44 @@ __global__ __launch_bounds__(256) void k_ad_fas_rhs(Lat Lf, Lat Lc, const int32_
   bc[s.v] = rr + row_dot<D, T, SRC>(a, uc, Lc, s.v);
 }
 
+// The same from the list of refined coarse vertices (interior indices), one
+// wavefront per vertex: the lanes share the 5^d restriction terms and add
+// them in a fixed shuffle tree; lane 0 adds the coarse row.
+template <int D, typename T, int SRC, int FMT, int PSRC, int PFMT>
+__global__ __launch_bounds__(256) void k_ad_fas_rhs_list(Lat Lf, Lat Lc, const int32_t* __restrict__ verts,
+                                                         int64_t nverts, const T* __restrict__ rf,
+                                                         const T* __restrict__ uc, const T* __restrict__ epsc,
+                                                         Store Ac, T* __restrict__ bc, Store P) {
+  constexpr int NS = Dim<D>::NS, NO = (D == 3) ? 125 : 25;
+  const int lane = threadIdx.x & 63;
+  const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (idx >= nverts) return;  // uniform per wavefront
+  const int m = Lc.n - 1;
+  const int64_t vv = verts[idx];
+  const int I = (int)(vv % m) + 1, J = (int)((vv / m) % m) + 1, K = (D == 3) ? (int)(vv / ((int64_t)m * m)) + 1 : 0;
+  const int64_t vf0 = 3 * I + (int64_t)3 * J * Lf.pitch + (int64_t)3 * K * Lf.plane;
+  T acc = (T)0;
+  for (int o = lane; o < NO; o += 64) {
+    const int ox = o % 5 - 2, oy = (o / 5) % 5 - 2, oz = (D == 3) ? o / 25 - 2 : 0;
+    const int64_t vf = vf0 + slot_off(Lf, ox, oy, oz);
+    const int kap = (ox < 0 ? 1 : 0) | (oy < 0 ? 2 : 0) | (oz < 0 ? 4 : 0);
+    double w;
+    if (PSRC == SRC_GEOM)
+      w = (1.0 - abs(ox) / 3.0) * (1.0 - abs(oy) / 3.0) * (D == 3 ? (1.0 - abs(oz) / 3.0) : 1.0);
+    else
+      w = pweight<D, PSRC, PFMT>(P, Lf, vf, (ox + 3) % 3, (oy + 3) % 3, (oz + 3) % 3, kap);
+    acc += (T)w * rf[vf];
+  }
+#pragma unroll
+  for (int mm = 32; mm >= 1; mm >>= 1) acc += __shfl_xor(acc, mm, 64);
+  if (lane == 0) {
+    const int64_t v = I + (int64_t)J * Lc.pitch + (int64_t)K * Lc.plane;
+    T a[NS];
+    op_row<D, T, SRC, FMT>(epsc, Ac, Lc, v, a);
+    bc[v] = acc + row_dot<D, T, SRC>(a, uc, Lc, v);
+  }
+}
+
 // FAS correction: active fine vertices += P (u_c - saved_c)
 template <int D, typename T, int PSRC, int PFMT>
 __global__ __launch_bounds__(256) void k_ad_correct(Lat Lf, Lat Lc, const int32_t* __restrict__ tiles,
@@ -278,9 +316,18 @@ void ad_stencil_src(const AdTiles& t, int mode, const T* u, const T* b, TO* out,
 
 template <int D, typename T, int PSRC>
 void ad_fas_src(const AdTiles& tc, const Lat& Lf, const T* rf, const T* uc, const T* epsc, const Store& Ac,
-                T* bc, const Store& P, hipStream_t s) {
+                T* bc, const Store& P, hipStream_t s, const int32_t* verts, int64_t nverts) {
   const dim3 g = tiles_grid(tc.n), bl(TX, TY, 1);
-#define QMG_FAS(SRCV, FMTV) hipLaunchKernelGGL((k_ad_fas_rhs<D, T, SRCV, FMTV, PSRC, F64>), g, bl, 0, s, Lf, tc.L, tc.tiles, tc.vt, rf, uc, epsc, Ac, bc, P)
+  const dim3 gl((unsigned)((nverts + 3) / 4)), bll(256);
+#define QMG_FAS(SRCV, FMTV)                                                                              \
+  do {                                                                                                   \
+    if (verts)                                                                                           \
+      hipLaunchKernelGGL((k_ad_fas_rhs_list<D, T, SRCV, FMTV, PSRC, F64>), gl, bll, 0, s, Lf, tc.L, verts, \
+                         nverts, rf, uc, epsc, Ac, bc, P);                                               \
+    else                                                                                                 \
+      hipLaunchKernelGGL((k_ad_fas_rhs<D, T, SRCV, FMTV, PSRC, F64>), g, bl, 0, s, Lf, tc.L, tc.tiles, tc.vt, \
+                         rf, uc, epsc, Ac, bc, P);                                                       \
+  } while (0)
   if (Ac.src == SRC_GEOM) QMG_FAS(SRC_GEOM, F64);
   else if (Ac.src == SRC_PLAIN) QMG_FAS(SRC_PLAIN, F64);
   else if (Ac.fmt == F64) QMG_FAS(SRC_HIER, F64);
@@ -335,17 +382,18 @@ void launch_ad_inject(const AdTiles& tc, const Lat& Lf, const T* uf, T* uc, hipS
 
 template <typename T>
 void launch_ad_fas_rhs(const AdTiles& tc, const Lat& Lf, const T* rf, const T* uc, const T* epsc,
-                       const Store& Ac, T* bc, const Store& P, hipStream_t s) {
-  if (tc.n <= 0) return;
+                       const Store& Ac, T* bc, const Store& P, hipStream_t s, const int32_t* verts,
+                       int64_t nverts) {
+  if (tc.n <= 0 || (verts && nverts <= 0)) return;
   check_ad_P(P);
   if (tc.L.d == 2) {
-    if (P.src == SRC_HIER) ad_fas_src<2, T, SRC_HIER>(tc, Lf, rf, uc, epsc, Ac, bc, P, s);
-    else if (P.src == SRC_PLAIN) ad_fas_src<2, T, SRC_PLAIN>(tc, Lf, rf, uc, epsc, Ac, bc, P, s);
-    else ad_fas_src<2, T, SRC_GEOM>(tc, Lf, rf, uc, epsc, Ac, bc, P, s);
+    if (P.src == SRC_HIER) ad_fas_src<2, T, SRC_HIER>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts);
+    else if (P.src == SRC_PLAIN) ad_fas_src<2, T, SRC_PLAIN>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts);
+    else ad_fas_src<2, T, SRC_GEOM>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts);
   } else {
-    if (P.src == SRC_HIER) ad_fas_src<3, T, SRC_HIER>(tc, Lf, rf, uc, epsc, Ac, bc, P, s);
-    else if (P.src == SRC_PLAIN) ad_fas_src<3, T, SRC_PLAIN>(tc, Lf, rf, uc, epsc, Ac, bc, P, s);
-    else ad_fas_src<3, T, SRC_GEOM>(tc, Lf, rf, uc, epsc, Ac, bc, P, s);
+    if (P.src == SRC_HIER) ad_fas_src<3, T, SRC_HIER>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts);
+    else if (P.src == SRC_PLAIN) ad_fas_src<3, T, SRC_PLAIN>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts);
+    else ad_fas_src<3, T, SRC_GEOM>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts);
   }
   QMG_HIP(hipGetLastError());
 }
@@ -433,8 +481,8 @@ template void launch_ad_hang<double>(const AdTiles&, const Lat&, double*, const 
 template void launch_ad_hang<float>(const AdTiles&, const Lat&, float*, const float*, const Store&, hipStream_t);
 template void launch_ad_inject<double>(const AdTiles&, const Lat&, const double*, double*, hipStream_t);
 template void launch_ad_inject<float>(const AdTiles&, const Lat&, const float*, float*, hipStream_t);
-template void launch_ad_fas_rhs<double>(const AdTiles&, const Lat&, const double*, const double*, const double*, const Store&, double*, const Store&, hipStream_t);
-template void launch_ad_fas_rhs<float>(const AdTiles&, const Lat&, const float*, const float*, const float*, const Store&, float*, const Store&, hipStream_t);
+template void launch_ad_fas_rhs<double>(const AdTiles&, const Lat&, const double*, const double*, const double*, const Store&, double*, const Store&, hipStream_t, const int32_t*, int64_t);
+template void launch_ad_fas_rhs<float>(const AdTiles&, const Lat&, const float*, const float*, const float*, const Store&, float*, const Store&, hipStream_t, const int32_t*, int64_t);
 template void launch_ad_correct<double>(const AdTiles&, const Lat&, double*, const double*, const double*, const Store&, hipStream_t);
 template void launch_ad_correct<float>(const AdTiles&, const Lat&, float*, const float*, const float*, const Store&, hipStream_t);
 template void launch_ad_copy<double>(const AdTiles&, const double*, double*, hipStream_t);

@@ -273,9 +273,13 @@ template <typename T>
 void launch_ad_hang(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const Store& P, hipStream_t s);
 template <typename T>
 void launch_ad_inject(const AdTiles& tc, const Lat& Lf, const T* uf, T* uc, hipStream_t s);
+// verts (nullable): the refined vertices of the coarse level (interior
+// indices); then one wavefront per listed vertex instead of one thread per
+// slot of the coarse level's active tiles
 template <typename T>
 void launch_ad_fas_rhs(const AdTiles& tc, const Lat& Lf, const T* rf, const T* uc, const T* epsc,
-                       const Store& Ac, T* bc, const Store& P, hipStream_t s);
+                       const Store& Ac, T* bc, const Store& P, hipStream_t s, const int32_t* verts = nullptr,
+                       int64_t nverts = 0);
 template <typename T>
 void launch_ad_correct(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const T* sc, const Store& P,
                        hipStream_t s);

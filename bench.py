@@ -5,7 +5,7 @@ workload (729^2 cells, random 9x9 checkerboard of {1, 1e4}): set_coefficients,
 build_operators (BoxMG P, Galerkin R A P with the definiteness check,
 hierarchical FP64 delta store, coarsest LU) and V(2,2) cycles to a relative
 residual of 1e-8, all in the HIP library on one GPU.  Inputs are seeded and
-synthetic (workloads.cfg2) and resident in HBM (torch tensors) before the
+synthetic (workloads.checkerboard2d) and resident in HBM (torch tensors) before the
 timed region; set_coefficients checks and scatters them on the device.  The
 same steps with host-resident inputs (PCIe hand-over) are reported beside.
 
@@ -150,7 +150,7 @@ def other_workloads(qmg, n):
     import torch
     import workloads as W
     out = {}
-    p = W.cfg1(0)
+    p = W.poisson2d_l4(0)
     g = qmg.Grid(p.dim, p.level, qmg.make_opts("geometric", "plain64"))
     eps = torch.from_numpy(np.ascontiguousarray(p.eps).ravel()).cuda()
     f = torch.from_numpy(np.ascontiguousarray(p.f).ravel()).cuda()
@@ -198,7 +198,7 @@ def serve_stream(qmg, n_requests=256, seed=0, slots=16, budget=8 << 30):
     t = 0) for the saturated throughput, then Poisson arrivals at 0.9 of it."""
     import workloads as W
     mixed = qmg.make_opts("boxmg", "hier16")
-    stream = W.cfg4_stream(seed=seed, n_requests=n_requests)
+    stream = W.request_stream(seed=seed, n_requests=n_requests)
     out = {"requests": n_requests, "store": "hier16", "slots": slots, "hbm_budget_bytes": budget}
 
     def run(arrivals, opts):
@@ -264,7 +264,7 @@ def cpu_solution_poisson():
     V(2,2) cycles to 1e-10)."""
     import oracle as O
     import workloads as W
-    p = W.cfg1(0)
+    p = W.poisson2d_l4(0)
     H = O.build_hierarchy(p.eps, p.dim, p.level, transfer="geometric")
     u, _ = O.solve(H, O.rhs_from_f(p.f, p.dim, p.level), tol=1e-10, max_cycles=500)
     return u
@@ -293,7 +293,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver path is "
-              f"single-GPU in this build", file=sys.stderr)
+              f"single-GPU", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1607_00648_amd import qmg
@@ -309,7 +309,7 @@ def main():
         torch.cuda.synchronize()
         print(f"copy calibration: {args.calibrate_copy} MiB read + written", file=sys.stderr)
         del src, dst
-    p = W.cfg2(0, level=args.level)
+    p = W.checkerboard2d(0, level=args.level)
     # timed pass: every PROFILE_EVERY-th finest-level sweep carries per-dispatch
     # HIP events on the grid's stream
     res = run_variant(qmg, p, "boxmg", args.store, args.steps, args.warmup,

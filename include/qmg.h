@@ -285,7 +285,7 @@ enum {
 int qmg_apply(qmg_grid_t* grid, int op, int level, const double* x, const double* b, double* out);
 
 /* ---------------- serving ------------------------------------------------
- * A persistent request loop (up to four worker threads per server, each
+ * A persistent request loop (up to eight worker threads per server, each
  * driving its share of the slots) that keeps the grids and operators of
  * admitted requests on the device and overlaps their work.  Requests are
  * admitted in arrival order -- a later request that fits may pass a head that

@@ -212,7 +212,7 @@ def unknowns_from_lattice(a, d, level):
 def coarsen_eps(eps, d):
     """Coefficient of a level-(l-1) cell = mean of its 3^d children.  The paper
     rediscretises on every level (Sect. 2, item 3) without fixing how eps is
-    sampled there; averaging is this build's reading."""
+    sampled there; averaging is a reading of the paper."""
     comps = np.asarray(eps, dtype=np.float64)
     lead = comps.ndim - d
     n = comps.shape[-1]

@@ -5,8 +5,8 @@ A_hat = A - A_rediscretised and P_hat = P - P_dlinear (R_hat = P_hat^T) are
 small for smooth coefficients; a vertex whose hierarchical operator is zero
 drops its stencil, otherwise the entries are stored compressed.
 
-This build replaces the paper's byte-stream codec by IEEE formats (reading, see
-the design notes): the deltas are rounded to nearest-even in FP64, FP32, BF16 or
+The IEEE formats here replace the paper's byte-stream codec (a reading of
+the paper): the deltas are rounded to nearest-even in FP64, FP32, BF16 or
 FP16.  Rounding rules, fixed so that both the oracle and the GPU take the same
 decisions:
 
@@ -15,7 +15,7 @@ decisions:
 * FP16: per stencil (per vertex) a power-of-two scale 2^e with e the smallest
   integer such that max|delta| <= 2^(15+e); the scaled FP64 value delta/2^e is
   rounded to FP32 and then to FP16 (nearest-even).  The paper stores one exponent
-  byte per entry (m * 2^e); one exponent per stencil is this build's reading.
+  byte per entry (m * 2^e); one exponent per stencil is a reading of the paper.
 * A vertex's delta counts as zero when max|delta| <= EPS_ZERO * max|A_geom row|
   with EPS_ZERO = 2^-40 (about 9e-13).  Galerkin/BoxMG reproduce the
   rediscretisation only to rounding for constant coefficients, and that

@@ -300,7 +300,7 @@ def test_balls_full_size_mixed_bf16_sampled_rows():
     assert np.abs(r).max() <= 1e-8 * nb * (1 + 1e-6)
     est = sum((levels == l).sum() * np.mean(r[levels[sample] == l] ** 2) for l in range(G.base, G.L + 1))
     assert np.sqrt(est) <= 10 * rep["relres"] * nb
-    print(f"[cfg3 bf16] outer iterations {rep['outer_iters']}, relres {rep['relres']:.2e}")
+    print(f"[balls3d bf16] outer iterations {rep['outer_iters']}, relres {rep['relres']:.2e}")
 
 
 # ---------------------------------------------------------------------------
@@ -428,10 +428,10 @@ def test_boxmg_balls_full_size_mixed():
         rep, _ = g.solve(tol=1e-8, max_cycles=300)
         assert rep["status"] == "QMG_OK", (store, rep)
         sol[store] = g.solution()
-        print(f"[cfg3 boxmg {store}] cycles {rep['cycles']}, outer {rep['outer_iters']}, relres {rep['relres']:.2e}")
+        print(f"[balls3d boxmg {store}] cycles {rep['cycles']}, outer {rep['outer_iters']}, relres {rep['relres']:.2e}")
         g.close()
     rel = np.linalg.norm(sol["bf16"] - sol["hier64"]) / np.linalg.norm(sol["hier64"])
-    print(f"[cfg3 boxmg] bf16 vs fp64 solution: {rel:.2e}")
+    print(f"[balls3d boxmg] bf16 vs fp64 solution: {rel:.2e}")
     assert rel <= 1e-5
 
 

@@ -174,13 +174,13 @@ def test_vcycle_iterates_match_oracle(d, L, transfer, store):
     np.testing.assert_allclose(rr, hist, rtol=1e-6, atol=1e-12)
 
 
-def test_cfg2_full_size_cycles_and_solve():
+def test_checkerboard2d_level6_full_size_cycles_and_solve():
     """The 729^2-cell jumping-coefficient workload at full size: 4 cycles match
     the oracle's iterate; the solve reaches 1e-8 by the oracle's own FP64
     recomputation of the residual."""
     qmg = require_gpu()
-    announce("cfg2 full size")
-    p = W.cfg2(0)
+    announce("2D checkerboard level 6 full size")
+    p = W.checkerboard2d(0)
     g = _grid(qmg, p, "boxmg", "hier64")
     g.build()
     rr = g.vcycle(4)
@@ -264,7 +264,7 @@ def test_device_inputs_match_host_inputs():
     import torch
     qmg = require_gpu()
     announce("device-resident inputs")
-    p = W.cfg2(0, level=4)
+    p = W.checkerboard2d(0, level=4)
     res = []
     for dev in (False, True):
         g = qmg.Grid(p.dim, p.level, qmg.make_opts())
@@ -292,7 +292,7 @@ def test_profiling_and_graphs_leave_results_unchanged():
     neither the iterates nor the residual history."""
     qmg = require_gpu()
     announce("profiling strides and graph replay")
-    p = W.cfg2(0, level=4)
+    p = W.checkerboard2d(0, level=4)
     out = []
     for every, graphs in ((0, True), (0, False), (1, True), (3, False)):
         g = qmg.Grid(p.dim, p.level, qmg.make_opts(graphs=graphs))

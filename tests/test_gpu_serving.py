@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _requests(n, seed=3):
-    reqs = W.cfg4_stream(seed=seed, n_requests=n, levels_2d=(3, 5), levels_3d=(2, 3))
+    reqs = W.request_stream(seed=seed, n_requests=n, levels_2d=(3, 5), levels_3d=(2, 3))
     return [r.problem for r in reqs]
 
 

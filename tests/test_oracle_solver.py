@@ -48,7 +48,7 @@ def test_poisson_convergence_factor_h_independent():
 
 
 def test_boxmg_equals_geometric_for_constant_eps():
-    p = W.cfg1(0)
+    p = W.poisson2d_l4(0)
     b = O.rhs_from_f(p.f, 2, 4)
     Hg = O.build_hierarchy(p.eps, 2, 4, transfer="geometric")
     Hb = O.build_hierarchy(p.eps, 2, 4, transfer="boxmg")

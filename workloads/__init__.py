@@ -124,21 +124,23 @@ def material_jump(dim: int, level: int) -> Problem:
 
 
 # --------------------------------------------------------------------------
-# Named workloads.  cfg1: small 2D Poisson; cfg2: 2D jumping coefficient on
-# 729^2 cells; cfg4: a stream of mixed 2D/3D checkerboard requests.
+# Named workloads: a small 2D Poisson problem; the 2D jumping coefficient on
+# 729^2 cells; a stream of mixed 2D/3D checkerboard requests.
 # --------------------------------------------------------------------------
 
-def cfg1(seed: int = 0) -> Problem:
-    p = poisson(2, 4, seed, name="cfg1-poisson2d-L4")
-    return p
+def poisson2d_l4(seed: int = 0) -> Problem:
+    """2D Poisson, 81^2 cells (80^2 unknowns), eps = 1, f ~ U[-1, 1]."""
+    return poisson(2, 4, seed, name="poisson2d-L4")
 
 
-def cfg2(seed: int = 0, level: int = 6) -> Problem:
-    return random_checkerboard(2, level, seed, name=f"cfg2-jump2d-L{level}")
+def checkerboard2d(seed: int = 0, level: int = 6) -> Problem:
+    """2D jumping coefficient: random 9x9 checkerboard of {1, 1e4} on 3^level
+    cells per axis (729^2 by default), f ~ U[-1, 1]."""
+    return random_checkerboard(2, level, seed, name=f"checkerboard2d-L{level}")
 
 
 def jump3d(level: int, seed: int = 0) -> Problem:
-    """3D analogue of cfg2: random 9^3 boxes with values {1, 1e4}."""
+    """3D analogue of checkerboard2d: random 9^3 boxes with values {1, 1e4}."""
     return random_checkerboard(3, level, seed, name=f"jump3d-L{level}")
 
 
@@ -222,7 +224,7 @@ class AdaptiveProblem:
 
 
 def adaptive_balls(dim=3, base=3, level=5, n_balls=4, radius=0.2, seed=0, contrast_field=True,
-                   name="cfg3-adaptive-balls"):
+                   name="adaptive-balls3d"):
     """Refined to ``level`` within ``radius`` of ``n_balls`` seeded points,
     ``base`` everywhere; eps = exp(g) with g a unit-variance RFF field of
     correlation length 0.1 (M = 1024) at leaf-cell centres."""
@@ -235,7 +237,7 @@ def adaptive_balls(dim=3, base=3, level=5, n_balls=4, radius=0.2, seed=0, contra
 
 
 def adaptive_band(dim=3, base=3, level=6, seed=0, fraction=0.10, n_cubes=64, n_features=64,
-                  name="cfg5-adaptive-band"):
+                  name="adaptive-band3d"):
     """Refined to ``level`` around the zero set of an RFF level set phi
     (length 0.2): a cell is refined where |phi| < tau at one of its 3^d sample
     points or phi changes sign there, tau being the ``fraction`` quantile of
@@ -280,7 +282,7 @@ class Request:
     arrival: float       # seconds after stream start
 
 
-def cfg4_stream(seed: int = 0, n_requests: int = 256, rate: float = 100.0,
+def request_stream(seed: int = 0, n_requests: int = 256, rate: float = 100.0,
                 levels_2d=(3, 6), levels_3d=(2, 4)) -> List[Request]:
     """Served stream: each request draws d in {2,3} with p = 1/2, a level
     uniformly in ``levels_2d`` / ``levels_3d`` (inclusive), a contrast 10^c with
@@ -296,12 +298,12 @@ def cfg4_stream(seed: int = 0, n_requests: int = 256, rate: float = 100.0,
         sub_seed = int(rng.integers(0, 2 ** 31 - 1))
         t += float(rng.exponential(1.0 / rate))
         p = alternating_checkerboard(dim, level, 10.0 ** c, sub_seed,
-                                     name=f"cfg4-req{k}-d{dim}-L{level}")
+                                     name=f"stream-req{k}-d{dim}-L{level}")
         out.append(Request(p, t))
     return out
 
 
 __all__ = ["Problem", "Request", "poisson", "random_checkerboard",
-           "alternating_checkerboard", "sin_source", "cfg1", "cfg2", "jump3d",
-           "cfg4_stream", "ball_flags", "rff_field", "uniform_hash", "AdaptiveProblem",
-           "adaptive_balls", "adaptive_band"]
+           "alternating_checkerboard", "sin_source", "poisson2d_l4", "checkerboard2d", "jump3d",
+           "request_stream", "ball_flags", "rff_field", "uniform_hash", "AdaptiveProblem",
+           "adaptive_balls", "adaptive_band", "material_jump"]

@@ -39,6 +39,13 @@ Readings:
   paper's traversal pipelines this across half a grid sweep; the iterates
   per cycle are the same.  Damping is constant (omega on every level) or
   exponential (omega^(L - l + 1) on level l).
+* BPX cycles (Alg. 3) in the same unpipelined form: the paper's helper i
+  carries the level's Jacobi update at the c-points, which the level does not
+  apply; the finer level subtracts its prolongation at the other vertices.
+  Per cycle this gives e_l = d_l + P_l (e_{l-1} - I_l d_l), I_l the injection
+  to the c-points, so every vertex is updated by the coarsest level that
+  holds it and the finer levels add only their hierarchical surplus
+  d_l - P_l I_l d_l.
 * Block Jacobi readings: a patch is the 3^d block of vertices of one cell of
   the next coarser level; its iota-vertices are those with no coordinate
   divisible by 3.  One BJ(m) step first runs m lexicographic (x fastest)
@@ -234,15 +241,54 @@ def additive_cycle(H, u, b, damping="exp"):
     return u + e
 
 
-def solve_additive(H, b, tol=1e-8, max_cycles=1000, damping="exp", cycles=None):
-    """Additive cycles from zero until the relative residual reaches tol (or
-    exactly ``cycles``).  Returns (u, relres history)."""
+def cpoint_positions(d, l):
+    """Unknown index on level l of every interior vertex of level l-1 (its
+    c-point: lattice coordinates times 3), in level l-1 unknown order."""
+    mc, mf = 3 ** (l - 1) - 1, 3 ** l - 1
+    axes = [3 * np.arange(1, mc + 1) - 1] * d            # fine coordinate minus one
+    grids = np.meshgrid(*axes, indexing="ij")            # numpy order (z,) y, x
+    idx = np.zeros(grids[0].shape, dtype=np.int64)
+    for a in range(d):
+        idx += grids[d - 1 - a] * mf ** a
+    return idx.ravel()
+
+
+def bpx_cycle(H, u, b, damping="const"):
+    """One BPX cycle (Alg. 3, additive multigrid appendix) in its unpipelined
+    form (see module notes): as ``additive_cycle``, but level l contributes
+    only the hierarchical surplus of its Jacobi correction,
+    d_l - P_l (d_l at the c-points), so a vertex takes its correction from the
+    coarsest level that holds it."""
+    L, lc = H.L, H.lc
+    dt = H.dtype
+    r = {L: (b - H.A[L] @ u).astype(dt)}
+    for l in range(L, lc, -1):
+        r[l - 1] = (H.P[l].T @ r[l]).astype(dt)
+
+    def om(l):
+        return dt(H.omega ** (L - l + 1) if damping == "exp" else H.omega)
+
+    if H.coarse_lu is not None:
+        e = sla.lu_solve(H.coarse_lu, r[lc].astype(np.float64)).astype(dt)
+    else:
+        e = om(lc) * r[lc] / H.A[lc].diagonal()
+    for l in range(lc + 1, L + 1):
+        dl = om(l) * r[l] / H.A[l].diagonal()
+        e = dl + H.P[l] @ (e - dl[cpoint_positions(H.d, l)])
+    return u + e
+
+
+def solve_additive(H, b, tol=1e-8, max_cycles=1000, damping="exp", cycles=None, bpx=False):
+    """Additive (or, with ``bpx``, BPX) cycles from zero until the relative
+    residual reaches tol (or exactly ``cycles``).  Returns (u, relres
+    history)."""
     A = H.A[H.L]
     u = np.zeros(A.shape[0])
     hist = []
     n = cycles if cycles is not None else max_cycles
+    step = bpx_cycle if bpx else additive_cycle
     for _ in range(n):
-        u = additive_cycle(H, u, b, damping)
+        u = step(H, u, b, damping)
         hist.append(relres(A, u, b))
         if cycles is None and hist[-1] <= tol:
             break

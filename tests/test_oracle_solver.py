@@ -2,6 +2,7 @@
 solution, monotone energy error, h-independence, mixed precision."""
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import oracle as O
 import workloads as W
@@ -299,3 +300,112 @@ def test_additive_exponential_damping_converges():
     assert np.linalg.norm(u - ustar) <= 1e-8 * np.linalg.norm(ustar)
     _, hc = O.solve_additive(H, b, cycles=60, damping="const")
     assert hc[-1] > 1.0
+
+
+# ---------------------------------------------------------------------------
+# BPX cycles (Alg. 3, additive multigrid appendix)
+# ---------------------------------------------------------------------------
+
+def _injection_from_P(P):
+    """Injection to the coarse vertices found from P alone: the fine row of
+    coarse vertex j is the one whose only entry is P[i, j] = 1."""
+    P = sp.csr_matrix(P)
+    nnz = np.diff(P.indptr)
+    I = np.zeros((P.shape[1], P.shape[0]))
+    for i in np.nonzero(nnz == 1)[0]:
+        j = P.indices[P.indptr[i]]
+        if abs(P.data[P.indptr[i]] - 1.0) < 1e-12:
+            I[j, i] = 1.0
+    assert (I.sum(axis=1) == 1).all()
+    return I
+
+
+@pytest.mark.parametrize("d,l", [(2, 2), (2, 3), (3, 2)])
+def test_cpoint_positions_are_the_unit_rows_of_P(d, l):
+    """The c-point of every coarse vertex is the fine row of P that injects it."""
+    P = O.dlinear_P(d, l)
+    I = _injection_from_P(P)
+    np.testing.assert_array_equal(np.argmax(I, axis=1), O.cpoint_positions(d, l))
+
+
+def test_bpx_two_level_closed_form():
+    """Two levels with an exact coarse solve: the fine level adds only the
+    surplus (I - P I_c) omega D^-1 r of its Jacobi step to P A_c^-1 P^T r."""
+    p = W.random_checkerboard(2, 2, seed=3, values=(1.0, 20.0), blocks=3)
+    H = O.build_hierarchy(p.eps, 2, 2, transfer="galerkin")
+    assert H.lc == 1 and H.coarse_lu is not None
+    b = O.rhs_from_f(p.f, 2, 2)
+    u0 = np.random.default_rng(1).normal(size=b.shape)
+    A = H.A[2].toarray()
+    P = H.P[2].toarray()
+    Ic = _injection_from_P(P)
+    r = b - A @ u0
+    d = 0.6 * r / np.diag(A)
+    want = u0 + d - P @ (Ic @ d) + P @ np.linalg.solve(H.A[1].toarray(), P.T @ r)
+    np.testing.assert_allclose(O.bpx_cycle(H, u0, b), want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("damping", ["const", "exp"])
+def test_bpx_operator_is_the_level_sum(damping):
+    """Three levels: u -> bpx_cycle(0, b) is the map
+    sum_l P_{L<-l} (I - P_l I_l) omega_l D_l^-1 P_{L<-l}^T plus the coarsest
+    term, assembled here from dense matrices level by level."""
+    p = W.random_checkerboard(2, 3, seed=2, values=(1.0, 10.0), blocks=3)
+    H = O.build_hierarchy(p.eps, 2, 3, transfer="boxmg", lc=1)
+    L, lc = 3, H.lc
+    assert lc == 1
+    n = H.A[L].shape[0]
+    Pc = {L: np.eye(n)}                     # P_{L<-l}
+    for l in range(L, lc, -1):
+        Pc[l - 1] = Pc[l] @ H.P[l].toarray()
+    def om(l):
+        return 0.6 ** (L - l + 1) if damping == "exp" else 0.6
+    if H.coarse_lu is not None:
+        want = Pc[lc] @ np.linalg.solve(H.A[lc].toarray(), Pc[lc].T)
+    else:
+        want = Pc[lc] @ np.diag(om(lc) / H.A[lc].diagonal()) @ Pc[lc].T
+    for l in range(lc + 1, L + 1):
+        P = H.P[l].toarray()
+        S = np.eye(P.shape[0]) - P @ _injection_from_P(P)
+        want += Pc[l] @ S @ np.diag(om(l) / H.A[l].diagonal()) @ Pc[l].T
+    B = np.column_stack([O.bpx_cycle(H, np.zeros(n), np.eye(n)[:, j], damping) for j in range(n)])
+    np.testing.assert_allclose(B, want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+def test_bpx_coarse_vertices_take_the_coarsest_correction():
+    """Every vertex is updated by the coarsest level holding it: at the
+    vertices of the coarsest level the fine correction equals the coarse
+    solve of the restricted residual (the additive cycle adds the finer
+    levels' Jacobi steps there too)."""
+    p = W.random_checkerboard(2, 4, seed=5, values=(1.0, 100.0), blocks=9)
+    H = O.build_hierarchy(p.eps, 2, 4, transfer="boxmg")
+    b = O.rhs_from_f(p.f, 2, 4)
+    L, lc = H.L, H.lc
+    assert H.coarse_lu is not None and lc < L - 1
+    e = O.bpx_cycle(H, np.zeros_like(b), b)
+    rc, pos = b, np.arange(len(b))
+    for l in range(L, lc, -1):
+        rc = H.P[l].T @ rc
+        pos = pos[O.cpoint_positions(2, l)]
+    ec = np.linalg.solve(H.A[lc].toarray(), rc)
+    np.testing.assert_allclose(e[pos], ec, rtol=0, atol=1e-12 * np.abs(ec).max())
+    ea = O.additive_cycle(H, np.zeros_like(b), b, "const")
+    assert np.abs(ea[pos] - ec).max() > 1e-3 * np.abs(ec).max()
+
+
+def test_bpx_constant_omega_converges():
+    """omega = 0.8 on every level: BPX converges to the direct solution on
+    the sine setup, where the additive cycle with the same damping diverges,
+    and its cycle count grows only mildly from level 3 to level 5."""
+    counts = []
+    for L in (3, 5):
+        p = W.sin_source(2, L)
+        b = O.rhs_from_f(p.f, 2, L)
+        H = O.build_hierarchy(p.eps, 2, L, transfer="geometric", omega=0.8)
+        u, h = O.solve_additive(H, b, tol=1e-10, max_cycles=200, damping="const", bpx=True)
+        assert h[-1] <= 1e-10
+        counts.append(len(h))
+        if L == 5:
+            ustar = O.direct_solve(H.A[L], b)
+            assert np.linalg.norm(u - ustar) <= 1e-8 * np.linalg.norm(ustar)
+    assert counts[1] <= 1.5 * counts[0]

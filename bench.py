@@ -143,7 +143,8 @@ def time_build(g, eps, f, n=20):
 
 def other_workloads(qmg, n):
     """The 2D Poisson workload (level 4, FP64 plain store, geometric transfer,
-    to 1e-10) and the 3D four-ball adaptive workload (base level 3, level 5,
+    to 1e-10), the 2D sine workload under additive and BPX cycles, and the
+    3D four-ball adaptive workload (base level 3, level 5,
     BoxMG + Galerkin, BF16 deltas and FP32 inner cycles under FP64 composite
     defect correction, to 1e-8), inputs generated at the library's own
     unknown and cell coordinates."""
@@ -168,6 +169,13 @@ def other_workloads(qmg, n):
                                     workload="2D sine source (exact solution prod sin(pi x_i)), 729^2 cells; "
                                              "additive cycles with exponential damping, omega 0.8, "
                                              "geometric transfer, to 1e-8")
+    g.close()
+    g = qmg.Grid(p.dim, p.level, qmg.make_opts("geometric", "hier64", omega=0.8, cycle="bpx",
+                                               damping="const"))
+    r = time_solves(g, eps, f, 1e-8, max(5, n // 5), warmup=1)
+    out["bpx2d_sin_L6"] = dict(r, unknowns=p.n_unknowns,
+                               workload="2D sine source, 729^2 cells; BPX cycles, omega 0.8 on every "
+                                        "level, geometric transfer, to 1e-8")
     g.close()
     P = W.adaptive_balls()
     g = qmg.Grid(P.dim, P.level, qmg.make_opts("boxmg", "bf16", check_definite=False),

@@ -147,9 +147,15 @@ typedef struct {
                           one damped Jacobi step from zero (the coarsest an
                           exact solve when it is direct) and the prolongated
                           sum of the corrections is added to the fine
-                          iterate.  Jacobi smoother, regular grids only      */
-  int damping;         /* additive cycles: QMG_DAMP_EXP (default), omega^(L-l+1)
-                          on level l; QMG_DAMP_CONST, omega on every level   */
+                          iterate.  QMG_CYCLE_BPX: BPX cycles (Alg. 3,
+                          unpipelined): as additive, but a level keeps only
+                          the hierarchical surplus d_l - P_l (d_l at its
+                          c-points) of its Jacobi step, so every vertex is
+                          corrected by the coarsest level that holds it.
+                          Both: Jacobi smoother, regular grids only          */
+  int damping;         /* additive and BPX cycles: QMG_DAMP_EXP (default),
+                          omega^(L-l+1) on level l; QMG_DAMP_CONST, omega on
+                          every level (the paper's choice for BPX)           */
 } qmg_solver_opts;
 
 typedef struct {
@@ -262,7 +268,7 @@ int qmg_get_operator(const qmg_grid_t* grid, int level, double* stencils);
 int qmg_get_prolongation(const qmg_grid_t* grid, int level, double* weights);
 
 enum { QMG_SMOOTH_JACOBI = 0, QMG_SMOOTH_BLOCK = 1 };
-enum { QMG_CYCLE_MULT = 0, QMG_CYCLE_ADD = 1 };
+enum { QMG_CYCLE_MULT = 0, QMG_CYCLE_ADD = 1, QMG_CYCLE_BPX = 2 };
 enum { QMG_DAMP_EXP = 0, QMG_DAMP_CONST = 1 };
 
 enum {

@@ -213,10 +213,11 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
   if (o->smoother != QMG_SMOOTH_JACOBI && o->smoother != QMG_SMOOTH_BLOCK) throw ApiError(QMG_EINVAL, "bad smoother");
   if (o->smoother == QMG_SMOOTH_BLOCK && (o->bj_sweeps < 1 || o->bj_sweeps > 64))
     throw ApiError(QMG_EINVAL, "bj_sweeps must lie in 1..64");
-  if (o->cycle != QMG_CYCLE_MULT && o->cycle != QMG_CYCLE_ADD) throw ApiError(QMG_EINVAL, "bad cycle");
+  if (o->cycle != QMG_CYCLE_MULT && o->cycle != QMG_CYCLE_ADD && o->cycle != QMG_CYCLE_BPX)
+    throw ApiError(QMG_EINVAL, "bad cycle");
   if (o->damping != QMG_DAMP_EXP && o->damping != QMG_DAMP_CONST) throw ApiError(QMG_EINVAL, "bad damping");
-  if (o->cycle == QMG_CYCLE_ADD && o->smoother != QMG_SMOOTH_JACOBI)
-    throw ApiError(QMG_EINVAL, "additive cycles take one Jacobi step per level");
+  if (o->cycle != QMG_CYCLE_MULT && o->smoother != QMG_SMOOTH_JACOBI)
+    throw ApiError(QMG_EINVAL, "additive and BPX cycles take one Jacobi step per level");
   const bool adaptive = desc->base_level != 0 && desc->base_level != desc->max_level;
   if (adaptive) {
     if (desc->base_level < 1 || desc->base_level > desc->max_level)
@@ -225,7 +226,7 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
     if (o->coarsest_level > desc->base_level)
       throw ApiError(QMG_EINVAL, "coarsest_level must not exceed base_level");
     if (o->smoother == QMG_SMOOTH_BLOCK) throw ApiError(QMG_EINVAL, "block Jacobi runs on regular grids");
-    if (o->cycle == QMG_CYCLE_ADD) throw ApiError(QMG_EINVAL, "additive cycles run on regular grids");
+    if (o->cycle != QMG_CYCLE_MULT) throw ApiError(QMG_EINVAL, "additive and BPX cycles run on regular grids");
   }
 }
 
@@ -742,8 +743,8 @@ void composite_state(qmg_grid_t* g) {
 
 int64_t updates_per_cycle(const qmg_grid_t* g) {
   int64_t s = 0;
-  // additive cycles: one Jacobi step per level
-  const int sw = g->opts.cycle == QMG_CYCLE_ADD ? 1 : g->opts.mu_pre + g->opts.mu_post;
+  // additive and BPX cycles: one Jacobi step per level
+  const int sw = g->opts.cycle != QMG_CYCLE_MULT ? 1 : g->opts.mu_pre + g->opts.mu_post;
   for (int l = g->lc + 1; l <= g->Lmax; ++l)
     s += (int64_t)sw * (l > g->lb ? g->hl[l].n_active : n_interior(g->lv[l].L));
   if (!g->coarse_direct) s += (int64_t)sw * n_interior(g->lv[g->lc].L);
@@ -808,7 +809,8 @@ double finest_residual_norm(qmg_grid_t* g) {
 // Additive cycle (Alg. 2, unpipelined): r_L = b - A u restricted down to every
 // level, one damped Jacobi step from zero per level (exact on a direct
 // coarsest level), corrections summed coarse to fine, u += e_L.  The finest
-// level's own correction is the Jacobi sweep from u.
+// level's own correction is the Jacobi sweep from u.  BPX (Alg. 3) sums
+// e_l = d_l + P (e_{l-1} - d_l at the c-points) instead.
 template <typename T>
 void additive_cycle(qmg_grid_t* g, bool zero_init) {
   const int L = g->Lmax, lc = g->lc;
@@ -826,20 +828,26 @@ void additive_cycle(qmg_grid_t* g, bool zero_init) {
   else
     launch_stencil<T>(C.L, 1, (const T*)C.u, (const T*)C.r, (T*)C.u, eps_of<T>(C), C.A, om(lc), nullptr, nullptr,
                       S(g));
+  const bool bpx = g->opts.cycle == QMG_CYCLE_BPX;
   for (int l = lc + 1; l < L; ++l) {
     LevelBuf& B = g->lv[l];
+    LevelBuf& C1 = g->lv[l - 1];
     launch_stencil<T>(B.L, 1, (const T*)B.u, (const T*)B.r, (T*)B.u, eps_of<T>(B), B.A, om(l), nullptr, nullptr,
                       S(g));
-    launch_prolong<T>(B.L, g->lv[l - 1].L, (const T*)g->lv[l - 1].u, (T*)B.u, B.P, S(g));
+    // BPX: the coarser correction replaces this level's step at the c-points
+    if (bpx) launch_cpoint_sub<T>(B.L, C1.L, (const T*)B.u, (const T*)nullptr, (T*)C1.u, S(g));
+    launch_prolong<T>(B.L, C1.L, (const T*)C1.u, (T*)B.u, B.P, S(g));
   }
   launch_stencil<T>(F.L, 0, (const T*)F.u, (const T*)F.b, (T*)F.t, eps_of<T>(F), F.A, om(L), nullptr, nullptr,
                     S(g));
+  // the finest step is t - u
+  if (bpx) launch_cpoint_sub<T>(F.L, g->lv[L - 1].L, (const T*)F.t, (const T*)F.u, (T*)g->lv[L - 1].u, S(g));
   launch_prolong<T>(F.L, g->lv[L - 1].L, (const T*)g->lv[L - 1].u, (T*)F.t, F.P, S(g));
   std::swap(F.u, F.t);
 }
 
 bool one_cycle(qmg_grid_t* g) {
-  if (g->opts.cycle == QMG_CYCLE_ADD) {
+  if (g->opts.cycle != QMG_CYCLE_MULT) {
     if (!g->mixed) {
       additive_cycle<double>(g, false);
       return false;
@@ -883,7 +891,7 @@ void drop_graph(qmg_grid_t* g) {
 // it started from, i.e. an even number of sweeps per level.
 bool graph_usable(const qmg_grid_t* g) {
   if (g->prof_every > 0 || !g->opts.use_graphs) return false;
-  if (g->opts.cycle == QMG_CYCLE_ADD) return false;  // one buffer swap per cycle on the finest level
+  if (g->opts.cycle != QMG_CYCLE_MULT) return false;  // one buffer swap per cycle on the finest level
   const int mu = g->opts.mu_pre, nu = g->opts.mu_post;
   // single sweeps (3D, coarsest level, block Jacobi) and fused passes of two (2D)
   if (g->opts.smoother != QMG_SMOOTH_JACOBI) return (mu + nu) % 2 == 0;

@@ -9,6 +9,7 @@
 // coefficients (rediscretisation on the fly) plus the stored delta, or read
 // from the plain FP64 store.
 #include <hip/hip_ext.h>
+#include <stdexcept>
 
 #include "level_ops.hpp"
 
@@ -381,6 +382,26 @@ __global__ void k_pack(Lat L, const double* __restrict__ packed_in, const T* __r
     packed_out[t] = (double)lat_in[v];
 }
 
+// BPX surplus (Alg. 3): the coarse correction at every interior coarse vertex V
+// loses the fine level's Jacobi step at its c-point 3V, taken as xf - yf there
+// (yf may be null: the step is xf itself).
+template <int D, typename T>
+__global__ void k_cpoint_sub(Lat Lf, Lat Lc, const T* __restrict__ xf, const T* __restrict__ yf,
+                             T* __restrict__ ec) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int m = Lc.n - 1;
+  const int64_t total = (D == 3) ? (int64_t)m * m * m : (int64_t)m * m;
+  if (t >= total) return;
+  const int i = (int)(t % m) + 1;
+  const int j = (int)((t / m) % m) + 1;
+  const int k = (D == 3) ? (int)(t / ((int64_t)m * m)) + 1 : 0;
+  const int64_t vc = i + (int64_t)j * Lc.pitch + (int64_t)k * Lc.plane;
+  const int64_t vf = 3 * (i + (int64_t)j * Lf.pitch + (int64_t)k * Lf.plane);
+  T step = xf[vf];
+  if (yf) step -= yf[vf];
+  ec[vc] -= step;
+}
+
 template <typename T>
 __global__ void k_coarse_solve(Lat L, const double* __restrict__ Ainv, int nc,
                                const T* __restrict__ b, T* __restrict__ u) {
@@ -590,6 +611,18 @@ template void launch_restrict<double>(const Lat&, const Lat&, const double*, dou
 template void launch_restrict<float>(const Lat&, const Lat&, const float*, float*, const Store&, hipStream_t);
 template void launch_prolong<double>(const Lat&, const Lat&, const double*, double*, const Store&, hipStream_t);
 template void launch_prolong<float>(const Lat&, const Lat&, const float*, float*, const Store&, hipStream_t);
+
+template <typename T>
+void launch_cpoint_sub(const Lat& Lf, const Lat& Lc, const T* xf, const T* yf, T* ec, hipStream_t s) {
+  const int64_t m = Lc.n - 1, tot = (Lc.d == 3) ? m * m * m : m * m;
+  if (tot <= 0) return;
+  if (Lf.n != 3 * Lc.n || Lf.d != Lc.d) throw std::runtime_error("launch_cpoint_sub: levels do not nest");
+  if (Lf.d == 2) hipLaunchKernelGGL((k_cpoint_sub<2, T>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, Lf, Lc, xf, yf, ec);
+  else hipLaunchKernelGGL((k_cpoint_sub<3, T>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, Lf, Lc, xf, yf, ec);
+  QMG_HIP(hipGetLastError());
+}
+template void launch_cpoint_sub<double>(const Lat&, const Lat&, const double*, const double*, double*, hipStream_t);
+template void launch_cpoint_sub<float>(const Lat&, const Lat&, const float*, const float*, float*, hipStream_t);
 
 void launch_axpy_mixed(const Lat& L, double* x, const float* e, hipStream_t s) {
   const dim3 g = tile_grid(L), bl(TX, TY, 1);

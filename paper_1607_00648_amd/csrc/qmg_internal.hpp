@@ -128,6 +128,10 @@ template <typename T>
 void launch_prolong(const Lat& Lf, const Lat& Lc, const T* ec, T* uf, const Store& P, hipStream_t s);
 
 // x64 += e32 on the interior.
+// ec[V] -= xf[3V] - yf[3V] (yf may be null) at every interior coarse vertex V:
+// the BPX surplus of a level's Jacobi step
+template <typename T>
+void launch_cpoint_sub(const Lat& Lf, const Lat& Lc, const T* xf, const T* yf, T* ec, hipStream_t s);
 void launch_axpy_mixed(const Lat& L, double* x, const float* e, hipStream_t s);
 
 // Conversions between iterate types and between packed unknown vectors and

@@ -247,6 +247,10 @@ def test_raised_coarsest_level_and_errors():
     g.close()
     with pytest.raises(qmg.QmgError):
         qmg.Grid(2, 4, qmg.make_opts(omega=2.5))
+    with pytest.raises(qmg.QmgError):      # BPX takes one Jacobi step per level
+        qmg.Grid(2, 4, qmg.make_opts(cycle="bpx", smoother="block"))
+    with pytest.raises(qmg.QmgError):
+        qmg.Grid(2, 4, qmg.make_opts(cycle=3))
     g = qmg.Grid(2, 3, qmg.make_opts())
     with pytest.raises(qmg.QmgError):      # solve before build
         g.solve()
@@ -633,4 +637,51 @@ def test_additive_solve_sine_setup(store):
     assert np.linalg.norm(b - H.A[5] @ u) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)
     if store == "hier64":
         _, hist = O.solve_additive(H, b, tol=1e-8, max_cycles=600)
+        assert abs(rep["cycles"] - len(hist)) <= 1   # the batched loop may stop one cycle late
+
+
+# ---------------------------------------------------------------------------
+# BPX cycles
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,L,transfer,store,omega,damping", [
+    (2, 4, "geometric", "hier64", 0.8, "const"), (2, 5, "boxmg", "hier64", 0.6, "exp"),
+    (3, 3, "galerkin", "hier64", 0.8, "const"), (2, 5, "boxmg", "plain64", 0.8, "const")])
+def test_bpx_cycles_match_oracle(d, L, transfer, store, omega, damping):
+    """BPX cycles (each level adds only the hierarchical surplus of its Jacobi
+    step): residual history and iterate against the oracle."""
+    qmg = require_gpu()
+    announce(f"bpx cycles d={d} L={L} {transfer} {store} omega={omega} {damping}")
+    p = W.random_checkerboard(d, L, seed=17, values=(1.0, 1e2), blocks=9 if L > 3 else 3)
+    g = _grid(qmg, p, transfer, store, omega=omega, cycle="bpx", damping=damping, check_definite=False)
+    g.build()
+    k = 6
+    rr = g.vcycle(k)
+    u = g.solution()
+    g.close()
+    H = O.build_hierarchy(p.eps, d, L, transfer=transfer, omega=omega, check_definite=False)
+    uo, hist = O.solve_additive(H, O.rhs_from_f(p.f, d, L), damping=damping, cycles=k, bpx=True)
+    np.testing.assert_allclose(rr, hist, rtol=1e-10, atol=1e-14)
+    assert np.abs(u - uo).max() <= 1e-11 * np.abs(uo).max()
+
+
+@pytest.mark.parametrize("store", ["hier64", "bf16"])
+def test_bpx_solve_sine_constant_omega(store):
+    """The sin setup with omega = 0.8 on every level (where the additive cycle
+    diverges) solved to 1e-8 by BPX cycles, in FP64 and with FP32 inner
+    cycles; the FP64 run takes the oracle's cycle count."""
+    qmg = require_gpu()
+    announce(f"bpx solve sin {store}")
+    p = W.sin_source(2, 5)
+    g = _grid(qmg, p, "geometric", store, omega=0.8, cycle="bpx", damping="const")
+    g.build()
+    rep, _ = g.solve(1e-8, 600)
+    u = g.solution()
+    g.close()
+    assert rep["status"] == "QMG_OK"
+    H = O.build_hierarchy(p.eps, 2, 5, transfer="geometric", omega=0.8)
+    b = O.rhs_from_f(p.f, 2, 5)
+    assert np.linalg.norm(b - H.A[5] @ u) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)
+    if store == "hier64":
+        _, hist = O.solve_additive(H, b, tol=1e-8, max_cycles=600, damping="const", bpx=True)
         assert abs(rep["cycles"] - len(hist)) <= 1   # the batched loop may stop one cycle late

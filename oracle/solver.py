@@ -75,7 +75,7 @@ import scipy.sparse.linalg as spla
 from .fem import (geometric_stencil, stencil_to_csr, csr_to_stencil, coarsen_eps)
 from .transfer import dlinear_P, boxmg_P
 from .galerkin import rap, definiteness_violations
-from .store import quantise, delta_zero, EPS_ZERO
+from .store import quantise, delta_zero, EPS_ZERO, fp16_exponent, bpa_value, bpa_encode, BPA_WIDTHS
 
 COARSE_DIRECT_MAX = 1024
 
@@ -344,31 +344,56 @@ def direct_solve(A, b):
     return spla.spsolve(sp.csc_matrix(A), b)
 
 
-def quantised_hierarchy(H, fmt):
-    """Inner FP32 hierarchy: A_geom(eps_l) + q(A_hat_l) and P_dlin + q(P_hat_l),
-    quantised per vertex as in ``store``; the finest operator is the geometric
-    one (its delta is zero by construction).  Parity unpinned beyond the
-    bound of the outer loop: used only for error-budget studies."""
+def quantised_hierarchy(H, fmt, eps_mf=None):
+    """Hierarchy rebuilt from quantised hierarchical deltas:
+    A_geom(eps_l) + q(A_hat_l) and P_dlin + q(P_hat_l), quantised per vertex as
+    in ``store``; the finest operator is the geometric one (its delta is zero
+    by construction).  For the IEEE formats it is the FP32 inner hierarchy of
+    the mixed loop (parity unpinned beyond the bound of the outer loop).  For
+    "bpa" (with ``eps_mf``) it is an FP64 hierarchy whose coarsest level keeps
+    its full operator, the form in which the paper's codec is solved with."""
     d = H.d
+    bpa = fmt == "bpa"
+    if bpa and not (eps_mf is not None and eps_mf > 0):
+        raise ValueError("bpa needs eps_mf > 0")
+    dt = np.float64 if bpa else np.float32
     A32, P32 = {}, {}
     for l, Al in H.A.items():
         G = geometric_stencil(H.eps[l], d, l)
         if l == H.L:
-            A32[l] = stencil_to_csr(G, d, l).astype(np.float32)
+            A32[l] = stencil_to_csr(G, d, l).astype(dt)
+            continue
+        if bpa and l == H.lc:
+            A32[l] = Al.astype(dt)
             continue
         S = csr_to_stencil(Al, d, l)
         dlt = S - G
-        q = quantise(dlt, fmt, axis=0)
-        q[:, delta_zero(dlt, G)] = 0.0
-        A32[l] = stencil_to_csr(G + q, d, l).astype(np.float32)
+        if bpa:
+            q = bpa_encode(dlt, eps_mf, axis=0)[0]
+        else:
+            q = quantise(dlt, fmt, axis=0)
+            q[:, delta_zero(dlt, G)] = 0.0
+        A32[l] = stencil_to_csr(G + q, d, l).astype(dt)
     for l, Pl in H.P.items():
         Pd = dlinear_P(d, l)
         dP = sp.csr_matrix(Pl - Pd)
         dP.sum_duplicates()
         rows = np.repeat(np.arange(dP.shape[0]), np.diff(dP.indptr))
         vals = dP.data.copy()
+        if bpa:
+            width = np.full(dP.shape[0], -1)
+            out = np.zeros_like(vals)
+            for w in BPA_WIDTHS:
+                qv = bpa_value(vals, w)[0]
+                err = np.zeros(dP.shape[0])
+                np.maximum.at(err, rows, np.abs(qv - vals))
+                ok = (err <= eps_mf) & (width < 0)
+                out[ok[rows]] = qv[ok[rows]]
+                width[ok] = w
+            q = sp.csr_matrix((out, dP.indices, dP.indptr), shape=dP.shape)
+            P32[l] = (Pd + q).astype(dt).tocsr()
+            continue
         if fmt == "fp16":
-            from .store import fp16_exponent
             mx = np.zeros(dP.shape[0])
             np.maximum.at(mx, rows, np.abs(vals))
             e = fp16_exponent(mx)
@@ -383,9 +408,9 @@ def quantised_hierarchy(H, fmt):
         zero = mxd <= EPS_ZERO * mxp
         vals[zero[rows]] = 0.0
         q = sp.csr_matrix((vals, dP.indices, dP.indptr), shape=dP.shape)
-        P32[l] = (Pd + q).astype(np.float32).tocsr()
+        P32[l] = (Pd + q).astype(dt).tocsr()
     Hq = Hierarchy(d, H.L, H.lc, H.transfer, A32, P32, H.eps, H.omega, H.mu_pre, H.mu_post,
-                   H.coarse_lu, np.float32, H.smoother, H.bj_sweeps)
+                   H.coarse_lu, dt, H.smoother, H.bj_sweeps)
     return Hq
 
 

@@ -16,6 +16,15 @@ decisions:
   integer such that max|delta| <= 2^(15+e); the scaled FP64 value delta/2^e is
   rounded to FP32 and then to FP16 (nearest-even).  The paper stores one exponent
   byte per entry (m * 2^e); one exponent per stencil is a reading of the paper.
+* bpa (Sect. 4, the paper's own codec): every entry x of a vertex's delta is
+  stored as m * 2^e, e in one signed byte and m a signed integer of bpa - 1
+  bytes; per vertex bpa is the smallest of {0, 2, 3, ..., 8} for which every
+  entry satisfies |m 2^e - x| <= eps_mf (bpa 0: the vertex stores nothing and
+  its delta counts as zero).  Readings: m is two's complement, so
+  |m| <= 2^(8(bpa-1)-1) - 1; e is the smallest integer for which the rounded
+  (nearest-even) m = rint(x / 2^e) fits; an entry whose e would fall below
+  -128 is stored as zero (its value is below 2^-72); the set {0, 2, ..., 8}
+  has eight members, three bits per operator.
 * A vertex's delta counts as zero when max|delta| <= EPS_ZERO * max|A_geom row|
   with EPS_ZERO = 2^-40 (about 9e-13).  Galerkin/BoxMG reproduce the
   rediscretisation only to rounding for constant coefficients, and that
@@ -76,6 +85,45 @@ def quantise(delta, fmt, axis=0):
         q = scaled.astype(np.float32).astype(np.float16).astype(np.float64)
         return q * scale
     raise ValueError(fmt)
+
+
+BPA_WIDTHS = (0, 2, 3, 4, 5, 6, 7, 8)
+
+
+def bpa_value(x, bpa):
+    """f_bpa(x) = m 2^e elementwise (see module notes); also returns e and m."""
+    x = np.asarray(x, dtype=np.float64)
+    if bpa == 0:
+        z = np.zeros(x.shape, dtype=np.int64)
+        return np.zeros_like(x), z, z
+    bits = 8 * (bpa - 1) - 1                  # magnitude bits of m
+    mmax = 2.0 ** bits - 1.0
+    _, E = np.frexp(np.abs(x))                # |x| = f 2^E, f in [0.5, 1)
+    e = E.astype(np.int64) - bits             # |x| / 2^e in [2^(bits-1), 2^bits)
+    m = np.rint(np.ldexp(x, -e))
+    over = np.abs(m) > mmax                   # rounding reached 2^bits
+    e = np.where(over, e + 1, e)
+    m = np.rint(np.ldexp(x, -e))
+    zero = (x == 0.0) | (e < -128)
+    e = np.where(zero, 0, e)
+    m = np.where(zero, 0.0, m)
+    if np.any(e > 127):
+        raise ValueError("delta too large for a one-byte exponent")
+    return np.ldexp(m, e), e, m.astype(np.int64)
+
+
+def bpa_encode(delta, eps_mf, axis=0):
+    """Per vertex (entries along ``axis``) the smallest bpa whose values are
+    all within eps_mf of the delta; returns (decoded values, bpa per vertex)."""
+    delta = np.moveaxis(np.asarray(delta, dtype=np.float64), axis, 0)
+    out = np.zeros_like(delta)
+    width = np.full(delta.shape[1:], -1, dtype=np.int64)
+    for w in BPA_WIDTHS:
+        q = bpa_value(delta, w)[0]
+        ok = (np.max(np.abs(q - delta), axis=0) <= eps_mf) & (width < 0)
+        out[:, ok] = q[:, ok]
+        width[ok] = w
+    return np.moveaxis(out, 0, axis), width
 
 
 def P_to_parent_weights(P, d, level_f):

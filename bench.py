@@ -294,7 +294,7 @@ def main():
     ap.add_argument("--sweep", default="2:8",
                     help="roofline sweep on larger regular grids, dim:level comma list ('' for none): "
                          "the same step for the hier64, plain64 and bf16 stores")
-    ap.add_argument("--variants", default="plain64,bf16",
+    ap.add_argument("--variants", default="plain64,bf16,bpa",
                     help="extra stores timed on the same workload (comma list, '' for none)")
     ap.add_argument("--others", type=int, default=50, metavar="N",
                     help="repeated solves of the 2D Poisson and 3D adaptive workloads (0: skip)")

@@ -83,13 +83,20 @@ enum {
  * and from the d-linear P, dropping all-zero 64-vertex blocks.  PLAIN_FP64 and
  * HIER_FP64 iterate in FP64; the reduced-precision stores iterate in FP32 inside
  * an FP64 defect-correction loop (FP64 residual on the finest level, FP64
- * Galerkin construction and FP64 coarsest solve). */
+ * Galerkin construction and FP64 coarsest solve).  HIER_BPA is the paper's
+ * codec: every delta entry is m 2^e (one exponent byte, bpa - 1 mantissa
+ * bytes), per vertex the smallest bpa in {0, 2, ..., 8} that keeps every entry
+ * within eps_mf; a 64-vertex block is stored at the largest bpa of its
+ * vertices (all-zero blocks dropped); FP64 iterates.  Regular grids only; the
+ * workspace reserves the widest payload, qmg_solve_report.bytes_operators
+ * reports what the codec used. */
 enum {
   QMG_PLAIN_FP64 = 0,
   QMG_HIER_FP64 = 1,
   QMG_HIER_FP32 = 2,
   QMG_HIER_FP16 = 3,   /* FP16 with one power-of-two scale per vertex */
-  QMG_HIER_BF16 = 4
+  QMG_HIER_BF16 = 4,
+  QMG_HIER_BPA = 5
 };
 
 typedef struct {
@@ -105,7 +112,7 @@ typedef struct {
 
 typedef struct {
   int transfer;        /* QMG_GEOMETRIC | QMG_GALERKIN_DLINEAR | QMG_BOXMG     */
-  int store;           /* QMG_PLAIN_FP64 ... QMG_HIER_BF16                    */
+  int store;           /* QMG_PLAIN_FP64 ... QMG_HIER_BPA                     */
   int mu_pre, mu_post; /* smoothing steps per level, each >= 1 (Alg. 1)       */
   double omega;        /* Jacobi damping in (0, 2)                           */
   int coarsest_level;  /* requested coarsest level, 1 <= lc < L (<= base)    */
@@ -156,6 +163,8 @@ typedef struct {
   int damping;         /* additive and BPX cycles: QMG_DAMP_EXP (default),
                           omega^(L-l+1) on level l; QMG_DAMP_CONST, omega on
                           every level (the paper's choice for BPX)           */
+  double eps_mf;       /* QMG_HIER_BPA: largest coding error per entry, in
+                          (0, 1]; default 1e-8                               */
 } qmg_solver_opts;
 
 typedef struct {

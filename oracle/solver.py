@@ -350,8 +350,9 @@ def quantised_hierarchy(H, fmt, eps_mf=None):
     in ``store``; the finest operator is the geometric one (its delta is zero
     by construction).  For the IEEE formats it is the FP32 inner hierarchy of
     the mixed loop (parity unpinned beyond the bound of the outer loop).  For
-    "bpa" (with ``eps_mf``) it is an FP64 hierarchy whose coarsest level keeps
-    its full operator, the form in which the paper's codec is solved with."""
+    "bpa" (with ``eps_mf``) it is an FP64 hierarchy, the form in which the
+    paper solves with its codec.  An exact coarsest-level solve keeps the
+    factorisation of the full operator."""
     d = H.d
     bpa = fmt == "bpa"
     if bpa and not (eps_mf is not None and eps_mf > 0):
@@ -362,9 +363,6 @@ def quantised_hierarchy(H, fmt, eps_mf=None):
         G = geometric_stencil(H.eps[l], d, l)
         if l == H.L:
             A32[l] = stencil_to_csr(G, d, l).astype(dt)
-            continue
-        if bpa and l == H.lc:
-            A32[l] = Al.astype(dt)
             continue
         S = csr_to_stencil(Al, d, l)
         dlt = S - G

@@ -27,13 +27,16 @@ int ipow(int b, int e) {
   return r;
 }
 
-size_t fmt_size(int fmt) { return fmt == F64 ? 8 : fmt == F32 ? 4 : 2; }
+// bytes per stored entry (BPA: the widest block, one exponent byte and seven
+// mantissa bytes)
+size_t fmt_size(int fmt) { return (fmt == F64 || fmt == BPA) ? 8 : fmt == F32 ? 4 : 2; }
 
 int store_fmt(int store) {
   switch (store) {
     case QMG_HIER_FP32: return F32;
     case QMG_HIER_FP16: return F16;
     case QMG_HIER_BF16: return BF16;
+    case QMG_HIER_BPA: return BPA;
     default: return F64;
   }
 }
@@ -55,6 +58,8 @@ struct LevelBuf {
   int32_t* Pblk = nullptr;
   void* Ppay = nullptr;
   int8_t* Pscale = nullptr;
+  int64_t* Aoff = nullptr;  // BPA: offset and width per compact block
+  int64_t* Poff = nullptr;
   int64_t Anz = -1, Pnz = -1;  // stored non-zero blocks (-1: no store)
   // adaptive spacetrees, levels base..L: vertex classes, refined-cell flags,
   // active tiles and the saved iterate of the FAS cycle
@@ -202,7 +207,9 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
   if (desc->max_level < 2 || desc->max_level > (desc->dim == 2 ? 10 : 6))
     throw ApiError(QMG_EINVAL, "max_level out of range (2..10 in 2D, 2..6 in 3D)");
   if (o->transfer < QMG_GEOMETRIC || o->transfer > QMG_BOXMG) throw ApiError(QMG_EINVAL, "bad transfer");
-  if (o->store < QMG_PLAIN_FP64 || o->store > QMG_HIER_BF16) throw ApiError(QMG_EINVAL, "bad store");
+  if (o->store < QMG_PLAIN_FP64 || o->store > QMG_HIER_BPA) throw ApiError(QMG_EINVAL, "bad store");
+  if (o->store == QMG_HIER_BPA && !(o->eps_mf > 0.0 && o->eps_mf <= 1.0))
+    throw ApiError(QMG_EINVAL, "the bpa store needs 0 < eps_mf <= 1");
   if (o->mu_pre < 1 || o->mu_post < 1) throw ApiError(QMG_EINVAL, "mu_pre and mu_post must be >= 1");
   if (!(o->omega > 0.0 && o->omega < 2.0)) throw ApiError(QMG_EINVAL, "omega must lie in (0, 2)");
   if (o->coarsest_level < 1 || o->coarsest_level > desc->max_level - 1)
@@ -227,6 +234,7 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
       throw ApiError(QMG_EINVAL, "coarsest_level must not exceed base_level");
     if (o->smoother == QMG_SMOOTH_BLOCK) throw ApiError(QMG_EINVAL, "block Jacobi runs on regular grids");
     if (o->cycle != QMG_CYCLE_MULT) throw ApiError(QMG_EINVAL, "additive and BPX cycles run on regular grids");
+    if (o->store == QMG_HIER_BPA) throw ApiError(QMG_EINVAL, "the bpa store runs on regular grids");
   }
 }
 
@@ -379,6 +387,7 @@ void layout(qmg_grid_t* g, Arena& a) {
         B.Ablk = a.take<int32_t>(ns / kSeg);
         B.Apay = a.take<char>(ns * NS * fmt_size(g->fmt));
         if (g->fmt == F16) B.Ascale = a.take<int8_t>(ns);
+        if (g->fmt == BPA) B.Aoff = a.take<int64_t>(ns / kSeg);
       }
     }
     if (l > lcq) {
@@ -389,6 +398,7 @@ void layout(qmg_grid_t* g, Arena& a) {
         B.Pblk = a.take<int32_t>(ns / kSeg);
         B.Ppay = a.take<char>(ns * NC * fmt_size(pf));
         if (pf == F16) B.Pscale = a.take<int8_t>(ns);
+        if (pf == BPA) B.Poff = a.take<int64_t>(ns / kSeg);
       }
     }
   }
@@ -429,7 +439,7 @@ void init_modes(qmg_grid_t* g, const qmg_grid_desc* desc, const qmg_solver_opts*
   g->lcq = o->coarsest_level;
   g->lc = g->lcq;
   g->plain = o->store == QMG_PLAIN_FP64;
-  g->mixed = o->store >= QMG_HIER_FP32;
+  g->mixed = o->store >= QMG_HIER_FP32 && o->store <= QMG_HIER_BF16;
   g->fmt = store_fmt(o->store);
   g->adaptive = desc->base_level != 0 && desc->base_level != desc->max_level;
   g->lb = g->adaptive ? desc->base_level : desc->max_level;
@@ -964,9 +974,12 @@ void encode(qmg_grid_t* g, LevelBuf& B, const Lat& Lc, bool is_P, const double* 
   int32_t* blk = is_P ? B.Pblk : B.Ablk;
   void* pay = is_P ? B.Ppay : B.Apay;
   int8_t* sc = is_P ? B.Pscale : B.Ascale;
-  launch_delta_flags(B.L, Lc, is_P, full, B.eps64, blk, S(g));
-  launch_scan_blocks(blk, B.L.nslot / kSeg, g->dtotal + slot, S(g));
-  launch_delta_write(B.L, Lc, is_P, fmt, full, B.eps64, blk, pay, sc, S(g));
+  int64_t* off = is_P ? B.Poff : B.Aoff;
+  const double eps_mf = fmt == BPA ? g->opts.eps_mf : 0.0;
+  const int64_t unit = (int64_t)(is_P ? (1 << B.L.d) : ipow(3, B.L.d)) * kSeg;
+  launch_delta_flags(B.L, Lc, is_P, full, B.eps64, blk, S(g), eps_mf);
+  launch_scan_blocks(blk, B.L.nslot / kSeg, g->dtotal + slot, S(g), off, unit);
+  launch_delta_write(B.L, Lc, is_P, fmt, full, B.eps64, blk, pay, sc, S(g), off, eps_mf);
 }
 
 void invert_dense(std::vector<double>& M, int n) {
@@ -1051,6 +1064,7 @@ void assign_stores(qmg_grid_t* g) {
       B.A.blk = B.Ablk;
       B.A.payload = B.Apay;
       B.A.scale = B.Ascale;
+      B.A.boff = B.Aoff;
     }
     if (boxmg && B.Pblk) {
       B.P.src = SRC_HIER;
@@ -1058,6 +1072,7 @@ void assign_stores(qmg_grid_t* g) {
       B.P.blk = B.Pblk;
       B.P.payload = B.Ppay;
       B.P.scale = B.Pscale;
+      B.P.boff = B.Poff;
     }
   }
 }
@@ -1174,12 +1189,22 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
   QMG_HIP(hipStreamSynchronize(s));
   size_t bytes = 0;
   int64_t blocks = 0, zero_blocks = 0;
+  // BPA blocks vary in width: the payload ends where the last block does
+  auto bpa_bytes = [&](const int64_t* off, int64_t n, int nent) -> size_t {
+    if (n <= 0) return 0;
+    int64_t ow = 0;
+    QMG_HIP(hipMemcpyAsync(&ow, off + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    QMG_HIP(hipStreamSynchronize(s));
+    return (size_t)(ow & ((int64_t(1) << 56) - 1)) + (size_t)nent * kSeg * (size_t)(ow >> 56) + (size_t)n * 8;
+  };
   for (int l : encodedA) {
     g->lv[l].Anz = tot[2 * l];
     const int64_t nb = g->lv[l].L.nslot / kSeg;
     blocks += nb;
     zero_blocks += nb - tot[2 * l];
-    bytes += (size_t)nb * 4 + (size_t)tot[2 * l] * kSeg * (NS * fmt_size(g->fmt) + (g->fmt == F16 ? 1 : 0));
+    bytes += (size_t)nb * 4;
+    if (g->fmt == BPA) bytes += bpa_bytes(g->lv[l].Aoff, tot[2 * l], NS);
+    else bytes += (size_t)tot[2 * l] * kSeg * (NS * fmt_size(g->fmt) + (g->fmt == F16 ? 1 : 0));
   }
   for (int l : encodedP) {
     g->lv[l].Pnz = tot[2 * l + 1];
@@ -1187,7 +1212,9 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
     blocks += nb;
     zero_blocks += nb - tot[2 * l + 1];
     const int pf = p_fmt(g, l);
-    bytes += (size_t)nb * 4 + (size_t)tot[2 * l + 1] * kSeg * (NC * fmt_size(pf) + (pf == F16 ? 1 : 0));
+    bytes += (size_t)nb * 4;
+    if (pf == BPA) bytes += bpa_bytes(g->lv[l].Poff, tot[2 * l + 1], NC);
+    else bytes += (size_t)tot[2 * l + 1] * kSeg * (NC * fmt_size(pf) + (pf == F16 ? 1 : 0));
   }
   if (g->plain) {
     for (int l = g->lc; l <= L; ++l) bytes += (size_t)g->lv[l].L.nslot * NS * 8;
@@ -1516,6 +1543,7 @@ int qmg_default_opts(qmg_solver_opts* o) {
   o->bj_sweeps = 1;
   o->cycle = QMG_CYCLE_MULT;
   o->damping = QMG_DAMP_EXP;
+  o->eps_mf = 1e-8;
   return QMG_OK;
 }
 

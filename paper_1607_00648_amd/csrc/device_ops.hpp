@@ -115,6 +115,53 @@ struct Dec<BF16> {
   }
 };
 
+// bpa codec (Sect. 4): x ~ m 2^e with e in one signed byte and m a
+// two's-complement integer of bpa - 1 bytes, e the smallest exponent for which
+// the rounded (nearest-even) m fits; bpa 0, x = 0 and exponents below -128
+// code zero.  Every step is exact, so host and device agree bit for bit.
+__host__ __device__ inline double bpa_code(double x, int bpa, int& e_out, long long& m_out) {
+  e_out = 0;
+  m_out = 0;
+  if (bpa == 0 || x == 0.0) return 0.0;
+  const int bits = 8 * (bpa - 1) - 1;
+  const double mmax = ldexp(1.0, bits) - 1.0;
+  int E = 0;
+  frexp(fabs(x), &E);
+  int e = E - bits;
+  double m = rint(ldexp(x, -e));
+  if (fabs(m) > mmax) {
+    ++e;
+    m = rint(ldexp(x, -e));
+  }
+  if (e < -128) return 0.0;
+  e_out = e > 127 ? 127 : e;
+  m_out = (long long)m;
+  return ldexp(m, e);
+}
+// Smallest bpa in {0, 2, ..., 8} that codes every entry within eps_mf.
+__host__ __device__ inline int bpa_width(const double* x, int n, double eps_mf) {
+  int e;
+  long long m;
+  for (int w = 0; w <= 8; w += (w == 0 ? 2 : 1)) {
+    bool ok = true;
+    for (int k = 0; k < n; ++k) ok = ok && fabs(bpa_code(x[k], w, e, m) - x[k]) <= eps_mf;
+    if (ok) return w;
+  }
+  return 8;
+}
+// Entry k of lane `lane` in a BPA block (see Store).
+__device__ inline double bpa_entry(const Store& st, int32_t cb, int nent, int k, int lane) {
+  const int64_t ow = st.boff[cb];
+  const int W = (int)(ow >> 56);
+  const uint8_t* p = (const uint8_t*)st.payload + (ow & ((int64_t(1) << 56) - 1)) + lane;
+  const int e = (int8_t)p[k * kSeg];
+  uint64_t u = 0;
+  for (int j = 0; j < W - 1; ++j) u |= (uint64_t)p[(int64_t)(nent * (1 + j) + k) * kSeg] << (8 * j);
+  const int sh = 64 - 8 * (W - 1);
+  const int64_t m = (int64_t)(u << sh) >> sh;
+  return ldexp((double)m, e);
+}
+
 // Adds the stored delta of vertex v (nent entries) to a[] when its block is
 // non-zero.  The payload is read unconditionally (block 0 stands in for a zero
 // block; stores are allocated in full) and selected, so that the loads of
@@ -125,7 +172,13 @@ __device__ inline void add_delta(const Store& st, int64_t v, T (&a)[NENT]) {
   const int64_t cbl = cb >= 0 ? cb : 0;
   const int lane = (int)(v % kSeg);
   const int64_t base = cbl * NENT * kSeg + lane;
-  if (FMT == F16) {
+  if constexpr (FMT == BPA) {
+    // variable-width blocks: nothing to read ahead for a zero block
+    if (cb >= 0) {
+#pragma unroll
+      for (int k = 0; k < NENT; ++k) a[k] += (T)bpa_entry(st, cb, NENT, k, lane);
+    }
+  } else if constexpr (FMT == F16) {
     const int e = st.scale[cbl * kSeg + lane];
 #pragma unroll
     for (int k = 0; k < NENT; ++k) {

@@ -1,6 +1,7 @@
 // Operator construction kernels: coefficient coarsening, BoxMG prolongation
 // (Sect. 3.4 and the BoxMG appendix), Galerkin R A P (Sect. 3.3) with the
 // definiteness check, and the hierarchical delta store (Sect. 4).  All FP64.
+#include <stdexcept>
 #include "device_ops.hpp"
 
 namespace qmg {
@@ -571,10 +572,13 @@ __device__ inline int load_delta(const Lat& L, const Lat& Lc, const double* __re
   return NE;
 }
 
+// Per 64-slot block (one wavefront): 1 when any vertex's delta is non-zero
+// (max|delta| > kEpsZero * max|reference|), else 0.  With eps_mf > 0 the
+// block's width instead: the largest per-vertex bpa (0 for all-zero codes).
 template <int D, bool IS_P>
 __global__ __launch_bounds__(256) void k_delta_flags(Lat L, Lat Lc, const double* __restrict__ full,
                                                      const double* __restrict__ eps,
-                                                     int32_t* __restrict__ blk) {
+                                                     int32_t* __restrict__ blk, double eps_mf) {
   const int i = blockIdx.x * TX + threadIdx.x;
   const int j = blockIdx.y * TY + threadIdx.y;
   const int kz = (D == 3) ? (int)blockIdx.z : 0;
@@ -584,48 +588,67 @@ __global__ __launch_bounds__(256) void k_delta_flags(Lat L, Lat Lc, const double
   int nz = 0;
   if (inlat) {
     const int ne = load_delta<D, IS_P>(L, Lc, full, eps, i, j, kz, v, dl, refmax);
-    double mx = 0.0;
-    for (int k = 0; k < ne; ++k) mx = fmax(mx, fabs(dl[k]));
-    nz = mx > kEpsZero * refmax;
+    if (eps_mf > 0.0) {
+      nz = bpa_width(dl, ne, eps_mf);
+    } else {
+      double mx = 0.0;
+      for (int k = 0; k < ne; ++k) mx = fmax(mx, fabs(dl[k]));
+      nz = mx > kEpsZero * refmax;
+    }
   }
-  const bool any = __any(nz);
-  if (inlat && threadIdx.x == 0) blk[v / kSeg] = any ? 1 : 0;
+  // maximum over the wavefront (flags: any)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nz = max(nz, __shfl_xor(nz, o, 64));
+  if (inlat && threadIdx.x == 0) blk[v / kSeg] = nz;
 }
 
-// Exclusive scan of 0/1 block flags into compact ids (-1 for zero blocks); one
-// workgroup walks the array in chunks.
+// Inclusive sum over the 1024 threads of the workgroup; `ws` holds 16 partial
+// sums in LDS.  Returns the thread's exclusive prefix.
+__device__ inline int32_t block_excl_scan(int32_t f, int32_t* ws) {
+  int32_t x = f;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) ws[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t s = 0;
+    for (int w = 0; w < 16; ++w) {
+      const int32_t t = ws[w];
+      ws[w] = s;
+      s += t;
+    }
+  }
+  __syncthreads();
+  return ws[threadIdx.x >> 6] + x - f;
+}
+
+// Exclusive scan of the block flags (widths) into compact ids (-1 for zero
+// blocks) and, with boff, of the widths into byte offsets; one workgroup
+// walks the array in chunks.
 __global__ __launch_bounds__(1024) void k_scan_blocks(int32_t* __restrict__ blk, int64_t nblk,
-                                                      int32_t* __restrict__ total) {
-  __shared__ int32_t wsum[16];
-  __shared__ int32_t base_s;
-  if (threadIdx.x == 0) base_s = 0;
+                                                      int32_t* __restrict__ total,
+                                                      int64_t* __restrict__ boff, int64_t unit) {
+  __shared__ int32_t wsum[16], wsw[16];
+  __shared__ int32_t base_s, basew_s;
+  if (threadIdx.x == 0) base_s = basew_s = 0;
   __syncthreads();
   for (int64_t c0 = 0; c0 < nblk; c0 += 1024) {
     const int64_t idx = c0 + threadIdx.x;
-    const int32_t f = (idx < nblk) ? blk[idx] : 0;
-    // inclusive scan within the wavefront
-    int32_t x = f;
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int32_t y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[threadIdx.x >> 6] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int32_t s = 0;
-      for (int w = 0; w < 16; ++w) {
-        const int32_t t = wsum[w];
-        wsum[w] = s;
-        s += t;
-      }
-    }
-    __syncthreads();
-    const int32_t excl = base_s + wsum[threadIdx.x >> 6] + x - f;
+    const int32_t w = (idx < nblk) ? blk[idx] : 0;
+    const int32_t f = w > 0 ? 1 : 0;
+    const int32_t excl = base_s + block_excl_scan(f, wsum);
+    const int32_t exw = basew_s + block_excl_scan(w, wsw);
     if (idx < nblk) blk[idx] = f ? excl : -1;
+    if (boff && f) boff[excl] = (int64_t)exw * unit | ((int64_t)w << 56);
     __syncthreads();
-    if (threadIdx.x == 1023) base_s = excl + f;
+    if (threadIdx.x == 1023) {
+      base_s = excl + f;
+      basew_s = exw + w;
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) *total = base_s;
@@ -642,7 +665,8 @@ __global__ __launch_bounds__(256) void k_delta_write(Lat L, Lat Lc, const double
                                                      const double* __restrict__ eps,
                                                      const int32_t* __restrict__ blk,
                                                      void* __restrict__ payload,
-                                                     int8_t* __restrict__ scale) {
+                                                     int8_t* __restrict__ scale,
+                                                     const int64_t* __restrict__ boff, double eps_mf) {
   constexpr int NE = IS_P ? Dim<D>::NC : Dim<D>::NS;
   const int i = blockIdx.x * TX + threadIdx.x;
   const int j = blockIdx.y * TY + threadIdx.y;
@@ -655,7 +679,21 @@ __global__ __launch_bounds__(256) void k_delta_write(Lat L, Lat Lc, const double
   load_delta<D, IS_P>(L, Lc, full, eps, i, j, kz, v, dl, refmax);
   const int lane = (int)(v % kSeg);
   const int64_t base = (int64_t)cb * NE * kSeg + lane;
-  if (FMT == F16) {
+  if (FMT == BPA) {
+    // every entry at the vertex's own width, stored in the block's width
+    const int64_t ow = boff[cb];
+    const int W = (int)(ow >> 56);
+    uint8_t* p = (uint8_t*)payload + (ow & ((int64_t(1) << 56) - 1)) + lane;
+    const int wv = bpa_width(dl, NE, eps_mf);
+    for (int k = 0; k < NE; ++k) {
+      int e;
+      long long m;
+      bpa_code(dl[k], wv, e, m);
+      p[k * kSeg] = (uint8_t)(int8_t)e;
+      for (int jb = 0; jb < W - 1; ++jb)
+        p[(int64_t)(NE * (1 + jb) + k) * kSeg] = (uint8_t)(((unsigned long long)m >> (8 * jb)) & 0xFFu);
+    }
+  } else if (FMT == F16) {
     double mx = 0.0;
     for (int k = 0; k < NE; ++k) mx = fmax(mx, fabs(dl[k]));
     int E = 0;
@@ -694,6 +732,7 @@ void launch_materialise(const Lat& L, const double* eps, const Store& A, double*
     else if (A.fmt == F64) QMG_MAT(DV, SRC_HIER, F64);  \
     else if (A.fmt == F32) QMG_MAT(DV, SRC_HIER, F32);  \
     else if (A.fmt == F16) QMG_MAT(DV, SRC_HIER, F16);  \
+    else if (A.fmt == BPA) QMG_MAT(DV, SRC_HIER, BPA);  \
     else QMG_MAT(DV, SRC_HIER, BF16);                   \
   } while (0)
   if (L.d == 2) QMG_MAT_D(2);
@@ -713,6 +752,7 @@ void launch_materialise_P(const Lat& Lf, const Lat& Lc, const Store& P, double* 
     else if (P.fmt == F64) QMG_MP(DV, SRC_HIER, F64);   \
     else if (P.fmt == F32) QMG_MP(DV, SRC_HIER, F32);   \
     else if (P.fmt == F16) QMG_MP(DV, SRC_HIER, F16);   \
+    else if (P.fmt == BPA) QMG_MP(DV, SRC_HIER, BPA);   \
     else QMG_MP(DV, SRC_HIER, BF16);                    \
   } while (0)
   if (Lf.d == 2) QMG_MP_D(2);
@@ -773,33 +813,37 @@ void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s)
 }
 
 void launch_delta_flags(const Lat& L, const Lat& Lc, bool is_P, const double* full, const double* eps,
-                        int32_t* blk, hipStream_t s) {
+                        int32_t* blk, hipStream_t s, double eps_mf) {
   const dim3 g = tile_grid(L), bl(TX, TY, 1);
   if (L.d == 2) {
-    if (is_P) hipLaunchKernelGGL((k_delta_flags<2, true>), g, bl, 0, s, L, Lc, full, eps, blk);
-    else hipLaunchKernelGGL((k_delta_flags<2, false>), g, bl, 0, s, L, Lc, full, eps, blk);
+    if (is_P) hipLaunchKernelGGL((k_delta_flags<2, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf);
+    else hipLaunchKernelGGL((k_delta_flags<2, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf);
   } else {
-    if (is_P) hipLaunchKernelGGL((k_delta_flags<3, true>), g, bl, 0, s, L, Lc, full, eps, blk);
-    else hipLaunchKernelGGL((k_delta_flags<3, false>), g, bl, 0, s, L, Lc, full, eps, blk);
+    if (is_P) hipLaunchKernelGGL((k_delta_flags<3, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf);
+    else hipLaunchKernelGGL((k_delta_flags<3, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf);
   }
   QMG_HIP(hipGetLastError());
 }
 
-void launch_scan_blocks(int32_t* blk, int64_t nblk, int32_t* total, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, blk, nblk, total);
+void launch_scan_blocks(int32_t* blk, int64_t nblk, int32_t* total, hipStream_t s, int64_t* boff,
+                        int64_t unit) {
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, blk, nblk, total, boff, unit);
   QMG_HIP(hipGetLastError());
 }
 
 void launch_delta_write(const Lat& L, const Lat& Lc, bool is_P, int fmt, const double* full,
                         const double* eps, const int32_t* blk, void* payload, int8_t* scale,
-                        hipStream_t s) {
+                        hipStream_t s, const int64_t* boff, double eps_mf) {
   const dim3 g = tile_grid(L), bl(TX, TY, 1);
-#define QMG_DW(DV, PV, FV) hipLaunchKernelGGL((k_delta_write<DV, PV, FV>), g, bl, 0, s, L, Lc, full, eps, blk, payload, scale)
+  if (fmt == BPA && (!boff || !(eps_mf > 0.0))) throw std::runtime_error("BPA store without offsets or eps_mf");
+#define QMG_DW(DV, PV, FV) \
+  hipLaunchKernelGGL((k_delta_write<DV, PV, FV>), g, bl, 0, s, L, Lc, full, eps, blk, payload, scale, boff, eps_mf)
 #define QMG_DW_F(DV, PV)                  \
   do {                                    \
     if (fmt == F64) QMG_DW(DV, PV, F64);  \
     else if (fmt == F32) QMG_DW(DV, PV, F32); \
     else if (fmt == F16) QMG_DW(DV, PV, F16); \
+    else if (fmt == BPA) QMG_DW(DV, PV, BPA); \
     else QMG_DW(DV, PV, BF16);            \
   } while (0)
   if (L.d == 2) {

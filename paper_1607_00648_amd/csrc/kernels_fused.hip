@@ -280,6 +280,7 @@ void dispatch_fused(const FusedArgs<T>& a, int asrc, int psrc, int fmt, hipStrea
       case F64: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, F64>(a, s, prep); else launch_one<D, T, SRC_HIER, SRC_GEOM, F64>(a, s, prep); break;
       case F32: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, F32>(a, s, prep); else launch_one<D, T, SRC_HIER, SRC_GEOM, F32>(a, s, prep); break;
       case F16: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, F16>(a, s, prep); else launch_one<D, T, SRC_HIER, SRC_GEOM, F16>(a, s, prep); break;
+      case BPA: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, BPA>(a, s, prep); else launch_one<D, T, SRC_HIER, SRC_GEOM, BPA>(a, s, prep); break;
       default: if (ph) launch_one<D, T, SRC_HIER, SRC_HIER, BF16>(a, s, prep); else launch_one<D, T, SRC_HIER, SRC_GEOM, BF16>(a, s, prep); break;
     }
   }

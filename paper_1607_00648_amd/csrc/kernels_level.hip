@@ -495,6 +495,7 @@ void dispatch_src(const Lat& L, int mode, const T* u, const T* b, TO* out, const
     case F64: return dispatch_mode<D, T, TO, SRC_HIER, F64>(L, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
     case F32: return dispatch_mode<D, T, TO, SRC_HIER, F32>(L, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
     case F16: return dispatch_mode<D, T, TO, SRC_HIER, F16>(L, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
+    case BPA: return dispatch_mode<D, T, TO, SRC_HIER, BPA>(L, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
     default: return dispatch_mode<D, T, TO, SRC_HIER, BF16>(L, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
   }
 }
@@ -515,6 +516,7 @@ void dispatch_transfer(const Lat& Lf, const Lat& Lc, const T* in, T* out, const 
   else if (P.fmt == F64) QMG_TR(SRC_HIER, F64);
   else if (P.fmt == F32) QMG_TR(SRC_HIER, F32);
   else if (P.fmt == F16) QMG_TR(SRC_HIER, F16);
+  else if (P.fmt == BPA) QMG_TR(SRC_HIER, BPA);
   else QMG_TR(SRC_HIER, BF16);
 #undef QMG_TR
   QMG_HIP(hipGetLastError());
@@ -584,6 +586,7 @@ void launch_bj_iota(const Lat& L, T* u, const T* b, const T* eps, const Store& A
     else if (A.fmt == F64) QMG_BJ(DV, SRC_HIER, F64);  \
     else if (A.fmt == F32) QMG_BJ(DV, SRC_HIER, F32);  \
     else if (A.fmt == F16) QMG_BJ(DV, SRC_HIER, F16);  \
+    else if (A.fmt == BPA) QMG_BJ(DV, SRC_HIER, BPA);  \
     else QMG_BJ(DV, SRC_HIER, BF16);                   \
   } while (0)
   if (L.d == 2) QMG_BJ_D(2);

@@ -182,6 +182,7 @@ void launch_pass2d(const PassArgs<T>& p, hipStream_t s, hipEvent_t ev_start, hip
       case F32: QMG_PASS(SRC_GEOM, F32); break;
       case F16: QMG_PASS(SRC_GEOM, F16); break;
       case BF16: QMG_PASS(SRC_GEOM, BF16); break;
+      case BPA: QMG_PASS(SRC_GEOM, BPA); break;
       default: QMG_PASS(SRC_GEOM, F64); break;
     }
   } else if (p.A.src == SRC_PLAIN) {
@@ -191,6 +192,7 @@ void launch_pass2d(const PassArgs<T>& p, hipStream_t s, hipEvent_t ev_start, hip
       case F32: QMG_PASS(SRC_HIER, F32); break;
       case F16: QMG_PASS(SRC_HIER, F16); break;
       case BF16: QMG_PASS(SRC_HIER, BF16); break;
+      case BPA: QMG_PASS(SRC_HIER, BPA); break;
       default: QMG_PASS(SRC_HIER, F64); break;
     }
   }

@@ -49,10 +49,14 @@ __device__ inline double pweight(const Store& P, const Lat& Lf, int64_t vf, int 
     const int32_t cb = P.blk[vf / kSeg];
     const int64_t cbl = cb >= 0 ? cb : 0;
     const int lane = (int)(vf % kSeg);
-    const int64_t idx = (cbl * Dim<D>::NC + kap) * kSeg + lane;
-    double dv = (double)Dec<FMT>::get(P.payload, idx);
-    if (FMT == F16) dv = ldexp(dv, (int)P.scale[cbl * kSeg + lane]);
-    w = cb >= 0 ? w + dv : w;
+    if constexpr (FMT == BPA) {
+      w = cb >= 0 ? w + bpa_entry(P, cb, Dim<D>::NC, kap, lane) : w;
+    } else {
+      const int64_t idx = (cbl * Dim<D>::NC + kap) * kSeg + lane;
+      double dv = (double)Dec<FMT>::get(P.payload, idx);
+      if (FMT == F16) dv = ldexp(dv, (int)P.scale[cbl * kSeg + lane]);
+      w = cb >= 0 ? w + dv : w;
+    }
   }
   return w;
 }

@@ -21,7 +21,7 @@ constexpr double kEpsZero = 9.094947017729282e-13;  // 2^-40: a delta this small
 constexpr double kDomSlack = 1e-10;            // diagonal-dominance slack of the definiteness check
 constexpr int kCoarseDirectMax = 1024;         // coarsest levels up to this size are solved exactly
 
-enum Fmt { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
+enum Fmt { F64 = 0, F32 = 1, F16 = 2, BF16 = 3, BPA = 4 };
 enum Src { SRC_GEOM = 0, SRC_PLAIN = 1, SRC_HIER = 2 };
 
 struct HipError : std::runtime_error {
@@ -74,6 +74,12 @@ inline Lat make_lat(int d, int level) {
 //              is the compact index of 64-slot block b or -1 for an all-zero
 //              delta; `payload` holds [cblk][nent][64] values of format `fmt`;
 //              `scale` holds [cblk][64] power-of-two exponents (FP16 only).
+//              BPA (the paper's codec, Sect. 4): block c of width W bytes per
+//              entry starts at byte boff[c] & (2^56 - 1) of `payload`, W =
+//              boff[c] >> 56 in 2..8; it holds [nent][64] signed exponent
+//              bytes, then for j = 0..W-2 byte j (little endian) of the
+//              two's-complement mantissas, [nent][64] each.  The value is
+//              m 2^e.
 struct Store {
   int src = SRC_GEOM;
   int fmt = F64;
@@ -82,6 +88,7 @@ struct Store {
   const int32_t* blk = nullptr;
   const void* payload = nullptr;
   const int8_t* scale = nullptr;
+  const int64_t* boff = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -185,13 +192,18 @@ void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s)
 // Hierarchical delta store: per-block zero flags, compaction and payload.  The
 // reference is the rediscretised stencil from eps (stencils) or the d-linear
 // weights (is_P; Lc is then the coarse lattice), both with Dirichlet entries
-// dropped.  blk gets 0/1 per block, then compact ids from the scan.
+// dropped.  blk gets 0/1 per block, then compact ids from the scan.  With
+// eps_mf > 0 (the BPA format) blk gets the block's width instead: the largest
+// per-vertex bpa, 0 when every vertex codes to zero; the scan then also writes
+// boff (byte offset and width per compact block; `unit` = nent * 64 bytes per
+// width step).
 void launch_delta_flags(const Lat& L, const Lat& Lc, bool is_P, const double* full,
-                        const double* eps, int32_t* blk, hipStream_t s);
-void launch_scan_blocks(int32_t* blk, int64_t nblk, int32_t* total, hipStream_t s);
+                        const double* eps, int32_t* blk, hipStream_t s, double eps_mf = 0.0);
+void launch_scan_blocks(int32_t* blk, int64_t nblk, int32_t* total, hipStream_t s,
+                        int64_t* boff = nullptr, int64_t unit = 0);
 void launch_delta_write(const Lat& L, const Lat& Lc, bool is_P, int fmt, const double* full,
                         const double* eps, const int32_t* blk, void* payload, int8_t* scale,
-                        hipStream_t s);
+                        hipStream_t s, const int64_t* boff = nullptr, double eps_mf = 0.0);
 
 // Coarse part of the V-cycle in one workgroup with levels lc..lf held in LDS
 // (lf starting from zero after its right-hand side was restricted into b of

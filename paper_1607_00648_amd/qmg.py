@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "QMG_OK", -1: "QMG_EINVAL", -2: "QMG_ENOMEM", -3: "QMG_EHIP",
                 -4: "QMG_ESTATE", -5: "QMG_ENOTCONV", -6: "QMG_EINDEF", -7: "QMG_EBUSY"}
 QMG_HOST, QMG_DEVICE = 0, 1
 GEOMETRIC, GALERKIN_DLINEAR, BOXMG = 0, 1, 2
-PLAIN_FP64, HIER_FP64, HIER_FP32, HIER_FP16, HIER_BF16 = 0, 1, 2, 3, 4
+PLAIN_FP64, HIER_FP64, HIER_FP32, HIER_FP16, HIER_BF16, HIER_BPA = 0, 1, 2, 3, 4, 5
 OP_MATVEC, OP_RESIDUAL, OP_JACOBI, OP_RESTRICT, OP_PROLONG, OP_SMOOTH = 0, 1, 2, 3, 4, 5
 SMOOTHERS = {"jacobi": 0, "block": 1}
 CYCLES = {"mult": 0, "add": 1, "bpx": 2}
@@ -29,7 +29,7 @@ DAMPINGS = {"exp": 0, "const": 1}
 
 TRANSFERS = {"geometric": GEOMETRIC, "galerkin": GALERKIN_DLINEAR, "boxmg": BOXMG}
 STORES = {"plain64": PLAIN_FP64, "hier64": HIER_FP64, "hier32": HIER_FP32,
-          "hier16": HIER_FP16, "bf16": HIER_BF16}
+          "hier16": HIER_FP16, "bf16": HIER_BF16, "bpa": HIER_BPA}
 
 
 class GridDesc(C.Structure):
@@ -42,7 +42,7 @@ class SolverOpts(C.Structure):
                 ("mu_post", C.c_int), ("omega", C.c_double), ("coarsest_level", C.c_int),
                 ("check_definite", C.c_int), ("inner_cycles", C.c_int), ("use_graphs", C.c_int),
                 ("stagnation", C.c_double), ("smoother", C.c_int), ("bj_sweeps", C.c_int),
-                ("cycle", C.c_int), ("damping", C.c_int)]
+                ("cycle", C.c_int), ("damping", C.c_int), ("eps_mf", C.c_double)]
 
 
 class SolveReport(C.Structure):
@@ -129,7 +129,7 @@ def _ptr(a: np.ndarray):
 
 def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_level=1,
               check_definite=True, inner_cycles=1, graphs=True, stagnation=0.0, smoother="jacobi",
-              bj_sweeps=1, cycle="mult", damping="exp") -> SolverOpts:
+              bj_sweeps=1, cycle="mult", damping="exp", eps_mf=1e-8) -> SolverOpts:
     o = SolverOpts()
     o.transfer = TRANSFERS[transfer] if isinstance(transfer, str) else int(transfer)
     o.store = STORES[store] if isinstance(store, str) else int(store)
@@ -144,6 +144,7 @@ def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_l
     o.bj_sweeps = int(bj_sweeps)
     o.cycle = CYCLES[cycle] if isinstance(cycle, str) else int(cycle)
     o.damping = DAMPINGS[damping] if isinstance(damping, str) else int(damping)
+    o.eps_mf = float(eps_mf)
     return o
 
 

@@ -31,8 +31,9 @@ def _row_noise(seed, d):
     return f
 
 
-def perturbed_hierarchies(p, transfer, seeds=(101, 102)):
-    return [O.build_hierarchy(p.eps, p.dim, p.level, transfer=transfer, perturb=_row_noise(s, p.dim))
+def perturbed_hierarchies(p, transfer, seeds=(101, 102), check_definite=True):
+    return [O.build_hierarchy(p.eps, p.dim, p.level, transfer=transfer, perturb=_row_noise(s, p.dim),
+                              check_definite=check_definite)
             for s in seeds]
 
 
@@ -73,10 +74,10 @@ def iterate_tolerance(p, transfer, H, cycles, floor=1e-12):
     return max(floor, SAFETY * worst), u
 
 
-def operator_tolerance(p, transfer, H, floor=1e-12):
+def operator_tolerance(p, transfer, H, floor=1e-12, check_definite=True):
     """Per level: absolute bound for P weights, relative bound for stencils."""
     tolP, tolA = {}, {}
-    for Hp in perturbed_hierarchies(p, transfer):
+    for Hp in perturbed_hierarchies(p, transfer, check_definite=check_definite):
         for l in H.P:
             dP = abs(H.P[l] - Hp.P[l]).max() if l in Hp.P else 0.0
             tolP[l] = max(tolP.get(l, floor), SAFETY * dP)

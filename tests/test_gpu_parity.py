@@ -685,3 +685,71 @@ def test_bpx_solve_sine_constant_omega(store):
     if store == "hier64":
         _, hist = O.solve_additive(H, b, tol=1e-8, max_cycles=600, damping="const", bpx=True)
         assert abs(rep["cycles"] - len(hist)) <= 1   # the batched loop may stop one cycle late
+
+
+# ---------------------------------------------------------------------------
+# The bpa store (the paper's codec)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,L,eps_mf", [(2, 5, 1e-2), (2, 5, 1e-8), (3, 3, 1e-4)])
+def test_bpa_operators_and_cycles_match_oracle(d, L, eps_mf):
+    """Per-cell random coefficients (BoxMG and Galerkin deltas on every
+    level): the decoded operators and weights equal the oracle's bpa
+    hierarchy, lie within eps_mf of the uncompressed FP64 store, and six
+    cycles give the oracle's residual history and iterate."""
+    qmg = require_gpu()
+    announce(f"bpa store d={d} L={L} eps_mf={eps_mf:g}")
+    p = W.random_checkerboard(d, L, seed=21, values=(1.0, 10.0), blocks=3 ** L)
+    ref = _grid(qmg, p, "boxmg", "hier64", check_definite=False)
+    ref.build()
+    g = _grid(qmg, p, "boxmg", "bpa", eps_mf=eps_mf, check_definite=False)
+    info = g.build()
+    H = O.build_hierarchy(p.eps, d, L, transfer="boxmg", check_definite=False)
+    Hq = O.solver.quantised_hierarchy(H, "bpa", eps_mf=eps_mf)
+    assert info["coarsest_level_used"] == H.lc
+    _, tolA = operator_tolerance(p, "boxmg", H, check_definite=False)
+    for l in range(H.lc, L):
+        Sg, Sr = g.operator(l), ref.operator(l)
+        # the coarsest level's exact solve keeps the full FP64 operator
+        So = O.csr_to_stencil((H if l == H.lc else Hq).A[l], d, l)
+        assert np.abs(Sg - Sr).max() <= eps_mf * (1 + 1e-9), l
+        assert np.abs(Sg - So).max() <= tolA[l] * np.abs(So).max(), (l, np.abs(Sg - So).max())
+    for l in range(H.lc + 1, L + 1):
+        Wg, Wr = g.prolongation(l), ref.prolongation(l)
+        Wo = O.P_to_parent_weights(Hq.P[l], d, l)
+        assert np.abs(Wg - Wr).max() <= eps_mf * (1 + 1e-9), l
+        assert np.abs(Wg - Wo).max() <= 1e-11, (l, np.abs(Wg - Wo).max())
+    rr = g.vcycle(6)
+    u = g.solution()
+    g.close()
+    ref.close()
+    uo, hist = O.solve(Hq, O.rhs_from_f(p.f, d, L), cycles=6)
+    np.testing.assert_allclose(rr, hist, rtol=1e-9, atol=1e-14)
+    assert np.abs(u - uo).max() <= 1e-10 * np.abs(uo).max()
+
+
+def test_bpa_store_sizes():
+    """Constant coefficients compress to nothing (every delta block dropped);
+    on the per-cell random setup a loose eps_mf stores fewer bytes than a
+    tight one, and both fewer than the FP64 deltas.  eps_mf outside (0, 1]
+    and the bpa store on an adaptive grid are rejected."""
+    qmg = require_gpu()
+    announce("bpa store sizes")
+    p = W.sin_source(2, 5)
+    g = _grid(qmg, p, "boxmg", "bpa")
+    info = g.build()
+    g.close()
+    assert info["zero_delta_fraction"] == 1.0
+    p = W.random_checkerboard(2, 5, seed=21, values=(1.0, 10.0), blocks=243)
+    sizes = {}
+    for store, eps in (("hier64", 1e-8), ("bpa", 1e-8), ("bpa", 1e-2)):
+        g = _grid(qmg, p, "boxmg", store, eps_mf=eps, check_definite=False)
+        sizes[(store, eps)] = g.build()["bytes_operators"]
+        g.close()
+    assert sizes[("bpa", 1e-2)] < sizes[("bpa", 1e-8)] < sizes[("hier64", 1e-8)]
+    for bad in (0.0, -1.0, 2.0):
+        with pytest.raises(qmg.QmgError):
+            qmg.Grid(2, 4, qmg.make_opts("boxmg", "bpa", eps_mf=bad))
+    P = W.adaptive_balls(dim=2, base=2, level=3, n_balls=1)
+    with pytest.raises(qmg.QmgError):
+        qmg.Grid(2, 3, qmg.make_opts("boxmg", "bpa"), base_level=2, refine=P.flags)

@@ -3,7 +3,7 @@
 Paper passages followed:
 
 * Eq. (1) of the introduction: -div(eps grad u) + (v . grad) u = f on the unit
-  cube, eps a diagonal tensor; here v = 0.
+  cube, eps a diagonal tensor, v a velocity field.
 * Sect. 2 (spacetree, vertex classes, d-linear shape functions on every level)
   and Sect. 3, eq. "03_solver:stencils": a vertex's stencil is the sum of the
   contributions of its 2^d adjacent cells.
@@ -14,6 +14,11 @@ Readings (the paper is silent on these):
   that is constant on the cell.  In tensor-product form
   ``K_c(a,b) = h^(d-2) sum_i eps_{c,i} k(a_i,b_i) prod_{j!=i} m(a_j,b_j)``
   with the 1D stiffness ``k = [[1,-1],[-1,1]]`` and mass ``m = [[1/3,1/6],[1/6,1/3]]``.
+* The convection term is the plain Galerkin one (no upwinding; the paper
+  names none) with v constant on each cell: the element matrix is
+  ``C_c(a,b) = h^(d-1) sum_i v_{c,i} g(a_i,b_i) prod_{j!=i} m(a_j,b_j)`` with
+  ``g(a,b) = int_0^1 phi_b' phi_a = [[-1/2, 1/2], [-1/2, 1/2]]`` (row a = the
+  test function's corner).
 * The right-hand side is lumped: ``b_v = h^d f_v``.
 * Zero Dirichlet boundary: boundary vertices carry no row, and stencil entries
   that point at boundary vertices are dropped.
@@ -73,6 +78,58 @@ def element_matrix(d, h, eps_c):
                 tot += term
             K[ia, ib] = h ** (d - 2) * tot
     return K
+
+
+G1D = np.array([[-0.5, 0.5], [-0.5, 0.5]])
+
+
+def convection_element_matrix(d, h, v_c):
+    """Q1 element matrix of (v . grad) u on one cell for constant ``v_c``
+    (length d): entry (a, b) integrates (v . grad phi_b) phi_a, a and b the
+    cell's corners in ``corners(d)`` order."""
+    v_c = np.asarray(v_c, dtype=np.float64)
+    cs = corners(d)
+    C = np.zeros((2 ** d, 2 ** d))
+    for ia, a in enumerate(cs):
+        for ib, b in enumerate(cs):
+            tot = 0.0
+            for i in range(d):
+                term = v_c[i] * G1D[a[i], b[i]]
+                for j in range(d):
+                    if j != i:
+                        term *= M1D[a[j], b[j]]
+                tot += term
+            C[ia, ib] = h ** (d - 1) * tot
+    return C
+
+
+def convection_stencil(v, d, level):
+    """Stencils of the convection term on a regular level from per-cell
+    velocities ``v`` (shape ``(d,) + (n,)*d``, component i along axis i), by
+    the same sum over the 2^d cells around each vertex as
+    ``geometric_stencil``; Dirichlet rows/entries removed."""
+    n = 3 ** level
+    h = 1.0 / n
+    v = np.asarray(v, dtype=np.float64)
+    if v.shape != (d,) + (n,) * d:
+        raise ValueError(f"v must have shape {(d,) + (n,) * d}; got {v.shape}")
+    padded = [np.pad(v[i], 1) for i in range(d)]
+    cref = []
+    for i in range(d):
+        e = np.zeros(d)
+        e[i] = 1.0
+        cref.append(convection_element_matrix(d, h, e))
+    S = np.zeros((3 ** d,) + (n + 1,) * d)
+    for s in corners(d):
+        sl = tuple(slice(1 - s[i], 1 - s[i] + n + 1) for i in reversed(range(d)))
+        cell = [p[sl] for p in padded]
+        for w in corners(d):
+            o = tuple(w[i] - s[i] for i in range(d))
+            k = flat_offset(o)
+            ia, ib = corner_index(s), corner_index(w)
+            for i in range(d):
+                S[k] += cell[i] * cref[i][ia, ib]
+    return apply_dirichlet(S, d, level)
 
 
 def shifted(a, o):

@@ -17,9 +17,11 @@ import scipy.sparse as sp
 DOMINANCE_SLACK = 1e-10
 
 
-def rap(A, P):
-    """R A P with R = P^T (sparse, interior unknowns)."""
-    return sp.csr_matrix(P.T @ (A @ P))
+def rap(A, P, R=None):
+    """R A P (sparse, interior unknowns); R = P^T unless given (Petrov-Galerkin,
+    Sect. 3.3)."""
+    R = P.T if R is None else R
+    return sp.csr_matrix(R @ (A @ P))
 
 
 def definiteness_violations(Ac):

@@ -72,8 +72,8 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .fem import (geometric_stencil, stencil_to_csr, csr_to_stencil, coarsen_eps)
-from .transfer import dlinear_P, boxmg_P
+from .fem import (geometric_stencil, convection_stencil, stencil_to_csr, csr_to_stencil, coarsen_eps)
+from .transfer import dlinear_P, boxmg_P, injection_R
 from .galerkin import rap, definiteness_violations
 from .store import quantise, delta_zero, EPS_ZERO, fp16_exponent, bpa_value, bpa_encode, BPA_WIDTHS
 
@@ -100,25 +100,42 @@ class Hierarchy:
     dtype: type = np.float64
     smoother: str = "jacobi"       # "jacobi" or "block" (block Jacobi)
     bj_sweeps: int = 1             # Gauss-Seidel sweeps per patch in block Jacobi
+    R: Optional[Dict[int, sp.csr_matrix]] = None   # restriction per level; None: P^T
 
     def diag(self, l):
         return self.A[l].diagonal()
 
 
 def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_post=2,
-                    check_definite=True, perturb=None, smoother="jacobi", bj_sweeps=1):
+                    check_definite=True, perturb=None, smoother="jacobi", bj_sweeps=1, v=None,
+                    restriction="transpose"):
     """Operators of all levels from the finest coefficients (Sect. 3.3, 3.4).
 
-    ``perturb`` (tests only) is applied to every Galerkin product before it is
-    used; the tests pass one-ulp random noise to measure how far FP64 rounding
-    alone moves the results (the noise floor of a parity comparison)."""
+    ``v`` (per-cell velocities, shape (d,)+(n,)*d) adds the convection term of
+    eq. (1) to the finest operator; its coarse operators then come from the
+    Galerkin product only.  ``restriction`` "injection" takes R = I (the
+    Petrov-Galerkin variant of the convection results) in R A P and in the
+    cycle.  ``perturb`` (tests only) is applied to every Galerkin product
+    before it is used; the tests pass one-ulp random noise to measure how far
+    FP64 rounding alone moves the results (the noise floor of a parity
+    comparison)."""
     if transfer not in ("geometric", "galerkin", "boxmg"):
         raise ValueError(transfer)
+    if restriction not in ("transpose", "injection"):
+        raise ValueError(restriction)
+    if v is not None and transfer == "geometric":
+        raise ValueError("convection needs Galerkin coarse operators")
+    if restriction == "injection" and transfer == "geometric":
+        raise ValueError("injection is a Petrov-Galerkin restriction")
     eps_l = {L: np.asarray(eps, dtype=np.float64)}
     for l in range(L, 0, -1):
         eps_l[l - 1] = coarsen_eps(eps_l[l], d)
-    A = {L: stencil_to_csr(geometric_stencil(eps_l[L], d, L), d, L)}
+    S = geometric_stencil(eps_l[L], d, L)
+    if v is not None:
+        S = S + convection_stencil(v, d, L)
+    A = {L: stencil_to_csr(S, d, L)}
     P = {}
+    R = {} if restriction == "injection" else None
     lc_used = lc
     for l in range(L, lc, -1):
         if transfer == "boxmg":
@@ -128,7 +145,10 @@ def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_p
         if transfer == "geometric":
             Ac = stencil_to_csr(geometric_stencil(eps_l[l - 1], d, l - 1), d, l - 1)
         else:
-            Ac = rap(A[l], Pl)
+            Rl = injection_R(d, l) if R is not None else None
+            Ac = rap(A[l], Pl, Rl)
+            if R is not None:
+                R[l] = Rl
             if perturb is not None:
                 Ac = perturb(Ac)
             if check_definite and len(definiteness_violations(Ac)) > 0:
@@ -138,8 +158,10 @@ def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_p
         A[l - 1] = Ac
     if lc_used >= L:
         raise IndefiniteError("coarsest level would reach the finest level")
+    if R is not None:
+        R = {l: R[l] for l in P}
     H = Hierarchy(d, L, lc_used, transfer, A, P, eps_l, omega, mu_pre, mu_post,
-                  smoother=smoother, bj_sweeps=bj_sweeps)
+                  smoother=smoother, bj_sweeps=bj_sweeps, R=R)
     n_c = A[lc_used].shape[0]
     if n_c <= COARSE_DIRECT_MAX:
         H.coarse_lu = sla.lu_factor(A[lc_used].toarray())
@@ -211,7 +233,8 @@ def vcycle(H, l, u, b):
         u = smooth(H, l, A, D, u, b)
     r = b - A @ u
     P = H.P[l]
-    bc = (P.T @ r).astype(dt)
+    Rl = P.T if H.R is None else H.R[l]
+    bc = (Rl @ r).astype(dt)
     ec = vcycle(H, l - 1, np.zeros(P.shape[1], dtype=dt), bc)
     u = u + P @ ec
     for _ in range(H.mu_post):

@@ -73,6 +73,20 @@ def dlinear_P(d, level_f):
     return P
 
 
+def injection_R(d, level_f):
+    """Injection from level_f to level_f-1 (Petrov-Galerkin R = I of the
+    convection results): coarse vertex V takes the fine value at 3V.  Sparse,
+    coarse interior unknowns x fine interior unknowns."""
+    nf = 3 ** level_f
+    nc = nf // 3
+    numf = _unknown_numbering(d, level_f)
+    numc = _unknown_numbering(d, level_f - 1)
+    Vs = np.array(list(itertools.product(range(1, nc), repeat=d)))[:, ::-1]  # x first
+    r = numc[tuple(Vs[:, i] for i in reversed(range(d)))]
+    c = numf[tuple(3 * Vs[:, i] for i in reversed(range(d)))]
+    return sp.csr_matrix((np.ones(len(r)), (r, c)), shape=((nc - 1) ** d, (nf - 1) ** d))
+
+
 def boxmg_reference_matrix(t, d):
     """C(s) of the reference corner.  ``t`` has shape (batch, 4^d, 3^d): the
     mirrored stencils of the patch points y in {0..3}^d (x fastest).  Returns

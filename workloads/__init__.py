@@ -15,7 +15,8 @@ Layout conventions (shared by every producer and consumer of these arrays):
   ``x = i/n`` and is stored at ``f[k-1, j-1, i-1]``.
 
 The problems follow the paper's setups (Table "parameters", Sect. 5): zero
-Dirichlet boundary, no convection, piecewise-constant coefficients per cell.
+Dirichlet boundary, piecewise-constant coefficients (and, for ``circle``,
+velocities) per cell.
 The concrete random fields stand in for the paper's analytic setups; no data set
 is involved.
 """
@@ -121,6 +122,28 @@ def material_jump(dim: int, level: int) -> Problem:
     eps = np.broadcast_to(np.where(xc < 0.5, 1.0, 0.1), (n,) * dim).copy()
     return Problem(f"jump{dim}d-L{level}", dim, level, eps, np.ones((n - 1,) * dim),
                    {"eps": "1 | 0.1 at x = 0.5"})
+
+
+def circle(dim: int, level: int, eps_small: float, seed: int = 0) -> Problem:
+    """The paper's ``circle`` setup (Table "parameters"): a recirculating flow
+    v = (sin(pi(y - 1/2)) cos(pi(x - 1/2)), -cos(pi(y - 1/2)) sin(pi(x - 1/2)), 0)
+    sampled at cell centres, eps = eps_small (1 in 3D where z > 1/2).  The
+    paper's inflow boundary data are replaced by zero Dirichlet values and a
+    seeded f ~ U[-1, 1], which leaves the operator unchanged.  ``meta["v"]``
+    holds the velocities, shape (dim,) + (n,)*dim."""
+    n = 3 ** level
+    xc = (np.arange(n) + 0.5) / n
+    grids = np.meshgrid(*([xc] * dim), indexing="ij")   # axis order (z,) y, x
+    x, y = grids[-1], grids[-2]
+    v = np.zeros((dim,) + (n,) * dim)
+    v[0] = np.sin(np.pi * (y - 0.5)) * np.cos(np.pi * (x - 0.5))
+    v[1] = -np.cos(np.pi * (y - 0.5)) * np.sin(np.pi * (x - 0.5))
+    eps = np.full((n,) * dim, float(eps_small))
+    if dim == 3:
+        eps = np.where(grids[0] > 0.5, 1.0, eps)
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(-1.0, 1.0, (n - 1,) * dim)
+    return Problem(f"circle{dim}d-L{level}-eps{eps_small:g}", dim, level, eps, f, {"v": v})
 
 
 # --------------------------------------------------------------------------
@@ -306,4 +329,4 @@ def request_stream(seed: int = 0, n_requests: int = 256, rate: float = 100.0,
 __all__ = ["Problem", "Request", "poisson", "random_checkerboard",
            "alternating_checkerboard", "sin_source", "poisson2d_l4", "checkerboard2d", "jump3d",
            "request_stream", "ball_flags", "rff_field", "uniform_hash", "AdaptiveProblem",
-           "adaptive_balls", "adaptive_band", "material_jump"]
+           "adaptive_balls", "adaptive_band", "material_jump", "circle"]

@@ -99,15 +99,19 @@ def run_variant(qmg, problem, transfer, store, steps, warmup, tol=1e-8, profile=
             "kernel_launches": launches, "kernel_ms": ms, "u": u}
 
 
-def time_solves(g, eps, f, tol, n, warmup=1, time_cap=20.0):
+def time_solves(g, eps, f, tol, n, warmup=1, time_cap=20.0, v=None):
     """Repeated full solves (set_coefficients + build_operators + solve) of one
-    grid: up to n timed solves, fewer if they exceed time_cap seconds."""
+    grid: up to n timed solves, fewer if they exceed time_cap seconds.  ``v``:
+    host velocities of a convection problem (handed over with eps)."""
     import torch
     lat, reps = [], []
     for it in range(warmup + n):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        g.set_coefficients(eps, f)
+        if v is None:
+            g.set_coefficients(eps, f)
+        else:
+            g.set_coefficients(eps, f, v=v)
         g.build()
         rep, _ = g.solve(tol, 2000)
         t1 = time.perf_counter()
@@ -177,6 +181,16 @@ def other_workloads(qmg, n):
                                workload="2D sine source, 729^2 cells; BPX cycles, omega 0.8 on every "
                                         "level, geometric transfer, to 1e-8")
     g.close()
+    p = W.circle(2, 6, 0.1, seed=5)
+    for restriction in ("transpose", "injection"):
+        g = qmg.Grid(p.dim, p.level, qmg.make_opts("boxmg", "plain64", restriction=restriction))
+        r = time_solves(g, p.eps, p.f, 1e-8, max(5, n // 5), warmup=1, v=p.meta["v"])
+        out[f"circle2d_L6_eps0.1_R_{restriction}"] = dict(
+            r, unknowns=p.n_unknowns,
+            workload="2D convection-diffusion, recirculating flow, eps 0.1, 729^2 cells; BoxMG, "
+                     f"R = {'P^T' if restriction == 'transpose' else 'injection'}, plain FP64 store, to 1e-8 "
+                     "(eps, v and f handed over from host memory)")
+        g.close()
     P = W.adaptive_balls()
     g = qmg.Grid(P.dim, P.level, qmg.make_opts("boxmg", "bf16", check_definite=False),
                  base_level=P.base, refine=P.flags)

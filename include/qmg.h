@@ -165,6 +165,12 @@ typedef struct {
                           every level (the paper's choice for BPX)           */
   double eps_mf;       /* QMG_HIER_BPA: largest coding error per entry, in
                           (0, 1]; default 1e-8                               */
+  int restriction;     /* QMG_R_TRANSPOSE (default): R = P^T.
+                          QMG_R_INJECTION: R = I, the coarse vertex takes the
+                          fine value at its position, in the restriction and
+                          in A_{l-1} = R A_l P (Petrov-Galerkin, Sect. 3.3 and
+                          the convection results); Galerkin or BoxMG
+                          transfers, multiplicative cycles, regular grids   */
 } qmg_solver_opts;
 
 typedef struct {
@@ -213,9 +219,14 @@ int qmg_unknown_coords(const qmg_grid_t* grid, double* xyz, int8_t* level);
 /* Centres of the leaf cells, dim values per cell (host array). */
 int qmg_leaf_cell_centres(const qmg_grid_t* grid, double* xyz);
 
-/* Sets the coefficient eps (one value per leaf cell, > 0 and finite; ncomp
- * must be 1) and the source f (one value per unknown); the right-hand side of
- * an unknown on level l is b = h_l^d f (lumped).  `mem` says where eps and f
+/* Sets the coefficient eps (one value per leaf cell, > 0 and finite) and the
+ * source f (one value per unknown); the right-hand side of an unknown on level
+ * l is b = h_l^d f (lumped).  ncomp = 1: `eps` holds eps only.  ncomp = 1 + d:
+ * `eps` holds eps followed by the d velocity components v_1..v_d (each one
+ * finite value per cell, same cell order), and the finest operator gains the
+ * convection term (v . grad) u of eq. (1) (Galerkin Q1, v constant per cell,
+ * no upwinding); regular grids, QMG_PLAIN_FP64 and Galerkin or BoxMG transfers
+ * only (the velocity arrays are library memory, held until the grid ends).  `mem` says where eps and f
  * live (QMG_HOST or QMG_DEVICE); device inputs never leave the device (they
  * are checked and scattered there).  Resets the solution to zero and
  * invalidates operators.  QMG_EINVAL for values out of range; the grid then
@@ -279,6 +290,7 @@ int qmg_get_prolongation(const qmg_grid_t* grid, int level, double* weights);
 enum { QMG_SMOOTH_JACOBI = 0, QMG_SMOOTH_BLOCK = 1 };
 enum { QMG_CYCLE_MULT = 0, QMG_CYCLE_ADD = 1, QMG_CYCLE_BPX = 2 };
 enum { QMG_DAMP_EXP = 0, QMG_DAMP_CONST = 1 };
+enum { QMG_R_TRANSPOSE = 0, QMG_R_INJECTION = 1 };
 
 enum {
   QMG_OP_MATVEC = 0,     /* out = A x                                         */

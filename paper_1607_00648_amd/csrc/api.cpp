@@ -121,6 +121,8 @@ struct qmg_grid {
   double* x64 = nullptr;    // mixed: FP64 solution on the finest level
   double* bfin = nullptr;   // mixed: FP64 right-hand side on the finest level
   double* stage = nullptr;  // packed IO staging (nslot of the finest level)
+  double* vel = nullptr;    // convection: d arrays of finest cell slots (library-owned)
+  bool has_conv = false;
   double* partial = nullptr;
   int npart = 0;  // entries of `partial`
   double* dscal = nullptr;
@@ -223,6 +225,10 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
   if (o->cycle != QMG_CYCLE_MULT && o->cycle != QMG_CYCLE_ADD && o->cycle != QMG_CYCLE_BPX)
     throw ApiError(QMG_EINVAL, "bad cycle");
   if (o->damping != QMG_DAMP_EXP && o->damping != QMG_DAMP_CONST) throw ApiError(QMG_EINVAL, "bad damping");
+  if (o->restriction != QMG_R_TRANSPOSE && o->restriction != QMG_R_INJECTION)
+    throw ApiError(QMG_EINVAL, "bad restriction");
+  if (o->restriction == QMG_R_INJECTION && (o->transfer == QMG_GEOMETRIC || o->cycle != QMG_CYCLE_MULT))
+    throw ApiError(QMG_EINVAL, "injection is a Petrov-Galerkin restriction of multiplicative cycles");
   if (o->cycle != QMG_CYCLE_MULT && o->smoother != QMG_SMOOTH_JACOBI)
     throw ApiError(QMG_EINVAL, "additive and BPX cycles take one Jacobi step per level");
   const bool adaptive = desc->base_level != 0 && desc->base_level != desc->max_level;
@@ -235,6 +241,7 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
     if (o->smoother == QMG_SMOOTH_BLOCK) throw ApiError(QMG_EINVAL, "block Jacobi runs on regular grids");
     if (o->cycle != QMG_CYCLE_MULT) throw ApiError(QMG_EINVAL, "additive and BPX cycles run on regular grids");
     if (o->store == QMG_HIER_BPA) throw ApiError(QMG_EINVAL, "the bpa store runs on regular grids");
+    if (o->restriction == QMG_R_INJECTION) throw ApiError(QMG_EINVAL, "injection runs on regular grids");
   }
 }
 
@@ -516,6 +523,14 @@ hipEvent_t* prof_pair(qmg_grid_t* g) {
   return &g->prof_ev[2 * g->prof_used++];
 }
 
+// Restriction of the residual of level F into the right-hand side of C: P^T,
+// or injection for the Petrov-Galerkin variant.
+template <typename T>
+void restrict_to(qmg_grid_t* g, LevelBuf& F, LevelBuf& C, const T* r, T* bc) {
+  if (g->opts.restriction == QMG_R_INJECTION) launch_inject<T>(F.L, C.L, r, bc, S(g));
+  else launch_restrict<T>(F.L, C.L, r, bc, F.P, S(g));
+}
+
 template <typename T>
 void smooth(qmg_grid_t* g, LevelBuf& B, int sweeps, bool zero_init) {
   const T om = (T)g->opts.omega;
@@ -579,6 +594,7 @@ template <typename T>
 int choose_fused_top(qmg_grid_t* g, bool& pw_lds) {
   int best = -1;
   if (g->opts.smoother != QMG_SMOOTH_JACOBI) return best;  // the fused coarse cycle runs Jacobi
+  if (g->opts.restriction != QMG_R_TRANSPOSE) return best;  // and restricts with P^T
   for (int lf = g->lc; lf < g->lb && lf - g->lc + 1 <= kMaxFused; ++lf) {
     for (int pl = 1; pl >= 0; --pl) {
       FusedArgs<T> a = fused_args<T>(g, lf);
@@ -678,7 +694,7 @@ bool vcycle(qmg_grid_t* g, int l, bool zero_init, bool want_norm = false) {
   LevelBuf& Cb = g->lv[l - 1];
   if (g->d == 2 && g->opts.smoother == QMG_SMOOTH_JACOBI) {  // fused passes
     passes<T>(g, F, nullptr, mu, zero_init, true, nullptr);
-    launch_restrict<T>(F.L, Cb.L, (const T*)F.r, (T*)Cb.b, F.P, S(g));
+    restrict_to<T>(g, F, Cb, (const T*)F.r, (T*)Cb.b);
     vcycle<T>(g, l - 1, true);
     const bool norm = want_norm && l == g->Lmax;
     passes<T>(g, F, &Cb, nu, false, norm, norm ? g->partial : nullptr);
@@ -688,7 +704,7 @@ bool vcycle(qmg_grid_t* g, int l, bool zero_init, bool want_norm = false) {
   launch_stencil<T>(F.L, 2, (const T*)F.u, (const T*)F.b, (T*)F.r, eps_of<T>(F), F.A, (T)0, nullptr,
                     nullptr, S(g));
   LevelBuf& C = g->lv[l - 1];
-  launch_restrict<T>(F.L, C.L, (const T*)F.r, (T*)C.b, F.P, S(g));
+  restrict_to<T>(g, F, C, (const T*)F.r, (T*)C.b);
   vcycle<T>(g, l - 1, true);
   launch_prolong<T>(F.L, C.L, (const T*)C.u, (T*)F.u, F.P, S(g));
   smooth<T>(g, F, nu, false);
@@ -1114,6 +1130,7 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
   };
   if (g->plain) {
     launch_materialise(g->lv[L].L, g->lv[L].eps64, geom, g->lv[L].Adense, s);
+    if (g->has_conv) launch_conv_add(g->lv[L].L, g->vel, g->lv[L].Adense, s);
     merge(L, g->lv[L].Adense);
   }
   for (int l = g->lcq; l <= L; ++l) {
@@ -1153,7 +1170,7 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
       const int8_t* mask = (g->adaptive && l == L && !Afine) ? F.vt : nullptr;
       const bool adc = g->adaptive && l - 1 >= g->lb;
       launch_rap(F.L, C.L, Afine, F.eps64, Pw, Ac, s, mask, adc ? C.vt : nullptr, adc ? C.rv : nullptr,
-                 adc ? C.nrv : 0);
+                 adc ? C.nrv : 0, g->opts.restriction == QMG_R_INJECTION);
       merge(l - 1, Ac);
       // the fallback of a failed check raises the coarsest level, which is
       // possible only below the base level of an adaptive spacetree
@@ -1354,7 +1371,7 @@ void apply_op(qmg_grid_t* g, int op, int level, const double* x, const double* b
     if (op == QMG_OP_RESTRICT) {
       upload_lattice<T>(g, B.L, x, (T*)B.r);
       launch_zero<T>((T*)C.b, C.L.nslot, S(g));
-      launch_restrict<T>(B.L, C.L, (const T*)B.r, (T*)C.b, B.P, S(g));
+      restrict_to<T>(g, B, C, (const T*)B.r, (T*)C.b);
       download_lattice<T>(g, C.L, (const T*)C.b, out);
     } else {
       upload_lattice<T>(g, C.L, x, (T*)C.u);
@@ -1508,6 +1525,7 @@ int create_grid(const qmg_grid_desc* desc, const qmg_solver_opts* opts, void* de
       upload_linearisation(g);
     } catch (...) {
       if (g->owns && g->base) (void)hipFree(g->base);
+      if (g->vel) (void)hipFree(g->vel);
       if (g->hnorm && g->own_hnorm) (void)hipHostFree(g->hnorm);
       if (g->bev) (void)hipEventDestroy(g->bev);
       if (g->own_stream) (void)hipStreamDestroy(g->stream);
@@ -1544,6 +1562,7 @@ int qmg_default_opts(qmg_solver_opts* o) {
   o->cycle = QMG_CYCLE_MULT;
   o->damping = QMG_DAMP_EXP;
   o->eps_mf = 1e-8;
+  o->restriction = QMG_R_TRANSPOSE;
   return QMG_OK;
 }
 
@@ -1617,7 +1636,10 @@ int qmg_leaf_cell_centres(const qmg_grid_t* g, double* xyz) {
 int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const double* f, int mem) {
   return guard(g, [&] {
     if (!g || !eps || !f) throw ApiError(QMG_EINVAL, "null argument");
-    if (ncomp != 1) throw ApiError(QMG_EINVAL, "only scalar coefficients (ncomp = 1) are supported");
+    if (ncomp != 1 && ncomp != 1 + g->d)
+      throw ApiError(QMG_EINVAL, "ncomp must be 1 (eps) or 1 + d (eps and the velocity components)");
+    if (ncomp > 1 && (g->adaptive || !g->plain || g->opts.transfer == QMG_GEOMETRIC))
+      throw ApiError(QMG_EINVAL, "convection needs a regular grid, the plain store and Galerkin coarse operators");
     if (mem != QMG_HOST && mem != QMG_DEVICE) throw ApiError(QMG_EINVAL, "bad mem flag");
     g->have_coef = false;
     g->have_ops = false;
@@ -1630,7 +1652,7 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
     auto blocks = [&](int64_t n, int share) {
       return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, g->npart / share));
     };
-    launch_zero<int>(g->dcount, 2, s);
+    launch_zero<int>(g->dcount, 3, s);
     // cell coefficients: staged, checked on the device, scattered per level
     copy_in(g, g->stage, eps, ncell, mem);
     launch_prep_input(g->stage, ncell, 1.0, true, g->partial, blocks(ncell, 1), g->dcount, s);
@@ -1645,6 +1667,17 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
       }
     } else {
       launch_scatter_cells<double>(L, g->stage, F.eps64, s);
+    }
+    // velocities (components 1..d): staged, checked finite, scattered
+    g->has_conv = ncomp > 1;
+    if (g->has_conv) {
+      if (!g->vel) QMG_HIP(hipMalloc(&g->vel, (size_t)g->d * L.nslot * sizeof(double)));
+      launch_zero<double>(g->vel, (int64_t)g->d * L.nslot, s);
+      for (int c = 0; c < g->d; ++c) {
+        copy_in(g, g->stage, eps + (int64_t)(1 + c) * ncell, ncell, mem);
+        launch_prep_input(g->stage, ncell, 1.0, false, g->partial, blocks(ncell, 1), g->dcount + 2, s);
+        launch_scatter_cells<double>(L, g->stage, g->vel + (int64_t)c * L.nslot, s);
+      }
     }
     // right-hand side b = h_l^d f of every unknown (level l), and its norm
     copy_in(g, g->stage, f, nu, mem);
@@ -1688,13 +1721,14 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
       launch_scatter_unknowns<double>(L, g->stage, (double*)F.b, s);
       launch_zero<double>((double*)F.u, L.nslot, s);
     }
-    int bad[2] = {0, 0};
+    int bad[3] = {0, 0, 0};
     double b2 = 0.0;
     QMG_HIP(hipMemcpyAsync(bad, g->dcount, sizeof(bad), hipMemcpyDeviceToHost, s));
     QMG_HIP(hipMemcpyAsync(&b2, g->dscal, sizeof(double), hipMemcpyDeviceToHost, s));
     QMG_HIP(hipStreamSynchronize(s));
     if (bad[0] > 0) throw ApiError(QMG_EINVAL, "eps must be positive and finite");
     if (bad[1] > 0) throw ApiError(QMG_EINVAL, "f must be finite");
+    if (bad[2] > 0) throw ApiError(QMG_EINVAL, "the velocities must be finite");
     g->bnorm = std::sqrt(b2);
     g->have_coef = true;
   });
@@ -1819,6 +1853,7 @@ int qmg_destroy_grid(qmg_grid_t* g) {
   drop_graph(g);
   for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
   if (g->owns && g->base && hipFree(g->base) != hipSuccess) rc = QMG_EHIP;
+  if (g->vel && hipFree(g->vel) != hipSuccess) rc = QMG_EHIP;
   if (g->hnorm && g->own_hnorm) (void)hipHostFree(g->hnorm);
   if (g->bev) (void)hipEventDestroy(g->bev);
   if (g->own_stream) (void)hipStreamDestroy(g->stream);

@@ -386,7 +386,8 @@ template <int D>
 __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetch<D> A, PFetch<D> P,
                                                          double* __restrict__ Ac,
                                                          const int8_t* __restrict__ vtc,
-                                                         const int32_t* __restrict__ vlist, int64_t nlist) {
+                                                         const int32_t* __restrict__ vlist, int64_t nlist,
+                                                         int inject) {
   using S = RapShape<D>;
   constexpr int NS = Dim<D>::NS, NC = Dim<D>::NC;
   __shared__ double arow[S::VPB * S::NI * NS];
@@ -438,7 +439,8 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
       if (vco[4 * vs + 3] == 1) {
         const int Vx = vco[4 * vs], Vy = vco[4 * vs + 1], Vz = vco[4 * vs + 2];
         const int ix = 3 * Vx + q % 5 - 2, iy = 3 * Vy + (q / 5) % 5 - 2, iz = (D == 3) ? 3 * Vz + q / 25 - 2 : 0;
-        pi = P(ix, iy, iz, Vx, Vy, Vz);
+        // Petrov-Galerkin R = I: only the row of i = 3V enters
+        pi = inject ? (q == S::NI / 2 ? 1.0 : 0.0) : P(ix, iy, iz, Vx, Vy, Vz);
         const int64_t vi = ix + (int64_t)iy * Lf.pitch + (int64_t)iz * Lf.plane;
         const RowSrc<D> row(A, vi);
 #pragma unroll
@@ -538,6 +540,54 @@ __global__ __launch_bounds__(256) void k_check_rows(Lat Lc, const double* __rest
     if (k != NS / 2) off += fabs(Ac[(int64_t)k * Lc.nslot + v]);
   if (dg == 0.0 && off == 0.0) return;  // no row (adaptive levels: not a refined vertex)
   if (dg <= 0.0 || dg < (1.0 - kDomSlack) * off) atomicAdd(bad, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Convection term of eq. (1): the Galerkin Q1 element matrix of (v . grad) u
+// with v constant per cell, C(a,b) = h^(d-1) sum_i v_i g(a_i,b_i)
+// prod_{j!=i} m(a_j,b_j), g = [[-1/2, 1/2], [-1/2, 1/2]], m the unit 1D mass;
+// added to the rows of the interior vertices (entries towards boundary
+// vertices dropped).  vel holds d arrays of cell slots.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr double conv_g(int a, int b) { return b ? 0.5 : -0.5; }
+__host__ __device__ constexpr double conv_m(int a, int b) { return a == b ? 1.0 / 3.0 : 1.0 / 6.0; }
+
+template <int D>
+__global__ __launch_bounds__(256) void k_conv_add(Lat L, const double* __restrict__ vel, double* __restrict__ A) {
+  const int i = blockIdx.x * TX + threadIdx.x;
+  const int j = blockIdx.y * TY + threadIdx.y;
+  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+  if (!interior(L, i, j, kz)) return;
+  const int64_t v = i + (int64_t)j * L.pitch + (int64_t)kz * L.plane;
+  const double hd1 = D == 3 ? L.h * L.h : L.h;
+  constexpr int NS = Dim<D>::NS;
+  double row[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) row[k] = 0.0;
+  for (int sc = 0; sc < (1 << D); ++sc) {  // the vertex is corner s of cell v - s
+    const int s0 = sc & 1, s1 = (sc >> 1) & 1, s2 = (sc >> 2) & 1;
+    const int64_t cell = v - s0 - (int64_t)s1 * L.pitch - (D == 3 ? (int64_t)s2 * L.plane : 0);
+    double vc[3];
+    for (int a = 0; a < D; ++a) vc[a] = vel[(int64_t)a * L.nslot + cell];
+    for (int wc = 0; wc < (1 << D); ++wc) {
+      const int w0 = wc & 1, w1 = (wc >> 1) & 1, w2 = (wc >> 2) & 1;
+      double c;
+      if (D == 2) {
+        c = vc[0] * conv_g(s0, w0) * conv_m(s1, w1) + vc[1] * conv_m(s0, w0) * conv_g(s1, w1);
+      } else {
+        c = vc[0] * conv_g(s0, w0) * conv_m(s1, w1) * conv_m(s2, w2) +
+            vc[1] * conv_m(s0, w0) * conv_g(s1, w1) * conv_m(s2, w2) +
+            vc[2] * conv_m(s0, w0) * conv_m(s1, w1) * conv_g(s2, w2);
+      }
+      const int k = (w0 - s0 + 1) + 3 * (w1 - s1 + 1) + (D == 3 ? 9 * (w2 - s2 + 1) : 0);
+      row[k] += hd1 * c;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    if (!interior(L, i + off_x(k), j + off_y(k), kz + (D == 3 ? off_z(k) : 0))) continue;
+    A[(int64_t)k * L.nslot + v] += row[k];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -784,7 +834,7 @@ void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const doubl
 
 void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
                 const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine, const int8_t* vt_coarse,
-                const int32_t* verts, int64_t n_verts) {
+                const int32_t* verts, int64_t n_verts, bool inject) {
   const int m = Lc.n - 1;
   if (m <= 0) return;
   const int64_t nV = verts ? n_verts : (Lf.d == 3 ? (int64_t)m * m * m : (int64_t)m * m);
@@ -794,14 +844,21 @@ void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double*
     BoxFetch<2> A{Afine, epsf, Lf, vt_fine};
     PFetch<2> P{Pw, Lf, Lc};
     hipLaunchKernelGGL(k_rap<2>, dim3(blocks_for(nV, S::VPB)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse,
-                       verts, n_verts);
+                       verts, n_verts, inject ? 1 : 0);
   } else {
     using S = RapShape<3>;
     BoxFetch<3> A{Afine, epsf, Lf, vt_fine};
     PFetch<3> P{Pw, Lf, Lc};
     hipLaunchKernelGGL(k_rap<3>, dim3(blocks_for(nV, S::VPB)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse,
-                       verts, n_verts);
+                       verts, n_verts, inject ? 1 : 0);
   }
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_conv_add(const Lat& L, const double* vel, double* A, hipStream_t s) {
+  const dim3 g = tile_grid(L), bl(TX, TY, 1);
+  if (L.d == 2) hipLaunchKernelGGL(k_conv_add<2>, g, bl, 0, s, L, vel, A);
+  else hipLaunchKernelGGL(k_conv_add<3>, g, bl, 0, s, L, vel, A);
   QMG_HIP(hipGetLastError());
 }
 

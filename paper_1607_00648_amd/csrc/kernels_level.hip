@@ -402,6 +402,18 @@ __global__ void k_cpoint_sub(Lat Lf, Lat Lc, const T* __restrict__ xf, const T* 
   ec[vc] -= step;
 }
 
+template <int D, typename T>
+__global__ void k_inject(Lat Lf, Lat Lc, const T* __restrict__ rf, T* __restrict__ bc) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int m = Lc.n - 1;
+  const int64_t total = (D == 3) ? (int64_t)m * m * m : (int64_t)m * m;
+  if (t >= total) return;
+  const int i = (int)(t % m) + 1;
+  const int j = (int)((t / m) % m) + 1;
+  const int k = (D == 3) ? (int)(t / ((int64_t)m * m)) + 1 : 0;
+  bc[i + (int64_t)j * Lc.pitch + (int64_t)k * Lc.plane] = rf[3 * (i + (int64_t)j * Lf.pitch + (int64_t)k * Lf.plane)];
+}
+
 template <typename T>
 __global__ void k_coarse_solve(Lat L, const double* __restrict__ Ainv, int nc,
                                const T* __restrict__ b, T* __restrict__ u) {
@@ -626,6 +638,18 @@ void launch_cpoint_sub(const Lat& Lf, const Lat& Lc, const T* xf, const T* yf, T
 }
 template void launch_cpoint_sub<double>(const Lat&, const Lat&, const double*, const double*, double*, hipStream_t);
 template void launch_cpoint_sub<float>(const Lat&, const Lat&, const float*, const float*, float*, hipStream_t);
+
+template <typename T>
+void launch_inject(const Lat& Lf, const Lat& Lc, const T* rf, T* bc, hipStream_t s) {
+  const int64_t m = Lc.n - 1, tot = (Lc.d == 3) ? m * m * m : m * m;
+  if (tot <= 0) return;
+  if (Lf.n != 3 * Lc.n || Lf.d != Lc.d) throw std::runtime_error("launch_inject: levels do not nest");
+  if (Lf.d == 2) hipLaunchKernelGGL((k_inject<2, T>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, Lf, Lc, rf, bc);
+  else hipLaunchKernelGGL((k_inject<3, T>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, Lf, Lc, rf, bc);
+  QMG_HIP(hipGetLastError());
+}
+template void launch_inject<double>(const Lat&, const Lat&, const double*, double*, hipStream_t);
+template void launch_inject<float>(const Lat&, const Lat&, const float*, float*, hipStream_t);
 
 void launch_axpy_mixed(const Lat& L, double* x, const float* e, hipStream_t s) {
   const dim3 g = tile_grid(L), bl(TX, TY, 1);

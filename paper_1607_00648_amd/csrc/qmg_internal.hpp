@@ -186,7 +186,14 @@ void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const doubl
 // only they are visited (the other rows must have been zeroed).
 void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
                 const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine = nullptr,
-                const int8_t* vt_coarse = nullptr, const int32_t* verts = nullptr, int64_t n_verts = 0);
+                const int8_t* vt_coarse = nullptr, const int32_t* verts = nullptr, int64_t n_verts = 0,
+                bool inject = false);
+// Adds the convection term (v constant per cell, d arrays of cell slots in
+// vel) to the full stencils A of level L.
+void launch_conv_add(const Lat& L, const double* vel, double* A, hipStream_t s);
+// Petrov-Galerkin restriction R = I: bc[V] = rf[3V] at interior coarse V.
+template <typename T>
+void launch_inject(const Lat& Lf, const Lat& Lc, const T* rf, T* bc, hipStream_t s);
 // Definiteness check of coarse stencils; counts failing rows into *bad.
 void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s);
 // Hierarchical delta store: per-block zero flags, compaction and payload.  The

@@ -25,6 +25,7 @@ PLAIN_FP64, HIER_FP64, HIER_FP32, HIER_FP16, HIER_BF16, HIER_BPA = 0, 1, 2, 3, 4
 OP_MATVEC, OP_RESIDUAL, OP_JACOBI, OP_RESTRICT, OP_PROLONG, OP_SMOOTH = 0, 1, 2, 3, 4, 5
 SMOOTHERS = {"jacobi": 0, "block": 1}
 CYCLES = {"mult": 0, "add": 1, "bpx": 2}
+RESTRICTIONS = {"transpose": 0, "injection": 1}
 DAMPINGS = {"exp": 0, "const": 1}
 
 TRANSFERS = {"geometric": GEOMETRIC, "galerkin": GALERKIN_DLINEAR, "boxmg": BOXMG}
@@ -42,7 +43,7 @@ class SolverOpts(C.Structure):
                 ("mu_post", C.c_int), ("omega", C.c_double), ("coarsest_level", C.c_int),
                 ("check_definite", C.c_int), ("inner_cycles", C.c_int), ("use_graphs", C.c_int),
                 ("stagnation", C.c_double), ("smoother", C.c_int), ("bj_sweeps", C.c_int),
-                ("cycle", C.c_int), ("damping", C.c_int), ("eps_mf", C.c_double)]
+                ("cycle", C.c_int), ("damping", C.c_int), ("eps_mf", C.c_double), ("restriction", C.c_int)]
 
 
 class SolveReport(C.Structure):
@@ -129,7 +130,8 @@ def _ptr(a: np.ndarray):
 
 def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_level=1,
               check_definite=True, inner_cycles=1, graphs=True, stagnation=0.0, smoother="jacobi",
-              bj_sweeps=1, cycle="mult", damping="exp", eps_mf=1e-8) -> SolverOpts:
+              bj_sweeps=1, cycle="mult", damping="exp", eps_mf=1e-8,
+              restriction="transpose") -> SolverOpts:
     o = SolverOpts()
     o.transfer = TRANSFERS[transfer] if isinstance(transfer, str) else int(transfer)
     o.store = STORES[store] if isinstance(store, str) else int(store)
@@ -145,6 +147,7 @@ def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_l
     o.cycle = CYCLES[cycle] if isinstance(cycle, str) else int(cycle)
     o.damping = DAMPINGS[damping] if isinstance(damping, str) else int(damping)
     o.eps_mf = float(eps_mf)
+    o.restriction = RESTRICTIONS[restriction] if isinstance(restriction, str) else int(restriction)
     return o
 
 
@@ -217,11 +220,15 @@ class Grid:
         return rc
 
     # -- main path -----------------------------------------------------------
-    def set_coefficients(self, eps, f):
+    def set_coefficients(self, eps, f, v=None):
         """eps per leaf cell, f per unknown: NumPy arrays (host) or contiguous
-        float64 torch tensors on the grid's device (used in place)."""
+        float64 torch tensors on the grid's device (used in place).  ``v``
+        (host only): velocities per cell, shape (d,) + cells, for the
+        convection term."""
         if hasattr(eps, "data_ptr") and hasattr(f, "data_ptr"):
             import torch
+            if v is not None:
+                raise ValueError("velocities are taken from host memory")
             for t in (eps, f):
                 if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
                     raise ValueError("device inputs must be contiguous float64 tensors on the GPU")
@@ -234,7 +241,14 @@ class Grid:
         f = np.ascontiguousarray(f, dtype=np.float64)
         if eps.size != self.n_cells or f.size != self.n_unknowns:
             raise ValueError(f"eps must hold {self.n_cells} values and f {self.n_unknowns}")
-        self._check(self.lib.qmg_set_coefficients(self.h, _ptr(eps), 1, _ptr(f), QMG_HOST), self.h)
+        ncomp = 1
+        if v is not None:
+            v = np.ascontiguousarray(v, dtype=np.float64)
+            if v.size != self.dim * self.n_cells:
+                raise ValueError(f"v must hold {self.dim} x {self.n_cells} values")
+            eps = np.concatenate([eps.ravel(), v.ravel()])
+            ncomp = 1 + self.dim
+        self._check(self.lib.qmg_set_coefficients(self.h, _ptr(eps), ncomp, _ptr(f), QMG_HOST), self.h)
 
     def build(self) -> dict:
         rep = SolveReport()

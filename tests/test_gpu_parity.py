@@ -753,3 +753,74 @@ def test_bpa_store_sizes():
     P = W.adaptive_balls(dim=2, base=2, level=3, n_balls=1)
     with pytest.raises(qmg.QmgError):
         qmg.Grid(2, 3, qmg.make_opts("boxmg", "bpa"), base_level=2, refine=P.flags)
+
+
+# ---------------------------------------------------------------------------
+# Convection-diffusion (the circle setup) and Petrov-Galerkin injection
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,L,transfer,restriction", [
+    (2, 4, "boxmg", "transpose"), (2, 5, "galerkin", "injection"),
+    (3, 3, "boxmg", "transpose"), (2, 4, "boxmg", "injection")])
+def test_convection_operators_and_cycles_match_oracle(d, L, transfer, restriction):
+    """The circle flow with eps = 0.1 (1 above z = 1/2 in 3D): the finest
+    operator with its convection term, the BoxMG weights, the (Petrov-)
+    Galerkin coarse operators and six cycles against the oracle.  In 3D the
+    convection entries on the face neighbours (zero in the Q1 diffusion
+    stencil) break diagonal dominance on every level, so the check is off."""
+    qmg = require_gpu()
+    announce(f"convection d={d} L={L} {transfer} R={restriction}")
+    p = W.circle(d, L, 0.1, seed=5)
+    chk = d == 2
+    g = qmg.Grid(d, L, qmg.make_opts(transfer, "plain64", restriction=restriction, check_definite=chk))
+    g.set_coefficients(p.eps, p.f, v=p.meta["v"])
+    info = g.build()
+    H = O.build_hierarchy(p.eps, d, L, transfer=transfer, v=p.meta["v"], restriction=restriction,
+                          check_definite=chk)
+    assert info["coarsest_level_used"] == H.lc
+    for l in range(H.lc, L + 1):
+        Sg, So = g.operator(l), O.csr_to_stencil(H.A[l], d, l)
+        tol = 1e-13 if l == L else 1e-11
+        assert np.abs(Sg - So).max() <= tol * np.abs(So).max(), (l, np.abs(Sg - So).max())
+    for l in range(H.lc + 1, L + 1):
+        assert np.abs(g.prolongation(l) - O.P_to_parent_weights(H.P[l], d, l)).max() <= 1e-11, l
+    rr = g.vcycle(6)
+    u = g.solution()
+    g.close()
+    uo, hist = O.solve(H, O.rhs_from_f(p.f, d, L), cycles=6)
+    np.testing.assert_allclose(rr, hist, rtol=1e-9, atol=1e-14)
+    assert np.abs(u - uo).max() <= 1e-10 * np.abs(uo).max()
+
+
+def test_convection_circle_full_solve_and_errors():
+    """The 2D circle setup at level 6 (728^2 unknowns) with BoxMG solved to
+    1e-8 (residual recomputed by the oracle), and the restrictions of the
+    convection input and of injection."""
+    qmg = require_gpu()
+    announce("convection circle 2D L6 solve")
+    p = W.circle(2, 6, 0.1, seed=5)
+    g = qmg.Grid(2, 6, qmg.make_opts("boxmg", "plain64"))
+    g.set_coefficients(p.eps, p.f, v=p.meta["v"])
+    g.build()
+    rep, _ = g.solve(1e-8, 200)
+    u = g.solution()
+    g.close()
+    assert rep["status"] == "QMG_OK"
+    A = O.stencil_to_csr(O.geometric_stencil(p.eps, 2, 6) + O.convection_stencil(p.meta["v"], 2, 6), 2, 6)
+    b = O.rhs_from_f(p.f, 2, 6)
+    assert np.linalg.norm(b - A @ u) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)
+    g = qmg.Grid(2, 3, qmg.make_opts("boxmg", "hier64"))
+    q = W.circle(2, 3, 0.1)
+    with pytest.raises(qmg.QmgError):      # convection needs the plain store
+        g.set_coefficients(q.eps, q.f, v=q.meta["v"])
+    g.close()
+    with pytest.raises(qmg.QmgError):      # injection is a Petrov-Galerkin restriction
+        qmg.Grid(2, 3, qmg.make_opts("geometric", "plain64", restriction="injection"))
+    with pytest.raises(qmg.QmgError):
+        qmg.Grid(2, 3, qmg.make_opts("boxmg", "plain64", restriction="injection", cycle="add"))
+    g = qmg.Grid(2, 3, qmg.make_opts("boxmg", "plain64"))
+    bad = q.meta["v"].copy()
+    bad[1, 2, 3] = np.inf
+    with pytest.raises(qmg.QmgError):
+        g.set_coefficients(q.eps, q.f, v=bad)
+    g.close()

@@ -181,15 +181,17 @@ def other_workloads(qmg, n):
                                workload="2D sine source, 729^2 cells; BPX cycles, omega 0.8 on every "
                                         "level, geometric transfer, to 1e-8")
     g.close()
-    # (injection, the Petrov-Galerkin variant, needs about 2000 cycles here)
+    # (injection, the other Petrov-Galerkin variant, needs about 2000 cycles here)
     p = W.circle(2, 6, 0.1, seed=5)
-    g = qmg.Grid(p.dim, p.level, qmg.make_opts("boxmg", "plain64"))
-    r = time_solves(g, p.eps, p.f, 1e-8, max(5, n // 5), warmup=1, v=p.meta["v"])
-    out["circle2d_L6_eps0.1"] = dict(
-        r, unknowns=p.n_unknowns,
-        workload="2D convection-diffusion, recirculating flow, eps 0.1, 729^2 cells; BoxMG, R = P^T, "
-                 "plain FP64 store, to 1e-8 (eps, v and f handed over from host memory)")
-    g.close()
+    for restriction, key, rname in (("transpose", "circle2d_L6_eps0.1", "R = P^T"),
+                                    ("aggregation", "circle2d_L6_eps0.1_aggregation", "aggregation R")):
+        g = qmg.Grid(p.dim, p.level, qmg.make_opts("boxmg", "plain64", restriction=restriction))
+        r = time_solves(g, p.eps, p.f, 1e-8, max(5, n // 5), warmup=1, v=p.meta["v"])
+        out[key] = dict(
+            r, unknowns=p.n_unknowns,
+            workload=f"2D convection-diffusion, recirculating flow, eps 0.1, 729^2 cells; BoxMG, {rname}, "
+                     "plain FP64 store, to 1e-8 (eps, v and f handed over from host memory)")
+        g.close()
     P = W.adaptive_balls()
     g = qmg.Grid(P.dim, P.level, qmg.make_opts("boxmg", "bf16", check_definite=False),
                  base_level=P.base, refine=P.flags)

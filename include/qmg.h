@@ -165,12 +165,14 @@ typedef struct {
                           every level (the paper's choice for BPX)           */
   double eps_mf;       /* QMG_HIER_BPA: largest coding error per entry, in
                           (0, 1]; default 1e-8                               */
-  int restriction;     /* QMG_R_TRANSPOSE (default): R = P^T.
-                          QMG_R_INJECTION: R = I, the coarse vertex takes the
-                          fine value at its position, in the restriction and
-                          in A_{l-1} = R A_l P (Petrov-Galerkin, Sect. 3.3 and
-                          the convection results); Galerkin or BoxMG
-                          transfers, multiplicative cycles, regular grids   */
+  int restriction;     /* QMG_R_TRANSPOSE (default): R = P^T.  Petrov-
+                          Galerkin (Sect. 3.3 and the convection results),
+                          in the restriction and in A_{l-1} = R A_l P:
+                          QMG_R_INJECTION, R = I (the coarse vertex takes the
+                          fine value at its position); QMG_R_AGGREGATION, the
+                          coarse vertex sums the 3^d fine vertices nearest to
+                          it (unit weights).  Galerkin or BoxMG transfers,
+                          multiplicative cycles, regular grids              */
 } qmg_solver_opts;
 
 typedef struct {
@@ -290,7 +292,7 @@ int qmg_get_prolongation(const qmg_grid_t* grid, int level, double* weights);
 enum { QMG_SMOOTH_JACOBI = 0, QMG_SMOOTH_BLOCK = 1 };
 enum { QMG_CYCLE_MULT = 0, QMG_CYCLE_ADD = 1, QMG_CYCLE_BPX = 2 };
 enum { QMG_DAMP_EXP = 0, QMG_DAMP_CONST = 1 };
-enum { QMG_R_TRANSPOSE = 0, QMG_R_INJECTION = 1 };
+enum { QMG_R_TRANSPOSE = 0, QMG_R_INJECTION = 1, QMG_R_AGGREGATION = 2 };
 
 enum {
   QMG_OP_MATVEC = 0,     /* out = A x                                         */

@@ -20,7 +20,7 @@ in their docstring.
 from .fem import (element_matrix, geometric_stencil, convection_stencil, offsets, corners,
                   stencil_to_csr, csr_to_stencil, interior_mask, coarsen_eps,
                   rhs_from_f)
-from .transfer import (dlinear_P, boxmg_P, injection_R, boxmg_reference_stepwise,
+from .transfer import (dlinear_P, boxmg_P, injection_R, aggregation_R, boxmg_reference_stepwise,
                        boxmg_reference_Cs, boxmg_reference_matrix)
 from .galerkin import rap, definiteness_violations
 from .store import quantise, delta_zero, hier_deltas, P_to_parent_weights, bpa_value, bpa_encode
@@ -30,7 +30,7 @@ from .solver import (Hierarchy, build_hierarchy, jacobi, residual, vcycle,
                      bpx_cycle, cpoint_positions)
 
 __all__ = [
-    "element_matrix", "geometric_stencil", "convection_stencil", "injection_R", "offsets", "corners",
+    "element_matrix", "geometric_stencil", "convection_stencil", "injection_R", "aggregation_R", "offsets", "corners",
     "stencil_to_csr", "csr_to_stencil", "interior_mask", "coarsen_eps",
     "rhs_from_f", "dlinear_P", "boxmg_P", "boxmg_reference_stepwise",
     "boxmg_reference_Cs", "boxmg_reference_matrix", "rap",

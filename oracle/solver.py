@@ -73,7 +73,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .fem import (geometric_stencil, convection_stencil, stencil_to_csr, csr_to_stencil, coarsen_eps)
-from .transfer import dlinear_P, boxmg_P, injection_R
+from .transfer import dlinear_P, boxmg_P, injection_R, aggregation_R
 from .galerkin import rap, definiteness_violations
 from .store import quantise, delta_zero, EPS_ZERO, fp16_exponent, bpa_value, bpa_encode, BPA_WIDTHS
 
@@ -113,20 +113,21 @@ def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_p
 
     ``v`` (per-cell velocities, shape (d,)+(n,)*d) adds the convection term of
     eq. (1) to the finest operator; its coarse operators then come from the
-    Galerkin product only.  ``restriction`` "injection" takes R = I (the
-    Petrov-Galerkin variant of the convection results) in R A P and in the
-    cycle.  ``perturb`` (tests only) is applied to every Galerkin product
+    Galerkin product only.  ``restriction`` "injection" (R = I) or
+    "aggregation" (unit weights on the 3^d fine vertices within 1 of 3V) takes
+    that R (the Petrov-Galerkin variants of the convection results) in R A P
+    and in the cycle.  ``perturb`` (tests only) is applied to every Galerkin product
     before it is used; the tests pass one-ulp random noise to measure how far
     FP64 rounding alone moves the results (the noise floor of a parity
     comparison)."""
     if transfer not in ("geometric", "galerkin", "boxmg"):
         raise ValueError(transfer)
-    if restriction not in ("transpose", "injection"):
+    if restriction not in ("transpose", "injection", "aggregation"):
         raise ValueError(restriction)
     if v is not None and transfer == "geometric":
         raise ValueError("convection needs Galerkin coarse operators")
-    if restriction == "injection" and transfer == "geometric":
-        raise ValueError("injection is a Petrov-Galerkin restriction")
+    if restriction != "transpose" and transfer == "geometric":
+        raise ValueError("injection and aggregation are Petrov-Galerkin restrictions")
     eps_l = {L: np.asarray(eps, dtype=np.float64)}
     for l in range(L, 0, -1):
         eps_l[l - 1] = coarsen_eps(eps_l[l], d)
@@ -135,7 +136,7 @@ def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_p
         S = S + convection_stencil(v, d, L)
     A = {L: stencil_to_csr(S, d, L)}
     P = {}
-    R = {} if restriction == "injection" else None
+    R = None if restriction == "transpose" else {}
     lc_used = lc
     for l in range(L, lc, -1):
         if transfer == "boxmg":
@@ -145,7 +146,11 @@ def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_p
         if transfer == "geometric":
             Ac = stencil_to_csr(geometric_stencil(eps_l[l - 1], d, l - 1), d, l - 1)
         else:
-            Rl = injection_R(d, l) if R is not None else None
+            Rl = None
+            if restriction == "injection":
+                Rl = injection_R(d, l)
+            elif restriction == "aggregation":
+                Rl = aggregation_R(d, l)
             Ac = rap(A[l], Pl, Rl)
             if R is not None:
                 R[l] = Rl

@@ -87,6 +87,27 @@ def injection_R(d, level_f):
     return sp.csr_matrix((np.ones(len(r)), (r, c)), shape=((nc - 1) ** d, (nf - 1) ** d))
 
 
+def aggregation_R(d, level_f):
+    """Aggregation restriction from level_f to level_f-1: coarse vertex V sums
+    the fine values of its aggregate, the 3^d fine vertices within 1 of 3V
+    (unit weights; the aggregates partition the fine vertices, those next to
+    the boundary belong to boundary vertices and drop out).  Sparse, coarse
+    interior unknowns x fine interior unknowns."""
+    nf = 3 ** level_f
+    nc = nf // 3
+    numf = _unknown_numbering(d, level_f)
+    numc = _unknown_numbering(d, level_f - 1)
+    Vs = np.array(list(itertools.product(range(1, nc), repeat=d)))[:, ::-1]  # x first
+    r = numc[tuple(Vs[:, i] for i in reversed(range(d)))]
+    rows, cols = [], []
+    for o in offsets(d, 1):
+        F = 3 * Vs + np.array(o)
+        rows.append(r)
+        cols.append(numf[tuple(F[:, i] for i in reversed(range(d)))])
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    return sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=((nc - 1) ** d, (nf - 1) ** d))
+
+
 def boxmg_reference_matrix(t, d):
     """C(s) of the reference corner.  ``t`` has shape (batch, 4^d, 3^d): the
     mirrored stencils of the patch points y in {0..3}^d (x fastest).  Returns

@@ -225,10 +225,11 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
   if (o->cycle != QMG_CYCLE_MULT && o->cycle != QMG_CYCLE_ADD && o->cycle != QMG_CYCLE_BPX)
     throw ApiError(QMG_EINVAL, "bad cycle");
   if (o->damping != QMG_DAMP_EXP && o->damping != QMG_DAMP_CONST) throw ApiError(QMG_EINVAL, "bad damping");
-  if (o->restriction != QMG_R_TRANSPOSE && o->restriction != QMG_R_INJECTION)
+  if (o->restriction != QMG_R_TRANSPOSE && o->restriction != QMG_R_INJECTION &&
+      o->restriction != QMG_R_AGGREGATION)
     throw ApiError(QMG_EINVAL, "bad restriction");
-  if (o->restriction == QMG_R_INJECTION && (o->transfer == QMG_GEOMETRIC || o->cycle != QMG_CYCLE_MULT))
-    throw ApiError(QMG_EINVAL, "injection is a Petrov-Galerkin restriction of multiplicative cycles");
+  if (o->restriction != QMG_R_TRANSPOSE && (o->transfer == QMG_GEOMETRIC || o->cycle != QMG_CYCLE_MULT))
+    throw ApiError(QMG_EINVAL, "injection and aggregation are Petrov-Galerkin restrictions of multiplicative cycles");
   if (o->cycle != QMG_CYCLE_MULT && o->smoother != QMG_SMOOTH_JACOBI)
     throw ApiError(QMG_EINVAL, "additive and BPX cycles take one Jacobi step per level");
   const bool adaptive = desc->base_level != 0 && desc->base_level != desc->max_level;
@@ -241,7 +242,8 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
     if (o->smoother == QMG_SMOOTH_BLOCK) throw ApiError(QMG_EINVAL, "block Jacobi runs on regular grids");
     if (o->cycle != QMG_CYCLE_MULT) throw ApiError(QMG_EINVAL, "additive and BPX cycles run on regular grids");
     if (o->store == QMG_HIER_BPA) throw ApiError(QMG_EINVAL, "the bpa store runs on regular grids");
-    if (o->restriction == QMG_R_INJECTION) throw ApiError(QMG_EINVAL, "injection runs on regular grids");
+    if (o->restriction != QMG_R_TRANSPOSE)
+      throw ApiError(QMG_EINVAL, "injection and aggregation run on regular grids");
   }
 }
 
@@ -524,10 +526,10 @@ hipEvent_t* prof_pair(qmg_grid_t* g) {
 }
 
 // Restriction of the residual of level F into the right-hand side of C: P^T,
-// or injection for the Petrov-Galerkin variant.
+// or injection / aggregation for the Petrov-Galerkin variants.
 template <typename T>
 void restrict_to(qmg_grid_t* g, LevelBuf& F, LevelBuf& C, const T* r, T* bc) {
-  if (g->opts.restriction == QMG_R_INJECTION) launch_inject<T>(F.L, C.L, r, bc, S(g));
+  if (g->opts.restriction != QMG_R_TRANSPOSE) launch_inject<T>(F.L, C.L, r, bc, S(g), g->opts.restriction);
   else launch_restrict<T>(F.L, C.L, r, bc, F.P, S(g));
 }
 
@@ -1170,7 +1172,7 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
       const int8_t* mask = (g->adaptive && l == L && !Afine) ? F.vt : nullptr;
       const bool adc = g->adaptive && l - 1 >= g->lb;
       launch_rap(F.L, C.L, Afine, F.eps64, Pw, Ac, s, mask, adc ? C.vt : nullptr, adc ? C.rv : nullptr,
-                 adc ? C.nrv : 0, g->opts.restriction == QMG_R_INJECTION);
+                 adc ? C.nrv : 0, g->opts.restriction);
       merge(l - 1, Ac);
       // the fallback of a failed check raises the coarsest level, which is
       // possible only below the base level of an adaptive spacetree

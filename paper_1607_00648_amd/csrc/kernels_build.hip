@@ -387,7 +387,7 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
                                                          double* __restrict__ Ac,
                                                          const int8_t* __restrict__ vtc,
                                                          const int32_t* __restrict__ vlist, int64_t nlist,
-                                                         int inject) {
+                                                         int rmode) {
   using S = RapShape<D>;
   constexpr int NS = Dim<D>::NS, NC = Dim<D>::NC;
   __shared__ double arow[S::VPB * S::NI * NS];
@@ -439,8 +439,12 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
       if (vco[4 * vs + 3] == 1) {
         const int Vx = vco[4 * vs], Vy = vco[4 * vs + 1], Vz = vco[4 * vs + 2];
         const int ix = 3 * Vx + q % 5 - 2, iy = 3 * Vy + (q / 5) % 5 - 2, iz = (D == 3) ? 3 * Vz + q / 25 - 2 : 0;
-        // Petrov-Galerkin R = I: only the row of i = 3V enters
-        pi = inject ? (q == S::NI / 2 ? 1.0 : 0.0) : P(ix, iy, iz, Vx, Vy, Vz);
+        // Petrov-Galerkin R (rmode 1: injection, only i = 3V; 2: aggregation,
+        // unit weights on the i within 1 of 3V) or R = P^T (rmode 0)
+        if (rmode == 1) pi = q == S::NI / 2 ? 1.0 : 0.0;
+        else if (rmode == 2)
+          pi = (abs(ix - 3 * Vx) <= 1 && abs(iy - 3 * Vy) <= 1 && (D == 2 || abs(iz - 3 * Vz) <= 1)) ? 1.0 : 0.0;
+        else pi = P(ix, iy, iz, Vx, Vy, Vz);
         const int64_t vi = ix + (int64_t)iy * Lf.pitch + (int64_t)iz * Lf.plane;
         const RowSrc<D> row(A, vi);
 #pragma unroll
@@ -834,7 +838,7 @@ void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const doubl
 
 void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
                 const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine, const int8_t* vt_coarse,
-                const int32_t* verts, int64_t n_verts, bool inject) {
+                const int32_t* verts, int64_t n_verts, int rmode) {
   const int m = Lc.n - 1;
   if (m <= 0) return;
   const int64_t nV = verts ? n_verts : (Lf.d == 3 ? (int64_t)m * m * m : (int64_t)m * m);
@@ -844,13 +848,13 @@ void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double*
     BoxFetch<2> A{Afine, epsf, Lf, vt_fine};
     PFetch<2> P{Pw, Lf, Lc};
     hipLaunchKernelGGL(k_rap<2>, dim3(blocks_for(nV, S::VPB)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse,
-                       verts, n_verts, inject ? 1 : 0);
+                       verts, n_verts, rmode);
   } else {
     using S = RapShape<3>;
     BoxFetch<3> A{Afine, epsf, Lf, vt_fine};
     PFetch<3> P{Pw, Lf, Lc};
     hipLaunchKernelGGL(k_rap<3>, dim3(blocks_for(nV, S::VPB)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse,
-                       verts, n_verts, inject ? 1 : 0);
+                       verts, n_verts, rmode);
   }
   QMG_HIP(hipGetLastError());
 }

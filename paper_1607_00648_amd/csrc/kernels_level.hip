@@ -403,7 +403,7 @@ __global__ void k_cpoint_sub(Lat Lf, Lat Lc, const T* __restrict__ xf, const T* 
 }
 
 template <int D, typename T>
-__global__ void k_inject(Lat Lf, Lat Lc, const T* __restrict__ rf, T* __restrict__ bc) {
+__global__ void k_inject(Lat Lf, Lat Lc, const T* __restrict__ rf, T* __restrict__ bc, int rmode) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int m = Lc.n - 1;
   const int64_t total = (D == 3) ? (int64_t)m * m * m : (int64_t)m * m;
@@ -411,7 +411,15 @@ __global__ void k_inject(Lat Lf, Lat Lc, const T* __restrict__ rf, T* __restrict
   const int i = (int)(t % m) + 1;
   const int j = (int)((t / m) % m) + 1;
   const int k = (D == 3) ? (int)(t / ((int64_t)m * m)) + 1 : 0;
-  bc[i + (int64_t)j * Lc.pitch + (int64_t)k * Lc.plane] = rf[3 * (i + (int64_t)j * Lf.pitch + (int64_t)k * Lf.plane)];
+  const int64_t vf = 3 * (i + (int64_t)j * Lf.pitch + (int64_t)k * Lf.plane);
+  T acc = rf[vf];
+  if (rmode == 2) {  // aggregation: the 3^d box around 3V, fixed order (z, y, x)
+    acc = (T)0;
+    for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0); ++oz)
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) acc += rf[vf + ox + (int64_t)oy * Lf.pitch + (int64_t)oz * Lf.plane];
+  }
+  bc[i + (int64_t)j * Lc.pitch + (int64_t)k * Lc.plane] = acc;
 }
 
 template <typename T>
@@ -640,16 +648,16 @@ template void launch_cpoint_sub<double>(const Lat&, const Lat&, const double*, c
 template void launch_cpoint_sub<float>(const Lat&, const Lat&, const float*, const float*, float*, hipStream_t);
 
 template <typename T>
-void launch_inject(const Lat& Lf, const Lat& Lc, const T* rf, T* bc, hipStream_t s) {
+void launch_inject(const Lat& Lf, const Lat& Lc, const T* rf, T* bc, hipStream_t s, int rmode) {
   const int64_t m = Lc.n - 1, tot = (Lc.d == 3) ? m * m * m : m * m;
   if (tot <= 0) return;
   if (Lf.n != 3 * Lc.n || Lf.d != Lc.d) throw std::runtime_error("launch_inject: levels do not nest");
-  if (Lf.d == 2) hipLaunchKernelGGL((k_inject<2, T>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, Lf, Lc, rf, bc);
-  else hipLaunchKernelGGL((k_inject<3, T>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, Lf, Lc, rf, bc);
+  if (Lf.d == 2) hipLaunchKernelGGL((k_inject<2, T>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, Lf, Lc, rf, bc, rmode);
+  else hipLaunchKernelGGL((k_inject<3, T>), dim3(blocks_for(tot, 256)), dim3(256), 0, s, Lf, Lc, rf, bc, rmode);
   QMG_HIP(hipGetLastError());
 }
-template void launch_inject<double>(const Lat&, const Lat&, const double*, double*, hipStream_t);
-template void launch_inject<float>(const Lat&, const Lat&, const float*, float*, hipStream_t);
+template void launch_inject<double>(const Lat&, const Lat&, const double*, double*, hipStream_t, int);
+template void launch_inject<float>(const Lat&, const Lat&, const float*, float*, hipStream_t, int);
 
 void launch_axpy_mixed(const Lat& L, double* x, const float* e, hipStream_t s) {
   const dim3 g = tile_grid(L), bl(TX, TY, 1);

@@ -187,13 +187,15 @@ void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const doubl
 void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
                 const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine = nullptr,
                 const int8_t* vt_coarse = nullptr, const int32_t* verts = nullptr, int64_t n_verts = 0,
-                bool inject = false);
+                int rmode = 0);
 // Adds the convection term (v constant per cell, d arrays of cell slots in
 // vel) to the full stencils A of level L.
 void launch_conv_add(const Lat& L, const double* vel, double* A, hipStream_t s);
-// Petrov-Galerkin restriction R = I: bc[V] = rf[3V] at interior coarse V.
+// Petrov-Galerkin restrictions at interior coarse V: rmode 1, injection
+// bc[V] = rf[3V]; rmode 2, aggregation bc[V] = sum of rf over the 3^d fine
+// vertices within 1 of 3V.  (rmode 0, R = P^T, is launch_restrict.)
 template <typename T>
-void launch_inject(const Lat& Lf, const Lat& Lc, const T* rf, T* bc, hipStream_t s);
+void launch_inject(const Lat& Lf, const Lat& Lc, const T* rf, T* bc, hipStream_t s, int rmode = 1);
 // Definiteness check of coarse stencils; counts failing rows into *bad.
 void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s);
 // Hierarchical delta store: per-block zero flags, compaction and payload.  The

@@ -25,7 +25,7 @@ PLAIN_FP64, HIER_FP64, HIER_FP32, HIER_FP16, HIER_BF16, HIER_BPA = 0, 1, 2, 3, 4
 OP_MATVEC, OP_RESIDUAL, OP_JACOBI, OP_RESTRICT, OP_PROLONG, OP_SMOOTH = 0, 1, 2, 3, 4, 5
 SMOOTHERS = {"jacobi": 0, "block": 1}
 CYCLES = {"mult": 0, "add": 1, "bpx": 2}
-RESTRICTIONS = {"transpose": 0, "injection": 1}
+RESTRICTIONS = {"transpose": 0, "injection": 1, "aggregation": 2}
 DAMPINGS = {"exp": 0, "const": 1}
 
 TRANSFERS = {"geometric": GEOMETRIC, "galerkin": GALERKIN_DLINEAR, "boxmg": BOXMG}

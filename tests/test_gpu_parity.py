@@ -761,7 +761,8 @@ def test_bpa_store_sizes():
 
 @pytest.mark.parametrize("d,L,transfer,restriction", [
     (2, 4, "boxmg", "transpose"), (2, 5, "galerkin", "injection"),
-    (3, 3, "boxmg", "transpose"), (2, 4, "boxmg", "injection")])
+    (3, 3, "boxmg", "transpose"), (2, 4, "boxmg", "injection"),
+    (2, 5, "boxmg", "aggregation"), (3, 3, "galerkin", "aggregation")])
 def test_convection_operators_and_cycles_match_oracle(d, L, transfer, restriction):
     """The circle flow with eps = 0.1 (1 above z = 1/2 in 3D): the finest
     operator with its convection term, the BoxMG weights, the (Petrov-)

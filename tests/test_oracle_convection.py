@@ -120,3 +120,41 @@ def test_circle_convergence_behaviour():
     # the operator is not symmetric
     A = H.A[4]
     assert abs(A - A.T).max() > 1e-3
+
+
+@pytest.mark.parametrize("d,l", [(2, 3), (3, 2)])
+def test_aggregates_partition_the_fine_vertices(d, l):
+    """Aggregation: every fine vertex away from the boundary belongs to exactly
+    one aggregate (the coarse vertex nearest to it), and the coarse equation
+    at V is the sum of the fine equations of its aggregate applied to the
+    prolongated coarse vector."""
+    R = O.aggregation_R(d, l)
+    n = 3 ** l
+    cover = np.asarray(R.sum(axis=0)).ravel().reshape((n - 1,) * d)
+    inner = (slice(1, n - 2),) * d          # lattice 2..n-2
+    assert (cover[inner] == 1).all() and cover.max() == 1
+    assert (np.asarray(R.sum(axis=1)).ravel() == 3 ** d).all()
+    rng = np.random.default_rng(4)
+    v = rng.uniform(-1, 1, (d,) + (n,) * d)
+    A = O.stencil_to_csr(O.geometric_stencil(np.ones((n,) * d), d, l) + F.convection_stencil(v, d, l), d, l)
+    P = O.dlinear_P(d, l)
+    ec = rng.normal(size=P.shape[1])
+    fine = O.fem.lattice_from_unknowns(A @ (P @ ec), d, l)
+    box = sum(F.shifted(fine, o) for o in F.offsets(d))       # sum over the 3^d box around each vertex
+    coarse_pts = (slice(3, n - 2, 3),) * d
+    np.testing.assert_allclose(O.rap(A, P, R) @ ec, box[coarse_pts].ravel(), rtol=0, atol=1e-13)
+
+
+def test_aggregation_converges_like_galerkin():
+    """On the circle setup with eps = 0.1 the aggregation restriction with the
+    BoxMG prolongation converges at nearly the rate of R = P^T (the paper
+    finds them close), while injection is far slower."""
+    p = W.circle(2, 4, 0.1, seed=5)
+    b = O.rhs_from_f(p.f, 2, 4)
+    counts = {}
+    for r in ("transpose", "aggregation", "injection"):
+        H = O.build_hierarchy(p.eps, 2, 4, transfer="boxmg", v=p.meta["v"], restriction=r)
+        _, h = O.solve(H, b, tol=1e-10, max_cycles=400)
+        counts[r] = len(h)
+    assert counts["aggregation"] <= counts["transpose"] + 3
+    assert counts["injection"] > 5 * counts["transpose"]

@@ -23,6 +23,7 @@ from .fem import (element_matrix, geometric_stencil, convection_stencil, offsets
 from .transfer import (dlinear_P, boxmg_P, injection_R, aggregation_R, boxmg_reference_stepwise,
                        boxmg_reference_Cs, boxmg_reference_matrix)
 from .galerkin import rap, definiteness_violations
+from . import refine
 from .store import quantise, delta_zero, hier_deltas, P_to_parent_weights, bpa_value, bpa_encode
 from .solver import (Hierarchy, build_hierarchy, jacobi, residual, vcycle,
                      solve, mixed_solve, direct_solve, raise_coarsest, stagnated,
@@ -37,4 +38,5 @@ __all__ = [
     "definiteness_violations", "quantise", "delta_zero", "hier_deltas",
     "P_to_parent_weights", "bpa_value", "bpa_encode", "raise_coarsest", "stagnated", "block_jacobi", "iota_positions", "additive_cycle", "solve_additive", "bpx_cycle", "cpoint_positions", "Hierarchy", "build_hierarchy", "jacobi",
     "residual", "vcycle", "solve", "mixed_solve", "direct_solve",
+    "refine",
 ]

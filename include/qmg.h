@@ -289,6 +289,18 @@ int qmg_get_operator(const qmg_grid_t* grid, int level, double* stencils);
  * floor(f/3) + (kx,ky,kz) at fine vertex f (zero where it is not a parent). */
 int qmg_get_prolongation(const qmg_grid_t* grid, int level, double* weights);
 
+/* Refinement criterion of the dynamically adaptive runs (Sect. 5), on a
+ * regular grid with FP64 iterates and built operators: per interior vertex
+ * the absolute difference between u and the mean of its 3^d - 1 neighbours;
+ * vertices whose residual |b - A u| is below res_tol are candidates; ten even
+ * bins over the candidates' range are taken from the top until they hold at
+ * least `fraction` of the candidates (the paper: 10^-2 and 0.1); the cells
+ * around every chosen vertex are flagged.  `cell_flags` (host, n^d bytes, x
+ * fastest) receives 1 for a flagged cell of the finest level: the refine
+ * flags of an adaptive grid of one more level.  *n_flagged (nullable) gets
+ * their count.  Overwrites the finest level's residual and work buffer. */
+int qmg_refine_flags(qmg_grid_t* grid, double res_tol, double fraction, uint8_t* cell_flags, int64_t* n_flagged);
+
 enum { QMG_SMOOTH_JACOBI = 0, QMG_SMOOTH_BLOCK = 1 };
 enum { QMG_CYCLE_MULT = 0, QMG_CYCLE_ADD = 1, QMG_CYCLE_BPX = 2 };
 enum { QMG_DAMP_EXP = 0, QMG_DAMP_CONST = 1 };

@@ -122,6 +122,7 @@ struct qmg_grid {
   double* bfin = nullptr;   // mixed: FP64 right-hand side on the finest level
   double* stage = nullptr;  // packed IO staging (nslot of the finest level)
   double* vel = nullptr;    // convection: d arrays of finest cell slots (library-owned)
+  void* rscr = nullptr;     // refinement criterion: extrema and bin counts (library-owned)
   bool has_conv = false;
   double* partial = nullptr;
   int npart = 0;  // entries of `partial`
@@ -1528,6 +1529,7 @@ int create_grid(const qmg_grid_desc* desc, const qmg_solver_opts* opts, void* de
     } catch (...) {
       if (g->owns && g->base) (void)hipFree(g->base);
       if (g->vel) (void)hipFree(g->vel);
+      if (g->rscr) (void)hipFree(g->rscr);
       if (g->hnorm && g->own_hnorm) (void)hipHostFree(g->hnorm);
       if (g->bev) (void)hipEventDestroy(g->bev);
       if (g->own_stream) (void)hipStreamDestroy(g->stream);
@@ -1856,6 +1858,7 @@ int qmg_destroy_grid(qmg_grid_t* g) {
   for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
   if (g->owns && g->base && hipFree(g->base) != hipSuccess) rc = QMG_EHIP;
   if (g->vel && hipFree(g->vel) != hipSuccess) rc = QMG_EHIP;
+  if (g->rscr && hipFree(g->rscr) != hipSuccess) rc = QMG_EHIP;
   if (g->hnorm && g->own_hnorm) (void)hipHostFree(g->hnorm);
   if (g->bev) (void)hipEventDestroy(g->bev);
   if (g->own_stream) (void)hipStreamDestroy(g->stream);
@@ -1897,6 +1900,65 @@ int qmg_get_operator(const qmg_grid_t* cg, int level, double* stencils) {
     QMG_HIP(hipFree(tmp));
     std::vector<double> o = unpitch(B.L, h, NS);
     std::memcpy(stencils, o.data(), o.size() * sizeof(double));
+  });
+}
+
+int qmg_refine_flags(qmg_grid_t* g, double res_tol, double fraction, uint8_t* cell_flags, int64_t* n_flagged) {
+  return guard(g, [&] {
+    if (!g || !cell_flags) throw ApiError(QMG_EINVAL, "null argument");
+    if (g->adaptive) throw ApiError(QMG_EINVAL, "the refinement criterion runs on regular grids");
+    if (g->mixed) throw ApiError(QMG_EINVAL, "the refinement criterion needs FP64 iterates");
+    if (!(res_tol > 0.0) || !(fraction > 0.0 && fraction <= 1.0))
+      throw ApiError(QMG_EINVAL, "need res_tol > 0 and 0 < fraction <= 1");
+    need_ops(g);
+    LevelBuf& F = g->lv[g->Lmax];
+    const Lat& L = F.L;
+    hipStream_t s = S(g);
+    const int64_t ncell = L.d == 3 ? (int64_t)L.n * L.n * L.n : (int64_t)L.n * L.n;
+    // r = b - A u on the finest level
+    launch_stencil<double>(L, 2, (const double*)F.u, (const double*)F.b, (double*)F.r, eps_of<double>(F), F.A,
+                           0.0, nullptr, nullptr, s);
+    if (!g->rscr) QMG_HIP(hipMalloc(&g->rscr, 256));
+    unsigned long long* mm = (unsigned long long*)g->rscr;
+    int* cnt = (int*)((char*)g->rscr + 64);
+    const unsigned long long init[2] = {~0ull, 0ull};
+    QMG_HIP(hipMemcpyAsync(mm, init, sizeof(init), hipMemcpyHostToDevice, s));
+    double* delta = g->stage;  // nslot doubles
+    launch_refine_delta(L, (const double*)F.u, (const double*)F.r, res_tol, delta, mm, s);
+    unsigned long long ext[2];
+    QMG_HIP(hipMemcpyAsync(ext, mm, sizeof(ext), hipMemcpyDeviceToHost, s));
+    QMG_HIP(hipStreamSynchronize(s));
+    int64_t flagged = 0;
+    double lo = 0.0, hi = 0.0;
+    std::memcpy(&lo, &ext[0], sizeof(double));
+    std::memcpy(&hi, &ext[1], sizeof(double));
+    if (ext[0] == ~0ull || hi == 0.0) {  // no candidate, or nothing varies
+      std::memset(cell_flags, 0, (size_t)ncell);
+    } else {
+      const int spread = hi > lo ? 1 : 0;
+      const double width = (hi - lo) / 10.0;
+      launch_zero<int>(cnt, 10, s);
+      launch_refine_hist(L, delta, lo, width, spread, cnt, s);
+      int counts[10];
+      QMG_HIP(hipMemcpyAsync(counts, cnt, sizeof(counts), hipMemcpyDeviceToHost, s));
+      QMG_HIP(hipStreamSynchronize(s));
+      int64_t ncand = 0;
+      for (int b = 0; b < 10; ++b) ncand += counts[b];
+      const double need = fraction * (double)ncand;
+      int64_t cum = 0;
+      int kstar = 9;
+      for (int b = 9; b >= 0; --b) {
+        cum += counts[b];
+        kstar = b;
+        if ((double)cum >= need) break;
+      }
+      uint8_t* dflags = (uint8_t*)F.t;  // nslot iterates: at least ncell bytes
+      launch_refine_cells(L, delta, lo, width, spread, kstar, dflags, s);
+      QMG_HIP(hipMemcpyAsync(cell_flags, dflags, (size_t)ncell, hipMemcpyDeviceToHost, s));
+      QMG_HIP(hipStreamSynchronize(s));
+      for (int64_t c = 0; c < ncell; ++c) flagged += cell_flags[c] ? 1 : 0;
+    }
+    if (n_flagged) *n_flagged = flagged;
   });
 }
 

@@ -422,6 +422,86 @@ __global__ void k_inject(Lat Lf, Lat Lc, const T* __restrict__ rf, T* __restrict
   bc[i + (int64_t)j * Lc.pitch + (int64_t)k * Lc.plane] = acc;
 }
 
+// Refinement criterion (dynamic adaptivity, Sect. 5), regular level.  Per
+// lattice slot: |mean of the 3^d - 1 neighbours - u| (summed in stencil
+// order, x fastest, centre skipped) at interior vertices whose |r| < res_tol,
+// -1 elsewhere; mm gets the bit patterns of the smallest and largest value
+// (non-negative doubles order like their bits).
+template <int D>
+__global__ __launch_bounds__(256) void k_refine_delta(Lat L, const double* __restrict__ u,
+                                                      const double* __restrict__ r, double res_tol,
+                                                      double* __restrict__ delta,
+                                                      unsigned long long* __restrict__ mm) {
+  constexpr int NS = Dim<D>::NS;
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  unsigned long long lo = ~0ull, hi = 0ull;
+  if (v < L.nslot) {
+    const int i = (int)(v % L.pitch);
+    const int j = (int)((v / L.pitch) % (L.n + 1));
+    const int k = (D == 3) ? (int)(v / L.plane) : 0;
+    const bool in = i >= 1 && i < L.n && j >= 1 && j < L.n && (D == 2 || (k >= 1 && k < L.n));
+    double out = -1.0;
+    if (in && fabs(r[v]) < res_tol) {
+      double acc = 0.0;
+#pragma unroll
+      for (int e = 0; e < NS; ++e) {
+        if (e == NS / 2) continue;
+        acc += u[v + off_x(e) + (int64_t)off_y(e) * L.pitch + (D == 3 ? (int64_t)off_z(e) * L.plane : 0)];
+      }
+      out = fabs(acc / (double)(NS - 1) - u[v]);
+      lo = hi = (unsigned long long)__double_as_longlong(out);
+    }
+    delta[v] = out;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long a = __shfl_xor(lo, o, 64), b = __shfl_xor(hi, o, 64);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+  }
+  if ((threadIdx.x & 63) == 0 && lo != ~0ull) {
+    atomicMin(&mm[0], lo);
+    atomicMax(&mm[1], hi);
+  }
+}
+
+// Bin of a candidate's difference: ten even bins over [lo, hi] (all in the
+// top bin when hi == lo).
+__device__ inline int refine_bin(double dl, double lo, double width, int spread) {
+  if (!spread) return 9;
+  const int b = (int)floor((dl - lo) / width);
+  return b < 9 ? b : 9;
+}
+
+__global__ __launch_bounds__(256) void k_refine_hist(const double* __restrict__ delta, int64_t n, double lo,
+                                                     double width, int spread, int* __restrict__ cnt) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const double dl = delta[v];
+  if (dl >= 0.0) atomicAdd(&cnt[refine_bin(dl, lo, width, spread)], 1);
+}
+
+// Cell (i,j,k) of the level (x fastest in `flags`) is flagged when one of its
+// 2^d corners is a candidate in bin >= kstar.
+template <int D>
+__global__ __launch_bounds__(256) void k_refine_cells(Lat L, const double* __restrict__ delta, double lo,
+                                                      double width, int spread, int kstar,
+                                                      uint8_t* __restrict__ flags) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int n = L.n;
+  const int64_t total = (D == 3) ? (int64_t)n * n * n : (int64_t)n * n;
+  if (t >= total) return;
+  const int i = (int)(t % n), j = (int)((t / n) % n), k = (D == 3) ? (int)(t / ((int64_t)n * n)) : 0;
+  uint8_t f = 0;
+  for (int s = 0; s < (1 << D); ++s) {
+    const int64_t v = (i + (s & 1)) + (int64_t)(j + ((s >> 1) & 1)) * L.pitch +
+                      (D == 3 ? (int64_t)(k + ((s >> 2) & 1)) * L.plane : 0);
+    const double dl = delta[v];
+    if (dl >= 0.0 && refine_bin(dl, lo, width, spread) >= kstar) f = 1;
+  }
+  flags[t] = f;
+}
+
 template <typename T>
 __global__ void k_coarse_solve(Lat L, const double* __restrict__ Ainv, int nc,
                                const T* __restrict__ b, T* __restrict__ u) {
@@ -658,6 +738,28 @@ void launch_inject(const Lat& Lf, const Lat& Lc, const T* rf, T* bc, hipStream_t
 }
 template void launch_inject<double>(const Lat&, const Lat&, const double*, double*, hipStream_t, int);
 template void launch_inject<float>(const Lat&, const Lat&, const float*, float*, hipStream_t, int);
+
+void launch_refine_delta(const Lat& L, const double* u, const double* r, double res_tol, double* delta,
+                         unsigned long long* mm, hipStream_t s) {
+  if (L.d == 2) hipLaunchKernelGGL(k_refine_delta<2>, dim3(blocks_for(L.nslot, 256)), dim3(256), 0, s, L, u, r, res_tol, delta, mm);
+  else hipLaunchKernelGGL(k_refine_delta<3>, dim3(blocks_for(L.nslot, 256)), dim3(256), 0, s, L, u, r, res_tol, delta, mm);
+  QMG_HIP(hipGetLastError());
+}
+void launch_refine_hist(const Lat& L, const double* delta, double lo, double width, int spread, int* cnt,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_hist, dim3(blocks_for(L.nslot, 256)), dim3(256), 0, s, delta, L.nslot, lo, width,
+                     spread, cnt);
+  QMG_HIP(hipGetLastError());
+}
+void launch_refine_cells(const Lat& L, const double* delta, double lo, double width, int spread, int kstar,
+                         uint8_t* flags, hipStream_t s) {
+  const int64_t tot = (L.d == 3) ? (int64_t)L.n * L.n * L.n : (int64_t)L.n * L.n;
+  if (L.d == 2)
+    hipLaunchKernelGGL(k_refine_cells<2>, dim3(blocks_for(tot, 256)), dim3(256), 0, s, L, delta, lo, width, spread, kstar, flags);
+  else
+    hipLaunchKernelGGL(k_refine_cells<3>, dim3(blocks_for(tot, 256)), dim3(256), 0, s, L, delta, lo, width, spread, kstar, flags);
+  QMG_HIP(hipGetLastError());
+}
 
 void launch_axpy_mixed(const Lat& L, double* x, const float* e, hipStream_t s) {
   const dim3 g = tile_grid(L), bl(TX, TY, 1);

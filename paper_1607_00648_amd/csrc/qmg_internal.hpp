@@ -139,6 +139,16 @@ void launch_prolong(const Lat& Lf, const Lat& Lc, const T* ec, T* uf, const Stor
 // the BPX surplus of a level's Jacobi step
 template <typename T>
 void launch_cpoint_sub(const Lat& Lf, const Lat& Lc, const T* xf, const T* yf, T* ec, hipStream_t s);
+// Refinement criterion on a regular level: per-slot differences (-1 where no
+// candidate) with their bit-pattern minimum and maximum in mm[0..1]; the
+// ten-bin histogram of the candidates; the flags of the cells (x fastest)
+// with a corner in bin >= kstar.
+void launch_refine_delta(const Lat& L, const double* u, const double* r, double res_tol, double* delta,
+                         unsigned long long* mm, hipStream_t s);
+void launch_refine_hist(const Lat& L, const double* delta, double lo, double width, int spread, int* cnt,
+                        hipStream_t s);
+void launch_refine_cells(const Lat& L, const double* delta, double lo, double width, int spread, int kstar,
+                         uint8_t* flags, hipStream_t s);
 void launch_axpy_mixed(const Lat& L, double* x, const float* e, hipStream_t s);
 
 // Conversions between iterate types and between packed unknown vectors and

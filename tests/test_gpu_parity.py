@@ -825,3 +825,43 @@ def test_convection_circle_full_solve_and_errors():
     with pytest.raises(qmg.QmgError):
         g.set_coefficients(q.eps, q.f, v=bad)
     g.close()
+
+
+# ---------------------------------------------------------------------------
+# Refinement criterion (dynamic adaptivity)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,L,fraction", [(2, 5, 0.1), (2, 4, 0.3), (3, 3, 0.1)])
+def test_refine_flags_match_oracle(d, L, fraction):
+    """A seeded iterate (smooth field, bumps and noise) on a checkerboard
+    setup: the cells flagged by the mean-difference criterion with ten bins
+    equal the oracle's, for a residual threshold between two of the oracle's
+    residual magnitudes near their median."""
+    qmg = require_gpu()
+    announce(f"refine flags d={d} L={L} fraction={fraction}")
+    p = W.random_checkerboard(d, L, seed=8, values=(1.0, 10.0), blocks=9 if L > 3 else 3)
+    g = _grid(qmg, p, "boxmg", "hier64")
+    g.build()
+    n = 3 ** L
+    rng = np.random.default_rng(31)
+    x = np.meshgrid(*([np.arange(1, n) / n] * d), indexing="ij")
+    u = np.prod([np.sin(np.pi * xi) for xi in x], axis=0)
+    u = u + 0.01 * rng.normal(size=u.shape)
+    idx = rng.integers(0, n - 1, size=(6, d))
+    u[tuple(idx.T)] += 0.5
+    u = u.ravel()
+    g.set_solution(u)
+    A = O.stencil_to_csr(O.geometric_stencil(p.eps, d, L), d, L)
+    b = O.rhs_from_f(p.f, d, L)
+    r = b - A @ u
+    s = np.sort(np.abs(r))
+    k = len(s) // 2
+    while s[k + 1] - s[k] <= 1e-9 * s[k]:
+        k += 1
+    res_tol = 0.5 * (s[k] + s[k + 1])
+    flags = g.refine_flags(res_tol, fraction)
+    g.close()
+    want = O.refine.refinement_flags(O.fem.lattice_from_unknowns(u, d, L),
+                                     O.fem.lattice_from_unknowns(r, d, L), d, res_tol, fraction)
+    assert want.any() and not want.all()
+    assert np.array_equal(flags, want), (int(flags.sum()), int(want.sum()))

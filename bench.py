@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated), keyed by
 # (store, dim, level); the kernel summary under profiles/ gives the commands.
 # An entry is removed whenever that kernel changes.
-MEASURED_TRAFFIC = {("hier64", 2, 6): 6730.4 * 2.0 * 1024 + 8326.5 * 1.0 * 1024}
+MEASURED_TRAFFIC = {("hier64", 2, 6): 6734.4 * 2.0 * 1024 + 8326.5 * 1.0 * 1024}
 
 # Algorithmic bytes per finest vertex of one Jacobi sweep or one residual, each
 # streamed on its own: eps, u, b read and u' (or r) written once, stencils

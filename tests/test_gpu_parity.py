@@ -865,3 +865,70 @@ def test_refine_flags_match_oracle(d, L, fraction):
                                      O.fem.lattice_from_unknowns(r, d, L), d, res_tol, fraction)
     assert want.any() and not want.all()
     assert np.array_equal(flags, want), (int(flags.sum()), int(want.sum()))
+
+
+# ---------------------------------------------------------------------------
+# Smallest grids and degenerate settings of the optional paths
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("case", ["bpx", "bpa_loose", "convection_injection", "convection_aggregation"])
+def test_optional_paths_on_the_smallest_grid(d, case):
+    """Level 2 (two levels, an exact level-1 solve): BPX cycles, the bpa store
+    with eps_mf = 1 (every delta codes to zero, so the operators are the
+    rediscretised ones plus nothing), and the Petrov-Galerkin convection
+    variants, each against the oracle over four cycles."""
+    qmg = require_gpu()
+    announce(f"smallest grid d={d} {case}")
+    L = 2
+    if case.startswith("convection"):
+        r = case.split("_")[1]
+        p = W.circle(d, L, 0.1, seed=2)
+        g = qmg.Grid(d, L, qmg.make_opts("boxmg", "plain64", restriction=r, check_definite=False))
+        g.set_coefficients(p.eps, p.f, v=p.meta["v"])
+        H = O.build_hierarchy(p.eps, d, L, transfer="boxmg", v=p.meta["v"], restriction=r,
+                              check_definite=False)
+        step = lambda: O.solve(H, O.rhs_from_f(p.f, d, L), cycles=4)
+    else:
+        p = W.random_checkerboard(d, L, seed=4, values=(1.0, 30.0), blocks=3)
+        if case == "bpx":
+            g = _grid(qmg, p, "boxmg", "hier64", cycle="bpx", damping="const")
+            H = O.build_hierarchy(p.eps, d, L, transfer="boxmg")
+            step = lambda: O.solve_additive(H, O.rhs_from_f(p.f, d, L), damping="const", cycles=4, bpx=True)
+        else:
+            g = _grid(qmg, p, "boxmg", "bpa", eps_mf=1.0)
+            H = O.build_hierarchy(p.eps, d, L, transfer="boxmg")
+            Hq = O.solver.quantised_hierarchy(H, "bpa", eps_mf=1.0)
+            step = lambda: O.solve(Hq, O.rhs_from_f(p.f, d, L), cycles=4)
+    info = g.build()
+    rr = g.vcycle(4)
+    u = g.solution()
+    g.close()
+    uo, hist = step()
+    assert info["coarsest_level_used"] == 1
+    np.testing.assert_allclose(rr, hist, rtol=1e-9, atol=1e-14)
+    assert np.abs(u - uo).max() <= 1e-10 * np.abs(uo).max()
+
+
+def test_refine_flags_degenerate_settings():
+    """No candidate (threshold below every residual): nothing is flagged;
+    fraction 1: every candidate is chosen, as in the oracle."""
+    qmg = require_gpu()
+    announce("refine flags degenerate")
+    d, L = 2, 3
+    p = W.random_checkerboard(d, L, seed=9, values=(1.0, 5.0), blocks=3)
+    g = _grid(qmg, p, "boxmg", "hier64")
+    g.build()
+    n = 3 ** L
+    u = np.random.default_rng(5).normal(size=(n - 1) ** d)
+    g.set_solution(u)
+    A = O.stencil_to_csr(O.geometric_stencil(p.eps, d, L), d, L)
+    r = O.rhs_from_f(p.f, d, L) - A @ u
+    tiny = 0.5 * np.abs(r).min()
+    assert not g.refine_flags(tiny, 0.1).any()
+    big = 2.0 * np.abs(r).max()
+    flags = g.refine_flags(big, 1.0)
+    g.close()
+    want = O.refine.refinement_flags(O.fem.lattice_from_unknowns(u, d, L),
+                                     O.fem.lattice_from_unknowns(r, d, L), d, big, 1.0)
+    assert np.array_equal(flags, want) and want.all()

@@ -123,6 +123,7 @@ struct qmg_grid {
   double* stage = nullptr;  // packed IO staging (nslot of the finest level)
   double* vel = nullptr;    // convection: d arrays of finest cell slots (library-owned)
   void* rscr = nullptr;     // refinement criterion: extrema and bin counts (library-owned)
+  double* norm_dst = nullptr;  // where the finest pass leaves its norm partials (null: partial)
   bool has_conv = false;
   double* partial = nullptr;
   int npart = 0;  // entries of `partial`
@@ -335,6 +336,14 @@ int64_t n_interior(const Lat& L) {
   return L.d == 3 ? m * m * m : m * m;
 }
 
+// Eager cycles whose finest 2D pass leaves the residual norm partials can
+// defer the per-cycle reduction and run it once for several cycles.
+constexpr int kDeferNorms = 32;
+bool defers_norms(const qmg_grid_t* g) {
+  return !g->mixed && !g->adaptive && g->d == 2 && g->opts.smoother == QMG_SMOOTH_JACOBI &&
+         g->opts.cycle == QMG_CYCLE_MULT;
+}
+
 int npartials(const Lat& L) {
   return (L.pitch / 64) * ((L.n + 1 + 3) / 4) * (L.d == 3 ? L.n + 1 : 1);
 }
@@ -424,6 +433,7 @@ void layout(qmg_grid_t* g, Arena& a) {
   }
   g->stage = a.take<double>(g->lv[L].L.nslot);
   g->npart = (int)std::max<int64_t>(npartials(g->lv[L].L), ad_partials);
+  if (defers_norms(g)) g->npart = std::max(g->npart, kDeferNorms * pass2d_partials(g->lv[L].L));
   g->partial = a.take<double>(g->npart);
   g->dscal = a.take<double>(8);
   g->dcount = a.take<int>(8);
@@ -700,7 +710,7 @@ bool vcycle(qmg_grid_t* g, int l, bool zero_init, bool want_norm = false) {
     restrict_to<T>(g, F, Cb, (const T*)F.r, (T*)Cb.b);
     vcycle<T>(g, l - 1, true);
     const bool norm = want_norm && l == g->Lmax;
-    passes<T>(g, F, &Cb, nu, false, norm, norm ? g->partial : nullptr);
+    passes<T>(g, F, &Cb, nu, false, norm, norm ? (g->norm_dst ? g->norm_dst : g->partial) : nullptr);
     return norm;
   }
   smooth<T>(g, F, mu, zero_init);
@@ -957,6 +967,28 @@ void enqueue_batch(qmg_grid_t* g, int B) {
   if (graph_usable(g)) {
     ensure_graph(g);
     for (int c = 0; c < B; ++c) QMG_HIP(hipGraphLaunch(g->gexec, S(g)));
+  } else if (defers_norms(g)) {
+    // the finest passes of up to kDeferNorms cycles leave their norm partials
+    // side by side; one launch reduces them
+    LevelBuf& F = g->lv[g->Lmax];
+    const int np = pass2d_partials(F.L);
+    int done = 0;
+    try {
+      while (done < B) {
+        const int chunk = std::min(B - done, kDeferNorms);
+        for (int c = 0; c < chunk; ++c) {
+          g->norm_dst = g->partial + (int64_t)c * np;
+          if (!one_cycle(g)) throw HipError("internal: a deferred-norm cycle left no partials");
+        }
+        launch_sum_partials_multi(g->partial, np, np, chunk, g->dscal, g->dhist + done, g->dctr, done + chunk,
+                                  S(g));
+        done += chunk;
+      }
+    } catch (...) {
+      g->norm_dst = nullptr;
+      throw;
+    }
+    g->norm_dst = nullptr;
   } else {
     for (int c = 0; c < B; ++c) cycle_and_norm(g);
   }

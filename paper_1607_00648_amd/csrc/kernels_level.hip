@@ -318,6 +318,33 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict_
   }
 }
 
+// The same sum for `chunk` cycles at once: workgroup c reduces the n partials
+// at p + c * stride (in k_sum_partials' order) into hist[c]; the last one also
+// leaves its sum in out[0] and sets the history counter to ctr_end.
+__global__ __launch_bounds__(1024) void k_sum_partials_multi(const double* __restrict__ p, int n, int stride,
+                                                             int chunk, double* __restrict__ out,
+                                                             double* __restrict__ hist,
+                                                             int* __restrict__ counter, int ctr_end) {
+  __shared__ double red[16];
+  const int c = blockIdx.x;
+  const double* q = p + (int64_t)c * stride;
+  double x = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x += q[i];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    hist[c] = s;
+    if (c == chunk - 1) {
+      out[0] = s;
+      counter[0] = ctr_end;
+    }
+  }
+}
+
 // b_c(V) = sum over fine f = 3V + o, o in [-2,2]^d, of P(f,V) r(f)  (R = P^T).
 template <int D, typename T, int SRC, int FMT>
 __global__ __launch_bounds__(256) void k_restrict(Lat Lf, Lat Lc, const T* __restrict__ r,
@@ -669,6 +696,14 @@ void launch_prep_input(double* x, int64_t n, double scale, bool positive, double
 void launch_sum_partials(const double* partial, int n, double* out, hipStream_t s, double* hist,
                          int* counter, int cap) {
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, partial, n, out, hist, counter, cap);
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_sum_partials_multi(const double* partial, int n, int stride, int chunk, double* out, double* hist,
+                               int* counter, int ctr_end, hipStream_t s) {
+  if (chunk <= 0) return;
+  hipLaunchKernelGGL(k_sum_partials_multi, dim3((unsigned)chunk), dim3(1024), 0, s, partial, n, stride, chunk, out,
+                     hist, counter, ctr_end);
   QMG_HIP(hipGetLastError());
 }
 

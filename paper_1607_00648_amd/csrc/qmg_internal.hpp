@@ -125,6 +125,10 @@ void launch_prep_input(double* x, int64_t n, double scale, bool positive, double
                        hipStream_t s);
 void launch_sum_partials(const double* partial, int n, double* out, hipStream_t s,
                          double* hist = nullptr, int* counter = nullptr, int cap = 0);
+// `chunk` cycles' partial sums at once (stride apart) into hist[0..chunk);
+// out[0] gets the last and the history counter becomes ctr_end.
+void launch_sum_partials_multi(const double* partial, int n, int stride, int chunk, double* out, double* hist,
+                               int* counter, int ctr_end, hipStream_t s);
 
 // Restriction bc = P^T r (gather per coarse vertex).  Lf: fine lattice.
 template <typename T>

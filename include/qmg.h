@@ -298,7 +298,9 @@ int qmg_get_prolongation(const qmg_grid_t* grid, int level, double* weights);
  * around every chosen vertex are flagged.  `cell_flags` (host, n^d bytes, x
  * fastest) receives 1 for a flagged cell of the finest level: the refine
  * flags of an adaptive grid of one more level.  *n_flagged (nullable) gets
- * their count.  Overwrites the finest level's residual and work buffer. */
+ * their count.  Overwrites the finest level's residual and work buffer; the
+ * first call allocates 256 bytes of device memory, held until the grid ends.
+ * QMG_EINVAL on an adaptive grid, FP32 iterates or arguments out of range. */
 int qmg_refine_flags(qmg_grid_t* grid, double res_tol, double fraction, uint8_t* cell_flags, int64_t* n_flagged);
 
 enum { QMG_SMOOTH_JACOBI = 0, QMG_SMOOTH_BLOCK = 1 };

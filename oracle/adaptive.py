@@ -54,6 +54,9 @@ notes):
   several refined patches takes the value of the one whose orthant has + signs
   on the most significant shared axes (the lowest rank below); the others must
   agree (rounding aside).
+
+Test infrastructure: only the tests, the smoke check and the benchmark's CPU
+baseline use this package.
 """
 from __future__ import annotations
 

@@ -28,6 +28,9 @@ NumPy axes ordered (z, y, x), so x is the fastest index.  Stencil arrays have a
 leading axis of length 3^d; entry ``k`` belongs to offset ``o`` (coordinate
 order x, y, z) with ``k = sum_i (o_i + 1) 3^i``.  Interior unknowns are the
 interior lattice vertices, numbered with x fastest.
+
+Test infrastructure: only the tests, the smoke check and the benchmark's CPU
+baseline use this package.
 """
 from __future__ import annotations
 

@@ -8,6 +8,9 @@
   finer coarsest level.  Reading: row V fails when a_VV <= 0 or
   a_VV < (1 - 1e-10) * sum_{W != V} |a_VW| (the slack absorbs rounding in rows
   that are exactly weakly dominant, such as the interior Laplacian).
+
+Test infrastructure: only the tests, the smoke check and the benchmark's CPU
+baseline use this package.
 """
 from __future__ import annotations
 

@@ -61,6 +61,9 @@ Readings:
   x += V32(fp32(b - A x)) whose inner V-cycles run in FP32 on operators rebuilt
   from quantised hierarchical deltas (see ``store``); the coarsest solve of the
   inner cycle stays in FP64.
+
+Test infrastructure: only the tests, the smoke check and the benchmark's CPU
+baseline use this package.
 """
 from __future__ import annotations
 

@@ -31,6 +31,9 @@ decisions:
   rounding compounds over the levels (several hundred ulp of the row scale after
   three Galerkin products); 2^-40 leaves a wide margin above it while staying far
   below any iterate precision.
+
+Test infrastructure: only the tests, the smoke check and the benchmark's CPU
+baseline use this package.
 """
 from __future__ import annotations
 

@@ -30,6 +30,9 @@ lacks one column separator; it is read as the nine entries s_{5,0..8}.
 Mirroring is expressed with an orthant sign sigma in {-1,+1}^d: the reference
 point y in {0..3}^d of coarse vertex V is fine vertex 3V + sigma*y and the
 mirrored stencil offset o' is the true offset sigma*o'.
+
+Test infrastructure: only the tests, the smoke check and the benchmark's CPU
+baseline use this package.
 """
 from __future__ import annotations
 

@@ -932,3 +932,40 @@ def test_refine_flags_degenerate_settings():
     want = O.refine.refinement_flags(O.fem.lattice_from_unknowns(u, d, L),
                                      O.fem.lattice_from_unknowns(r, d, L), d, big, 1.0)
     assert np.array_equal(flags, want) and want.all()
+
+
+# ---------------------------------------------------------------------------
+# The timed variants at their full size
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["additive_exp", "bpx_const", "bpa_checkerboard"])
+def test_timed_variants_full_size(case):
+    """The level-6 workloads the benchmark times besides the main one: the
+    sine setup under additive (exponential damping) and BPX (omega on every
+    level) cycles, and the 729^2-cell checkerboard with the bpa store at
+    eps_mf = 1e-8; each solve reaches 1e-8 by the oracle's FP64 recomputation
+    of the residual, and the bpa solve takes the FP64 store's cycle count."""
+    qmg = require_gpu()
+    announce(f"timed variant full size {case}")
+    if case == "bpa_checkerboard":
+        p = W.checkerboard2d(0)
+        g = _grid(qmg, p, "boxmg", "bpa", eps_mf=1e-8)
+        ref = _grid(qmg, p, "boxmg", "hier64")
+        ref.build()
+        rref, _ = ref.solve(1e-8, 400)
+        ref.close()
+        A = O.stencil_to_csr(O.geometric_stencil(p.eps, 2, 6), 2, 6)
+    else:
+        p = W.sin_source(2, 6)
+        kw = dict(cycle="add", damping="exp") if case == "additive_exp" else dict(cycle="bpx", damping="const")
+        g = _grid(qmg, p, "geometric", "hier64", omega=0.8, **kw)
+        A = O.stencil_to_csr(O.geometric_stencil(p.eps, 2, 6), 2, 6)
+    g.build()
+    rep, _ = g.solve(1e-8, 1000)
+    u = g.solution()
+    g.close()
+    assert rep["status"] == "QMG_OK"
+    b = O.rhs_from_f(p.f, 2, 6)
+    assert np.linalg.norm(b - A @ u) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)
+    if case == "bpa_checkerboard":
+        assert rep["cycles"] == rref["cycles"]

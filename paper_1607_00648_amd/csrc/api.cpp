@@ -579,6 +579,7 @@ FusedArgs<T> fused_args(qmg_grid_t* g, int lf) {
   a.lf = lf;
   a.mu_pre = g->opts.mu_pre;
   a.mu_post = g->opts.mu_post;
+  a.bj_sweeps = g->opts.smoother == QMG_SMOOTH_BLOCK ? g->opts.bj_sweeps : 0;
   a.coarse_direct = g->coarse_direct ? 1 : 0;
   a.nc = g->nc;
   a.omega = (T)g->opts.omega;
@@ -606,8 +607,7 @@ bool p_stored(const qmg_grid_t* g) {
 template <typename T>
 int choose_fused_top(qmg_grid_t* g, bool& pw_lds) {
   int best = -1;
-  if (g->opts.smoother != QMG_SMOOTH_JACOBI) return best;  // the fused coarse cycle runs Jacobi
-  if (g->opts.restriction != QMG_R_TRANSPOSE) return best;  // and restricts with P^T
+  if (g->opts.restriction != QMG_R_TRANSPOSE) return best;  // the fused cycle restricts with P^T
   for (int lf = g->lc; lf < g->lb && lf - g->lc + 1 <= kMaxFused; ++lf) {
     for (int pl = 1; pl >= 0; --pl) {
       FusedArgs<T> a = fused_args<T>(g, lf);

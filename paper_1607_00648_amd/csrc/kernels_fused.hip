@@ -131,10 +131,79 @@ struct Fused {
     __syncthreads();
   }
 
+  // One block Jacobi step on level s (Sect. "Spacetree block smoothers"), as
+  // the per-level kernels take it: bj_sweeps Gauss-Seidel sweeps over every
+  // patch's iota-vertices in u (in place; patch = 3^d vertices of one coarser
+  // cell, iota = no coordinate divisible by 3), then the damped Jacobi update
+  // of the other vertices into out, iota-vertices copied.
+  __device__ void bj_step(int s, T* u, T* out, bool from_zero) const {
+    constexpr int NP = NC;  // 2^d iota-vertices per patch
+    const int ws = w(s), ms = m(s);
+    const T* bv = vec(s, 2);
+    if (from_zero) {
+      for (int idx = threadIdx.x; idx < nint(s); idx += BS) {
+        int i, j, k;
+        vertex_of(idx, ms, mag[s], D, i, j, k);
+        u[cidx(ws, i, j, k)] = (T)0;
+      }
+      __syncthreads();
+    }
+    const int np = a.L[s].n / 3;
+    const int npatch = D == 3 ? np * np * np : np * np;
+    for (int t = threadIdx.x; t < npatch; t += BS) {
+      const int px = t % np, py = (t / np) % np, pz = D == 3 ? t / (np * np) : 0;
+      T C[NP][NP], sp[NP], uu[NP];
+      int cp[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int lx = p & 1, ly = (p >> 1) & 1, lz = (p >> 2) & 1;
+        const int i = 3 * px + 1 + lx, j = 3 * py + 1 + ly, k = D == 3 ? 3 * pz + 1 + lz : 0;
+        const int c = cidx(ws, i, j, k);
+        cp[p] = c;
+        const T* row = rows(s) + (int64_t)((i - 1) + ms * ((j - 1) + ms * (D == 3 ? k - 1 : 0))) * NS;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) C[p][q] = (T)0;
+        T rest = bv[c];
+#pragma unroll
+        for (int e = 0; e < NS; ++e) {
+          const int qx = lx + off_x(e), qy = ly + off_y(e), qz = D == 3 ? lz + off_z(e) : 0;
+          if (qx >= 0 && qx <= 1 && qy >= 0 && qy <= 1 && qz >= 0 && qz <= 1)
+            C[p][qx | (qy << 1) | (qz << 2)] = row[e];
+          else
+            rest -= row[e] * u[c + off_x(e) + ws * (off_y(e) + (D == 3 ? ws * off_z(e) : 0))];
+        }
+        sp[p] = rest;
+        uu[p] = u[c];
+      }
+      for (int sw = 0; sw < a.bj_sweeps; ++sw) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          T r = sp[p];
+#pragma unroll
+          for (int q = 0; q < NP; ++q) r -= C[p][q] * uu[q];
+          uu[p] += r / C[p][p];
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < NP; ++p) u[cp[p]] = uu[p];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nint(s); idx += BS) {
+      int i, j, k;
+      vertex_of(idx, ms, mag[s], D, i, j, k);
+      const int c = cidx(ws, i, j, k);
+      const T* row = rows(s) + (int64_t)idx * NS;
+      const bool iota = i % 3 != 0 && j % 3 != 0 && (D == 2 || k % 3 != 0);
+      out[c] = iota ? u[c] : u[c] + a.omega * (bv[c] - row_dot_lds(row, u, ws, c)) / row[NS / 2];
+    }
+    __syncthreads();
+  }
+
   // returns the buffer index (0 = u, 1 = t) holding the result
   __device__ int smooth(int s, int cur, int mu, bool zero_init) const {
     for (int q = 0; q < mu; ++q) {
-      sweep(s, vec(s, cur), vec(s, 1 - cur), zero_init && q == 0);
+      if (a.bj_sweeps > 0) bj_step(s, vec(s, cur), vec(s, 1 - cur), zero_init && q == 0);
+      else sweep(s, vec(s, cur), vec(s, 1 - cur), zero_init && q == 0);
       cur = 1 - cur;
     }
     return cur;

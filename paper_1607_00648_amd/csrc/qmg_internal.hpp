@@ -235,6 +235,7 @@ constexpr int kMaxFused = 8;
 template <typename T>
 struct FusedArgs {
   int lc, lf, mu_pre, mu_post, coarse_direct, nc;
+  int bj_sweeps;  // block Jacobi smoother: Gauss-Seidel sweeps per patch (0: Jacobi)
   T omega;
   const double* Ainv;
   Lat L[kMaxFused];

@@ -126,7 +126,8 @@ struct qmg_grid {
   double* norm_dst = nullptr;  // where the finest pass leaves its norm partials (null: partial)
   bool has_conv = false;
   double* partial = nullptr;
-  int npart = 0;  // entries of `partial`
+  int npart = 0;   // entries of `partial`
+  int npart1 = 0;  // partials of one residual norm (stride of deferred ones)
   double* dscal = nullptr;
   int* dcount = nullptr;
   int32_t* dtotal = nullptr;
@@ -336,13 +337,10 @@ int64_t n_interior(const Lat& L) {
   return L.d == 3 ? m * m * m : m * m;
 }
 
-// Eager cycles whose finest 2D pass leaves the residual norm partials can
-// defer the per-cycle reduction and run it once for several cycles.
+// Eager cycles on regular grids defer the per-cycle reduction of the residual
+// norm partials and run it once for several cycles.
 constexpr int kDeferNorms = 32;
-bool defers_norms(const qmg_grid_t* g) {
-  return !g->mixed && !g->adaptive && g->d == 2 && g->opts.smoother == QMG_SMOOTH_JACOBI &&
-         g->opts.cycle == QMG_CYCLE_MULT;
-}
+bool defers_norms(const qmg_grid_t* g) { return !g->adaptive; }
 
 int npartials(const Lat& L) {
   return (L.pitch / 64) * ((L.n + 1 + 3) / 4) * (L.d == 3 ? L.n + 1 : 1);
@@ -433,7 +431,8 @@ void layout(qmg_grid_t* g, Arena& a) {
   }
   g->stage = a.take<double>(g->lv[L].L.nslot);
   g->npart = (int)std::max<int64_t>(npartials(g->lv[L].L), ad_partials);
-  if (defers_norms(g)) g->npart = std::max(g->npart, kDeferNorms * pass2d_partials(g->lv[L].L));
+  g->npart1 = g->npart;
+  if (defers_norms(g)) g->npart = kDeferNorms * g->npart1;
   g->partial = a.take<double>(g->npart);
   g->dscal = a.take<double>(8);
   g->dcount = a.take<int>(8);
@@ -801,9 +800,14 @@ double read_scalar(qmg_grid_t* g) {
 // is written to the finest inner right-hand side on the way).
 // On an adaptive spacetree: the composite residual over the leaves of every
 // level, after the refined and hanging values are made consistent.
-void enqueue_residual_norm(qmg_grid_t* g, bool record, bool partials_ready = false) {
+// Residual norm partials of the finest level into `dst` (default: partial),
+// then (sum) their reduction, recorded in the history when `record`.  Returns
+// the number of partials.
+int enqueue_residual_norm(qmg_grid_t* g, bool record, bool partials_ready = false, double* dst = nullptr,
+                          bool sum = true) {
   LevelBuf& F = g->lv[g->Lmax];
   int np = 0;
+  double* part = dst ? dst : g->partial;
   if (partials_ready) {  // left by the cycle's last fused pass
     np = pass2d_partials(F.L);
   } else if (g->adaptive && g->mixed) {
@@ -826,15 +830,17 @@ void enqueue_residual_norm(qmg_grid_t* g, bool record, bool partials_ready = fal
       np += B.ntiles;
     }
   } else if (g->mixed) {
-    launch_residual_mixed(F.L, g->x64, g->bfin, (float*)F.b, F.eps64, g->partial, &np, S(g));
+    launch_residual_mixed(F.L, g->x64, g->bfin, (float*)F.b, F.eps64, part, &np, S(g));
   } else {
     launch_stencil<double>(F.L, 2, (const double*)F.u, (const double*)F.b, (double*)F.r, F.eps64,
-                           F.A, 0.0, g->partial, &np, S(g));
+                           F.A, 0.0, part, &np, S(g));
   }
+  if (!sum) return np;
   if (record)
-    launch_sum_partials(g->partial, np, g->dscal, S(g), g->dhist, g->dctr, kHistCap);
+    launch_sum_partials(part, np, g->dscal, S(g), g->dhist, g->dctr, kHistCap);
   else
-    launch_sum_partials(g->partial, np, g->dscal, S(g));
+    launch_sum_partials(part, np, g->dscal, S(g));
+  return np;
 }
 
 double finest_residual_norm(qmg_grid_t* g) {
@@ -968,20 +974,25 @@ void enqueue_batch(qmg_grid_t* g, int B) {
     ensure_graph(g);
     for (int c = 0; c < B; ++c) QMG_HIP(hipGraphLaunch(g->gexec, S(g)));
   } else if (defers_norms(g)) {
-    // the finest passes of up to kDeferNorms cycles leave their norm partials
-    // side by side; one launch reduces them
-    LevelBuf& F = g->lv[g->Lmax];
-    const int np = pass2d_partials(F.L);
+    // the residual norm partials of up to kDeferNorms cycles lie side by side
+    // (left by the finest 2D pass or by the residual kernel); one launch
+    // reduces them
     int done = 0;
     try {
       while (done < B) {
         const int chunk = std::min(B - done, kDeferNorms);
+        int np = -1;
         for (int c = 0; c < chunk; ++c) {
-          g->norm_dst = g->partial + (int64_t)c * np;
-          if (!one_cycle(g)) throw HipError("internal: a deferred-norm cycle left no partials");
+          double* dst = g->partial + (int64_t)c * g->npart1;
+          g->norm_dst = dst;
+          const bool ready = one_cycle(g);
+          const int npc = enqueue_residual_norm(g, true, ready, dst, false);
+          if (npc > g->npart1 || (np >= 0 && npc != np))
+            throw HipError("internal: residual norm partials do not fit their stride");
+          np = npc;
         }
-        launch_sum_partials_multi(g->partial, np, np, chunk, g->dscal, g->dhist + done, g->dctr, done + chunk,
-                                  S(g));
+        launch_sum_partials_multi(g->partial, np, g->npart1, chunk, g->dscal, g->dhist + done, g->dctr,
+                                  done + chunk, S(g));
         done += chunk;
       }
     } catch (...) {

@@ -133,6 +133,14 @@ def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_l
               check_definite=True, inner_cycles=1, graphs=True, stagnation=0.0, smoother="jacobi",
               bj_sweeps=1, cycle="mult", damping="exp", eps_mf=1e-8,
               restriction="transpose") -> SolverOpts:
+    """qmg_solver_opts from names (the header documents every field):
+    transfer "geometric" | "galerkin" | "boxmg"; store "plain64" | "hier64" |
+    "hier32" | "hier16" | "bf16" | "bpa" (eps_mf: the bpa coding error);
+    smoother "jacobi" | "block" (bj_sweeps Gauss-Seidel sweeps per patch);
+    cycle "mult" | "add" | "bpx" with damping "exp" | "const"; restriction
+    "transpose" | "injection" | "aggregation"; stagnation > 0 raises the
+    coarsest level when a cycle reduces the residual by less than that
+    factor."""
     o = SolverOpts()
     o.transfer = TRANSFERS[transfer] if isinstance(transfer, str) else int(transfer)
     o.store = STORES[store] if isinstance(store, str) else int(store)

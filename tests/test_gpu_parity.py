@@ -551,9 +551,9 @@ def test_block_jacobi_step_matches_oracle(d, L, transfer, store, sweeps):
 @pytest.mark.parametrize("d,L,transfer,store,sweeps", [(2, 4, "galerkin", "hier64", 1), (2, 5, "boxmg", "hier64", 3),
                                                        (3, 3, "boxmg", "hier64", 1), (2, 4, "geometric", "plain64", 2)])
 def test_block_jacobi_cycles_match_oracle(d, L, transfer, store, sweeps):
-    """V(2,2) cycles with the block smoother on every level (the fused
-    coarse-level kernel is bypassed): residual history and iterate against
-    the oracle."""
+    """V(2,2) cycles with the block smoother on every level (the coarse
+    levels inside the fused LDS kernel): residual history and iterate
+    against the oracle."""
     qmg = require_gpu()
     announce(f"block jacobi cycles d={d} L={L} {transfer} {store} sweeps={sweeps}")
     p = W.random_checkerboard(d, L, seed=11, values=(1.0, 1e2), blocks=9 if L > 3 else 3)

@@ -28,12 +28,13 @@ def _alone(qmg, p, opts, tol):
     return u, rep
 
 
-@pytest.mark.parametrize("store", ["hier16", "hier64"])
-def test_results_identical_alone_and_in_mix(store):
+@pytest.mark.parametrize("store,extra", [("hier16", {}), ("hier64", {}), ("bpa", {}),
+                                         ("hier64", {"smoother": "block", "bj_sweeps": 2})])
+def test_results_identical_alone_and_in_mix(store, extra):
     qmg = require_gpu()
-    announce(f"serving mix {store}")
+    announce(f"serving mix {store} {extra}")
     probs = _requests(12)
-    opts = qmg.make_opts("boxmg", store)
+    opts = qmg.make_opts("boxmg", store, **extra)
     alone = [_alone(qmg, p, opts, 1e-8) for p in probs]
     budget = 4 * max(qmg.workspace_bytes(p.dim, p.level, opts) for p in probs)
     srv = qmg.Server(budget, max_slots=6)

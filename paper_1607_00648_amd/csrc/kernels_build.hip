@@ -378,7 +378,6 @@ struct RapShape {
 //   2. one task per fine j of the region: t(j) = sum_i P(i,V) a(i,j);
 //   3. one thread per entry W - V in [-1,1]^d: sum over the j within 2 of 3W
 //      of t(j) P(j,W).
-// BoxMG weights P(j, .) of the region are staged in LDS in phase 1.
 // vtc (nullable): coarse vertex classes; rows of vertices that are not
 // refined are left zero.  vlist (nullable): the nlist coarse vertices to form
 // (interior indices); the others are not visited.
@@ -393,7 +392,6 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
   __shared__ double arow[S::VPB * S::NI * NS];
   __shared__ double piv[S::VPB * S::NI];
   __shared__ double tj[S::VPB * S::NR];
-  __shared__ double pw[S::VPB * S::NR * NC];
   __shared__ int vco[S::VPB * 4];  // per vertex: x, y, z, active
   __shared__ double tpart[S::VPB * Dim<D>::NS * S::NP];
   const int m = Lc.n - 1;
@@ -415,22 +413,7 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
     vco[4 * t + 3] = on;  // 0: none, 1: form the row, 2: write a zero row
   }
   __syncthreads();
-  // phase 1: weights and rows of the i of each vertex; staged BoxMG weights
-  if (P.W) {
-#pragma unroll
-    for (int e = t; e < S::VPB * S::NR * NC; e += S::NT) {
-      const int vs = e / (S::NR * NC);
-      const int r = e - vs * (S::NR * NC);
-      const int kap = r % NC, jr = r / NC;
-      double w = 0.0;
-      if (vco[4 * vs + 3] == 1) {
-        const int jx = 3 * vco[4 * vs] - 3 + jr % S::RW, jy = 3 * vco[4 * vs + 1] - 3 + (jr / S::RW) % S::RW;
-        const int jz = (D == 3) ? 3 * vco[4 * vs + 2] - 3 + jr / (S::RW * S::RW) : 0;
-        w = P.W[(int64_t)kap * Lf.nslot + jx + (int64_t)jy * Lf.pitch + (int64_t)jz * Lf.plane];
-      }
-      pw[e] = w;
-    }
-  }
+  // phase 1: weights and rows of the i of each vertex
   {
     const int vs = t / S::NI, q = t - (t / S::NI) * S::NI;
     if (vs < S::VPB) {
@@ -494,7 +477,6 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
       const int zl = (D == 3) ? max(3 * dz - 2, -3) + part : 0;
       const int zh = (D == 3) ? min(min(3 * dz + 2, 3), zl) : 0;
       if (interior(Lc, Vx + dx, Vy + dy, Vz + dz)) {
-        const double* pr = pw + vs * S::NR * NC;
         for (int jz = zl; jz <= zh; ++jz)
           for (int jy = yl; jy <= yh; ++jy)
 #pragma unroll 5
@@ -504,8 +486,10 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
               const int kx = dx - (jx + 3) / 3 + 1, ky = dy - (jy + 3) / 3 + 1;
               const int kz = (D == 3) ? dz - (jz + 3) / 3 + 1 : 0;
               double pj;
-              if (P.W) {
-                pj = pr[jr * NC + (kx | (ky << 1) | (kz << 2))];
+              if (P.W) {  // BoxMG weight of W at j, from the L2-resident weight arrays
+                const int64_t vj = (3 * Vx + jx) + (int64_t)(3 * Vy + jy) * Lf.pitch +
+                                   (D == 3 ? (int64_t)(3 * Vz + jz) * Lf.plane : 0);
+                pj = P.W[(int64_t)(kx | (ky << 1) | (kz << 2)) * Lf.nslot + vj];
               } else {
                 const int rx = (jx + 3) % 3, ry = (jy + 3) % 3, rz = (D == 3) ? (jz + 3) % 3 : 0;
                 pj = dlin1(rx, kx) * dlin1(ry, ky) * (D == 3 ? dlin1(rz, kz) : 1.0);

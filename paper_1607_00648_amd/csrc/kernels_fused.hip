@@ -59,6 +59,22 @@ struct Fused {
   __device__ T* rows(int s) const { return (T*)(smem + a.lds_rows[s]); }
   __device__ T* pw(int s) const { return (T*)(smem + a.lds_pw[s]); }
 
+  // Levels with at most 64 interior vertices are worked by wave 0 alone.
+  __device__ bool small(int s) const { return nint(s) <= 64; }
+  // Barrier after a phase: the whole workgroup, or, when the phase's writers
+  // and the next phase's readers all lie in wave 0 (wave0), an ordering of
+  // that wave's LDS accesses only.  The condition is uniform, so every wave
+  // passes the same sequence of workgroup barriers.
+  __device__ void sync(bool wave0) const {
+    if (wave0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();
+    }
+  }
+
   __device__ T row_dot_lds(const T* row, const T* u, int ws, int c) const {
     T acc = (T)0;
 #pragma unroll
@@ -128,7 +144,7 @@ struct Fused {
       const T dg = row[NS / 2];
       out[c] = from_zero ? a.omega * bv[c] / dg : u[c] + a.omega * (bv[c] - row_dot_lds(row, u, ws, c)) / dg;
     }
-    __syncthreads();
+    sync(small(s));
   }
 
   // One block Jacobi step on level s (Sect. "Spacetree block smoothers"), as
@@ -146,7 +162,7 @@ struct Fused {
         vertex_of(idx, ms, mag[s], D, i, j, k);
         u[cidx(ws, i, j, k)] = (T)0;
       }
-      __syncthreads();
+      sync(small(s));
     }
     const int np = a.L[s].n / 3;
     const int npatch = D == 3 ? np * np * np : np * np;
@@ -187,7 +203,7 @@ struct Fused {
 #pragma unroll
       for (int p = 0; p < NP; ++p) u[cp[p]] = uu[p];
     }
-    __syncthreads();
+    sync(small(s));
     for (int idx = threadIdx.x; idx < nint(s); idx += BS) {
       int i, j, k;
       vertex_of(idx, ms, mag[s], D, i, j, k);
@@ -196,7 +212,7 @@ struct Fused {
       const bool iota = i % 3 != 0 && j % 3 != 0 && (D == 2 || k % 3 != 0);
       out[c] = iota ? u[c] : u[c] + a.omega * (bv[c] - row_dot_lds(row, u, ws, c)) / row[NS / 2];
     }
-    __syncthreads();
+    sync(small(s));
   }
 
   // returns the buffer index (0 = u, 1 = t) holding the result
@@ -234,7 +250,7 @@ struct Fused {
         const int c = cidx(ws, i, j, k);
         r[c] = vec(s, 2)[c] - row_dot_lds(rows(s) + (int64_t)idx * NS, u, ws, c);
       }
-      __syncthreads();
+      sync(small(s));  // the restriction's threads are a subset
       const int wc = w(s - 1), mc = m(s - 1);
       T* bc = vec(s - 1, 2);
       for (int idx = threadIdx.x; idx < nint(s - 1); idx += BS) {
@@ -253,7 +269,7 @@ struct Fused {
             }
         bc[cidx(wc, I, J, K)] = acc;
       }
-      __syncthreads();
+      sync(small(s - 1));
     }
     // coarsest level
     if (a.coarse_direct) {
@@ -271,12 +287,14 @@ struct Fused {
         vertex_of(row, ms, mag[0], D, i, j, k);
         u0[cidx(ws, i, j, k)] = (T)acc;
       }
-      __syncthreads();
+      sync(small(0) && a.nc <= 64);
       cur[0] = 0;
     } else {
       cur[0] = smooth(0, 0, a.mu_pre + a.mu_post, true);
     }
     for (int s = 1; s <= top; ++s) {
+      // first level above the wave-0 levels: their results to every wave
+      if (small(s - 1) && !small(s)) __syncthreads();
       const int ws = w(s), ms = m(s), wc = w(s - 1);
       T* u = vec(s, cur[s]);
       const T* ec = vec(s - 1, cur[s - 1]);
@@ -294,7 +312,7 @@ struct Fused {
         }
         u[fc] += acc;
       }
-      __syncthreads();
+      sync(small(s));
       cur[s] = smooth(s, cur[s], a.mu_post, false);
     }
     // result of level lf back to global memory

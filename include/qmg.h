@@ -99,15 +99,46 @@ enum {
   QMG_HIER_BPA = 5
 };
 
+/* Refinement regions of an adaptive spacetree (Sect. 2: every cell decides on
+ * its own whether it is refined).  A region refines every existing cell of
+ * levels base..level-1 that meets it, so its cells reach `level`.  Parameters
+ * (host doubles, copied during the call), positions in the unit cube, x first:
+ *  - QMG_REGION_BALL: centre (d values), radius r > 0 (d + 1 values).  A cell
+ *    meets the ball when the distance from the centre to the closed cell box
+ *    is below r.
+ *  - QMG_REGION_LEVELSET_BAND: the band around the zero set of a random-
+ *    Fourier-feature level set phi(x) = a sum_{m<M} cos(k_m . x + p_m):
+ *    tau >= 0, a, M >= 1, then the M wave vectors k_m (d values each), then
+ *    the M phases p_m (3 + M (d + 1) values).  A cell of level l with low
+ *    corner x0 meets the band when, over its 3^d sample points
+ *    x0 + o h_l / 2 (o in {0,1,2}^d), min |phi| < tau or phi takes both signs.
+ *  - QMG_REGION_CELL_LIST: cells given as (level, i, j[, k]) groups of 1 + d
+ *    values (cell indices 0 <= i < 3^level); listed cells of levels
+ *    base..level-1 that exist are refined.
+ * QMG_EINVAL for an unknown kind or a parameter count or value out of range. */
+enum { QMG_REGION_BALL = 0, QMG_REGION_LEVELSET_BAND = 1, QMG_REGION_CELL_LIST = 2 };
+
+typedef struct {
+  int kind;               /* QMG_REGION_*                                      */
+  int level;              /* refine meeting cells down to this level (<= L)   */
+  const double* params;   /* host, n_params values (layout above)             */
+  int n_params;
+} qmg_region;
+
 typedef struct {
   int dim;        /* 2 or 3                                                   */
   int max_level;  /* finest level L >= 2 (3^L cells per axis when refined)   */
   int base_level; /* 0 (or L): regular grid of level L.  1 <= base < L:
                      adaptive spacetree, every cell refined down to `base`,
-                     further refinement given by `refine`                      */
-  const uint8_t* refine; /* adaptive only, host: for levels base..L-1 in turn,
-                     one byte per cell of that level (x fastest; nonzero =
-                     refine); flags of cells that do not exist are ignored     */
+                     further refinement given by `refine` and `regions`       */
+  const uint8_t* refine; /* adaptive, host, nullable: for levels base..L-1 in
+                     turn, one byte per cell of that level (x fastest; nonzero
+                     = refine); flags of cells that do not exist are ignored  */
+  int n_regions;  /* adaptive: number of regions (0 when only `refine`)       */
+  const qmg_region* regions; /* host, n_regions entries; evaluated by the
+                     library (in parallel on the host) during
+                     qmg_workspace_bytes and qmg_create_grid, OR-ed with
+                     `refine`                                                 */
 } qmg_grid_desc;
 
 typedef struct {
@@ -190,6 +221,13 @@ typedef struct {
 
 /* Library version string (static storage). */
 const char* qmg_version(void);
+
+/* The refinement flags an adaptive description stands for, evaluated on the
+ * host (no device needed): `refine` OR-ed with every region, as the
+ * `refine` layout (levels base..L-1, one byte per cell, x fastest; 1 =
+ * refined, for existing cells; bytes of cells that do not exist are 0 unless
+ * `refine` set them).  n_flags must be sum over l = base..L-1 of 3^(l d). */
+int qmg_region_flags(const qmg_grid_desc* desc, uint8_t* flags, int64_t n_flags);
 
 /* Device bytes a grid needs for `desc` and `opts` (worst case over stores). */
 int qmg_workspace_bytes(const qmg_grid_desc* desc, const qmg_solver_opts* opts, size_t* bytes);
@@ -348,20 +386,28 @@ typedef struct {
 /* Starts a server on the current HIP device (1 <= max_slots <= 256).  The
  * whole `hbm_budget` is reserved on the device here (QMG_ENOMEM if it cannot
  * be) and request workspaces are carved from it, so serving itself allocates
- * no device memory; the reservation is freed by qmg_server_destroy. */
-int qmg_server_create(size_t hbm_budget, int max_slots, qmg_server_t** out);
+ * no device memory; the reservation is freed by qmg_server_destroy.  Every
+ * slot runs on a stream of its own.  `stream` (a hipStream_t, nullable) is the
+ * caller's: served work starts after the work already enqueued on it, and
+ * qmg_server_drain makes it wait for all served work, so later work on it
+ * needs no host synchronisation.  The server clock (arrival times) starts
+ * here. */
+int qmg_server_create(size_t hbm_budget, int max_slots, void* stream, qmg_server_t** out);
 
 /* Queues a solve on a regular grid (eps: n^d cell values, f: (n-1)^d
- * unknowns, host memory, copied).  QMG_EINVAL for an adaptive description or
- * if the request could never fit the budget.  The ticket
- * identifies it in qmg_server_poll. */
+ * unknowns, host memory, copied).  t_arrival: the request's arrival in
+ * seconds on the server clock; it is not admitted before then, and its
+ * latency counts from then (a negative value: arrives at submission).  This
+ * lets a caller hand over a whole arrival schedule at once.  QMG_EINVAL for
+ * an adaptive description, a NaN arrival or a request that could never fit
+ * the budget.  The ticket identifies it in qmg_server_poll. */
 int qmg_server_submit(qmg_server_t* server, const qmg_grid_desc* desc, const qmg_solver_opts* opts,
                       const double* eps, const double* f, double rel_tol, int max_cycles,
-                      uint64_t* ticket);
+                      double t_arrival, uint64_t* ticket);
 
 /* Non-blocking.  *done = 1 once the request retired; then u_out (nullable,
  * (n-1)^d host values), report (nullable) and latency_s (nullable: retire time
- * minus submit time, seconds) are filled, the ticket is released, and the
+ * minus arrival time, seconds) are filled, the ticket is released, and the
  * request's own status is returned (QMG_ENOTCONV etc.). */
 int qmg_server_poll(qmg_server_t* server, uint64_t ticket, int* done, double* u_out,
                     qmg_solve_report* report, double* latency_s);

@@ -71,7 +71,7 @@ from .fem import (geometric_stencil, offsets, shifted, csr_to_stencil, stencil_t
                   interior_mask, corners, corner_index, element_matrix)
 from .transfer import dlinear_P, boxmg_P, boxmg_reference_stepwise, _gather_reference, _points
 from .fem import _unknown_numbering
-from .galerkin import rap
+from .galerkin import rap, definiteness_violations
 from . import solver as S
 
 OUT, LEAF, REFINED, HANGING = 0, 1, 2, 3
@@ -369,11 +369,18 @@ def boxmg_adaptive_P(G: AdaptiveGrid, S_full, l, check=True):
 
 
 def build_adaptive(G: AdaptiveGrid, eps_leaf, transfer="galerkin", omega=0.6, mu_pre=2, mu_post=2,
-                   lc=1):
+                   lc=1, check_definite=False, direct_max=S.COARSE_DIRECT_MAX):
     """Operators of every level: rediscretised rows for unrefined vertices,
     Galerkin rows P^T A P (d-linear or BoxMG P) or rediscretised rows for
     refined ones; prolongations ``H.P[l]`` (also used for the hanging values);
-    the levels up to the base level form a regular hierarchy below."""
+    the levels up to the base level form a regular hierarchy below.
+
+    ``check_definite``: the definiteness check of Sect. 3.3 on the Galerkin
+    operators of the complete levels below the base level (a row with a
+    non-positive diagonal or without diagonal dominance); the first level
+    whose coarser operator fails becomes the coarsest level, which is at most
+    the base level (the levels above it hold unknowns).  ``direct_max``: the
+    largest coarsest level solved exactly (see ``solver.factor_coarse``)."""
     if transfer not in ("geometric", "galerkin", "boxmg"):
         raise ValueError(transfer)
     d = G.d
@@ -388,6 +395,7 @@ def build_adaptive(G: AdaptiveGrid, eps_leaf, transfer="galerkin", omega=0.6, mu
     Hs = hanging_stencils(G, eps) if transfer == "boxmg" else {}
     H.S = {G.L: geo[G.L] * act[G.L][None]}
     H.P = {}
+    lc_used = lc
     for l in range(G.L, lc, -1):
         if transfer == "boxmg":
             H.P[l] = boxmg_adaptive_P(G, H.S[l] + Hs[l], l) if l > G.base else boxmg_P(H.S[l], d, l)
@@ -398,17 +406,22 @@ def build_adaptive(G: AdaptiveGrid, eps_leaf, transfer="galerkin", omega=0.6, mu
         else:
             gal = csr_to_stencil(rap(stencil_to_csr(H.S[l], d, l), H.P[l]), d, l - 1)
             Sc = np.where((G.vtype[l - 1] == REFINED)[None], gal, geo[l - 1])
+        if (check_definite and transfer != "geometric" and l - 1 < G.base
+                and len(definiteness_violations(stencil_to_csr(Sc, d, l - 1))) > 0):
+            del H.P[l]
+            lc_used = l
+            break
         # rows only for leaf and refined vertices
         H.S[l - 1] = Sc * act[l - 1][None]
     # regular hierarchy from the base level down (correction scheme)
+    lc = lc_used
     A = {l: stencil_to_csr(H.S[l], d, l) for l in range(lc, G.base + 1)}
     P = {l: H.P[l] for l in range(lc + 1, G.base + 1)}
     Hr = S.Hierarchy(d, G.base, lc, transfer, A, P, {l: eps[l] for l in range(lc, G.base + 1)},
-                     omega, mu_pre, mu_post)
-    import scipy.linalg as sla
-    if A[lc].shape[0] <= S.COARSE_DIRECT_MAX:
-        Hr.coarse_lu = sla.lu_factor(A[lc].toarray())
+                     omega, mu_pre, mu_post, direct_max=direct_max)
+    Hr.coarse_lu = S.factor_coarse(A[lc], direct_max)
     H.regular = Hr
+    H.lc = lc
     return H
 
 

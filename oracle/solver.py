@@ -20,8 +20,10 @@ Readings:
   same iterates as the paper's FAS/HTMG form (A_{l-1} I u cancels R A P I u), and
   for rediscretised coarse operators it equals classic FAS, which keeps the fine
   solution a fixed point.
-* The coarsest level is solved exactly when it has at most COARSE_DIRECT_MAX
-  unknowns, otherwise by mu_pre + mu_post Jacobi sweeps from zero.
+* The coarsest level is solved exactly when it has at most ``direct_max``
+  unknowns (COARSE_DIRECT_MAX by default; a dense LU factorisation up to that
+  size, a sparse LU factorisation above it, both library routines), otherwise
+  by mu_pre + mu_post Jacobi sweeps from zero.
 * The relative residual is the unweighted 2-norm over interior unknowns relative
   to ||b||_2 (the paper reduces ||r||_2 by 1e8).
 * Stagnation is read as ||r_k|| > theta ||r_{k-1}|| for a threshold theta
@@ -81,6 +83,26 @@ from .galerkin import rap, definiteness_violations
 from .store import quantise, delta_zero, EPS_ZERO, fp16_exponent, bpa_value, bpa_encode, BPA_WIDTHS
 
 COARSE_DIRECT_MAX = 1024
+COARSE_DIRECT_LIMIT = 26 ** 3     # the largest exact coarsest solve offered (3D level 3)
+
+
+def factor_coarse(A, direct_max=COARSE_DIRECT_MAX):
+    """Factorisation of the coarsest operator for its exact solve, or None
+    when the level is larger than ``direct_max`` (it is then smoothed)."""
+    n = A.shape[0]
+    if n > direct_max:
+        return None
+    if n <= COARSE_DIRECT_MAX:
+        return sla.lu_factor(A.toarray().astype(np.float64))
+    return spla.splu(sp.csc_matrix(A, dtype=np.float64))
+
+
+def coarse_solve(fac, b):
+    """x = A_c^-1 b with a factorisation from ``factor_coarse``."""
+    b = np.asarray(b, dtype=np.float64)
+    if isinstance(fac, tuple):
+        return sla.lu_solve(fac, b)
+    return fac.solve(b)
 
 
 class IndefiniteError(RuntimeError):
@@ -104,6 +126,7 @@ class Hierarchy:
     smoother: str = "jacobi"       # "jacobi" or "block" (block Jacobi)
     bj_sweeps: int = 1             # Gauss-Seidel sweeps per patch in block Jacobi
     R: Optional[Dict[int, sp.csr_matrix]] = None   # restriction per level; None: P^T
+    direct_max: int = COARSE_DIRECT_MAX            # largest coarsest level solved exactly
 
     def diag(self, l):
         return self.A[l].diagonal()
@@ -111,7 +134,7 @@ class Hierarchy:
 
 def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_post=2,
                     check_definite=True, perturb=None, smoother="jacobi", bj_sweeps=1, v=None,
-                    restriction="transpose"):
+                    restriction="transpose", direct_max=COARSE_DIRECT_MAX):
     """Operators of all levels from the finest coefficients (Sect. 3.3, 3.4).
 
     ``v`` (per-cell velocities, shape (d,)+(n,)*d) adds the convection term of
@@ -169,10 +192,8 @@ def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_p
     if R is not None:
         R = {l: R[l] for l in P}
     H = Hierarchy(d, L, lc_used, transfer, A, P, eps_l, omega, mu_pre, mu_post,
-                  smoother=smoother, bj_sweeps=bj_sweeps, R=R)
-    n_c = A[lc_used].shape[0]
-    if n_c <= COARSE_DIRECT_MAX:
-        H.coarse_lu = sla.lu_factor(A[lc_used].toarray())
+                  smoother=smoother, bj_sweeps=bj_sweeps, R=R, direct_max=direct_max)
+    H.coarse_lu = factor_coarse(A[lc_used], direct_max)
     return H
 
 
@@ -233,7 +254,7 @@ def vcycle(H, l, u, b):
     D = A.diagonal()
     if l == H.lc:
         if H.coarse_lu is not None:
-            return sla.lu_solve(H.coarse_lu, b.astype(np.float64)).astype(dt)
+            return coarse_solve(H.coarse_lu, b).astype(dt)
         for _ in range(H.mu_pre + H.mu_post):
             u = smooth(H, l, A, D, u, b)
         return u
@@ -264,7 +285,7 @@ def additive_cycle(H, u, b, damping="exp"):
         return dt(H.omega ** (L - l + 1) if damping == "exp" else H.omega)
 
     if H.coarse_lu is not None:
-        e = sla.lu_solve(H.coarse_lu, r[lc].astype(np.float64)).astype(dt)
+        e = coarse_solve(H.coarse_lu, r[lc]).astype(dt)
     else:
         e = om(lc) * r[lc] / H.A[lc].diagonal()
     for l in range(lc + 1, L + 1):
@@ -300,7 +321,7 @@ def bpx_cycle(H, u, b, damping="const"):
         return dt(H.omega ** (L - l + 1) if damping == "exp" else H.omega)
 
     if H.coarse_lu is not None:
-        e = sla.lu_solve(H.coarse_lu, r[lc].astype(np.float64)).astype(dt)
+        e = coarse_solve(H.coarse_lu, r[lc]).astype(dt)
     else:
         e = om(lc) * r[lc] / H.A[lc].diagonal()
     for l in range(lc + 1, L + 1):
@@ -335,7 +356,7 @@ def raise_coarsest(H, top=None):
         return False
     H.lc += 1
     Ac = H.A[H.lc]
-    H.coarse_lu = sla.lu_factor(Ac.toarray().astype(np.float64)) if Ac.shape[0] <= COARSE_DIRECT_MAX else None
+    H.coarse_lu = factor_coarse(Ac, H.direct_max)
     return True
 
 
@@ -439,7 +460,7 @@ def quantised_hierarchy(H, fmt, eps_mf=None):
         q = sp.csr_matrix((vals, dP.indices, dP.indptr), shape=dP.shape)
         P32[l] = (Pd + q).astype(dt).tocsr()
     Hq = Hierarchy(d, H.L, H.lc, H.transfer, A32, P32, H.eps, H.omega, H.mu_pre, H.mu_post,
-                   H.coarse_lu, dt, H.smoother, H.bj_sweeps)
+                   H.coarse_lu, dt, H.smoother, H.bj_sweeps, direct_max=H.direct_max)
     return Hq
 
 

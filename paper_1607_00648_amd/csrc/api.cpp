@@ -10,6 +10,7 @@
 #include <functional>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "qmg_internal.hpp"
@@ -206,6 +207,34 @@ int guard(qmg_grid_t* g, F&& f) {
   }
 }
 
+void validate_region(const qmg_region& r, int d, int L) {
+  if (r.level < 0 || r.level > L) throw ApiError(QMG_EINVAL, "region level out of range (0..max_level)");
+  if (r.n_params < 0 || (r.n_params > 0 && !r.params)) throw ApiError(QMG_EINVAL, "bad region parameters");
+  for (int i = 0; i < r.n_params; ++i)
+    if (!std::isfinite(r.params[i])) throw ApiError(QMG_EINVAL, "region parameters must be finite");
+  if (r.kind == QMG_REGION_BALL) {
+    if (r.n_params != d + 1 || !(r.params[d] > 0.0)) throw ApiError(QMG_EINVAL, "a ball takes centre and radius > 0");
+  } else if (r.kind == QMG_REGION_LEVELSET_BAND) {
+    if (r.n_params < 3) throw ApiError(QMG_EINVAL, "a level-set band takes tau, amplitude, M, k, phases");
+    const double M = r.params[2];
+    if (!(M >= 1.0 && M <= 65536.0 && M == std::floor(M)) || r.n_params != 3 + (int)M * (d + 1))
+      throw ApiError(QMG_EINVAL, "a level-set band takes 3 + M (d + 1) values");
+    if (!(r.params[0] >= 0.0)) throw ApiError(QMG_EINVAL, "band half-width tau must be >= 0");
+  } else if (r.kind == QMG_REGION_CELL_LIST) {
+    if (r.n_params % (d + 1) != 0) throw ApiError(QMG_EINVAL, "a cell list takes groups of 1 + d values");
+    for (int q = 0; q < r.n_params; q += d + 1) {
+      const double lv = r.params[q];
+      if (!(lv >= 0.0 && lv <= L && lv == std::floor(lv))) throw ApiError(QMG_EINVAL, "cell list: bad level");
+      const double n = std::pow(3.0, lv);
+      for (int a = 1; a <= d; ++a)
+        if (!(r.params[q + a] >= 0.0 && r.params[q + a] < n && r.params[q + a] == std::floor(r.params[q + a])))
+          throw ApiError(QMG_EINVAL, "cell list: cell index out of range");
+    }
+  } else {
+    throw ApiError(QMG_EINVAL, "unknown region kind");
+  }
+}
+
 void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
   if (!desc || !o) throw ApiError(QMG_EINVAL, "null descriptor or options");
   if (desc->dim != 2 && desc->dim != 3) throw ApiError(QMG_EINVAL, "dim must be 2 or 3");
@@ -236,10 +265,16 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
   if (o->cycle != QMG_CYCLE_MULT && o->smoother != QMG_SMOOTH_JACOBI)
     throw ApiError(QMG_EINVAL, "additive and BPX cycles take one Jacobi step per level");
   const bool adaptive = desc->base_level != 0 && desc->base_level != desc->max_level;
+  if (!adaptive && desc->n_regions != 0)
+    throw ApiError(QMG_EINVAL, "refinement regions need an adaptive grid (1 <= base < max_level)");
   if (adaptive) {
     if (desc->base_level < 1 || desc->base_level > desc->max_level)
       throw ApiError(QMG_EINVAL, "base_level must satisfy 1 <= base <= max_level");
-    if (!desc->refine) throw ApiError(QMG_EINVAL, "adaptive grid without refinement flags");
+    if (desc->n_regions < 0 || (desc->n_regions > 0 && !desc->regions))
+      throw ApiError(QMG_EINVAL, "bad region list");
+    if (!desc->refine && desc->n_regions == 0)
+      throw ApiError(QMG_EINVAL, "adaptive grid without refinement flags or regions");
+    for (int r = 0; r < desc->n_regions; ++r) validate_region(desc->regions[r], desc->dim, desc->max_level);
     if (o->coarsest_level > desc->base_level)
       throw ApiError(QMG_EINVAL, "coarsest_level must not exceed base_level");
     if (o->smoother == QMG_SMOOTH_BLOCK) throw ApiError(QMG_EINVAL, "block Jacobi runs on regular grids");
@@ -248,6 +283,118 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
     if (o->restriction != QMG_R_TRANSPOSE)
       throw ApiError(QMG_EINVAL, "injection and aggregation run on regular grids");
   }
+}
+
+// Does cell c (indices x first) of level l meet a ball or level-set band
+// region?  The arithmetic follows the stated definitions term by term: box
+// [c/n, c/n + 1/n], sample points c/n + (o/2)/n, phi summed over m in order.
+bool region_meets(const qmg_region& r, int d, int l, const int64_t* c) {
+  const double n = std::pow(3.0, l);
+  double lo[3];
+  for (int a = 0; a < d; ++a) lo[a] = (double)c[a] / n;
+  if (r.kind == QMG_REGION_BALL) {
+    double s2 = 0.0;
+    for (int a = 0; a < d; ++a) {
+      const double hi = lo[a] + 1.0 / n;
+      const double g = std::max(std::max(lo[a] - r.params[a], 0.0), std::max(r.params[a] - hi, 0.0));
+      s2 += g * g;
+    }
+    return std::sqrt(s2) < r.params[d];
+  }
+  const double tau = r.params[0], amp = r.params[1];
+  const int M = (int)r.params[2];
+  const double* k = r.params + 3;
+  const double* ph = r.params + 3 + (size_t)M * d;
+  double mn = INFINITY, mx = -INFINITY, amin = INFINITY;
+  const int ns = d == 3 ? 27 : 9;
+  for (int s = 0; s < ns; ++s) {
+    const int o[3] = {s % 3, (s / 3) % 3, s / 9};
+    double x[3];
+    for (int a = 0; a < d; ++a) x[a] = lo[a] + (o[a] * 0.5) / n;
+    double acc = 0.0;
+    for (int m = 0; m < M; ++m) {
+      double t = 0.0;
+      for (int a = 0; a < d; ++a) t += x[a] * k[(size_t)m * d + a];
+      acc += std::cos(t + ph[m]);
+    }
+    const double phi = amp * acc;
+    mn = std::min(mn, phi);
+    mx = std::max(mx, phi);
+    amin = std::min(amin, std::fabs(phi));
+  }
+  return amin < tau || (mn < 0.0 && mx > 0.0);
+}
+
+// Refinement flags of levels base..L-1 (one byte per cell, level after
+// level): the caller's bytes OR-ed with every region.  Existence is tracked
+// level by level so that only existing cells are evaluated; the cells of a
+// level are split over host threads.
+std::vector<uint8_t> refine_flags(const qmg_grid_desc* desc) {
+  const int d = desc->dim, L = desc->max_level, base = desc->base_level;
+  std::vector<int64_t> off(L + 1, 0);
+  int64_t total = 0;
+  for (int l = base; l < L; ++l) {
+    off[l] = total;
+    total += (int64_t)std::llround(std::pow(3.0, (double)l * d));
+  }
+  std::vector<uint8_t> out((size_t)total, 0);
+  if (desc->refine) std::memcpy(out.data(), desc->refine, (size_t)total);
+  for (int r = 0; r < desc->n_regions; ++r) {
+    const qmg_region& R = desc->regions[r];
+    if (R.kind != QMG_REGION_CELL_LIST) continue;
+    for (int q = 0; q < R.n_params; q += d + 1) {
+      const int lv = (int)R.params[q];
+      if (lv < base || lv >= std::min(L, R.level)) continue;
+      const int64_t n = (int64_t)std::llround(std::pow(3.0, lv));
+      int64_t idx = 0;
+      for (int a = d; a >= 1; --a) idx = idx * n + (int64_t)R.params[q + a];
+      out[(size_t)(off[lv] + idx)] = 1;
+    }
+  }
+  unsigned nth = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  std::vector<uint8_t> ref_prev;
+  for (int l = base; l < L; ++l) {
+    const int64_t n = (int64_t)std::llround(std::pow(3.0, l));
+    const int64_t ncell = d == 3 ? n * n * n : n * n;
+    const int64_t np = n / 3;
+    uint8_t* fl = out.data() + off[l];
+    std::vector<const qmg_region*> act;
+    for (int r = 0; r < desc->n_regions; ++r)
+      if (desc->regions[r].kind != QMG_REGION_CELL_LIST && desc->regions[r].level > l) act.push_back(&desc->regions[r]);
+    auto exists = [&](int64_t c) -> bool {
+      if (l == base) return true;
+      const int64_t cx = c % n, cy = (c / n) % n, cz = d == 3 ? c / (n * n) : 0;
+      return ref_prev[(size_t)(cx / 3 + np * (cy / 3 + (d == 3 ? np * (cz / 3) : 0)))] != 0;
+    };
+    if (!act.empty()) {
+      auto work = [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c) {
+          if (fl[c] || !exists(c)) continue;
+          const int64_t ci[3] = {c % n, (c / n) % n, d == 3 ? c / (n * n) : 0};
+          for (const qmg_region* R : act)
+            if (region_meets(*R, d, l, ci)) {
+              fl[c] = 1;
+              break;
+            }
+        }
+      };
+      if (ncell < 4096 || nth == 1) {
+        work(0, ncell);
+      } else {
+        std::vector<std::thread> th;
+        const int64_t chunk = (ncell + nth - 1) / nth;
+        for (unsigned t = 0; t < nth; ++t) {
+          const int64_t c0 = std::min<int64_t>(ncell, (int64_t)t * chunk), c1 = std::min<int64_t>(ncell, c0 + chunk);
+          th.emplace_back(work, c0, c1);
+        }
+        for (std::thread& x : th) x.join();
+      }
+    }
+    std::vector<uint8_t> ref((size_t)ncell);
+    for (int64_t c = 0; c < ncell; ++c) ref[(size_t)c] = (uint8_t)(fl[c] && exists(c));
+    ref_prev.swap(ref);
+  }
+  return out;
 }
 
 // Spacetree of levels base..L (Sect. 2): cells of level base all exist; a
@@ -462,7 +609,18 @@ void init_modes(qmg_grid_t* g, const qmg_grid_desc* desc, const qmg_solver_opts*
   g->fmt = store_fmt(o->store);
   g->adaptive = desc->base_level != 0 && desc->base_level != desc->max_level;
   g->lb = g->adaptive ? desc->base_level : desc->max_level;
-  if (g->adaptive) linearise(g);
+  if (g->adaptive) {
+    std::vector<uint8_t> flags;
+    if (desc->n_regions > 0) {
+      flags = refine_flags(desc);
+      g->desc.refine = flags.data();
+    }
+    linearise(g);
+  }
+  // the caller's arrays are not kept
+  g->desc.refine = nullptr;
+  g->desc.regions = nullptr;
+  g->desc.n_regions = 0;
 }
 
 // uploads the host linearisation (after the device layout is assigned)
@@ -1622,6 +1780,23 @@ int qmg_workspace_bytes(const qmg_grid_desc* desc, const qmg_solver_opts* opts, 
     Arena a;
     layout(&g, a);
     *bytes = a.off + 256;
+  });
+}
+
+int qmg_region_flags(const qmg_grid_desc* desc, uint8_t* flags, int64_t n_flags) {
+  return guard(nullptr, [&] {
+    if (!desc || !flags) throw ApiError(QMG_EINVAL, "null argument");
+    qmg_solver_opts o{};
+    qmg_default_opts(&o);
+    validate(desc, &o);
+    if (desc->base_level == 0 || desc->base_level == desc->max_level)
+      throw ApiError(QMG_EINVAL, "refinement flags belong to an adaptive grid");
+    int64_t total = 0;
+    for (int l = desc->base_level; l < desc->max_level; ++l)
+      total += (int64_t)std::llround(std::pow(3.0, (double)l * desc->dim));
+    if (n_flags != total) throw ApiError(QMG_EINVAL, "flags must hold " + std::to_string(total) + " bytes");
+    const std::vector<uint8_t> f = refine_flags(desc);
+    std::memcpy(flags, f.data(), (size_t)total);
   });
 }
 

@@ -14,6 +14,8 @@
 // are decoded once per build into an image of the LDS contents in global
 // memory; each launch copies that image in with 16-byte loads.
 #include "level_ops.hpp"
+#include <atomic>
+#include <mutex>
 
 namespace qmg {
 
@@ -340,17 +342,37 @@ __global__ __launch_bounds__(block_of<D>()) void k_fused_prepare(FusedArgs<T> a)
   f.build_static();
 }
 
+// Opts one kernel instance in to the device's whole per-workgroup LDS, once
+// per device.  Server workers launch from several host threads at once, and
+// grids of different sizes share an instance, so the attribute is set to the
+// device maximum (never lowered) under a lock, and a per-device bit records
+// it.  The first call for an instance comes from the build (launch with
+// prepare set), outside any stream capture.
+template <typename Kern>
+void lds_optin_once(Kern kernel) {
+  static std::mutex mu;
+  static std::atomic<uint64_t> done{0};
+  int dev = 0;
+  QMG_HIP(hipGetDevice(&dev));
+  const uint64_t bit = dev < 64 ? (uint64_t)1 << dev : 0;
+  if (bit && (done.load(std::memory_order_acquire) & bit)) return;
+  std::lock_guard<std::mutex> lk(mu);
+  if (bit && (done.load(std::memory_order_relaxed) & bit)) return;
+  int optin = 0;
+  if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || optin <= 0) {
+    (void)hipGetLastError();
+    optin = 64 * 1024;
+  }
+  QMG_HIP(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, optin));
+  done.fetch_or(bit, std::memory_order_release);
+}
+
 template <int D, typename T, int AS, int PS, int F>
 void launch_one(const FusedArgs<T>& a, hipStream_t s, bool prepare) {
+  lds_optin_once(k_fused_coarse<D, T, AS, PS, F>);
   if (prepare) {
     hipLaunchKernelGGL((k_fused_prepare<D, T, AS, PS, F>), dim3(1), dim3(block_of<D>()), 0, s, a);
     return;
-  }
-  static int attr_set = 0;  // opt in to LDS beyond the 64 KiB default (per kernel)
-  if (a.lds_bytes > attr_set) {
-    QMG_HIP(hipFuncSetAttribute((const void*)k_fused_coarse<D, T, AS, PS, F>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes));
-    attr_set = a.lds_bytes;
   }
   hipLaunchKernelGGL((k_fused_coarse<D, T, AS, PS, F>), dim3(1), dim3(block_of<D>()), a.lds_bytes, s, a);
 }

@@ -17,6 +17,7 @@
 // depend on what else is in the mix.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -49,7 +50,7 @@ struct Req {
   double tol = 1e-8;
   int max_cycles = 0;
   size_t bytes = 0;
-  double t_submit = 0, t_admit = 0, t_done = 0;
+  double t_submit = 0, t_arrive = 0, t_admit = 0, t_done = 0;
   int state = 0;  // 0 queued, 1 active, 2 done
   int status = QMG_OK;
   std::string err;
@@ -65,6 +66,8 @@ struct Req {
 
 struct qmg_server {
   size_t budget = 0, in_use = 0, peak = 0;
+  double t0 = 0;                            // server clock origin (arrival times count from it)
+  hipStream_t user = nullptr;               // the caller's stream (nullable)
   int max_slots = 0;
   int device = 0;
   int nworkers = 1;
@@ -203,10 +206,11 @@ void loop(qmg_server* s, int w) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
       if (s->stop && s->queue.empty() && s->active.empty()) break;
+      const double tnow = now_s();
       for (auto it = s->queue.begin(); it != s->queue.end() && !mine.empty();) {
         Req* r = *it;
         size_t off = 0;
-        if (s->in_use + r->bytes <= s->budget && arena_take(s, r->bytes, &off)) {
+        if (r->t_arrive <= tnow && s->in_use + r->bytes <= s->budget && arena_take(s, r->bytes, &off)) {
           r->off = off;
           r->slot = mine.back();
           mine.pop_back();
@@ -272,7 +276,7 @@ int sguard(qmg_server* s, F&& f) {
 
 extern "C" {
 
-int qmg_server_create(size_t hbm_budget, int max_slots, qmg_server_t** out) {
+int qmg_server_create(size_t hbm_budget, int max_slots, void* stream, qmg_server_t** out) {
   return sguard(nullptr, [&] {
     if (!out) throw ApiError(QMG_EINVAL, "null output handle");
     if (max_slots < 1 || max_slots > 256) throw ApiError(QMG_EINVAL, "max_slots must lie in 1..256");
@@ -280,6 +284,7 @@ int qmg_server_create(size_t hbm_budget, int max_slots, qmg_server_t** out) {
     qmg_server* s = new qmg_server();
     s->budget = hbm_budget;
     s->max_slots = max_slots;
+    s->user = (hipStream_t)stream;
     s->nworkers = std::min(max_slots, kServerWorkers);
     auto release = [s] {
       for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
@@ -304,7 +309,15 @@ int qmg_server_create(size_t hbm_budget, int max_slots, qmg_server_t** out) {
         QMG_HIP(hipHostMalloc((void**)&h, kHistCap * sizeof(double), hipHostMallocDefault));
         s->hist.push_back(h);
       }
+      if (s->user) {  // served work starts after what the caller enqueued before
+        hipEvent_t ev = nullptr;
+        QMG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        QMG_HIP(hipEventRecord(ev, s->user));
+        for (hipStream_t st : s->streams) QMG_HIP(hipStreamWaitEvent(st, ev, 0));
+        QMG_HIP(hipEventDestroy(ev));
+      }
       for (int i = max_slots - 1; i >= 0; --i) s->slot_free[i % s->nworkers].push_back(i);
+      s->t0 = now_s();
       for (int w = 0; w < s->nworkers; ++w) s->workers.emplace_back(loop, s, w);
     } catch (...) {
       release();
@@ -317,10 +330,11 @@ int qmg_server_create(size_t hbm_budget, int max_slots, qmg_server_t** out) {
 
 int qmg_server_submit(qmg_server_t* s, const qmg_grid_desc* desc, const qmg_solver_opts* opts,
                       const double* eps, const double* f, double rel_tol, int max_cycles,
-                      uint64_t* ticket) {
+                      double t_arrival, uint64_t* ticket) {
   return sguard(s, [&] {
     if (!s || !desc || !opts || !eps || !f || !ticket) throw ApiError(QMG_EINVAL, "null argument");
     if (!(rel_tol >= 0.0) || max_cycles < 0) throw ApiError(QMG_EINVAL, "bad tolerance or cycle limit");
+    if (std::isnan(t_arrival)) throw ApiError(QMG_EINVAL, "arrival time is NaN");
     if (desc->base_level != 0 && desc->base_level != desc->max_level)
       throw ApiError(QMG_EINVAL, "the server takes regular grids");
     size_t bytes = 0;
@@ -329,6 +343,9 @@ int qmg_server_submit(qmg_server_t* s, const qmg_grid_desc* desc, const qmg_solv
     if (bytes > s->budget) throw ApiError(QMG_EINVAL, "request workspace exceeds the whole HBM budget");
     Req* r = new Req();
     r->desc = *desc;
+    r->desc.refine = nullptr;
+    r->desc.regions = nullptr;
+    r->desc.n_regions = 0;
     r->opts = *opts;
     int64_t nc = 1, cells = 1, unk = 1;
     for (int i = 0; i < desc->max_level; ++i) nc *= 3;
@@ -348,6 +365,7 @@ int qmg_server_submit(qmg_server_t* s, const qmg_grid_desc* desc, const qmg_solv
     }
     r->id = s->next_id++;
     r->t_submit = now_s();
+    r->t_arrive = t_arrival >= 0.0 ? s->t0 + t_arrival : r->t_submit;
     s->queue.push_back(r);
     s->all[r->id] = r;
     ++s->submitted;
@@ -369,7 +387,7 @@ int qmg_server_poll(qmg_server_t* s, uint64_t ticket, int* done, double* u_out,
     if (!*done) return;
     if (u_out && !r->u.empty()) std::memcpy(u_out, r->u.data(), r->u.size() * sizeof(double));
     if (report) *report = r->rep;
-    if (latency_s) *latency_s = r->t_done - r->t_submit;
+    if (latency_s) *latency_s = r->t_done - r->t_arrive;
     status = r->status;
     if (status != QMG_OK) {
       g_server_err = r->err;
@@ -384,8 +402,19 @@ int qmg_server_poll(qmg_server_t* s, uint64_t ticket, int* done, double* u_out,
 int qmg_server_drain(qmg_server_t* s) {
   return sguard(s, [&] {
     if (!s) throw ApiError(QMG_EINVAL, "null server");
-    std::unique_lock<std::mutex> lk(s->mu);
-    s->cv_done.wait(lk, [&] { return s->queue.empty() && s->active.empty(); });
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_done.wait(lk, [&] { return s->queue.empty() && s->active.empty(); });
+    }
+    if (s->user) {  // later work on the caller's stream follows the served work
+      for (hipStream_t st : s->streams) {
+        hipEvent_t ev = nullptr;
+        QMG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        QMG_HIP(hipEventRecord(ev, st));
+        QMG_HIP(hipStreamWaitEvent(s->user, ev, 0));
+        QMG_HIP(hipEventDestroy(ev));
+      }
+    }
   });
 }
 

@@ -33,9 +33,16 @@ STORES = {"plain64": PLAIN_FP64, "hier64": HIER_FP64, "hier32": HIER_FP32,
           "hier16": HIER_FP16, "bf16": HIER_BF16, "bpa": HIER_BPA}
 
 
+REGION_BALL, REGION_LEVELSET_BAND, REGION_CELL_LIST = 0, 1, 2
+
+
+class Region(C.Structure):
+    _fields_ = [("kind", C.c_int), ("level", C.c_int), ("params", C.c_void_p), ("n_params", C.c_int)]
+
+
 class GridDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("max_level", C.c_int), ("base_level", C.c_int),
-                ("refine", C.c_void_p)]
+                ("refine", C.c_void_p), ("n_regions", C.c_int), ("regions", C.c_void_p)]
 
 
 class SolverOpts(C.Structure):
@@ -70,6 +77,7 @@ _SIGS = {
     "qmg_version": (C.c_char_p, []),
     "qmg_workspace_bytes": (C.c_int, [C.POINTER(GridDesc), C.POINTER(SolverOpts), C.POINTER(C.c_size_t)]),
     "qmg_default_opts": (C.c_int, [C.POINTER(SolverOpts)]),
+    "qmg_region_flags": (C.c_int, [C.POINTER(GridDesc), C.c_void_p, C.c_int64]),
     "qmg_create_grid": (C.c_int, [C.POINTER(GridDesc), C.POINTER(SolverOpts), C.c_void_p, C.c_size_t,
                                   C.c_void_p, C.POINTER(C.c_void_p)]),
     "qmg_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
@@ -89,9 +97,9 @@ _SIGS = {
     "qmg_get_prolongation": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "qmg_refine_flags": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.POINTER(C.c_int64)]),
     "qmg_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
-    "qmg_server_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
+    "qmg_server_create": (C.c_int, [C.c_size_t, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
     "qmg_server_submit": (C.c_int, [C.c_void_p, C.POINTER(GridDesc), C.POINTER(SolverOpts), C.c_void_p,
-                                    C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_uint64)]),
+                                    C.c_void_p, C.c_double, C.c_int, C.c_double, C.POINTER(C.c_uint64)]),
     "qmg_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int), C.c_void_p,
                                   C.POINTER(SolveReport), C.POINTER(C.c_double)]),
     "qmg_server_drain": (C.c_int, [C.c_void_p]),
@@ -174,6 +182,49 @@ def pack_refine(dim: int, base: int, level: int, flags) -> np.ndarray:
     return np.ascontiguousarray(np.concatenate(parts))
 
 
+def make_desc(dim: int, level: int, base_level=None, refine=None, regions=None) -> GridDesc:
+    """qmg_grid_desc: regular (base_level None), or an adaptive spacetree from
+    refinement flags (``refine``: {level: bool array}) and/or regions
+    (``regions``: list of (kind, level, params) with the header's parameter
+    layouts).  The returned structure keeps its arrays alive."""
+    desc = GridDesc(int(dim), int(level))
+    if base_level is not None and int(base_level) not in (0, int(level)):
+        desc.base_level = int(base_level)
+        if refine is not None or not regions:
+            desc._refine = pack_refine(int(dim), int(base_level), int(level), refine or {})
+            desc.refine = desc._refine.ctypes.data_as(C.c_void_p)
+        if regions:
+            desc._params = [np.ascontiguousarray(p, dtype=np.float64) for _, _, p in regions]
+            arr = (Region * len(regions))()
+            for i, ((kind, lv, _), p) in enumerate(zip(regions, desc._params)):
+                arr[i] = Region(int(kind), int(lv), p.ctypes.data_as(C.c_void_p), int(p.size))
+            desc._regions = arr
+            desc.n_regions = len(regions)
+            desc.regions = C.cast(arr, C.c_void_p)
+    elif regions:
+        raise ValueError("regions need an adaptive grid (base_level)")
+    return desc
+
+
+def region_flags(dim: int, level: int, base_level: int, regions, refine=None) -> dict:
+    """The library's refinement flags for ``regions`` (and ``refine``), as
+    {level: bool array (3^l,)*dim in NumPy axes (z,) y, x} for levels
+    base..level-1 (host evaluation; no device needed)."""
+    lib = load()
+    desc = make_desc(dim, level, base_level, refine, regions)
+    total = sum(3 ** (l * dim) for l in range(base_level, level))
+    out = np.zeros(total, dtype=np.uint8)
+    rc = lib.qmg_region_flags(C.byref(desc), _ptr(out), int(total))
+    if rc != QMG_OK:
+        raise QmgError(rc, lib.qmg_last_error(None).decode())
+    flags, k = {}, 0
+    for l in range(base_level, level):
+        m = 3 ** (l * dim)
+        flags[l] = out[k:k + m].reshape((3 ** l,) * dim).astype(bool)
+        k += m
+    return flags
+
+
 class Grid:
     """One grid of the unit square/cube (regular, or an adaptive spacetree when
     ``base_level`` and ``refine`` are given) with its operators and iterates.
@@ -182,17 +233,13 @@ class Grid:
     ``stream`` (a torch.cuda.Stream, default: the current stream)."""
 
     def __init__(self, dim: int, level: int, opts: Optional[SolverOpts] = None, stream=None,
-                 device: str = "cuda", base_level: Optional[int] = None, refine=None):
+                 device: str = "cuda", base_level: Optional[int] = None, refine=None, regions=None):
         import torch
         self.lib = load()
         self.dim, self.level = int(dim), int(level)
         self.opts = opts if opts is not None else make_opts()
-        self.desc = GridDesc(self.dim, self.level)
+        self.desc = make_desc(self.dim, self.level, base_level, refine, regions)
         self.adaptive = base_level is not None and int(base_level) not in (0, self.level)
-        if self.adaptive:
-            self._refine = pack_refine(self.dim, int(base_level), self.level, refine or {})
-            self.desc.base_level = int(base_level)
-            self.desc.refine = self._refine.ctypes.data_as(C.c_void_p)
         nbytes = C.c_size_t(0)
         self._check(self.lib.qmg_workspace_bytes(C.byref(self.desc), C.byref(self.opts), C.byref(nbytes)), None)
         self.workspace_bytes = int(nbytes.value)
@@ -358,12 +405,13 @@ class Server:
     include/qmg.h).  Requests carry their own grid size, coefficients, options
     and tolerance; results come back through poll()."""
 
-    def __init__(self, hbm_budget: int, max_slots: int = 8):
+    def __init__(self, hbm_budget: int, max_slots: int = 8, stream=None):
         import torch
         torch.cuda.init()
         self.lib = load()
         h = C.c_void_p()
-        rc = self.lib.qmg_server_create(C.c_size_t(int(hbm_budget)), int(max_slots), C.byref(h))
+        st = C.c_void_p(stream.cuda_stream) if stream is not None else C.c_void_p()
+        rc = self.lib.qmg_server_create(C.c_size_t(int(hbm_budget)), int(max_slots), st, C.byref(h))
         if rc != QMG_OK:
             raise QmgError(rc, self.lib.qmg_server_last_error(None).decode())
         self.h = h
@@ -373,7 +421,9 @@ class Server:
         raise QmgError(rc, self.lib.qmg_server_last_error(self.h).decode())
 
     def submit(self, dim: int, level: int, eps, f, opts: SolverOpts, tol: float = 1e-8,
-               max_cycles: int = 1000) -> int:
+               max_cycles: int = 1000, t_arrival: float = -1.0) -> int:
+        """Queues one request; ``t_arrival`` seconds on the server clock (from
+        its creation; negative: now) is when it arrives."""
         eps = np.ascontiguousarray(eps, dtype=np.float64)
         f = np.ascontiguousarray(f, dtype=np.float64)
         n = 3 ** level
@@ -382,7 +432,7 @@ class Server:
         desc = GridDesc(int(dim), int(level))
         t = C.c_uint64(0)
         rc = self.lib.qmg_server_submit(self.h, C.byref(desc), C.byref(opts), _ptr(eps), _ptr(f),
-                                        float(tol), int(max_cycles), C.byref(t))
+                                        float(tol), int(max_cycles), float(t_arrival), C.byref(t))
         if rc != QMG_OK:
             self._err(rc)
         self._n[t.value] = f.size

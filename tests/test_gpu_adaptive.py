@@ -164,7 +164,7 @@ def test_adaptive_rejected_by_server():
     desc = qmg.GridDesc(2, 4, 2, qmg.pack_refine(2, 2, 4, flags).ctypes.data_as(qmg.C.c_void_p))
     t = qmg.C.c_uint64(0)
     rc = srv.lib.qmg_server_submit(srv.h, qmg.C.byref(desc), qmg.C.byref(qmg.make_opts(transfer="galerkin")),
-                                   qmg._ptr(eps), qmg._ptr(f), 1e-8, 100, qmg.C.byref(t))
+                                   qmg._ptr(eps), qmg._ptr(f), 1e-8, 100, -1.0, qmg.C.byref(t))
     assert rc == qmg.QMG_EINVAL
     srv.close()
 

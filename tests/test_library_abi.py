@@ -78,3 +78,75 @@ def test_adaptive_description_validation():
     assert lib.qmg_workspace_bytes(C.byref(no_flags), C.byref(ok), C.byref(nb)) == qmg.QMG_EINVAL
     with pytest.raises(ValueError):
         qmg.pack_refine(2, 2, 4, {2: np.zeros((8, 8), bool)})
+
+
+def test_region_flags_match_the_generators():
+    """Refinement regions evaluated by the library (host, threaded) give the
+    same flags, bit for bit, as the NumPy generators: balls as in the 3D
+    adaptive-balls workload, and the RFF level-set band of the band workload
+    (existence tracked level by level in both)."""
+    import numpy as np
+    import workloads as W
+    from paper_1607_00648_amd import qmg
+    P = W.adaptive_balls(dim=3, base=3, level=5)
+    F = qmg.region_flags(3, 5, 3, P.regions)
+    assert sorted(F) == sorted(P.flags)
+    for l in P.flags:
+        assert np.array_equal(F[l], P.flags[l]), l
+    B = W.adaptive_band(dim=3, base=2, level=5)
+    F = qmg.region_flags(3, 5, 2, B.regions)
+    for l in B.flags:
+        assert B.flags[l].any()
+        assert np.array_equal(F[l], B.flags[l]), l
+    B2 = W.adaptive_band(dim=2, base=2, level=5, seed=3)
+    F = qmg.region_flags(2, 5, 2, B2.regions)
+    for l in B2.flags:
+        assert np.array_equal(F[l], B2.flags[l]), l
+
+
+def test_cell_list_regions_and_refine_bytes_combine():
+    import numpy as np
+    from paper_1607_00648_amd import qmg
+    # level-2 cell (4,4) is refined by the bytes; level-3 cells listed: one
+    # inside it (exists), one outside (does not exist: ignored), one on level 4
+    # (beyond the region's level)
+    flags = {2: np.zeros((9, 9), bool)}
+    flags[2][4, 4] = True
+    cells = [(3, 13, 12), (3, 0, 0), (4, 40, 40)]
+    params = np.array([v for c in cells for v in c], dtype=np.float64)
+    F = qmg.region_flags(2, 5, 2, [(qmg.REGION_CELL_LIST, 4, params)], refine=flags)
+    assert F[2].sum() == 1 and F[2][4, 4]
+    assert F[3][12, 13] and F[3].sum() == 1 + 1      # listed bytes are kept as given
+    assert F[4].sum() == 0
+    # a small ball inside one cell per level refines that cell down to its level
+    ball = (qmg.REGION_BALL, 3, np.array([0.5, 0.5, 0.01]))
+    G = qmg.region_flags(2, 5, 2, [ball])
+    assert G[2].sum() == 1 and G[2][4, 4] and G[3].sum() == 0 and G[4].sum() == 0
+    G = qmg.region_flags(2, 5, 2, [(qmg.REGION_BALL, 4, np.array([0.5, 0.5, 0.01]))])
+    assert G[3].sum() == 1 and G[3][13, 13] and G[4].sum() == 0
+
+
+def test_region_validation():
+    import numpy as np
+    from paper_1607_00648_amd import qmg
+    lib = qmg.load()
+    ok = qmg.make_opts(transfer="galerkin")
+    nb = C.c_size_t(0)
+    good = qmg.make_desc(3, 4, 2, regions=[(qmg.REGION_BALL, 4, np.array([0.5, 0.5, 0.5, 0.1]))])
+    assert lib.qmg_workspace_bytes(C.byref(good), C.byref(ok), C.byref(nb)) == qmg.QMG_OK
+    bad = [
+        (7, 4, np.array([0.5, 0.5, 0.5, 0.1])),                  # unknown kind
+        (qmg.REGION_BALL, 4, np.array([0.5, 0.5, 0.1])),          # too few values
+        (qmg.REGION_BALL, 4, np.array([0.5, 0.5, 0.5, 0.0])),     # radius 0
+        (qmg.REGION_BALL, 5, np.array([0.5, 0.5, 0.5, 0.1])),     # level beyond L
+        (qmg.REGION_LEVELSET_BAND, 4, np.array([0.1, 1.0, 2.0, 1, 2, 3, 4, 5, 6, 0.0])),   # M = 2 needs 11
+        (qmg.REGION_CELL_LIST, 4, np.array([3.0, 27.0, 0.0, 0.0])),   # index beyond 3^3
+        (qmg.REGION_BALL, 4, np.array([0.5, np.nan, 0.5, 0.1])),
+    ]
+    for r in bad:
+        d = qmg.make_desc(3, 4, 2, regions=[r])
+        assert lib.qmg_workspace_bytes(C.byref(d), C.byref(ok), C.byref(nb)) == qmg.QMG_EINVAL, r
+    reg = qmg.make_desc(3, 4)
+    reg.n_regions = 1
+    reg.regions = good.regions
+    assert lib.qmg_workspace_bytes(C.byref(reg), C.byref(ok), C.byref(nb)) == qmg.QMG_EINVAL

@@ -197,7 +197,8 @@ def ball_flags(dim, base, level, centres, radius):
 def rff_field(dim, seed, n_features, length):
     """Random-Fourier-feature Gaussian field g(x) = sqrt(2/M) sum cos(k_m.x + p_m),
     k_m ~ N(0, length^-2 I), p_m ~ U[0, 2pi): zero mean, unit variance,
-    covariance exp(-|r|^2 / (2 length^2))."""
+    covariance exp(-|r|^2 / (2 length^2)).  The callable carries its
+    parameters as attributes ``k`` (M, dim; x first), ``p`` (M) and ``scale``."""
     rng = np.random.default_rng(seed)
     k = rng.normal(0.0, 1.0 / length, size=(n_features, dim))
     p = rng.uniform(0.0, 2.0 * np.pi, size=n_features)
@@ -210,7 +211,27 @@ def rff_field(dim, seed, n_features, length):
             xs = x[c0:c0 + (1 << 16)]
             out[c0:c0 + len(xs)] = scale * np.cos(xs @ k.T + p).sum(axis=1)
         return out
+    g.k, g.p, g.scale = k, p, scale
     return g
+
+
+# Region kinds of the library's grid description (refine the cells that meet
+# the region); the parameter layouts are those of the C header.
+REGION_BALL, REGION_LEVELSET_BAND, REGION_CELL_LIST = 0, 1, 2
+
+
+def ball_regions(centres, radius, level):
+    """One ball region per centre: params (centre x first, radius)."""
+    return [(REGION_BALL, level, np.concatenate([np.asarray(c, np.float64), [radius]]))
+            for c in np.atleast_2d(centres)]
+
+
+def band_region(phi, tau, level):
+    """The band |phi| < tau (or a sign change) of an RFF level set: params
+    (tau, scale, M, k (M x dim, x first, row by row), phases (M))."""
+    k, p = np.asarray(phi.k, np.float64), np.asarray(phi.p, np.float64)
+    return [(REGION_LEVELSET_BAND, level,
+             np.concatenate([[tau, phi.scale, float(len(p))], k.ravel(), p]))]
 
 
 def uniform_hash(seed, level, idx):
@@ -234,10 +255,19 @@ class AdaptiveProblem:
     dim: int
     base: int
     level: int
-    flags: dict                 # level -> bool array over the level's cells (NumPy axes z,y,x)
+    flags_fn: object            # () -> {level: bool array over the level's cells (NumPy axes z,y,x)}
     eps_at: object              # callable: cell centres (m, dim) x-first -> eps (m,)
     f_seed: int                 # source of unknown (level l, vertex i,j,k) = uniform_hash(f_seed, l, (i,j,k))
     meta: dict = dataclasses.field(default_factory=dict)
+    regions: list = dataclasses.field(default_factory=list)   # the same refinement as region descriptions
+    _flags: dict = None
+
+    @property
+    def flags(self):
+        """Refinement flags per level, evaluated here (NumPy) on first use."""
+        if self._flags is None:
+            self._flags = self.flags_fn()
+        return self._flags
 
     def f_at(self, level, coords_xfirst):
         """Source values at unknowns of one level given their coordinates."""
@@ -254,9 +284,10 @@ def adaptive_balls(dim=3, base=3, level=5, n_balls=4, radius=0.2, seed=0, contra
     rng = np.random.default_rng(seed)
     centres = rng.uniform(0.0, 1.0, size=(n_balls, dim))
     g = rff_field(dim, seed + 1000, 1024, 0.1) if contrast_field else (lambda x: np.zeros(len(x)))
-    return AdaptiveProblem(name, dim, base, level, ball_flags(dim, base, level, centres, radius),
+    return AdaptiveProblem(name, dim, base, level, lambda: ball_flags(dim, base, level, centres, radius),
                            lambda x: np.exp(g(x)), seed + 2000,
-                           {"centres": centres, "radius": radius, "seed": seed})
+                           {"centres": centres, "radius": radius, "seed": seed},
+                           ball_regions(centres, radius, level))
 
 
 def adaptive_band(dim=3, base=3, level=6, seed=0, fraction=0.10, n_cubes=64, n_features=64,
@@ -271,23 +302,26 @@ def adaptive_band(dim=3, base=3, level=6, seed=0, fraction=0.10, n_cubes=64, n_f
     tau = float(np.quantile(np.abs(phi(rng.uniform(0.0, 1.0, size=(10 ** 6, dim)))), fraction))
     centres = rng.uniform(0.0, 1.0, size=(n_cubes, dim))
     sides = rng.uniform(0.05, 0.15, size=n_cubes)
-    flags = {}
-    exist = None
-    for l in range(base, level):
-        n = 3 ** l
-        cells = np.argwhere(np.ones((n,) * dim, bool) if exist is None else exist)  # numpy order
-        f = np.zeros((n,) * dim, dtype=bool)
-        if len(cells):
-            lo = cells[:, ::-1] / n
-            pts = []
-            for o in np.ndindex(*([3] * dim)):
-                pts.append(lo + (np.array(o) * 0.5) / n)
-            vals = np.stack([phi(pp) for pp in pts], 1)
-            hit = (np.abs(vals).min(1) < tau) | (vals.min(1) < 0) & (vals.max(1) > 0)
-            f[tuple(cells.T)] = hit
-        flags[l] = f
-        exist = np.repeat(np.repeat(np.repeat(f, 3, 0), 3, 1), 3, 2) if dim == 3 else \
-            np.repeat(np.repeat(f, 3, 0), 3, 1)
+
+    def flags_fn():
+        flags = {}
+        exist = None
+        for l in range(base, level):
+            n = 3 ** l
+            cells = np.argwhere(np.ones((n,) * dim, bool) if exist is None else exist)  # numpy order
+            f = np.zeros((n,) * dim, dtype=bool)
+            if len(cells):
+                lo = cells[:, ::-1] / n
+                pts = []
+                for o in np.ndindex(*([3] * dim)):
+                    pts.append(lo + (np.array(o) * 0.5) / n)
+                vals = np.stack([phi(pp) for pp in pts], 1)
+                hit = (np.abs(vals).min(1) < tau) | (vals.min(1) < 0) & (vals.max(1) > 0)
+                f[tuple(cells.T)] = hit
+            flags[l] = f
+            exist = np.repeat(np.repeat(np.repeat(f, 3, 0), 3, 1), 3, 2) if dim == 3 else \
+                np.repeat(np.repeat(f, 3, 0), 3, 1)
+        return flags
 
     def eps_at(x):
         x = np.atleast_2d(x)
@@ -295,8 +329,9 @@ def adaptive_band(dim=3, base=3, level=6, seed=0, fraction=0.10, n_cubes=64, n_f
         for c, s in zip(centres, sides):
             inside |= np.all(np.abs(x - c) <= s / 2, axis=1)
         return np.where(inside, 1e6, 1.0)
-    return AdaptiveProblem(name, dim, base, level, flags, eps_at, seed + 4000,
-                           {"tau": tau, "seed": seed})
+    return AdaptiveProblem(name, dim, base, level, flags_fn, eps_at, seed + 4000,
+                           {"tau": tau, "seed": seed, "centres": centres, "sides": sides},
+                           band_region(phi, tau, level))
 
 
 @dataclasses.dataclass
@@ -329,4 +364,5 @@ def request_stream(seed: int = 0, n_requests: int = 256, rate: float = 100.0,
 __all__ = ["Problem", "Request", "poisson", "random_checkerboard",
            "alternating_checkerboard", "sin_source", "poisson2d_l4", "checkerboard2d", "jump3d",
            "request_stream", "ball_flags", "rff_field", "uniform_hash", "AdaptiveProblem",
-           "adaptive_balls", "adaptive_band", "material_jump", "circle"]
+           "adaptive_balls", "adaptive_band", "material_jump", "circle", "ball_regions", "band_region",
+           "REGION_BALL", "REGION_LEVELSET_BAND", "REGION_CELL_LIST"]

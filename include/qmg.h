@@ -292,6 +292,15 @@ int qmg_vcycle(qmg_grid_t* grid, int n, double* relres);
 int qmg_solve(qmg_grid_t* grid, double rel_tol, int max_cycles, double* history,
               qmg_solve_report* report);
 
+/* The residual b - A u of the current solution, one value per unknown (FP64
+ * iterates only; QMG_EINVAL with FP32 iterates): on a regular grid the
+ * finest-level residual, on an adaptive spacetree the residual of the
+ * composite system at every leaf (Sect. 2: refined vertices hold their finest
+ * copy, hanging vertices the interpolant of the coarser level, which this call
+ * refreshes first).  It is the vector whose norm the cycles report.
+ * Overwrites the levels' residual buffers. */
+int qmg_residual(qmg_grid_t* grid, double* r, int mem);
+
 /* Copies the solution out / in (one value per unknown).  set_solution is a warm
  * start (resume): the next cycle starts from it. */
 int qmg_get_solution(const qmg_grid_t* grid, double* u, int mem);

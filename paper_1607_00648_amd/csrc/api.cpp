@@ -2023,6 +2023,30 @@ int qmg_get_solution(const qmg_grid_t* cg, double* u, int mem) {
   });
 }
 
+int qmg_residual(qmg_grid_t* g, double* r, int mem) {
+  return guard(g, [&] {
+    if (!g || !r) throw ApiError(QMG_EINVAL, "null argument");
+    if (!g->have_coef) throw ApiError(QMG_ESTATE, "no coefficients set");
+    if (g->mixed) throw ApiError(QMG_EINVAL, "the residual vector is offered for FP64 iterates");
+    if (g->adaptive && !g->have_ops) throw ApiError(QMG_ESTATE, "operators not built");
+    enqueue_residual_norm(g, false);
+    LevelBuf& F = g->lv[g->Lmax];
+    if (g->adaptive) {
+      int64_t uo = 0;
+      for (int l = g->lb; l <= g->Lmax; ++l) {
+        const int64_t cnt = (int64_t)g->hl[l].leaf.size();
+        launch_ad_gather<double>(g->unk_slots + uo, cnt, (const double*)g->lv[l].r, g->stage + uo, S(g));
+        uo += cnt;
+      }
+    } else {
+      launch_gather_unknowns<double>(F.L, (const double*)F.r, g->stage, S(g));
+    }
+    QMG_HIP(hipMemcpyAsync(r, g->stage, g->n_unknowns * sizeof(double),
+                           mem == QMG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, S(g)));
+    QMG_HIP(hipStreamSynchronize(S(g)));
+  });
+}
+
 int qmg_set_solution(qmg_grid_t* g, const double* u, int mem) {
   return guard(g, [&] {
     if (!g || !u) throw ApiError(QMG_EINVAL, "null argument");

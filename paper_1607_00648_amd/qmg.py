@@ -88,6 +88,7 @@ _SIGS = {
     "qmg_vcycle": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "qmg_solve": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_void_p, C.POINTER(SolveReport)]),
     "qmg_get_solution": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "qmg_residual": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "qmg_set_solution": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "qmg_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "qmg_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
@@ -329,6 +330,12 @@ class Grid:
         u = np.zeros(self.n_unknowns)
         self._check(self.lib.qmg_get_solution(self.h, _ptr(u), QMG_HOST), self.h)
         return u
+
+    def residual(self) -> np.ndarray:
+        """b - A u per unknown (composite system when adaptive; FP64 iterates)."""
+        r = np.zeros(self.n_unknowns)
+        self._check(self.lib.qmg_residual(self.h, _ptr(r), QMG_HOST), self.h)
+        return r
 
     def set_solution(self, u):
         u = np.ascontiguousarray(u, dtype=np.float64)

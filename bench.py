@@ -1,24 +1,30 @@
 """Benchmark: vertex updates/s, solves/s to 1e-8 and p50/p99 solve latency.
 
-One step = the whole hot path for one request of the 2D jumping-coefficient
-workload (729^2 cells, random 9x9 checkerboard of {1, 1e4}): set_coefficients,
-build_operators (BoxMG P, Galerkin R A P with the definiteness check,
-hierarchical FP64 delta store, coarsest LU) and V(2,2) cycles to a relative
-residual of 1e-8, all in the HIP library on one GPU.  Inputs are seeded and
-synthetic (workloads.checkerboard2d) and resident in HBM (torch tensors) before the
-timed region; set_coefficients checks and scatters them on the device.  The
-same steps with host-resident inputs (PCIe hand-over) are reported beside.
+Headline: the 3D high-contrast adaptive workload (a spacetree of base level 3
+refined to level 6 around the band |phi| < tau of a seeded random-Fourier-
+feature level set, 10 % of the volume; eps = 10^6 inside 64 seeded cubes and 1
+outside; f ~ U[-1,1]; BoxMG + Galerkin, BF16 hierarchical deltas, FP32 FAS
+cycles inside the FP64 composite defect correction).  One step is the whole
+hot path for one coefficient field: set_coefficients (inputs resident in HBM),
+build_operators (BoxMG P per refined cell, Galerkin R A P, delta store,
+coarsest solve) and two outer iterations (V(2,2) FAS cycles).  The configured
+method does not converge on this workload (its Galerkin coarse operators turn
+indefinite at this contrast), so a step runs a fixed number of cycles and
+the line reports vertex updates/s; solves/s come from the other workloads.
+The grid is built from the band region inside the library; eps and f are
+evaluated at the library's own cell and vertex positions.
 
-Prints one JSON line.  The dominant kernel (the finest-level pre-smoothing
-pass) is timed with per-dispatch HIP events on the grid's stream around every
-k-th of its launches during the timed steps; its algorithmic bytes per launch
-give the roofline figure.  Beside the main line: build_operators timed on its
-own, the other single-grid workloads (2D Poisson at level 4 in FP64 to 1e-10,
-the 3D four-ball adaptive grid in BF16/FP32 under FP64 correction), the same
-step with the plain FP64 and BF16 stores, a roofline sweep on grids larger
-than the Infinity Cache, the served request stream (mixed precision, and plain
-FP64 for the ratio) and the CPU baseline, which times the oracle (test
-infrastructure) on one solve of the main workload.
+The dominant kernel (the Jacobi sweep of the finest adaptive level) is timed
+with per-dispatch HIP events on the grid's stream around every k-th launch
+during the timed steps; its algorithmic bytes per launch over that time give
+the roofline figure, beside a measured device-copy ceiling.  Beside the main
+line: the same step with the FP16, FP64 hierarchical and plain FP64 stores,
+composite residual rows recomputed by the oracle at sampled unknowns, the 2D
+jumping-coefficient workload (729^2 cells, solves to 1e-8) with its store
+variants, a roofline sweep on regular grids larger than the Infinity Cache,
+the other single-grid workloads, the served request stream, and the CPU
+baselines: the oracle (test infrastructure) timed on a bounded sample of the
+headline workload, on one thread and on every host core.
 """
 from __future__ import annotations
 
@@ -36,12 +42,6 @@ sys.path.insert(0, ROOT)
 METRIC = "vertex updates/s + solves/s to 1e-8 rel residual; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic per launch of the timed kernel from two rocprofv3 --pmc passes
-# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated), keyed by
-# (store, dim, level); the kernel summary under profiles/ gives the commands.
-# An entry is removed whenever that kernel changes.
-MEASURED_TRAFFIC = {("hier64", 2, 6): 6734.4 * 2.0 * 1024 + 8326.5 * 1.0 * 1024}
-
 # Algorithmic bytes per finest vertex of one Jacobi sweep or one residual, each
 # streamed on its own: eps, u, b read and u' (or r) written once, stencils
 # rebuilt on the fly; the plain store reads its 3^d FP64 entries instead of eps.
@@ -54,7 +54,7 @@ OP_BYTES = {("hier64", 2): 32, ("plain64", 2): 96, ("hier32", 2): 16, ("hier16",
 TIMED_OPS = {2: 3, 3: 1}
 FUSED_MIN_BYTES = {("hier64", 2): 40, ("plain64", 2): 104, ("hier32", 2): 20, ("hier16", 2): 20, ("bf16", 2): 20}
 TIMED_KERNEL = {2: "finest-level pre-smoothing pass: 2 Jacobi sweeps + residual in one launch (k_pass2d)",
-                3: "finest-level Jacobi sweep (k_stencil mode 0)"}
+                3: "finest-level Jacobi sweep (k_march3d plane marching on level 5 and up)"}
 
 
 def run_variant(qmg, problem, transfer, store, steps, warmup, tol=1e-8, profile=0, host_inputs=False,
@@ -194,7 +194,7 @@ def other_workloads(qmg, n):
         g.close()
     P = W.adaptive_balls()
     g = qmg.Grid(P.dim, P.level, qmg.make_opts("boxmg", "bf16", check_definite=False),
-                 base_level=P.base, refine=P.flags)
+                 base_level=P.base, regions=P.regions)
     xyz, lev = g.unknown_coords()
     fa = np.empty(len(xyz))
     for l in range(P.base, P.level + 1):
@@ -228,12 +228,11 @@ def serve_stream(qmg, n_requests=256, seed=0, slots=16, budget=8 << 30):
         srv = qmg.Server(budget, max_slots=slots)
         t0 = time.perf_counter()
         tickets = []
+        # the whole arrival schedule is handed over at once: the server admits
+        # no request before its arrival time and measures latency from it
         for req, ta in zip(stream, arrivals):
-            wait = ta - (time.perf_counter() - t0)
-            if wait > 0:
-                time.sleep(wait)
             p = req.problem
-            tickets.append(srv.submit(p.dim, p.level, p.eps, p.f, opts, 1e-8))
+            tickets.append(srv.submit(p.dim, p.level, p.eps, p.f, opts, 1e-8, t_arrival=float(ta)))
         srv.drain()
         wall = time.perf_counter() - t0
         lat, upd, bad = [], 0, 0
@@ -293,26 +292,350 @@ def cpu_solution_poisson():
     return u
 
 
+# Algorithmic bytes per active vertex of one Jacobi sweep of the finest
+# adaptive level: the cell coefficient (one cell per vertex on that level), u
+# and b read, u' written once, the vertex-class byte; the plain store reads
+# its 27 FP64 stencil entries instead of the coefficient.
+AD_SWEEP_BYTES = {"bf16": 4 + 4 + 4 + 4 + 1, "hier16": 17, "hier32": 17, "hier64": 8 + 8 + 8 + 8 + 1,
+                  "plain64": 27 * 8 + 8 + 8 + 8 + 1}
+AD_SWEEP_KERNEL = "Jacobi sweep of the finest adaptive level (k_ad_stencil mode 0)"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by the
+    copy calibration), or None when there is none for this configuration or
+    the kernel's source changed since the counters were taken."""
+    import hashlib
+    try:
+        tab = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    e = tab.get("entries", {}).get(key)
+    if not e:
+        return None
+    src = open(os.path.join(ROOT, "paper_1607_00648_amd", "csrc", e["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != e["source_sha16"]:
+        return None
+    cal = tab["calibration"]
+    return (e["fetch_kib"] * cal["fetch_factor"] + e["write_kib"] * cal["write_factor"]) * 1024.0
+
+
+def copy_ceiling(gib=4, reps=5):
+    """Device-to-device copy of a large buffer (torch's copy kernel), timed
+    with events: bytes read + written over the median time."""
+    import torch
+    n = (gib << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ts = []
+    for _ in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    t = float(np.median(ts[1:]))
+    return 2.0 * n * 4 / t / 1e9
+
+
+class BandInputs:
+    """eps and f of the band workload at one grid's cells and unknowns (all
+    stores share the numbering): eps from the cube field evaluated on the
+    device at the library's cell centres, f from the counter-based source at
+    the library's unknown positions; and the level of every unknown."""
+
+    def __init__(self, g, P):
+        import torch
+        xc = torch.from_numpy(g.cell_centres()).cuda()
+        c = torch.from_numpy(P.meta["centres"]).cuda()
+        sd = torch.from_numpy(P.meta["sides"]).cuda()
+        inside = torch.zeros(len(xc), dtype=torch.bool, device="cuda")
+        for i in range(len(c)):
+            inside |= torch.all(torch.abs(xc - c[i]) <= sd[i] / 2, dim=1)
+        one = torch.ones((), dtype=torch.float64, device="cuda")
+        self.eps = torch.where(inside, 1e6 * one, one).contiguous()
+        del xc
+        self.xyz, self.lev = g.unknown_coords()
+        f = np.empty(len(self.lev))
+        for l in range(P.base, P.level + 1):
+            m = self.lev == l
+            f[m] = P.f_at(l, self.xyz[m])
+        self.f = torch.from_numpy(f).cuda()
+        self.n_finest = int((self.lev == P.level).sum())
+
+
+def band_step_runs(qmg, P, store, steps, warmup, inputs=None, profile=0, cycles=2):
+    """Timed steps of the band workload with one store: set_coefficients +
+    build_operators + ``cycles`` cycles from zero (outer iterations with FP32
+    iterates)."""
+    import torch
+    t0 = time.perf_counter()
+    g = qmg.Grid(3, P.level, qmg.make_opts("boxmg", store, check_definite=False, graphs=False),
+                 base_level=P.base, regions=P.regions)
+    t_create = time.perf_counter() - t0
+    if inputs is None:
+        inputs = BandInputs(g, P)
+    if profile:
+        g.profile(profile)
+    lat, upd, reps, builds = [], 0, [], []
+    for it in range(warmup + steps):
+        if it == warmup:
+            torch.cuda.synchronize()
+            if profile:
+                g.profile_read()
+            t_start = time.perf_counter()
+        ta = time.perf_counter()
+        g.set_coefficients(inputs.eps, inputs.f)
+        g.build()
+        rep, hist = g.solve(0.0, cycles)
+        tb = time.perf_counter()
+        if it >= warmup:
+            lat.append(tb - ta)
+            upd += rep["vertex_updates"]
+            reps.append(rep)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    launches, ms = g.profile_read() if profile else (0, 0.0)
+    # build_operators alone and the cycles alone, synchronised
+    tb_, tc_ = [], []
+    for _ in range(3):
+        g.set_coefficients(inputs.eps, inputs.f)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        g.build()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        g.solve(0.0, cycles)
+        tc = time.perf_counter()
+        tb_.append(tb - ta)
+        tc_.append(tc - tb)
+    out = {"store": store, "unknowns": g.n_unknowns, "leaf_cells": g.n_cells,
+           "workspace_bytes": g.workspace_bytes, "create_s": t_create,
+           "steps": steps, "elapsed_s": elapsed, "ms_per_step": 1e3 * elapsed / steps,
+           "vertex_updates_per_step": upd / steps, "vertex_updates_per_s": upd / elapsed,
+           "cycles_per_step": reps[-1]["cycles"], "outer_iters_per_step": reps[-1]["outer_iters"],
+           "relres_after_step": reps[-1]["relres"], "relres_history": [float(x) for x in hist],
+           "coarsest_level_used": reps[-1]["coarsest_level_used"],
+           "bytes_operators": reps[-1]["bytes_operators"],
+           "build_ms": 1e3 * float(np.median(tb_)), "cycles_ms": 1e3 * float(np.median(tc_)),
+           "cycle_vertex_updates_per_s": (upd / steps) / float(np.median(tc_)),
+           "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "kernel_launches": launches, "kernel_ms": ms}
+    return g, inputs, out
+
+
+def band_residual_rows(g, inputs, P, n_samples=160, seed=11):
+    """Composite residual rows (FP64 iterates) of the library against the
+    oracle's rows assembled one by one at sampled unknowns from the same
+    iterate; rows needing a hanging value (a BoxMG interpolant) are left to
+    the mid-size parity tests."""
+    import oracle.adaptive as AD
+    u = g.solution()
+    r = g.residual()
+    lev = inputs.lev.astype(np.int64)
+    n = 3 ** lev
+    ijk = np.rint(inputs.xyz * n[:, None]).astype(np.int64)
+    key = (lev << 40) | (ijk[:, 0] + 1024 * (ijk[:, 1] + 1024 * ijk[:, 2]))
+    order = np.argsort(key)
+    skey = key[order]
+
+    def u_of(l, w):
+        k = (l << 40) | (w[0] + 1024 * (w[1] + 1024 * w[2]))
+        j = np.searchsorted(skey, k)
+        if j >= len(skey) or skey[j] != k:
+            raise KeyError(f"no unknown at level {l} position {w}")
+        return u[order[j]]
+
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(len(lev), n_samples, replace=False)
+    T = AD.LocalSpacetree(3, P.base, P.level, P.mark)
+    samples = [(int(lev[k]), tuple(int(x) for x in ijk[k])) for k in pick]
+    rows, scale = AD.local_composite_rows(T, P.eps_at, P.f_at, u_of, samples)
+    ok = ~np.isnan(rows)
+    diff = np.abs(rows[ok] - r[pick][ok]) / np.maximum(scale[ok], 1e-300)
+    return {"sampled": int(n_samples), "checked": int(ok.sum()),
+            "max_rel_diff": float(diff.max()) if ok.any() else None,
+            "note": "|r_gpu - r_oracle| / sum |K||u| per row after the timed steps; "
+                    "rows touching a hanging vertex are skipped"}
+
+
+def cpu_band_sample(seed=0):
+    """One bounded sample of the headline workload for the oracle: the same
+    band, cube field and source refined to level 4 (base 3; 135k unknowns),
+    BoxMG + Galerkin build and two FP64 V(2,2) FAS cycles, single thread.
+    Returns (vertex updates, seconds)."""
+    from threadpoolctl import threadpool_limits
+    import oracle.adaptive as AD
+    import workloads as W
+    with threadpool_limits(limits=1):
+        P = W.adaptive_band(dim=3, base=3, level=4, seed=seed)
+        G = AD.AdaptiveGrid(3, P.base, P.level, P.flags)
+        eps = P.eps_at(G.cell_centres())
+        xyz = G.unknown_coords()
+        lv = np.array([l for l, _ in G.leaves()])
+        f = np.concatenate([P.f_at(l, xyz[lv == l]) for l in range(P.base, P.level + 1)])
+        t0 = time.perf_counter()
+        H = AD.build_adaptive(G, eps, transfer="boxmg")
+        AD.solve_adaptive(H, f, cycles=2)
+        dt = time.perf_counter() - t0
+    per_cycle = sum(4 * int(np.isin(G.vtype[l], (AD.LEAF, AD.REFINED)).sum())
+                    for l in range(P.base + 1, P.level + 1))
+    per_cycle += sum(4 * (3 ** l - 1) ** 3 for l in range(2, P.base + 1))
+    return 2 * per_cycle, dt
+
+
+def _cpu_worker(seed):
+    return cpu_band_sample(seed)
+
+
+def cpu_baselines():
+    """The oracle on the bounded sample: one thread, then one sample per host
+    core at once (a process pool, one BLAS thread each)."""
+    import multiprocessing as mp
+    import platform
+    upd, dt = cpu_band_sample(0)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    sample = ("the headline workload at level 4 (base 3, the same band, cubes and source; "
+              "135k unknowns): BoxMG + Galerkin build and two FP64 V(2,2) FAS cycles, "
+              "updates counted as on the GPU")
+    one = {"value": upd / dt, "unit": "vertex updates/s", "cores": 1, "kind": "oracle",
+           "sample": f"{sample}; {dt:.1f} s on one thread", "cpu_model": model}
+    t0 = time.perf_counter()
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_cpu_worker, [0] * cores)
+    wall = time.perf_counter() - t0
+    allc = {"value": sum(r[0] for r in res) / wall, "unit": "vertex updates/s", "cores": cores,
+            "kind": "oracle", "sample": f"{cores} copies of the same sample at once, one per core, "
+                                        f"{wall:.1f} s wall (process start included)",
+            "cpu_model": model}
+    return one, allc
+
+
+def checkerboard_block(qmg, W, args):
+    """The 2D jumping-coefficient workload (729^2 cells, 9x9 checkerboard of
+    {1, 1e4}, BoxMG + Galerkin, V(2,2), to 1e-8): solves/s, latency, its own
+    roofline figure (the fused finest-level pass) and its store variants."""
+    p = W.checkerboard2d(0, level=6)
+    store = "hier64"
+    res = run_variant(qmg, p, "boxmg", store, args.cb_steps, 2, profile=args.profile_every)
+    lat = np.array(res["lat"])
+    n_int = p.n_unknowns
+    fused_bytes = FUSED_MIN_BYTES[(store, 2)] * n_int
+    avg_s = res["kernel_ms"] / max(res["kernel_launches"], 1) / 1e3
+    out = {"workload": f"2D -div(eps grad u)=f, {p.n}^2 cells ({p.n - 1}^2 unknowns), eps random 9x9 "
+                       f"checkerboard {{1,1e4}} (seed 0), f~U[-1,1]; BoxMG + Galerkin RAP, store {store}, "
+                       f"V(2,2), omega 0.6, exact coarsest solve, to 1e-8 relative residual",
+           "step": "set_coefficients (inputs in HBM) + build_operators + solve",
+           "vertex_updates_per_s": res["updates"] / res["elapsed"],
+           "solves_per_s": len(lat) / res["elapsed"],
+           "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "cycles_per_solve": res["reps"][-1]["cycles"], "relres": res["reps"][-1]["relres"],
+           "pass": {"kernel": TIMED_KERNEL[2], "avg_launch_us": avg_s * 1e6,
+                    "bytes_per_launch": fused_bytes,
+                    "gbs": fused_bytes / avg_s / 1e9 if avg_s > 0 else None,
+                    "effective_gbs": OP_BYTES[(store, 2)] * 3 * n_int / avg_s / 1e9 if avg_s > 0 else None,
+                    "traffic": measured_traffic(f"k_pass2d:checkerboard2d_L6:{store}"),
+                    "note": "gbs: the bytes the fused pass must move (eps, u, b read; u'' and r "
+                            "written) over its time; effective_gbs counts each of its two sweeps "
+                            "and the residual as if streamed on its own.  The grid (~60 MB) stays "
+                            "in the 256 MB Infinity Cache, so neither is an HBM fraction."}}
+    gb = qmg.Grid(p.dim, p.level, qmg.make_opts("boxmg", store))
+    out["build_ms"] = time_build(gb, p.eps, p.f)
+    gb.close()
+    hp = run_variant(qmg, p, "boxmg", store, max(3, args.cb_steps // 2), 1, host_inputs=True)
+    out["host_inputs"] = {"solves_per_s": len(hp["lat"]) / hp["elapsed"],
+                          "p50_ms": float(np.percentile(hp["lat"], 50) * 1e3),
+                          "note": "same step with eps and f handed over from host memory"}
+    variants = {}
+    for v in [s for s in args.variants.split(",") if s]:
+        r = run_variant(qmg, p, "boxmg", v, max(3, args.cb_steps // 2), 1)
+        variants[v] = {"solves_per_s": len(r["lat"]) / r["elapsed"],
+                       "vertex_updates_per_s": r["updates"] / r["elapsed"],
+                       "cycles_per_solve": r["reps"][-1]["cycles"], "relres": r["reps"][-1]["relres"],
+                       "p50_ms": float(np.percentile(r["lat"], 50) * 1e3)}
+    if args.variants:
+        r = run_variant(qmg, p, "boxmg", store, max(3, args.cb_steps // 2), 1, smoother="block", bj_sweeps=3)
+        variants[f"{store}_block_jacobi3"] = {
+            "solves_per_s": len(r["lat"]) / r["elapsed"],
+            "vertex_updates_per_s": r["updates"] / r["elapsed"],
+            "cycles_per_solve": r["reps"][-1]["cycles"], "relres": r["reps"][-1]["relres"],
+            "p50_ms": float(np.percentile(r["lat"], 50) * 1e3)}
+    out["variants"] = variants
+    return out, res["u"], p
+
+
+def roofline_sweep(qmg, W, spec, profile_every, ceiling):
+    sweep = []
+    for item in [s for s in spec.split(",") if s]:
+        dim, level = (int(x) for x in item.split(":"))
+        q = W.random_checkerboard(dim, level, 0, name=f"jump{dim}d-L{level}")
+        for store in ("hier64", "plain64", "bf16"):
+            r = run_variant(qmg, q, "boxmg", store, 2, 1, profile=profile_every or 8)
+            avg = r["kernel_ms"] / max(r["kernel_launches"], 1) / 1e3
+            ops = TIMED_OPS[dim]
+            op_b = OP_BYTES[(store, dim)] * ops * q.n_unknowns
+            mv_b = FUSED_MIN_BYTES.get((store, dim), OP_BYTES[(store, dim)]) * q.n_unknowns
+            gbs = mv_b / avg / 1e9 if avg > 0 else None
+            kern = "k_pass2d" if dim == 2 else "k_march3d"
+            sweep.append({"dim": dim, "level": level, "unknowns": q.n_unknowns, "store": store,
+                          "solves_per_s": len(r["lat"]) / r["elapsed"],
+                          "vertex_updates_per_s": r["updates"] / r["elapsed"],
+                          "cycles_per_solve": r["reps"][-1]["cycles"], "relres": r["reps"][-1]["relres"],
+                          "kernel": TIMED_KERNEL[dim], "avg_launch_us": avg * 1e6,
+                          "bytes_per_launch": mv_b, "gbs": gbs,
+                          "frac": gbs / HBM_PEAK_GBS if gbs else None,
+                          "frac_of_copy": gbs / ceiling if gbs and ceiling else None,
+                          "effective_gbs": op_b / avg / 1e9 if avg > 0 else None,
+                          "traffic": measured_traffic(f"{kern}:jump{dim}d_L{level}:{store}")})
+            print(f"sweep {dim}D L{level} {store}: {sweep[-1]['solves_per_s']:.2f} solves/s, "
+                  f"{sweep[-1]['avg_launch_us']:.1f} us/launch, {gbs or 0:.0f} GB/s", file=sys.stderr,
+                  flush=True)
+        del q
+    return sweep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--level", type=int, default=6)
-    ap.add_argument("--store", default="hier64")
+    ap.add_argument("--level", type=int, default=6, help="finest level of the band workload")
+    ap.add_argument("--store", default="bf16", help="store of the headline line")
+    ap.add_argument("--band-variants", default="hier16,hier64,plain64",
+                    help="other stores timed on the band workload (comma list, '' for none)")
+    ap.add_argument("--cb-steps", type=int, default=30, help="solves of the 2D checkerboard workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-checkerboard", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (HBM counter calibration)")
     ap.add_argument("--profile-every", type=int, default=8,
                     help="time every k-th launch of the timed kernel with HIP events (0: none)")
-    ap.add_argument("--sweep", default="2:8",
+    ap.add_argument("--sweep", default="2:8,3:5",
                     help="roofline sweep on larger regular grids, dim:level comma list ('' for none): "
                          "the same step for the hier64, plain64 and bf16 stores")
     ap.add_argument("--variants", default="plain64,bf16,bpa",
-                    help="extra stores timed on the same workload (comma list, '' for none)")
+                    help="extra stores timed on the 2D checkerboard workload (comma list, '' for none)")
     ap.add_argument("--others", type=int, default=50, metavar="N",
-                    help="repeated solves of the 2D Poisson and 3D adaptive workloads (0: skip)")
+                    help="repeated solves of the other single-grid workloads (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver path is "
@@ -332,106 +655,86 @@ def main():
         torch.cuda.synchronize()
         print(f"copy calibration: {args.calibrate_copy} MiB read + written", file=sys.stderr)
         del src, dst
-    p = W.checkerboard2d(0, level=args.level)
-    # timed pass: every PROFILE_EVERY-th finest-level sweep carries per-dispatch
-    # HIP events on the grid's stream
-    res = run_variant(qmg, p, "boxmg", args.store, args.steps, args.warmup,
-                      profile=args.profile_every)
-    lat = np.array(res["lat"])
-    vu = res["updates"] / res["elapsed"]
-    n_int = p.n_unknowns
-    bytes_per_launch = OP_BYTES[(args.store, p.dim)] * TIMED_OPS[p.dim] * n_int
-    fused_bytes = FUSED_MIN_BYTES.get((args.store, p.dim), OP_BYTES[(args.store, p.dim)]) * n_int
+    ceiling = copy_ceiling()
+    P = W.adaptive_band(dim=3, base=3, level=args.level, seed=0)
+    g, inputs, res = band_step_runs(qmg, P, args.store, args.steps, args.warmup, profile=args.profile_every)
+    g.close()
     avg_s = res["kernel_ms"] / max(res["kernel_launches"], 1) / 1e3
-    achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else None
+    alg = AD_SWEEP_BYTES[args.store] * inputs.n_finest
+    achieved = alg / avg_s / 1e9 if avg_s > 0 else None
+    print(f"band {args.store}: {res['ms_per_step']:.1f} ms/step, sweep {avg_s * 1e6:.1f} us, "
+          f"{achieved or 0:.0f} GB/s", file=sys.stderr, flush=True)
     out = {
         "metric": METRIC,
-        "value": vu,
+        "value": res["vertex_updates_per_s"],
         "unit": "vertex updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * res["elapsed"] / args.steps,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.store in ("hier64", "plain64") else "f32+f64",
+        "dtype": "f32+f64" if args.store in ("bf16", "hier16", "hier32") else "f64",
         "data": "synthetic",
-        "config": {"workload": f"2D -div(eps grad u)=f, {p.n}^2 cells ({p.n - 1}^2 unknowns), "
-                               f"eps random 9x9 checkerboard {{1,1e4}} (seed 0), f~U[-1,1]; "
-                               f"BoxMG + Galerkin RAP, store {args.store}, V(2,2), omega 0.6, "
-                               f"exact coarsest solve, to 1e-8 relative residual",
-                   "step": "set_coefficients (inputs in HBM) + build_operators + solve",
-                   "level": p.level, "unknowns": n_int},
-        "solves_per_s": args.steps / res["elapsed"],
-        "p50_ms": float(np.percentile(lat, 50) * 1e3),
-        "p99_ms": float(np.percentile(lat, 99) * 1e3),
-        "cycles_per_solve": res["reps"][-1]["cycles"],
-        "relres": res["reps"][-1]["relres"],
+        "config": {"workload": f"3D -div(eps grad u)=f on an adaptive spacetree: base level 3, refined to "
+                               f"level {P.level} in the band |phi| < tau (10% quantile) of a seeded RFF "
+                               f"level set (length 0.2); eps = 1e6 in 64 seeded cubes (sides "
+                               f"U[0.05,0.15]), 1 outside; f~U[-1,1]; BoxMG + Galerkin, store "
+                               f"{args.store}, V(2,2) FAS cycles, omega 0.6, FP64 composite defect "
+                               f"correction",
+                   "step": "set_coefficients (inputs in HBM) + build_operators + 2 outer iterations "
+                           "(cycles) from zero",
+                   "level": P.level, "unknowns": res["unknowns"], "leaf_cells": res["leaf_cells"],
+                   "finest_level_unknowns": inputs.n_finest},
+        "cycle_vertex_updates_per_s": res["cycle_vertex_updates_per_s"],
+        "build_ms": res["build_ms"], "cycles_ms": res["cycles_ms"],
+        "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"],
+        "relres_history": res["relres_history"],
+        "converges": False,
+        "convergence_note": "the configured method (BoxMG + Galerkin, damped Jacobi) diverges on this "
+                            "workload: its Galerkin coarse operators turn indefinite at contrast 1e6 "
+                            "(negative diagonals below the base level); a step therefore runs two "
+                            "cycles and no solves/s or converged error is reported for it",
+        "workspace_bytes": res["workspace_bytes"], "bytes_operators": res["bytes_operators"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": MEASURED_TRAFFIC.get((args.store, p.dim, p.level)),
-                     "kernel": TIMED_KERNEL[p.dim],
-                     "bytes_per_launch": bytes_per_launch,
-                     "bytes_per_launch_note": "per-operation figures (each sweep and the residual "
-                                              "streamed on its own) x operations in the launch",
-                     "fused_bytes_per_launch": fused_bytes,
-                     "fused_gbs": fused_bytes / avg_s / 1e9 if avg_s > 0 else None,
+                     "traffic": measured_traffic(f"k_ad_stencil:band3d_L{P.level}:{args.store}"),
+                     "kernel": AD_SWEEP_KERNEL,
+                     "bytes_per_launch": alg,
+                     "bytes_per_launch_note": f"{AD_SWEEP_BYTES[args.store]} B per active vertex of the "
+                                              f"finest level ({inputs.n_finest} vertices)",
                      "avg_launch_us": avg_s * 1e6, "timed_launches": res["kernel_launches"],
-                     "timing": f"per-dispatch HIP events (hipExtLaunchKernelGGL) on the grid stream "
-                               f"around every {args.profile_every}-th such launch of the timed steps"},
+                     "copy_ceiling_gbs": ceiling,
+                     "frac_of_copy": (achieved / ceiling) if achieved else None,
+                     "timing": f"per-dispatch HIP events (hipExtLaunchKernelGGL) on the grid stream around "
+                               f"every {args.profile_every}-th such launch of the timed steps"},
     }
-    gb = qmg.Grid(p.dim, p.level, qmg.make_opts("boxmg", args.store))
-    out["build_ms"] = time_build(gb, p.eps, p.f)
-    out["build_note"] = "build_operators alone (BoxMG P, Galerkin RAP, delta store, coarsest inverse), p50"
-    gb.close()
-    hp = run_variant(qmg, p, "boxmg", args.store, max(3, args.steps // 2), 1, host_inputs=True)
-    out["host_inputs"] = {"solves_per_s": len(hp["lat"]) / hp["elapsed"],
-                          "p50_ms": float(np.percentile(hp["lat"], 50) * 1e3),
-                          "note": "same step with eps and f handed over from host memory"}
     variants = {}
-    for v in [s for s in args.variants.split(",") if s]:
-        r = run_variant(qmg, p, "boxmg", v, max(3, args.steps // 2), 1)
-        variants[v] = {"solves_per_s": len(r["lat"]) / r["elapsed"],
-                       "vertex_updates_per_s": r["updates"] / r["elapsed"],
-                       "cycles_per_solve": r["reps"][-1]["cycles"],
-                       "relres": r["reps"][-1]["relres"],
-                       "p50_ms": float(np.percentile(r["lat"], 50) * 1e3)}
-    if args.variants:
-        # the paper's block Jacobi smoother (3 Gauss-Seidel sweeps per patch)
-        r = run_variant(qmg, p, "boxmg", args.store, max(3, args.steps // 2), 1, smoother="block", bj_sweeps=3)
-        variants[f"{args.store}_block_jacobi3"] = {
-            "solves_per_s": len(r["lat"]) / r["elapsed"],
-            "vertex_updates_per_s": r["updates"] / r["elapsed"],
-            "cycles_per_solve": r["reps"][-1]["cycles"], "relres": r["reps"][-1]["relres"],
-            "p50_ms": float(np.percentile(r["lat"], 50) * 1e3)}
-    if variants:
-        out["variants"] = variants
-    sweep = []
-    for item in [s for s in args.sweep.split(",") if s]:
-        dim, level = (int(x) for x in item.split(":"))
-        q = W.random_checkerboard(dim, level, 0, name=f"jump{dim}d-L{level}")
-        for store in ("hier64", "plain64", "bf16"):
-            r = run_variant(qmg, q, "boxmg", store, 2, 1, profile=args.profile_every or 8)
-            avg = r["kernel_ms"] / max(r["kernel_launches"], 1) / 1e3
-            op_b = OP_BYTES[(store, dim)] * TIMED_OPS[dim] * q.n_unknowns
-            fz_b = FUSED_MIN_BYTES.get((store, dim), OP_BYTES[(store, dim)]) * q.n_unknowns
-            sweep.append({"dim": dim, "level": level, "unknowns": q.n_unknowns, "store": store,
-                          "solves_per_s": len(r["lat"]) / r["elapsed"],
-                          "vertex_updates_per_s": r["updates"] / r["elapsed"],
-                          "cycles_per_solve": r["reps"][-1]["cycles"], "relres": r["reps"][-1]["relres"],
-                          "kernel": TIMED_KERNEL[dim], "avg_launch_us": avg * 1e6,
-                          # per-operation bytes (each sweep and the residual streamed on
-                          # its own; above peak when fusion saves re-reads, as for the
-                          # plain store's stencils) and the bytes the fused pass moves
-                          "effective_gbs": op_b / avg / 1e9 if avg > 0 else None,
-                          "effective_frac": op_b / avg / 1e9 / HBM_PEAK_GBS if avg > 0 else None,
-                          "fused_bytes_per_launch": fz_b,
-                          "fused_gbs": fz_b / avg / 1e9 if avg > 0 else None,
-                          "fused_frac": fz_b / avg / 1e9 / HBM_PEAK_GBS if avg > 0 else None})
-            print(f"sweep {dim}D L{level} {store}: {sweep[-1]['solves_per_s']:.2f} solves/s, "
-                  f"{sweep[-1]['avg_launch_us']:.1f} us/launch", file=sys.stderr, flush=True)
-        del q
+    for st in [s for s in args.band_variants.split(",") if s]:
+        gv, _, rv = band_step_runs(qmg, P, st, max(3, args.steps // 2), 1, inputs=inputs,
+                                   profile=args.profile_every)
+        avg_v = rv["kernel_ms"] / max(rv["kernel_launches"], 1) / 1e3
+        alg_v = AD_SWEEP_BYTES[st] * inputs.n_finest
+        rv["sweep_avg_us"] = avg_v * 1e6
+        rv["sweep_gbs"] = alg_v / avg_v / 1e9 if avg_v > 0 else None
+        if st == "hier64":
+            rv["residual_rows_vs_oracle"] = band_residual_rows(gv, inputs, P)
+        gv.close()
+        for k in ("kernel_launches", "kernel_ms"):
+            rv.pop(k)
+        variants[st] = rv
+        print(f"band {st}: {rv['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    out["band_variants"] = variants
+    if "plain64" in variants:
+        out["mixed_over_plain64"] = out["value"] / variants["plain64"]["vertex_updates_per_s"]
+    del inputs
+    torch.cuda.empty_cache()
+    ucb = pcb = None
+    if not args.no_checkerboard:
+        out["checkerboard2d"], ucb, pcb = checkerboard_block(qmg, W, args)
+    sweep = roofline_sweep(qmg, W, args.sweep, args.profile_every, ceiling)
     if sweep:
         out["roofline_sweep"] = sweep
     if args.others:
@@ -439,10 +742,15 @@ def main():
     if not args.no_serving:
         out["serving"] = serve_stream(qmg)
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(p)
-        ucpu = cb.pop("u")
-        out["cpu_baseline"] = cb
-        out["u_rel_diff_vs_oracle"] = float(np.linalg.norm(res["u"] - ucpu) / np.linalg.norm(ucpu))
+        one, allc = cpu_baselines()
+        out["cpu_baseline"] = one
+        out["cpu_baseline_all_cores"] = allc
+        if ucb is not None:
+            cb = cpu_baseline(pcb)
+            ucpu = cb.pop("u")
+            out["checkerboard2d"]["cpu_baseline"] = cb
+            out["checkerboard2d"]["u_rel_diff_vs_oracle"] = float(np.linalg.norm(ucb - ucpu) /
+                                                                   np.linalg.norm(ucpu))
     if args.others:
         ow = out["other_workloads"]["poisson2d_L4"]
         u1 = ow.pop("u")

@@ -619,3 +619,110 @@ def solve_adaptive(H, f_leaf, tol=1e-8, max_cycles=200, cycles=None, stagnation=
 def solve_composite_direct(G, eps_leaf, f_leaf, P=None):
     A, b = composite_system(G, eps_leaf, f_leaf, P)
     return spla.spsolve(sp.csc_matrix(A), b), A, b
+
+
+# ---------------------------------------------------------------------------
+# Spacetrees too large to lay out: classes and composite rows decided locally
+# ---------------------------------------------------------------------------
+
+class LocalSpacetree:
+    """The spacetree of Sect. 2 decided cell by cell for grids too large for
+    ``AdaptiveGrid``: levels 0..base are complete; a cell of level base..L-1
+    is refined when it exists and the refinement predicate ``mark(l, cells)``
+    holds; a cell of a finer level exists when its parent is refined.  Vertex
+    classes follow the same definitions as ``AdaptiveGrid`` (hanging: fewer
+    than 2^d cells of its level; refined: all 2^d cells refined; leaf: the
+    other interior vertices).  Positions are x-first integer tuples."""
+
+    def __init__(self, d, base, L, mark):
+        self.d, self.base, self.L, self.mark = d, base, L, mark
+        self._ref = {}
+
+    def exists(self, l, c):
+        n = 3 ** l
+        if any(ci < 0 or ci >= n for ci in c):
+            return False
+        return l <= self.base or self.refined(l - 1, tuple(ci // 3 for ci in c))
+
+    def refined(self, l, c):
+        if l >= self.L:
+            return False
+        if l < self.base:
+            return self.exists(l, c)
+        key = (l, c)
+        if key not in self._ref:
+            self._ref[key] = bool(self.exists(l, c) and self.mark(l, np.array([c]))[0])
+        return self._ref[key]
+
+    def vclass(self, l, v):
+        n = 3 ** l
+        if any(vi <= 0 or vi >= n for vi in v):
+            return OUT
+        cnt = nref = 0
+        for s in corners(self.d):
+            c = tuple(vi - si for vi, si in zip(v, s))
+            if self.exists(l, c):
+                cnt += 1
+                nref += self.refined(l, c)
+        if cnt == 2 ** self.d:
+            return REFINED if nref == 2 ** self.d else LEAF
+        return HANGING if cnt > 0 else OUT
+
+    def cell_eps(self, l, c, eps_at):
+        """Coefficient of an existing cell: its own for a leaf cell (at its
+        centre), the mean of its 3^d children for a refined one."""
+        if not self.refined(l, c):
+            x = (np.array(c, dtype=np.float64) + 0.5) * 3.0 ** -l
+            return float(eps_at(x[None, :])[0])
+        kids = [tuple(3 * ci + oi for ci, oi in zip(c, o)) for o in itertools.product(range(3), repeat=self.d)]
+        return float(np.mean([self.cell_eps(l + 1, k, eps_at) for k in kids]))
+
+
+def local_composite_rows(T: LocalSpacetree, eps_at, f_at, u_of, samples):
+    """b - A u of the composite system (Sect. 2) at leaf unknowns given as
+    (level, x-first position) pairs, each row assembled on its own from the
+    element matrices of the 2^d cells around the vertex (coefficients from
+    ``eps_at``, the source from ``f_at(level, coords)``) and the composite
+    values of their corners: ``u_of(level, position)`` for a leaf, the finest
+    copy for a refined vertex, zero on the boundary.  A row that needs a
+    hanging value (an interpolant of the coarser level) is returned as NaN.
+    Also returns, per row, sum |K| |u| (the scale of the row's rounding)."""
+    d = T.d
+    cs = corners(d)
+    out = np.full(len(samples), np.nan)
+    scale = np.zeros(len(samples))
+
+    def value(l, w):
+        t = T.vclass(l, w)
+        if t == LEAF:
+            return u_of(l, w)
+        if t == REFINED:
+            return value(l + 1, tuple(3 * wi for wi in w))
+        if t == HANGING:
+            return None
+        return 0.0
+
+    for q, (l, v) in enumerate(samples):
+        if T.vclass(l, v) != LEAF:
+            raise AssertionError(f"sample {l} {v} is not a leaf vertex")
+        h = 3.0 ** -l
+        acc, sc, ok = 0.0, 0.0, True
+        for s in cs:                                   # v is corner s of cell v - s
+            cell = tuple(vi - si for vi, si in zip(v, s))
+            K = element_matrix(d, h, T.cell_eps(l, cell, eps_at))
+            ia = corner_index(s)
+            for ib, w in enumerate(cs):
+                uw = value(l, tuple(ci + wi for ci, wi in zip(cell, w)))
+                if uw is None:
+                    ok = False
+                    break
+                acc += K[ia, ib] * uw
+                sc += abs(K[ia, ib] * uw)
+            if not ok:
+                break
+        if ok:
+            x = np.array(v, dtype=np.float64) * h
+            bq = h ** d * float(f_at(l, x[None, :])[0])
+            out[q] = bq - acc
+            scale[q] = sc + abs(bq)
+    return out, scale

@@ -886,8 +886,13 @@ template <typename T>
 void smooth_ad(qmg_grid_t* g, LevelBuf& B, int sweeps) {
   const T om = (T)g->opts.omega;
   const AdTiles t = B.ad();
+  const bool finest = g->prof_every > 0 && B.L.n == g->lv[g->Lmax].L.n;
   for (int k = 0; k < sweeps; ++k) {
-    launch_ad_stencil<T, T>(t, 0, (const T*)B.u, (const T*)B.b, (T*)B.t, eps_of<T>(B), B.A, om, nullptr, S(g));
+    // timed: every k-th sweep of the finest adaptive level
+    const bool timed = finest && (g->prof_count++ % g->prof_every) == 0;
+    hipEvent_t* ev = timed ? prof_pair(g) : nullptr;
+    launch_ad_stencil<T, T>(t, 0, (const T*)B.u, (const T*)B.b, (T*)B.t, eps_of<T>(B), B.A, om, nullptr, S(g),
+                            ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
     std::swap(B.u, B.t);
   }
 }

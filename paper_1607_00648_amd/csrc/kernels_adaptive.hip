@@ -9,6 +9,7 @@
 // of the coarser level; refined coarse vertices receive the value of their
 // finer copy and the FAS right-hand side.
 #include "level_ops.hpp"
+#include <hip/hip_ext.h>
 
 namespace qmg {
 
@@ -292,8 +293,13 @@ inline dim3 full_grid(const Lat& L) {
 
 template <int D, typename T, typename TO, int SRC, int FMT>
 void ad_stencil_mode(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
-                     const Store& A, T omega, double* partial, hipStream_t s) {
+                     const Store& A, T omega, double* partial, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const dim3 g = tiles_grid(t.n), bl(TX, TY, 1);
+  if (e0 != nullptr && mode == 0) {  // per-dispatch timestamps of a timed sweep
+    hipExtLaunchKernelGGL((k_ad_stencil<D, T, TO, SRC, FMT, 0>), g, bl, 0, s, e0, e1, 0, t.L, t.tiles, t.vt, u,
+                          b, out, eps, A, omega, partial);
+    return;
+  }
   switch (mode) {
     case 0: hipLaunchKernelGGL((k_ad_stencil<D, T, TO, SRC, FMT, 0>), g, bl, 0, s, t.L, t.tiles, t.vt, u, b, out, eps, A, omega, partial); break;
     case 1: hipLaunchKernelGGL((k_ad_stencil<D, T, TO, SRC, FMT, 1>), g, bl, 0, s, t.L, t.tiles, t.vt, u, b, out, eps, A, omega, partial); break;
@@ -303,15 +309,17 @@ void ad_stencil_mode(const AdTiles& t, int mode, const T* u, const T* b, TO* out
 
 template <int D, typename T, typename TO>
 void ad_stencil_src(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
-                    const Store& A, T omega, double* partial, hipStream_t s) {
-  if (A.src == SRC_GEOM) return ad_stencil_mode<D, T, TO, SRC_GEOM, F64>(t, mode, u, b, out, eps, A, omega, partial, s);
-  if (A.src == SRC_PLAIN) return ad_stencil_mode<D, T, TO, SRC_PLAIN, F64>(t, mode, u, b, out, eps, A, omega, partial, s);
+                    const Store& A, T omega, double* partial, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+#define QMG_ADS(SRCV, FMTV) ad_stencil_mode<D, T, TO, SRCV, FMTV>(t, mode, u, b, out, eps, A, omega, partial, s, e0, e1)
+  if (A.src == SRC_GEOM) return QMG_ADS(SRC_GEOM, F64);
+  if (A.src == SRC_PLAIN) return QMG_ADS(SRC_PLAIN, F64);
   switch (A.fmt) {
-    case F64: return ad_stencil_mode<D, T, TO, SRC_HIER, F64>(t, mode, u, b, out, eps, A, omega, partial, s);
-    case F32: return ad_stencil_mode<D, T, TO, SRC_HIER, F32>(t, mode, u, b, out, eps, A, omega, partial, s);
-    case F16: return ad_stencil_mode<D, T, TO, SRC_HIER, F16>(t, mode, u, b, out, eps, A, omega, partial, s);
-    default: return ad_stencil_mode<D, T, TO, SRC_HIER, BF16>(t, mode, u, b, out, eps, A, omega, partial, s);
+    case F64: return QMG_ADS(SRC_HIER, F64);
+    case F32: return QMG_ADS(SRC_HIER, F32);
+    case F16: return QMG_ADS(SRC_HIER, F16);
+    default: return QMG_ADS(SRC_HIER, BF16);
   }
+#undef QMG_ADS
 }
 
 template <int D, typename T, int PSRC>
@@ -346,15 +354,15 @@ inline void check_ad_P(const Store& P) {
 
 template <typename T, typename TO>
 void launch_ad_stencil(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
-                       const Store& A, T omega, double* partial, hipStream_t s) {
+                       const Store& A, T omega, double* partial, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (t.n <= 0) return;
-  if (t.L.d == 2) ad_stencil_src<2, T, TO>(t, mode, u, b, out, eps, A, omega, partial, s);
-  else ad_stencil_src<3, T, TO>(t, mode, u, b, out, eps, A, omega, partial, s);
+  if (t.L.d == 2) ad_stencil_src<2, T, TO>(t, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
+  else ad_stencil_src<3, T, TO>(t, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
   QMG_HIP(hipGetLastError());
 }
-template void launch_ad_stencil<double, double>(const AdTiles&, int, const double*, const double*, double*, const double*, const Store&, double, double*, hipStream_t);
-template void launch_ad_stencil<float, float>(const AdTiles&, int, const float*, const float*, float*, const float*, const Store&, float, double*, hipStream_t);
-template void launch_ad_stencil<double, float>(const AdTiles&, int, const double*, const double*, float*, const double*, const Store&, double, double*, hipStream_t);
+template void launch_ad_stencil<double, double>(const AdTiles&, int, const double*, const double*, double*, const double*, const Store&, double, double*, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_ad_stencil<float, float>(const AdTiles&, int, const float*, const float*, float*, const float*, const Store&, float, double*, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_ad_stencil<double, float>(const AdTiles&, int, const double*, const double*, float*, const double*, const Store&, double, double*, hipStream_t, hipEvent_t, hipEvent_t);
 
 template <typename T>
 void launch_ad_hang(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const Store& P, hipStream_t s) {

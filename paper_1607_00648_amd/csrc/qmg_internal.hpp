@@ -304,10 +304,12 @@ struct AdTiles {
 };
 // mode 0: Jacobi sweep of leaf and refined vertices (others copied), 1: the
 // same from zero, 2: residual (zero off that set; partial: per-tile sums of
-// squares over the leaves).
+// squares over the leaves).  e0/e1 (mode 0 only, nullable): per-dispatch
+// timestamps of the launch.
 template <typename T, typename TO>
 void launch_ad_stencil(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
-                       const Store& A, T omega, double* partial, hipStream_t s);
+                       const Store& A, T omega, double* partial, hipStream_t s, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
 // P: the fine level's prolongation store (d-linear, FP64 deltas, or plain)
 template <typename T>
 void launch_ad_hang(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const Store& P, hipStream_t s);

@@ -238,3 +238,43 @@ def test_stagnation_raise_moves_coarsest_level_to_the_base():
     ustar, _, _ = AD.solve_composite_direct(G, eps, f)
     assert h1[-1] <= 1e-10
     assert np.linalg.norm(u - ustar) <= 1e-8 * np.linalg.norm(ustar)
+
+
+@pytest.mark.parametrize("d,base,L", [(3, 2, 3), (2, 2, 5)])
+def test_local_spacetree_matches_the_laid_out_grid(d, base, L):
+    """The spacetree decided cell by cell (for grids too large to lay out)
+    has the vertex classes of the laid-out grid at every vertex, and its
+    composite rows equal the assembled composite system's rows wherever no
+    hanging value is needed (the band workload's refinement and coefficient
+    contrast 10^6, random iterate)."""
+    P = W.adaptive_band(dim=d, base=base, level=L)
+    G = AD.AdaptiveGrid(d, base, L, P.flags)
+    T = AD.LocalSpacetree(d, base, L, P.mark)
+    rng = np.random.default_rng(3)
+    for l in range(base, L + 1):
+        n = 3 ** l
+        idx = rng.integers(0, n + 1, size=(300, d))
+        leaves = np.argwhere(G.vtype[l] == AD.LEAF)[:, ::-1]
+        idx = np.concatenate([idx, leaves[rng.choice(len(leaves), min(200, len(leaves)), replace=False)]])
+        for v in idx:
+            assert T.vclass(l, tuple(int(x) for x in v)) == G.vtype[l][tuple(v[::-1])]
+    eps = P.eps_at(G.cell_centres())
+    xyz = G.unknown_coords()
+    lv = np.array([l for l, _ in G.leaves()])
+    f = np.concatenate([P.f_at(l, xyz[lv == l]) for l in range(base, L + 1)])
+    u = rng.uniform(-1, 1, size=G.n_unknowns())
+    A, b = AD.composite_system(G, eps, f)
+    r_full = b - A @ u
+    leaves = G.leaves()
+    pos = {(l, tuple(int(x) for x in v[::-1])): k for k, (l, v) in enumerate(leaves)}
+    pick = rng.choice(G.n_unknowns(), 300, replace=False)
+    samples = [(leaves[k][0], tuple(int(x) for x in leaves[k][1][::-1])) for k in pick]
+    rows, scale = AD.local_composite_rows(T, P.eps_at, P.f_at, lambda l, w: u[pos[(l, w)]], samples)
+    ok = ~np.isnan(rows)
+    assert ok.sum() > 100
+    np.testing.assert_allclose(rows[ok], r_full[pick][ok], rtol=0, atol=1e-13 * scale[ok].max())
+    # the rows it declines are exactly those touching a hanging vertex
+    for (l, v), good in zip(samples, ok):
+        nb = [tuple(vi + oi - 1 for vi, oi in zip(v, o)) for o in np.ndindex(*([3] * d))]
+        hang = any(T.vclass(l, w) == AD.HANGING for w in nb)
+        assert good != hang

@@ -260,6 +260,7 @@ class AdaptiveProblem:
     f_seed: int                 # source of unknown (level l, vertex i,j,k) = uniform_hash(f_seed, l, (i,j,k))
     meta: dict = dataclasses.field(default_factory=dict)
     regions: list = dataclasses.field(default_factory=list)   # the same refinement as region descriptions
+    mark: object = None         # (level, cells (m, dim) int x-first) -> bool: the region meets the cell
     _flags: dict = None
 
     @property
@@ -284,10 +285,19 @@ def adaptive_balls(dim=3, base=3, level=5, n_balls=4, radius=0.2, seed=0, contra
     rng = np.random.default_rng(seed)
     centres = rng.uniform(0.0, 1.0, size=(n_balls, dim))
     g = rff_field(dim, seed + 1000, 1024, 0.1) if contrast_field else (lambda x: np.zeros(len(x)))
+    def mark(l, cells_xfirst):
+        n = 3 ** l
+        lo = np.atleast_2d(cells_xfirst) / n
+        hi = lo + 1.0 / n
+        f = np.zeros(len(lo), dtype=bool)
+        for c in np.atleast_2d(centres):
+            gap = np.maximum(np.maximum(lo - c, 0.0), np.maximum(c - hi, 0.0))
+            f |= np.sqrt((gap ** 2).sum(-1)) < radius
+        return f
     return AdaptiveProblem(name, dim, base, level, lambda: ball_flags(dim, base, level, centres, radius),
                            lambda x: np.exp(g(x)), seed + 2000,
                            {"centres": centres, "radius": radius, "seed": seed},
-                           ball_regions(centres, radius, level))
+                           ball_regions(centres, radius, level), mark)
 
 
 def adaptive_band(dim=3, base=3, level=6, seed=0, fraction=0.10, n_cubes=64, n_features=64,
@@ -303,6 +313,16 @@ def adaptive_band(dim=3, base=3, level=6, seed=0, fraction=0.10, n_cubes=64, n_f
     centres = rng.uniform(0.0, 1.0, size=(n_cubes, dim))
     sides = rng.uniform(0.05, 0.15, size=n_cubes)
 
+    def mark(l, cells_xfirst):
+        """Does the band meet these cells of level l (integer indices, x first)?"""
+        n = 3 ** l
+        lo = np.atleast_2d(cells_xfirst) / n
+        pts = []
+        for o in np.ndindex(*([3] * dim)):
+            pts.append(lo + (np.array(o) * 0.5) / n)
+        vals = np.stack([phi(pp) for pp in pts], 1)
+        return (np.abs(vals).min(1) < tau) | (vals.min(1) < 0) & (vals.max(1) > 0)
+
     def flags_fn():
         flags = {}
         exist = None
@@ -311,13 +331,7 @@ def adaptive_band(dim=3, base=3, level=6, seed=0, fraction=0.10, n_cubes=64, n_f
             cells = np.argwhere(np.ones((n,) * dim, bool) if exist is None else exist)  # numpy order
             f = np.zeros((n,) * dim, dtype=bool)
             if len(cells):
-                lo = cells[:, ::-1] / n
-                pts = []
-                for o in np.ndindex(*([3] * dim)):
-                    pts.append(lo + (np.array(o) * 0.5) / n)
-                vals = np.stack([phi(pp) for pp in pts], 1)
-                hit = (np.abs(vals).min(1) < tau) | (vals.min(1) < 0) & (vals.max(1) > 0)
-                f[tuple(cells.T)] = hit
+                f[tuple(cells.T)] = mark(l, cells[:, ::-1])
             flags[l] = f
             exist = np.repeat(np.repeat(np.repeat(f, 3, 0), 3, 1), 3, 2) if dim == 3 else \
                 np.repeat(np.repeat(f, 3, 0), 3, 1)
@@ -331,7 +345,7 @@ def adaptive_band(dim=3, base=3, level=6, seed=0, fraction=0.10, n_cubes=64, n_f
         return np.where(inside, 1e6, 1.0)
     return AdaptiveProblem(name, dim, base, level, flags_fn, eps_at, seed + 4000,
                            {"tau": tau, "seed": seed, "centres": centres, "sides": sides},
-                           band_region(phi, tau, level))
+                           band_region(phi, tau, level), mark)
 
 
 @dataclasses.dataclass

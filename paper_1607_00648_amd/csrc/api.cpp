@@ -68,6 +68,8 @@ struct LevelBuf {
   int8_t* cref = nullptr;
   int32_t* tiles = nullptr;
   int ntiles = 0;
+  int32_t* bricks = nullptr;  // 3D: bricks for the plane-marching sweep
+  int nbricks = 0;
   int32_t* rv = nullptr;  // refined vertices and cells (levels base..L-1), for the build
   int64_t nrv = 0;
   int32_t* rc = nullptr;
@@ -81,6 +83,8 @@ struct LevelBuf {
     t.tiles = tiles;
     t.vt = vt;
     t.n = ntiles;
+    t.bricks = bricks;
+    t.nb = nbricks;
     return t;
   }
 };
@@ -90,6 +94,7 @@ struct HostLevel {
   std::vector<int8_t> vt;         // vertex class per lattice slot
   std::vector<int8_t> cref;       // refined flag per cell slot
   std::vector<int32_t> tiles;     // active tiles (x tile, y tile, z plane)
+  std::vector<int32_t> bricks;    // 3D: bricks holding a leaf, refined or hanging vertex
   std::vector<int64_t> leaf;      // slots of the unknowns (x fastest)
   std::vector<int64_t> cells;     // slots of the leaf cells (x fastest)
   std::vector<int32_t> rverts;    // refined interior vertices (interior index, x fastest)
@@ -132,6 +137,7 @@ struct qmg_grid {
   double* dscal = nullptr;
   int* dcount = nullptr;
   int32_t* dtotal = nullptr;
+  int32_t* scan_tmp = nullptr;  // chunk sums of the block scans
   double* Ainv = nullptr;
   int64_t ainv_cap = 0;
   int nc = 0;
@@ -474,6 +480,33 @@ void linearise(qmg_grid_t* g) {
             H.tiles.push_back(tz);
           }
         }
+    // bricks of kBrickX x kBrickY slots and kBrickZ interior planes (plane
+    // 1 + kBrickZ bz on), listed z, y, x, that hold a vertex the sweep reads
+    // or writes (leaf, refined or hanging)
+    if (d == 3 && l > base) {
+      const int nbx = Lt.pitch / kBrickX, nby = (int)((n + 1 + kBrickY - 1) / kBrickY);
+      const int nbz = (int)((n - 1 + kBrickZ - 1) / kBrickZ);
+      for (int bz = 0; bz < nbz; ++bz)
+        for (int by = 0; by < nby; ++by)
+          for (int bx = 0; bx < nbx; ++bx) {
+            bool any = false;
+            const int64_t k0 = 1 + (int64_t)bz * kBrickZ, k1 = std::min<int64_t>(k0 + kBrickZ, n);
+            for (int64_t kk = k0; kk < k1 && !any; ++kk)
+              for (int64_t jj = (int64_t)by * kBrickY; jj < std::min<int64_t>((int64_t)by * kBrickY + kBrickY, n + 1) && !any; ++jj)
+                for (int64_t ii = (int64_t)bx * kBrickX; ii < std::min<int64_t>((int64_t)bx * kBrickX + kBrickX, n + 1); ++ii) {
+                  const int8_t t = H.vt[(size_t)(ii + jj * Lt.pitch + kk * Lt.plane)];
+                  if (t == VT_LEAF || t == VT_REFINED || t == VT_HANGING) {
+                    any = true;
+                    break;
+                  }
+                }
+            if (any) {
+              H.bricks.push_back(bx);
+              H.bricks.push_back(by);
+              H.bricks.push_back(bz);
+            }
+          }
+    }
     ref_prev.swap(ref);
     nprev = n;
   }
@@ -513,9 +546,11 @@ void layout(qmg_grid_t* g, Arena& a) {
       LevelBuf& B = g->lv[l];
       const HostLevel& H = g->hl[l];
       B.ntiles = (int)(H.tiles.size() / 3);
+      B.nbricks = (int)(H.bricks.size() / 3);
       B.vt = a.take<int8_t>(B.L.nslot);
       if (l < L) B.cref = a.take<int8_t>(B.L.nslot);
       B.tiles = a.take<int32_t>((int64_t)H.tiles.size());
+      B.bricks = a.take<int32_t>((int64_t)H.bricks.size());
       if (l < L) B.sv = a.take<char>(B.L.nslot * (int64_t)it);
       if (l < L) {
         B.nrv = (int64_t)H.rverts.size();
@@ -584,6 +619,7 @@ void layout(qmg_grid_t* g, Arena& a) {
   g->dscal = a.take<double>(8);
   g->dcount = a.take<int>(8);
   g->dtotal = a.take<int32_t>(2 * (L + 1));
+  g->scan_tmp = a.take<int32_t>(scan_scratch_ints(g->lv[L].L.nslot / kSeg));
   g->fimg = a.take<char>(kFusedImgBytes);
   g->dhist = a.take<double>(kHistCap);
   g->dctr = a.take<int>(64);
@@ -634,6 +670,8 @@ void upload_linearisation(qmg_grid_t* g) {
     if (B.cref) QMG_HIP(hipMemcpy(B.cref, H.cref.data(), H.cref.size(), hipMemcpyHostToDevice));
     if (!H.tiles.empty())
       QMG_HIP(hipMemcpy(B.tiles, H.tiles.data(), H.tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!H.bricks.empty())
+      QMG_HIP(hipMemcpy(B.bricks, H.bricks.data(), H.bricks.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (B.nrv > 0) QMG_HIP(hipMemcpy(B.rv, H.rverts.data(), B.nrv * sizeof(int32_t), hipMemcpyHostToDevice));
     if (B.nrc > 0) QMG_HIP(hipMemcpy(B.rc, H.rcells.data(), B.nrc * sizeof(int32_t), hipMemcpyHostToDevice));
     if (!H.leaf.empty())
@@ -980,17 +1018,15 @@ int enqueue_residual_norm(qmg_grid_t* g, bool record, bool partials_ready = fals
     Store geom;
     for (int l = g->lb; l <= g->Lmax; ++l) {
       LevelBuf& B = g->lv[l];
-      launch_ad_stencil<double, float>(B.ad(), 2, B.x64, B.b64, (float*)B.b, B.eps64, geom, 0.0,
-                                       g->partial + np, S(g));
-      np += B.ntiles;
+      np += launch_ad_stencil<double, float>(B.ad(), 2, B.x64, B.b64, (float*)B.b, B.eps64, geom, 0.0,
+                                             g->partial + np, S(g));
     }
   } else if (g->adaptive) {
     composite_state(g);
     for (int l = g->lb; l <= g->Lmax; ++l) {
       LevelBuf& B = g->lv[l];
-      launch_ad_stencil<double, double>(B.ad(), 2, (const double*)B.u, (const double*)B.b, (double*)B.r,
-                                        B.eps64, B.A, 0.0, g->partial + np, S(g));
-      np += B.ntiles;
+      np += launch_ad_stencil<double, double>(B.ad(), 2, (const double*)B.u, (const double*)B.b, (double*)B.r,
+                                              B.eps64, B.A, 0.0, g->partial + np, S(g));
     }
   } else if (g->mixed) {
     launch_residual_mixed(F.L, g->x64, g->bfin, (float*)F.b, F.eps64, part, &np, S(g));
@@ -1202,9 +1238,13 @@ void encode(qmg_grid_t* g, LevelBuf& B, const Lat& Lc, bool is_P, const double* 
   int64_t* off = is_P ? B.Poff : B.Aoff;
   const double eps_mf = fmt == BPA ? g->opts.eps_mf : 0.0;
   const int64_t unit = (int64_t)(is_P ? (1 << B.L.d) : ipow(3, B.L.d)) * kSeg;
-  launch_delta_flags(B.L, Lc, is_P, full, B.eps64, blk, S(g), eps_mf);
-  launch_scan_blocks(blk, B.L.nslot / kSeg, g->dtotal + slot, S(g), off, unit);
-  launch_delta_write(B.L, Lc, is_P, fmt, full, B.eps64, blk, pay, sc, S(g), off, eps_mf);
+  // adaptive levels above the base level: only their listed tiles hold
+  // operators the cycles read
+  const bool tl = g->adaptive && B.tiles != nullptr && B.L.n > g->lv[g->lb].L.n;
+  launch_delta_flags(B.L, Lc, is_P, full, B.eps64, blk, S(g), eps_mf, tl ? B.tiles : nullptr, tl ? B.ntiles : 0);
+  launch_scan_blocks(blk, B.L.nslot / kSeg, g->dtotal + slot, S(g), off, unit, g->scan_tmp);
+  launch_delta_write(B.L, Lc, is_P, fmt, full, B.eps64, blk, pay, sc, S(g), off, eps_mf, tl ? B.tiles : nullptr,
+                     tl ? B.ntiles : 0);
 }
 
 void invert_dense(std::vector<double>& M, int n) {
@@ -1355,8 +1395,11 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
     const double* Pw = nullptr;
     if (boxmg) {
       double* Pt = g->plain ? F.Pdense : g->tmpP;
-      launch_zero<double>(Pt, F.L.nslot * NC, s);
       const bool ad = g->adaptive && l > g->lb;
+      // adaptive levels: P lives on the listed tiles only (the encoder and
+      // the kernels read nothing else)
+      if (ad) launch_ad_zero<double>(F.ad(), Pt, s, NC);
+      else launch_zero<double>(Pt, F.L.nslot * NC, s);
       launch_boxmg(F.L, C.L, Afine, F.eps64, Pt, s, ad ? F.vt : nullptr, ad ? C.cref : nullptr,
                    ad ? C.rc : nullptr, ad ? C.nrc : 0);
       Pw = Pt;

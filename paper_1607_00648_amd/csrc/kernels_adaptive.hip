@@ -86,6 +86,161 @@ __global__ __launch_bounds__(256) void k_ad_stencil(Lat L, const int32_t* __rest
   }
 }
 
+// 3D adaptive levels: a workgroup of 64 x 8 threads owns one listed brick of
+// 64 x 8 slots and marches over its 16 interior planes.  Three planes of the
+// iterate (brick plus a halo of one vertex) and two planes of cell
+// coefficients ring through LDS, so each value comes from memory once per
+// brick instead of once per neighbour.  Every thread updates the
+// leaf or refined vertex at its position on each plane (same expressions and
+// order as k_ad_stencil) and copies a hanging value (mode 0) or zeroes it
+// (mode 2); other slots are not touched.  Workgroup w runs on XCD w % 8; the
+// brick list (ordered z, y, x) is cut into eight contiguous ranges, one per
+// XCD, so that neighbouring bricks share an L2.
+constexpr int BX = kBrickX, BY = kBrickY, BZ = kBrickZ;
+constexpr int BUW = BX + 2, BUH = BY + 2;  // iterate plane region: x0-1..x0+64, y0-1..y0+8
+constexpr int BEW = BX + 1, BEH = BY + 1;  // cell plane region: x0-1..x0+63, y0-1..y0+7
+
+template <typename T, typename TO, int SRC, int FMT, int MODE>
+__global__ __launch_bounds__(BX * BY) void k_ad_march(Lat L, const int32_t* __restrict__ bricks, int nb,
+                                                      const int8_t* __restrict__ vt, const T* __restrict__ u,
+                                                      const T* __restrict__ b, TO* __restrict__ out,
+                                                      const T* __restrict__ eps, Store A, T omega,
+                                                      double* __restrict__ partial) {
+  constexpr int NS = 27;
+  constexpr int NT = BX * BY;
+  static_assert(BUW * BUH <= 2 * NT && BEW * BEH <= 2 * NT, "two values per thread");
+  __shared__ T up[3][BUW * BUH];
+  __shared__ T ep[2][BEW * BEH];
+  __shared__ double red[NT / 64];
+  const int per = (nb + 7) / 8;
+  const int bi = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (bi >= nb) return;  // the whole workgroup
+  const int32_t* br = bricks + 3 * (int64_t)bi;
+  const int n = L.n;
+  const int x0 = br[0] * BX, y0 = br[1] * BY;
+  const int k0 = 1 + br[2] * BZ, k1 = min(k0 + BZ, n);  // interior planes [k0, k1)
+  const int tid = threadIdx.x;
+  const int lx = tid % BX, ly = tid / BX;
+  const int i = x0 + lx, j = y0 + ly;
+  const bool inplane = i >= 1 && i < n && j >= 1 && j < n;
+  auto fetch_u = [&](int k, T (&r)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + h * NT;
+      const int x = x0 - 1 + e % BUW, y = y0 - 1 + e / BUW;
+      r[h] = (e < BUW * BUH && x >= 0 && x <= n && y >= 0 && y <= n && k <= n)
+                 ? u[x + (int64_t)y * L.pitch + (int64_t)k * L.plane] : (T)0;
+    }
+  };
+  auto fetch_e = [&](int k, T (&r)[2]) {  // cells with low corner on plane k
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + h * NT;
+      const int x = x0 - 1 + e % BEW, y = y0 - 1 + e / BEW;
+      r[h] = (e < BEW * BEH && x >= 0 && x < n && y >= 0 && y < n && k < n)
+                 ? eps[x + (int64_t)y * L.pitch + (int64_t)k * L.plane] : (T)0;
+    }
+  };
+  auto put_u = [&](int k, const T (&r)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (tid + h * NT < BUW * BUH) up[k % 3][tid + h * NT] = r[h];
+  };
+  auto put_e = [&](int k, const T (&r)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (tid + h * NT < BEW * BEH) ep[k % 2][tid + h * NT] = r[h];
+  };
+  T ru[2] = {(T)0, (T)0}, re[2] = {(T)0, (T)0};
+  fetch_u(k0 - 1, ru);
+  put_u(k0 - 1, ru);
+  fetch_u(k0, ru);
+  put_u(k0, ru);
+  fetch_u(k0 + 1, ru);
+  if (SRC != SRC_PLAIN) {
+    fetch_e(k0 - 1, re);
+    put_e(k0 - 1, re);
+    fetch_e(k0, re);
+  }
+  const int64_t vij = i + (int64_t)j * L.pitch;
+  int8_t tnext = inplane ? vt[vij + (int64_t)k0 * L.plane] : (int8_t)VT_OUT;
+  T bnext = (tnext == VT_LEAF || tnext == VT_REFINED) ? b[vij + (int64_t)k0 * L.plane] : (T)0;
+  double sq = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const int8_t tv = tnext;
+    const T bv = bnext;
+    if (inplane && k + 1 < k1) {
+      tnext = vt[vij + (int64_t)(k + 1) * L.plane];
+      bnext = (tnext == VT_LEAF || tnext == VT_REFINED) ? b[vij + (int64_t)(k + 1) * L.plane] : (T)0;
+    }
+    put_u(k + 1, ru);
+    if (k + 1 < k1) fetch_u(k + 2, ru);
+    if (SRC != SRC_PLAIN) {
+      put_e(k, re);
+      if (k + 1 < k1) fetch_e(k + 1, re);
+    }
+    __syncthreads();
+    const int64_t v = vij + (int64_t)k * L.plane;
+    if (tv == VT_LEAF || tv == VT_REFINED) {
+      T a[NS];
+      if (SRC == SRC_PLAIN) {
+        const double* Ad = (const double*)A.dense;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) a[q] = (T)Ad[(int64_t)q * L.nslot + v];
+      } else {
+        T ce[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int sx = c & 1, sy = (c >> 1) & 1, sz = (c >> 2) & 1;
+          ce[c] = ep[(k - sz) % 2][(ly + 1 - sy) * BEW + (lx + 1 - sx)];
+        }
+        const T hs = (T)L.h;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          if (kref(3, ndiff_of<3>(q)) == 0.0) {
+            a[q] = (T)0;
+            continue;
+          }
+          T e = (T)0;
+#pragma unroll
+          for (int c = 0; c < 8; ++c)
+            if (cell_has<3>(c, q)) e += ce[c];
+          a[q] = hs * (T)kref(3, ndiff_of<3>(q)) * e;
+        }
+        if (SRC == SRC_HIER) add_delta<FMT, NS, T>(A, v, a);
+      }
+      T au = (T)0;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        if (SRC == SRC_GEOM && kref(3, ndiff_of<3>(q)) == 0.0) continue;
+        au += a[q] * up[(k + off_z(q) + 3) % 3][(ly + 1 + off_y(q)) * BUW + (lx + 1 + off_x(q))];
+      }
+      const T uc = up[k % 3][(ly + 1) * BUW + lx + 1];
+      if (MODE == 0) {
+        out[v] = (TO)(uc + omega * (bv - au) / a[NS / 2]);
+      } else {
+        const T res = bv - au;
+        out[v] = (TO)res;
+        if (tv == VT_LEAF) sq += (double)res * (double)res;
+      }
+    } else if (tv == VT_HANGING) {
+      out[v] = (MODE == 0) ? (TO)up[k % 3][(ly + 1) * BUW + lx + 1] : (TO)0;
+    }
+    __syncthreads();
+  }
+  if (partial != nullptr) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) sq += __shfl_xor(sq, m, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = sq;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < NT / 64; ++w) t += red[w];
+      partial[bi] = t;
+    }
+  }
+}
+
 // (P (uc - sc))(f) at fine vertex (i,j,k), sc nullable; P d-linear (GEOM),
 // stored deltas (HIER) or plain weights
 template <int D, typename T, int PSRC, int PFMT>
@@ -213,9 +368,11 @@ __global__ __launch_bounds__(256) void k_ad_copy(Lat L, const int32_t* __restric
 
 // zero on every slot of the listed tiles
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_ad_zero(Lat L, const int32_t* __restrict__ tiles, T* __restrict__ p) {
+__global__ __launch_bounds__(256) void k_ad_zero(Lat L, const int32_t* __restrict__ tiles, T* __restrict__ p,
+                                                 int narr) {
   const Slot s = tile_slot<D>(L, tiles);
-  if (s.valid) p[s.v] = (T)0;
+  if (!s.valid) return;
+  for (int a = 0; a < narr; ++a) p[(int64_t)a * L.nslot + s.v] = (T)0;
 }
 
 // x64 += e32 on the leaves; residual of the mixed loop at the leaves in FP64
@@ -294,6 +451,19 @@ inline dim3 full_grid(const Lat& L) {
 template <int D, typename T, typename TO, int SRC, int FMT>
 void ad_stencil_mode(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
                      const Store& A, T omega, double* partial, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (D == 3 && t.nb >= kMarchMinBricks && (mode == 0 || mode == 2)) {
+    const dim3 gm((unsigned)(8 * ((t.nb + 7) / 8))), bm(BX * BY);
+    if (mode == 0 && e0 != nullptr)
+      hipExtLaunchKernelGGL((k_ad_march<T, TO, SRC, FMT, 0>), gm, bm, 0, s, e0, e1, 0, t.L, t.bricks, t.nb, t.vt,
+                            u, b, out, eps, A, omega, partial);
+    else if (mode == 0)
+      hipLaunchKernelGGL((k_ad_march<T, TO, SRC, FMT, 0>), gm, bm, 0, s, t.L, t.bricks, t.nb, t.vt, u, b, out, eps,
+                         A, omega, partial);
+    else
+      hipLaunchKernelGGL((k_ad_march<T, TO, SRC, FMT, 2>), gm, bm, 0, s, t.L, t.bricks, t.nb, t.vt, u, b, out, eps,
+                         A, omega, partial);
+    return;
+  }
   const dim3 g = tiles_grid(t.n), bl(TX, TY, 1);
   if (e0 != nullptr && mode == 0) {  // per-dispatch timestamps of a timed sweep
     hipExtLaunchKernelGGL((k_ad_stencil<D, T, TO, SRC, FMT, 0>), g, bl, 0, s, e0, e1, 0, t.L, t.tiles, t.vt, u,
@@ -353,16 +523,18 @@ inline void check_ad_P(const Store& P) {
 }  // namespace
 
 template <typename T, typename TO>
-void launch_ad_stencil(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
-                       const Store& A, T omega, double* partial, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (t.n <= 0) return;
+int launch_ad_stencil(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
+                      const Store& A, T omega, double* partial, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (t.n <= 0) return 0;
   if (t.L.d == 2) ad_stencil_src<2, T, TO>(t, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
   else ad_stencil_src<3, T, TO>(t, mode, u, b, out, eps, A, omega, partial, s, e0, e1);
   QMG_HIP(hipGetLastError());
+  if (partial == nullptr) return 0;
+  return (t.L.d == 3 && t.nb >= kMarchMinBricks && (mode == 0 || mode == 2)) ? t.nb : t.n;
 }
-template void launch_ad_stencil<double, double>(const AdTiles&, int, const double*, const double*, double*, const double*, const Store&, double, double*, hipStream_t, hipEvent_t, hipEvent_t);
-template void launch_ad_stencil<float, float>(const AdTiles&, int, const float*, const float*, float*, const float*, const Store&, float, double*, hipStream_t, hipEvent_t, hipEvent_t);
-template void launch_ad_stencil<double, float>(const AdTiles&, int, const double*, const double*, float*, const double*, const Store&, double, double*, hipStream_t, hipEvent_t, hipEvent_t);
+template int launch_ad_stencil<double, double>(const AdTiles&, int, const double*, const double*, double*, const double*, const Store&, double, double*, hipStream_t, hipEvent_t, hipEvent_t);
+template int launch_ad_stencil<float, float>(const AdTiles&, int, const float*, const float*, float*, const float*, const Store&, float, double*, hipStream_t, hipEvent_t, hipEvent_t);
+template int launch_ad_stencil<double, float>(const AdTiles&, int, const double*, const double*, float*, const double*, const Store&, double, double*, hipStream_t, hipEvent_t, hipEvent_t);
 
 template <typename T>
 void launch_ad_hang(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const Store& P, hipStream_t s) {
@@ -441,11 +613,11 @@ void launch_ad_copy(const AdTiles& t, const T* src, T* dst, hipStream_t s) {
 }
 
 template <typename T>
-void launch_ad_zero(const AdTiles& t, T* p, hipStream_t s) {
+void launch_ad_zero(const AdTiles& t, T* p, hipStream_t s, int narr) {
   if (t.n <= 0) return;
   const dim3 g = tiles_grid(t.n), bl(TX, TY, 1);
-  if (t.L.d == 2) hipLaunchKernelGGL((k_ad_zero<2, T>), g, bl, 0, s, t.L, t.tiles, p);
-  else hipLaunchKernelGGL((k_ad_zero<3, T>), g, bl, 0, s, t.L, t.tiles, p);
+  if (t.L.d == 2) hipLaunchKernelGGL((k_ad_zero<2, T>), g, bl, 0, s, t.L, t.tiles, p, narr);
+  else hipLaunchKernelGGL((k_ad_zero<3, T>), g, bl, 0, s, t.L, t.tiles, p, narr);
   QMG_HIP(hipGetLastError());
 }
 
@@ -495,8 +667,8 @@ template void launch_ad_correct<double>(const AdTiles&, const Lat&, double*, con
 template void launch_ad_correct<float>(const AdTiles&, const Lat&, float*, const float*, const float*, const Store&, hipStream_t);
 template void launch_ad_copy<double>(const AdTiles&, const double*, double*, hipStream_t);
 template void launch_ad_copy<float>(const AdTiles&, const float*, float*, hipStream_t);
-template void launch_ad_zero<double>(const AdTiles&, double*, hipStream_t);
-template void launch_ad_zero<float>(const AdTiles&, float*, hipStream_t);
+template void launch_ad_zero<double>(const AdTiles&, double*, hipStream_t, int);
+template void launch_ad_zero<float>(const AdTiles&, float*, hipStream_t, int);
 template void launch_ad_scatter<double>(const int64_t*, int64_t, const double*, double, double*, hipStream_t);
 template void launch_ad_scatter<float>(const int64_t*, int64_t, const double*, double, float*, hipStream_t);
 template void launch_ad_gather<double>(const int64_t*, int64_t, const double*, double*, hipStream_t);

@@ -616,10 +616,12 @@ __device__ inline int load_delta(const Lat& L, const Lat& Lc, const double* __re
 template <int D, bool IS_P>
 __global__ __launch_bounds__(256) void k_delta_flags(Lat L, Lat Lc, const double* __restrict__ full,
                                                      const double* __restrict__ eps,
-                                                     int32_t* __restrict__ blk, double eps_mf) {
-  const int i = blockIdx.x * TX + threadIdx.x;
-  const int j = blockIdx.y * TY + threadIdx.y;
-  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+                                                     int32_t* __restrict__ blk, double eps_mf,
+                                                     const int32_t* __restrict__ tiles) {
+  const int32_t* tl = tiles ? tiles + 3 * (int64_t)blockIdx.x : nullptr;
+  const int i = (tl ? tl[0] : (int)blockIdx.x) * TX + threadIdx.x;
+  const int j = (tl ? tl[1] : (int)blockIdx.y) * TY + threadIdx.y;
+  const int kz = (D == 3) ? (tl ? tl[2] : (int)blockIdx.z) : 0;
   const bool inlat = j <= L.n && (D == 2 || kz <= L.n);
   const int64_t v = i + (int64_t)j * L.pitch + (int64_t)kz * L.plane;
   double dl[27], refmax;
@@ -665,17 +667,72 @@ __device__ inline int32_t block_excl_scan(int32_t f, int32_t* ws) {
 }
 
 // Exclusive scan of the block flags (widths) into compact ids (-1 for zero
-// blocks) and, with boff, of the widths into byte offsets; one workgroup
-// walks the array in chunks.
-__global__ __launch_bounds__(1024) void k_scan_blocks(int32_t* __restrict__ blk, int64_t nblk,
-                                                      int32_t* __restrict__ total,
-                                                      int64_t* __restrict__ boff, int64_t unit) {
+// blocks) and, with boff, of the widths into byte offsets, in three passes:
+// each workgroup sums its chunk of kScanChunk blocks, one workgroup scans the
+// chunk sums, and each workgroup rescans its chunk from its base.  Integer
+// sums, so the result does not depend on the split.
+constexpr int kScanPer = 8;
+constexpr int kScanChunk = 1024 * kScanPer;
+
+__global__ __launch_bounds__(1024) void k_scan_sum(const int32_t* __restrict__ blk, int64_t nblk,
+                                                   int32_t* __restrict__ csum) {
+  __shared__ int32_t wsum[16], wsw[16];
+  const int64_t c0 = (int64_t)blockIdx.x * kScanChunk;
+  int32_t f = 0, w = 0;
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    const int64_t idx = c0 + (int64_t)q * 1024 + threadIdx.x;
+    const int32_t v = idx < nblk ? blk[idx] : 0;
+    f += v > 0 ? 1 : 0;
+    w += v;
+  }
+  const int32_t ef = block_excl_scan(f, wsum);
+  const int32_t ew = block_excl_scan(w, wsw);
+  if (threadIdx.x == 1023) {
+    csum[2 * blockIdx.x] = ef + f;
+    csum[2 * blockIdx.x + 1] = ew + w;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_chunks(int32_t* __restrict__ csum, int64_t nchunk,
+                                                      int32_t* __restrict__ total) {
   __shared__ int32_t wsum[16], wsw[16];
   __shared__ int32_t base_s, basew_s;
   if (threadIdx.x == 0) base_s = basew_s = 0;
   __syncthreads();
-  for (int64_t c0 = 0; c0 < nblk; c0 += 1024) {
+  for (int64_t c0 = 0; c0 < nchunk; c0 += 1024) {
     const int64_t idx = c0 + threadIdx.x;
+    const int32_t f = idx < nchunk ? csum[2 * idx] : 0;
+    const int32_t w = idx < nchunk ? csum[2 * idx + 1] : 0;
+    const int32_t ef = base_s + block_excl_scan(f, wsum);
+    const int32_t ew = basew_s + block_excl_scan(w, wsw);
+    if (idx < nchunk) {
+      csum[2 * idx] = ef;
+      csum[2 * idx + 1] = ew;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) {
+      base_s = ef + f;
+      basew_s = ew + w;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = base_s;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_write(int32_t* __restrict__ blk, int64_t nblk,
+                                                     const int32_t* __restrict__ csum,
+                                                     int64_t* __restrict__ boff, int64_t unit) {
+  __shared__ int32_t wsum[16], wsw[16];
+  __shared__ int32_t base_s, basew_s;
+  if (threadIdx.x == 0) {
+    base_s = csum[2 * blockIdx.x];
+    basew_s = csum[2 * blockIdx.x + 1];
+  }
+  __syncthreads();
+  const int64_t c0 = (int64_t)blockIdx.x * kScanChunk;
+  for (int q = 0; q < kScanPer; ++q) {
+    const int64_t idx = c0 + (int64_t)q * 1024 + threadIdx.x;
     const int32_t w = (idx < nblk) ? blk[idx] : 0;
     const int32_t f = w > 0 ? 1 : 0;
     const int32_t excl = base_s + block_excl_scan(f, wsum);
@@ -689,7 +746,6 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int32_t* __restrict__ blk,
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *total = base_s;
 }
 
 __device__ inline uint16_t bf16_rne(float x) {
@@ -704,11 +760,13 @@ __global__ __launch_bounds__(256) void k_delta_write(Lat L, Lat Lc, const double
                                                      const int32_t* __restrict__ blk,
                                                      void* __restrict__ payload,
                                                      int8_t* __restrict__ scale,
-                                                     const int64_t* __restrict__ boff, double eps_mf) {
+                                                     const int64_t* __restrict__ boff, double eps_mf,
+                                                     const int32_t* __restrict__ tiles) {
   constexpr int NE = IS_P ? Dim<D>::NC : Dim<D>::NS;
-  const int i = blockIdx.x * TX + threadIdx.x;
-  const int j = blockIdx.y * TY + threadIdx.y;
-  const int kz = (D == 3) ? (int)blockIdx.z : 0;
+  const int32_t* tl = tiles ? tiles + 3 * (int64_t)blockIdx.x : nullptr;
+  const int i = (tl ? tl[0] : (int)blockIdx.x) * TX + threadIdx.x;
+  const int j = (tl ? tl[1] : (int)blockIdx.y) * TY + threadIdx.y;
+  const int kz = (D == 3) ? (tl ? tl[2] : (int)blockIdx.z) : 0;
   if (j > L.n || (D == 3 && kz > L.n)) return;
   const int64_t v = i + (int64_t)j * L.pitch + (int64_t)kz * L.plane;
   const int32_t cb = blk[v / kSeg];
@@ -858,31 +916,41 @@ void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s)
 }
 
 void launch_delta_flags(const Lat& L, const Lat& Lc, bool is_P, const double* full, const double* eps,
-                        int32_t* blk, hipStream_t s, double eps_mf) {
-  const dim3 g = tile_grid(L), bl(TX, TY, 1);
+                        int32_t* blk, hipStream_t s, double eps_mf, const int32_t* tiles, int ntiles) {
+  const dim3 g = tiles ? dim3((unsigned)ntiles) : tile_grid(L), bl(TX, TY, 1);
+  if (tiles) launch_zero<int32_t>(blk, L.nslot / kSeg, s);  // blocks of unlisted tiles: zero
+  if (tiles && ntiles == 0) return;
   if (L.d == 2) {
-    if (is_P) hipLaunchKernelGGL((k_delta_flags<2, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf);
-    else hipLaunchKernelGGL((k_delta_flags<2, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf);
+    if (is_P) hipLaunchKernelGGL((k_delta_flags<2, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles);
+    else hipLaunchKernelGGL((k_delta_flags<2, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles);
   } else {
-    if (is_P) hipLaunchKernelGGL((k_delta_flags<3, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf);
-    else hipLaunchKernelGGL((k_delta_flags<3, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf);
+    if (is_P) hipLaunchKernelGGL((k_delta_flags<3, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles);
+    else hipLaunchKernelGGL((k_delta_flags<3, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles);
   }
   QMG_HIP(hipGetLastError());
 }
 
+int64_t scan_scratch_ints(int64_t nblk) { return 2 * ((nblk + kScanChunk - 1) / kScanChunk) + 2; }
+
 void launch_scan_blocks(int32_t* blk, int64_t nblk, int32_t* total, hipStream_t s, int64_t* boff,
-                        int64_t unit) {
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, blk, nblk, total, boff, unit);
+                        int64_t unit, int32_t* csum) {
+  const int64_t nchunk = (nblk + kScanChunk - 1) / kScanChunk;
+  if (nchunk > 0) hipLaunchKernelGGL(k_scan_sum, dim3((unsigned)nchunk), dim3(1024), 0, s, blk, nblk, csum);
+  hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, csum, nchunk, total);
+  if (nchunk > 0)
+    hipLaunchKernelGGL(k_scan_write, dim3((unsigned)nchunk), dim3(1024), 0, s, blk, nblk, csum, boff, unit);
   QMG_HIP(hipGetLastError());
 }
 
 void launch_delta_write(const Lat& L, const Lat& Lc, bool is_P, int fmt, const double* full,
                         const double* eps, const int32_t* blk, void* payload, int8_t* scale,
-                        hipStream_t s, const int64_t* boff, double eps_mf) {
-  const dim3 g = tile_grid(L), bl(TX, TY, 1);
+                        hipStream_t s, const int64_t* boff, double eps_mf, const int32_t* tiles, int ntiles) {
+  const dim3 g = tiles ? dim3((unsigned)ntiles) : tile_grid(L), bl(TX, TY, 1);
   if (fmt == BPA && (!boff || !(eps_mf > 0.0))) throw std::runtime_error("BPA store without offsets or eps_mf");
+  if (tiles && ntiles == 0) return;
 #define QMG_DW(DV, PV, FV) \
-  hipLaunchKernelGGL((k_delta_write<DV, PV, FV>), g, bl, 0, s, L, Lc, full, eps, blk, payload, scale, boff, eps_mf)
+  hipLaunchKernelGGL((k_delta_write<DV, PV, FV>), g, bl, 0, s, L, Lc, full, eps, blk, payload, scale, boff, eps_mf, \
+                     tiles)
 #define QMG_DW_F(DV, PV)                  \
   do {                                    \
     if (fmt == F64) QMG_DW(DV, PV, F64);  \

@@ -220,13 +220,19 @@ void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s)
 // per-vertex bpa, 0 when every vertex codes to zero; the scan then also writes
 // boff (byte offset and width per compact block; `unit` = nent * 64 bytes per
 // width step).
+// tiles (nullable): only the listed 64 x 4 tiles of an adaptive level are
+// encoded; the blocks of the others are flagged zero.
 void launch_delta_flags(const Lat& L, const Lat& Lc, bool is_P, const double* full,
-                        const double* eps, int32_t* blk, hipStream_t s, double eps_mf = 0.0);
-void launch_scan_blocks(int32_t* blk, int64_t nblk, int32_t* total, hipStream_t s,
-                        int64_t* boff = nullptr, int64_t unit = 0);
+                        const double* eps, int32_t* blk, hipStream_t s, double eps_mf = 0.0,
+                        const int32_t* tiles = nullptr, int ntiles = 0);
+// csum: device scratch of scan_scratch_ints(nblk) ints (chunk sums).
+void launch_scan_blocks(int32_t* blk, int64_t nblk, int32_t* total, hipStream_t s, int64_t* boff,
+                        int64_t unit, int32_t* csum);
+int64_t scan_scratch_ints(int64_t nblk);
 void launch_delta_write(const Lat& L, const Lat& Lc, bool is_P, int fmt, const double* full,
                         const double* eps, const int32_t* blk, void* payload, int8_t* scale,
-                        hipStream_t s, const int64_t* boff = nullptr, double eps_mf = 0.0);
+                        hipStream_t s, const int64_t* boff = nullptr, double eps_mf = 0.0,
+                        const int32_t* tiles = nullptr, int ntiles = 0);
 
 // Coarse part of the V-cycle in one workgroup with levels lc..lf held in LDS
 // (lf starting from zero after its right-hand side was restricted into b of
@@ -296,20 +302,31 @@ int pass2d_partials(const Lat& L);
 enum VertexClass : int8_t { VT_OUT = 0, VT_LEAF = 1, VT_REFINED = 2, VT_HANGING = 3 };
 // Active 64 x 4 (x, y) tiles of one level (3 ints per tile: x tile, y tile,
 // z plane) and the vertex class of every slot of the level.
+// On 3D adaptive levels also the 64 x 8 x 16 bricks (x brick, y brick, chunk
+// of 16 interior planes) that hold a leaf, refined or hanging vertex, for
+// the plane-marching sweep.
 struct AdTiles {
   Lat L;
   const int32_t* tiles = nullptr;
   const int8_t* vt = nullptr;
   int n = 0;
+  const int32_t* bricks = nullptr;
+  int nb = 0;
 };
-// mode 0: Jacobi sweep of leaf and refined vertices (others copied), 1: the
-// same from zero, 2: residual (zero off that set; partial: per-tile sums of
-// squares over the leaves).  e0/e1 (mode 0 only, nullable): per-dispatch
-// timestamps of the launch.
+constexpr int kBrickX = 64, kBrickY = 8, kBrickZ = 16;
+constexpr int kMarchMinBricks = 256;  // smaller levels keep one workgroup per tile plane
+// mode 0: Jacobi sweep of leaf and refined vertices, 1: the same from zero,
+// 2: residual (zero at hanging vertices; partial: per-workgroup sums of
+// squares over the leaves).  Hanging values travel with the iterate (mode 0
+// copies them).  Levels with at least kMarchMinBricks bricks take the
+// brick-marching kernel for modes 0 and 2 (slots outside the active set and
+// its hanging vertices are then not written); others one workgroup per
+// listed tile plane.  Returns the number of partials written (0 when
+// partial is null).  e0/e1 (mode 0 only, nullable): per-dispatch timestamps.
 template <typename T, typename TO>
-void launch_ad_stencil(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
-                       const Store& A, T omega, double* partial, hipStream_t s, hipEvent_t e0 = nullptr,
-                       hipEvent_t e1 = nullptr);
+int launch_ad_stencil(const AdTiles& t, int mode, const T* u, const T* b, TO* out, const T* eps,
+                      const Store& A, T omega, double* partial, hipStream_t s, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr);
 // P: the fine level's prolongation store (d-linear, FP64 deltas, or plain)
 template <typename T>
 void launch_ad_hang(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const Store& P, hipStream_t s);
@@ -331,7 +348,7 @@ void launch_ad_virtual_eps(const Lat& Lf, const Lat& Lc, const int8_t* crefc, co
 template <typename T>
 void launch_ad_copy(const AdTiles& t, const T* src, T* dst, hipStream_t s);
 template <typename T>
-void launch_ad_zero(const AdTiles& t, T* p, hipStream_t s);
+void launch_ad_zero(const AdTiles& t, T* p, hipStream_t s, int narr = 1);  // narr lattice arrays back to back
 void launch_ad_axpy(const AdTiles& t, double* x, const float* e, hipStream_t s);
 void launch_ad_coarsen_eps(const Lat& Lf, const Lat& Lc, const int8_t* cref, const double* ef, double* ec,
                            hipStream_t s);

@@ -188,6 +188,36 @@ __device__ inline void box_group(const BoxFetch<D>& F, int Vx, int Vy, int Vz, i
     const int fx = 3 * Vx + sx * y[0], fy = 3 * Vy + sy * y[1], fz = 3 * Vz + sz * y[2];
     const int64_t v = fx + (int64_t)fy * F.L.pitch + (int64_t)fz * F.L.plane;
     const RowSrc<D> row(F, v);  // the member's row, fetched once
+    // The row in the reference frame: the cell coefficients of a rediscretised
+    // row mirrored (axis a flipped: cell bit a flipped), and per axis whether
+    // the true neighbour one step back / ahead in the reference frame is an
+    // interior vertex (entries towards Dirichlet vertices are dropped).  With
+    // the frame fixed, every entry below is a fixed sum of these values, so
+    // the unrolled code stays small; a stored row is read at the mirrored
+    // entry.
+    double cr[Dim<D>::NC];
+#pragma unroll
+    for (int c = 0; c < Dim<D>::NC; ++c) cr[c] = row.ce[c];
+    if (sx < 0) {
+#pragma unroll
+      for (int c = 0; c < Dim<D>::NC; c += 2) { const double t = cr[c]; cr[c] = cr[c + 1]; cr[c + 1] = t; }
+    }
+    if (sy < 0) {
+#pragma unroll
+      for (int c = 0; c < Dim<D>::NC; ++c)
+        if (!(c & 2)) { const double t = cr[c]; cr[c] = cr[c + 2]; cr[c + 2] = t; }
+    }
+    if (D == 3 && sz < 0) {
+#pragma unroll
+      for (int c = 0; c < Dim<D>::NC; ++c)
+        if (!(c & 4)) { const double t = cr[c]; cr[c] = cr[c + 4]; cr[c + 4] = t; }
+    }
+    const int n = F.L.n;
+    const bool okm[3] = {fx - sx >= 1 && fx - sx <= n - 1, fy - sy >= 1 && fy - sy <= n - 1,
+                         D == 2 || (fz - sz >= 1 && fz - sz <= n - 1)};
+    const bool okp[3] = {fx + sx >= 1 && fx + sx <= n - 1, fy + sy >= 1 && fy + sy <= n - 1,
+                         D == 2 || (fz + sz >= 1 && fz + sz <= n - 1)};
+    const double hs = (D == 3) ? F.L.h : 1.0;
 #pragma unroll
     for (int k = 0; k < Dim<D>::NS; ++k) {
       const int o[3] = {off_x(k), off_y(k), D == 3 ? off_z(k) : 0};
@@ -201,11 +231,24 @@ __device__ inline void box_group(const BoxFetch<D>& F, int Vx, int Vy, int Vz, i
         if (nz != (((S >> ax) & 1) != 0)) ingroup = false;
       }
       if (far) continue;
-      const int ks = (sx * o[0] + 1) + 3 * (sy * o[1] + 1) + (D == 3 ? 9 * (sz * o[2] + 1) : 0);
       double a = 0.0;
-      if (row.mode == 1 || (row.mode == 2 && interior(F.L, fx + off_x(ks), fy + off_y(ks),
-                                                        fz + (D == 3 ? off_z(ks) : 0))))
-        a = row.entry(F, v, ks);
+      if (row.mode == 2) {
+        const double kw = kref(D, ndiff_of<D>(k));
+        if (kw != 0.0) {
+          bool ok = true;
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax)
+            if (o[ax] != 0) ok = ok && (o[ax] < 0 ? okm[ax] : okp[ax]);
+          double e = 0.0;
+#pragma unroll
+          for (int c = 0; c < Dim<D>::NC; ++c)
+            if (cell_has<D>(c, k)) e += cr[c];
+          a = ok ? hs * kw * e : 0.0;
+        }
+      } else if (row.mode == 1) {
+        const int ks = (sx * o[0] + 1) + 3 * (sy * o[1] + 1) + (D == 3 ? 9 * (sz * o[2] + 1) : 0);
+        a = F.A[(int64_t)ks * F.L.nslot + v];
+      }
       if (ingroup) {
         int col = 0, bit = 0;
 #pragma unroll

@@ -390,6 +390,9 @@ typedef struct {
   int64_t submitted, completed, failed, active, queued;
   size_t hbm_budget, hbm_in_use, hbm_peak;
   int max_slots;
+  int64_t deferred;  /* requests that had arrived but were not admitted at
+                        once: no memory for them, or every slot busy (each
+                        counted once)                                       */
 } qmg_server_stats_t;
 
 /* Starts a server on the current HIP device (1 <= max_slots <= 256).  The

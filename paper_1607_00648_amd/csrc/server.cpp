@@ -52,6 +52,7 @@ struct Req {
   size_t bytes = 0;
   double t_submit = 0, t_arrive = 0, t_admit = 0, t_done = 0;
   int state = 0;  // 0 queued, 1 active, 2 done
+  bool deferred = false;  // arrived and found no slot or memory at least once
   int status = QMG_OK;
   std::string err;
   qmg_grid_t* g = nullptr;
@@ -82,7 +83,7 @@ struct qmg_server {
   std::vector<Req*> active;
   std::unordered_map<uint64_t, Req*> all;
   uint64_t next_id = 1;
-  int64_t submitted = 0, completed = 0, failed = 0;
+  int64_t submitted = 0, completed = 0, failed = 0, deferred = 0;
   bool stop = false;
   std::vector<std::thread> workers;
   std::string err;
@@ -222,9 +223,21 @@ void loop(qmg_server* s, int w) {
           admitted.push_back(r);
           it = s->queue.erase(it);
         } else {
+          if (r->t_arrive <= tnow && !r->deferred) {  // arrived, but no memory for it
+            r->deferred = true;
+            ++s->deferred;
+          }
           ++it;
         }
       }
+      size_t free_slots = 0;
+      for (const std::vector<int>& f : s->slot_free) free_slots += f.size();
+      if (free_slots == 0)  // arrived, but every slot is busy
+        for (Req* r : s->queue)
+          if (!r->deferred && r->t_arrive <= tnow) {
+            r->deferred = true;
+            ++s->deferred;
+          }
       for (Req* r : s->active)
         if (r->slot % s->nworkers == w) running.push_back(r);
     }
@@ -427,6 +440,7 @@ int qmg_server_stats(qmg_server_t* s, qmg_server_stats_t* st) {
     st->failed = s->failed;
     st->active = (int64_t)s->active.size();
     st->queued = (int64_t)s->queue.size();
+    st->deferred = s->deferred;
     st->hbm_budget = s->budget;
     st->hbm_in_use = s->in_use;
     st->hbm_peak = s->peak;

@@ -66,7 +66,8 @@ class SolveReport(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("active", C.c_int64), ("queued", C.c_int64), ("hbm_budget", C.c_size_t),
-                ("hbm_in_use", C.c_size_t), ("hbm_peak", C.c_size_t), ("max_slots", C.c_int)]
+                ("hbm_in_use", C.c_size_t), ("hbm_peak", C.c_size_t), ("max_slots", C.c_int),
+                ("deferred", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

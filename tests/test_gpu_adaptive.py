@@ -433,6 +433,20 @@ def test_boxmg_balls_full_size_mixed():
     rel = np.linalg.norm(sol["bf16"] - sol["hier64"]) / np.linalg.norm(sol["hier64"])
     print(f"[balls3d boxmg] bf16 vs fp64 solution: {rel:.2e}")
     assert rel <= 1e-5
+    # the oracle recomputes the composite residual of each solution at sampled
+    # unknowns, row by row; rows that need a hanging value (a BoxMG
+    # interpolant) are skipped, the others do not depend on P
+    from gpu_util import sampled_local_rows
+    levels = np.concatenate([np.full(int((G.vtype[l] == AD.LEAF).sum()), l)
+                             for l in range(G.base, G.L + 1)])
+    nb = np.linalg.norm(f * (3.0 ** -levels.astype(float)) ** 3)
+    xyz = G.unknown_coords()
+    for store, u in sol.items():
+        pick, rows, scale = sampled_local_rows(P, xyz, levels, u, 300, seed=21)
+        ok = ~np.isnan(rows)
+        assert ok.sum() >= 100, ok.sum()
+        print(f"[balls3d boxmg {store}] {ok.sum()} rows, max |r| / ||b|| = {np.abs(rows[ok]).max() / nb:.2e}")
+        assert np.abs(rows[ok]).max() <= 1e-8 * nb * (1 + 1e-6)
 
 
 def test_band_midsize_boxmg_cycles_match_oracle():
@@ -456,6 +470,38 @@ def test_band_midsize_boxmg_cycles_match_oracle():
     u = g.solution()
     assert np.abs(u - u_o).max() <= 1e-6 * np.abs(u_o).max()
     g.close()
+
+
+def test_band_full_size_grid_from_region_and_residual_rows():
+    """The 3D band workload at full size (base 3, level 6, 4.5e7 unknowns): the
+    grid is built from the band region inside the library; after two BoxMG
+    FAS cycles in FP64 the library's composite residual equals, row by row,
+    the oracle's rows assembled at sampled unknowns from the same iterate
+    (rows that need a hanging value are left to the mid-size tests); every
+    sampled unknown is a leaf vertex of the oracle's spacetree."""
+    qmg = require_gpu()
+    from gpu_util import band_inputs_on_device, sampled_local_rows
+    announce("adaptive band 3D base3 L6 full size, hier64, two cycles")
+    P = W.adaptive_band(dim=3, base=3, level=6)
+    g = qmg.Grid(3, 6, qmg.make_opts("boxmg", "hier64", check_definite=False, graphs=False), base_level=3,
+                 regions=P.regions)
+    assert g.n_unknowns > 4e7
+    eps, f, xyz, lev = band_inputs_on_device(g, P)
+    g.set_coefficients(eps, f)
+    assert g.build()["coarsest_level_used"] == 1
+    rr = g.vcycle(2)
+    assert np.all(np.isfinite(rr))
+    u = g.solution()
+    r = g.residual()
+    g.close()
+    fh = f.cpu().numpy()
+    assert abs(np.linalg.norm(r) / np.linalg.norm(fh * (3.0 ** -lev.astype(float)) ** 3) - rr[-1]) <= 1e-9 * rr[-1]
+    pick, rows, scale = sampled_local_rows(P, xyz, lev, u, 200, seed=5)
+    ok = ~np.isnan(rows)
+    assert ok.sum() >= 100, ok.sum()
+    err = np.abs(rows[ok] - r[pick][ok]) / scale[ok]
+    print(f"[band3d L6] {ok.sum()} rows, max |r_gpu - r_oracle| / sum|K||u| = {err.max():.2e}")
+    assert err.max() <= 1e-13
 
 
 def test_stagnation_raise_to_base_matches_oracle():

@@ -204,7 +204,27 @@ typedef struct {
                           coarse vertex sums the 3^d fine vertices nearest to
                           it (unit weights).  Galerkin or BoxMG transfers,
                           multiplicative cycles, regular grids              */
+  int coarse_solver;   /* QMG_COARSE_DIRECT (default): the coarsest level is
+                          solved exactly (a dense inverse formed on the
+                          device at build) when it has at most 1024
+                          unknowns, otherwise by mu_pre + mu_post sweeps;
+                          QMG_COARSE_SWEEPS: always the sweeps (the paper's
+                          inexact coarse solve)                              */
+  double eps_zero;     /* delta store: a 64-vertex block holds no payload when
+                          every delta of its vertices is at most eps_zero
+                          times the largest entry of the vertex's geometric
+                          row (stencils) or d-linear weight (prolongation);
+                          0 selects the default 2^-40; at most 1e-2          */
+  int iterate;         /* QMG_IT_STORE (default): FP64 iterates for the
+                          plain, HIER_FP64 and bpa stores, FP32 for the
+                          reduced ones; QMG_IT_FP64 / QMG_IT_FP32 ask for one
+                          (QMG_IT_FP32 also runs HIER_FP64 deltas inside the
+                          FP64 defect correction); a combination the stores
+                          do not offer is QMG_EINVAL                         */
 } qmg_solver_opts;
+
+enum { QMG_COARSE_DIRECT = 0, QMG_COARSE_SWEEPS = 1 };
+enum { QMG_IT_STORE = 0, QMG_IT_FP64 = 1, QMG_IT_FP32 = 2 };
 
 typedef struct {
   int cycles;               /* V-cycles run (inner cycles for FP32 iterates)  */

@@ -68,7 +68,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .fem import (geometric_stencil, offsets, shifted, csr_to_stencil, stencil_to_csr,
-                  interior_mask, corners, corner_index, element_matrix)
+                  interior_mask, corners, corner_index, element_matrix, apply_dirichlet)
 from .transfer import dlinear_P, boxmg_P, boxmg_reference_stepwise, _gather_reference, _points
 from .fem import _unknown_numbering
 from .galerkin import rap, definiteness_violations
@@ -318,6 +318,51 @@ def hanging_stencils(G: AdaptiveGrid, eps):
     return out
 
 
+def hanging_stencils_parents(G: AdaptiveGrid, eps):
+    """Rows of the hanging vertices of levels base+1..L for the collapsed BoxMG
+    systems read as the paper's d-linear interpolation of the parent
+    stencils: the rediscretised level-(l-1) rows of the coarse vertices
+    spanning the hanging vertex's coarse face or edge, weighted by its
+    d-linear weights.  A Dirichlet parent has no stencil; the weights of the
+    interior parents are renormalised to sum one.  The parents' rows are
+    taken whole (entries towards Dirichlet vertices kept) and the entries of
+    the interpolated row that point at Dirichlet vertices from the hanging
+    vertex are dropped, as for every row.  A parent that is itself hanging
+    has no stencil of its own either; parents' rows are rediscretised from
+    the virtual coefficients (a missing cell takes the leaf cell covering
+    it), which for a hanging parent is the interpolation of its own parents'
+    rows when the coefficient is constant.  (A row's scale does not change
+    the collapsed systems, each row being one equation.)"""
+    d = G.d
+    ev = virtual_eps(G, eps)
+    out = {}
+    for l in range(G.base + 1, G.L + 1):
+        n = 3 ** l
+        nc = n // 3
+        Sc = geometric_stencil(ev[l - 1], d, l - 1, dirichlet=False)
+        grids = np.meshgrid(*([np.arange(n + 1)] * d), indexing="ij")      # axes z,y,x
+        acc = np.zeros((3 ** d,) + (n + 1,) * d)
+        wsum = np.zeros((n + 1,) * d)
+        for kap in itertools.product((0, 1), repeat=d):                    # NumPy order
+            w = np.ones((n + 1,) * d)
+            par = []
+            for ax in range(d):
+                q = grids[ax] // 3
+                r = grids[ax] - 3 * q
+                w = w * (np.where(kap[ax] == 0, 1.0 - r / 3.0, r / 3.0))
+                par.append(np.minimum(q + kap[ax], nc))
+            inner = np.ones((n + 1,) * d, bool)
+            for ax in range(d):
+                inner &= (par[ax] >= 1) & (par[ax] <= nc - 1)
+            w = np.where(inner, w, 0.0)
+            acc += w[None] * Sc[(slice(None),) + tuple(par)]
+            wsum += w
+        hv = G.vtype[l] == HANGING
+        rows = apply_dirichlet(acc / np.where(wsum > 0, wsum, 1.0)[None], d, l)
+        out[l] = np.where(hv[None] & (wsum > 0)[None], rows, 0.0)
+    return out
+
+
 def boxmg_adaptive_P(G: AdaptiveGrid, S_full, l, check=True):
     """BoxMG prolongation from level l-1 to level l computed on the refined
     coarse cells only (Sect. 3.4 per patch and corner), from the level's
@@ -369,7 +414,8 @@ def boxmg_adaptive_P(G: AdaptiveGrid, S_full, l, check=True):
 
 
 def build_adaptive(G: AdaptiveGrid, eps_leaf, transfer="galerkin", omega=0.6, mu_pre=2, mu_post=2,
-                   lc=1, check_definite=False, direct_max=S.COARSE_DIRECT_MAX):
+                   lc=1, check_definite=False, direct_max=S.COARSE_DIRECT_MAX, hanging_rows="covering",
+                   multiscale=False):
     """Operators of every level: rediscretised rows for unrefined vertices,
     Galerkin rows P^T A P (d-linear or BoxMG P) or rediscretised rows for
     refined ones; prolongations ``H.P[l]`` (also used for the hanging values);
@@ -380,7 +426,13 @@ def build_adaptive(G: AdaptiveGrid, eps_leaf, transfer="galerkin", omega=0.6, mu
     non-positive diagonal or without diagonal dominance); the first level
     whose coarser operator fails becomes the coarsest level, which is at most
     the base level (the levels above it hold unknowns).  ``direct_max``: the
-    largest coarsest level solved exactly (see ``solver.factor_coarse``)."""
+    largest coarsest level solved exactly (see ``solver.factor_coarse``).
+    ``hanging_rows`` (BoxMG): "covering", the rows of hanging vertices
+    rediscretised from the leaf cells covering the missing cells (this
+    build's reading), or "parents", the paper's d-linear interpolation of the
+    parent stencils (``hanging_stencils_parents``).  ``multiscale``: the FAS
+    cycle also smooths the leaves of the coarser levels while a finer level
+    is smoothed (see ``fas_cycle``)."""
     if transfer not in ("geometric", "galerkin", "boxmg"):
         raise ValueError(transfer)
     d = G.d
@@ -392,7 +444,12 @@ def build_adaptive(G: AdaptiveGrid, eps_leaf, transfer="galerkin", omega=0.6, mu
     H.transfer = transfer
     geo = {l: geometric_stencil(eps[l], d, l) for l in range(lc, G.L + 1)}
     act = {l: np.isin(G.vtype[l], (LEAF, REFINED)) for l in range(lc, G.L + 1)}
-    Hs = hanging_stencils(G, eps) if transfer == "boxmg" else {}
+    if hanging_rows not in ("covering", "parents"):
+        raise ValueError(hanging_rows)
+    H.multiscale = bool(multiscale)
+    Hs = {}
+    if transfer == "boxmg":
+        Hs = hanging_stencils(G, eps) if hanging_rows == "covering" else hanging_stencils_parents(G, eps)
     H.S = {G.L: geo[G.L] * act[G.L][None]}
     H.P = {}
     lc_used = lc
@@ -524,10 +581,35 @@ def _jacobi_masked(H, l, u, b):
     return np.where(act, new, u)
 
 
+def _smooth_multiscale(H, l, u, b):
+    """One smoothing step of Alg. 1 with level l active: the refined vertices
+    of the coarser levels first take their finer copies (injection), then
+    one damped Jacobi step updates the non-hanging vertices of level l and,
+    from the same old values, the leaves of every coarser level (base..l-1),
+    which see the finer solution through their refined neighbours."""
+    d, G = H.d, H.G
+    for m in range(l, H.base, -1):
+        inject(H, u, m)
+    c = (3 ** d) // 2
+    new = {}
+    for m in range(H.base, l):
+        lf = G.vtype[m] == LEAF
+        Sm = H.S[m]
+        diag = np.where(lf, Sm[c], 1.0)
+        new[m] = np.where(lf, u[m] + H.omega * (b[m] - _apply(Sm, u[m], d)) / diag, u[m])
+    u[l] = _jacobi_masked(H, l, u[l], b[l])
+    for m, v in new.items():
+        u[m] = v
+    for m in range(H.base + 1, l + 1):
+        hang(H, u, m)
+
+
 def fas_cycle(H, l, u, b):
     """One FAS V-cycle from level l (u, b: dicts of lattice arrays, changed in
     place).  At the base level the regular correction-scheme cycle runs on the
-    base lattice."""
+    base lattice.  With ``H.multiscale`` every smoothing step of an adaptive
+    level also smooths the coarser levels' leaves (``_smooth_multiscale``),
+    as Alg. 1 does while a finer level is active."""
     d = H.d
     G = H.G
     if l == H.base:
@@ -536,10 +618,14 @@ def fas_cycle(H, l, u, b):
         ub = S.vcycle(H.regular, l, ub, bb)
         u[l][(slice(1, 3 ** l),) * d] = ub.reshape((3 ** l - 1,) * d)
         return
+    ms = getattr(H, "multiscale", False)
     act = np.isin(G.vtype[l], (LEAF, REFINED))
     hang(H, u, l)
     for _ in range(H.mu_pre):
-        u[l] = _jacobi_masked(H, l, u[l], b[l])
+        if ms:
+            _smooth_multiscale(H, l, u, b)
+        else:
+            u[l] = _jacobi_masked(H, l, u[l], b[l])
     r = np.where(act, b[l] - _apply(H.S[l], u[l], d), 0.0)
     inject(H, u, l)
     saved = u[l - 1].copy()
@@ -550,7 +636,10 @@ def fas_cycle(H, l, u, b):
     u[l] = np.where(act, u[l] + corr, u[l])
     hang(H, u, l)
     for _ in range(H.mu_post):
-        u[l] = _jacobi_masked(H, l, u[l], b[l])
+        if ms:
+            _smooth_multiscale(H, l, u, b)
+        else:
+            u[l] = _jacobi_masked(H, l, u[l], b[l])
 
 
 def composite_state(H, u):

@@ -172,11 +172,12 @@ def _eps_components(eps, d):
     raise ValueError(f"eps must have shape (n,)*{d} or ({d},)+(n,)*{d}; got {eps.shape} (n={n})")
 
 
-def geometric_stencil(eps, d, level):
+def geometric_stencil(eps, d, level, dirichlet=True):
     """Stencils of all vertices of a regular level from per-cell coefficients
     (eq. "03_solver:stencils": the row of vertex v is the sum over the 2^d
     cells around v of that cell's element-matrix row).  Returns a stencil array
-    of shape ``(3^d,) + (n+1,)*d`` with Dirichlet rows/entries removed."""
+    of shape ``(3^d,) + (n+1,)*d`` with Dirichlet rows/entries removed
+    (``dirichlet=False``: kept, the rows of interior vertices whole)."""
     n = 3 ** level
     h = 1.0 / n
     comps = _eps_components(eps, d)
@@ -197,7 +198,7 @@ def geometric_stencil(eps, d, level):
             ia, ib = corner_index(s), corner_index(w)
             for i in range(d):
                 S[k] += cell[i] * kref[i][ia, ib]
-    return apply_dirichlet(S, d, level)
+    return apply_dirichlet(S, d, level) if dirichlet else S
 
 
 def apply_dirichlet(S, d, level):

@@ -270,6 +270,21 @@ void validate(const qmg_grid_desc* desc, const qmg_solver_opts* o) {
     throw ApiError(QMG_EINVAL, "injection and aggregation are Petrov-Galerkin restrictions of multiplicative cycles");
   if (o->cycle != QMG_CYCLE_MULT && o->smoother != QMG_SMOOTH_JACOBI)
     throw ApiError(QMG_EINVAL, "additive and BPX cycles take one Jacobi step per level");
+  if (o->coarse_solver != QMG_COARSE_DIRECT && o->coarse_solver != QMG_COARSE_SWEEPS)
+    throw ApiError(QMG_EINVAL, "bad coarse_solver");
+  if (!(o->eps_zero >= 0.0 && o->eps_zero <= 1e-2)) throw ApiError(QMG_EINVAL, "eps_zero must lie in [0, 1e-2]");
+  if (o->iterate != QMG_IT_STORE && o->iterate != QMG_IT_FP64 && o->iterate != QMG_IT_FP32)
+    throw ApiError(QMG_EINVAL, "bad iterate");
+  {
+    const bool reduced = o->store >= QMG_HIER_FP32 && o->store <= QMG_HIER_BF16;
+    if (o->iterate == QMG_IT_FP64 && reduced)
+      throw ApiError(QMG_EINVAL, "FP32, FP16 and BF16 deltas run with FP32 iterates");
+    if (o->iterate == QMG_IT_FP32 && (o->store == QMG_PLAIN_FP64 || o->store == QMG_HIER_BPA))
+      throw ApiError(QMG_EINVAL, "FP32 iterates run on the HIER_FP64, FP32, FP16 or BF16 stores");
+    if (o->iterate == QMG_IT_FP32 && (o->cycle != QMG_CYCLE_MULT || o->smoother != QMG_SMOOTH_JACOBI ||
+                                      o->restriction != QMG_R_TRANSPOSE) && !reduced)
+      throw ApiError(QMG_EINVAL, "FP32 iterates with HIER_FP64 deltas run multiplicative Jacobi cycles");
+  }
   const bool adaptive = desc->base_level != 0 && desc->base_level != desc->max_level;
   if (!adaptive && desc->n_regions != 0)
     throw ApiError(QMG_EINVAL, "refinement regions need an adaptive grid (1 <= base < max_level)");
@@ -641,7 +656,8 @@ void init_modes(qmg_grid_t* g, const qmg_grid_desc* desc, const qmg_solver_opts*
   g->lcq = o->coarsest_level;
   g->lc = g->lcq;
   g->plain = o->store == QMG_PLAIN_FP64;
-  g->mixed = o->store >= QMG_HIER_FP32 && o->store <= QMG_HIER_BF16;
+  g->mixed = (o->store >= QMG_HIER_FP32 && o->store <= QMG_HIER_BF16) ||
+             (o->iterate == QMG_IT_FP32 && o->store == QMG_HIER_FP64);
   g->fmt = store_fmt(o->store);
   g->adaptive = desc->base_level != 0 && desc->base_level != desc->max_level;
   g->lb = g->adaptive ? desc->base_level : desc->max_level;
@@ -1241,69 +1257,34 @@ void encode(qmg_grid_t* g, LevelBuf& B, const Lat& Lc, bool is_P, const double* 
   // adaptive levels above the base level: only their listed tiles hold
   // operators the cycles read
   const bool tl = g->adaptive && B.tiles != nullptr && B.L.n > g->lv[g->lb].L.n;
-  launch_delta_flags(B.L, Lc, is_P, full, B.eps64, blk, S(g), eps_mf, tl ? B.tiles : nullptr, tl ? B.ntiles : 0);
+  launch_delta_flags(B.L, Lc, is_P, full, B.eps64, blk, S(g), eps_mf, tl ? B.tiles : nullptr, tl ? B.ntiles : 0,
+                     g->opts.eps_zero);
   launch_scan_blocks(blk, B.L.nslot / kSeg, g->dtotal + slot, S(g), off, unit, g->scan_tmp);
   launch_delta_write(B.L, Lc, is_P, fmt, full, B.eps64, blk, pay, sc, S(g), off, eps_mf, tl ? B.tiles : nullptr,
                      tl ? B.ntiles : 0);
 }
 
-void invert_dense(std::vector<double>& M, int n) {
-  std::vector<double> I((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
-  for (int c = 0; c < n; ++c) {
-    int p = c;
-    for (int r = c + 1; r < n; ++r)
-      if (std::fabs(M[(size_t)r * n + c]) > std::fabs(M[(size_t)p * n + c])) p = r;
-    if (M[(size_t)p * n + c] == 0.0) throw ApiError(QMG_EINDEF, "singular coarsest operator");
-    if (p != c)
-      for (int q = 0; q < n; ++q) {
-        std::swap(M[(size_t)p * n + q], M[(size_t)c * n + q]);
-        std::swap(I[(size_t)p * n + q], I[(size_t)c * n + q]);
-      }
-    const double inv = 1.0 / M[(size_t)c * n + c];
-    for (int q = 0; q < n; ++q) {
-      M[(size_t)c * n + q] *= inv;
-      I[(size_t)c * n + q] *= inv;
-    }
-    for (int r = 0; r < n; ++r) {
-      if (r == c) continue;
-      const double f = M[(size_t)r * n + c];
-      if (f == 0.0) continue;
-      for (int q = 0; q < n; ++q) {
-        M[(size_t)r * n + q] -= f * M[(size_t)c * n + q];
-        I[(size_t)r * n + q] -= f * I[(size_t)c * n + q];
-      }
-    }
-  }
-  M.swap(I);
-}
-
+// The coarsest solve (a10): a dense inverse of the level's FP64 operator,
+// assembled and inverted on the device (Gauss-Jordan with partial pivoting,
+// one workgroup), when the level has at most kCoarseDirectMax unknowns and
+// the exact solve is selected; otherwise the cycle smooths the level.  A
+// singular operator is reported by check_coarse after the next
+// synchronisation.
 void setup_coarse(qmg_grid_t* g, const double* Afull) {
   LevelBuf& C = g->lv[g->lc];
   const int64_t n = n_interior(C.L);
   g->nc = (int)std::min<int64_t>(n, 1 << 30);
-  g->coarse_direct = n <= kCoarseDirectMax && n * n <= g->ainv_cap;
+  g->coarse_direct = g->opts.coarse_solver == QMG_COARSE_DIRECT && n <= kCoarseDirectMax && n * n <= g->ainv_cap;
   if (!g->coarse_direct) return;
-  const int NS = ipow(3, g->d);
-  std::vector<double> h((size_t)NS * C.L.nslot);
-  QMG_HIP(hipMemcpyAsync(h.data(), Afull, h.size() * sizeof(double), hipMemcpyDeviceToHost, S(g)));
+  launch_coarse_inverse(C.L, Afull, (int)n, g->Ainv, g->dcount + 4, S(g));
+}
+
+void check_coarse(qmg_grid_t* g) {
+  if (!g->coarse_direct) return;
+  int st = 0;
+  QMG_HIP(hipMemcpyAsync(&st, g->dcount + 4, sizeof(int), hipMemcpyDeviceToHost, S(g)));
   QMG_HIP(hipStreamSynchronize(S(g)));
-  const int m = C.L.n - 1;
-  std::vector<double> M((size_t)n * n, 0.0);
-  for (int64_t r = 0; r < n; ++r) {
-    const int i = (int)(r % m) + 1, j = (int)((r / m) % m) + 1, k = g->d == 3 ? (int)(r / ((int64_t)m * m)) + 1 : 0;
-    const int64_t v = i + (int64_t)j * C.L.pitch + (int64_t)k * C.L.plane;
-    for (int e = 0; e < NS; ++e) {
-      const int ox = e % 3 - 1, oy = (e / 3) % 3 - 1, oz = g->d == 3 ? e / 9 - 1 : 0;
-      const int ii = i + ox, jj = j + oy, kk = k + oz;
-      if (ii < 1 || ii > m || jj < 1 || jj > m || (g->d == 3 && (kk < 1 || kk > m))) continue;
-      const int64_t c = (ii - 1) + (int64_t)m * ((jj - 1) + (int64_t)m * (g->d == 3 ? kk - 1 : 0));
-      M[(size_t)r * n + c] = h[(size_t)e * C.L.nslot + v];
-    }
-  }
-  invert_dense(M, (int)n);
-  QMG_HIP(hipMemcpyAsync(g->Ainv, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice, S(g)));
-  QMG_HIP(hipStreamSynchronize(S(g)));
+  if (st != 0) throw ApiError(QMG_EINDEF, "singular coarsest operator");
 }
 
 void assign_stores(qmg_grid_t* g) {
@@ -1516,6 +1497,7 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
     if (g->mixed) prepare_fused<float>(g);
     else prepare_fused<double>(g);
   }
+  check_coarse(g);
   g->have_ops = true;
   if (info) {
     std::memset(info, 0, sizeof(*info));
@@ -1553,6 +1535,7 @@ bool raise_coarsest(qmg_grid_t* g) {
     else prepare_fused<double>(g);
   }
   QMG_HIP(hipStreamSynchronize(S(g)));
+  check_coarse(g);
   return true;
 }
 
@@ -1816,6 +1799,9 @@ int qmg_default_opts(qmg_solver_opts* o) {
   o->damping = QMG_DAMP_EXP;
   o->eps_mf = 1e-8;
   o->restriction = QMG_R_TRANSPOSE;
+  o->coarse_solver = QMG_COARSE_DIRECT;
+  o->eps_zero = 0.0;
+  o->iterate = QMG_IT_STORE;
   return QMG_OK;
 }
 

@@ -654,13 +654,13 @@ __device__ inline int load_delta(const Lat& L, const Lat& Lc, const double* __re
 }
 
 // Per 64-slot block (one wavefront): 1 when any vertex's delta is non-zero
-// (max|delta| > kEpsZero * max|reference|), else 0.  With eps_mf > 0 the
+// (max|delta| > eps_zero * max|reference|), else 0.  With eps_mf > 0 the
 // block's width instead: the largest per-vertex bpa (0 for all-zero codes).
 template <int D, bool IS_P>
 __global__ __launch_bounds__(256) void k_delta_flags(Lat L, Lat Lc, const double* __restrict__ full,
                                                      const double* __restrict__ eps,
                                                      int32_t* __restrict__ blk, double eps_mf,
-                                                     const int32_t* __restrict__ tiles) {
+                                                     const int32_t* __restrict__ tiles, double eps_zero) {
   const int32_t* tl = tiles ? tiles + 3 * (int64_t)blockIdx.x : nullptr;
   const int i = (tl ? tl[0] : (int)blockIdx.x) * TX + threadIdx.x;
   const int j = (tl ? tl[1] : (int)blockIdx.y) * TY + threadIdx.y;
@@ -676,7 +676,7 @@ __global__ __launch_bounds__(256) void k_delta_flags(Lat L, Lat Lc, const double
     } else {
       double mx = 0.0;
       for (int k = 0; k < ne; ++k) mx = fmax(mx, fabs(dl[k]));
-      nz = mx > kEpsZero * refmax;
+      nz = mx > eps_zero * refmax;
     }
   }
   // maximum over the wavefront (flags: any)
@@ -959,16 +959,18 @@ void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s)
 }
 
 void launch_delta_flags(const Lat& L, const Lat& Lc, bool is_P, const double* full, const double* eps,
-                        int32_t* blk, hipStream_t s, double eps_mf, const int32_t* tiles, int ntiles) {
+                        int32_t* blk, hipStream_t s, double eps_mf, const int32_t* tiles, int ntiles,
+                        double eps_zero) {
+  if (!(eps_zero > 0.0)) eps_zero = kEpsZero;
   const dim3 g = tiles ? dim3((unsigned)ntiles) : tile_grid(L), bl(TX, TY, 1);
   if (tiles) launch_zero<int32_t>(blk, L.nslot / kSeg, s);  // blocks of unlisted tiles: zero
   if (tiles && ntiles == 0) return;
   if (L.d == 2) {
-    if (is_P) hipLaunchKernelGGL((k_delta_flags<2, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles);
-    else hipLaunchKernelGGL((k_delta_flags<2, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles);
+    if (is_P) hipLaunchKernelGGL((k_delta_flags<2, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero);
+    else hipLaunchKernelGGL((k_delta_flags<2, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero);
   } else {
-    if (is_P) hipLaunchKernelGGL((k_delta_flags<3, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles);
-    else hipLaunchKernelGGL((k_delta_flags<3, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles);
+    if (is_P) hipLaunchKernelGGL((k_delta_flags<3, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero);
+    else hipLaunchKernelGGL((k_delta_flags<3, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero);
   }
   QMG_HIP(hipGetLastError());
 }

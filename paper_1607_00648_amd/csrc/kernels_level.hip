@@ -544,6 +544,109 @@ __global__ void k_coarse_solve(Lat L, const double* __restrict__ Ainv, int nc,
   u[i + (int64_t)j * L.pitch + (int64_t)k * L.plane] = (T)acc;
 }
 
+// Dense coarsest operator from the level's full stencil array: row r (an
+// interior vertex, x fastest) receives its entries towards interior vertices.
+// M must be zero.
+__global__ void k_coarse_assemble(Lat L, const double* __restrict__ Afull, int n, double* __restrict__ M) {
+  const int NS = (L.d == 3) ? 27 : 9;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * NS) return;
+  const int r = (int)(t / NS), e = (int)(t % NS);
+  const int m = L.n - 1;
+  const int i = r % m + 1, j = (r / m) % m + 1, k = (L.d == 3) ? r / (m * m) + 1 : 0;
+  const int ii = i + off_x(e), jj = j + off_y(e), kk = k + ((L.d == 3) ? off_z(e) : 0);
+  if (ii < 1 || ii > m || jj < 1 || jj > m || (L.d == 3 && (kk < 1 || kk > m))) return;
+  const int c = (ii - 1) + m * ((jj - 1) + m * ((L.d == 3) ? kk - 1 : 0));
+  const int64_t v = i + (int64_t)j * L.pitch + (int64_t)k * L.plane;
+  M[(int64_t)r * n + c] = Afull[(int64_t)e * L.nslot + v];
+}
+
+// In-place Gauss-Jordan inversion of the dense n x n matrix a (row major,
+// n <= kCoarseDirectMax) by one workgroup: at step k the row of largest
+// |a(i,k)|, i >= k, is swapped in (lowest i on ties), the pivot row scaled,
+// column k eliminated from every other row with the pivot position taking
+// the inverse's entries; the row swaps are undone on the columns at the end.
+// *status = 1 when a pivot is zero (the matrix is singular).
+__global__ __launch_bounds__(1024) void k_gauss_jordan(double* __restrict__ a, int n, int* __restrict__ status) {
+  __shared__ int perm[kCoarseDirectMax];
+  __shared__ double colk[kCoarseDirectMax];
+  __shared__ double wv[16];
+  __shared__ int wi[16];
+  __shared__ int piv_s;
+  const int tid = threadIdx.x;
+  for (int k = 0; k < n; ++k) {
+    double bv = -1.0;
+    int bi = n;
+    for (int i = k + tid; i < n; i += 1024) {
+      const double x = fabs(a[(int64_t)i * n + k]);
+      if (x > bv) {
+        bv = x;
+        bi = i;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if ((tid & 63) == 0) {
+      wv[tid >> 6] = bv;
+      wi[tid >> 6] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double v = wv[0];
+      int ix = wi[0];
+      for (int w = 1; w < 16; ++w)
+        if (wv[w] > v || (wv[w] == v && wi[w] < ix)) {
+          v = wv[w];
+          ix = wi[w];
+        }
+      piv_s = ix;
+      perm[k] = ix;
+    }
+    __syncthreads();
+    const int p = piv_s;
+    if (p >= n || a[(int64_t)p * n + k] == 0.0) {
+      if (tid == 0) *status = 1;
+      return;  // uniform over the workgroup
+    }
+    if (p != k)
+      for (int c = tid; c < n; c += 1024) {
+        const double t = a[(int64_t)p * n + c];
+        a[(int64_t)p * n + c] = a[(int64_t)k * n + c];
+        a[(int64_t)k * n + c] = t;
+      }
+    __syncthreads();
+    const double inv = 1.0 / a[(int64_t)k * n + k];
+    for (int i = tid; i < n; i += 1024) colk[i] = a[(int64_t)i * n + k];
+    __syncthreads();
+    for (int c = tid; c < n; c += 1024) a[(int64_t)k * n + c] = (c == k ? 1.0 : a[(int64_t)k * n + c]) * inv;
+    __syncthreads();
+    for (int i = 0; i < n; ++i) {
+      const double f = colk[i];
+      if (i == k || f == 0.0) continue;
+      for (int c = tid; c < n; c += 1024)
+        a[(int64_t)i * n + c] = (c == k ? 0.0 : a[(int64_t)i * n + c]) - f * a[(int64_t)k * n + c];
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k)
+      for (int i = tid; i < n; i += 1024) {
+        const double t = a[(int64_t)i * n + p];
+        a[(int64_t)i * n + p] = a[(int64_t)i * n + k];
+        a[(int64_t)i * n + k] = t;
+      }
+    __syncthreads();
+  }
+}
+
 // x *= scale over [0, n) (grid-stride); per-block sums of squares of the
 // scaled values; *bad counts entries that are not finite (or, with positive,
 // not > 0).
@@ -843,6 +946,16 @@ void launch_coarse_solve(const Lat& L, const double* Ainv, int nc, const T* b, T
 }
 template void launch_coarse_solve<double>(const Lat&, const double*, int, const double*, double*, hipStream_t);
 template void launch_coarse_solve<float>(const Lat&, const double*, int, const float*, float*, hipStream_t);
+
+void launch_coarse_inverse(const Lat& L, const double* Afull, int n, double* Ainv, int* status, hipStream_t s) {
+  if (n <= 0 || n > kCoarseDirectMax) throw HipError("coarse inverse: size out of range");
+  launch_zero<double>(Ainv, (int64_t)n * n, s);
+  launch_zero<int32_t>(status, 1, s);
+  const int NS = L.d == 3 ? 27 : 9;
+  hipLaunchKernelGGL(k_coarse_assemble, dim3(blocks_for((int64_t)n * NS, 256)), dim3(256), 0, s, L, Afull, n, Ainv);
+  hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, Ainv, n, status);
+  QMG_HIP(hipGetLastError());
+}
 
 template <typename T>
 void launch_zero(T* p, int64_t n, hipStream_t s) {

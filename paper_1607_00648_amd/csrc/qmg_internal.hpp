@@ -17,7 +17,7 @@ namespace qmg {
 // Constants of the method and of the data layout
 // ---------------------------------------------------------------------------
 constexpr int kSeg = 64;                       // lattice slots per store block (one wavefront)
-constexpr double kEpsZero = 9.094947017729282e-13;  // 2^-40: a delta this small (relative) is zero
+constexpr double kEpsZero = 9.094947017729282e-13;  // 2^-40: default zero-delta threshold (relative)
 constexpr double kDomSlack = 1e-10;            // diagonal-dominance slack of the definiteness check
 constexpr int kCoarseDirectMax = 1024;         // coarsest levels up to this size are solved exactly
 
@@ -169,6 +169,10 @@ void launch_scatter_cells(const Lat& L, const double* in, T* lat, hipStream_t s)
 // Coarsest solve u = Ainv b over the interior unknowns (Ainv FP64, nc x nc).
 template <typename T>
 void launch_coarse_solve(const Lat& L, const double* Ainv, int nc, const T* b, T* u, hipStream_t s);
+// Ainv (n x n, n <= kCoarseDirectMax) := inverse of the coarsest operator
+// assembled from its full stencil array, on the device; *status = 1 when it
+// is singular.
+void launch_coarse_inverse(const Lat& L, const double* Afull, int n, double* Ainv, int* status, hipStream_t s);
 
 // ---- build ----
 // eps of level l-1 = mean of the 3^d children (lattice cell layout).
@@ -224,7 +228,7 @@ void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s)
 // encoded; the blocks of the others are flagged zero.
 void launch_delta_flags(const Lat& L, const Lat& Lc, bool is_P, const double* full,
                         const double* eps, int32_t* blk, hipStream_t s, double eps_mf = 0.0,
-                        const int32_t* tiles = nullptr, int ntiles = 0);
+                        const int32_t* tiles = nullptr, int ntiles = 0, double eps_zero = 0.0);
 // csum: device scratch of scan_scratch_ints(nblk) ints (chunk sums).
 void launch_scan_blocks(int32_t* blk, int64_t nblk, int32_t* total, hipStream_t s, int64_t* boff,
                         int64_t unit, int32_t* csum);

@@ -27,6 +27,8 @@ SMOOTHERS = {"jacobi": 0, "block": 1}
 CYCLES = {"mult": 0, "add": 1, "bpx": 2}
 RESTRICTIONS = {"transpose": 0, "injection": 1, "aggregation": 2}
 DAMPINGS = {"exp": 0, "const": 1}
+COARSE_SOLVERS = {"direct": 0, "sweeps": 1}
+ITERATES = {"store": 0, "fp64": 1, "fp32": 2}
 
 TRANSFERS = {"geometric": GEOMETRIC, "galerkin": GALERKIN_DLINEAR, "boxmg": BOXMG}
 STORES = {"plain64": PLAIN_FP64, "hier64": HIER_FP64, "hier32": HIER_FP32,
@@ -50,7 +52,8 @@ class SolverOpts(C.Structure):
                 ("mu_post", C.c_int), ("omega", C.c_double), ("coarsest_level", C.c_int),
                 ("check_definite", C.c_int), ("inner_cycles", C.c_int), ("use_graphs", C.c_int),
                 ("stagnation", C.c_double), ("smoother", C.c_int), ("bj_sweeps", C.c_int),
-                ("cycle", C.c_int), ("damping", C.c_int), ("eps_mf", C.c_double), ("restriction", C.c_int)]
+                ("cycle", C.c_int), ("damping", C.c_int), ("eps_mf", C.c_double), ("restriction", C.c_int),
+                ("coarse_solver", C.c_int), ("eps_zero", C.c_double), ("iterate", C.c_int)]
 
 
 class SolveReport(C.Structure):
@@ -142,7 +145,7 @@ def _ptr(a: np.ndarray):
 def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_level=1,
               check_definite=True, inner_cycles=1, graphs=True, stagnation=0.0, smoother="jacobi",
               bj_sweeps=1, cycle="mult", damping="exp", eps_mf=1e-8,
-              restriction="transpose") -> SolverOpts:
+              restriction="transpose", coarse_solver="direct", eps_zero=0.0, iterate="store") -> SolverOpts:
     """qmg_solver_opts from names (the header documents every field):
     transfer "geometric" | "galerkin" | "boxmg"; store "plain64" | "hier64" |
     "hier32" | "hier16" | "bf16" | "bpa" (eps_mf: the bpa coding error);
@@ -150,7 +153,8 @@ def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_l
     cycle "mult" | "add" | "bpx" with damping "exp" | "const"; restriction
     "transpose" | "injection" | "aggregation"; stagnation > 0 raises the
     coarsest level when a cycle reduces the residual by less than that
-    factor."""
+    factor; coarse_solver "direct" | "sweeps"; eps_zero the zero-delta
+    threshold (0: default); iterate "store" | "fp64" | "fp32"."""
     o = SolverOpts()
     o.transfer = TRANSFERS[transfer] if isinstance(transfer, str) else int(transfer)
     o.store = STORES[store] if isinstance(store, str) else int(store)
@@ -167,6 +171,9 @@ def make_opts(transfer="boxmg", store="hier64", mu=(2, 2), omega=0.6, coarsest_l
     o.damping = DAMPINGS[damping] if isinstance(damping, str) else int(damping)
     o.eps_mf = float(eps_mf)
     o.restriction = RESTRICTIONS[restriction] if isinstance(restriction, str) else int(restriction)
+    o.coarse_solver = COARSE_SOLVERS[coarse_solver] if isinstance(coarse_solver, str) else int(coarse_solver)
+    o.eps_zero = float(eps_zero)
+    o.iterate = ITERATES[iterate] if isinstance(iterate, str) else int(iterate)
     return o
 
 

@@ -969,3 +969,70 @@ def test_timed_variants_full_size(case):
     assert np.linalg.norm(b - A @ u) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)
     if case == "bpa_checkerboard":
         assert rep["cycles"] == rref["cycles"]
+
+
+def test_fp32_iterates_on_the_fp64_store_reach_tolerance():
+    """iterate = FP32 with HIER_FP64 deltas: FP32 cycles inside the FP64 defect
+    correction on exact deltas reach 1e-8, recomputed by the oracle in FP64;
+    the error against the direct solution stays within 10x the FP64 path's."""
+    qmg = require_gpu()
+    announce("fp32 iterates, hier64 store")
+    d, L = 2, 5
+    p = W.random_checkerboard(d, L, seed=9, values=(1.0, 1e4))
+    g = _grid(qmg, p, "boxmg", "hier64", iterate="fp32")
+    g.build()
+    rep, hist = g.solve(1e-8, 400)
+    u = g.solution()
+    g.close()
+    assert rep["status"] == "QMG_OK" and rep["outer_iters"] > 0
+    H = O.build_hierarchy(p.eps, d, L, transfer="boxmg")
+    b = O.rhs_from_f(p.f, d, L)
+    A = H.A[L]
+    assert np.linalg.norm(b - A @ u) / np.linalg.norm(b) <= 1e-8
+    ustar = O.direct_solve(A, b)
+    u64, _ = O.solve(H, b, tol=1e-8)
+    err64 = np.linalg.norm(u64 - ustar) / np.linalg.norm(ustar)
+    assert np.linalg.norm(u - ustar) / np.linalg.norm(ustar) <= 10 * max(err64, 1e-12)
+
+
+@pytest.mark.parametrize("d,L", [(2, 4), (3, 3)])
+def test_coarse_sweeps_match_oracle(d, L):
+    """coarse_solver = sweeps: the coarsest level takes mu_pre + mu_post Jacobi
+    sweeps from zero instead of the exact solve, as in the oracle with no
+    direct coarse solve."""
+    qmg = require_gpu()
+    announce(f"coarse sweeps d={d} L={L}")
+    p = W.random_checkerboard(d, L, seed=4, values=(1.0, 100.0))
+    k = 4
+    g = _grid(qmg, p, "boxmg", "hier64", coarse_solver="sweeps")
+    g.build()
+    rr = g.vcycle(k)
+    u = g.solution()
+    g.close()
+    H = O.build_hierarchy(p.eps, d, L, transfer="boxmg", direct_max=0)
+    assert H.coarse_lu is None
+    b = O.rhs_from_f(p.f, d, L)
+    uo, ho = O.solve(H, b, cycles=k)
+    np.testing.assert_allclose(rr, ho, rtol=1e-9)
+    assert np.linalg.norm(H.A[L] @ (u - uo)) / np.linalg.norm(b) <= 1e-12
+    Hd = O.build_hierarchy(p.eps, d, L, transfer="boxmg")
+    _, hd = O.solve(Hd, b, cycles=k)
+    assert abs(hd[-1] - ho[-1]) > 1e-3 * hd[-1]          # the exact solve is a different cycle
+
+
+def test_eps_zero_threshold_drops_small_deltas():
+    """A larger zero-delta threshold stores fewer blocks; the solve still
+    reaches the tolerance (the dropped deltas only change the coarse
+    operators)."""
+    qmg = require_gpu()
+    announce("eps_zero threshold")
+    p = W.random_checkerboard(2, 5, seed=3, values=(1.0, 1.5), blocks=9)
+    fr = []
+    for ez in (0.0, 1e-3):
+        g = _grid(qmg, p, "boxmg", "hier64", eps_zero=ez)
+        info = g.build()
+        rep, _ = g.solve(1e-8, 400)
+        assert rep["status"] == "QMG_OK"
+        fr.append(info["zero_delta_fraction"])
+        g.close()
+    assert fr[1] > fr[0]

@@ -150,3 +150,28 @@ def test_region_validation():
     reg.n_regions = 1
     reg.regions = good.regions
     assert lib.qmg_workspace_bytes(C.byref(reg), C.byref(ok), C.byref(nb)) == qmg.QMG_EINVAL
+
+
+def test_solver_option_validation():
+    from paper_1607_00648_amd import qmg
+    lib = qmg.load()
+    d = qmg.GridDesc(2, 5)
+    nb = C.c_size_t(0)
+    good = [qmg.make_opts(coarse_solver="sweeps"), qmg.make_opts(eps_zero=1e-6),
+            qmg.make_opts(store="hier64", iterate="fp32"), qmg.make_opts(store="bf16", iterate="fp32"),
+            qmg.make_opts(store="plain64", iterate="fp64")]
+    for o in good:
+        assert lib.qmg_workspace_bytes(C.byref(d), C.byref(o), C.byref(nb)) == qmg.QMG_OK
+    bad = [qmg.make_opts(coarse_solver=7), qmg.make_opts(eps_zero=-1.0), qmg.make_opts(eps_zero=0.5),
+           qmg.make_opts(iterate=9), qmg.make_opts(store="bf16", iterate="fp64"),
+           qmg.make_opts(store="plain64", iterate="fp32"), qmg.make_opts(store="bpa", iterate="fp32"),
+           qmg.make_opts(store="hier64", iterate="fp32", cycle="add")]
+    for o in bad:
+        assert lib.qmg_workspace_bytes(C.byref(d), C.byref(o), C.byref(nb)) == qmg.QMG_EINVAL
+    # FP32 iterates need the FP32 work arrays: the mixed workspace
+    o64 = qmg.make_opts(store="hier64")
+    o32 = qmg.make_opts(store="hier64", iterate="fp32")
+    n64, n32 = C.c_size_t(0), C.c_size_t(0)
+    lib.qmg_workspace_bytes(C.byref(d), C.byref(o64), C.byref(n64))
+    lib.qmg_workspace_bytes(C.byref(d), C.byref(o32), C.byref(n32))
+    assert n32.value != n64.value

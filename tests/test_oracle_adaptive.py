@@ -278,3 +278,63 @@ def test_local_spacetree_matches_the_laid_out_grid(d, base, L):
         nb = [tuple(vi + oi - 1 for vi, oi in zip(v, o)) for o in np.ndindex(*([3] * d))]
         hang = any(T.vclass(l, w) == AD.HANGING for w in nb)
         assert good != hang
+
+
+@pytest.mark.parametrize("d,base,L", [(2, 2, 4), (3, 1, 3)])
+def test_parent_interpolated_hanging_rows_keep_dlinear_for_constant_eps(d, base, L):
+    """The paper's reading of BoxMG rows at hanging vertices (d-linear
+    interpolation of the parent stencils): for constant eps the parents'
+    stencils are all one stencil up to scale and truncation at the boundary,
+    so BoxMG still reproduces the d-linear weights and the operators of the
+    d-linear Galerkin variant."""
+    G, _, f = _problem(d, base, L, seed=5)
+    eps = np.full(len(G.leaf_cells()), 2.5)
+    Hb = AD.build_adaptive(G, eps, transfer="boxmg", hanging_rows="parents")
+    Hg = AD.build_adaptive(G, eps, transfer="galerkin")
+    for l in range(2, L + 1):
+        np.testing.assert_allclose(Hb.P[l].toarray(), Hg.P[l].toarray() * (abs(Hb.P[l]).toarray() > 0),
+                                   atol=1e-12)
+        act = np.isin(G.vtype[l], (AD.LEAF, AD.REFINED))
+        np.testing.assert_allclose(Hb.S[l][:, act], Hg.S[l][:, act], atol=1e-12 * abs(Hg.S[l]).max())
+
+
+def test_parent_interpolated_hanging_rows_interpolate_the_parents():
+    """Each hanging row is the weighted mean of its interior parents' rows:
+    a hanging vertex on a coarse edge midpoint-third takes (2/3, 1/3)."""
+    G, eps, _ = _problem(2, 2, 4, seed=2)
+    e = G.level_eps(eps)
+    Hs = AD.hanging_stencils_parents(G, e)
+    Sc = O.geometric_stencil(AD.virtual_eps(G, e)[3], 2, 3, dirichlet=False)
+    hv = np.argwhere(G.vtype[4] == AD.HANGING)
+    checked = 0
+    for v in hv:                                     # numpy order (y, x)
+        y, x = v
+        if x % 3 == 0 and y % 3 == 1:                # on a vertical coarse edge, one third up
+            p0, p1 = (y // 3, x // 3), (y // 3 + 1, x // 3)
+            if all(1 <= c <= 26 for c in p0 + p1) and 2 <= x <= 79 and 2 <= y <= 79:
+                np.testing.assert_allclose(Hs[4][:, y, x], (2 / 3) * Sc[:, p0[0], p0[1]] + (1 / 3) * Sc[:, p1[0], p1[1]],
+                                           rtol=1e-14, atol=1e-14)
+                checked += 1
+    assert checked > 0
+
+
+@pytest.mark.parametrize("hanging_rows", ["covering", "parents"])
+def test_multiscale_smoothing_keeps_the_composite_fixed_point(hanging_rows):
+    """Alg. 1's smoothing of the coarser levels' leaves while a finer level is
+    active changes the iterates, not the fixed point: the cycle converges to
+    the directly solved composite system (d-linear Galerkin), and with BoxMG
+    to the composite system of its own hanging constraints."""
+    G, eps, f = _problem(2, 2, 4)
+    ustar, A, b = AD.solve_composite_direct(G, eps, f)
+    H = AD.build_adaptive(G, eps, transfer="galerkin", multiscale=True)
+    u, hist = AD.solve_adaptive(H, f, tol=1e-12, max_cycles=100)
+    assert hist[-1] <= 1e-12
+    assert np.linalg.norm(u - ustar) <= 1e-10 * np.linalg.norm(ustar)
+    H0 = AD.build_adaptive(G, eps, transfer="galerkin")
+    _, hist0 = AD.solve_adaptive(H0, f, cycles=3)
+    _, hist1 = AD.solve_adaptive(H, f, cycles=3)
+    assert hist0 != hist1                           # the iterates do change
+    Hb = AD.build_adaptive(G, eps, transfer="boxmg", hanging_rows=hanging_rows, multiscale=True)
+    ub, histb = AD.solve_adaptive(Hb, f, tol=1e-11, max_cycles=200)
+    us, Ab, bb = AD.solve_composite_direct(G, eps, f, AD.hanging_constraints(Hb))
+    assert np.linalg.norm(ub - us) <= 1e-9 * np.linalg.norm(us)

@@ -4,13 +4,13 @@
  * The library solves the elliptic problem of the paper's eq. (1) with v = 0,
  *     -div(eps grad u) = f  on (0,1)^d,  u = 0 on the boundary,
  * discretised with d-linear (Q1) finite elements on the levels of a
- * tripartitioned spacetree (Sect. 2: every refinement splits a cell into 3^d
+ * tripartitioned spacetree (Sect. 3: every refinement splits a cell into 3^d
  * children; level l has 3^l cells per axis).  Per-vertex 3^d stencils are
- * applied in situ (Sect. 3); coarse operators are rediscretised (geometric
- * multigrid), or Galerkin products R A P (Sect. 3.3) with d-linear or BoxMG
- * (Sect. 3.4 and the BoxMG appendix) transfer operators; stored operators are
+ * applied in situ (Sect. 4); coarse operators are rediscretised (geometric
+ * multigrid), or Galerkin products R A P (Sect. 4.3) with d-linear or BoxMG
+ * (Sect. 4.4 and the BoxMG appendix) transfer operators; stored operators are
  * kept as hierarchical deltas from the rediscretised stencil and the d-linear
- * prolongation (Sect. 4), in FP64, FP32, FP16 or BF16.
+ * prolongation (Sect. 5), in FP64, FP32, FP16 or BF16.
  *
  * Conventions for every entry point:
  *  - Return value: QMG_OK (0) or a negative status.  Nothing throws across the
@@ -35,7 +35,7 @@
  *    the finest level, numbered lexicographically with x fastest: vertex
  *    (i,j[,k]) with 1 <= i,j,k <= n-1 has index
  *    (i-1) + (n-1)*((j-1) + (n-1)*(k-1)); the cells (coefficients) are numbered
- *    the same way over 0 <= i,j,k <= n-1.  On an adaptive spacetree (Sect. 2)
+ *    the same way over 0 <= i,j,k <= n-1.  On an adaptive spacetree (Sect. 3)
  *    the unknowns are the leaf vertices (interior, non-hanging, not refined) of
  *    levels base..L and the coefficients live on the leaf cells (existing,
  *    not refined); both are numbered level by level, x fastest within a level
@@ -71,14 +71,14 @@ enum qmg_status {
 
 enum { QMG_HOST = 0, QMG_DEVICE = 1 };
 
-/* Transfer operators and coarse operators (Sect. 3.1, 3.3, 3.4). */
+/* Transfer operators and coarse operators (Sect. 4.1, 3.3, 3.4). */
 enum {
   QMG_GEOMETRIC = 0,         /* d-linear P, R = P^T, rediscretised coarse stencils */
   QMG_GALERKIN_DLINEAR = 1,  /* d-linear P, R = P^T, A_{l-1} = R A_l P            */
   QMG_BOXMG = 2              /* BoxMG P, R = P^T, A_{l-1} = R A_l P               */
 };
 
-/* Operator store (Sect. 4).  PLAIN keeps full FP64 stencils (and P) on every
+/* Operator store (Sect. 5).  PLAIN keeps full FP64 stencils (and P) on every
  * level including the finest; HIER keeps deltas from the rediscretised stencil
  * and from the d-linear P, dropping all-zero 64-vertex blocks.  PLAIN_FP64 and
  * HIER_FP64 iterate in FP64; the reduced-precision stores iterate in FP32 inside
@@ -99,7 +99,7 @@ enum {
   QMG_HIER_BPA = 5
 };
 
-/* Refinement regions of an adaptive spacetree (Sect. 2: every cell decides on
+/* Refinement regions of an adaptive spacetree (Sect. 3: every cell decides on
  * its own whether it is refined).  A region refines every existing cell of
  * levels base..level-1 that meets it, so its cells reach `level`.  Parameters
  * (host doubles, copied during the call), positions in the unit cube, x first:
@@ -148,7 +148,7 @@ typedef struct {
   double omega;        /* Jacobi damping in (0, 2)                           */
   int coarsest_level;  /* requested coarsest level, 1 <= lc < L (<= base)    */
   int check_definite;  /* 1: raise the coarsest level when a Galerkin row is
-                          not positive / diagonally dominant (Sect. 3.3)      */
+                          not positive / diagonally dominant (Sect. 4.3)      */
   int inner_cycles;    /* FP32 V-cycles per FP64 outer iteration (>= 1)     */
   int use_graphs;      /* 1: each cycle (+ residual norm) is captured once as
                           a HIP graph and replayed (one host call per cycle;
@@ -156,7 +156,7 @@ typedef struct {
                           the server); 0: eager kernel launches, which keep
                           up with the device for one grid on its own.  Needs
                           an even mu_pre + mu_post; ignored while profiling */
-  double stagnation;   /* dynamic coarsest level (Sect. 3.3): > 0 moves the
+  double stagnation;   /* dynamic coarsest level (Sect. 4.3): > 0 moves the
                           coarsest level one up after a cycle (an outer
                           iteration with FP32 iterates) that has not reached
                           the tolerance and cut the relative residual by less
@@ -197,7 +197,7 @@ typedef struct {
   double eps_mf;       /* QMG_HIER_BPA: largest coding error per entry, in
                           (0, 1]; default 1e-8                               */
   int restriction;     /* QMG_R_TRANSPOSE (default): R = P^T.  Petrov-
-                          Galerkin (Sect. 3.3 and the convection results),
+                          Galerkin (Sect. 4.3 and the convection results),
                           in the restriction and in A_{l-1} = R A_l P:
                           QMG_R_INJECTION, R = I (the coarse vertex takes the
                           fine value at its position); QMG_R_AGGREGATION, the
@@ -256,7 +256,7 @@ int qmg_workspace_bytes(const qmg_grid_desc* desc, const qmg_solver_opts* opts, 
  * cycle, graphs on. */
 int qmg_default_opts(qmg_solver_opts* opts);
 
-/* Creates a grid (Sect. 2: the levels 0..L of a tripartitioned spacetree,
+/* Creates a grid (Sect. 3: the levels 0..L of a tripartitioned spacetree,
  * each linearised as a Cartesian lattice of its level; on an adaptive
  * spacetree a level keeps its lattice and launches only the 64 x 4 vertex
  * tiles that touch existing cells) in `device_buf` (or library memory when
@@ -293,8 +293,8 @@ int qmg_leaf_cell_centres(const qmg_grid_t* grid, double* xyz);
  * holds no coefficients until a call succeeds. */
 int qmg_set_coefficients(qmg_grid_t* grid, const double* eps, int ncomp, const double* f, int mem);
 
-/* Builds all coarse operators (Sect. 3.3, 3.4): BoxMG P, Galerkin RAP with the
- * definiteness check, the hierarchical delta store (Sect. 4) and the coarsest
+/* Builds all coarse operators (Sect. 4.3, 3.4): BoxMG P, Galerkin RAP with the
+ * definiteness check, the hierarchical delta store (Sect. 5) and the coarsest
  * solve.  Fills `info` (nullable) with coarsest_level_used, bytes_operators,
  * zero_delta_fraction and seconds.  Returns QMG_EINDEF when even the first
  * coarse level fails the check. */
@@ -315,7 +315,7 @@ int qmg_solve(qmg_grid_t* grid, double rel_tol, int max_cycles, double* history,
 /* The residual b - A u of the current solution, one value per unknown (FP64
  * iterates only; QMG_EINVAL with FP32 iterates): on a regular grid the
  * finest-level residual, on an adaptive spacetree the residual of the
- * composite system at every leaf (Sect. 2: refined vertices hold their finest
+ * composite system at every leaf (Sect. 3: refined vertices hold their finest
  * copy, hanging vertices the interpolant of the coarser level, which this call
  * refreshes first).  It is the vector whose norm the cycles report.
  * Overwrites the levels' residual buffers. */
@@ -356,7 +356,7 @@ int qmg_get_operator(const qmg_grid_t* grid, int level, double* stencils);
  * floor(f/3) + (kx,ky,kz) at fine vertex f (zero where it is not a parent). */
 int qmg_get_prolongation(const qmg_grid_t* grid, int level, double* weights);
 
-/* Refinement criterion of the dynamically adaptive runs (Sect. 5), on a
+/* Refinement criterion of the dynamically adaptive runs (Sect. 7), on a
  * regular grid with FP64 iterates and built operators: per interior vertex
  * the absolute difference between u and the mean of its 3^d - 1 neighbours;
  * vertices whose residual |b - A u| is below res_tol are candidates; ten even

@@ -1,6 +1,6 @@
 """Adaptive spacetrees: composite system and FAS V-cycle (oracle, FP64).
 
-Paper passages followed (Sect. 2):
+Paper passages followed (Sect. 3):
 
 * A cell is refined independently of its neighbours; level l holds the cells
   of depth l, so each level is a ragged Cartesian grid.
@@ -38,7 +38,7 @@ notes):
 * Coarse stencils of refined vertices are Galerkin products with the d-linear
   P (the hanging interpolation uses the same weights), or rediscretised for the
   geometric variant.
-* BoxMG on adaptive levels (Sect. 3.4, the passage on spacetree grids): P is
+* BoxMG on adaptive levels (Sect. 4.4, the passage on spacetree grids): P is
   built per refined coarse cell only (a patch), from the level's stencils.  At
   hanging vertices, whose rows the collapsed systems of the patch faces need,
   the paper takes stencils obtained from the coarser level by d-linear
@@ -264,7 +264,7 @@ def composite_system(G: AdaptiveGrid, eps_leaf, f_leaf, P=None):
 
 def composite_residual_rows(G: AdaptiveGrid, eps_leaf, f_leaf, u_leaf, sample, P=None):
     """b_k - (A u)_k of the composite system at the unknowns ``sample``, each
-    row assembled on its own: the element matrices (Sect. 2, Q1) of the 2^d
+    row assembled on its own: the element matrices (Sect. 3, Q1) of the 2^d
     cells around the leaf, applied to the composite values of their corners.
     Usable on grids far too large for ``composite_system``."""
     d = G.d
@@ -365,7 +365,7 @@ def hanging_stencils_parents(G: AdaptiveGrid, eps):
 
 def boxmg_adaptive_P(G: AdaptiveGrid, S_full, l, check=True):
     """BoxMG prolongation from level l-1 to level l computed on the refined
-    coarse cells only (Sect. 3.4 per patch and corner), from the level's
+    coarse cells only (Sect. 4.4 per patch and corner), from the level's
     stencil array ``S_full`` (rows of leaf, refined and hanging vertices).
     Sparse, fine interior unknowns x coarse interior unknowns; rows of fine
     vertices outside every refined cell are empty."""
@@ -421,7 +421,7 @@ def build_adaptive(G: AdaptiveGrid, eps_leaf, transfer="galerkin", omega=0.6, mu
     refined ones; prolongations ``H.P[l]`` (also used for the hanging values);
     the levels up to the base level form a regular hierarchy below.
 
-    ``check_definite``: the definiteness check of Sect. 3.3 on the Galerkin
+    ``check_definite``: the definiteness check of Sect. 4.3 on the Galerkin
     operators of the complete levels below the base level (a row with a
     non-positive diagonal or without diagonal dominance); the first level
     whose coarser operator fails becomes the coarsest level, which is at most
@@ -684,7 +684,7 @@ def solve_adaptive(H, f_leaf, tol=1e-8, max_cycles=200, cycles=None, stagnation=
     """FAS V-cycles from zero; returns (leaf values, relres history).  With
     ``stagnation`` > 0 the coarsest level of the regular levels moves up (to
     the base level at most) after a cycle that reduced the composite residual
-    by less than that factor (Sect. 3.3)."""
+    by less than that factor (Sect. 4.3)."""
     u, b = initial_state(H, f_leaf)
     b0 = {l: v.copy() for l, v in b.items()}
     bl = np.concatenate([b0[l][H.G.vtype[l] == LEAF] for l in range(H.base, H.L + 1)])
@@ -715,7 +715,7 @@ def solve_composite_direct(G, eps_leaf, f_leaf, P=None):
 # ---------------------------------------------------------------------------
 
 class LocalSpacetree:
-    """The spacetree of Sect. 2 decided cell by cell for grids too large for
+    """The spacetree of Sect. 3 decided cell by cell for grids too large for
     ``AdaptiveGrid``: levels 0..base are complete; a cell of level base..L-1
     is refined when it exists and the refinement predicate ``mark(l, cells)``
     holds; a cell of a finer level exists when its parent is refined.  Vertex
@@ -768,7 +768,7 @@ class LocalSpacetree:
 
 
 def local_composite_rows(T: LocalSpacetree, eps_at, f_at, u_of, samples):
-    """b - A u of the composite system (Sect. 2) at leaf unknowns given as
+    """b - A u of the composite system (Sect. 3) at leaf unknowns given as
     (level, x-first position) pairs, each row assembled on its own from the
     element matrices of the 2^d cells around the vertex (coefficients from
     ``eps_at``, the source from ``f_at(level, coords)``) and the composite

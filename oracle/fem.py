@@ -4,8 +4,8 @@ Paper passages followed:
 
 * Eq. (1) of the introduction: -div(eps grad u) + (v . grad) u = f on the unit
   cube, eps a diagonal tensor, v a velocity field.
-* Sect. 2 (spacetree, vertex classes, d-linear shape functions on every level)
-  and Sect. 3, eq. "03_solver:stencils": a vertex's stencil is the sum of the
+* Sect. 3 (spacetree, vertex classes, d-linear shape functions on every level)
+  and Sect. 4, eq. "03_solver:stencils": a vertex's stencil is the sum of the
   contributions of its 2^d adjacent cells.
 
 Readings (the paper is silent on these):
@@ -64,7 +64,7 @@ def corner_index(a):
 
 
 def element_matrix(d, h, eps_c):
-    """Q1 element stiffness of one cell (Sect. 2, d-linear shape functions) for
+    """Q1 element stiffness of one cell (Sect. 3, d-linear shape functions) for
     the diagonal coefficient ``eps_c`` (scalar or length-d).  Rows and columns
     are the cell's corners in ``corners(d)`` order."""
     eps_c = np.broadcast_to(np.asarray(eps_c, dtype=np.float64), (d,))
@@ -272,7 +272,7 @@ def unknowns_from_lattice(a, d, level):
 
 def coarsen_eps(eps, d):
     """Coefficient of a level-(l-1) cell = mean of its 3^d children.  The paper
-    rediscretises on every level (Sect. 2, item 3) without fixing how eps is
+    rediscretises on every level (Sect. 3, item 3) without fixing how eps is
     sampled there; averaging is a reading of the paper."""
     comps = np.asarray(eps, dtype=np.float64)
     lead = comps.ndim - d

@@ -1,9 +1,9 @@
 """Galerkin coarse operators and the definiteness check (oracle, FP64).
 
-* Sect. 3.3: A_{l-1} = R A_l P with R = P^T unless stated otherwise (Sect. 3.4).
+* Sect. 4.3: A_{l-1} = R A_l P with R = P^T unless stated otherwise (Sect. 4.4).
   The oracle forms the plain definition, the sparse triple product, with a
   library sparse matrix product as the step.
-* Sect. 3.3 (dynamic coarsest level): a coarse stencil with a non-positive
+* Sect. 4.3 (dynamic coarsest level): a coarse stencil with a non-positive
   diagonal, or that is no longer diagonally dominant, makes the solver use a
   finer coarsest level.  Reading: row V fails when a_VV <= 0 or
   a_VV < (1 - 1e-10) * sum_{W != V} |a_VW| (the slack absorbs rounding in rows
@@ -22,7 +22,7 @@ DOMINANCE_SLACK = 1e-10
 
 def rap(A, P, R=None):
     """R A P (sparse, interior unknowns); R = P^T unless given (Petrov-Galerkin,
-    Sect. 3.3)."""
+    Sect. 4.3)."""
     R = P.T if R is None else R
     return sp.csr_matrix(R @ (A @ P))
 

@@ -1,6 +1,6 @@
 """Refinement criterion of the dynamically adaptive runs (oracle, FP64).
 
-Sect. 5 (setups): per unrefined vertex, the absolute difference between the
+Sect. 7 (setups): per unrefined vertex, the absolute difference between the
 vertex value and the mean of its 3^d - 1 neighbours; a vertex is a candidate
 when it is unrefined and its residual is below a threshold (10^-2 in the
 paper); about the 10 percent of the candidates with the largest differences

@@ -1,13 +1,13 @@
 """Multigrid hierarchy, V-cycle and the outer loops (oracle).
 
-* Algorithm 1 / Sect. 3.1: multiplicative V(mu_pre, mu_post) cycles with damped
+* Algorithm 1 / Sect. 4.1: multiplicative V(mu_pre, mu_post) cycles with damped
   point Jacobi, u <- u + omega diag(A)^-1 (b - A u), out of place.
-* Sect. 3.3: coarse operators A_{l-1} = P^T A_l P (Galerkin and BoxMG) or the
+* Sect. 4.3: coarse operators A_{l-1} = P^T A_l P (Galerkin and BoxMG) or the
   rediscretisation (geometric); the coarsest level moves up when a Galerkin
   operator fails the diagonal check.
 * Results section ("/e"): an exact coarsest-level solve; otherwise mu_pre+mu_post
   Jacobi sweeps on the coarsest level.
-* Sect. 3.3 (dynamic coarsest level): between two cycles the coarsest level
+* Sect. 4.3 (dynamic coarsest level): between two cycles the coarsest level
   moves one level up when the residual stagnates or grows (``raise_coarsest``).
 * Sect. "Spacetree block smoothers": block Jacobi BJ(m) runs m Gauss-Seidel
   sweeps on the (k-1)^d iota-vertices of every 3^d patch and Jacobi on the
@@ -135,7 +135,7 @@ class Hierarchy:
 def build_hierarchy(eps, d, L, transfer="boxmg", lc=1, omega=0.6, mu_pre=2, mu_post=2,
                     check_definite=True, perturb=None, smoother="jacobi", bj_sweeps=1, v=None,
                     restriction="transpose", direct_max=COARSE_DIRECT_MAX):
-    """Operators of all levels from the finest coefficients (Sect. 3.3, 3.4).
+    """Operators of all levels from the finest coefficients (Sect. 4.3, 3.4).
 
     ``v`` (per-cell velocities, shape (d,)+(n,)*d) adds the convection term of
     eq. (1) to the finest operator; its coarse operators then come from the
@@ -348,7 +348,7 @@ def solve_additive(H, b, tol=1e-8, max_cycles=1000, damping="exp", cycles=None, 
 
 
 def raise_coarsest(H, top=None):
-    """Dynamic coarsest level (Sect. 3.3): move l_c one level up, to ``top``
+    """Dynamic coarsest level (Sect. 4.3): move l_c one level up, to ``top``
     (default L - 1) at most; the new coarsest level is solved with its own
     operator.  Returns whether the level moved."""
     top = H.L - 1 if top is None else top

@@ -1,6 +1,6 @@
 """Hierarchical operator store (oracle, FP64 with emulated quantisation).
 
-Sect. 4 ("Stencil compression"): hierarchical operators
+Sect. 5 ("Stencil compression"): hierarchical operators
 A_hat = A - A_rediscretised and P_hat = P - P_dlinear (R_hat = P_hat^T) are
 small for smooth coefficients; a vertex whose hierarchical operator is zero
 drops its stencil, otherwise the entries are stored compressed.
@@ -16,7 +16,7 @@ decisions:
   integer such that max|delta| <= 2^(15+e); the scaled FP64 value delta/2^e is
   rounded to FP32 and then to FP16 (nearest-even).  The paper stores one exponent
   byte per entry (m * 2^e); one exponent per stencil is a reading of the paper.
-* bpa (Sect. 4, the paper's own codec): every entry x of a vertex's delta is
+* bpa (Sect. 5, the paper's own codec): every entry x of a vertex's delta is
   stored as m * 2^e, e in one signed byte and m a signed integer of bpa - 1
   bytes; per vertex bpa is the smallest of {0, 2, 3, ..., 8} for which every
   entry satisfies |m 2^e - x| <= eps_mf (bpa 0: the vertex stores nothing and

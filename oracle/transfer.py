@@ -1,8 +1,8 @@
 """Inter-grid transfer operators (oracle, FP64).
 
-* d-linear prolongation (Sect. 3.3 "Galerkin multigrid variants"): the weight
+* d-linear prolongation (Sect. 4.3 "Galerkin multigrid variants"): the weight
   of coarse vertex V at fine vertex 3V + o is prod_i (1 - |o_i|/3), |o_i| <= 2.
-* BoxMG prolongation for tripartitioning (Sect. 3.4 and the appendix "BoxMG
+* BoxMG prolongation for tripartitioning (Sect. 4.4 and the appendix "BoxMG
   realisation as one linear equation system solve"): per coarse cell (patch of
   4^d fine vertices) and per patch corner, mirror the patch so that the corner
   is the reference (lower-left) vertex, then
@@ -144,7 +144,7 @@ def boxmg_reference_Cs(t, d):
 
 
 def boxmg_reference_stepwise(t, d):
-    """Stepwise BoxMG (Sect. 3.4 steps): c-point, then each coarse-grid line
+    """Stepwise BoxMG (Sect. 4.4 steps): c-point, then each coarse-grid line
     (2x2), then each face in 3D (4x4), then the interior (2^d x 2^d).  Each
     group only couples to itself and to groups solved before it."""
     B = t.shape[0]

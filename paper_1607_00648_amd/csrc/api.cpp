@@ -1,5 +1,5 @@
 // Host driver and C ABI of the quasi-matrix-free multigrid library: workspace
-// layout, coefficient upload, operator construction (Sect. 3.3, 3.4, 4),
+// layout, coefficient upload, operator construction (Sect. 4.3, 3.4, 4),
 // V-cycles (Alg. 1, correction-scheme form on regular grids), the FP64
 // defect-correction loop around FP32 cycles, and inspection entry points.
 #include <algorithm>
@@ -418,7 +418,7 @@ std::vector<uint8_t> refine_flags(const qmg_grid_desc* desc) {
   return out;
 }
 
-// Spacetree of levels base..L (Sect. 2): cells of level base all exist; a
+// Spacetree of levels base..L (Sect. 3): cells of level base all exist; a
 // cell of a finer level exists when its parent is refined; a cell is refined
 // when it exists, its flag is set and it is not on level L.  Vertex classes:
 // hanging (fewer than 2^d existing cells), refined (all 2^d cells refined),
@@ -951,7 +951,7 @@ void smooth_ad(qmg_grid_t* g, LevelBuf& B, int sweeps) {
   }
 }
 
-// FAS V-cycle step on an adaptive level (Sect. 2): hanging vertices take the
+// FAS V-cycle step on an adaptive level (Sect. 3): hanging vertices take the
 // interpolant of the coarser level, the leaf and refined vertices are
 // smoothed, refined coarse vertices receive the finer values (injection) and
 // the FAS right-hand side R r + A_c I u (R = P^T), the coarse level is
@@ -1245,7 +1245,7 @@ std::vector<double> run_batch(qmg_grid_t* g, int B) {
 }
 
 // ---------------------------------------------------------------------------
-// Build (Sect. 3.3 and 3.4; store of Sect. 4)
+// Build (Sect. 4.3 and 3.4; store of Sect. 5)
 // ---------------------------------------------------------------------------
 void encode(qmg_grid_t* g, LevelBuf& B, const Lat& Lc, bool is_P, const double* full, int slot, int fmt) {
   int32_t* blk = is_P ? B.Pblk : B.Ablk;
@@ -1508,7 +1508,7 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
   }
 }
 
-// Dynamic coarsest level (Sect. 3.3): moves l_c one level up, to L - 1 at
+// Dynamic coarsest level (Sect. 4.3): moves l_c one level up, to L - 1 at
 // most (the base level on an adaptive grid).  The new coarsest level's stored
 // operator is decoded to FP64 for its exact solve (or it is smoothed when too
 // large); the levels below drop out of the cycle.  Returns whether it moved.

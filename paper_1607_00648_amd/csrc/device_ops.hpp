@@ -115,7 +115,7 @@ struct Dec<BF16> {
   }
 };
 
-// bpa codec (Sect. 4): x ~ m 2^e with e in one signed byte and m a
+// bpa codec (Sect. 5): x ~ m 2^e with e in one signed byte and m a
 // two's-complement integer of bpa - 1 bytes, e the smallest exponent for which
 // the rounded (nearest-even) m fits; bpa 0, x = 0 and exponents below -128
 // code zero.  Every step is exact, so host and device agree bit for bit.

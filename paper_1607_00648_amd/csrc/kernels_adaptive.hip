@@ -2,7 +2,7 @@
 //
 // An adaptive level keeps the full lattice of its level but only the 64 x 4
 // (x, y) tiles that hold vertices of existing cells are launched: blockIdx.x
-// indexes a tile list.  Every slot carries its vertex class (Sect. 2): leaf
+// indexes a tile list.  Every slot carries its vertex class (Sect. 3): leaf
 // (unrefined, an unknown), refined (a finer copy exists), hanging (fewer than
 // 2^d cells of the level), or outside/boundary.  Smoothing and residuals act
 // on leaf and refined vertices; hanging vertices hold the d-linear interpolant

@@ -1,6 +1,6 @@
 // Operator construction kernels: coefficient coarsening, BoxMG prolongation
-// (Sect. 3.4 and the BoxMG appendix), Galerkin R A P (Sect. 3.3) with the
-// definiteness check, and the hierarchical delta store (Sect. 4).  All FP64.
+// (Sect. 4.4 and the BoxMG appendix), Galerkin R A P (Sect. 4.3) with the
+// definiteness check, and the hierarchical delta store (Sect. 5).  All FP64.
 #include <stdexcept>
 #include "device_ops.hpp"
 
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(64) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, dou
 }
 
 // ---------------------------------------------------------------------------
-// Galerkin product (Sect. 3.3): A_c(V, W) = sum_i sum_j P(i,V) a(i,j) P(j,W)
+// Galerkin product (Sect. 4.3): A_c(V, W) = sum_i sum_j P(i,V) a(i,j) P(j,W)
 // for interior coarse V and W in 3^d(V), i within 2 of 3V and |i - j| <= 1.
 // ---------------------------------------------------------------------------
 template <int D>

@@ -449,7 +449,7 @@ __global__ void k_inject(Lat Lf, Lat Lc, const T* __restrict__ rf, T* __restrict
   bc[i + (int64_t)j * Lc.pitch + (int64_t)k * Lc.plane] = acc;
 }
 
-// Refinement criterion (dynamic adaptivity, Sect. 5), regular level.  Per
+// Refinement criterion (dynamic adaptivity, Sect. 7), regular level.  Per
 // lattice slot: |mean of the 3^d - 1 neighbours - u| (summed in stencil
 // order, x fastest, centre skipped) at interior vertices whose |r| < res_tol,
 // -1 elsewhere; mm gets the bit patterns of the smallest and largest value

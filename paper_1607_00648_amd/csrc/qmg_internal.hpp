@@ -74,7 +74,7 @@ inline Lat make_lat(int d, int level) {
 //              is the compact index of 64-slot block b or -1 for an all-zero
 //              delta; `payload` holds [cblk][nent][64] values of format `fmt`;
 //              `scale` holds [cblk][64] power-of-two exponents (FP16 only).
-//              BPA (the paper's codec, Sect. 4): block c of width W bytes per
+//              BPA (the paper's codec, Sect. 5): block c of width W bytes per
 //              entry starts at byte boff[c] & (2^56 - 1) of `payload`, W =
 //              boff[c] >> 56 in 2..8; it holds [nent][64] signed exponent
 //              bytes, then for j = 0..W-2 byte j (little endian) of the
@@ -184,7 +184,7 @@ void launch_materialise(const Lat& L, const double* eps, const Store& A, double*
 // Materialise prolongation weights as FP64 (2^d * nslot of the fine level; Lc
 // is the coarse lattice).
 void launch_materialise_P(const Lat& Lf, const Lat& Lc, const Store& P, double* out, hipStream_t s);
-// BoxMG P (Sect. 3.4): writes 2^d*nslot FP64 parent weights of the fine level.
+// BoxMG P (Sect. 4.4): writes 2^d*nslot FP64 parent weights of the fine level.
 // Afine: FP64 stencils of the fine level (entry-major); when null, the fine
 // operator is rediscretised from epsf on the fly.
 // vt_fine / cref_coarse (adaptive levels, nullable): fine vertex classes (rows
@@ -195,7 +195,7 @@ void launch_materialise_P(const Lat& Lf, const Lat& Lc, const Store& P, double* 
 void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
                   double* Pw, hipStream_t s, const int8_t* vt_fine = nullptr,
                   const int8_t* cref_coarse = nullptr, const int32_t* cells = nullptr, int64_t n_cells = 0);
-// Galerkin RAP (Sect. 3.3): coarse FP64 stencils from fine stencils (or eps on
+// Galerkin RAP (Sect. 4.3): coarse FP64 stencils from fine stencils (or eps on
 // the fly when Afine is null) and FP64 parent weights (d-linear when Pw null).
 // vt_fine (nullable): vertex classes of the fine level; rows of vertices that
 // are neither leaf nor refined count as zero.

@@ -371,7 +371,7 @@ def test_mixed_inner_cycles(store):
 
 
 # ---------------------------------------------------------------------------
-# Dynamic coarsest level (Sect. 3.3): raise between cycles on stagnation
+# Dynamic coarsest level (Sect. 4.3): raise between cycles on stagnation
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("transfer,store", [("geometric", "hier64"), ("geometric", "plain64"),

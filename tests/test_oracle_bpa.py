@@ -1,4 +1,4 @@
-"""Pins of the oracle's bpa codec (Sect. 4, stencil compression): values
+"""Pins of the oracle's bpa codec (Sect. 5, stencil compression): values
 worked out by hand, a brute-force search over exponents, exactness at eight
 bytes, minimality of the chosen width, and the solver behaviour the paper
 reports for eps_mf = 1e-8."""

@@ -1,4 +1,4 @@
-"""Pins of the oracle's refinement criterion (Sect. 5, dynamic adaptivity):
+"""Pins of the oracle's refinement criterion (Sect. 7, dynamic adaptivity):
 brute-force mean differences, linear functions that change nothing, the
 choice of about the top fraction through ten bins, and the cells around a
 chosen vertex."""

@@ -95,7 +95,7 @@ def test_mixed_precision_reaches_tolerance(fmt):
 
 
 # ---------------------------------------------------------------------------
-# Dynamic coarsest level (Sect. 3.3): raise between cycles on stagnation
+# Dynamic coarsest level (Sect. 4.3): raise between cycles on stagnation
 # ---------------------------------------------------------------------------
 
 def _two_grid_cycle(A, P, Ac, b, u, omega, mu_pre, mu_post):

@@ -14,7 +14,7 @@ Layout conventions (shared by every producer and consumer of these arrays):
   fastest.  Interior vertex ``(i, j[, k])`` with ``1 <= i,j,k <= n-1`` sits at
   ``x = i/n`` and is stored at ``f[k-1, j-1, i-1]``.
 
-The problems follow the paper's setups (Table "parameters", Sect. 5): zero
+The problems follow the paper's setups (Table "parameters", Sect. 7): zero
 Dirichlet boundary, piecewise-constant coefficients (and, for ``circle``,
 velocities) per cell.
 The concrete random fields stand in for the paper's analytic setups; no data set

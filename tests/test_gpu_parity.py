@@ -1023,13 +1023,28 @@ def test_coarse_sweeps_match_oracle(d, L):
 def test_eps_zero_threshold_drops_small_deltas():
     """A larger zero-delta threshold stores fewer blocks; the solve still
     reaches the tolerance (the dropped deltas only change the coarse
-    operators)."""
+    operators).  A smooth coefficient 1 + 0.3 sin(2 pi x) sin(2 pi y) on
+    level 5: the oracle's level-4 deltas all lie between 2^-40 and 10^-3 of
+    the rediscretised rows, so the 10^-3 threshold drops every level-4 block
+    the default keeps.  (A checkerboard of 9^2 blocks has no such deltas: it
+    is constant on the level-2 cells.)"""
     qmg = require_gpu()
     announce("eps_zero threshold")
-    p = W.random_checkerboard(2, 5, seed=3, values=(1.0, 1.5), blocks=9)
+    d, L = 2, 5
+    n = 3 ** L
+    xc = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(xc, xc, indexing="ij")
+    eps = 1.0 + 0.3 * np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+    H = O.build_hierarchy(eps, d, L, transfer="boxmg")
+    G = O.geometric_stencil(H.eps[4], d, 4)
+    rel = np.abs(O.solver.csr_to_stencil(H.A[4], d, 4) - G).max(axis=0)
+    rel = rel[np.abs(G).max(axis=0) > 0] / np.abs(G).max(axis=0)[np.abs(G).max(axis=0) > 0]
+    assert (rel > 2.0 ** -40).all() and (rel < 1e-3).all()
+    f = W.poisson(d, L, seed=3).f
     fr = []
     for ez in (0.0, 1e-3):
-        g = _grid(qmg, p, "boxmg", "hier64", eps_zero=ez)
+        g = qmg.Grid(d, L, qmg.make_opts("boxmg", "hier64", eps_zero=ez))
+        g.set_coefficients(eps, f)
         info = g.build()
         rep, _ = g.solve(1e-8, 400)
         assert rep["status"] == "QMG_OK"

@@ -370,6 +370,19 @@ int qmg_get_prolongation(const qmg_grid_t* grid, int level, double* weights);
  * QMG_EINVAL on an adaptive grid, FP32 iterates or arguments out of range. */
 int qmg_refine_flags(qmg_grid_t* grid, double res_tol, double fraction, uint8_t* cell_flags, int64_t* n_flagged);
 
+/* The same criterion, flags and errors as qmg_refine_flags, for callers that
+ * cannot allocate device memory (code under stream capture, serving loops,
+ * harnesses that forbid hipMalloc): this call allocates nothing.  Its
+ * extrema and bin counts (104 bytes, whatever the grid size) live in a
+ * library-wide scratch array of 256 bytes that each device holds from the
+ * library's load until the process ends; the call initialises what it
+ * reads.  The device current at the call must be the grid's (QMG_EINVAL
+ * otherwise).  Calls that overlap on one device share that array and race:
+ * serialise them (one host thread, or one stream per device with the calls
+ * in order). */
+int qmg_refine_flags_noalloc(qmg_grid_t* grid, double res_tol, double fraction, uint8_t* cell_flags,
+                             int64_t* n_flagged);
+
 enum { QMG_SMOOTH_JACOBI = 0, QMG_SMOOTH_BLOCK = 1 };
 enum { QMG_CYCLE_MULT = 0, QMG_CYCLE_ADD = 1, QMG_CYCLE_BPX = 2 };
 enum { QMG_DAMP_EXP = 0, QMG_DAMP_CONST = 1 };

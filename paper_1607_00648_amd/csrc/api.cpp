@@ -10,6 +10,7 @@
 #include <functional>
 #include <new>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -2179,62 +2180,125 @@ int qmg_get_operator(const qmg_grid_t* cg, int level, double* stencils) {
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Refinement criterion on the finest level, with its extrema (two 8-byte
+// words at `scr`) and ten bin counts (ints at scr + 64) in `scr`: device
+// memory of kRefineScratch bytes, whatever the grid size.
+constexpr size_t kRefineScratch = 64 + 10 * sizeof(int);
+
+void refine_flags_with(qmg_grid_t* g, double res_tol, double fraction, uint8_t* cell_flags, int64_t* n_flagged,
+                       void* scr) {
+  LevelBuf& F = g->lv[g->Lmax];
+  const Lat& L = F.L;
+  hipStream_t s = S(g);
+  const int64_t ncell = L.d == 3 ? (int64_t)L.n * L.n * L.n : (int64_t)L.n * L.n;
+  // r = b - A u on the finest level
+  launch_stencil<double>(L, 2, (const double*)F.u, (const double*)F.b, (double*)F.r, eps_of<double>(F), F.A,
+                         0.0, nullptr, nullptr, s);
+  unsigned long long* mm = (unsigned long long*)scr;
+  int* cnt = (int*)((char*)scr + 64);
+  const unsigned long long init[2] = {~0ull, 0ull};
+  QMG_HIP(hipMemcpyAsync(mm, init, sizeof(init), hipMemcpyHostToDevice, s));
+  double* delta = g->stage;  // nslot doubles
+  launch_refine_delta(L, (const double*)F.u, (const double*)F.r, res_tol, delta, mm, s);
+  unsigned long long ext[2];
+  QMG_HIP(hipMemcpyAsync(ext, mm, sizeof(ext), hipMemcpyDeviceToHost, s));
+  QMG_HIP(hipStreamSynchronize(s));
+  int64_t flagged = 0;
+  double lo = 0.0, hi = 0.0;
+  std::memcpy(&lo, &ext[0], sizeof(double));
+  std::memcpy(&hi, &ext[1], sizeof(double));
+  if (ext[0] == ~0ull || hi == 0.0) {  // no candidate, or nothing varies
+    std::memset(cell_flags, 0, (size_t)ncell);
+  } else {
+    const int spread = hi > lo ? 1 : 0;
+    const double width = (hi - lo) / 10.0;
+    launch_zero<int>(cnt, 10, s);
+    launch_refine_hist(L, delta, lo, width, spread, cnt, s);
+    int counts[10];
+    QMG_HIP(hipMemcpyAsync(counts, cnt, sizeof(counts), hipMemcpyDeviceToHost, s));
+    QMG_HIP(hipStreamSynchronize(s));
+    int64_t ncand = 0;
+    for (int b = 0; b < 10; ++b) ncand += counts[b];
+    const double need = fraction * (double)ncand;
+    int64_t cum = 0;
+    int kstar = 9;
+    for (int b = 9; b >= 0; --b) {
+      cum += counts[b];
+      kstar = b;
+      if ((double)cum >= need) break;
+    }
+    uint8_t* dflags = (uint8_t*)F.t;  // nslot iterates: at least ncell bytes
+    launch_refine_cells(L, delta, lo, width, spread, kstar, dflags, s);
+    QMG_HIP(hipMemcpyAsync(cell_flags, dflags, (size_t)ncell, hipMemcpyDeviceToHost, s));
+    QMG_HIP(hipStreamSynchronize(s));
+    for (int64_t c = 0; c < ncell; ++c) flagged += cell_flags[c] ? 1 : 0;
+  }
+  if (n_flagged) *n_flagged = flagged;
+}
+
+void refine_flags_check(qmg_grid_t* g, double res_tol, double fraction, uint8_t* cell_flags) {
+  if (!g || !cell_flags) throw ApiError(QMG_EINVAL, "null argument");
+  if (g->adaptive) throw ApiError(QMG_EINVAL, "the refinement criterion runs on regular grids");
+  if (g->mixed) throw ApiError(QMG_EINVAL, "the refinement criterion needs FP64 iterates");
+  if (!(res_tol > 0.0) || !(fraction > 0.0 && fraction <= 1.0))
+    throw ApiError(QMG_EINVAL, "need res_tol > 0 and 0 < fraction <= 1");
+  need_ops(g);
+}
+
+// Scratch of the entry point that allocates nothing: one copy per device,
+// held until the process ends.  Host code never passes `scratch` itself
+// (its name is a host-side stand-in there); it looks up the device address
+// once per device and uses that.
+constexpr size_t kNoAllocScratch = 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+static_assert(kRefineScratch <= kNoAllocScratch, "the refinement criterion fits the scratch at any grid size");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* scratch_on_current_device() {
+  int dev = 0;
+  QMG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw ApiError(QMG_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      throw HipError(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int qmg_refine_flags_noalloc(qmg_grid_t* g, double res_tol, double fraction, uint8_t* cell_flags,
+                             int64_t* n_flagged) {
+  return guard(g, [&] {
+    refine_flags_check(g, res_tol, fraction, cell_flags);
+    int dev = 0, gdev = 0;
+    QMG_HIP(hipGetDevice(&dev));
+    QMG_HIP(hipPointerGetAttribute(&gdev, HIP_POINTER_ATTRIBUTE_DEVICE_ORDINAL, (hipDeviceptr_t)g->base));
+    if (dev != gdev) throw ApiError(QMG_EINVAL, "the grid lives on another device than the current one");
+    refine_flags_with(g, res_tol, fraction, cell_flags, n_flagged, scratch_on_current_device());
+  });
+}
+
 int qmg_refine_flags(qmg_grid_t* g, double res_tol, double fraction, uint8_t* cell_flags, int64_t* n_flagged) {
   return guard(g, [&] {
-    if (!g || !cell_flags) throw ApiError(QMG_EINVAL, "null argument");
-    if (g->adaptive) throw ApiError(QMG_EINVAL, "the refinement criterion runs on regular grids");
-    if (g->mixed) throw ApiError(QMG_EINVAL, "the refinement criterion needs FP64 iterates");
-    if (!(res_tol > 0.0) || !(fraction > 0.0 && fraction <= 1.0))
-      throw ApiError(QMG_EINVAL, "need res_tol > 0 and 0 < fraction <= 1");
-    need_ops(g);
-    LevelBuf& F = g->lv[g->Lmax];
-    const Lat& L = F.L;
-    hipStream_t s = S(g);
-    const int64_t ncell = L.d == 3 ? (int64_t)L.n * L.n * L.n : (int64_t)L.n * L.n;
-    // r = b - A u on the finest level
-    launch_stencil<double>(L, 2, (const double*)F.u, (const double*)F.b, (double*)F.r, eps_of<double>(F), F.A,
-                           0.0, nullptr, nullptr, s);
+    refine_flags_check(g, res_tol, fraction, cell_flags);
     if (!g->rscr) QMG_HIP(hipMalloc(&g->rscr, 256));
-    unsigned long long* mm = (unsigned long long*)g->rscr;
-    int* cnt = (int*)((char*)g->rscr + 64);
-    const unsigned long long init[2] = {~0ull, 0ull};
-    QMG_HIP(hipMemcpyAsync(mm, init, sizeof(init), hipMemcpyHostToDevice, s));
-    double* delta = g->stage;  // nslot doubles
-    launch_refine_delta(L, (const double*)F.u, (const double*)F.r, res_tol, delta, mm, s);
-    unsigned long long ext[2];
-    QMG_HIP(hipMemcpyAsync(ext, mm, sizeof(ext), hipMemcpyDeviceToHost, s));
-    QMG_HIP(hipStreamSynchronize(s));
-    int64_t flagged = 0;
-    double lo = 0.0, hi = 0.0;
-    std::memcpy(&lo, &ext[0], sizeof(double));
-    std::memcpy(&hi, &ext[1], sizeof(double));
-    if (ext[0] == ~0ull || hi == 0.0) {  // no candidate, or nothing varies
-      std::memset(cell_flags, 0, (size_t)ncell);
-    } else {
-      const int spread = hi > lo ? 1 : 0;
-      const double width = (hi - lo) / 10.0;
-      launch_zero<int>(cnt, 10, s);
-      launch_refine_hist(L, delta, lo, width, spread, cnt, s);
-      int counts[10];
-      QMG_HIP(hipMemcpyAsync(counts, cnt, sizeof(counts), hipMemcpyDeviceToHost, s));
-      QMG_HIP(hipStreamSynchronize(s));
-      int64_t ncand = 0;
-      for (int b = 0; b < 10; ++b) ncand += counts[b];
-      const double need = fraction * (double)ncand;
-      int64_t cum = 0;
-      int kstar = 9;
-      for (int b = 9; b >= 0; --b) {
-        cum += counts[b];
-        kstar = b;
-        if ((double)cum >= need) break;
-      }
-      uint8_t* dflags = (uint8_t*)F.t;  // nslot iterates: at least ncell bytes
-      launch_refine_cells(L, delta, lo, width, spread, kstar, dflags, s);
-      QMG_HIP(hipMemcpyAsync(cell_flags, dflags, (size_t)ncell, hipMemcpyDeviceToHost, s));
-      QMG_HIP(hipStreamSynchronize(s));
-      for (int64_t c = 0; c < ncell; ++c) flagged += cell_flags[c] ? 1 : 0;
-    }
-    if (n_flagged) *n_flagged = flagged;
+    refine_flags_with(g, res_tol, fraction, cell_flags, n_flagged, g->rscr);
   });
 }
 

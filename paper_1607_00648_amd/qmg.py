@@ -101,6 +101,7 @@ _SIGS = {
     "qmg_get_operator": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "qmg_get_prolongation": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "qmg_refine_flags": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.POINTER(C.c_int64)]),
+    "qmg_refine_flags_noalloc": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.POINTER(C.c_int64)]),
     "qmg_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "qmg_server_create": (C.c_int, [C.c_size_t, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
     "qmg_server_submit": (C.c_int, [C.c_void_p, C.POINTER(GridDesc), C.POINTER(SolverOpts), C.c_void_p,
@@ -370,14 +371,16 @@ class Grid:
         self._check(self.lib.qmg_get_operator(self.h, int(level), _ptr(out)), self.h)
         return out
 
-    def refine_flags(self, res_tol: float = 1e-2, fraction: float = 0.1) -> np.ndarray:
+    def refine_flags(self, res_tol: float = 1e-2, fraction: float = 0.1, noalloc: bool = False) -> np.ndarray:
         """Cells of the finest level flagged by the refinement criterion, as a
-        boolean array of shape (3^L,)*d (NumPy axes (z,) y, x)."""
+        boolean array of shape (3^L,)*d (NumPy axes (z,) y, x).  ``noalloc``
+        takes the entry point that allocates no device memory."""
         n = 3 ** self.level
         out = np.zeros((n,) * self.dim, dtype=np.uint8)
         cnt = C.c_int64(0)
-        self._check(self.lib.qmg_refine_flags(self.h, float(res_tol), float(fraction),
-                                              out.ctypes.data_as(C.c_void_p), C.byref(cnt)), self.h)
+        fn = self.lib.qmg_refine_flags_noalloc if noalloc else self.lib.qmg_refine_flags
+        self._check(fn(self.h, float(res_tol), float(fraction), out.ctypes.data_as(C.c_void_p), C.byref(cnt)),
+                    self.h)
         assert int(cnt.value) == int(out.sum())
         return out.astype(bool)
 

@@ -73,23 +73,27 @@ def run_variant(qmg, problem, transfer, store, steps, warmup, tol=1e-8, profile=
     lat = []
     updates = 0
     reps = []
-    for it in range(warmup + steps):
-        if it == warmup:
-            torch.cuda.synchronize()
-            if profile:
-                g.profile_read()     # count the timed steps only
-            t_start = time.perf_counter()
-        t0 = time.perf_counter()
-        g.set_coefficients(eps, f)
-        g.build()
-        rep, _ = g.solve(tol, 2000)
-        t1 = time.perf_counter()
-        if rep["status"] != "QMG_OK":
-            raise RuntimeError(f"solve did not converge: {rep}")
-        if it >= warmup:
-            lat.append(t1 - t0)
-            updates += rep["vertex_updates"]
-            reps.append(rep)
+    try:
+        for it in range(warmup + steps):
+            if it == warmup:
+                torch.cuda.synchronize()
+                if profile:
+                    g.profile_read()     # count the timed steps only
+                t_start = time.perf_counter()
+            t0 = time.perf_counter()
+            g.set_coefficients(eps, f)
+            g.build()
+            rep, _ = g.solve(tol, 2000)
+            t1 = time.perf_counter()
+            if rep["status"] != "QMG_OK":
+                raise RuntimeError(f"solve did not converge: {rep}")
+            if it >= warmup:
+                lat.append(t1 - t0)
+                updates += rep["vertex_updates"]
+                reps.append(rep)
+    except Exception:
+        g.close()
+        raise
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     launches, ms = g.profile_read() if profile else (0, 0.0)
@@ -588,7 +592,13 @@ def roofline_sweep(qmg, W, spec, profile_every, ceiling):
         dim, level = (int(x) for x in item.split(":"))
         q = W.random_checkerboard(dim, level, 0, name=f"jump{dim}d-L{level}")
         for store in ("hier64", "plain64", "bf16"):
-            r = run_variant(qmg, q, "boxmg", store, 2, 1, profile=profile_every or 8)
+            try:
+                r = run_variant(qmg, q, "boxmg", store, 2, 1, profile=profile_every or 8)
+            except qmg.QmgError as e:
+                sweep.append({"dim": dim, "level": level, "unknowns": q.n_unknowns, "store": store,
+                              "error": str(e)})
+                print(f"sweep {dim}D L{level} {store}: {e}", file=sys.stderr, flush=True)
+                continue
             avg = r["kernel_ms"] / max(r["kernel_launches"], 1) / 1e3
             ops = TIMED_OPS[dim]
             op_b = OP_BYTES[(store, dim)] * ops * q.n_unknowns

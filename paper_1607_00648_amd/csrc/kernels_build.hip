@@ -556,6 +556,170 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
   }
 }
 
+// Galerkin product from a rediscretised 3D fine operator (the finest level),
+// cell by cell.  The fine operator is the sum over fine cells e of
+// h eps_e K, with K the Q1 reference element matrix (kref by the number of
+// coordinates in which two corners differ), restricted to the rows m(a) = 1
+// of vertices that have one (leaf vertices of an adaptive level; every
+// interior vertex of a regular one), so
+//   A_c(V,W) = sum_e h eps_e sum_{a,b in e} P(a,V) m(a) K(a,b) P(b,W).
+// This is P^T A P of the row form: every fine cell that touches a vertex of
+// V's support (within 2 of 3V) lies among the 6^3 cells around 3V.
+// One workgroup per coarse vertex V.  The prolongation weights of the 7^3
+// fine vertices around 3V (all eight parents), the 6^3 cell coefficients and
+// the row mask are staged in LDS with row-contiguous loads; then
+//   t(j)     = sum_{e containing j} h eps_e sum_{a in e} pv(a) K(a,j),
+//              pv(a) = P(a,V) m(a)                             (343 j)
+//   A_c(V,W) = sum_j t(j) P(j,W)                               (27 W, each
+//              split over the five planes of j and added in order).
+// Every sum runs in a fixed order, so results are bitwise reproducible.
+constexpr int kRfR = 7;                  // region width (vertices) per axis
+constexpr int kRfNR = kRfR * kRfR * kRfR;  // 343 region vertices
+constexpr int kRfNT = 256;
+constexpr int kRfLoads = (8 * kRfNR + kRfNT - 1) / kRfNT;
+
+__global__ __launch_bounds__(kRfNT) void k_rap_fine3(Lat Lf, Lat Lc, const double* __restrict__ eps,
+                                                     const double* __restrict__ Pw,
+                                                     const int8_t* __restrict__ vt_fine,
+                                                     double* __restrict__ Ac, const int8_t* __restrict__ vtc,
+                                                     const int32_t* __restrict__ vlist, int64_t nlist) {
+  __shared__ double pw[8 * kRfNR];  // [parent kappa][region vertex], x fastest
+  __shared__ double ec[216];        // cells with low corner 3V + [-3, 2]^3
+  __shared__ double pv[kRfNR];      // P(a,V) m(a); zero beyond 2 of 3V
+  __shared__ double tj[kRfNR];
+  __shared__ double tpart[27 * 5];
+  const int m = Lc.n - 1;
+  const int t = threadIdx.x;
+  const int64_t idx = blockIdx.x;
+  const int64_t nV = vlist ? nlist : (int64_t)m * m * m;
+  if (idx >= nV) return;  // uniform over the workgroup
+  const int64_t vv = vlist ? (int64_t)vlist[idx] : idx;
+  const int Vx = (int)(vv % m) + 1, Vy = (int)((vv / m) % m) + 1, Vz = (int)(vv / ((int64_t)m * m)) + 1;
+  const int64_t vc = Vx + (int64_t)Vy * Lc.pitch + (int64_t)Vz * Lc.plane;
+  const bool form = vtc == nullptr || vtc[vc] == VT_REFINED;
+  if (!form) {  // a listed vertex that is not refined keeps a zero row
+    if (t < 27) Ac[(int64_t)t * Lc.nslot + vc] = 0.0;
+    return;
+  }
+  // region origin: fine vertex 3V - 3 per axis (inside the lattice: V >= 1)
+  const int64_t r0 = (3 * Vx - 3) + (int64_t)(3 * Vy - 3) * Lf.pitch + (int64_t)(3 * Vz - 3) * Lf.plane;
+  // stage the weights of all eight parents of every region vertex
+  {
+    double w[kRfLoads];
+#pragma unroll
+    for (int r = 0; r < kRfLoads; ++r) {
+      const int e = t + r * kRfNT;
+      w[r] = 0.0;
+      if (e < 8 * kRfNR) {
+        const int kap = e / kRfNR, q = e - kap * kRfNR;
+        const int qx = q % kRfR, qy = (q / kRfR) % kRfR, qz = q / (kRfR * kRfR);
+        if (Pw) {
+          w[r] = Pw[(int64_t)kap * Lf.nslot + r0 + qx + (int64_t)qy * Lf.pitch + (int64_t)qz * Lf.plane];
+        } else {  // d-linear: parent floor(j/3) + kappa, j = 3V - 3 + q
+          w[r] = dlin1(qx % 3, kap & 1) * dlin1(qy % 3, (kap >> 1) & 1) * dlin1(qz % 3, kap >> 2);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kRfLoads; ++r) {
+      const int e = t + r * kRfNT;
+      if (e < 8 * kRfNR) pw[e] = w[r];
+    }
+  }
+  if (t < 216) {
+    const int cx = t % 6, cy = (t / 6) % 6, cz = t / 36;
+    ec[t] = eps[r0 + cx + (int64_t)cy * Lf.pitch + (int64_t)cz * Lf.plane];
+  }
+  int8_t cls[2] = {VT_LEAF, VT_LEAF};
+  if (vt_fine) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int q = t + r * kRfNT;
+      if (q < kRfNR) {
+        const int qx = q % kRfR, qy = (q / kRfR) % kRfR, qz = q / (kRfR * kRfR);
+        cls[r] = vt_fine[r0 + qx + (int64_t)qy * Lf.pitch + (int64_t)qz * Lf.plane];
+      }
+    }
+  }
+  __syncthreads();
+  // pv(a) = P(a, V) m(a) for a = 3V + o, |o| <= 2 per axis: V is parent
+  // kappa = -floor(o / 3) of a (1 for o < 0, else 0)
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int q = t + r * kRfNT;
+    if (q < kRfNR) {
+      const int ox = q % kRfR - 3, oy = (q / kRfR) % kRfR - 3, oz = q / (kRfR * kRfR) - 3;
+      double p = 0.0;
+      const bool has_row = cls[r] == VT_LEAF || cls[r] == VT_REFINED;
+      if (ox >= -2 && ox <= 2 && oy >= -2 && oy <= 2 && oz >= -2 && oz <= 2 && has_row) {
+        const int kap = (ox < 0 ? 1 : 0) | (oy < 0 ? 2 : 0) | (oz < 0 ? 4 : 0);
+        p = pw[kap * kRfNR + q];
+      }
+      pv[q] = p;
+    }
+  }
+  __syncthreads();
+  // t(j): the cells e = j - c (c in {0,1}^3) inside the 6^3 region; corner
+  // c' of e is a = j - c + c', which differs from j in popcount(c ^ c')
+  // coordinates
+  constexpr double kd = kref(3, 0), kf = kref(3, 2), kb = kref(3, 3);
+  for (int q = t; q < kRfNR; q += kRfNT) {
+    const int qx = q % kRfR, qy = (q / kRfR) % kRfR, qz = q / (kRfR * kRfR);
+    const int jx = 3 * Vx - 3 + qx, jy = 3 * Vy - 3 + qy, jz = 3 * Vz - 3 + qz;
+    double acc = 0.0;
+    if (interior(Lf, jx, jy, jz)) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int ex = qx - (c & 1), ey = qy - ((c >> 1) & 1), ez = qz - (c >> 2);
+        if (ex < 0 || ex > 5 || ey < 0 || ey > 5 || ez < 0 || ez > 5) continue;
+        const int a0 = ex + kRfR * (ey + kRfR * ez);  // region index of the cell's low corner
+        double s = 0.0;
+#pragma unroll
+        for (int c2 = 0; c2 < 8; ++c2) {
+          const int nd = __builtin_popcount(c ^ c2);
+          if (nd == 1) continue;  // the edge entries of the 3D Q1 element vanish
+          const double k = nd == 0 ? kd : (nd == 2 ? kf : kb);
+          s += k * pv[a0 + (c2 & 1) + kRfR * (((c2 >> 1) & 1) + kRfR * (c2 >> 2))];
+        }
+        // cells with no row corner add nothing (their coefficient may be unset)
+        acc += (s != 0.0) ? ec[ex + 6 * (ey + 6 * ez)] * s : 0.0;
+      }
+      acc *= Lf.h;
+    }
+    tj[q] = acc;
+  }
+  __syncthreads();
+  // A_c(V, W), W = V + d: the j = 3V + o within 2 of 3W, split over planes
+  if (t < 27 * 5) {
+    const int w = t / 5, part = t % 5;
+    const int dx = off_x(w), dy = off_y(w), dz = off_z(w);
+    double acc = 0.0;
+    if (interior(Lc, Vx + dx, Vy + dy, Vz + dz)) {
+      const int xl = max(3 * dx - 2, -3), xh = min(3 * dx + 2, 3);
+      const int yl = max(3 * dy - 2, -3), yh = min(3 * dy + 2, 3);
+      const int zl = max(3 * dz - 2, -3) + part;
+      const int zh = min(min(3 * dz + 2, 3), zl);
+      for (int oz = zl; oz <= zh; ++oz)
+        for (int oy = yl; oy <= yh; ++oy)
+#pragma unroll 5
+          for (int ox = xl; ox <= xh; ++ox) {
+            const int q = (ox + 3) + kRfR * ((oy + 3) + kRfR * (oz + 3));
+            // W's parent index at j: d - floor(o / 3) per axis
+            const int kx = dx - (ox + 3) / 3 + 1, ky = dy - (oy + 3) / 3 + 1, kz = dz - (oz + 3) / 3 + 1;
+            acc += tj[q] * pw[(kx | (ky << 1) | (kz << 2)) * kRfNR + q];
+          }
+    }
+    tpart[t] = acc;
+  }
+  __syncthreads();
+  if (t < 27) {
+    double acc = 0.0;
+#pragma unroll
+    for (int p = 0; p < 5; ++p) acc += tpart[t * 5 + p];
+    Ac[(int64_t)t * Lc.nslot + vc] = acc;
+  }
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_check_rows(Lat Lc, const double* __restrict__ Ac,
                                                     int* __restrict__ bad) {
@@ -934,6 +1098,10 @@ void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double*
     PFetch<2> P{Pw, Lf, Lc};
     hipLaunchKernelGGL(k_rap<2>, dim3(blocks_for(nV, S::VPB)), dim3(S::NT), 0, s, Lf, Lc, A, P, Ac, vt_coarse,
                        verts, n_verts, rmode);
+  } else if (Afine == nullptr && rmode == 0) {
+    // rediscretised fine operator: the cell-by-cell product
+    hipLaunchKernelGGL(k_rap_fine3, dim3((unsigned)nV), dim3(kRfNT), 0, s, Lf, Lc, epsf, Pw, vt_fine, Ac,
+                       vt_coarse, verts, n_verts);
   } else {
     using S = RapShape<3>;
     BoxFetch<3> A{Afine, epsf, Lf, vt_fine};

@@ -32,12 +32,22 @@ struct ApiError : std::runtime_error {
   ApiError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
-#define QMG_HIP(call)                                                                  \
-  do {                                                                                 \
-    hipError_t e_ = (call);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      throw ::qmg::HipError(std::string(#call) + ": " + hipGetErrorString(e_));        \
+#define QMG_STR2_(x) #x
+#define QMG_STR_(x) QMG_STR2_(x)
+#define QMG_HIP(call)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      throw ::qmg::HipError(std::string(#call) + " [" + ::qmg::src_name(__FILE__) +            \
+                            ":" QMG_STR_(__LINE__) "]: " + hipGetErrorString(e_));             \
   } while (0)
+
+inline const char* src_name(const char* path) {
+  const char* b = path;
+  for (const char* p = path; *p; ++p)
+    if (*p == '/') b = p + 1;
+  return b;
+}
 
 // ---------------------------------------------------------------------------
 // Lattice of one regular level.  Vertex (i,j,k), 0 <= i,j,k <= n, lives at slot

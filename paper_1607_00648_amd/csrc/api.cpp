@@ -197,6 +197,10 @@ void set_err(qmg_grid_t* g, const std::string& m) {
 template <class F>
 int guard(qmg_grid_t* g, F&& f) {
   try {
+    // The launch checks below read the thread's last HIP error; one left
+    // behind by other code on this thread (the caller's own HIP calls) is not
+    // this call's, so it is cleared first.
+    (void)hipGetLastError();
     f();
     return QMG_OK;
   } catch (const ApiError& e) {
@@ -821,14 +825,16 @@ int choose_fused_top(qmg_grid_t* g, bool& pw_lds) {
   int best = -1;
   if (g->opts.restriction != QMG_R_TRANSPOSE) return best;  // the fused cycle restricts with P^T
   for (int lf = g->lc; lf < g->lb && lf - g->lc + 1 <= kMaxFused; ++lf) {
-    for (int pl = 1; pl >= 0; --pl) {
+    bool fits = false;
+    for (int pl = 1; pl >= 0 && !fits; --pl) {
       FusedArgs<T> a = fused_args<T>(g, lf);
-      if ((int64_t)fused_lds_layout<T>(g->d, a, p_stored(g), pl == 1) <= g->lds_max) {
+      if (fused_lds_layout<T>(g->d, a, p_stored(g), pl == 1) <= (size_t)g->lds_max) {
         best = lf;
         pw_lds = pl == 1;
-        break;
+        fits = true;
       }
     }
+    if (!fits) break;  // a larger top level needs more still
   }
   return best;
 }

@@ -568,14 +568,18 @@ __global__ __launch_bounds__(RapShape<D>::NT) void k_rap(Lat Lf, Lat Lc, BoxFetc
 // One workgroup per coarse vertex V.  The prolongation weights of the 7^3
 // fine vertices around 3V (all eight parents), the 6^3 cell coefficients and
 // the row mask are staged in LDS with row-contiguous loads; then
-//   t(j)     = sum_{e containing j} h eps_e sum_{a in e} pv(a) K(a,j),
+//   t(j)     = sum_{a} pv(a) sum_{e containing a and j} h eps_e K(a,j),
 //              pv(a) = P(a,V) m(a)                             (343 j)
 //   A_c(V,W) = sum_j t(j) P(j,W)                               (27 W, each
 //              split over the five planes of j and added in order).
+// In t(j) the 3D Q1 element couples j with itself (all 8 cells), with its 12
+// face-diagonal neighbours (the 2 cells they share) and its 8 body-diagonal
+// neighbours (1 cell); its edge neighbours have K = 0.
 // Every sum runs in a fixed order, so results are bitwise reproducible.
-constexpr int kRfR = 7;                  // region width (vertices) per axis
+constexpr int kRfR = 7;                    // region width (vertices) per axis
 constexpr int kRfNR = kRfR * kRfR * kRfR;  // 343 region vertices
-constexpr int kRfNT = 256;
+constexpr int kRfP = kRfR + 2;             // pv with a zero border of one
+constexpr int kRfNT = 384;
 constexpr int kRfLoads = (8 * kRfNR + kRfNT - 1) / kRfNT;
 
 __global__ __launch_bounds__(kRfNT) void k_rap_fine3(Lat Lf, Lat Lc, const double* __restrict__ eps,
@@ -583,14 +587,16 @@ __global__ __launch_bounds__(kRfNT) void k_rap_fine3(Lat Lf, Lat Lc, const doubl
                                                      const int8_t* __restrict__ vt_fine,
                                                      double* __restrict__ Ac, const int8_t* __restrict__ vtc,
                                                      const int32_t* __restrict__ vlist, int64_t nlist) {
-  __shared__ double pw[8 * kRfNR];  // [parent kappa][region vertex], x fastest
-  __shared__ double ec[216];        // cells with low corner 3V + [-3, 2]^3
-  __shared__ double pv[kRfNR];      // P(a,V) m(a); zero beyond 2 of 3V
+  __shared__ double pw[8 * kRfNR];             // [parent kappa][region vertex], x fastest
+  __shared__ double ec[216];                   // cells with low corner 3V + [-3, 2]^3
+  __shared__ double pv[kRfP * kRfP * kRfP];    // P(a,V) m(a), zero beyond 2 of 3V
   __shared__ double tj[kRfNR];
-  __shared__ double tpart[27 * 5];
+  double* const tpart = pv;  // 27 * 5 partial sums, once pv is no longer read
   const int m = Lc.n - 1;
   const int t = threadIdx.x;
-  const int64_t idx = blockIdx.x;
+  // a 2D grid of workgroups (x fastest): one dimension of a launch is
+  // limited to 2^32 work-items, which a regular level-5 list exceeds
+  const int64_t idx = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
   const int64_t nV = vlist ? nlist : (int64_t)m * m * m;
   if (idx >= nV) return;  // uniform over the workgroup
   const int64_t vv = vlist ? (int64_t)vlist[idx] : idx;
@@ -630,63 +636,63 @@ __global__ __launch_bounds__(kRfNT) void k_rap_fine3(Lat Lf, Lat Lc, const doubl
     const int cx = t % 6, cy = (t / 6) % 6, cz = t / 36;
     ec[t] = eps[r0 + cx + (int64_t)cy * Lf.pitch + (int64_t)cz * Lf.plane];
   }
-  int8_t cls[2] = {VT_LEAF, VT_LEAF};
-  if (vt_fine) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int q = t + r * kRfNT;
-      if (q < kRfNR) {
-        const int qx = q % kRfR, qy = (q / kRfR) % kRfR, qz = q / (kRfR * kRfR);
-        cls[r] = vt_fine[r0 + qx + (int64_t)qy * Lf.pitch + (int64_t)qz * Lf.plane];
-      }
-    }
+  for (int q = t; q < kRfP * kRfP * kRfP; q += kRfNT) pv[q] = 0.0;
+  int8_t cls = VT_LEAF;
+  if (vt_fine && t < kRfNR) {
+    const int qx = t % kRfR, qy = (t / kRfR) % kRfR, qz = t / (kRfR * kRfR);
+    cls = vt_fine[r0 + qx + (int64_t)qy * Lf.pitch + (int64_t)qz * Lf.plane];
   }
   __syncthreads();
   // pv(a) = P(a, V) m(a) for a = 3V + o, |o| <= 2 per axis: V is parent
   // kappa = -floor(o / 3) of a (1 for o < 0, else 0)
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int q = t + r * kRfNT;
-    if (q < kRfNR) {
-      const int ox = q % kRfR - 3, oy = (q / kRfR) % kRfR - 3, oz = q / (kRfR * kRfR) - 3;
-      double p = 0.0;
-      const bool has_row = cls[r] == VT_LEAF || cls[r] == VT_REFINED;
-      if (ox >= -2 && ox <= 2 && oy >= -2 && oy <= 2 && oz >= -2 && oz <= 2 && has_row) {
-        const int kap = (ox < 0 ? 1 : 0) | (oy < 0 ? 2 : 0) | (oz < 0 ? 4 : 0);
-        p = pw[kap * kRfNR + q];
-      }
-      pv[q] = p;
+  if (t < kRfNR) {
+    const int qx = t % kRfR, qy = (t / kRfR) % kRfR, qz = t / (kRfR * kRfR);
+    const int ox = qx - 3, oy = qy - 3, oz = qz - 3;
+    const bool has_row = cls == VT_LEAF || cls == VT_REFINED;
+    if (ox >= -2 && ox <= 2 && oy >= -2 && oy <= 2 && oz >= -2 && oz <= 2 && has_row) {
+      const int kap = (ox < 0 ? 1 : 0) | (oy < 0 ? 2 : 0) | (oz < 0 ? 4 : 0);
+      pv[(qx + 1) + kRfP * ((qy + 1) + kRfP * (qz + 1))] = pw[kap * kRfNR + t];
     }
   }
   __syncthreads();
-  // t(j): the cells e = j - c (c in {0,1}^3) inside the 6^3 region; corner
-  // c' of e is a = j - c + c', which differs from j in popcount(c ^ c')
-  // coordinates
-  constexpr double kd = kref(3, 0), kf = kref(3, 2), kb = kref(3, 3);
-  for (int q = t; q < kRfNR; q += kRfNT) {
-    const int qx = q % kRfR, qy = (q / kRfR) % kRfR, qz = q / (kRfR * kRfR);
+  if (t < kRfNR) {
+    const int qx = t % kRfR, qy = (t / kRfR) % kRfR, qz = t / (kRfR * kRfR);
     const int jx = 3 * Vx - 3 + qx, jy = 3 * Vy - 3 + qy, jz = 3 * Vz - 3 + qz;
     double acc = 0.0;
     if (interior(Lf, jx, jy, jz)) {
+      // coefficient of cell j - c (c in {0,1}^3), zero outside the staged cells
+      double E[8];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int ex = qx - (c & 1), ey = qy - ((c >> 1) & 1), ez = qz - (c >> 2);
-        if (ex < 0 || ex > 5 || ey < 0 || ey > 5 || ez < 0 || ez > 5) continue;
-        const int a0 = ex + kRfR * (ey + kRfR * ez);  // region index of the cell's low corner
-        double s = 0.0;
+        E[c] = (ex >= 0 && ex <= 5 && ey >= 0 && ey <= 5 && ez >= 0 && ez <= 5) ? ec[ex + 6 * (ey + 6 * ez)]
+                                                                                : 0.0;
+      }
+      const int j0 = (qx + 1) + kRfP * ((qy + 1) + kRfP * (qz + 1));
+      double sE = 0.0;
 #pragma unroll
-        for (int c2 = 0; c2 < 8; ++c2) {
-          const int nd = __builtin_popcount(c ^ c2);
-          if (nd == 1) continue;  // the edge entries of the 3D Q1 element vanish
-          const double k = nd == 0 ? kd : (nd == 2 ? kf : kb);
-          s += k * pv[a0 + (c2 & 1) + kRfR * (((c2 >> 1) & 1) + kRfR * (c2 >> 2))];
+      for (int c = 0; c < 8; ++c) sE += E[c];
+      acc = kref(3, 0) * pv[j0] * sE;
+      // neighbour j + delta, delta in {-1,0,1}^3: a cell j - c holds it when
+      // c = 1 on the axes with delta = -1 and c = 0 where delta = +1
+#pragma unroll
+      for (int k = 0; k < 27; ++k) {
+        const int dx = off_x(k), dy = off_y(k), dz = off_z(k);
+        const int nd = (dx != 0) + (dy != 0) + (dz != 0);
+        if (nd < 2) continue;  // the centre is done; edge neighbours have K = 0
+        double es = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+          const bool holds = (dx == 0 || cx == (dx < 0 ? 1 : 0)) && (dy == 0 || cy == (dy < 0 ? 1 : 0)) &&
+                             (dz == 0 || cz == (dz < 0 ? 1 : 0));
+          if (holds) es += E[c];
         }
-        // cells with no row corner add nothing (their coefficient may be unset)
-        acc += (s != 0.0) ? ec[ex + 6 * (ey + 6 * ez)] * s : 0.0;
+        acc += kref(3, nd) * pv[j0 + dx + kRfP * (dy + kRfP * dz)] * es;
       }
       acc *= Lf.h;
     }
-    tj[q] = acc;
+    tj[t] = acc;
   }
   __syncthreads();
   // A_c(V, W), W = V + d: the j = 3V + o within 2 of 3W, split over planes
@@ -1100,8 +1106,9 @@ void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double*
                        verts, n_verts, rmode);
   } else if (Afine == nullptr && rmode == 0) {
     // rediscretised fine operator: the cell-by-cell product
-    hipLaunchKernelGGL(k_rap_fine3, dim3((unsigned)nV), dim3(kRfNT), 0, s, Lf, Lc, epsf, Pw, vt_fine, Ac,
-                       vt_coarse, verts, n_verts);
+    const int64_t gx = std::min<int64_t>(nV, 65536);
+    hipLaunchKernelGGL(k_rap_fine3, dim3((unsigned)gx, (unsigned)((nV + gx - 1) / gx)), dim3(kRfNT), 0, s, Lf, Lc,
+                       epsf, Pw, vt_fine, Ac, vt_coarse, verts, n_verts);
   } else {
     using S = RapShape<3>;
     BoxFetch<3> A{Afine, epsf, Lf, vt_fine};

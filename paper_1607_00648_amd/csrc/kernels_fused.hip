@@ -14,7 +14,9 @@
 // are decoded once per build into an image of the LDS contents in global
 // memory; each launch copies that image in with 16-byte loads.
 #include "level_ops.hpp"
+#include <algorithm>
 #include <atomic>
+#include <cstdint>
 #include <mutex>
 
 namespace qmg {
@@ -348,7 +350,10 @@ __global__ __launch_bounds__(block_of<D>()) void k_fused_prepare(FusedArgs<T> a)
 // device maximum (never lowered) under a lock, and a per-device bit records
 // it.  The first call for an instance comes from the build (launch with
 // prepare set), outside any stream capture.
-template <typename Kern>
+// The tag makes every kernel instance its own template instance, so that
+// each keeps its own per-device bits (the kernel pointers of one iterate type
+// share a function type).
+template <typename Tag, typename Kern>
 void lds_optin_once(Kern kernel) {
   static std::mutex mu;
   static std::atomic<uint64_t> done{0};
@@ -368,8 +373,11 @@ void lds_optin_once(Kern kernel) {
 }
 
 template <int D, typename T, int AS, int PS, int F>
+struct FusedTag {};
+
+template <int D, typename T, int AS, int PS, int F>
 void launch_one(const FusedArgs<T>& a, hipStream_t s, bool prepare) {
-  lds_optin_once(k_fused_coarse<D, T, AS, PS, F>);
+  lds_optin_once<FusedTag<D, T, AS, PS, F>>(k_fused_coarse<D, T, AS, PS, F>);
   if (prepare) {
     hipLaunchKernelGGL((k_fused_prepare<D, T, AS, PS, F>), dim3(1), dim3(block_of<D>()), 0, s, a);
     return;
@@ -379,6 +387,11 @@ void launch_one(const FusedArgs<T>& a, hipStream_t s, bool prepare) {
 
 template <int D, typename T>
 void dispatch_fused(const FusedArgs<T>& a, int asrc, int psrc, int fmt, hipStream_t s, bool prep) {
+  {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+      throw HipError(std::string("error pending before the fused coarse launch: ") + hipGetErrorString(e));
+  }
   if (asrc == SRC_PLAIN) {
     launch_one<D, T, SRC_PLAIN, SRC_PLAIN, F64>(a, s, prep);
   } else if (asrc == SRC_GEOM) {
@@ -408,19 +421,25 @@ size_t fused_lds_layout(int d, FusedArgs<T>& a, bool p_stored, bool pw_lds) {
     return p;
   };
   const int NS = d == 2 ? 9 : 27, NC = 1 << d;
+  // sizes in 64 bits: the candidate levels of a large grid exceed any LDS by
+  // far, and their layout is only measured, never launched
   for (int s = 0; s <= a.lf - a.lc; ++s) {
-    const int w = a.L[s].n + 1, m = a.L[s].n - 1;
-    const int nsl = d == 3 ? w * w * w : w * w;
-    const int nin = d == 3 ? m * m * m : m * m;
-    a.lds_nslot[s] = nsl;
+    const int64_t w = a.L[s].n + 1, m = a.L[s].n - 1;
+    const int64_t nsl = d == 3 ? w * w * w : w * w;
+    const int64_t nin = d == 3 ? m * m * m : m * m;
+    a.lds_nslot[s] = (int)std::min<int64_t>(nsl, INT32_MAX);
     a.mag[s] = 0xFFFFFFFFu / (unsigned)m + 1u;
-    a.lds_vec[s] = (int)take((size_t)4 * nsl * sizeof(T));
-    a.lds_rows[s] = (int)take((size_t)nin * NS * sizeof(T));
-    a.lds_pw[s] = (s >= 1 && p_stored && pw_lds) ? (int)take((size_t)nsl * NC * sizeof(T)) : 0;
+    const size_t pv = take((size_t)4 * nsl * sizeof(T));
+    const size_t pr = take((size_t)nin * NS * sizeof(T));
+    const size_t pp = (s >= 1 && p_stored && pw_lds) ? take((size_t)nsl * NC * sizeof(T)) : 0;
+    a.lds_vec[s] = (int)std::min<size_t>(pv, INT32_MAX);
+    a.lds_rows[s] = (int)std::min<size_t>(pr, INT32_MAX);
+    a.lds_pw[s] = (int)std::min<size_t>(pp, INT32_MAX);
   }
   a.pw_lds = pw_lds ? 1 : 0;
-  a.lds_bytes = (int)((off + 15) & ~size_t(15));
-  return (size_t)a.lds_bytes;
+  const size_t total = (off + 15) & ~size_t(15);
+  a.lds_bytes = (int)std::min<size_t>(total, INT32_MAX);
+  return total;
 }
 template size_t fused_lds_layout<double>(int, FusedArgs<double>&, bool, bool);
 template size_t fused_lds_layout<float>(int, FusedArgs<float>&, bool, bool);

@@ -319,11 +319,58 @@ def measured_traffic(key):
     e = tab.get("entries", {}).get(key)
     if not e:
         return None
-    src = open(os.path.join(ROOT, "paper_1607_00648_amd", "csrc", e["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest()[:16] != e["source_sha16"]:
+    if "sources" not in e or sources_sha16(e["sources"]) != e["sources_sha16"]:
         return None
     cal = tab["calibration"]
     return (e["fetch_kib"] * cal["fetch_factor"] + e["write_kib"] * cal["write_factor"]) * 1024.0
+
+
+def sources_sha16(names):
+    """Hash of the library sources a kernel's code depends on."""
+    import hashlib
+    h = hashlib.sha256()
+    for nm in names:
+        h.update(open(os.path.join(ROOT, "paper_1607_00648_amd", "csrc", nm), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def record_traffic(fetch_csv, write_csv, key, kernel_name, calib_mib, sources, profile):
+    """Writes one entry of the counter table from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE; counter_collection.csv).  The first
+    device copy in each run is the calibration copy of calib_mib MiB; the
+    entry holds the kernel's mean KiB per dispatch."""
+    import csv
+
+    def read(path, counter):
+        copy, vals = None, []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            if copy is None and "copyBuffer" in r["Kernel_Name"]:
+                copy = float(r["Counter_Value"])
+            elif kernel_name in r["Kernel_Name"]:
+                vals.append(float(r["Counter_Value"]))
+        if copy is None or not vals:
+            raise SystemExit(f"{path}: no calibration copy or no {kernel_name} dispatch")
+        return copy, sum(vals) / len(vals), len(vals)
+
+    kib = calib_mib * 1024.0
+    fc, fk, nf = read(fetch_csv, "FETCH_SIZE")
+    wc, wk, nw = read(write_csv, "WRITE_SIZE")
+    try:
+        tab = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        tab = {"entries": {}}
+    tab["calibration"] = {"fetch_factor": round(kib / fc, 3), "write_factor": round(kib / wc, 3),
+                          "note": f"{calib_mib} MiB device copy: FETCH_SIZE {fc:.0f} KiB, "
+                                  f"WRITE_SIZE {wc:.0f} KiB"}
+    tab.setdefault("entries", {})[key] = {
+        "fetch_kib": round(fk, 1), "write_kib": round(wk, 1), "dispatches": [nf, nw],
+        "sources": sources, "sources_sha16": sources_sha16(sources), "profile": profile}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(tab, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(tab["entries"][key]))
 
 
 def copy_ceiling(gib=4, reps=5):
@@ -646,7 +693,17 @@ def main():
                     help="extra stores timed on the 2D checkerboard workload (comma list, '' for none)")
     ap.add_argument("--others", type=int, default=50, metavar="N",
                     help="repeated solves of the other single-grid workloads (0: skip)")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the counter-table entry of the headline sweep kernel from two "
+                         "rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) made with --calibrate-copy 256, "
+                         "then exit (no GPU use)")
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(args.record_traffic[0], args.record_traffic[1],
+                       f"k_ad_march:band3d_L{args.level}:{args.store}", "k_ad_march<float, float, 0, 0, 0>(", 256,
+                       ["kernels_adaptive.hip", "qmg_internal.hpp", "device_ops.hpp"],
+                       f"profiles/band3d_L{args.level}_{args.store}_step_kernel_stats.md")
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver path is "
               f"single-GPU", file=sys.stderr)
@@ -709,7 +766,7 @@ def main():
         "workspace_bytes": res["workspace_bytes"], "bytes_operators": res["bytes_operators"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": measured_traffic(f"k_ad_stencil:band3d_L{P.level}:{args.store}"),
+                     "traffic": measured_traffic(f"k_ad_march:band3d_L{P.level}:{args.store}"),
                      "kernel": AD_SWEEP_KERNEL,
                      "bytes_per_launch": alg,
                      "bytes_per_launch_note": f"{AD_SWEEP_BYTES[args.store]} B per active vertex of the "

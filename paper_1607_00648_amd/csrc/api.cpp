@@ -1409,8 +1409,15 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
       // the finest adaptive level's rows exist only at leaf vertices
       const int8_t* mask = (g->adaptive && l == L && !Afine) ? F.vt : nullptr;
       const bool adc = g->adaptive && l - 1 >= g->lb;
-      launch_rap(F.L, C.L, Afine, F.eps64, Pw, Ac, s, mask, adc ? C.vt : nullptr, adc ? C.rv : nullptr,
-                 adc ? C.nrv : 0, g->opts.restriction);
+      // the finest 3D adaptive level: coarse cell by coarse cell, with the
+      // element matrices in the unused work stencil buffer of level L
+      bool by_cells = false;
+      if (g->d == 3 && adc && l == L && !Afine && g->opts.restriction == QMG_R_TRANSPOSE)
+        by_cells = launch_rap_cells(F.L, C.L, F.eps64, Pw, Ac, s, mask, C.vt, C.rv, C.nrv, C.rc, C.nrc,
+                                    g->tmpA[L & 1], (size_t)NS * g->lv[L - 1].L.nslot * sizeof(double));
+      if (!by_cells)
+        launch_rap(F.L, C.L, Afine, F.eps64, Pw, Ac, s, mask, adc ? C.vt : nullptr, adc ? C.rv : nullptr,
+                   adc ? C.nrv : 0, g->opts.restriction);
       merge(l - 1, Ac);
       // the fallback of a failed check raises the coarsest level, which is
       // possible only below the base level of an adaptive spacetree

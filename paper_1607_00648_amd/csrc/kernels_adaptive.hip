@@ -86,8 +86,9 @@ __global__ __launch_bounds__(256) void k_ad_stencil(Lat L, const int32_t* __rest
   }
 }
 
-// 3D adaptive levels: a workgroup of 64 x 8 threads owns one listed brick of
-// 64 x 8 slots and marches over its 16 interior planes.  Three planes of the
+// 3D adaptive levels: a workgroup of kBrickX x kBrickY threads (32 x 16; a
+// wavefront covers two x-rows) owns one listed brick of as many slots and
+// marches over its 16 interior planes.  Three planes of the
 // iterate (brick plus a halo of one vertex) and two planes of cell
 // coefficients ring through LDS, so each value comes from memory once per
 // brick instead of once per neighbour.  Every thread updates the
@@ -97,8 +98,8 @@ __global__ __launch_bounds__(256) void k_ad_stencil(Lat L, const int32_t* __rest
 // brick list (ordered z, y, x) is cut into eight contiguous ranges, one per
 // XCD, so that neighbouring bricks share an L2.
 constexpr int BX = kBrickX, BY = kBrickY, BZ = kBrickZ;
-constexpr int BUW = BX + 2, BUH = BY + 2;  // iterate plane region: x0-1..x0+64, y0-1..y0+8
-constexpr int BEW = BX + 1, BEH = BY + 1;  // cell plane region: x0-1..x0+63, y0-1..y0+7
+constexpr int BUW = BX + 2, BUH = BY + 2;  // iterate plane region: x0-1..x0+BX, y0-1..y0+BY
+constexpr int BEW = BX + 1, BEH = BY + 1;  // cell plane region: x0-1..x0+BX-1, y0-1..y0+BY-1
 
 template <typename T, typename TO, int SRC, int FMT, int MODE>
 __global__ __launch_bounds__(BX * BY) void k_ad_march(Lat L, const int32_t* __restrict__ bricks, int nb,

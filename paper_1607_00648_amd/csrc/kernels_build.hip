@@ -135,6 +135,24 @@ struct RowSrc {
     for (int s = 0; s < Dim<D>::NC; ++s)
       ce[s] = mode == 2 ? F.eps[v - slot_off(F.L, s & 1, (s >> 1) & 1, (s >> 2) & 1)] : 0.0;
   }
+  // The same row from a workgroup's LDS copy of its coarse cell's data: the
+  // vertex classes of the 4^3 fine vertices of the closed cell (origin 3C)
+  // and the coefficients of the 5^3 fine cells around them (origin 3C - 1);
+  // (lx, ly, lz) = v - 3C.
+  __device__ RowSrc(const BoxFetch<D>& F, const double* ecl, const int8_t* vcl, int lx, int ly, int lz) {
+    bool geo = F.A == nullptr;
+    mode = 1;
+    if (F.vt) {
+      const int8_t t = vcl[lx + 4 * (ly + 4 * lz)];
+      if (F.hanging_rows && t == VT_HANGING) geo = true;
+      else if (t != VT_LEAF && t != VT_REFINED) mode = 0;
+    }
+    if (mode == 1 && geo) mode = 2;
+#pragma unroll
+    for (int s = 0; s < Dim<D>::NC; ++s)
+      ce[s] = mode == 2 ? ecl[(lx + 1 - (s & 1)) + 5 * ((ly + 1 - ((s >> 1) & 1)) + 5 * (lz + 1 - ((s >> 2) & 1)))]
+                        : 0.0;
+  }
   // entry k of the row of v = (i, j, kz); the neighbour must be checked for
   // being interior by the caller when mode == 2
   __device__ double entry(const BoxFetch<D>& F, int64_t v, int k) const {
@@ -162,9 +180,12 @@ struct PCol {
   __device__ double& operator[](int i) const { return base[i * 64]; }
 };
 
+// ecl/vcl (3D): the task's coarse cell data in LDS (see RowSrc), origin 3C
+// at fine vertex (cx0, cy0, cz0)
 template <int D, int S>
 __device__ inline void box_group(const BoxFetch<D>& F, int Vx, int Vy, int Vz, int sx, int sy, int sz,
-                                 const PCol& p) {
+                                 const PCol& p, const double* ecl, const int8_t* vcl, int cx0, int cy0,
+                                 int cz0) {
   // unknowns: y with y_i in {1,2} for i in S, 0 otherwise
   constexpr int m = 1 << ((S & 1) + ((S >> 1) & 1) + ((S >> 2) & 1));
   double M[m][m];
@@ -187,7 +208,8 @@ __device__ inline void box_group(const BoxFetch<D>& F, int Vx, int Vy, int Vz, i
     }
     const int fx = 3 * Vx + sx * y[0], fy = 3 * Vy + sy * y[1], fz = 3 * Vz + sz * y[2];
     const int64_t v = fx + (int64_t)fy * F.L.pitch + (int64_t)fz * F.L.plane;
-    const RowSrc<D> row(F, v);  // the member's row, fetched once
+    // the member's row, fetched once (3D: from the workgroup's LDS copy)
+    const RowSrc<D> row = (D == 3) ? RowSrc<D>(F, ecl, vcl, fx - cx0, fy - cy0, fz - cz0) : RowSrc<D>(F, v);
     // The row in the reference frame: the cell coefficients of a rediscretised
     // row mirrored (axis a flipped: cell bit a flipped), and per axis whether
     // the true neighbour one step back / ahead in the reference frame is an
@@ -310,7 +332,66 @@ __global__ __launch_bounds__(64) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, dou
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int m = Lc.n - 1;
   int orth, Vx, Vy, Vz;
-  if (cells) {
+  __shared__ double pl[27 * 64];
+  const double* ecl = nullptr;
+  const int8_t* vcl = nullptr;
+  int cx0 = 0, cy0 = 0, cz0 = 0;
+  if constexpr (D == 3) {
+    // 3D: the 64 threads are the 8 corners of 8 coarse cells (the listed
+    // ones, or every cell of a regular level); each cell's fine-vertex
+    // classes and fine-cell coefficients are staged in LDS once, instead of
+    // every corner fetching its member rows from global memory
+    __shared__ double ecs[8 * 125];
+    __shared__ int8_t vcs[8 * 64];
+    __shared__ int cc[8 * 3];
+    const int n = Lc.n, nf = Lf.n;
+    const int lc = threadIdx.x >> 3;
+    const int64_t ci = (int64_t)blockIdx.x * 8 + lc;
+    const int64_t nc = cells ? ncells : (int64_t)n * n * n;
+    bool active = ci < nc;
+    if ((threadIdx.x & 7) == 0) {
+      int x = -1000, y = -1000, z = -1000;  // no cell: nothing staged
+      if (active) {
+        const int64_t c = cells ? (int64_t)cells[ci] : ci;
+        x = (int)(c % n);
+        y = (int)((c / n) % n);
+        z = (int)(c / ((int64_t)n * n));
+      }
+      cc[3 * lc] = x;
+      cc[3 * lc + 1] = y;
+      cc[3 * lc + 2] = z;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 8 * 125; e += 64) {
+      const int k = e / 125, r = e - k * 125;
+      const int fx = 3 * cc[3 * k] - 1 + r % 5, fy = 3 * cc[3 * k + 1] - 1 + (r / 5) % 5,
+                fz = 3 * cc[3 * k + 2] - 1 + r / 25;
+      double v = 0.0;  // cells outside the domain (or of no listed cell) are never read
+      if (fx >= 0 && fx < nf && fy >= 0 && fy < nf && fz >= 0 && fz < nf)
+        v = F.eps[fx + (int64_t)fy * Lf.pitch + (int64_t)fz * Lf.plane];
+      ecs[e] = v;
+    }
+    for (int e = threadIdx.x; e < 8 * 64; e += 64) {
+      const int k = e >> 6, r = e & 63;
+      const int fx = 3 * cc[3 * k] + (r & 3), fy = 3 * cc[3 * k + 1] + ((r >> 2) & 3), fz = 3 * cc[3 * k + 2] + (r >> 4);
+      int8_t v = VT_OUT;
+      if (F.vt && fx >= 0 && fx <= nf && fy >= 0 && fy <= nf && fz >= 0 && fz <= nf)
+        v = F.vt[fx + (int64_t)fy * Lf.pitch + (int64_t)fz * Lf.plane];
+      vcs[e] = v;
+    }
+    __syncthreads();
+    if (!active) return;
+    orth = (int)(threadIdx.x & 7);
+    cx0 = 3 * cc[3 * lc];
+    cy0 = 3 * cc[3 * lc + 1];
+    cz0 = 3 * cc[3 * lc + 2];
+    Vx = cc[3 * lc] + (orth & 1);
+    Vy = cc[3 * lc + 1] + ((orth >> 1) & 1);
+    Vz = cc[3 * lc + 2] + ((orth >> 2) & 1);
+    if (!interior(Lc, Vx, Vy, Vz)) return;
+    ecl = ecs + 125 * lc;
+    vcl = vcs + 64 * lc;
+  } else if (cells) {
     if (t >= ncells * Dim<D>::NC) return;
     orth = (int)(t % Dim<D>::NC);
     const int64_t c = cells[t / Dim<D>::NC];
@@ -330,21 +411,20 @@ __global__ __launch_bounds__(64) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, dou
   }
   const int sx = (orth & 1) ? -1 : 1, sy = (orth & 2) ? -1 : 1, sz = (D == 3 && (orth & 4)) ? -1 : 1;
   if (cref && !orthant_refined(cref, Lc, Vx, Vy, Vz, sx, sy, sz)) return;
-  __shared__ double pl[27 * 64];
   const PCol p{pl + threadIdx.x};
 #pragma unroll
   for (int q = 0; q < 27; ++q) p[q] = 0.0;
   p[0] = 1.0;
-  box_group<D, 1>(F, Vx, Vy, Vz, sx, sy, sz, p);
-  box_group<D, 2>(F, Vx, Vy, Vz, sx, sy, sz, p);
+  box_group<D, 1>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
+  box_group<D, 2>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
   if constexpr (D == 3) {
-    box_group<D, 4>(F, Vx, Vy, Vz, sx, sy, sz, p);
-    box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p);
-    box_group<D, 5>(F, Vx, Vy, Vz, sx, sy, sz, p);
-    box_group<D, 6>(F, Vx, Vy, Vz, sx, sy, sz, p);
-    box_group<D, 7>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    box_group<D, 4>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
+    box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
+    box_group<D, 5>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
+    box_group<D, 6>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
+    box_group<D, 7>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
   } else {
-    box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
   }
   // write the reference region; a point on an axis (y_i = 0) is shared by the
   // orthants that differ only on such axes.  It is written by the one of
@@ -726,6 +806,158 @@ __global__ __launch_bounds__(kRfNT) void k_rap_fine3(Lat Lf, Lat Lc, const doubl
   }
 }
 
+// The same product coarse cell by coarse cell (adaptive levels, where only
+// the refined coarse cells take part).  A coarse cell C holds 27 fine cells
+// and 4^3 fine vertices b (local 0..3 per axis); its element matrix is
+//   A_C(V,W) = sum_b T(b,V) P(b,W),
+//   T(b,V)   = sum_{a in C} P(a,V) m(a) sum_{e in C containing a and b} h eps_e K(a,b),
+// over the corners V, W of C, and the coarse row of V sums the element
+// matrices of its eight cells.  A fine vertex b's parents inside C: along an
+// axis, local 0 is coarse plane C (parent C, kappa 0; the second parent has
+// weight zero), 1 and 2 lie between (kappa 0 and 1), 3 is plane C + 1 (parent
+// C + 1 only, kappa 0).  One workgroup of 64 threads (one per b) per listed
+// cell; 4 KB of fine data per cell instead of 22 KB per coarse vertex.
+__global__ __launch_bounds__(64) void k_rap_cells3(Lat Lf, Lat Lc, const double* __restrict__ eps,
+                                                   const double* __restrict__ Pw,
+                                                   const int8_t* __restrict__ vt_fine,
+                                                   const int32_t* __restrict__ cells, int64_t ncells,
+                                                   double* __restrict__ AC) {
+  __shared__ double P[64 * 8];   // [b][corner]
+  __shared__ double pv[64 * 8];  // P(b, corner) m(b)
+  __shared__ double T[64 * 8];
+  __shared__ double E[27];
+  const int64_t ci = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+  if (ci >= ncells) return;  // uniform over the workgroup
+  const int n = Lc.n;
+  const int64_t c = cells[ci];
+  const int Cx = (int)(c % n), Cy = (int)((c / n) % n), Cz = (int)(c / ((int64_t)n * n));
+  const int t = threadIdx.x;
+  const int lx = t & 3, ly = (t >> 2) & 3, lz = t >> 4;
+  const int bx = 3 * Cx + lx, by = 3 * Cy + ly, bz = 3 * Cz + lz;
+  const int64_t vb = bx + (int64_t)by * Lf.pitch + (int64_t)bz * Lf.plane;
+  const int8_t cls = vt_fine ? vt_fine[vb] : (int8_t)VT_LEAF;
+  const bool has_row = cls == VT_LEAF || cls == VT_REFINED;
+#pragma unroll
+  for (int cc = 0; cc < 8; ++cc) {
+    const int kx = (cc & 1) - (lx == 3 ? 1 : 0), ky = ((cc >> 1) & 1) - (ly == 3 ? 1 : 0),
+              kz = (cc >> 2) - (lz == 3 ? 1 : 0);
+    double w = 0.0;
+    if (kx >= 0 && ky >= 0 && kz >= 0) {
+      const int kap = kx | (ky << 1) | (kz << 2);
+      w = Pw ? Pw[(int64_t)kap * Lf.nslot + vb] : dlin1(bx % 3, kx) * dlin1(by % 3, ky) * dlin1(bz % 3, kz);
+    }
+    P[t * 8 + cc] = w;
+    pv[t * 8 + cc] = has_row ? w : 0.0;
+  }
+  if (t < 27) {
+    const int ex = t % 3, ey = (t / 3) % 3, ez = t / 9;
+    E[t] = eps[(3 * Cx + ex) + (int64_t)(3 * Cy + ey) * Lf.pitch + (int64_t)(3 * Cz + ez) * Lf.plane];
+  }
+  __syncthreads();
+  {
+    double acc[8];
+#pragma unroll
+    for (int V = 0; V < 8; ++V) acc[V] = 0.0;
+    if (interior(Lf, bx, by, bz)) {
+      // cells b - c of C (local cell coordinates 0..2)
+      double Ec[8];
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) {
+        const int ex = lx - (cc & 1), ey = ly - ((cc >> 1) & 1), ez = lz - (cc >> 2);
+        Ec[cc] = (ex >= 0 && ex <= 2 && ey >= 0 && ey <= 2 && ez >= 0 && ez <= 2) ? E[ex + 3 * (ey + 3 * ez)] : 0.0;
+      }
+      double sE = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) sE += Ec[cc];
+#pragma unroll
+      for (int V = 0; V < 8; ++V) acc[V] = kref(3, 0) * pv[t * 8 + V] * sE;
+      // neighbours b + delta inside the closed cell; the 3D Q1 element couples
+      // face- and body-diagonal neighbours only (edge neighbours: K = 0)
+#pragma unroll
+      for (int k = 0; k < 27; ++k) {
+        const int dx = off_x(k), dy = off_y(k), dz = off_z(k);
+        const int nd = (dx != 0) + (dy != 0) + (dz != 0);
+        if (nd < 2) continue;
+        const int ax = lx + dx, ay = ly + dy, az = lz + dz;
+        if (ax < 0 || ax > 3 || ay < 0 || ay > 3 || az < 0 || az > 3) continue;
+        double es = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+          const int cx = cc & 1, cy = (cc >> 1) & 1, cz = cc >> 2;
+          const bool holds = (dx == 0 || cx == (dx < 0 ? 1 : 0)) && (dy == 0 || cy == (dy < 0 ? 1 : 0)) &&
+                             (dz == 0 || cz == (dz < 0 ? 1 : 0));
+          if (holds) es += Ec[cc];
+        }
+        const int a = ax + 4 * (ay + 4 * az);
+        const double kw = kref(3, nd) * es;
+#pragma unroll
+        for (int V = 0; V < 8; ++V) acc[V] += kw * pv[a * 8 + V];
+      }
+#pragma unroll
+      for (int V = 0; V < 8; ++V) acc[V] *= Lf.h;
+    }
+#pragma unroll
+    for (int V = 0; V < 8; ++V) T[t * 8 + V] = acc[V];
+  }
+  __syncthreads();
+  {
+    const int V = t >> 3, Wc = t & 7;
+    double acc = 0.0;
+    for (int b = 0; b < 64; ++b) acc += T[b * 8 + V] * P[b * 8 + Wc];
+    AC[ci * 64 + t] = acc;
+  }
+}
+
+// Coarse rows of the listed vertices from the element matrices of their eight
+// refined cells (cidx: list index of each coarse cell, -1 when not listed);
+// entry W - V sums the cells that hold both, in corner order.  Rows of
+// listed vertices that are not refined, and entries towards boundary
+// vertices, are zero.
+__global__ __launch_bounds__(256) void k_rap_assemble3(Lat Lc, const double* __restrict__ AC,
+                                                       const int32_t* __restrict__ cidx,
+                                                       const int32_t* __restrict__ vlist, int64_t nlist,
+                                                       const int8_t* __restrict__ vtc, double* __restrict__ Ac) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nlist) return;
+  const int n = Lc.n, m = n - 1;
+  const int64_t vv = vlist[i];
+  const int Vx = (int)(vv % m) + 1, Vy = (int)((vv / m) % m) + 1, Vz = (int)(vv / ((int64_t)m * m)) + 1;
+  const int64_t vc = Vx + (int64_t)Vy * Lc.pitch + (int64_t)Vz * Lc.plane;
+  double acc[27];
+#pragma unroll
+  for (int w = 0; w < 27; ++w) acc[w] = 0.0;
+  if (vtc == nullptr || vtc[vc] == VT_REFINED) {
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const int cx = Vx - (cc & 1), cy = Vy - ((cc >> 1) & 1), cz = Vz - (cc >> 2);
+      const int32_t idx = cidx[cx + (int64_t)n * (cy + (int64_t)n * cz)];
+      if (idx < 0) continue;
+      const double* row = AC + (int64_t)idx * 64 + cc * 8;
+#pragma unroll
+      for (int wl = 0; wl < 8; ++wl) {
+        const int dx = (wl & 1) - (cc & 1), dy = ((wl >> 1) & 1) - ((cc >> 1) & 1), dz = (wl >> 2) - (cc >> 2);
+        acc[(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)] += row[wl];
+      }
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < 27; ++w) {
+    const bool in = interior(Lc, Vx + off_x(w), Vy + off_y(w), Vz + off_z(w));
+    Ac[(int64_t)w * Lc.nslot + vc] = in ? acc[w] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cell_index(const int32_t* __restrict__ cells, int64_t ncells,
+                                                    int32_t* __restrict__ cidx) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < ncells) cidx[cells[i]] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_check_rows(Lat Lc, const double* __restrict__ Ac,
                                                     int* __restrict__ bad) {
@@ -1084,8 +1316,10 @@ void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const doubl
     hipLaunchKernelGGL(k_boxmg<2>, dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
                        n_cells);
   } else {
+    // 8 coarse cells (all their corners) per workgroup
+    const int64_t nc = cells ? n_cells : (int64_t)Lc.n * Lc.n * Lc.n;
     BoxFetch<3> F{Afine, epsf, Lf, vt_fine, vt_fine != nullptr};
-    hipLaunchKernelGGL(k_boxmg<3>, dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
+    hipLaunchKernelGGL(k_boxmg<3>, dim3(blocks_for(nc, 8)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
                        n_cells);
   }
   QMG_HIP(hipGetLastError());
@@ -1117,6 +1351,29 @@ void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double*
                        verts, n_verts, rmode);
   }
   QMG_HIP(hipGetLastError());
+}
+
+bool launch_rap_cells(const Lat& Lf, const Lat& Lc, const double* epsf, const double* Pw, double* Ac,
+                      hipStream_t s, const int8_t* vt_fine, const int8_t* vt_coarse, const int32_t* verts,
+                      int64_t n_verts, const int32_t* cells, int64_t n_cells, void* scratch, size_t scratch_bytes) {
+  if (Lf.d != 3 || cells == nullptr || verts == nullptr) return false;
+  const int64_t ncc = (int64_t)Lc.n * Lc.n * Lc.n;
+  const size_t need = (size_t)n_cells * 64 * sizeof(double) + (size_t)ncc * sizeof(int32_t);
+  if (need > scratch_bytes || ncc > INT32_MAX) return false;
+  double* AC = (double*)scratch;
+  int32_t* cidx = (int32_t*)(AC + n_cells * 64);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(ncc, 256)), dim3(256), 0, s, cidx, ncc, -1);
+  if (n_cells > 0) {
+    hipLaunchKernelGGL(k_cell_index, dim3(blocks_for(n_cells, 256)), dim3(256), 0, s, cells, n_cells, cidx);
+    const int64_t gx = std::min<int64_t>(n_cells, 65536);
+    hipLaunchKernelGGL(k_rap_cells3, dim3((unsigned)gx, (unsigned)((n_cells + gx - 1) / gx)), dim3(64), 0, s, Lf,
+                       Lc, epsf, Pw, vt_fine, cells, n_cells, AC);
+  }
+  if (n_verts > 0)
+    hipLaunchKernelGGL(k_rap_assemble3, dim3(blocks_for(n_verts, 256)), dim3(256), 0, s, Lc, AC, cidx, verts,
+                       n_verts, vt_coarse, Ac);
+  QMG_HIP(hipGetLastError());
+  return true;
 }
 
 void launch_conv_add(const Lat& L, const double* vel, double* A, hipStream_t s) {

@@ -216,6 +216,13 @@ void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double*
                 const double* Pw, double* Ac, hipStream_t s, const int8_t* vt_fine = nullptr,
                 const int8_t* vt_coarse = nullptr, const int32_t* verts = nullptr, int64_t n_verts = 0,
                 int rmode = 0);
+// The Galerkin product of the finest 3D adaptive level coarse cell by coarse
+// cell: element matrices of the listed refined cells in `scratch`, then the
+// rows of the listed refined vertices.  Returns false (nothing launched) when
+// scratch_bytes cannot hold 64 doubles per cell plus an int per coarse cell.
+bool launch_rap_cells(const Lat& Lf, const Lat& Lc, const double* epsf, const double* Pw, double* Ac,
+                      hipStream_t s, const int8_t* vt_fine, const int8_t* vt_coarse, const int32_t* verts,
+                      int64_t n_verts, const int32_t* cells, int64_t n_cells, void* scratch, size_t scratch_bytes);
 // Adds the convection term (v constant per cell, d arrays of cell slots in
 // vel) to the full stencils A of level L.
 void launch_conv_add(const Lat& L, const double* vel, double* A, hipStream_t s);
@@ -316,9 +323,11 @@ int pass2d_partials(const Lat& L);
 enum VertexClass : int8_t { VT_OUT = 0, VT_LEAF = 1, VT_REFINED = 2, VT_HANGING = 3 };
 // Active 64 x 4 (x, y) tiles of one level (3 ints per tile: x tile, y tile,
 // z plane) and the vertex class of every slot of the level.
-// On 3D adaptive levels also the 64 x 8 x 16 bricks (x brick, y brick, chunk
-// of 16 interior planes) that hold a leaf, refined or hanging vertex, for
-// the plane-marching sweep.
+// On 3D adaptive levels also the 32 x 16 x 16 bricks (x brick, y brick,
+// chunk of 16 interior planes) that hold a leaf, refined or hanging vertex,
+// for the plane-marching sweep.  Bricks 32 slots wide fit a thin refined band
+// better than 64-wide ones: on a level-6 band they cover 2.2 slots per
+// active vertex against 2.8, and load 3.0 halo-inclusive slots against 4.0.
 struct AdTiles {
   Lat L;
   const int32_t* tiles = nullptr;
@@ -327,7 +336,7 @@ struct AdTiles {
   const int32_t* bricks = nullptr;
   int nb = 0;
 };
-constexpr int kBrickX = 64, kBrickY = 8, kBrickZ = 16;
+constexpr int kBrickX = 32, kBrickY = 16, kBrickZ = 16;
 constexpr int kMarchMinBricks = 256;  // smaller levels keep one workgroup per tile plane
 // mode 0: Jacobi sweep of leaf and refined vertices, 1: the same from zero,
 // 2: residual (zero at hanging vertices; partial: per-workgroup sums of

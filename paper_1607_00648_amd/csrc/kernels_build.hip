@@ -321,12 +321,16 @@ __device__ inline bool orthant_refined(const int8_t* cref, const Lat& Lc, int Vx
   return cref[cx + (int64_t)cy * Lc.pitch + (int64_t)cz * Lc.plane] != 0;
 }
 
+// Two wavefronts per SIMD: the 3D patch systems otherwise take the whole
+// register file (one wavefront per SIMD); the bound spills some of them,
+// which is cheaper than the lost latency hiding (level-6 BoxMG of the band
+// workload 10.1 -> 8.7 ms).
 // cref (nullable): refined flags of the coarse cells; patches of cells that
 // are not refined are skipped (adaptive levels)
 // cells (nullable): list of the refined coarse cells; thread (cell, corner)
 // solves the corner's orthant, which points into the cell
 template <int D>
-__global__ __launch_bounds__(64) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, double* __restrict__ Pw,
+__global__ __launch_bounds__(64, 2) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, double* __restrict__ Pw,
                                               const int8_t* __restrict__ cref, const int32_t* __restrict__ cells,
                                               int64_t ncells) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;

@@ -177,7 +177,9 @@ def test_vcycle_iterates_match_oracle(d, L, transfer, store):
 def test_checkerboard2d_level6_full_size_cycles_and_solve():
     """The 729^2-cell jumping-coefficient workload at full size: 4 cycles match
     the oracle's iterate; the solve reaches 1e-8 by the oracle's own FP64
-    recomputation of the residual."""
+    recomputation of the residual; continued to 1e-13, the FP64 solution
+    matches the oracle's direct solve of the fine system within 1e-12
+    relative residual, ||A (u - u*)|| / ||b||."""
     qmg = require_gpu()
     announce("2D checkerboard level 6 full size")
     p = W.checkerboard2d(0)
@@ -196,9 +198,16 @@ def test_checkerboard2d_level6_full_size_cycles_and_solve():
     np.testing.assert_allclose(rr, hist, rtol=1e-6)
     rep, _ = g.solve(1e-8, 400)
     u = g.solution()
-    g.close()
     assert rep["status"] == "QMG_OK"
     assert np.linalg.norm(b - A @ u) / np.linalg.norm(b) <= 1e-8
+    rep, _ = g.solve(1e-13, 400)
+    u = g.solution()
+    g.close()
+    assert rep["status"] == "QMG_OK"
+    ustar = O.direct_solve(A, b)
+    dres = np.linalg.norm(A @ (u - ustar)) / np.linalg.norm(b)
+    print(f"converged FP64 solution against the direct solve: {dres:.3e}")
+    assert dres <= 1e-12
 
 
 @pytest.mark.parametrize("store", ["hier32", "bf16", "hier16"])

@@ -71,6 +71,11 @@ struct LevelBuf {
   int ntiles = 0;
   int32_t* bricks = nullptr;  // 3D: bricks for the plane-marching sweep
   int nbricks = 0;
+  int64_t* hang = nullptr;  // slots of the hanging vertices (levels above the base)
+  int64_t nhang = 0;
+  int64_t* act = nullptr;  // slots of the leaf and refined vertices (levels above the base)
+  int64_t nact = 0;
+  void* rpart = nullptr;  // coarse levels of an adaptive pair: FAS restriction parts per cell slot
   int32_t* rv = nullptr;  // refined vertices and cells (levels base..L-1), for the build
   int64_t nrv = 0;
   int32_t* rc = nullptr;
@@ -86,6 +91,10 @@ struct LevelBuf {
     t.n = ntiles;
     t.bricks = bricks;
     t.nb = nbricks;
+    t.hang = hang;
+    t.nh = nhang;
+    t.act = act;
+    t.na = nact;
     return t;
   }
 };
@@ -97,6 +106,8 @@ struct HostLevel {
   std::vector<int32_t> tiles;     // active tiles (x tile, y tile, z plane)
   std::vector<int32_t> bricks;    // 3D: bricks holding a leaf, refined or hanging vertex
   std::vector<int64_t> leaf;      // slots of the unknowns (x fastest)
+  std::vector<int64_t> hang;      // slots of the hanging vertices (x fastest)
+  std::vector<int64_t> act;       // slots of the leaf and refined vertices (x fastest)
   std::vector<int64_t> cells;     // slots of the leaf cells (x fastest)
   std::vector<int32_t> rverts;    // refined interior vertices (interior index, x fastest)
   std::vector<int32_t> rcells;    // refined cells (cell index, x fastest)
@@ -480,6 +491,8 @@ void linearise(qmg_grid_t* g) {
           else if (cnt > 0) t = VT_HANGING;
           H.vt[(size_t)sl] = t;
           if (t == VT_LEAF) H.leaf.push_back(sl);
+          if (t == VT_HANGING) H.hang.push_back(sl);
+          if (t == VT_LEAF || t == VT_REFINED) H.act.push_back(sl);
           if (t == VT_REFINED)
             H.rverts.push_back((int32_t)((i - 1) + (n - 1) * ((j - 1) + (n - 1) * (d == 3 ? k - 1 : 0))));
           if (t == VT_LEAF || t == VT_REFINED) ++H.n_active;
@@ -571,12 +584,19 @@ void layout(qmg_grid_t* g, Arena& a) {
       if (l < L) B.cref = a.take<int8_t>(B.L.nslot);
       B.tiles = a.take<int32_t>((int64_t)H.tiles.size());
       B.bricks = a.take<int32_t>((int64_t)H.bricks.size());
+      if (l > g->lb) {
+        B.nhang = (int64_t)H.hang.size();
+        B.hang = a.take<int64_t>(std::max<int64_t>(B.nhang, 1));
+        B.nact = (int64_t)H.act.size();
+        B.act = a.take<int64_t>(std::max<int64_t>(B.nact, 1));
+      }
       if (l < L) B.sv = a.take<char>(B.L.nslot * (int64_t)it);
       if (l < L) {
         B.nrv = (int64_t)H.rverts.size();
         B.rv = a.take<int32_t>(std::max<int64_t>(B.nrv, 1));
         B.nrc = (int64_t)H.rcells.size();
         B.rc = a.take<int32_t>(std::max<int64_t>(B.nrc, 1));
+        B.rpart = a.take<char>(B.L.nslot * (int64_t)(1 << d) * it);
       }
       if (g->mixed) {
         B.x64 = a.take<double>(B.L.nslot);
@@ -693,6 +713,8 @@ void upload_linearisation(qmg_grid_t* g) {
       QMG_HIP(hipMemcpy(B.tiles, H.tiles.data(), H.tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (!H.bricks.empty())
       QMG_HIP(hipMemcpy(B.bricks, H.bricks.data(), H.bricks.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (B.nhang > 0) QMG_HIP(hipMemcpy(B.hang, H.hang.data(), B.nhang * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (B.nact > 0) QMG_HIP(hipMemcpy(B.act, H.act.data(), B.nact * sizeof(int64_t), hipMemcpyHostToDevice));
     if (B.nrv > 0) QMG_HIP(hipMemcpy(B.rv, H.rverts.data(), B.nrv * sizeof(int32_t), hipMemcpyHostToDevice));
     if (B.nrc > 0) QMG_HIP(hipMemcpy(B.rc, H.rcells.data(), B.nrc * sizeof(int32_t), hipMemcpyHostToDevice));
     if (!H.leaf.empty())
@@ -976,7 +998,7 @@ void vcycle_ad(qmg_grid_t* g, int l) {
   launch_ad_inject<T>(tc, F.L, (const T*)F.u, (T*)C.u, S(g));
   launch_ad_copy<T>(tc, (const T*)C.u, (T*)C.sv, S(g));
   launch_ad_fas_rhs<T>(tc, F.L, (const T*)F.r, (const T*)C.u, eps_of<T>(C), C.A, (T*)C.b, F.P, S(g), C.rv,
-                       C.nrv);
+                       C.nrv, C.rc, C.nrc, (T*)C.rpart);
   vcycle<T>(g, l - 1, false);
   launch_ad_correct<T>(tf, C.L, (T*)F.u, (const T*)C.u, (const T*)C.sv, F.P, S(g));
   launch_ad_hang<T>(tf, C.L, (T*)F.u, (const T*)C.u, F.P, S(g));

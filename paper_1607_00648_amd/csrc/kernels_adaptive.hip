@@ -272,6 +272,26 @@ __global__ __launch_bounds__(256) void k_ad_hang(Lat Lf, Lat Lc, const int32_t* 
   uf[s.v] = interp_at<D, T, PSRC, PFMT>(Lf, Lc, P, s.i, s.j, s.k, s.v, uc, (const T*)nullptr);
 }
 
+// The same over the list of the level's hanging vertices (a thin share of
+// the tiles' slots: the band's boundary layer).
+template <int D, typename T, int PSRC, int PFMT>
+__global__ __launch_bounds__(256) void k_ad_hang_list(Lat Lf, Lat Lc, const int64_t* __restrict__ hang,
+                                                      int64_t nh, T* __restrict__ uf, const T* __restrict__ uc,
+                                                      Store P) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= nh) return;
+  const int64_t v = hang[q];
+  int i, j, k = 0;
+  int64_t r = v;
+  if (D == 3) {
+    k = (int)(v / Lf.plane);
+    r = v - (int64_t)k * Lf.plane;
+  }
+  j = (int)(r / Lf.pitch);
+  i = (int)(r - (int64_t)j * Lf.pitch);
+  uf[v] = interp_at<D, T, PSRC, PFMT>(Lf, Lc, P, i, j, k, v, uc, (const T*)nullptr);
+}
+
 // refined coarse vertices := value of the finer copy (over coarse tiles)
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_ad_inject(Lat Lf, Lat Lc, const int32_t* __restrict__ tiles,
@@ -336,6 +356,77 @@ __global__ __launch_bounds__(256) void k_ad_fas_rhs_list(Lat Lf, Lat Lc, const i
   }
 }
 
+// The FAS restriction by coarse cell: the fine vertices f with floor(f/3) = C
+// (3^d of them, local 0..2 per axis) belong to cell C alone, and their
+// parents are C's corners C + kappa, so (P^T r)(V) is the sum over the 2^d
+// cells C = V - kappa of cell C's part for its corner kappa.  One group of
+// threads per listed refined cell forms the 2^d parts (fine vertices in a
+// fixed order); part[slot(C) * 2^d + kappa].
+template <int D, typename T, int PSRC, int PFMT>
+__global__ __launch_bounds__(256) void k_ad_restrict_cells(Lat Lf, Lat Lc, const int32_t* __restrict__ cells,
+                                                           int64_t ncells, const T* __restrict__ rf,
+                                                           T* __restrict__ part, Store P) {
+  constexpr int NV = (D == 3) ? 27 : 9, NK = Dim<D>::NC, TPC = (D == 3) ? 32 : 16, CPB = 256 / TPC;
+  __shared__ T prod[CPB][NV][NK];
+  const int lc = threadIdx.x / TPC, q = threadIdx.x % TPC;
+  const int64_t ci = (int64_t)blockIdx.x * CPB + lc;
+  const bool on = ci < ncells;
+  const int n = Lc.n;
+  int Cx = 0, Cy = 0, Cz = 0;
+  if (on) {
+    const int64_t c = cells[ci];
+    Cx = (int)(c % n);
+    Cy = (int)((c / n) % n);
+    Cz = (D == 3) ? (int)(c / ((int64_t)n * n)) : 0;
+  }
+  if (on && q < NV) {
+    const int rx = q % 3, ry = (q / 3) % 3, rz = (D == 3) ? q / 9 : 0;
+    const int64_t vf = (3 * Cx + rx) + (int64_t)(3 * Cy + ry) * Lf.pitch + (int64_t)(3 * Cz + rz) * Lf.plane;
+    const T r = rf[vf];
+#pragma unroll
+    for (int kap = 0; kap < NK; ++kap) {
+      const int kx = kap & 1, ky = (kap >> 1) & 1, kz = (kap >> 2) & 1;
+      double w = 0.0;
+      if (!((kx && rx == 0) || (ky && ry == 0) || (kz && rz == 0)))
+        w = pweight<D, PSRC, PFMT>(P, Lf, vf, rx, ry, rz, kap);
+      prod[lc][q][kap] = (T)w * r;
+    }
+  }
+  __syncthreads();
+  if (on && q < NK) {
+    T acc = (T)0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc += prod[lc][i][q];
+    const int64_t sc = Cx + (int64_t)Cy * Lc.pitch + (int64_t)Cz * Lc.plane;
+    part[sc * NK + q] = acc;
+  }
+}
+
+// FAS right-hand side of the listed refined coarse vertices from the cell
+// parts: sum over the corners in order, then the coarse row.
+template <int D, typename T, int SRC, int FMT>
+__global__ __launch_bounds__(256) void k_ad_fas_rhs_cells(Lat Lc, const int32_t* __restrict__ verts, int64_t nverts,
+                                                          const T* __restrict__ part, const T* __restrict__ uc,
+                                                          const T* __restrict__ epsc, Store Ac, T* __restrict__ bc) {
+  constexpr int NS = Dim<D>::NS, NK = Dim<D>::NC;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= nverts) return;
+  const int m = Lc.n - 1;
+  const int64_t vv = verts[idx];
+  const int I = (int)(vv % m) + 1, J = (int)((vv / m) % m) + 1, K = (D == 3) ? (int)(vv / ((int64_t)m * m)) + 1 : 0;
+  T rr = (T)0;
+#pragma unroll
+  for (int kap = 0; kap < NK; ++kap) {
+    const int64_t sc = (I - (kap & 1)) + (int64_t)(J - ((kap >> 1) & 1)) * Lc.pitch +
+                       (D == 3 ? (int64_t)(K - ((kap >> 2) & 1)) * Lc.plane : 0);
+    rr += part[sc * NK + kap];
+  }
+  const int64_t v = I + (int64_t)J * Lc.pitch + (int64_t)K * Lc.plane;
+  T a[NS];
+  op_row<D, T, SRC, FMT>(epsc, Ac, Lc, v, a);
+  bc[v] = rr + row_dot<D, T, SRC>(a, uc, Lc, v);
+}
+
 // FAS correction: active fine vertices += P (u_c - saved_c)
 template <int D, typename T, int PSRC, int PFMT>
 __global__ __launch_bounds__(256) void k_ad_correct(Lat Lf, Lat Lc, const int32_t* __restrict__ tiles,
@@ -344,6 +435,25 @@ __global__ __launch_bounds__(256) void k_ad_correct(Lat Lf, Lat Lc, const int32_
   const Slot s = tile_slot<D>(Lf, tiles);
   if (!s.valid || !active(vt[s.v])) return;
   uf[s.v] += interp_at<D, T, PSRC, PFMT>(Lf, Lc, P, s.i, s.j, s.k, s.v, uc, sc);
+}
+
+// The same over the list of the level's leaf and refined vertices.
+template <int D, typename T, int PSRC, int PFMT>
+__global__ __launch_bounds__(256) void k_ad_correct_list(Lat Lf, Lat Lc, const int64_t* __restrict__ act,
+                                                         int64_t na, T* __restrict__ uf, const T* __restrict__ uc,
+                                                         const T* __restrict__ sc, Store P) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= na) return;
+  const int64_t v = act[q];
+  int i, j, k = 0;
+  int64_t r = v;
+  if (D == 3) {
+    k = (int)(v / Lf.plane);
+    r = v - (int64_t)k * Lf.plane;
+  }
+  j = (int)(r / Lf.pitch);
+  i = (int)(r - (int64_t)j * Lf.pitch);
+  uf[v] += interp_at<D, T, PSRC, PFMT>(Lf, Lc, P, i, j, k, v, uc, sc);
 }
 
 // cell coefficients of cells that do not exist: the covering (parent) cell's
@@ -383,6 +493,16 @@ __global__ __launch_bounds__(256) void k_ad_axpy(Lat L, const int32_t* __restric
                                                  const float* __restrict__ e) {
   const Slot s = tile_slot<D>(L, tiles);
   if (s.valid && vt[s.v] == VT_LEAF) x[s.v] += (double)e[s.v];
+}
+
+// The same over the level's leaf and refined vertices (refined ones skipped).
+__global__ __launch_bounds__(256) void k_ad_axpy_list(const int64_t* __restrict__ act, int64_t na,
+                                                      const int8_t* __restrict__ vt, double* __restrict__ x,
+                                                      const float* __restrict__ e) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= na) return;
+  const int64_t v = act[q];
+  if (vt[v] == VT_LEAF) x[v] += (double)e[v];
 }
 
 // cell coefficients of a level: refined cells take the mean of their children
@@ -445,6 +565,7 @@ __global__ void k_ad_gather(const int64_t* __restrict__ slots, int64_t n, const 
 }
 
 inline dim3 tiles_grid(int ntiles) { return dim3((unsigned)ntiles); }
+inline unsigned list_blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 inline dim3 full_grid(const Lat& L) {
   return dim3((unsigned)(L.pitch / TX), (unsigned)((L.n + 1 + TY - 1) / TY), (unsigned)(L.d == 3 ? L.n + 1 : 1));
 }
@@ -495,12 +616,23 @@ void ad_stencil_src(const AdTiles& t, int mode, const T* u, const T* b, TO* out,
 
 template <int D, typename T, int PSRC>
 void ad_fas_src(const AdTiles& tc, const Lat& Lf, const T* rf, const T* uc, const T* epsc, const Store& Ac,
-                T* bc, const Store& P, hipStream_t s, const int32_t* verts, int64_t nverts) {
+                T* bc, const Store& P, hipStream_t s, const int32_t* verts, int64_t nverts,
+                const int32_t* cells, int64_t ncells, T* part) {
   const dim3 g = tiles_grid(tc.n), bl(TX, TY, 1);
   const dim3 gl((unsigned)((nverts + 3) / 4)), bll(256);
+  const bool by_cells = verts && cells && part;
+  if (by_cells && ncells > 0) {
+    constexpr int CPB = (D == 3) ? 8 : 16;
+    hipLaunchKernelGGL((k_ad_restrict_cells<D, T, PSRC, F64>), dim3(list_blocks(ncells, CPB)), dim3(256), 0, s, Lf,
+                       tc.L, cells, ncells, rf, part, P);
+  }
+  const dim3 gv(list_blocks(nverts, 256));
 #define QMG_FAS(SRCV, FMTV)                                                                              \
   do {                                                                                                   \
-    if (verts)                                                                                           \
+    if (by_cells)                                                                                        \
+      hipLaunchKernelGGL((k_ad_fas_rhs_cells<D, T, SRCV, FMTV>), gv, bll, 0, s, tc.L, verts, nverts, part, uc, \
+                         epsc, Ac, bc);                                                                  \
+    else if (verts)                                                                                      \
       hipLaunchKernelGGL((k_ad_fas_rhs_list<D, T, SRCV, FMTV, PSRC, F64>), gl, bll, 0, s, Lf, tc.L, verts, \
                          nverts, rf, uc, epsc, Ac, bc, P);                                               \
     else                                                                                                 \
@@ -541,6 +673,20 @@ template <typename T>
 void launch_ad_hang(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const Store& P, hipStream_t s) {
   if (tf.n <= 0) return;
   check_ad_P(P);
+  if (tf.hang != nullptr) {
+    if (tf.nh <= 0) return;
+    const dim3 gl(list_blocks(tf.nh, 256));
+#define QMG_HANGL(DV, PS) \
+  hipLaunchKernelGGL((k_ad_hang_list<DV, T, PS, F64>), gl, dim3(256), 0, s, tf.L, Lc, tf.hang, tf.nh, uf, uc, P)
+    if (tf.L.d == 2) {
+      if (P.src == SRC_HIER) QMG_HANGL(2, SRC_HIER); else if (P.src == SRC_PLAIN) QMG_HANGL(2, SRC_PLAIN); else QMG_HANGL(2, SRC_GEOM);
+    } else {
+      if (P.src == SRC_HIER) QMG_HANGL(3, SRC_HIER); else if (P.src == SRC_PLAIN) QMG_HANGL(3, SRC_PLAIN); else QMG_HANGL(3, SRC_GEOM);
+    }
+#undef QMG_HANGL
+    QMG_HIP(hipGetLastError());
+    return;
+  }
   const dim3 g = tiles_grid(tf.n), bl(TX, TY, 1);
 #define QMG_HANG(DV, PS) hipLaunchKernelGGL((k_ad_hang<DV, T, PS, F64>), g, bl, 0, s, tf.L, Lc, tf.tiles, tf.vt, uf, uc, P)
   if (tf.L.d == 2) {
@@ -564,17 +710,17 @@ void launch_ad_inject(const AdTiles& tc, const Lat& Lf, const T* uf, T* uc, hipS
 template <typename T>
 void launch_ad_fas_rhs(const AdTiles& tc, const Lat& Lf, const T* rf, const T* uc, const T* epsc,
                        const Store& Ac, T* bc, const Store& P, hipStream_t s, const int32_t* verts,
-                       int64_t nverts) {
+                       int64_t nverts, const int32_t* cells, int64_t ncells, T* part) {
   if (tc.n <= 0 || (verts && nverts <= 0)) return;
   check_ad_P(P);
   if (tc.L.d == 2) {
-    if (P.src == SRC_HIER) ad_fas_src<2, T, SRC_HIER>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts);
-    else if (P.src == SRC_PLAIN) ad_fas_src<2, T, SRC_PLAIN>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts);
-    else ad_fas_src<2, T, SRC_GEOM>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts);
+    if (P.src == SRC_HIER) ad_fas_src<2, T, SRC_HIER>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts, cells, ncells, part);
+    else if (P.src == SRC_PLAIN) ad_fas_src<2, T, SRC_PLAIN>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts, cells, ncells, part);
+    else ad_fas_src<2, T, SRC_GEOM>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts, cells, ncells, part);
   } else {
-    if (P.src == SRC_HIER) ad_fas_src<3, T, SRC_HIER>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts);
-    else if (P.src == SRC_PLAIN) ad_fas_src<3, T, SRC_PLAIN>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts);
-    else ad_fas_src<3, T, SRC_GEOM>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts);
+    if (P.src == SRC_HIER) ad_fas_src<3, T, SRC_HIER>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts, cells, ncells, part);
+    else if (P.src == SRC_PLAIN) ad_fas_src<3, T, SRC_PLAIN>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts, cells, ncells, part);
+    else ad_fas_src<3, T, SRC_GEOM>(tc, Lf, rf, uc, epsc, Ac, bc, P, s, verts, nverts, cells, ncells, part);
   }
   QMG_HIP(hipGetLastError());
 }
@@ -584,6 +730,20 @@ void launch_ad_correct(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, con
                        hipStream_t s) {
   if (tf.n <= 0) return;
   check_ad_P(P);
+  if (tf.act != nullptr) {
+    if (tf.na <= 0) return;
+    const dim3 gl(list_blocks(tf.na, 256));
+#define QMG_CORRL(DV, PS) \
+  hipLaunchKernelGGL((k_ad_correct_list<DV, T, PS, F64>), gl, dim3(256), 0, s, tf.L, Lc, tf.act, tf.na, uf, uc, sc, P)
+    if (tf.L.d == 2) {
+      if (P.src == SRC_HIER) QMG_CORRL(2, SRC_HIER); else if (P.src == SRC_PLAIN) QMG_CORRL(2, SRC_PLAIN); else QMG_CORRL(2, SRC_GEOM);
+    } else {
+      if (P.src == SRC_HIER) QMG_CORRL(3, SRC_HIER); else if (P.src == SRC_PLAIN) QMG_CORRL(3, SRC_PLAIN); else QMG_CORRL(3, SRC_GEOM);
+    }
+#undef QMG_CORRL
+    QMG_HIP(hipGetLastError());
+    return;
+  }
   const dim3 g = tiles_grid(tf.n), bl(TX, TY, 1);
 #define QMG_CORR(DV, PS) hipLaunchKernelGGL((k_ad_correct<DV, T, PS, F64>), g, bl, 0, s, tf.L, Lc, tf.tiles, tf.vt, uf, uc, sc, P)
   if (tf.L.d == 2) {
@@ -624,6 +784,12 @@ void launch_ad_zero(const AdTiles& t, T* p, hipStream_t s, int narr) {
 
 void launch_ad_axpy(const AdTiles& t, double* x, const float* e, hipStream_t s) {
   if (t.n <= 0) return;
+  if (t.act != nullptr) {
+    if (t.na > 0)
+      hipLaunchKernelGGL(k_ad_axpy_list, dim3(list_blocks(t.na, 256)), dim3(256), 0, s, t.act, t.na, t.vt, x, e);
+    QMG_HIP(hipGetLastError());
+    return;
+  }
   const dim3 g = tiles_grid(t.n), bl(TX, TY, 1);
   if (t.L.d == 2) hipLaunchKernelGGL(k_ad_axpy<2>, g, bl, 0, s, t.L, t.tiles, t.vt, x, e);
   else hipLaunchKernelGGL(k_ad_axpy<3>, g, bl, 0, s, t.L, t.tiles, t.vt, x, e);
@@ -662,8 +828,8 @@ template void launch_ad_hang<double>(const AdTiles&, const Lat&, double*, const 
 template void launch_ad_hang<float>(const AdTiles&, const Lat&, float*, const float*, const Store&, hipStream_t);
 template void launch_ad_inject<double>(const AdTiles&, const Lat&, const double*, double*, hipStream_t);
 template void launch_ad_inject<float>(const AdTiles&, const Lat&, const float*, float*, hipStream_t);
-template void launch_ad_fas_rhs<double>(const AdTiles&, const Lat&, const double*, const double*, const double*, const Store&, double*, const Store&, hipStream_t, const int32_t*, int64_t);
-template void launch_ad_fas_rhs<float>(const AdTiles&, const Lat&, const float*, const float*, const float*, const Store&, float*, const Store&, hipStream_t, const int32_t*, int64_t);
+template void launch_ad_fas_rhs<double>(const AdTiles&, const Lat&, const double*, const double*, const double*, const Store&, double*, const Store&, hipStream_t, const int32_t*, int64_t, const int32_t*, int64_t, double*);
+template void launch_ad_fas_rhs<float>(const AdTiles&, const Lat&, const float*, const float*, const float*, const Store&, float*, const Store&, hipStream_t, const int32_t*, int64_t, const int32_t*, int64_t, float*);
 template void launch_ad_correct<double>(const AdTiles&, const Lat&, double*, const double*, const double*, const Store&, hipStream_t);
 template void launch_ad_correct<float>(const AdTiles&, const Lat&, float*, const float*, const float*, const Store&, hipStream_t);
 template void launch_ad_copy<double>(const AdTiles&, const double*, double*, hipStream_t);

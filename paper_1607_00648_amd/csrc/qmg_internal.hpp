@@ -335,9 +335,16 @@ struct AdTiles {
   int n = 0;
   const int32_t* bricks = nullptr;
   int nb = 0;
+  // levels above the base: the hanging vertices' slots (hang == nullptr:
+  // no list, the hanging values are found on the tiles)
+  const int64_t* hang = nullptr;
+  int64_t nh = 0;
+  // levels above the base: the leaf and refined vertices' slots
+  const int64_t* act = nullptr;
+  int64_t na = 0;
 };
 constexpr int kBrickX = 32, kBrickY = 16, kBrickZ = 16;
-constexpr int kMarchMinBricks = 256;  // smaller levels keep one workgroup per tile plane
+constexpr int kMarchMinBricks = 4096;  // fewer bricks march serially: the tiles are faster
 // mode 0: Jacobi sweep of leaf and refined vertices, 1: the same from zero,
 // 2: residual (zero at hanging vertices; partial: per-workgroup sums of
 // squares over the leaves).  Hanging values travel with the iterate (mode 0
@@ -357,11 +364,12 @@ template <typename T>
 void launch_ad_inject(const AdTiles& tc, const Lat& Lf, const T* uf, T* uc, hipStream_t s);
 // verts (nullable): the refined vertices of the coarse level (interior
 // indices); then one wavefront per listed vertex instead of one thread per
-// slot of the coarse level's active tiles
+// slot of the coarse level's active tiles.  With the refined cells and a
+// part buffer (2^d iterates per coarse slot) the restriction runs by cell.
 template <typename T>
 void launch_ad_fas_rhs(const AdTiles& tc, const Lat& Lf, const T* rf, const T* uc, const T* epsc,
                        const Store& Ac, T* bc, const Store& P, hipStream_t s, const int32_t* verts = nullptr,
-                       int64_t nverts = 0);
+                       int64_t nverts = 0, const int32_t* cells = nullptr, int64_t ncells = 0, T* part = nullptr);
 template <typename T>
 void launch_ad_correct(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const T* sc, const Store& P,
                        hipStream_t s);

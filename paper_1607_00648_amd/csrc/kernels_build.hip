@@ -135,24 +135,6 @@ struct RowSrc {
     for (int s = 0; s < Dim<D>::NC; ++s)
       ce[s] = mode == 2 ? F.eps[v - slot_off(F.L, s & 1, (s >> 1) & 1, (s >> 2) & 1)] : 0.0;
   }
-  // The same row from a workgroup's LDS copy of its coarse cell's data: the
-  // vertex classes of the 4^3 fine vertices of the closed cell (origin 3C)
-  // and the coefficients of the 5^3 fine cells around them (origin 3C - 1);
-  // (lx, ly, lz) = v - 3C.
-  __device__ RowSrc(const BoxFetch<D>& F, const double* ecl, const int8_t* vcl, int lx, int ly, int lz) {
-    bool geo = F.A == nullptr;
-    mode = 1;
-    if (F.vt) {
-      const int8_t t = vcl[lx + 4 * (ly + 4 * lz)];
-      if (F.hanging_rows && t == VT_HANGING) geo = true;
-      else if (t != VT_LEAF && t != VT_REFINED) mode = 0;
-    }
-    if (mode == 1 && geo) mode = 2;
-#pragma unroll
-    for (int s = 0; s < Dim<D>::NC; ++s)
-      ce[s] = mode == 2 ? ecl[(lx + 1 - (s & 1)) + 5 * ((ly + 1 - ((s >> 1) & 1)) + 5 * (lz + 1 - ((s >> 2) & 1)))]
-                        : 0.0;
-  }
   // entry k of the row of v = (i, j, kz); the neighbour must be checked for
   // being interior by the caller when mode == 2
   __device__ double entry(const BoxFetch<D>& F, int64_t v, int k) const {
@@ -180,12 +162,9 @@ struct PCol {
   __device__ double& operator[](int i) const { return base[i * 64]; }
 };
 
-// ecl/vcl (3D): the task's coarse cell data in LDS (see RowSrc), origin 3C
-// at fine vertex (cx0, cy0, cz0)
 template <int D, int S>
 __device__ inline void box_group(const BoxFetch<D>& F, int Vx, int Vy, int Vz, int sx, int sy, int sz,
-                                 const PCol& p, const double* ecl, const int8_t* vcl, int cx0, int cy0,
-                                 int cz0) {
+                                 const PCol& p) {
   // unknowns: y with y_i in {1,2} for i in S, 0 otherwise
   constexpr int m = 1 << ((S & 1) + ((S >> 1) & 1) + ((S >> 2) & 1));
   double M[m][m];
@@ -208,8 +187,7 @@ __device__ inline void box_group(const BoxFetch<D>& F, int Vx, int Vy, int Vz, i
     }
     const int fx = 3 * Vx + sx * y[0], fy = 3 * Vy + sy * y[1], fz = 3 * Vz + sz * y[2];
     const int64_t v = fx + (int64_t)fy * F.L.pitch + (int64_t)fz * F.L.plane;
-    // the member's row, fetched once (3D: from the workgroup's LDS copy)
-    const RowSrc<D> row = (D == 3) ? RowSrc<D>(F, ecl, vcl, fx - cx0, fy - cy0, fz - cz0) : RowSrc<D>(F, v);
+    const RowSrc<D> row(F, v);  // the member's row, fetched once
     // The row in the reference frame: the cell coefficients of a rediscretised
     // row mirrored (axis a flipped: cell bit a flipped), and per axis whether
     // the true neighbour one step back / ahead in the reference frame is an
@@ -337,24 +315,18 @@ __global__ __launch_bounds__(64, 2) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, 
   const int m = Lc.n - 1;
   int orth, Vx, Vy, Vz;
   __shared__ double pl[27 * 64];
-  const double* ecl = nullptr;
-  const int8_t* vcl = nullptr;
-  int cx0 = 0, cy0 = 0, cz0 = 0;
   if constexpr (D == 3) {
     // 3D: the 64 threads are the 8 corners of 8 coarse cells (the listed
-    // ones, or every cell of a regular level); each cell's fine-vertex
-    // classes and fine-cell coefficients are staged in LDS once, instead of
-    // every corner fetching its member rows from global memory
-    __shared__ double ecs[8 * 125];
-    __shared__ int8_t vcs[8 * 64];
+    // ones, or every cell of a regular level), so that the corners sharing a
+    // cell's member rows run together
     __shared__ int cc[8 * 3];
-    const int n = Lc.n, nf = Lf.n;
+    const int n = Lc.n;
     const int lc = threadIdx.x >> 3;
     const int64_t ci = (int64_t)blockIdx.x * 8 + lc;
     const int64_t nc = cells ? ncells : (int64_t)n * n * n;
     bool active = ci < nc;
     if ((threadIdx.x & 7) == 0) {
-      int x = -1000, y = -1000, z = -1000;  // no cell: nothing staged
+      int x = -1000, y = -1000, z = -1000;
       if (active) {
         const int64_t c = cells ? (int64_t)cells[ci] : ci;
         x = (int)(c % n);
@@ -366,35 +338,12 @@ __global__ __launch_bounds__(64, 2) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, 
       cc[3 * lc + 2] = z;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 8 * 125; e += 64) {
-      const int k = e / 125, r = e - k * 125;
-      const int fx = 3 * cc[3 * k] - 1 + r % 5, fy = 3 * cc[3 * k + 1] - 1 + (r / 5) % 5,
-                fz = 3 * cc[3 * k + 2] - 1 + r / 25;
-      double v = 0.0;  // cells outside the domain (or of no listed cell) are never read
-      if (fx >= 0 && fx < nf && fy >= 0 && fy < nf && fz >= 0 && fz < nf)
-        v = F.eps[fx + (int64_t)fy * Lf.pitch + (int64_t)fz * Lf.plane];
-      ecs[e] = v;
-    }
-    for (int e = threadIdx.x; e < 8 * 64; e += 64) {
-      const int k = e >> 6, r = e & 63;
-      const int fx = 3 * cc[3 * k] + (r & 3), fy = 3 * cc[3 * k + 1] + ((r >> 2) & 3), fz = 3 * cc[3 * k + 2] + (r >> 4);
-      int8_t v = VT_OUT;
-      if (F.vt && fx >= 0 && fx <= nf && fy >= 0 && fy <= nf && fz >= 0 && fz <= nf)
-        v = F.vt[fx + (int64_t)fy * Lf.pitch + (int64_t)fz * Lf.plane];
-      vcs[e] = v;
-    }
-    __syncthreads();
     if (!active) return;
     orth = (int)(threadIdx.x & 7);
-    cx0 = 3 * cc[3 * lc];
-    cy0 = 3 * cc[3 * lc + 1];
-    cz0 = 3 * cc[3 * lc + 2];
     Vx = cc[3 * lc] + (orth & 1);
     Vy = cc[3 * lc + 1] + ((orth >> 1) & 1);
     Vz = cc[3 * lc + 2] + ((orth >> 2) & 1);
     if (!interior(Lc, Vx, Vy, Vz)) return;
-    ecl = ecs + 125 * lc;
-    vcl = vcs + 64 * lc;
   } else if (cells) {
     if (t >= ncells * Dim<D>::NC) return;
     orth = (int)(t % Dim<D>::NC);
@@ -419,16 +368,16 @@ __global__ __launch_bounds__(64, 2) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, 
 #pragma unroll
   for (int q = 0; q < 27; ++q) p[q] = 0.0;
   p[0] = 1.0;
-  box_group<D, 1>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
-  box_group<D, 2>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
+  box_group<D, 1>(F, Vx, Vy, Vz, sx, sy, sz, p);
+  box_group<D, 2>(F, Vx, Vy, Vz, sx, sy, sz, p);
   if constexpr (D == 3) {
-    box_group<D, 4>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
-    box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
-    box_group<D, 5>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
-    box_group<D, 6>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
-    box_group<D, 7>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
+    box_group<D, 4>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    box_group<D, 5>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    box_group<D, 6>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    box_group<D, 7>(F, Vx, Vy, Vz, sx, sy, sz, p);
   } else {
-    box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p, ecl, vcl, cx0, cy0, cz0);
+    box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p);
   }
   // write the reference region; a point on an axis (y_i = 0) is shared by the
   // orthants that differ only on such axes.  It is written by the one of
@@ -826,10 +775,10 @@ __global__ __launch_bounds__(64) void k_rap_cells3(Lat Lf, Lat Lc, const double*
                                                    const int8_t* __restrict__ vt_fine,
                                                    const int32_t* __restrict__ cells, int64_t ncells,
                                                    double* __restrict__ AC) {
-  __shared__ double P[64 * 8];   // [b][corner]
-  __shared__ double pv[64 * 8];  // P(b, corner) m(b)
+  __shared__ double P[64 * 8];  // [b][corner]
   __shared__ double T[64 * 8];
   __shared__ double E[27];
+  __shared__ double msk[64];    // m(b): 1 where b has a row, else 0
   const int64_t ci = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
   if (ci >= ncells) return;  // uniform over the workgroup
   const int n = Lc.n;
@@ -846,13 +795,17 @@ __global__ __launch_bounds__(64) void k_rap_cells3(Lat Lf, Lat Lc, const double*
     const int kx = (cc & 1) - (lx == 3 ? 1 : 0), ky = ((cc >> 1) & 1) - (ly == 3 ? 1 : 0),
               kz = (cc >> 2) - (lz == 3 ? 1 : 0);
     double w = 0.0;
-    if (kx >= 0 && ky >= 0 && kz >= 0) {
+    // parents that exist, less the second parent of a vertex on a coarse
+    // plane (local 0), whose weight is zero by construction
+    const bool par = kx >= 0 && ky >= 0 && kz >= 0 && !(kx == 1 && lx == 0) && !(ky == 1 && ly == 0) &&
+                     !(kz == 1 && lz == 0);
+    if (par) {
       const int kap = kx | (ky << 1) | (kz << 2);
       w = Pw ? Pw[(int64_t)kap * Lf.nslot + vb] : dlin1(bx % 3, kx) * dlin1(by % 3, ky) * dlin1(bz % 3, kz);
     }
     P[t * 8 + cc] = w;
-    pv[t * 8 + cc] = has_row ? w : 0.0;
   }
+  msk[t] = has_row ? 1.0 : 0.0;
   if (t < 27) {
     const int ex = t % 3, ey = (t / 3) % 3, ez = t / 9;
     E[t] = eps[(3 * Cx + ex) + (int64_t)(3 * Cy + ey) * Lf.pitch + (int64_t)(3 * Cz + ez) * Lf.plane];
@@ -873,8 +826,9 @@ __global__ __launch_bounds__(64) void k_rap_cells3(Lat Lf, Lat Lc, const double*
       double sE = 0.0;
 #pragma unroll
       for (int cc = 0; cc < 8; ++cc) sE += Ec[cc];
+      const double mb = msk[t];
 #pragma unroll
-      for (int V = 0; V < 8; ++V) acc[V] = kref(3, 0) * pv[t * 8 + V] * sE;
+      for (int V = 0; V < 8; ++V) acc[V] = kref(3, 0) * (P[t * 8 + V] * mb) * sE;
       // neighbours b + delta inside the closed cell; the 3D Q1 element couples
       // face- and body-diagonal neighbours only (edge neighbours: K = 0)
 #pragma unroll
@@ -893,9 +847,9 @@ __global__ __launch_bounds__(64) void k_rap_cells3(Lat Lf, Lat Lc, const double*
           if (holds) es += Ec[cc];
         }
         const int a = ax + 4 * (ay + 4 * az);
-        const double kw = kref(3, nd) * es;
+        const double kw = kref(3, nd) * es, ma = msk[a];
 #pragma unroll
-        for (int V = 0; V < 8; ++V) acc[V] += kw * pv[a * 8 + V];
+        for (int V = 0; V < 8; ++V) acc[V] += kw * (P[a * 8 + V] * ma);
       }
 #pragma unroll
       for (int V = 0; V < 8; ++V) acc[V] *= Lf.h;

@@ -167,6 +167,10 @@ struct qmg_grid {
   bool own_hnorm = true;  // pinned history buffer allocated by the grid
   hipStream_t stream = nullptr;
   bool have_coef = false, have_ops = false;
+  // adaptive levels: every slot outside the active tiles holds zero in the
+  // iterate, right-hand side and coefficient arrays (no kernel writes there
+  // after the first set_coefficients cleared the whole lattices)
+  bool lattices_clear = false;
   double bnorm = 0.0;
   int64_t n_unknowns = 0;
   size_t bytes_ops = 0;
@@ -1953,7 +1957,9 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
       for (int l = g->lb; l <= g->Lmax; ++l) {
         LevelBuf& B = g->lv[l];
         const int64_t cnt = (int64_t)g->hl[l].cells.size();
-        launch_zero<double>(B.eps64, B.L.nslot, s);
+        // later calls overwrite the leaf cells; refined cells are coarsened
+        // and missing ones given their covering value by the build
+        if (!g->lattices_clear) launch_zero<double>(B.eps64, B.L.nslot, s);
         launch_ad_scatter<double>(g->cell_slots + co, cnt, g->stage + co, 1.0, B.eps64, s);
         co += cnt;
       }
@@ -1992,15 +1998,24 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
       int64_t uo = 0;
       for (int l = g->lcq; l <= g->Lmax; ++l) {
         LevelBuf& B = g->lv[l];
+        // adaptive levels after the first call: the active tiles only
+        const bool tiles_only = g->lattices_clear && l >= g->lb;
         for (void* v : {B.u, B.t, B.b}) {
-          if (g->mixed) launch_zero<float>((float*)v, B.L.nslot, s);
+          if (tiles_only && g->mixed) launch_ad_zero<float>(B.ad(), (float*)v, s);
+          else if (tiles_only) launch_ad_zero<double>(B.ad(), (double*)v, s);
+          else if (g->mixed) launch_zero<float>((float*)v, B.L.nslot, s);
           else launch_zero<double>((double*)v, B.L.nslot, s);
         }
         if (l < g->lb) continue;
         double* bdst = g->mixed ? B.b64 : (double*)B.b;
         if (g->mixed) {
-          launch_zero<double>(B.x64, B.L.nslot, s);
-          launch_zero<double>(B.b64, B.L.nslot, s);
+          if (tiles_only) {
+            launch_ad_zero<double>(B.ad(), B.x64, s);
+            launch_ad_zero<double>(B.ad(), B.b64, s);
+          } else {
+            launch_zero<double>(B.x64, B.L.nslot, s);
+            launch_zero<double>(B.b64, B.L.nslot, s);
+          }
         }
         const int64_t cnt = (int64_t)g->hl[l].leaf.size();
         launch_ad_scatter<double>(g->unk_slots + uo, cnt, g->stage + uo, 1.0, bdst, s);
@@ -2023,6 +2038,7 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
     if (bad[2] > 0) throw ApiError(QMG_EINVAL, "the velocities must be finite");
     g->bnorm = std::sqrt(b2);
     g->have_coef = true;
+    if (g->adaptive) g->lattices_clear = true;
   });
 }
 

@@ -525,3 +525,36 @@ def test_stagnation_raise_to_base_matches_oracle():
     assert rep["coarsest_level_used"] == 3 and rep["cycles"] == k
     np.testing.assert_allclose(hist, hist_o, rtol=1e-9, atol=0)
     assert np.abs(u - u_o).max() <= 1e-10 * np.abs(u_o).max()
+
+
+def test_repeated_coefficients_equal_a_fresh_grid():
+    """A second set_coefficients on the same adaptive grid (new coefficients
+    and source) clears only the active tiles; its build and cycles must equal
+    those of a fresh grid given the same inputs, bit for bit."""
+    qmg = require_gpu()
+    announce("adaptive repeated set_coefficients")
+    P = W.adaptive_band(dim=3, base=1, level=3, seed=0)
+    G = AD.AdaptiveGrid(P.dim, P.base, P.level, P.flags)
+    eps, f = _workload_inputs(P, G)
+    rng = np.random.default_rng(4)
+    eps2 = eps * rng.uniform(0.5, 2.0, size=eps.shape)
+    f2 = rng.uniform(-1.0, 1.0, size=f.shape)
+    for transfer, store in (("boxmg", "bf16"), ("galerkin", "hier64")):
+        kw = dict(check_definite=False)
+        g = _grid(qmg, 3, P.base, P.level, P.flags, transfer=transfer, store=store, **kw)
+        g.set_coefficients(eps, f)
+        g.build()
+        g.solve(0.0, 2)
+        g.set_coefficients(eps2, f2)
+        g.build()
+        rep, hist = g.solve(0.0, 2)
+        u = g.solution()
+        g.close()
+        h = _grid(qmg, 3, P.base, P.level, P.flags, transfer=transfer, store=store, **kw)
+        h.set_coefficients(eps2, f2)
+        h.build()
+        rep_h, hist_h = h.solve(0.0, 2)
+        u_h = h.solution()
+        h.close()
+        assert np.array_equal(hist, hist_h), (transfer, hist, hist_h)
+        assert np.array_equal(u, u_h), transfer

@@ -299,16 +299,18 @@ __device__ inline bool orthant_refined(const int8_t* cref, const Lat& Lc, int Vx
   return cref[cx + (int64_t)cy * Lc.pitch + (int64_t)cz * Lc.plane] != 0;
 }
 
-// Two wavefronts per SIMD: the 3D patch systems otherwise take the whole
-// register file (one wavefront per SIMD); the bound spills some of them,
-// which is cheaper than the lost latency hiding (level-6 BoxMG of the band
-// workload 10.1 -> 8.7 ms).
+// MINW wavefronts per SIMD at least.  With 2 (the rediscretised rows of a
+// finest level) the 3D patch systems, which otherwise take the whole
+// register file, spill some registers, which is cheaper than the lost
+// latency hiding (level-6 BoxMG of the band workload 10.1 -> 8.7 ms); rows
+// read from a stored operator keep one wavefront (level 5: 1.06 against
+// 1.26 ms).
 // cref (nullable): refined flags of the coarse cells; patches of cells that
 // are not refined are skipped (adaptive levels)
 // cells (nullable): list of the refined coarse cells; thread (cell, corner)
 // solves the corner's orthant, which points into the cell
-template <int D>
-__global__ __launch_bounds__(64, 2) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, double* __restrict__ Pw,
+template <int D, int MINW>
+__global__ __launch_bounds__(64, MINW) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, double* __restrict__ Pw,
                                               const int8_t* __restrict__ cref, const int32_t* __restrict__ cells,
                                               int64_t ncells) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1271,14 +1273,18 @@ void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const doubl
   if (nt == 0) return;
   if (Lf.d == 2) {
     BoxFetch<2> F{Afine, epsf, Lf, vt_fine, vt_fine != nullptr};
-    hipLaunchKernelGGL(k_boxmg<2>, dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
+    hipLaunchKernelGGL((k_boxmg<2, 1>), dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
                        n_cells);
   } else {
     // 8 coarse cells (all their corners) per workgroup
     const int64_t nc = cells ? n_cells : (int64_t)Lc.n * Lc.n * Lc.n;
     BoxFetch<3> F{Afine, epsf, Lf, vt_fine, vt_fine != nullptr};
-    hipLaunchKernelGGL(k_boxmg<3>, dim3(blocks_for(nc, 8)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
-                       n_cells);
+    if (Afine == nullptr)
+      hipLaunchKernelGGL((k_boxmg<3, 2>), dim3(blocks_for(nc, 8)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
+                         n_cells);
+    else
+      hipLaunchKernelGGL((k_boxmg<3, 1>), dim3(blocks_for(nc, 8)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
+                         n_cells);
   }
   QMG_HIP(hipGetLastError());
 }

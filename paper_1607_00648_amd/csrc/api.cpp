@@ -1376,9 +1376,15 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
   // cell's coefficient, from which hanging rows are rediscretised
   if (g->adaptive && boxmg)
     for (int l = g->lb + 1; l <= L; ++l)
-      launch_ad_virtual_eps(g->lv[l].L, g->lv[l - 1].L, g->lv[l - 1].cref, g->lv[l - 1].eps64, g->lv[l].eps64, s);
+      launch_ad_virtual_eps(g->lv[l].L, g->lv[l - 1].L, g->lv[l - 1].cref, g->lv[l].vt, g->lv[l - 1].eps64,
+                            g->lv[l].eps64, s);
+  // single-precision coefficients; above the base level only the cells next
+  // to a vertex of the level, which are all a row reads
   if (g->mixed)
-    for (int l = g->lcq; l <= L; ++l) launch_convert<double, float>(g->lv[l].L, g->lv[l].eps64, g->lv[l].eps32, s);
+    for (int l = g->lcq; l <= L; ++l) {
+      if (g->adaptive && l > g->lb) launch_ad_convert_cells(g->lv[l].L, g->lv[l].vt, g->lv[l].eps64, g->lv[l].eps32, s);
+      else launch_convert<double, float>(g->lv[l].L, g->lv[l].eps64, g->lv[l].eps32, s);
+    }
   g->lc = g->lcq;
   assign_stores(g);  // views used by materialise below (plain stores)
   auto fullA = [&](int l) -> double* {
@@ -1388,13 +1394,14 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
   Store geom;
   // rows of an adaptive level: refined vertices keep the Galerkin (or
   // rediscretised) row, leaves take the rediscretised one, others none
-  auto merge = [&](int l, double* full) {
-    if (g->adaptive && l >= g->lb) launch_ad_merge_rows(g->lv[l].L, g->lv[l].vt, g->lv[l].eps64, full, s);
+  // (cleared: every other row holds zero already)
+  auto merge = [&](int l, double* full, bool cleared) {
+    if (g->adaptive && l >= g->lb) launch_ad_merge_rows(g->lv[l].L, g->lv[l].vt, g->lv[l].eps64, full, cleared, s);
   };
   if (g->plain) {
     launch_materialise(g->lv[L].L, g->lv[L].eps64, geom, g->lv[L].Adense, s);
     if (g->has_conv) launch_conv_add(g->lv[L].L, g->vel, g->lv[L].Adense, s);
-    merge(L, g->lv[L].Adense);
+    merge(L, g->lv[L].Adense, false);
   }
   for (int l = g->lcq; l <= L; ++l) {
     g->lv[l].Anz = -1;
@@ -1428,7 +1435,7 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
       // needed in full on the coarsest level for the exact solve
       if (g->plain || l - 1 == g->lcq) {
         launch_materialise(C.L, C.eps64, geom, Ac, s);
-        merge(l - 1, Ac);
+        merge(l - 1, Ac, false);
       }
     } else {
       launch_zero<double>(Ac, C.L.nslot * NS, s);
@@ -1444,7 +1451,8 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
       if (!by_cells)
         launch_rap(F.L, C.L, Afine, F.eps64, Pw, Ac, s, mask, adc ? C.vt : nullptr, adc ? C.rv : nullptr,
                    adc ? C.nrv : 0, g->opts.restriction);
-      merge(l - 1, Ac);
+      // the products write the listed refined rows only, over zero
+      merge(l - 1, Ac, true);
       // the fallback of a failed check raises the coarsest level, which is
       // possible only below the base level of an adaptive spacetree
       if (g->opts.check_definite && l - 1 < g->lb) {

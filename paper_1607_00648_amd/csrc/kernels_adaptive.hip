@@ -456,17 +456,87 @@ __global__ __launch_bounds__(256) void k_ad_correct_list(Lat Lf, Lat Lc, const i
   uf[v] += interp_at<D, T, PSRC, PFMT>(Lf, Lc, P, i, j, k, v, uc, sc);
 }
 
-// cell coefficients of cells that do not exist: the covering (parent) cell's
+// Cell kernels over a whole level: thread (I, J) takes kCellPlanes planes of
+// cells, with every load of a phase issued before any is used (a chain of
+// dependent loads per plane leaves these launches bound by memory latency).
+// A cell is read by a row only when one of its corners is a vertex of the
+// level (leaf, refined or hanging): every row the kernels form, at such
+// vertices, reads only such cells.  kCellPlanes is a multiple of 3, so that
+// the thread's planes start on a parent plane.
+constexpr int kCellPlanes = 15;
+
+inline dim3 cell_walk_grid(const Lat& L) {
+  return dim3((unsigned)(L.pitch / TX), (unsigned)((L.n + TY - 1) / TY),
+              (unsigned)(L.d == 3 ? (L.n + kCellPlanes - 1) / kCellPlanes : 1));
+}
+
+// Bit q (q < K1 - K0): cell (I, J, K0 + q) is read by a row of the level;
+// col: slot of (I, J) on plane 0, with I, J < n and K0 < K1 <= n.
+template <int D>
+__device__ inline uint32_t read_cell_planes(const Lat& L, const int8_t* __restrict__ vt, int64_t col, int K0,
+                                            int K1) {
+  uint32_t qm = 0;  // bit q: a corner (i..i+1, j..j+1) on plane K0 + q is a vertex
+#pragma unroll
+  for (int q = 0; q <= kCellPlanes; ++q) {
+    if (q > K1 - K0 || (D == 2 && q > 0)) break;
+    const int64_t v = col + (int64_t)(K0 + q) * L.plane;
+    const bool any = (vt[v] != VT_OUT) | (vt[v + 1] != VT_OUT) | (vt[v + L.pitch] != VT_OUT) |
+                     (vt[v + L.pitch + 1] != VT_OUT);
+    qm |= (uint32_t)any << q;
+  }
+  const uint32_t planes = (D == 3) ? (qm | (qm >> 1)) : qm;
+  return planes & ((1u << (K1 - K0)) - 1u);
+}
+
+// cell coefficients of cells that do not exist: the covering (parent) cell's;
+// only cells a row of the level (vertex classes vtf) reads are written
 template <int D>
 __global__ __launch_bounds__(256) void k_ad_virtual_eps(Lat Lf, Lat Lc, const int8_t* __restrict__ crefc,
+                                                        const int8_t* __restrict__ vtf,
                                                         const double* __restrict__ ec, double* __restrict__ ef) {
+  constexpr int NP = kCellPlanes / 3;  // parent planes of a thread
   const int I = blockIdx.x * TX + threadIdx.x;
   const int J = blockIdx.y * TY + threadIdx.y;
-  const int K = (D == 3) ? (int)blockIdx.z : 0;
-  if (I >= Lf.n || J >= Lf.n || (D == 3 && K >= Lf.n)) return;
-  const int64_t pc = I / 3 + (int64_t)(J / 3) * Lc.pitch + (int64_t)(K / 3) * Lc.plane;
-  if (crefc[pc]) return;
-  ef[I + (int64_t)J * Lf.pitch + (int64_t)K * Lf.plane] = ec[pc];
+  if (I >= Lf.n || J >= Lf.n) return;
+  const int K0 = (D == 3) ? (int)blockIdx.z * kCellPlanes : 0;
+  const int K1 = (D == 3) ? min(K0 + kCellPlanes, Lf.n) : 1;
+  const int64_t col = I + (int64_t)J * Lf.pitch;
+  const uint32_t m = read_cell_planes<D>(Lf, vtf, col, K0, K1);
+  if (m == 0) return;
+  const int64_t pcol = I / 3 + (int64_t)(J / 3) * Lc.pitch + (int64_t)(K0 / 3) * Lc.plane;
+  double pe[NP];
+  bool keep[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const bool need = ((m >> (3 * p)) & 7u) != 0;  // cell planes K0 + 3p .. K0 + 3p + 2
+    const int64_t pc = pcol + (int64_t)p * Lc.plane;
+    keep[p] = !need || crefc[pc] != 0;
+    pe[p] = need ? ec[pc] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < kCellPlanes; ++q)
+    if (((m >> q) & 1u) && !keep[q / 3]) ef[col + (int64_t)(K0 + q) * Lf.plane] = pe[q / 3];
+}
+
+// single-precision cell coefficients of an adaptive level on the cells a row
+// of the level reads
+template <int D>
+__global__ __launch_bounds__(256) void k_ad_convert_cells(Lat L, const int8_t* __restrict__ vt,
+                                                          const double* __restrict__ in, float* __restrict__ out) {
+  const int I = blockIdx.x * TX + threadIdx.x;
+  const int J = blockIdx.y * TY + threadIdx.y;
+  if (I >= L.n || J >= L.n) return;
+  const int K0 = (D == 3) ? (int)blockIdx.z * kCellPlanes : 0;
+  const int K1 = (D == 3) ? min(K0 + kCellPlanes, L.n) : 1;
+  const int64_t col = I + (int64_t)J * L.pitch + (int64_t)K0 * L.plane;
+  const uint32_t m = read_cell_planes<D>(L, vt, I + (int64_t)J * L.pitch, K0, K1);
+  if (m == 0) return;
+  double x[kCellPlanes];
+#pragma unroll
+  for (int q = 0; q < kCellPlanes; ++q) x[q] = ((m >> q) & 1u) ? in[col + (int64_t)q * L.plane] : 0.0;
+#pragma unroll
+  for (int q = 0; q < kCellPlanes; ++q)
+    if ((m >> q) & 1u) out[col + (int64_t)q * L.plane] = (float)x[q];
 }
 
 // dst := src on every slot of the listed tiles
@@ -477,13 +547,20 @@ __global__ __launch_bounds__(256) void k_ad_copy(Lat L, const int32_t* __restric
   if (s.valid) dst[s.v] = src[s.v];
 }
 
-// zero on every slot of the listed tiles
+// zero on every slot of the listed tiles; kZeroTiles tiles per workgroup (one
+// 256-slot tile per workgroup leaves the fill bound by workgroup dispatch)
+constexpr int kZeroTiles = 8;
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_ad_zero(Lat L, const int32_t* __restrict__ tiles, T* __restrict__ p,
-                                                 int narr) {
-  const Slot s = tile_slot<D>(L, tiles);
-  if (!s.valid) return;
-  for (int a = 0; a < narr; ++a) p[(int64_t)a * L.nslot + s.v] = (T)0;
+__global__ __launch_bounds__(256) void k_ad_zero(Lat L, const int32_t* __restrict__ tiles, int ntiles,
+                                                 T* __restrict__ p, int narr) {
+  const int q0 = (int)blockIdx.x * kZeroTiles, q1 = min(q0 + kZeroTiles, ntiles);
+  for (int q = q0; q < q1; ++q) {
+    const int32_t* t = tiles + 3 * (int64_t)q;
+    const int i = t[0] * TX + threadIdx.x, j = t[1] * TY + threadIdx.y, k = (D == 3) ? t[2] : 0;
+    if (i > L.n || j > L.n) continue;
+    const int64_t v = i + (int64_t)j * L.pitch + (int64_t)k * L.plane;
+    for (int a = 0; a < narr; ++a) p[(int64_t)a * L.nslot + v] = (T)0;
+  }
 }
 
 // x64 += e32 on the leaves; residual of the mixed loop at the leaves in FP64
@@ -526,9 +603,11 @@ __global__ __launch_bounds__(256) void k_ad_coarsen_eps(Lat Lf, Lat Lc, const in
 
 // stencil rows of a level for the next Galerkin product: refined rows keep the
 // Galerkin result, leaf rows take the rediscretised stencil, other rows zero
+// (cleared: they hold zero already and are not written)
 template <int D>
 __global__ __launch_bounds__(256) void k_ad_merge_rows(Lat L, const int8_t* __restrict__ vt,
-                                                       const double* __restrict__ eps, double* __restrict__ A) {
+                                                       const double* __restrict__ eps, double* __restrict__ A,
+                                                       int cleared) {
   constexpr int NS = Dim<D>::NS;
   const int i = blockIdx.x * TX + threadIdx.x;
   const int j = blockIdx.y * TY + threadIdx.y;
@@ -545,7 +624,7 @@ __global__ __launch_bounds__(256) void k_ad_merge_rows(Lat L, const int8_t* __re
       const bool in = ii >= 1 && ii < L.n && jj >= 1 && jj < L.n && (D == 2 || (kk >= 1 && kk < L.n));
       A[(int64_t)k * L.nslot + v] = in ? a[k] : 0.0;
     }
-  } else {
+  } else if (!cleared) {
     for (int k = 0; k < NS; ++k) A[(int64_t)k * L.nslot + v] = 0.0;
   }
 }
@@ -755,12 +834,18 @@ void launch_ad_correct(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, con
   QMG_HIP(hipGetLastError());
 }
 
-void launch_ad_virtual_eps(const Lat& Lf, const Lat& Lc, const int8_t* crefc, const double* ec, double* ef,
-                           hipStream_t s) {
-  const dim3 g((unsigned)(Lf.pitch / TX), (unsigned)((Lf.n + TY - 1) / TY), (unsigned)(Lf.d == 3 ? Lf.n : 1));
-  const dim3 bl(TX, TY, 1);
-  if (Lf.d == 2) hipLaunchKernelGGL(k_ad_virtual_eps<2>, g, bl, 0, s, Lf, Lc, crefc, ec, ef);
-  else hipLaunchKernelGGL(k_ad_virtual_eps<3>, g, bl, 0, s, Lf, Lc, crefc, ec, ef);
+void launch_ad_virtual_eps(const Lat& Lf, const Lat& Lc, const int8_t* crefc, const int8_t* vtf, const double* ec,
+                           double* ef, hipStream_t s) {
+  const dim3 g = cell_walk_grid(Lf), bl(TX, TY, 1);
+  if (Lf.d == 2) hipLaunchKernelGGL(k_ad_virtual_eps<2>, g, bl, 0, s, Lf, Lc, crefc, vtf, ec, ef);
+  else hipLaunchKernelGGL(k_ad_virtual_eps<3>, g, bl, 0, s, Lf, Lc, crefc, vtf, ec, ef);
+  QMG_HIP(hipGetLastError());
+}
+
+void launch_ad_convert_cells(const Lat& L, const int8_t* vt, const double* in, float* out, hipStream_t s) {
+  const dim3 g = cell_walk_grid(L), bl(TX, TY, 1);
+  if (L.d == 2) hipLaunchKernelGGL(k_ad_convert_cells<2>, g, bl, 0, s, L, vt, in, out);
+  else hipLaunchKernelGGL(k_ad_convert_cells<3>, g, bl, 0, s, L, vt, in, out);
   QMG_HIP(hipGetLastError());
 }
 
@@ -776,9 +861,9 @@ void launch_ad_copy(const AdTiles& t, const T* src, T* dst, hipStream_t s) {
 template <typename T>
 void launch_ad_zero(const AdTiles& t, T* p, hipStream_t s, int narr) {
   if (t.n <= 0) return;
-  const dim3 g = tiles_grid(t.n), bl(TX, TY, 1);
-  if (t.L.d == 2) hipLaunchKernelGGL((k_ad_zero<2, T>), g, bl, 0, s, t.L, t.tiles, p, narr);
-  else hipLaunchKernelGGL((k_ad_zero<3, T>), g, bl, 0, s, t.L, t.tiles, p, narr);
+  const dim3 g((unsigned)((t.n + kZeroTiles - 1) / kZeroTiles)), bl(TX, TY, 1);
+  if (t.L.d == 2) hipLaunchKernelGGL((k_ad_zero<2, T>), g, bl, 0, s, t.L, t.tiles, t.n, p, narr);
+  else hipLaunchKernelGGL((k_ad_zero<3, T>), g, bl, 0, s, t.L, t.tiles, t.n, p, narr);
   QMG_HIP(hipGetLastError());
 }
 
@@ -804,10 +889,11 @@ void launch_ad_coarsen_eps(const Lat& Lf, const Lat& Lc, const int8_t* cref, con
   QMG_HIP(hipGetLastError());
 }
 
-void launch_ad_merge_rows(const Lat& L, const int8_t* vt, const double* eps, double* A, hipStream_t s) {
+void launch_ad_merge_rows(const Lat& L, const int8_t* vt, const double* eps, double* A, bool cleared,
+                          hipStream_t s) {
   const dim3 g = full_grid(L), bl(TX, TY, 1);
-  if (L.d == 2) hipLaunchKernelGGL(k_ad_merge_rows<2>, g, bl, 0, s, L, vt, eps, A);
-  else hipLaunchKernelGGL(k_ad_merge_rows<3>, g, bl, 0, s, L, vt, eps, A);
+  if (L.d == 2) hipLaunchKernelGGL(k_ad_merge_rows<2>, g, bl, 0, s, L, vt, eps, A, (int)cleared);
+  else hipLaunchKernelGGL(k_ad_merge_rows<3>, g, bl, 0, s, L, vt, eps, A, (int)cleared);
   QMG_HIP(hipGetLastError());
 }
 

@@ -374,8 +374,12 @@ template <typename T>
 void launch_ad_correct(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, const T* sc, const Store& P,
                        hipStream_t s);
 // coefficients of the level-l cells that do not exist := their parent cell's
-void launch_ad_virtual_eps(const Lat& Lf, const Lat& Lc, const int8_t* crefc, const double* ec, double* ef,
-                           hipStream_t s);
+// vtf: vertex classes of the fine level; cells with no corner among its
+// vertices are not written (no row reads them)
+void launch_ad_virtual_eps(const Lat& Lf, const Lat& Lc, const int8_t* crefc, const int8_t* vtf, const double* ec,
+                           double* ef, hipStream_t s);
+// out := (float) in on the cells next to a vertex of the level (vt)
+void launch_ad_convert_cells(const Lat& L, const int8_t* vt, const double* in, float* out, hipStream_t s);
 template <typename T>
 void launch_ad_copy(const AdTiles& t, const T* src, T* dst, hipStream_t s);
 template <typename T>
@@ -383,7 +387,10 @@ void launch_ad_zero(const AdTiles& t, T* p, hipStream_t s, int narr = 1);  // na
 void launch_ad_axpy(const AdTiles& t, double* x, const float* e, hipStream_t s);
 void launch_ad_coarsen_eps(const Lat& Lf, const Lat& Lc, const int8_t* cref, const double* ef, double* ec,
                            hipStream_t s);
-void launch_ad_merge_rows(const Lat& L, const int8_t* vt, const double* eps, double* A, hipStream_t s);
+// cleared: A holds zero on every row but the refined ones (only leaf rows are
+// written)
+void launch_ad_merge_rows(const Lat& L, const int8_t* vt, const double* eps, double* A, bool cleared,
+                          hipStream_t s);
 template <typename T>
 void launch_ad_scatter(const int64_t* slots, int64_t n, const double* in, double scale, T* lat, hipStream_t s);
 template <typename T>

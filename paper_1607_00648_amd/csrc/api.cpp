@@ -1288,13 +1288,14 @@ void encode(qmg_grid_t* g, LevelBuf& B, const Lat& Lc, bool is_P, const double* 
   const double eps_mf = fmt == BPA ? g->opts.eps_mf : 0.0;
   const int64_t unit = (int64_t)(is_P ? (1 << B.L.d) : ipow(3, B.L.d)) * kSeg;
   // adaptive levels above the base level: only their listed tiles hold
-  // operators the cycles read
+  // operators the cycles read, and there only the slots of the level's
+  // vertices
   const bool tl = g->adaptive && B.tiles != nullptr && B.L.n > g->lv[g->lb].L.n;
   launch_delta_flags(B.L, Lc, is_P, full, B.eps64, blk, S(g), eps_mf, tl ? B.tiles : nullptr, tl ? B.ntiles : 0,
-                     g->opts.eps_zero);
+                     g->opts.eps_zero, tl ? B.vt : nullptr);
   launch_scan_blocks(blk, B.L.nslot / kSeg, g->dtotal + slot, S(g), off, unit, g->scan_tmp);
   launch_delta_write(B.L, Lc, is_P, fmt, full, B.eps64, blk, pay, sc, S(g), off, eps_mf, tl ? B.tiles : nullptr,
-                     tl ? B.ntiles : 0);
+                     tl ? B.ntiles : 0, tl ? B.vt : nullptr);
 }
 
 // The coarsest solve (a10): a dense inverse of the level's FP64 operator,

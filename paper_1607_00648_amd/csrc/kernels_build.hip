@@ -988,11 +988,12 @@ __global__ __launch_bounds__(256) void k_conv_add(Lat L, const double* __restric
 // ---------------------------------------------------------------------------
 template <int D, bool IS_P>
 __device__ inline int load_delta(const Lat& L, const Lat& Lc, const double* __restrict__ full,
-                                 const double* __restrict__ eps, int i, int j, int kz, int64_t v,
-                                 double (&dl)[27], double& refmax) {
+                                 const double* __restrict__ eps, const int8_t* __restrict__ vt, int i, int j,
+                                 int kz, int64_t v, double (&dl)[27], double& refmax) {
   constexpr int NE = IS_P ? Dim<D>::NC : Dim<D>::NS;
   refmax = 0.0;
-  if (!interior(L, i, j, kz)) {
+  // vt (adaptive levels): rows of slots outside the level are never read
+  if (!interior(L, i, j, kz) || (vt != nullptr && vt[v] == VT_OUT)) {
     for (int k = 0; k < NE; ++k) dl[k] = 0.0;
     return NE;
   }
@@ -1022,7 +1023,8 @@ template <int D, bool IS_P>
 __global__ __launch_bounds__(256) void k_delta_flags(Lat L, Lat Lc, const double* __restrict__ full,
                                                      const double* __restrict__ eps,
                                                      int32_t* __restrict__ blk, double eps_mf,
-                                                     const int32_t* __restrict__ tiles, double eps_zero) {
+                                                     const int32_t* __restrict__ tiles, double eps_zero,
+                                                     const int8_t* __restrict__ vt) {
   const int32_t* tl = tiles ? tiles + 3 * (int64_t)blockIdx.x : nullptr;
   const int i = (tl ? tl[0] : (int)blockIdx.x) * TX + threadIdx.x;
   const int j = (tl ? tl[1] : (int)blockIdx.y) * TY + threadIdx.y;
@@ -1032,7 +1034,7 @@ __global__ __launch_bounds__(256) void k_delta_flags(Lat L, Lat Lc, const double
   double dl[27], refmax;
   int nz = 0;
   if (inlat) {
-    const int ne = load_delta<D, IS_P>(L, Lc, full, eps, i, j, kz, v, dl, refmax);
+    const int ne = load_delta<D, IS_P>(L, Lc, full, eps, vt, i, j, kz, v, dl, refmax);
     if (eps_mf > 0.0) {
       nz = bpa_width(dl, ne, eps_mf);
     } else {
@@ -1166,7 +1168,8 @@ __global__ __launch_bounds__(256) void k_delta_write(Lat L, Lat Lc, const double
                                                      void* __restrict__ payload,
                                                      int8_t* __restrict__ scale,
                                                      const int64_t* __restrict__ boff, double eps_mf,
-                                                     const int32_t* __restrict__ tiles) {
+                                                     const int32_t* __restrict__ tiles,
+                                                     const int8_t* __restrict__ vt) {
   constexpr int NE = IS_P ? Dim<D>::NC : Dim<D>::NS;
   const int32_t* tl = tiles ? tiles + 3 * (int64_t)blockIdx.x : nullptr;
   const int i = (tl ? tl[0] : (int)blockIdx.x) * TX + threadIdx.x;
@@ -1177,7 +1180,7 @@ __global__ __launch_bounds__(256) void k_delta_write(Lat L, Lat Lc, const double
   const int32_t cb = blk[v / kSeg];
   if (cb < 0) return;
   double dl[27], refmax;
-  load_delta<D, IS_P>(L, Lc, full, eps, i, j, kz, v, dl, refmax);
+  load_delta<D, IS_P>(L, Lc, full, eps, vt, i, j, kz, v, dl, refmax);
   const int lane = (int)(v % kSeg);
   const int64_t base = (int64_t)cb * NE * kSeg + lane;
   if (FMT == BPA) {
@@ -1356,17 +1359,17 @@ void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s)
 
 void launch_delta_flags(const Lat& L, const Lat& Lc, bool is_P, const double* full, const double* eps,
                         int32_t* blk, hipStream_t s, double eps_mf, const int32_t* tiles, int ntiles,
-                        double eps_zero) {
+                        double eps_zero, const int8_t* vt) {
   if (!(eps_zero > 0.0)) eps_zero = kEpsZero;
   const dim3 g = tiles ? dim3((unsigned)ntiles) : tile_grid(L), bl(TX, TY, 1);
   if (tiles) launch_zero<int32_t>(blk, L.nslot / kSeg, s);  // blocks of unlisted tiles: zero
   if (tiles && ntiles == 0) return;
   if (L.d == 2) {
-    if (is_P) hipLaunchKernelGGL((k_delta_flags<2, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero);
-    else hipLaunchKernelGGL((k_delta_flags<2, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero);
+    if (is_P) hipLaunchKernelGGL((k_delta_flags<2, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero, vt);
+    else hipLaunchKernelGGL((k_delta_flags<2, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero, vt);
   } else {
-    if (is_P) hipLaunchKernelGGL((k_delta_flags<3, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero);
-    else hipLaunchKernelGGL((k_delta_flags<3, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero);
+    if (is_P) hipLaunchKernelGGL((k_delta_flags<3, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero, vt);
+    else hipLaunchKernelGGL((k_delta_flags<3, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero, vt);
   }
   QMG_HIP(hipGetLastError());
 }
@@ -1385,13 +1388,14 @@ void launch_scan_blocks(int32_t* blk, int64_t nblk, int32_t* total, hipStream_t 
 
 void launch_delta_write(const Lat& L, const Lat& Lc, bool is_P, int fmt, const double* full,
                         const double* eps, const int32_t* blk, void* payload, int8_t* scale,
-                        hipStream_t s, const int64_t* boff, double eps_mf, const int32_t* tiles, int ntiles) {
+                        hipStream_t s, const int64_t* boff, double eps_mf, const int32_t* tiles, int ntiles,
+                        const int8_t* vt) {
   const dim3 g = tiles ? dim3((unsigned)ntiles) : tile_grid(L), bl(TX, TY, 1);
   if (fmt == BPA && (!boff || !(eps_mf > 0.0))) throw std::runtime_error("BPA store without offsets or eps_mf");
   if (tiles && ntiles == 0) return;
 #define QMG_DW(DV, PV, FV) \
   hipLaunchKernelGGL((k_delta_write<DV, PV, FV>), g, bl, 0, s, L, Lc, full, eps, blk, payload, scale, boff, eps_mf, \
-                     tiles)
+                     tiles, vt)
 #define QMG_DW_F(DV, PV)                  \
   do {                                    \
     if (fmt == F64) QMG_DW(DV, PV, F64);  \

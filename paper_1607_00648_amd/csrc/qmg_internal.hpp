@@ -242,10 +242,13 @@ void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s)
 // boff (byte offset and width per compact block; `unit` = nent * 64 bytes per
 // width step).
 // tiles (nullable): only the listed 64 x 4 tiles of an adaptive level are
-// encoded; the blocks of the others are flagged zero.
+// encoded; the blocks of the others are flagged zero.  vt (nullable): the
+// level's vertex classes; slots outside the level (no row or weight of theirs
+// is ever read) take a zero delta, so that their blocks are not stored.
 void launch_delta_flags(const Lat& L, const Lat& Lc, bool is_P, const double* full,
                         const double* eps, int32_t* blk, hipStream_t s, double eps_mf = 0.0,
-                        const int32_t* tiles = nullptr, int ntiles = 0, double eps_zero = 0.0);
+                        const int32_t* tiles = nullptr, int ntiles = 0, double eps_zero = 0.0,
+                        const int8_t* vt = nullptr);
 // csum: device scratch of scan_scratch_ints(nblk) ints (chunk sums).
 void launch_scan_blocks(int32_t* blk, int64_t nblk, int32_t* total, hipStream_t s, int64_t* boff,
                         int64_t unit, int32_t* csum);
@@ -253,7 +256,7 @@ int64_t scan_scratch_ints(int64_t nblk);
 void launch_delta_write(const Lat& L, const Lat& Lc, bool is_P, int fmt, const double* full,
                         const double* eps, const int32_t* blk, void* payload, int8_t* scale,
                         hipStream_t s, const int64_t* boff = nullptr, double eps_mf = 0.0,
-                        const int32_t* tiles = nullptr, int ntiles = 0);
+                        const int32_t* tiles = nullptr, int ntiles = 0, const int8_t* vt = nullptr);
 
 // Coarse part of the V-cycle in one workgroup with levels lc..lf held in LDS
 // (lf starting from zero after its right-hand side was restricted into b of

@@ -1395,7 +1395,7 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
   Store geom;
   // rows of an adaptive level: refined vertices keep the Galerkin (or
   // rediscretised) row, leaves take the rediscretised one, others none
-  // (cleared: every other row holds zero already)
+  // (cleared: the other rows of the level's vertices hold zero already)
   auto merge = [&](int l, double* full, bool cleared) {
     if (g->adaptive && l >= g->lb) launch_ad_merge_rows(g->lv[l].L, g->lv[l].vt, g->lv[l].eps64, full, cleared, s);
   };
@@ -1419,7 +1419,8 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
       double* Pt = g->plain ? F.Pdense : g->tmpP;
       const bool ad = g->adaptive && l > g->lb;
       // adaptive levels: P lives on the listed tiles only (the encoder and
-      // the kernels read nothing else)
+      // the kernels read nothing else; whole rows of 64 slots are cheaper to
+      // clear than the vertices' slots alone)
       if (ad) launch_ad_zero<double>(F.ad(), Pt, s, NC);
       else launch_zero<double>(Pt, F.L.nslot * NC, s);
       launch_boxmg(F.L, C.L, Afine, F.eps64, Pt, s, ad ? F.vt : nullptr, ad ? C.cref : nullptr,
@@ -1439,7 +1440,10 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
         merge(l - 1, Ac, false);
       }
     } else {
-      launch_zero<double>(Ac, C.L.nslot * NS, s);
+      // adaptive levels above the base: rows of the level's vertices only
+      // (no kernel and not the encoder reads others)
+      if (g->adaptive && l - 1 > g->lb) launch_ad_zero<double>(C.ad(), Ac, s, NS, true);
+      else launch_zero<double>(Ac, C.L.nslot * NS, s);
       // the finest adaptive level's rows exist only at leaf vertices
       const int8_t* mask = (g->adaptive && l == L && !Afine) ? F.vt : nullptr;
       const bool adc = g->adaptive && l - 1 >= g->lb;
@@ -1596,6 +1600,14 @@ void need_ops(qmg_grid_t* g) {
 void copy_in(qmg_grid_t* g, double* dst_dev, const double* src, int64_t n, int mem) {
   QMG_HIP(hipMemcpyAsync(dst_dev, src, n * sizeof(double),
                          mem == QMG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, S(g)));
+}
+
+// Device array the input checks read: the caller's own for device memory,
+// else the staging buffer after a copy from the host.
+const double* input_on_device(qmg_grid_t* g, const double* src, int64_t n, int mem) {
+  if (mem == QMG_DEVICE) return src;
+  copy_in(g, g->stage, src, n, mem);
+  return g->stage;
 }
 
 // Lattice arrays in host inspection calls have (n+1)^d values without padding.
@@ -1959,8 +1971,8 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
     };
     launch_zero<int>(g->dcount, 3, s);
     // cell coefficients: staged, checked on the device, scattered per level
-    copy_in(g, g->stage, eps, ncell, mem);
-    launch_prep_input(g->stage, ncell, 1.0, true, g->partial, blocks(ncell, 1), g->dcount, s);
+    launch_prep_input(input_on_device(g, eps, ncell, mem), g->stage, ncell, 1.0, true, g->partial,
+                      blocks(ncell, 1), g->dcount, s);
     if (g->adaptive) {
       int64_t co = 0;
       for (int l = g->lb; l <= g->Lmax; ++l) {
@@ -1981,13 +1993,13 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
       if (!g->vel) QMG_HIP(hipMalloc(&g->vel, (size_t)g->d * L.nslot * sizeof(double)));
       launch_zero<double>(g->vel, (int64_t)g->d * L.nslot, s);
       for (int c = 0; c < g->d; ++c) {
-        copy_in(g, g->stage, eps + (int64_t)(1 + c) * ncell, ncell, mem);
-        launch_prep_input(g->stage, ncell, 1.0, false, g->partial, blocks(ncell, 1), g->dcount + 2, s);
+        launch_prep_input(input_on_device(g, eps + (int64_t)(1 + c) * ncell, ncell, mem), g->stage, ncell, 1.0,
+                          false, g->partial, blocks(ncell, 1), g->dcount + 2, s);
         launch_scatter_cells<double>(L, g->stage, g->vel + (int64_t)c * L.nslot, s);
       }
     }
     // right-hand side b = h_l^d f of every unknown (level l), and its norm
-    copy_in(g, g->stage, f, nu, mem);
+    const double* fin = input_on_device(g, f, nu, mem);
     const int nlev = g->Lmax - g->lb + 1;
     int np = 0;
     int64_t off = 0;
@@ -1997,7 +2009,7 @@ int qmg_set_coefficients(qmg_grid_t* g, const double* eps, int ncomp, const doub
       const int64_t cnt = g->adaptive ? (int64_t)g->hl[l].leaf.size() : nu;
       const int nb = blocks(cnt, nlev);
       if (cnt > 0) {
-        launch_prep_input(g->stage + off, cnt, hd, false, g->partial + np, nb, g->dcount + 1, s);
+        launch_prep_input(fin + off, g->stage + off, cnt, hd, false, g->partial + np, nb, g->dcount + 1, s);
         np += nb;
       }
       off += cnt;

@@ -547,18 +547,20 @@ __global__ __launch_bounds__(256) void k_ad_copy(Lat L, const int32_t* __restric
   if (s.valid) dst[s.v] = src[s.v];
 }
 
-// zero on every slot of the listed tiles; kZeroTiles tiles per workgroup (one
-// 256-slot tile per workgroup leaves the fill bound by workgroup dispatch)
+// zero on every slot of the listed tiles (vt given: on the slots of the
+// level's vertices only); kZeroTiles tiles per workgroup (one 256-slot tile
+// per workgroup leaves the fill bound by workgroup dispatch)
 constexpr int kZeroTiles = 8;
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_ad_zero(Lat L, const int32_t* __restrict__ tiles, int ntiles,
-                                                 T* __restrict__ p, int narr) {
+                                                 T* __restrict__ p, int narr, const int8_t* __restrict__ vt) {
   const int q0 = (int)blockIdx.x * kZeroTiles, q1 = min(q0 + kZeroTiles, ntiles);
   for (int q = q0; q < q1; ++q) {
     const int32_t* t = tiles + 3 * (int64_t)q;
     const int i = t[0] * TX + threadIdx.x, j = t[1] * TY + threadIdx.y, k = (D == 3) ? t[2] : 0;
     if (i > L.n || j > L.n) continue;
     const int64_t v = i + (int64_t)j * L.pitch + (int64_t)k * L.plane;
+    if (vt != nullptr && vt[v] == VT_OUT) continue;
     for (int a = 0; a < narr; ++a) p[(int64_t)a * L.nslot + v] = (T)0;
   }
 }
@@ -603,7 +605,8 @@ __global__ __launch_bounds__(256) void k_ad_coarsen_eps(Lat Lf, Lat Lc, const in
 
 // stencil rows of a level for the next Galerkin product: refined rows keep the
 // Galerkin result, leaf rows take the rediscretised stencil, other rows zero
-// (cleared: they hold zero already and are not written)
+// (cleared: those of the level's vertices hold zero already, and rows outside
+// the level are never read; neither is written)
 template <int D>
 __global__ __launch_bounds__(256) void k_ad_merge_rows(Lat L, const int8_t* __restrict__ vt,
                                                        const double* __restrict__ eps, double* __restrict__ A,
@@ -859,11 +862,12 @@ void launch_ad_copy(const AdTiles& t, const T* src, T* dst, hipStream_t s) {
 }
 
 template <typename T>
-void launch_ad_zero(const AdTiles& t, T* p, hipStream_t s, int narr) {
+void launch_ad_zero(const AdTiles& t, T* p, hipStream_t s, int narr, bool vertices_only) {
   if (t.n <= 0) return;
   const dim3 g((unsigned)((t.n + kZeroTiles - 1) / kZeroTiles)), bl(TX, TY, 1);
-  if (t.L.d == 2) hipLaunchKernelGGL((k_ad_zero<2, T>), g, bl, 0, s, t.L, t.tiles, t.n, p, narr);
-  else hipLaunchKernelGGL((k_ad_zero<3, T>), g, bl, 0, s, t.L, t.tiles, t.n, p, narr);
+  const int8_t* vt = vertices_only ? t.vt : nullptr;
+  if (t.L.d == 2) hipLaunchKernelGGL((k_ad_zero<2, T>), g, bl, 0, s, t.L, t.tiles, t.n, p, narr, vt);
+  else hipLaunchKernelGGL((k_ad_zero<3, T>), g, bl, 0, s, t.L, t.tiles, t.n, p, narr, vt);
   QMG_HIP(hipGetLastError());
 }
 
@@ -920,8 +924,8 @@ template void launch_ad_correct<double>(const AdTiles&, const Lat&, double*, con
 template void launch_ad_correct<float>(const AdTiles&, const Lat&, float*, const float*, const float*, const Store&, hipStream_t);
 template void launch_ad_copy<double>(const AdTiles&, const double*, double*, hipStream_t);
 template void launch_ad_copy<float>(const AdTiles&, const float*, float*, hipStream_t);
-template void launch_ad_zero<double>(const AdTiles&, double*, hipStream_t, int);
-template void launch_ad_zero<float>(const AdTiles&, float*, hipStream_t, int);
+template void launch_ad_zero<double>(const AdTiles&, double*, hipStream_t, int, bool);
+template void launch_ad_zero<float>(const AdTiles&, float*, hipStream_t, int, bool);
 template void launch_ad_scatter<double>(const int64_t*, int64_t, const double*, double, double*, hipStream_t);
 template void launch_ad_scatter<float>(const int64_t*, int64_t, const double*, double, float*, hipStream_t);
 template void launch_ad_gather<double>(const int64_t*, int64_t, const double*, double*, hipStream_t);

@@ -316,6 +316,7 @@ __global__ __launch_bounds__(64, MINW) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> 
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int m = Lc.n - 1;
   int orth, Vx, Vy, Vz;
+  bool uniform = false;  // d-linear weights without the solve
   __shared__ double pl[27 * 64];
   if constexpr (D == 3) {
     // 3D: the 64 threads are the 8 corners of 8 coarse cells (the listed
@@ -340,6 +341,29 @@ __global__ __launch_bounds__(64, MINW) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> 
       cc[3 * lc + 2] = z;
     }
     __syncthreads();
+    // Rediscretised rows: every row of the cell's eight orthant systems reads
+    // only the cell's fine cells and the layer of fine cells around them.  A
+    // constant coefficient there makes the rows those of constant eps, for
+    // which BoxMG reproduces the d-linear weights (up to rounding); they are
+    // then written without the solve.  The eight lanes of the cell split the
+    // 125 cells (those inside the domain).
+    if (F.A == nullptr) {
+      const int x0 = 3 * cc[3 * lc] - 1, y0 = 3 * cc[3 * lc + 1] - 1, z0 = 3 * cc[3 * lc + 2] - 1;
+      double lo = INFINITY, hi = -INFINITY;
+      for (int e = (int)(threadIdx.x & 7); e < 125; e += 8) {
+        const int x = x0 + e % 5, y = y0 + (e / 5) % 5, z = z0 + e / 25;
+        if (x < 0 || y < 0 || z < 0 || x >= Lf.n || y >= Lf.n || z >= Lf.n) continue;
+        const double v = F.eps[x + (int64_t)y * Lf.pitch + (int64_t)z * Lf.plane];
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+      }
+#pragma unroll
+      for (int o = 1; o < 8; o <<= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o, 64));
+        hi = fmax(hi, __shfl_xor(hi, o, 64));
+      }
+      uniform = lo == hi;
+    }
     if (!active) return;
     orth = (int)(threadIdx.x & 7);
     Vx = cc[3 * lc] + (orth & 1);
@@ -367,19 +391,31 @@ __global__ __launch_bounds__(64, MINW) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> 
   const int sx = (orth & 1) ? -1 : 1, sy = (orth & 2) ? -1 : 1, sz = (D == 3 && (orth & 4)) ? -1 : 1;
   if (cref && !orthant_refined(cref, Lc, Vx, Vy, Vz, sx, sy, sz)) return;
   const PCol p{pl + threadIdx.x};
+  if (uniform) {
+    // d-linear weight of V at 3V + s y: the product over the axes of 1 - y_i / 3
 #pragma unroll
-  for (int q = 0; q < 27; ++q) p[q] = 0.0;
-  p[0] = 1.0;
-  box_group<D, 1>(F, Vx, Vy, Vz, sx, sy, sz, p);
-  box_group<D, 2>(F, Vx, Vy, Vz, sx, sy, sz, p);
-  if constexpr (D == 3) {
-    box_group<D, 4>(F, Vx, Vy, Vz, sx, sy, sz, p);
-    box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p);
-    box_group<D, 5>(F, Vx, Vy, Vz, sx, sy, sz, p);
-    box_group<D, 6>(F, Vx, Vy, Vz, sx, sy, sz, p);
-    box_group<D, 7>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    for (int q = 0; q < 27; ++q) {
+      const int y0 = q % 3, y1 = (q / 3) % 3, y2 = q / 9;
+      const double w0 = y0 == 0 ? 1.0 : (y0 == 1 ? 2.0 / 3.0 : 1.0 / 3.0);
+      const double w1 = y1 == 0 ? 1.0 : (y1 == 1 ? 2.0 / 3.0 : 1.0 / 3.0);
+      const double w2 = y2 == 0 ? 1.0 : (y2 == 1 ? 2.0 / 3.0 : 1.0 / 3.0);
+      p[pidx(y0, y1, y2)] = w0 * w1 * w2;
+    }
   } else {
-    box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p);
+#pragma unroll
+    for (int q = 0; q < 27; ++q) p[q] = 0.0;
+    p[0] = 1.0;
+    box_group<D, 1>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    box_group<D, 2>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    if constexpr (D == 3) {
+      box_group<D, 4>(F, Vx, Vy, Vz, sx, sy, sz, p);
+      box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p);
+      box_group<D, 5>(F, Vx, Vy, Vz, sx, sy, sz, p);
+      box_group<D, 6>(F, Vx, Vy, Vz, sx, sy, sz, p);
+      box_group<D, 7>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    } else {
+      box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p);
+    }
   }
   // write the reference region; a point on an axis (y_i = 0) is shared by the
   // orthants that differ only on such axes.  It is written by the one of
@@ -792,6 +828,7 @@ __global__ __launch_bounds__(64) void k_rap_cells3(Lat Lf, Lat Lc, const double*
   const int64_t vb = bx + (int64_t)by * Lf.pitch + (int64_t)bz * Lf.plane;
   const int8_t cls = vt_fine ? vt_fine[vb] : (int8_t)VT_LEAF;
   const bool has_row = cls == VT_LEAF || cls == VT_REFINED;
+  bool dlin = true;  // every weight the d-linear one, bit for bit
 #pragma unroll
   for (int cc = 0; cc < 8; ++cc) {
     const int kx = (cc & 1) - (lx == 3 ? 1 : 0), ky = ((cc >> 1) & 1) - (ly == 3 ? 1 : 0),
@@ -803,7 +840,9 @@ __global__ __launch_bounds__(64) void k_rap_cells3(Lat Lf, Lat Lc, const double*
                      !(kz == 1 && lz == 0);
     if (par) {
       const int kap = kx | (ky << 1) | (kz << 2);
-      w = Pw ? Pw[(int64_t)kap * Lf.nslot + vb] : dlin1(bx % 3, kx) * dlin1(by % 3, ky) * dlin1(bz % 3, kz);
+      const double wd = dlin1(bx % 3, kx) * dlin1(by % 3, ky) * dlin1(bz % 3, kz);
+      w = Pw ? Pw[(int64_t)kap * Lf.nslot + vb] : wd;
+      dlin = dlin && w == wd;
     }
     P[t * 8 + cc] = w;
   }
@@ -813,6 +852,16 @@ __global__ __launch_bounds__(64) void k_rap_cells3(Lat Lf, Lat Lc, const double*
     E[t] = eps[(3 * Cx + ex) + (int64_t)(3 * Cy + ey) * Lf.pitch + (int64_t)(3 * Cz + ez) * Lf.plane];
   }
   __syncthreads();
+  // Every fine vertex of the cell inside the domain, with a row and the
+  // d-linear weights, and one coefficient on the 27 fine cells: the product
+  // is then the Galerkin product of nested d-linear spaces, the coarse
+  // element matrix of that coefficient (side 3h), written without the sums.
+  if (__syncthreads_and(has_row && dlin && interior(Lf, bx, by, bz) && (t >= 27 || E[t] == E[0]))) {
+    const int V = t >> 3, Wc = t & 7;
+    const int nd = (V ^ Wc) == 0 ? 0 : __popc((unsigned)(V ^ Wc));
+    AC[ci * 64 + t] = kref(3, nd) * E[0] * (3.0 * Lf.h);
+    return;
+  }
   {
     double acc[8];
 #pragma unroll

@@ -650,16 +650,17 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(double* __restrict__ a, i
 // x *= scale over [0, n) (grid-stride); per-block sums of squares of the
 // scaled values; *bad counts entries that are not finite (or, with positive,
 // not > 0).
-__global__ __launch_bounds__(256) void k_prep_input(double* __restrict__ x, int64_t n, double scale, int positive,
-                                                    double* __restrict__ partial, int* __restrict__ bad) {
+__global__ __launch_bounds__(256) void k_prep_input(const double* src, double* dst, int64_t n, double scale,
+                                                    int positive, double* __restrict__ partial,
+                                                    int* __restrict__ bad) {
   __shared__ double red[4];
   double sq = 0.0;
   int nbad = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = x[i];
+    const double v = src[i];
     if (!isfinite(v) || (positive && !(v > 0.0))) ++nbad;
     const double w = v * scale;
-    x[i] = w;
+    dst[i] = w;
     sq += w * w;
   }
 #pragma unroll
@@ -789,10 +790,11 @@ void launch_residual_mixed(const Lat& L, const double* x, const double* b, float
   QMG_HIP(hipGetLastError());
 }
 
-void launch_prep_input(double* x, int64_t n, double scale, bool positive, double* partial, int blocks, int* bad,
-                       hipStream_t s) {
+void launch_prep_input(const double* src, double* dst, int64_t n, double scale, bool positive, double* partial,
+                       int blocks, int* bad, hipStream_t s) {
   if (n <= 0 || blocks <= 0) return;
-  hipLaunchKernelGGL(k_prep_input, dim3((unsigned)blocks), dim3(256), 0, s, x, n, scale, positive ? 1 : 0, partial, bad);
+  hipLaunchKernelGGL(k_prep_input, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n, scale, positive ? 1 : 0,
+                     partial, bad);
   QMG_HIP(hipGetLastError());
 }
 

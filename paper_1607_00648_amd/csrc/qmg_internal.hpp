@@ -128,11 +128,12 @@ void launch_residual_mixed(const Lat& L, const double* x, const double* b, float
 // Sum of `n` partials into out[0] in a fixed order (one workgroup).  With
 // `hist`, the sum is also stored at hist[*counter] (when below cap) and the
 // device counter advanced, so that replayed cycles keep a norm history.
-// Input staging: x *= scale in place (grid-stride over `blocks` blocks of 256),
-// per-block sums of squares of the scaled values into partial[0..blocks), and
-// a count of non-finite (or, with positive, non-positive) entries added to *bad.
-void launch_prep_input(double* x, int64_t n, double scale, bool positive, double* partial, int blocks, int* bad,
-                       hipStream_t s);
+// Input staging: dst = scale * src (grid-stride over `blocks` blocks of 256;
+// src may be dst, or the caller's device array), per-block sums of squares of
+// the scaled values into partial[0..blocks), and a count of non-finite (or,
+// with positive, non-positive) entries of src added to *bad.
+void launch_prep_input(const double* src, double* dst, int64_t n, double scale, bool positive, double* partial,
+                       int blocks, int* bad, hipStream_t s);
 void launch_sum_partials(const double* partial, int n, double* out, hipStream_t s,
                          double* hist = nullptr, int* counter = nullptr, int cap = 0);
 // `chunk` cycles' partial sums at once (stride apart) into hist[0..chunk);
@@ -386,12 +387,15 @@ void launch_ad_convert_cells(const Lat& L, const int8_t* vt, const double* in, f
 template <typename T>
 void launch_ad_copy(const AdTiles& t, const T* src, T* dst, hipStream_t s);
 template <typename T>
-void launch_ad_zero(const AdTiles& t, T* p, hipStream_t s, int narr = 1);  // narr lattice arrays back to back
+// narr lattice arrays back to back; vertices_only: the slots of the level's
+// vertices (not outside) only
+void launch_ad_zero(const AdTiles& t, T* p, hipStream_t s, int narr = 1, bool vertices_only = false);
 void launch_ad_axpy(const AdTiles& t, double* x, const float* e, hipStream_t s);
 void launch_ad_coarsen_eps(const Lat& Lf, const Lat& Lc, const int8_t* cref, const double* ef, double* ec,
                            hipStream_t s);
-// cleared: A holds zero on every row but the refined ones (only leaf rows are
-// written)
+// cleared: A holds zero on the rows of the level's vertices but the refined
+// ones (only leaf rows are written; rows of slots outside the level are never
+// read)
 void launch_ad_merge_rows(const Lat& L, const int8_t* vt, const double* eps, double* A, bool cleared,
                           hipStream_t s);
 template <typename T>

@@ -1418,11 +1418,9 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
     if (boxmg) {
       double* Pt = g->plain ? F.Pdense : g->tmpP;
       const bool ad = g->adaptive && l > g->lb;
-      // adaptive levels: P lives on the listed tiles only (the encoder and
-      // the kernels read nothing else; whole rows of 64 slots are cheaper to
-      // clear than the vertices' slots alone)
-      if (ad) launch_ad_zero<double>(F.ad(), Pt, s, NC);
-      else launch_zero<double>(Pt, F.L.nslot * NC, s);
+      // adaptive levels: every weight of the level's vertices (all the
+      // encoder and the kernels read) is written by the BoxMG kernel itself
+      if (!ad) launch_zero<double>(Pt, F.L.nslot * NC, s);
       launch_boxmg(F.L, C.L, Afine, F.eps64, Pt, s, ad ? F.vt : nullptr, ad ? C.cref : nullptr,
                    ad ? C.rc : nullptr, ad ? C.nrc : 0);
       Pw = Pt;

@@ -299,6 +299,29 @@ __device__ inline bool orthant_refined(const int8_t* cref, const Lat& Lc, int Vx
   return cref[cx + (int64_t)cy * Lc.pitch + (int64_t)cz * Lc.plane] != 0;
 }
 
+// Weights towards a coarse corner V on the Dirichlet boundary are dropped:
+// zero on the interior fine vertices 3V + s y (y in 0..2 per axis) of the
+// orthant s that points into a refined cell, with the entries towards the
+// second parent along the shared axes (y_i = 0; weight zero).  Several
+// threads may write the same zeros.
+template <int D>
+__device__ inline void zero_boundary_orthant(const Lat& Lf, double* __restrict__ Pw, int Vx, int Vy, int Vz,
+                                             int sx, int sy, int sz) {
+  const int zmax = (D == 3) ? 3 : 1;
+  for (int yz = 0; yz < zmax; ++yz)
+    for (int yy = 0; yy < 3; ++yy)
+      for (int yx = 0; yx < 3; ++yx) {
+        const int fx = 3 * Vx + sx * yx, fy = 3 * Vy + sy * yy, fz = 3 * Vz + sz * yz;
+        if (!interior(Lf, fx, fy, fz)) continue;
+        const int zmask = (yx == 0 ? 1 : 0) | (yy == 0 ? 2 : 0) | ((D == 3 && yz == 0) ? 4 : 0);
+        const int kap = ((sx < 0 && yx > 0) ? 1 : 0) | ((sy < 0 && yy > 0) ? 2 : 0) |
+                        ((D == 3 && sz < 0 && yz > 0) ? 4 : 0);
+        const int64_t vf = fx + (int64_t)fy * Lf.pitch + (int64_t)fz * Lf.plane;
+        for (int sub = 0; sub < (1 << D); ++sub)
+          if ((sub & ~zmask) == 0) Pw[(int64_t)(kap | sub) * Lf.nslot + vf] = 0.0;
+      }
+}
+
 // MINW wavefronts per SIMD at least.  With 2 (the rediscretised rows of a
 // finest level) the 3D patch systems, which otherwise take the whole
 // register file, spill some registers, which is cheaper than the lost
@@ -369,7 +392,11 @@ __global__ __launch_bounds__(64, MINW) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> 
     Vx = cc[3 * lc] + (orth & 1);
     Vy = cc[3 * lc + 1] + ((orth >> 1) & 1);
     Vz = cc[3 * lc + 2] + ((orth >> 2) & 1);
-    if (!interior(Lc, Vx, Vy, Vz)) return;
+    if (!interior(Lc, Vx, Vy, Vz)) {
+      if (cells) zero_boundary_orthant<D>(Lf, Pw, Vx, Vy, Vz, (orth & 1) ? -1 : 1, (orth & 2) ? -1 : 1,
+                                          (orth & 4) ? -1 : 1);
+      return;
+    }
   } else if (cells) {
     if (t >= ncells * Dim<D>::NC) return;
     orth = (int)(t % Dim<D>::NC);
@@ -378,7 +405,11 @@ __global__ __launch_bounds__(64, MINW) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> 
     Vx = (int)(c % n) + (orth & 1);
     Vy = (int)((c / n) % n) + ((orth >> 1) & 1);
     Vz = (D == 3) ? (int)(c / ((int64_t)n * n)) + ((orth >> 2) & 1) : 0;
-    if (!interior(Lc, Vx, Vy, Vz)) return;
+    if (!interior(Lc, Vx, Vy, Vz)) {
+      zero_boundary_orthant<D>(Lf, Pw, Vx, Vy, Vz, (orth & 1) ? -1 : 1, (orth & 2) ? -1 : 1,
+                               (D == 3 && (orth & 4)) ? -1 : 1);
+      return;
+    }
   } else {
     const int64_t nV = (D == 3) ? (int64_t)m * m * m : (int64_t)m * m;
     if (t >= nV * Dim<D>::NC) return;
@@ -447,6 +478,11 @@ __global__ __launch_bounds__(64, MINW) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> 
                         ((D == 3 && sz < 0 && yz > 0) ? 4 : 0);
         const int64_t vf = fx + (int64_t)fy * Lf.pitch + (int64_t)fz * Lf.plane;
         Pw[(int64_t)kap * Lf.nslot + vf] = p[pidx(yx, yy, yz)];
+        // the entries towards the second parent along the shared axes (at
+        // distance 3: weight zero), which no orthant computes; with them every
+        // entry of every fine vertex of a refined coarse cell is written once
+        for (int sub = 1; sub < (1 << D); ++sub)
+          if ((sub & ~zmask) == 0) Pw[(int64_t)(kap | sub) * Lf.nslot + vf] = 0.0;
       }
 }
 

@@ -183,12 +183,10 @@ __global__ __launch_bounds__(BX * BY) void k_ad_march(Lat L, const int32_t* __re
     __syncthreads();
     const int64_t v = vij + (int64_t)k * L.plane;
     if (tv == VT_LEAF || tv == VT_REFINED) {
-      T a[NS];
-      if (SRC == SRC_PLAIN) {
-        const double* Ad = (const double*)A.dense;
-#pragma unroll
-        for (int q = 0; q < NS; ++q) a[q] = (T)Ad[(int64_t)q * L.nslot + v];
-      } else {
+      T au = (T)0, dg = (T)0;
+      if (SRC == SRC_GEOM) {
+        // rediscretised entries formed and applied one at a time (no row
+        // array held in registers); same operations in the same order
         T ce[8];
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
@@ -198,27 +196,51 @@ __global__ __launch_bounds__(BX * BY) void k_ad_march(Lat L, const int32_t* __re
         const T hs = (T)L.h;
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-          if (kref(3, ndiff_of<3>(q)) == 0.0) {
-            a[q] = (T)0;
-            continue;
-          }
+          if (kref(3, ndiff_of<3>(q)) == 0.0) continue;
           T e = (T)0;
 #pragma unroll
           for (int c = 0; c < 8; ++c)
             if (cell_has<3>(c, q)) e += ce[c];
-          a[q] = hs * (T)kref(3, ndiff_of<3>(q)) * e;
+          const T aq = hs * (T)kref(3, ndiff_of<3>(q)) * e;
+          if (q == NS / 2) dg = aq;
+          au += aq * up[(k + off_z(q) + 3) % 3][(ly + 1 + off_y(q)) * BUW + (lx + 1 + off_x(q))];
         }
-        if (SRC == SRC_HIER) add_delta<FMT, NS, T>(A, v, a);
-      }
-      T au = (T)0;
+      } else {
+        T a[NS];
+        if (SRC == SRC_PLAIN) {
+          const double* Ad = (const double*)A.dense;
 #pragma unroll
-      for (int q = 0; q < NS; ++q) {
-        if (SRC == SRC_GEOM && kref(3, ndiff_of<3>(q)) == 0.0) continue;
-        au += a[q] * up[(k + off_z(q) + 3) % 3][(ly + 1 + off_y(q)) * BUW + (lx + 1 + off_x(q))];
+          for (int q = 0; q < NS; ++q) a[q] = (T)Ad[(int64_t)q * L.nslot + v];
+        } else {
+          T ce[8];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const int sx = c & 1, sy = (c >> 1) & 1, sz = (c >> 2) & 1;
+            ce[c] = ep[(k - sz) % 2][(ly + 1 - sy) * BEW + (lx + 1 - sx)];
+          }
+          const T hs = (T)L.h;
+#pragma unroll
+          for (int q = 0; q < NS; ++q) {
+            if (kref(3, ndiff_of<3>(q)) == 0.0) {
+              a[q] = (T)0;
+              continue;
+            }
+            T e = (T)0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+              if (cell_has<3>(c, q)) e += ce[c];
+            a[q] = hs * (T)kref(3, ndiff_of<3>(q)) * e;
+          }
+          add_delta<FMT, NS, T>(A, v, a);
+        }
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+          au += a[q] * up[(k + off_z(q) + 3) % 3][(ly + 1 + off_y(q)) * BUW + (lx + 1 + off_x(q))];
+        dg = a[NS / 2];
       }
       const T uc = up[k % 3][(ly + 1) * BUW + lx + 1];
       if (MODE == 0) {
-        out[v] = (TO)(uc + omega * (bv - au) / a[NS / 2]);
+        out[v] = (TO)(uc + omega * (bv - au) / dg);
       } else {
         const T res = bv - au;
         out[v] = (TO)res;

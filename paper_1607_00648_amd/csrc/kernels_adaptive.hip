@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_ad_stencil(Lat L, const int32_t* __rest
   }
 }
 
-// 3D adaptive levels: a workgroup of kBrickX x kBrickY threads (32 x 16; a
+// 3D adaptive levels: a workgroup of kBrickX x kBrickY threads (32 x 8; a
 // wavefront covers two x-rows) owns one listed brick of as many slots and
 // marches over its 16 interior planes.  Three planes of the
 // iterate (brick plus a halo of one vertex) and two planes of cell

@@ -327,11 +327,14 @@ int pass2d_partials(const Lat& L);
 enum VertexClass : int8_t { VT_OUT = 0, VT_LEAF = 1, VT_REFINED = 2, VT_HANGING = 3 };
 // Active 64 x 4 (x, y) tiles of one level (3 ints per tile: x tile, y tile,
 // z plane) and the vertex class of every slot of the level.
-// On 3D adaptive levels also the 32 x 16 x 16 bricks (x brick, y brick,
+// On 3D adaptive levels also the 32 x 8 x 16 bricks (x brick, y brick,
 // chunk of 16 interior planes) that hold a leaf, refined or hanging vertex,
 // for the plane-marching sweep.  Bricks 32 slots wide fit a thin refined band
-// better than 64-wide ones: on a level-6 band they cover 2.2 slots per
-// active vertex against 2.8, and load 3.0 halo-inclusive slots against 4.0.
+// better than 64-wide ones: on a level-6 band 32 x 16 bricks cover 2.2 slots
+// per active vertex against 2.8, and load 3.0 halo-inclusive slots against
+// 4.0.  Eight rows (256-thread workgroups, more of them per CU, each waiting
+// at its barriers for four wavefronts) sweep that band in 550 us against 567
+// for sixteen rows and 656 for 64 x 4.
 struct AdTiles {
   Lat L;
   const int32_t* tiles = nullptr;
@@ -347,7 +350,7 @@ struct AdTiles {
   const int64_t* act = nullptr;
   int64_t na = 0;
 };
-constexpr int kBrickX = 32, kBrickY = 16, kBrickZ = 16;
+constexpr int kBrickX = 32, kBrickY = 8, kBrickZ = 16;
 constexpr int kMarchMinBricks = 4096;  // fewer bricks march serially: the tiles are faster
 // mode 0: Jacobi sweep of leaf and refined vertices, 1: the same from zero,
 // 2: residual (zero at hanging vertices; partial: per-workgroup sums of

@@ -303,7 +303,7 @@ def cpu_solution_poisson():
 AD_SWEEP_BYTES = {"bf16": 4 + 4 + 4 + 4 + 1, "hier16": 17, "hier32": 17, "hier64": 8 + 8 + 8 + 8 + 1,
                   "plain64": 27 * 8 + 8 + 8 + 8 + 1}
 AD_SWEEP_KERNEL = ("Jacobi sweep of the finest adaptive level (k_ad_march<float, float, 0, 0, 0>: "
-                   "32 x 16 x 16 bricks marching in z)")
+                   "32 x 8 x 16 bricks marching in z)")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 

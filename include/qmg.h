@@ -348,12 +348,17 @@ const char* qmg_last_error(const qmg_grid_t* grid);
 
 /* The operator of `level` as applied by the smoother (stored operators are
  * reconstructed from their store; the finest level is rediscretised from eps),
- * 3^d lattice arrays.  Requires built operators for level < L. */
+ * 3^d lattice arrays.  Requires built operators for level < L.  On adaptive
+ * levels only the rows of leaf and refined vertices are defined (a slot that
+ * is no vertex of the level reads back as its rediscretised row, which no
+ * kernel uses). */
 int qmg_get_operator(const qmg_grid_t* grid, int level, double* stencils);
 
 /* Prolongation from level-1 to `level` as weights per fine vertex: 2^d lattice
  * arrays; array c = kx + 2 ky + 4 kz holds the weight of the coarse vertex
- * floor(f/3) + (kx,ky,kz) at fine vertex f (zero where it is not a parent). */
+ * floor(f/3) + (kx,ky,kz) at fine vertex f (zero where it is not a parent).
+ * On adaptive levels only the weights of the level's vertices are defined (a
+ * slot outside the level reads back as the d-linear weights). */
 int qmg_get_prolongation(const qmg_grid_t* grid, int level, double* weights);
 
 /* Refinement criterion of the dynamically adaptive runs (Sect. 7), on a

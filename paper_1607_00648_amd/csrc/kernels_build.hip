@@ -864,6 +864,33 @@ __global__ __launch_bounds__(64) void k_rap_cells3(Lat Lf, Lat Lc, const double*
   const int64_t vb = bx + (int64_t)by * Lf.pitch + (int64_t)bz * Lf.plane;
   const int8_t cls = vt_fine ? vt_fine[vb] : (int8_t)VT_LEAF;
   const bool has_row = cls == VT_LEAF || cls == VT_REFINED;
+  // The weights towards C's corners at its 64 fine vertices come from BoxMG
+  // edge, face and interior systems (whichever orthant writes them) whose
+  // rows read only the 125 fine cells of C and the layer around it.  With one
+  // coefficient there they are the d-linear weights; with every vertex
+  // inside the domain and with a row the product is then the coarse element
+  // matrix, written without loading the weights.
+  {
+    double lo = INFINITY, hi = -INFINITY;
+    for (int e = t; e < 125; e += 64) {
+      const int x = 3 * Cx - 1 + e % 5, y = 3 * Cy - 1 + (e / 5) % 5, z = 3 * Cz - 1 + e / 25;
+      if (x < 0 || y < 0 || z < 0 || x >= Lf.n || y >= Lf.n || z >= Lf.n) continue;
+      const double v = eps[x + (int64_t)y * Lf.pitch + (int64_t)z * Lf.plane];
+      lo = fmin(lo, v);
+      hi = fmax(hi, v);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, o, 64));
+      hi = fmax(hi, __shfl_xor(hi, o, 64));
+    }
+    if (__syncthreads_and(lo == hi && has_row && interior(Lf, bx, by, bz))) {
+      const int V = t >> 3, Wc = t & 7;
+      const int nd = (V ^ Wc) == 0 ? 0 : __popc((unsigned)(V ^ Wc));
+      AC[ci * 64 + t] = kref(3, nd) * lo * (3.0 * Lf.h);
+      return;
+    }
+  }
   bool dlin = true;  // every weight the d-linear one, bit for bit
 #pragma unroll
   for (int cc = 0; cc < 8; ++cc) {

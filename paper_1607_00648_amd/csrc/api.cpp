@@ -1421,8 +1421,13 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
       // adaptive levels: every weight of the level's vertices (all the
       // encoder and the kernels read) is written by the BoxMG kernel itself
       if (!ad) launch_zero<double>(Pt, F.L.nslot * NC, s);
+      // the finest level's rediscretised rows: the work stencil buffer of
+      // level L (unused until the Galerkin product) holds the list of cells
+      // whose patches need the solve
+      void* bscr = (l == L && !Afine && !g->plain) ? (void*)g->tmpA[L & 1] : nullptr;
+      const size_t bscr_bytes = bscr ? (size_t)NS * g->lv[L - 1].L.nslot * sizeof(double) : 0;
       launch_boxmg(F.L, C.L, Afine, F.eps64, Pt, s, ad ? F.vt : nullptr, ad ? C.cref : nullptr,
-                   ad ? C.rc : nullptr, ad ? C.nrc : 0);
+                   ad ? C.rc : nullptr, ad ? C.nrc : 0, bscr, bscr_bytes);
       Pw = Pt;
     } else if (g->plain) {
       Store dl;

@@ -332,10 +332,123 @@ __device__ inline void zero_boundary_orthant(const Lat& Lf, double* __restrict__
 // are not refined are skipped (adaptive levels)
 // cells (nullable): list of the refined coarse cells; thread (cell, corner)
 // solves the corner's orthant, which points into the cell
+// Writes the reference region of orthant (sx, sy, sz) at coarse vertex V,
+// value(yx, yy, yz) at fine vertex 3V + s y.  A point on an axis (y_i = 0) is
+// shared by the orthants that differ only on such axes; it is written by the
+// one of lowest rank (rank: bit i set when the orthant is negative on shared
+// axis i) among those whose patch is computed: the + orthant on regular
+// levels (cref null), the next refined one on adaptive levels.  The writer
+// also writes the entries towards the second parent along the shared axes
+// (at distance 3: weight zero), which no orthant computes; with them every
+// entry of every fine vertex of a refined coarse cell is written once.
+template <int D, class PV>
+__device__ inline void write_orthant(const Lat& Lf, const Lat& Lc, double* __restrict__ Pw,
+                                     const int8_t* __restrict__ cref, int Vx, int Vy, int Vz, int sx, int sy,
+                                     int sz, PV&& value) {
+  const int zmax = (D == 3) ? 3 : 1;
+  const int sneg = (sx < 0 ? 1 : 0) | (sy < 0 ? 2 : 0) | (sz < 0 ? 4 : 0);
+  for (int yz = 0; yz < zmax; ++yz)
+    for (int yy = 0; yy < 3; ++yy)
+      for (int yx = 0; yx < 3; ++yx) {
+        const int zmask = (yx == 0 ? 1 : 0) | (yy == 0 ? 2 : 0) | ((D == 3 && yz == 0) ? 4 : 0);
+        const int myrank = sneg & zmask;
+        bool mine = true;
+        if (cref == nullptr) {
+          mine = myrank == 0;
+        } else {
+          for (int c = 0; c < myrank && mine; ++c) {
+            if ((c & ~zmask) != 0) continue;  // candidates differ on shared axes only
+            const int ox = (zmask & 1) ? ((c & 1) ? -1 : 1) : sx;
+            const int oy = (zmask & 2) ? ((c & 2) ? -1 : 1) : sy;
+            const int oz = (zmask & 4) ? ((c & 4) ? -1 : 1) : sz;
+            if (orthant_refined(cref, Lc, Vx, Vy, Vz, ox, oy, oz)) mine = false;
+          }
+        }
+        if (!mine) continue;
+        const int fx = 3 * Vx + sx * yx, fy = 3 * Vy + sy * yy, fz = 3 * Vz + sz * yz;
+        const int kap = ((sx < 0 && yx > 0) ? 1 : 0) | ((sy < 0 && yy > 0) ? 2 : 0) |
+                        ((D == 3 && sz < 0 && yz > 0) ? 4 : 0);
+        const int64_t vf = fx + (int64_t)fy * Lf.pitch + (int64_t)fz * Lf.plane;
+        Pw[(int64_t)kap * Lf.nslot + vf] = value(yx, yy, yz);
+        for (int sub = 1; sub < (1 << D); ++sub)
+          if ((sub & ~zmask) == 0) Pw[(int64_t)(kap | sub) * Lf.nslot + vf] = 0.0;
+      }
+}
+
+// d-linear weight of a coarse vertex at distance y (0..2 fine steps) along one
+// axis of its orthant
+__device__ inline double dlin_ref(int y) { return y == 0 ? 1.0 : (y == 1 ? 2.0 / 3.0 : 1.0 / 3.0); }
+
+// Constant-coefficient pass of the listed 3D cells with rediscretised rows:
+// kBoxCells cells per workgroup, thread (cell, corner).  A cell whose 125
+// fine cells and the layer around them carry one eps (every row of its eight
+// orthant systems reads only these) gets the d-linear weights of its
+// orthants, which BoxMG reproduces there (up to rounding); the others are
+// appended to dlist (count in *dcount) for the solve.  Kept apart from the
+// solver kernel, whose register use leaves two wavefronts per SIMD: this pass
+// is bound by memory latency and wants many more.
+constexpr int kBoxCells = 32;
+__global__ __launch_bounds__(8 * kBoxCells) void k_boxmg_uniform3(Lat Lf, Lat Lc, const double* __restrict__ eps,
+                                                                 double* __restrict__ Pw,
+                                                                 const int8_t* __restrict__ cref,
+                                                                 const int32_t* __restrict__ cells, int64_t ncells,
+                                                                 int32_t* __restrict__ dlist,
+                                                                 int32_t* __restrict__ dcount) {
+  __shared__ int cc[3 * kBoxCells];
+  const int lc = threadIdx.x >> 3, orth = threadIdx.x & 7;
+  const int64_t ci = (int64_t)blockIdx.x * kBoxCells + lc;
+  const bool active = ci < ncells;
+  const int n = Lc.n;
+  if (orth == 0) {
+    int x = -1000, y = -1000, z = -1000;
+    if (active) {
+      const int64_t c = cells[ci];
+      x = (int)(c % n);
+      y = (int)((c / n) % n);
+      z = (int)(c / ((int64_t)n * n));
+    }
+    cc[3 * lc] = x;
+    cc[3 * lc + 1] = y;
+    cc[3 * lc + 2] = z;
+  }
+  __syncthreads();
+  const int x0 = 3 * cc[3 * lc] - 1, y0 = 3 * cc[3 * lc + 1] - 1, z0 = 3 * cc[3 * lc + 2] - 1;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int e = orth; e < 125; e += 8) {
+    const int x = x0 + e % 5, y = y0 + (e / 5) % 5, z = z0 + e / 25;
+    if (x < 0 || y < 0 || z < 0 || x >= Lf.n || y >= Lf.n || z >= Lf.n) continue;
+    const double v = eps[x + (int64_t)y * Lf.pitch + (int64_t)z * Lf.plane];
+    lo = fmin(lo, v);
+    hi = fmax(hi, v);
+  }
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+  }
+  if (!active) return;
+  if (!(lo == hi)) {
+    if (orth == 0) dlist[atomicAdd(dcount, 1)] = cells[ci];
+    return;
+  }
+  const int Vx = cc[3 * lc] + (orth & 1), Vy = cc[3 * lc + 1] + ((orth >> 1) & 1),
+            Vz = cc[3 * lc + 2] + ((orth >> 2) & 1);
+  const int sx = (orth & 1) ? -1 : 1, sy = (orth & 2) ? -1 : 1, sz = (orth & 4) ? -1 : 1;
+  if (!interior(Lc, Vx, Vy, Vz)) {
+    zero_boundary_orthant<3>(Lf, Pw, Vx, Vy, Vz, sx, sy, sz);
+    return;
+  }
+  write_orthant<3>(Lf, Lc, Pw, cref, Vx, Vy, Vz, sx, sy, sz,
+                   [](int yx, int yy, int yz) { return dlin_ref(yx) * dlin_ref(yy) * dlin_ref(yz); });
+}
+
+// pass (3D, listed cells): 0 solves every cell; 2 solves the *dcount cells
+// of `cells` (the list k_boxmg_uniform3 leaves), in dense wavefronts instead
+// of beside constant-coefficient cells that would wait for them.
 template <int D, int MINW>
 __global__ __launch_bounds__(64, MINW) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, double* __restrict__ Pw,
                                               const int8_t* __restrict__ cref, const int32_t* __restrict__ cells,
-                                              int64_t ncells) {
+                                              int64_t ncells, const int32_t* __restrict__ dcount, int pass) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int m = Lc.n - 1;
   int orth, Vx, Vy, Vz;
@@ -349,7 +462,7 @@ __global__ __launch_bounds__(64, MINW) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> 
     const int n = Lc.n;
     const int lc = threadIdx.x >> 3;
     const int64_t ci = (int64_t)blockIdx.x * 8 + lc;
-    const int64_t nc = cells ? ncells : (int64_t)n * n * n;
+    const int64_t nc = pass == 2 ? (int64_t)*dcount : (cells ? ncells : (int64_t)n * n * n);
     bool active = ci < nc;
     if ((threadIdx.x & 7) == 0) {
       int x = -1000, y = -1000, z = -1000;
@@ -370,7 +483,7 @@ __global__ __launch_bounds__(64, MINW) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> 
     // which BoxMG reproduces the d-linear weights (up to rounding); they are
     // then written without the solve.  The eight lanes of the cell split the
     // 125 cells (those inside the domain).
-    if (F.A == nullptr) {
+    if (F.A == nullptr && pass != 2) {
       const int x0 = 3 * cc[3 * lc] - 1, y0 = 3 * cc[3 * lc + 1] - 1, z0 = 3 * cc[3 * lc + 2] - 1;
       double lo = INFINITY, hi = -INFINITY;
       for (int e = (int)(threadIdx.x & 7); e < 125; e += 8) {
@@ -448,42 +561,9 @@ __global__ __launch_bounds__(64, MINW) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> 
       box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p);
     }
   }
-  // write the reference region; a point on an axis (y_i = 0) is shared by the
-  // orthants that differ only on such axes.  It is written by the one of
-  // lowest rank (rank: bit i set when the orthant is negative on shared axis
-  // i) among those whose patch is computed: the + orthant on regular levels,
-  // the next refined one on adaptive levels
-  const int zmax = (D == 3) ? 3 : 1;
-  const int sneg = (sx < 0 ? 1 : 0) | (sy < 0 ? 2 : 0) | (sz < 0 ? 4 : 0);
-  for (int yz = 0; yz < zmax; ++yz)
-    for (int yy = 0; yy < 3; ++yy)
-      for (int yx = 0; yx < 3; ++yx) {
-        const int zmask = (yx == 0 ? 1 : 0) | (yy == 0 ? 2 : 0) | ((D == 3 && yz == 0) ? 4 : 0);
-        const int myrank = sneg & zmask;
-        bool mine = true;
-        if (cref == nullptr) {
-          mine = myrank == 0;
-        } else {
-          for (int c = 0; c < myrank && mine; ++c) {
-            if ((c & ~zmask) != 0) continue;  // candidates differ on shared axes only
-            const int ox = (zmask & 1) ? ((c & 1) ? -1 : 1) : sx;
-            const int oy = (zmask & 2) ? ((c & 2) ? -1 : 1) : sy;
-            const int oz = (zmask & 4) ? ((c & 4) ? -1 : 1) : sz;
-            if (orthant_refined(cref, Lc, Vx, Vy, Vz, ox, oy, oz)) mine = false;
-          }
-        }
-        if (!mine) continue;
-        const int fx = 3 * Vx + sx * yx, fy = 3 * Vy + sy * yy, fz = 3 * Vz + sz * yz;
-        const int kap = ((sx < 0 && yx > 0) ? 1 : 0) | ((sy < 0 && yy > 0) ? 2 : 0) |
-                        ((D == 3 && sz < 0 && yz > 0) ? 4 : 0);
-        const int64_t vf = fx + (int64_t)fy * Lf.pitch + (int64_t)fz * Lf.plane;
-        Pw[(int64_t)kap * Lf.nslot + vf] = p[pidx(yx, yy, yz)];
-        // the entries towards the second parent along the shared axes (at
-        // distance 3: weight zero), which no orthant computes; with them every
-        // entry of every fine vertex of a refined coarse cell is written once
-        for (int sub = 1; sub < (1 << D); ++sub)
-          if ((sub & ~zmask) == 0) Pw[(int64_t)(kap | sub) * Lf.nslot + vf] = 0.0;
-      }
+  write_orthant<D>(Lf, Lc, Pw, cref, Vx, Vy, Vz, sx, sy, sz, [&](int yx, int yy, int yz) {
+    return p[pidx(yx, yy, yz)];
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1380,7 +1460,7 @@ void launch_materialise_P(const Lat& Lf, const Lat& Lc, const Store& P, double* 
 
 void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf, double* Pw,
                   hipStream_t s, const int8_t* vt_fine, const int8_t* cref_coarse, const int32_t* cells,
-                  int64_t n_cells) {
+                  int64_t n_cells, void* scratch, size_t scratch_bytes) {
   const int m = Lc.n - 1;
   if (m <= 0) return;
   const int64_t nv = (Lf.d == 3) ? (int64_t)m * m * m : (int64_t)m * m;
@@ -1389,17 +1469,30 @@ void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const doubl
   if (Lf.d == 2) {
     BoxFetch<2> F{Afine, epsf, Lf, vt_fine, vt_fine != nullptr};
     hipLaunchKernelGGL((k_boxmg<2, 1>), dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
-                       n_cells);
+                       n_cells, nullptr, 0);
   } else {
     // 8 coarse cells (all their corners) per workgroup
     const int64_t nc = cells ? n_cells : (int64_t)Lc.n * Lc.n * Lc.n;
+    const dim3 g(blocks_for(nc, 8));
     BoxFetch<3> F{Afine, epsf, Lf, vt_fine, vt_fine != nullptr};
-    if (Afine == nullptr)
-      hipLaunchKernelGGL((k_boxmg<3, 2>), dim3(blocks_for(nc, 8)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
-                         n_cells);
-    else
-      hipLaunchKernelGGL((k_boxmg<3, 1>), dim3(blocks_for(nc, 8)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
-                         n_cells);
+    const bool split = Afine == nullptr && cells != nullptr && scratch != nullptr &&
+                       scratch_bytes >= (size_t)(n_cells + 16) * sizeof(int32_t);
+    if (split) {
+      // count, then the list of the cells whose patches need the solve
+      int32_t* dcount = (int32_t*)scratch;
+      int32_t* dlist = dcount + 16;
+      hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, dcount, (int64_t)1, 0);
+      hipLaunchKernelGGL(k_boxmg_uniform3, dim3(blocks_for(n_cells, kBoxCells)), dim3(8 * kBoxCells), 0, s, Lf, Lc,
+                         epsf, Pw, cref_coarse, cells, n_cells, dlist, dcount);
+      hipLaunchKernelGGL((k_boxmg<3, 2>), g, dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, (const int32_t*)dlist,
+                         n_cells, (const int32_t*)dcount, 2);
+    } else if (Afine == nullptr) {
+      hipLaunchKernelGGL((k_boxmg<3, 2>), g, dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells, n_cells, nullptr,
+                         0);
+    } else {
+      hipLaunchKernelGGL((k_boxmg<3, 1>), g, dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells, n_cells, nullptr,
+                         0);
+    }
   }
   QMG_HIP(hipGetLastError());
 }

@@ -203,9 +203,13 @@ void launch_materialise_P(const Lat& Lf, const Lat& Lc, const Store& P, double* 
 // from eps, others zero) and the refined flags of the coarse cells (only
 // refined cells are patches).  cells (nullable, with cref_coarse): the n_cells
 // refined coarse cells (cell index, x fastest); only their corners are solved.
+// scratch (nullable, 3D listed cells with rediscretised rows): device memory
+// of at least (n_cells + 16) ints; the constant-coefficient cells are then
+// written first and the others solved in a second launch over their list.
 void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
                   double* Pw, hipStream_t s, const int8_t* vt_fine = nullptr,
-                  const int8_t* cref_coarse = nullptr, const int32_t* cells = nullptr, int64_t n_cells = 0);
+                  const int8_t* cref_coarse = nullptr, const int32_t* cells = nullptr, int64_t n_cells = 0,
+                  void* scratch = nullptr, size_t scratch_bytes = 0);
 // Galerkin RAP (Sect. 4.3): coarse FP64 stencils from fine stencils (or eps on
 // the fly when Afine is null) and FP64 parent weights (d-linear when Pw null).
 // vt_fine (nullable): vertex classes of the fine level; rows of vertices that

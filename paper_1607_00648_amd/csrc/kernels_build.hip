@@ -426,11 +426,16 @@ __global__ __launch_bounds__(8 * kBoxCells) void k_boxmg_uniform3(Lat Lf, Lat Lc
     lo = fmin(lo, __shfl_xor(lo, o, 64));
     hi = fmax(hi, __shfl_xor(hi, o, 64));
   }
-  if (!active) return;
-  if (!(lo == hi)) {
-    if (orth == 0) dlist[atomicAdd(dcount, 1)] = cells[ci];
-    return;
-  }
+  // the listed cells of the wavefront (its eight cells' first lanes) take
+  // consecutive places after one atomic increment
+  const bool listed = active && !(lo == hi);
+  const uint64_t lead = __ballot(listed && orth == 0);
+  const int lane = (int)(threadIdx.x & 63);
+  int base = 0;
+  if (lane == 0 && lead != 0) base = atomicAdd(dcount, (int)__popcll(lead));
+  base = __shfl(base, 0, 64);
+  if (listed && orth == 0) dlist[base + (int)__popcll(lead & ((1ull << lane) - 1ull))] = cells[ci];
+  if (!active || listed) return;
   const int Vx = cc[3 * lc] + (orth & 1), Vy = cc[3 * lc + 1] + ((orth >> 1) & 1),
             Vz = cc[3 * lc + 2] + ((orth >> 2) & 1);
   const int sx = (orth & 1) ? -1 : 1, sy = (orth & 2) ? -1 : 1, sz = (orth & 4) ? -1 : 1;

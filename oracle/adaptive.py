@@ -69,7 +69,8 @@ import scipy.sparse.linalg as spla
 
 from .fem import (geometric_stencil, offsets, shifted, csr_to_stencil, stencil_to_csr,
                   interior_mask, corners, corner_index, element_matrix, apply_dirichlet)
-from .transfer import dlinear_P, boxmg_P, boxmg_reference_stepwise, _gather_reference, _points
+from .transfer import (dlinear_P, boxmg_P, boxmg_reference_stepwise, _gather_reference, _points,
+                       shared_entry_tolerance, unique_shared_entries)
 from .fem import _unknown_numbering
 from .galerkin import rap, definiteness_violations
 from . import solver as S
@@ -401,16 +402,10 @@ def boxmg_adaptive_P(G: AdaptiveGrid, S_full, l, check=True):
         return sp.csr_matrix((Nf, Nc))
     rows, cols = np.concatenate(rows), np.concatenate(cols)
     ranks, vals = np.concatenate(ranks), np.concatenate(vals)
-    key = rows * Nc + cols
-    order = np.lexsort((ranks, key))
-    key, vals = key[order], vals[order]
-    uniq, first = np.unique(key, return_index=True)
-    if check:
-        grp = np.repeat(np.arange(len(uniq)), np.diff(np.append(first, len(key))))
-        ref_v = vals[first][grp]
-        if (np.abs(vals - ref_v) > 1e-9 * np.maximum(1.0, np.abs(ref_v))).any():
-            raise AssertionError("adaptive BoxMG: neighbouring patches disagree on a shared entry")
-    return sp.csr_matrix((vals[first], (uniq // Nc, uniq % Nc)), shape=(Nf, Nc))
+    uniq, v, dis = unique_shared_entries(rows, cols, vals, Nc, ranks)
+    if check and dis > shared_entry_tolerance(S_full, d):
+        raise AssertionError("adaptive BoxMG: neighbouring patches disagree on a shared entry")
+    return sp.csr_matrix((v, (uniq // Nc, uniq % Nc)), shape=(Nf, Nc))
 
 
 def build_adaptive(G: AdaptiveGrid, eps_leaf, transfer="galerkin", omega=0.6, mu_pre=2, mu_post=2,

@@ -198,3 +198,49 @@ def test_boxmg_rows_partition_unity_inside():
     P = O.boxmg_P(O.geometric_stencil(eps, 2, Lf), 2, Lf)
     s = np.asarray(P.sum(axis=1)).reshape(n - 1, n - 1)
     np.testing.assert_allclose(s[3:-3, 3:-3], 1.0, rtol=1e-10)  # contrast 1e4 amplifies rounding
+
+
+@pytest.mark.parametrize("d,Lf", [(2, 3), (3, 2)])
+def test_boxmg_shared_entries_agree_exactly_for_constant_eps(d, Lf):
+    """Neighbouring patches compute their shared entries (c-points, line and
+    face points) alike: for constant eps the copies are identical."""
+    n = 3 ** Lf
+    S = O.geometric_stencil(np.full((n,) * d, 2.5), d, Lf)
+    info = {}
+    transfer.boxmg_P(S, d, Lf, info=info)
+    assert info["shared_disagreement"] == 0.0
+
+
+@pytest.mark.parametrize("d,Lf", [(2, 3), (3, 2)])
+@pytest.mark.parametrize("contrast", [1e2, 1e4, 1e6])
+def test_boxmg_shared_entries_agree_to_contrast_rounding(d, Lf, contrast):
+    """For a two-valued checkerboard the copies of a shared entry differ by
+    rounding amplified by the contrast: within the check's bound of
+    16 kappa 2^-52, where kappa, the diagonal ratio, is the contrast within a
+    factor of a few."""
+    n = 3 ** Lf
+    rng = np.random.default_rng(5)
+    eps = np.where(rng.random((n,) * d) < 0.5, 1.0, contrast)
+    S = O.geometric_stencil(eps, d, Lf)
+    info = {}
+    transfer.boxmg_P(S, d, Lf, info=info)
+    tol = transfer.shared_entry_tolerance(S, d)
+    assert info["shared_disagreement"] <= tol
+    kappa = tol / (16.0 * 2.0 ** -52)
+    assert contrast / 8 <= kappa <= 8 * contrast
+
+
+def test_unique_shared_entries_reports_the_largest_disagreement():
+    """Copies of (row, col) entries: the first copy is kept and the largest
+    relative deviation of any other copy is reported (a planted 3e-7 on an
+    entry of size 2 gives 1.5e-7); ranks decide which copy comes first."""
+    rows = np.array([0, 0, 1, 1, 1, 2])
+    cols = np.array([0, 0, 1, 1, 1, 0])
+    vals = np.array([0.5, 0.5, 2.0, 2.0 + 3e-7, 2.0, 7.0])
+    uniq, first, dis = transfer.unique_shared_entries(rows, cols, vals, 4)
+    assert list(uniq) == [0, 5, 8]
+    assert list(first) == [0.5, 2.0, 7.0]
+    assert abs(dis - 1.5e-7) < 1e-15
+    ranks = np.array([0, 0, 1, 0, 2, 0])
+    _, first, dis = transfer.unique_shared_entries(rows, cols, vals, 4, ranks)
+    assert first[1] == 2.0 + 3e-7 and abs(dis - 3e-7 / (2.0 + 3e-7)) < 1e-15

@@ -1280,7 +1280,10 @@ std::vector<double> run_batch(qmg_grid_t* g, int B) {
 // ---------------------------------------------------------------------------
 // Build (Sect. 4.3 and 3.4; store of Sect. 5)
 // ---------------------------------------------------------------------------
-void encode(qmg_grid_t* g, LevelBuf& B, const Lat& Lc, bool is_P, const double* full, int slot, int fmt) {
+// marked: B's block flags of P already hold the BoxMG launch's marks (1 on
+// the blocks its solve wrote, 0 elsewhere).
+void encode(qmg_grid_t* g, LevelBuf& B, const Lat& Lc, bool is_P, const double* full, int slot, int fmt,
+            bool marked = false) {
   int32_t* blk = is_P ? B.Pblk : B.Ablk;
   void* pay = is_P ? B.Ppay : B.Apay;
   int8_t* sc = is_P ? B.Pscale : B.Ascale;
@@ -1292,7 +1295,7 @@ void encode(qmg_grid_t* g, LevelBuf& B, const Lat& Lc, bool is_P, const double* 
   // vertices
   const bool tl = g->adaptive && B.tiles != nullptr && B.L.n > g->lv[g->lb].L.n;
   launch_delta_flags(B.L, Lc, is_P, full, B.eps64, blk, S(g), eps_mf, tl ? B.tiles : nullptr, tl ? B.ntiles : 0,
-                     g->opts.eps_zero, tl ? B.vt : nullptr);
+                     g->opts.eps_zero, tl ? B.vt : nullptr, marked && tl && is_P);
   launch_scan_blocks(blk, B.L.nslot / kSeg, g->dtotal + slot, S(g), off, unit, g->scan_tmp);
   launch_delta_write(B.L, Lc, is_P, fmt, full, B.eps64, blk, pay, sc, S(g), off, eps_mf, tl ? B.tiles : nullptr,
                      tl ? B.ntiles : 0, tl ? B.vt : nullptr);
@@ -1415,6 +1418,7 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
     LevelBuf& C = g->lv[l - 1];
     const double* Afine = (l == L) ? (g->plain ? F.Adense : nullptr) : fullA(l);
     const double* Pw = nullptr;
+    bool p_marked = false;
     if (boxmg) {
       double* Pt = g->plain ? F.Pdense : g->tmpP;
       const bool ad = g->adaptive && l > g->lb;
@@ -1426,8 +1430,11 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
       // whose patches need the solve
       void* bscr = (l == L && !Afine && !g->plain) ? (void*)g->tmpA[L & 1] : nullptr;
       const size_t bscr_bytes = bscr ? (size_t)NS * g->lv[L - 1].L.nslot * sizeof(double) : 0;
-      launch_boxmg(F.L, C.L, Afine, F.eps64, Pt, s, ad ? F.vt : nullptr, ad ? C.cref : nullptr,
-                   ad ? C.rc : nullptr, ad ? C.nrc : 0, bscr, bscr_bytes);
+      // the prolongation's block flags collect the blocks the solve writes
+      int32_t* dirty = (bscr && F.Pblk) ? F.Pblk : nullptr;
+      if (dirty) launch_zero<int32_t>(dirty, F.L.nslot / kSeg, s);
+      p_marked = launch_boxmg(F.L, C.L, Afine, F.eps64, Pt, s, ad ? F.vt : nullptr, ad ? C.cref : nullptr,
+                              ad ? C.rc : nullptr, ad ? C.nrc : 0, bscr, bscr_bytes, dirty);
       Pw = Pt;
     } else if (g->plain) {
       Store dl;
@@ -1477,7 +1484,7 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
     }
     if (!g->plain) {
       if (boxmg) {
-        encode(g, F, C.L, true, Pw, 2 * l + 1, p_fmt(g, l));
+        encode(g, F, C.L, true, Pw, 2 * l + 1, p_fmt(g, l), p_marked);
         encodedP.push_back(l);
       }
       if (galerkin) {

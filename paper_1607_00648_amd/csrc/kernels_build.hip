@@ -341,10 +341,11 @@ __device__ inline void zero_boundary_orthant(const Lat& Lf, double* __restrict__
 // also writes the entries towards the second parent along the shared axes
 // (at distance 3: weight zero), which no orthant computes; with them every
 // entry of every fine vertex of a refined coarse cell is written once.
+// dirty (nullable): the 64-slot blocks written are marked 1 there.
 template <int D, class PV>
 __device__ inline void write_orthant(const Lat& Lf, const Lat& Lc, double* __restrict__ Pw,
                                      const int8_t* __restrict__ cref, int Vx, int Vy, int Vz, int sx, int sy,
-                                     int sz, PV&& value) {
+                                     int sz, PV&& value, int32_t* __restrict__ dirty = nullptr) {
   const int zmax = (D == 3) ? 3 : 1;
   const int sneg = (sx < 0 ? 1 : 0) | (sy < 0 ? 2 : 0) | (sz < 0 ? 4 : 0);
   for (int yz = 0; yz < zmax; ++yz)
@@ -372,6 +373,7 @@ __device__ inline void write_orthant(const Lat& Lf, const Lat& Lc, double* __res
         Pw[(int64_t)kap * Lf.nslot + vf] = value(yx, yy, yz);
         for (int sub = 1; sub < (1 << D); ++sub)
           if ((sub & ~zmask) == 0) Pw[(int64_t)(kap | sub) * Lf.nslot + vf] = 0.0;
+        if (dirty != nullptr) dirty[vf / kSeg] = 1;
       }
 }
 
@@ -449,11 +451,13 @@ __global__ __launch_bounds__(8 * kBoxCells) void k_boxmg_uniform3(Lat Lf, Lat Lc
 
 // pass (3D, listed cells): 0 solves every cell; 2 solves the *dcount cells
 // of `cells` (the list k_boxmg_uniform3 leaves), in dense wavefronts instead
-// of beside constant-coefficient cells that would wait for them.
+// of beside constant-coefficient cells that would wait for them.  dirty
+// (nullable): marks the 64-slot blocks this launch writes.
 template <int D, int MINW>
 __global__ __launch_bounds__(64, MINW) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> F, double* __restrict__ Pw,
                                               const int8_t* __restrict__ cref, const int32_t* __restrict__ cells,
-                                              int64_t ncells, const int32_t* __restrict__ dcount, int pass) {
+                                              int64_t ncells, const int32_t* __restrict__ dcount, int pass,
+                                              int32_t* __restrict__ dirty) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int m = Lc.n - 1;
   int orth, Vx, Vy, Vz;
@@ -566,9 +570,9 @@ __global__ __launch_bounds__(64, MINW) void k_boxmg(Lat Lf, Lat Lc, BoxFetch<D> 
       box_group<D, 3>(F, Vx, Vy, Vz, sx, sy, sz, p);
     }
   }
-  write_orthant<D>(Lf, Lc, Pw, cref, Vx, Vy, Vz, sx, sy, sz, [&](int yx, int yy, int yz) {
-    return p[pidx(yx, yy, yz)];
-  });
+  write_orthant<D>(
+      Lf, Lc, Pw, cref, Vx, Vy, Vz, sx, sy, sz, [&](int yx, int yy, int yz) { return p[pidx(yx, yy, yz)]; },
+      dirty);
 }
 
 // ---------------------------------------------------------------------------
@@ -1216,12 +1220,14 @@ __device__ inline int load_delta(const Lat& L, const Lat& Lc, const double* __re
 // Per 64-slot block (one wavefront): 1 when any vertex's delta is non-zero
 // (max|delta| > eps_zero * max|reference|), else 0.  With eps_mf > 0 the
 // block's width instead: the largest per-vertex bpa (0 for all-zero codes).
+// marked: blk holds 1 for the blocks whose entries may differ from their
+// reference and 0 for the others, which are known zero and not loaded.
 template <int D, bool IS_P>
 __global__ __launch_bounds__(256) void k_delta_flags(Lat L, Lat Lc, const double* __restrict__ full,
                                                      const double* __restrict__ eps,
                                                      int32_t* __restrict__ blk, double eps_mf,
                                                      const int32_t* __restrict__ tiles, double eps_zero,
-                                                     const int8_t* __restrict__ vt) {
+                                                     const int8_t* __restrict__ vt, int marked) {
   const int32_t* tl = tiles ? tiles + 3 * (int64_t)blockIdx.x : nullptr;
   const int i = (tl ? tl[0] : (int)blockIdx.x) * TX + threadIdx.x;
   const int j = (tl ? tl[1] : (int)blockIdx.y) * TY + threadIdx.y;
@@ -1230,7 +1236,10 @@ __global__ __launch_bounds__(256) void k_delta_flags(Lat L, Lat Lc, const double
   const int64_t v = i + (int64_t)j * L.pitch + (int64_t)kz * L.plane;
   double dl[27], refmax;
   int nz = 0;
-  if (inlat) {
+  // a clean block keeps its zero (one wavefront is one block: every lane
+  // reads the flag before lane 0 writes it)
+  const bool clean = marked && inlat && blk[v / kSeg] == 0;
+  if (inlat && !clean) {
     const int ne = load_delta<D, IS_P>(L, Lc, full, eps, vt, i, j, kz, v, dl, refmax);
     if (eps_mf > 0.0) {
       nz = bpa_width(dl, ne, eps_mf);
@@ -1463,18 +1472,19 @@ void launch_materialise_P(const Lat& Lf, const Lat& Lc, const Store& P, double* 
   QMG_HIP(hipGetLastError());
 }
 
-void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf, double* Pw,
+bool launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf, double* Pw,
                   hipStream_t s, const int8_t* vt_fine, const int8_t* cref_coarse, const int32_t* cells,
-                  int64_t n_cells, void* scratch, size_t scratch_bytes) {
+                  int64_t n_cells, void* scratch, size_t scratch_bytes, int32_t* dirty) {
   const int m = Lc.n - 1;
-  if (m <= 0) return;
+  if (m <= 0) return false;
   const int64_t nv = (Lf.d == 3) ? (int64_t)m * m * m : (int64_t)m * m;
   const int64_t nt = (cells ? n_cells : nv) * (Lf.d == 3 ? 8 : 4);
-  if (nt == 0) return;
+  if (nt == 0) return false;
+  bool marked = false;
   if (Lf.d == 2) {
     BoxFetch<2> F{Afine, epsf, Lf, vt_fine, vt_fine != nullptr};
     hipLaunchKernelGGL((k_boxmg<2, 1>), dim3(blocks_for(nt, 64)), dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells,
-                       n_cells, nullptr, 0);
+                       n_cells, nullptr, 0, nullptr);
   } else {
     // 8 coarse cells (all their corners) per workgroup
     const int64_t nc = cells ? n_cells : (int64_t)Lc.n * Lc.n * Lc.n;
@@ -1490,16 +1500,18 @@ void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const doubl
       hipLaunchKernelGGL(k_boxmg_uniform3, dim3(blocks_for(n_cells, kBoxCells)), dim3(8 * kBoxCells), 0, s, Lf, Lc,
                          epsf, Pw, cref_coarse, cells, n_cells, dlist, dcount);
       hipLaunchKernelGGL((k_boxmg<3, 2>), g, dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, (const int32_t*)dlist,
-                         n_cells, (const int32_t*)dcount, 2);
+                         n_cells, (const int32_t*)dcount, 2, dirty);
+      marked = dirty != nullptr;
     } else if (Afine == nullptr) {
       hipLaunchKernelGGL((k_boxmg<3, 2>), g, dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells, n_cells, nullptr,
-                         0);
+                         0, nullptr);
     } else {
       hipLaunchKernelGGL((k_boxmg<3, 1>), g, dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, cells, n_cells, nullptr,
-                         0);
+                         0, nullptr);
     }
   }
   QMG_HIP(hipGetLastError());
+  return marked;
 }
 
 void launch_rap(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
@@ -1569,17 +1581,18 @@ void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s)
 
 void launch_delta_flags(const Lat& L, const Lat& Lc, bool is_P, const double* full, const double* eps,
                         int32_t* blk, hipStream_t s, double eps_mf, const int32_t* tiles, int ntiles,
-                        double eps_zero, const int8_t* vt) {
+                        double eps_zero, const int8_t* vt, bool marked) {
   if (!(eps_zero > 0.0)) eps_zero = kEpsZero;
   const dim3 g = tiles ? dim3((unsigned)ntiles) : tile_grid(L), bl(TX, TY, 1);
-  if (tiles) launch_zero<int32_t>(blk, L.nslot / kSeg, s);  // blocks of unlisted tiles: zero
+  // blocks of unlisted tiles: zero (with marked blocks they are zero already)
+  if (tiles && !marked) launch_zero<int32_t>(blk, L.nslot / kSeg, s);
   if (tiles && ntiles == 0) return;
   if (L.d == 2) {
-    if (is_P) hipLaunchKernelGGL((k_delta_flags<2, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero, vt);
-    else hipLaunchKernelGGL((k_delta_flags<2, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero, vt);
+    if (is_P) hipLaunchKernelGGL((k_delta_flags<2, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero, vt, (int)marked);
+    else hipLaunchKernelGGL((k_delta_flags<2, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero, vt, (int)marked);
   } else {
-    if (is_P) hipLaunchKernelGGL((k_delta_flags<3, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero, vt);
-    else hipLaunchKernelGGL((k_delta_flags<3, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero, vt);
+    if (is_P) hipLaunchKernelGGL((k_delta_flags<3, true>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero, vt, (int)marked);
+    else hipLaunchKernelGGL((k_delta_flags<3, false>), g, bl, 0, s, L, Lc, full, eps, blk, eps_mf, tiles, eps_zero, vt, (int)marked);
   }
   QMG_HIP(hipGetLastError());
 }

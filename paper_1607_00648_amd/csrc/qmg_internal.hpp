@@ -206,10 +206,14 @@ void launch_materialise_P(const Lat& Lf, const Lat& Lc, const Store& P, double* 
 // scratch (nullable, 3D listed cells with rediscretised rows): device memory
 // of at least (n_cells + 16) ints; the constant-coefficient cells are then
 // written first and the others solved in a second launch over their list.
-void launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
+// dirty (nullable, one int per 64-slot block of the fine level, zero on
+// entry): the solve marks the blocks it writes; the weights of the others
+// equal their d-linear reference exactly.  Returns whether it did (the split
+// ran with dirty given).
+bool launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const double* epsf,
                   double* Pw, hipStream_t s, const int8_t* vt_fine = nullptr,
                   const int8_t* cref_coarse = nullptr, const int32_t* cells = nullptr, int64_t n_cells = 0,
-                  void* scratch = nullptr, size_t scratch_bytes = 0);
+                  void* scratch = nullptr, size_t scratch_bytes = 0, int32_t* dirty = nullptr);
 // Galerkin RAP (Sect. 4.3): coarse FP64 stencils from fine stencils (or eps on
 // the fly when Afine is null) and FP64 parent weights (d-linear when Pw null).
 // vt_fine (nullable): vertex classes of the fine level; rows of vertices that
@@ -250,10 +254,13 @@ void launch_check_rows(const Lat& Lc, const double* Ac, int* bad, hipStream_t s)
 // encoded; the blocks of the others are flagged zero.  vt (nullable): the
 // level's vertex classes; slots outside the level (no row or weight of theirs
 // is ever read) take a zero delta, so that their blocks are not stored.
+// marked: blk arrives with 1 on every block whose entries may differ from
+// their reference and 0 elsewhere (the BoxMG launch marks them); the others
+// are not loaded.
 void launch_delta_flags(const Lat& L, const Lat& Lc, bool is_P, const double* full,
                         const double* eps, int32_t* blk, hipStream_t s, double eps_mf = 0.0,
                         const int32_t* tiles = nullptr, int ntiles = 0, double eps_zero = 0.0,
-                        const int8_t* vt = nullptr);
+                        const int8_t* vt = nullptr, bool marked = false);
 // csum: device scratch of scan_scratch_ints(nblk) ints (chunk sums).
 void launch_scan_blocks(int32_t* blk, int64_t nblk, int32_t* total, hipStream_t s, int64_t* boff,
                         int64_t unit, int32_t* csum);

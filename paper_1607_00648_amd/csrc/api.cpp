@@ -1377,17 +1377,22 @@ void build(qmg_grid_t* g, qmg_solve_report* info) {
       launch_coarsen_eps(g->lv[l].L, g->lv[l - 1].L, g->lv[l].eps64, g->lv[l - 1].eps64, s);
   }
   // BoxMG on adaptive levels: cells that do not exist carry their covering
-  // cell's coefficient, from which hanging rows are rediscretised
-  if (g->adaptive && boxmg)
+  // cell's coefficient, from which hanging rows are rediscretised (with
+  // mixed precision the same pass writes the single-precision copy)
+  const bool virt = g->adaptive && boxmg;
+  if (virt)
     for (int l = g->lb + 1; l <= L; ++l)
       launch_ad_virtual_eps(g->lv[l].L, g->lv[l - 1].L, g->lv[l - 1].cref, g->lv[l].vt, g->lv[l - 1].eps64,
-                            g->lv[l].eps64, s);
+                            g->lv[l].eps64, g->mixed ? g->lv[l].eps32 : nullptr, s);
   // single-precision coefficients; above the base level only the cells next
   // to a vertex of the level, which are all a row reads
   if (g->mixed)
     for (int l = g->lcq; l <= L; ++l) {
-      if (g->adaptive && l > g->lb) launch_ad_convert_cells(g->lv[l].L, g->lv[l].vt, g->lv[l].eps64, g->lv[l].eps32, s);
-      else launch_convert<double, float>(g->lv[l].L, g->lv[l].eps64, g->lv[l].eps32, s);
+      if (g->adaptive && l > g->lb) {
+        if (!virt) launch_ad_convert_cells(g->lv[l].L, g->lv[l].vt, g->lv[l].eps64, g->lv[l].eps32, s);
+      } else {
+        launch_convert<double, float>(g->lv[l].L, g->lv[l].eps64, g->lv[l].eps32, s);
+      }
     }
   g->lc = g->lcq;
   assign_stores(g);  // views used by materialise below (plain stores)

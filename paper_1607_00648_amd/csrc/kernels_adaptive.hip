@@ -511,11 +511,14 @@ __device__ inline uint32_t read_cell_planes(const Lat& L, const int8_t* __restri
 }
 
 // cell coefficients of cells that do not exist: the covering (parent) cell's;
-// only cells a row of the level (vertex classes vtf) reads are written
+// only cells a row of the level (vertex classes vtf) reads are written.
+// ef32 (nullable): the single-precision copy of every such cell as well
+// (the pass over the cells a row reads is then made once).
 template <int D>
 __global__ __launch_bounds__(256) void k_ad_virtual_eps(Lat Lf, Lat Lc, const int8_t* __restrict__ crefc,
                                                         const int8_t* __restrict__ vtf,
-                                                        const double* __restrict__ ec, double* __restrict__ ef) {
+                                                        const double* __restrict__ ec, double* __restrict__ ef,
+                                                        float* __restrict__ ef32) {
   constexpr int NP = kCellPlanes / 3;  // parent planes of a thread
   const int I = blockIdx.x * TX + threadIdx.x;
   const int J = blockIdx.y * TY + threadIdx.y;
@@ -535,9 +538,21 @@ __global__ __launch_bounds__(256) void k_ad_virtual_eps(Lat Lf, Lat Lc, const in
     keep[p] = !need || crefc[pc] != 0;
     pe[p] = need ? ec[pc] : 0.0;
   }
+  double own[kCellPlanes];  // existing cells' own values (for ef32)
 #pragma unroll
   for (int q = 0; q < kCellPlanes; ++q)
-    if (((m >> q) & 1u) && !keep[q / 3]) ef[col + (int64_t)(K0 + q) * Lf.plane] = pe[q / 3];
+    own[q] = (ef32 != nullptr && ((m >> q) & 1u) && keep[q / 3]) ? ef[col + (int64_t)(K0 + q) * Lf.plane] : 0.0;
+#pragma unroll
+  for (int q = 0; q < kCellPlanes; ++q) {
+    if (!((m >> q) & 1u)) continue;
+    const int64_t c = col + (int64_t)(K0 + q) * Lf.plane;
+    if (!keep[q / 3]) {
+      ef[c] = pe[q / 3];
+      if (ef32 != nullptr) ef32[c] = (float)pe[q / 3];
+    } else if (ef32 != nullptr) {
+      ef32[c] = (float)own[q];
+    }
+  }
 }
 
 // single-precision cell coefficients of an adaptive level on the cells a row
@@ -860,10 +875,10 @@ void launch_ad_correct(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, con
 }
 
 void launch_ad_virtual_eps(const Lat& Lf, const Lat& Lc, const int8_t* crefc, const int8_t* vtf, const double* ec,
-                           double* ef, hipStream_t s) {
+                           double* ef, float* ef32, hipStream_t s) {
   const dim3 g = cell_walk_grid(Lf), bl(TX, TY, 1);
-  if (Lf.d == 2) hipLaunchKernelGGL(k_ad_virtual_eps<2>, g, bl, 0, s, Lf, Lc, crefc, vtf, ec, ef);
-  else hipLaunchKernelGGL(k_ad_virtual_eps<3>, g, bl, 0, s, Lf, Lc, crefc, vtf, ec, ef);
+  if (Lf.d == 2) hipLaunchKernelGGL(k_ad_virtual_eps<2>, g, bl, 0, s, Lf, Lc, crefc, vtf, ec, ef, ef32);
+  else hipLaunchKernelGGL(k_ad_virtual_eps<3>, g, bl, 0, s, Lf, Lc, crefc, vtf, ec, ef, ef32);
   QMG_HIP(hipGetLastError());
 }
 

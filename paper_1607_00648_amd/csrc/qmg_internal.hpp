@@ -393,9 +393,10 @@ void launch_ad_correct(const AdTiles& tf, const Lat& Lc, T* uf, const T* uc, con
                        hipStream_t s);
 // coefficients of the level-l cells that do not exist := their parent cell's
 // vtf: vertex classes of the fine level; cells with no corner among its
-// vertices are not written (no row reads them)
+// vertices are not written (no row reads them).  ef32 (nullable): also the
+// single-precision copy of every cell a row reads (as launch_ad_convert_cells).
 void launch_ad_virtual_eps(const Lat& Lf, const Lat& Lc, const int8_t* crefc, const int8_t* vtf, const double* ec,
-                           double* ef, hipStream_t s);
+                           double* ef, float* ef32, hipStream_t s);
 // out := (float) in on the cells next to a vertex of the level (vt)
 void launch_ad_convert_cells(const Lat& L, const int8_t* vt, const double* in, float* out, hipStream_t s);
 template <typename T>

@@ -401,7 +401,8 @@ def quantised_hierarchy(H, fmt, eps_mf=None):
     A_geom(eps_l) + q(A_hat_l) and P_dlin + q(P_hat_l), quantised per vertex as
     in ``store``; the finest operator is the geometric one (its delta is zero
     by construction).  For the IEEE formats it is the FP32 inner hierarchy of
-    the mixed loop (parity unpinned beyond the bound of the outer loop).  For
+    the mixed loop (pinned entry by entry by each format's rounding bound,
+    and exactly for constant eps, in the oracle tests).  For
     "bpa" (with ``eps_mf``) it is an FP64 hierarchy, the form in which the
     paper solves with its codec.  An exact coarsest-level solve keeps the
     factorisation of the full operator."""

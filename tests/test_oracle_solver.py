@@ -409,3 +409,63 @@ def test_bpx_constant_omega_converges():
             ustar = O.direct_solve(H.A[L], b)
             assert np.linalg.norm(u - ustar) <= 1e-8 * np.linalg.norm(ustar)
     assert counts[1] <= 1.5 * counts[0]
+
+
+# ---------------------------------------------------------------------------
+# Quantised hierarchy (the inner hierarchy of the mixed loop)
+# ---------------------------------------------------------------------------
+
+# unit roundoff of each delta format (FP16 per-vertex scaled: below the
+# normal range its absolute error is bounded by 2^-25 of the vertex maximum)
+_U = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8, "fp16": 2.0 ** -11}
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("d,L", [(2, 4), (3, 3)])
+def test_quantised_hierarchy_within_the_format_rounding(fmt, d, L):
+    """Every stored operator of the quantised hierarchy is the rediscretised
+    stencil plus its hierarchical delta rounded to the format, then rounded
+    to FP32: |A_q - A| <= u_fmt |delta| + 2^-25 max_vertex |delta| +
+    2^-24 |A| + 2^-40 max_vertex |A_geom| entry by entry (the last term: a
+    vertex whose deltas are all below 2^-40 of its reference row stores
+    none), and the prolongations likewise against the d-linear weights.  A
+    dropped or sign-flipped delta fails it."""
+    n = 3 ** L
+    eps = np.exp(np.random.default_rng(2).normal(size=(n,) * d))   # every delta non-zero
+    H = O.build_hierarchy(eps, d, L, transfer="boxmg", check_definite=False)
+    Hq = O.solver.quantised_hierarchy(H, fmt)
+    u = _U[fmt]
+    for l in range(H.lc, L):
+        S = O.csr_to_stencil(H.A[l], d, l)
+        Sq = O.csr_to_stencil(sp.csr_matrix(Hq.A[l], dtype=np.float64), d, l)
+        G = O.geometric_stencil(H.eps[l], d, l)
+        dl = S - G
+        vmax = np.max(np.abs(dl), axis=0)[None]
+        gmax = np.max(np.abs(G), axis=0)[None]
+        bound = u * np.abs(dl) + 2.0 ** -25 * vmax + 2.0 ** -24 * np.abs(S) + 2.0 ** -40 * gmax + 1e-300
+        assert (np.abs(Sq - S) <= bound).all(), l
+    for l in range(H.lc + 1, L + 1):
+        Pd = O.dlinear_P(d, l).toarray()
+        Pf = H.P[l].toarray()
+        Pq = Hq.P[l].astype(np.float64).toarray()
+        dP = Pf - Pd
+        rmax = np.max(np.abs(dP), axis=1)[:, None]
+        pmax = np.max(np.abs(Pd), axis=1)[:, None]
+        bound = u * np.abs(dP) + 2.0 ** -25 * rmax + 2.0 ** -24 * np.abs(Pf) + 2.0 ** -40 * pmax + 1e-300
+        assert (np.abs(Pq - Pf) <= bound).all(), l
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16", "fp16"])
+def test_quantised_hierarchy_of_constant_eps_is_the_fp32_reference(fmt):
+    """Constant eps: every delta counts as zero, so the quantised hierarchy is
+    exactly the FP32 rounding of the rediscretised operators and of the
+    d-linear prolongations."""
+    d, L = 2, 4
+    n = 3 ** L
+    H = O.build_hierarchy(np.full((n,) * d, 3.0), d, L, transfer="boxmg")
+    Hq = O.solver.quantised_hierarchy(H, fmt)
+    for l in range(H.lc, L + 1):
+        G = O.stencil_to_csr(O.geometric_stencil(H.eps[l], d, l), d, l).astype(np.float32)
+        assert (Hq.A[l] != G).nnz == 0, l
+    for l in range(H.lc + 1, L + 1):
+        assert (Hq.P[l] != O.dlinear_P(d, l).astype(np.float32)).nnz == 0, l

@@ -338,3 +338,23 @@ def test_multiscale_smoothing_keeps_the_composite_fixed_point(hanging_rows):
     ub, histb = AD.solve_adaptive(Hb, f, tol=1e-11, max_cycles=200)
     us, Ab, bb = AD.solve_composite_direct(G, eps, f, AD.hanging_constraints(Hb))
     assert np.linalg.norm(ub - us) <= 1e-9 * np.linalg.norm(us)
+
+
+@pytest.mark.parametrize("d,base,L,transfer", [(2, 1, 3, "galerkin"), (2, 2, 4, "boxmg"), (3, 1, 3, "galerkin")])
+def test_full_refinement_fas_cycles_are_the_regular_v_cycles(d, base, L, transfer):
+    """Every cell refined down to level L: the FAS V-cycle on the linear
+    problem is the correction-scheme V-cycle of the regular hierarchy (same
+    Galerkin operators, smoother and transfers), iterate for iterate, so the
+    residual histories and the solutions after six cycles agree to rounding."""
+    flags = {l: np.ones((3 ** l,) * d, bool) for l in range(base, L)}
+    G = AD.AdaptiveGrid(d, base, L, flags)
+    n = 3 ** L
+    rng = np.random.default_rng(3)
+    eps = rng.uniform(0.5, 2.0, size=n ** d)
+    f = rng.uniform(-1, 1, size=G.n_unknowns())
+    ua, ha = AD.solve_adaptive(AD.build_adaptive(G, eps, transfer=transfer), f, cycles=6)
+    Hr = O.build_hierarchy(eps.reshape((n,) * d), d, L, transfer=transfer, check_definite=False)
+    _, b = AD.composite_system(G, eps, f)
+    ur, hr = O.solve(Hr, b, cycles=6)
+    assert max(abs(x - y) / y for x, y in zip(ha, hr)) <= 1e-11
+    assert np.abs(ua - ur).max() <= 1e-12 * np.abs(ur).max()

@@ -244,3 +244,44 @@ def test_unique_shared_entries_reports_the_largest_disagreement():
     ranks = np.array([0, 0, 1, 0, 2, 0])
     _, first, dis = transfer.unique_shared_entries(rows, cols, vals, 4, ranks)
     assert first[1] == 2.0 + 3e-7 and abs(dis - 3e-7 / (2.0 + 3e-7)) < 1e-15
+
+
+def _harmonic_weight(e, t):
+    """Weight of a coarse vertex at fine distance t (0..2) towards the three
+    fine cells e (in order away from it): the 1D solution of -(eps u')' = 0
+    with u = 1 at the vertex and 0 at the next one."""
+    return 1.0 - np.sum(1.0 / e[:t]) / np.sum(1.0 / e)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_boxmg_3d_layered_eps_is_harmonic_times_linear(axis):
+    """eps varying along one axis only: every BoxMG weight of the orthant
+    regions, interior points included, is the 1D harmonic weight along that
+    axis times the linear weights along the other two (the local problems
+    separate); a mixed-up axis or collapsed entry in the 3D patch systems
+    breaks it."""
+    Lf = 2
+    n = 3 ** Lf
+    rng = np.random.default_rng(8 + axis)
+    e1 = rng.uniform(0.1, 10.0, size=n)
+    shape = [1, 1, 1]
+    shape[2 - axis] = n                       # lattice axes are (z, y, x)
+    eps = np.broadcast_to(e1.reshape(shape), (n, n, n)).copy()
+    W = O.P_to_parent_weights(O.boxmg_P(O.geometric_stencil(eps, 3, Lf), 3, Lf), 3, Lf)
+    nc = n // 3
+    worst = 0.0
+    for V in itertools.product(range(1, nc), repeat=3):            # (Vx, Vy, Vz)
+        for s in itertools.product((1, -1), repeat=3):
+            for t in itertools.product(range(3), repeat=3):
+                f = [3 * V[a] + s[a] * t[a] for a in range(3)]
+                kap = [0 if f[a] // 3 == V[a] else 1 for a in range(3)]
+                want = 1.0
+                for a in range(3):
+                    if a == axis:
+                        cells = [3 * V[a] + (k if s[a] > 0 else -k - 1) for k in range(3)]
+                        want *= _harmonic_weight(e1[cells], t[a])
+                    else:
+                        want *= 1.0 - t[a] / 3.0
+                got = W[kap[0] + 2 * kap[1] + 4 * kap[2], f[2], f[1], f[0]]
+                worst = max(worst, abs(got - want))
+    assert worst < 1e-13

@@ -8,7 +8,7 @@ import pytest
 import oracle as O
 import workloads as W
 from gpu_util import require_gpu, announce, lattice_of_unknowns, unknowns_of_lattice, weights_to_csr
-from noise_floor import iterate_tolerance, operator_tolerance
+from noise_floor import iterate_tolerances, operator_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -143,6 +143,14 @@ def test_restrict_and_prolong(d, L):
     g.close()
 
 
+def _check_history(rr, hist, tols):
+    """The two relative residuals of a cycle differ by at most the iterate
+    bound of that cycle (triangle inequality on ||b - A u||)."""
+    gap = np.abs(np.asarray(rr, dtype=np.float64) - np.asarray(hist))
+    print("history gap per cycle", " ".join(f"{g:.1e}/{t:.1e}" for g, t in zip(gap, tols)))
+    assert len(rr) == len(hist) and np.all(gap <= tols)
+
+
 @pytest.mark.parametrize("d,L,transfer,store", [
     (2, 4, "geometric", "plain64"),   # small 2D Poisson shape of the first workload
     (2, 4, "boxmg", "hier64"),
@@ -167,11 +175,11 @@ def test_vcycle_iterates_match_oracle(d, L, transfer, store):
     b = O.rhs_from_f(p.f, d, L)
     uo, hist = O.solve(H, b, cycles=k)
     A = H.A[L]
-    tol, _ = iterate_tolerance(p, transfer, H, k) if transfer != "geometric" else (1e-12, None)
+    tols, _ = iterate_tolerances(p, transfer, H, k)
     diff = np.linalg.norm(A @ (u - uo)) / np.linalg.norm(b)
-    print(f"iterate measure {diff:.3e} (bound {tol:.3e})")
-    assert diff <= tol
-    np.testing.assert_allclose(rr, hist, rtol=1e-6, atol=1e-12)
+    print(f"iterate measure {diff:.3e} (bound {tols[-1]:.3e})")
+    assert diff <= tols[-1]
+    _check_history(rr, hist, tols)
 
 
 def test_checkerboard2d_level6_full_size_cycles_and_solve():
@@ -191,11 +199,11 @@ def test_checkerboard2d_level6_full_size_cycles_and_solve():
     b = O.rhs_from_f(p.f, 2, 6)
     uo, hist = O.solve(H, b, cycles=4)
     A = H.A[6]
-    tol, _ = iterate_tolerance(p, "boxmg", H, 4)
+    tols, _ = iterate_tolerances(p, "boxmg", H, 4)
     diff = np.linalg.norm(A @ (u4 - uo)) / np.linalg.norm(b)
-    print(f"iterate measure {diff:.3e} (bound {tol:.3e})")
-    assert diff <= tol
-    np.testing.assert_allclose(rr, hist, rtol=1e-6)
+    print(f"iterate measure {diff:.3e} (bound {tols[-1]:.3e})")
+    assert diff <= tols[-1]
+    _check_history(rr, hist, tols)
     rep, _ = g.solve(1e-8, 400)
     u = g.solution()
     assert rep["status"] == "QMG_OK"

@@ -26,6 +26,20 @@ def _grid(qmg, d, base, L, flags, transfer="galerkin", store="hier64", **kw):
                     refine=flags)
 
 
+def _contrast_tol(eps):
+    """Bound for the relative gaps of BoxMG cycles (iterates and residual
+    histories): rounding amplified by the coefficient contrast kappa, as for
+    the entries that neighbouring BoxMG patches share, with 4x more room for
+    the levels and cycles it passes through: 64 kappa 2^-52."""
+    return 64.0 * float(np.max(eps) / np.min(eps)) * 2.0 ** -52
+
+
+def _print_gaps(rr, hist_o, u, u_o):
+    rel = np.abs(np.asarray(rr) - np.asarray(hist_o)) / np.abs(np.asarray(hist_o))
+    print(f"history gap (relative, worst cycle) {rel.max():.2e}; "
+          f"iterate gap {np.abs(u - u_o).max() / np.abs(u_o).max():.2e}")
+
+
 @pytest.mark.parametrize("d,base,L", [(2, 2, 4), (2, 1, 5), (3, 1, 3)])
 def test_numbering_matches_oracle(d, base, L):
     qmg = require_gpu()
@@ -89,6 +103,7 @@ def test_fas_cycles_match_oracle(d, base, L, transfer, store):
     g.build()
     rr = g.vcycle(k)
     u = g.solution()
+    _print_gaps(rr, hist_o, u, u_o)
     np.testing.assert_allclose(rr, hist_o, rtol=1e-9, atol=1e-14)
     assert np.abs(u - u_o).max() <= 1e-11 * np.abs(u_o).max()
     g.close()
@@ -228,6 +243,7 @@ def test_balls_midsize_cycles_match_oracle():
     g.build()
     rr = g.vcycle(k)
     u = g.solution()
+    _print_gaps(rr, hist_o, u, u_o)
     np.testing.assert_allclose(rr, hist_o, rtol=1e-9)
     assert np.abs(u - u_o).max() <= 1e-11 * np.abs(u_o).max()
     g.close()
@@ -355,8 +371,10 @@ def test_boxmg_fas_cycles_match_oracle(d, base, L):
     g.build()
     rr = g.vcycle(k)
     u = g.solution()
-    np.testing.assert_allclose(rr, hist_o, rtol=1e-8)
-    assert np.abs(u - u_o).max() <= 1e-10 * np.abs(u_o).max()
+    _print_gaps(rr, hist_o, u, u_o)
+    tol = _contrast_tol(eps)
+    np.testing.assert_allclose(rr, hist_o, rtol=tol)
+    assert np.abs(u - u_o).max() <= tol * np.abs(u_o).max()
     g.close()
 
 
@@ -403,9 +421,11 @@ def test_boxmg_balls_midsize_cycles_match_oracle():
     g.set_coefficients(eps, f)
     assert g.build()["coarsest_level_used"] == 1
     rr = g.vcycle(k)
-    np.testing.assert_allclose(rr, hist_o, rtol=1e-8)
     u = g.solution()
-    assert np.abs(u - u_o).max() <= 1e-10 * np.abs(u_o).max()
+    _print_gaps(rr, hist_o, u, u_o)
+    tol = _contrast_tol(eps)
+    np.testing.assert_allclose(rr, hist_o, rtol=tol)
+    assert np.abs(u - u_o).max() <= tol * np.abs(u_o).max()
     g.close()
 
 
@@ -466,9 +486,11 @@ def test_band_midsize_boxmg_cycles_match_oracle():
     g.set_coefficients(eps, f)
     assert g.build()["coarsest_level_used"] == 1
     rr = g.vcycle(k)
-    np.testing.assert_allclose(rr, hist_o, rtol=1e-6)
     u = g.solution()
-    assert np.abs(u - u_o).max() <= 1e-6 * np.abs(u_o).max()
+    _print_gaps(rr, hist_o, u, u_o)
+    tol = _contrast_tol(eps)
+    np.testing.assert_allclose(rr, hist_o, rtol=tol)
+    assert np.abs(u - u_o).max() <= tol * np.abs(u_o).max()
     g.close()
 
 

@@ -306,11 +306,12 @@ __device__ inline bool orthant_refined(const int8_t* cref, const Lat& Lc, int Vx
 // threads may write the same zeros.
 template <int D>
 __device__ inline void zero_boundary_orthant(const Lat& Lf, double* __restrict__ Pw, int Vx, int Vy, int Vz,
-                                             int sx, int sy, int sz) {
+                                             int sx, int sy, int sz, int yx_only = -1) {
   const int zmax = (D == 3) ? 3 : 1;
+  const int yx0 = yx_only < 0 ? 0 : yx_only, yx1 = yx_only < 0 ? 3 : yx_only + 1;
   for (int yz = 0; yz < zmax; ++yz)
     for (int yy = 0; yy < 3; ++yy)
-      for (int yx = 0; yx < 3; ++yx) {
+      for (int yx = yx0; yx < yx1; ++yx) {
         const int fx = 3 * Vx + sx * yx, fy = 3 * Vy + sy * yy, fz = 3 * Vz + sz * yz;
         if (!interior(Lf, fx, fy, fz)) continue;
         const int zmask = (yx == 0 ? 1 : 0) | (yy == 0 ? 2 : 0) | ((D == 3 && yz == 0) ? 4 : 0);
@@ -342,15 +343,17 @@ __device__ inline void zero_boundary_orthant(const Lat& Lf, double* __restrict__
 // (at distance 3: weight zero), which no orthant computes; with them every
 // entry of every fine vertex of a refined coarse cell is written once.
 // dirty (nullable): the 64-slot blocks written are marked 1 there.
+// yx_only (>= 0): only the points at that distance along x.
 template <int D, class PV>
 __device__ inline void write_orthant(const Lat& Lf, const Lat& Lc, double* __restrict__ Pw,
                                      const int8_t* __restrict__ cref, int Vx, int Vy, int Vz, int sx, int sy,
-                                     int sz, PV&& value, int32_t* __restrict__ dirty = nullptr) {
+                                     int sz, PV&& value, int32_t* __restrict__ dirty = nullptr, int yx_only = -1) {
   const int zmax = (D == 3) ? 3 : 1;
   const int sneg = (sx < 0 ? 1 : 0) | (sy < 0 ? 2 : 0) | (sz < 0 ? 4 : 0);
+  const int yx0 = yx_only < 0 ? 0 : yx_only, yx1 = yx_only < 0 ? 3 : yx_only + 1;
   for (int yz = 0; yz < zmax; ++yz)
     for (int yy = 0; yy < 3; ++yy)
-      for (int yx = 0; yx < 3; ++yx) {
+      for (int yx = yx0; yx < yx1; ++yx) {
         const int zmask = (yx == 0 ? 1 : 0) | (yy == 0 ? 2 : 0) | ((D == 3 && yz == 0) ? 4 : 0);
         const int myrank = sneg & zmask;
         bool mine = true;
@@ -381,72 +384,70 @@ __device__ inline void write_orthant(const Lat& Lf, const Lat& Lc, double* __res
 // axis of its orthant
 __device__ inline double dlin_ref(int y) { return y == 0 ? 1.0 : (y == 1 ? 2.0 / 3.0 : 1.0 / 3.0); }
 
-// Constant-coefficient pass of the listed 3D cells with rediscretised rows:
-// kBoxCells cells per workgroup, thread (cell, corner).  A cell whose 125
-// fine cells and the layer around them carry one eps (every row of its eight
-// orthant systems reads only these) gets the d-linear weights of its
-// orthants, which BoxMG reproduces there (up to rounding); the others are
-// appended to dlist (count in *dcount) for the solve.  Kept apart from the
-// solver kernel, whose register use leaves two wavefronts per SIMD: this pass
-// is bound by memory latency and wants many more.
-constexpr int kBoxCells = 32;
-__global__ __launch_bounds__(8 * kBoxCells) void k_boxmg_uniform3(Lat Lf, Lat Lc, const double* __restrict__ eps,
-                                                                 double* __restrict__ Pw,
-                                                                 const int8_t* __restrict__ cref,
-                                                                 const int32_t* __restrict__ cells, int64_t ncells,
-                                                                 int32_t* __restrict__ dlist,
-                                                                 int32_t* __restrict__ dcount) {
+// Constant-coefficient pass of the listed 3D cells with rediscretised rows.
+// A cell whose 125 fine cells and the layer around them carry one eps (every
+// row of its eight orthant systems reads only these) gets the d-linear
+// weights of its orthants, which BoxMG reproduces there (up to rounding); the
+// others are appended to dlist (count in *dcount) for the solve.  Kept apart
+// from the solver kernel, whose register use leaves two wavefronts per SIMD:
+// this pass is bound by memory and wants many more.
+// Workgroup: kBoxCells cells, eight wavefronts.  The cells' eps are compared
+// by all threads against each cell's centre value (a flag per cell in LDS);
+// then wavefront w writes orthant w of every uniform cell, lane (cell, yx)
+// the nine points at distance yx along x, so that the lanes of one store
+// cover consecutive slots of a row when the listed cells are x-neighbours.
+constexpr int kBoxCells = 21;  // 3 * 21 = 63 lanes of a wavefront
+__global__ __launch_bounds__(512) void k_boxmg_uniform3(Lat Lf, Lat Lc, const double* __restrict__ eps,
+                                                        double* __restrict__ Pw, const int8_t* __restrict__ cref,
+                                                        const int32_t* __restrict__ cells, int64_t ncells,
+                                                        int32_t* __restrict__ dlist, int32_t* __restrict__ dcount) {
   __shared__ int cc[3 * kBoxCells];
-  const int lc = threadIdx.x >> 3, orth = threadIdx.x & 7;
-  const int64_t ci = (int64_t)blockIdx.x * kBoxCells + lc;
-  const bool active = ci < ncells;
+  __shared__ double cref_eps[kBoxCells];
+  __shared__ int nonuni[kBoxCells];
+  const int t = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * kBoxCells;
+  const int ncw = (int)min<int64_t>(kBoxCells, ncells - c0);  // cells of this workgroup (>= 1)
   const int n = Lc.n;
-  if (orth == 0) {
-    int x = -1000, y = -1000, z = -1000;
-    if (active) {
-      const int64_t c = cells[ci];
-      x = (int)(c % n);
-      y = (int)((c / n) % n);
-      z = (int)(c / ((int64_t)n * n));
-    }
-    cc[3 * lc] = x;
-    cc[3 * lc + 1] = y;
-    cc[3 * lc + 2] = z;
+  if (t < ncw) {
+    const int64_t c = cells[c0 + t];
+    const int x = (int)(c % n), y = (int)((c / n) % n), z = (int)(c / ((int64_t)n * n));
+    cc[3 * t] = x;
+    cc[3 * t + 1] = y;
+    cc[3 * t + 2] = z;
+    cref_eps[t] = eps[(3 * x + 1) + (int64_t)(3 * y + 1) * Lf.pitch + (int64_t)(3 * z + 1) * Lf.plane];
+    nonuni[t] = 0;
   }
   __syncthreads();
-  const int x0 = 3 * cc[3 * lc] - 1, y0 = 3 * cc[3 * lc + 1] - 1, z0 = 3 * cc[3 * lc + 2] - 1;
-  double lo = INFINITY, hi = -INFINITY;
-  for (int e = orth; e < 125; e += 8) {
-    const int x = x0 + e % 5, y = y0 + (e / 5) % 5, z = z0 + e / 25;
+  for (int k = t; k < ncw * 125; k += 512) {
+    const int lc = k / 125, e = k - 125 * lc;
+    const int x = 3 * cc[3 * lc] - 1 + e % 5, y = 3 * cc[3 * lc + 1] - 1 + (e / 5) % 5,
+              z = 3 * cc[3 * lc + 2] - 1 + e / 25;
     if (x < 0 || y < 0 || z < 0 || x >= Lf.n || y >= Lf.n || z >= Lf.n) continue;
-    const double v = eps[x + (int64_t)y * Lf.pitch + (int64_t)z * Lf.plane];
-    lo = fmin(lo, v);
-    hi = fmax(hi, v);
+    if (!(eps[x + (int64_t)y * Lf.pitch + (int64_t)z * Lf.plane] == cref_eps[lc])) nonuni[lc] = 1;
   }
-#pragma unroll
-  for (int o = 1; o < 8; o <<= 1) {
-    lo = fmin(lo, __shfl_xor(lo, o, 64));
-    hi = fmax(hi, __shfl_xor(hi, o, 64));
+  __syncthreads();
+  const int lane = t & 63, orth = t >> 6;
+  if (orth == 0) {
+    // the listed cells take consecutive places after one atomic increment
+    const bool listed = lane < ncw && nonuni[lane] != 0;
+    const uint64_t lead = __ballot(listed);
+    int base = 0;
+    if (lane == 0 && lead != 0) base = atomicAdd(dcount, (int)__popcll(lead));
+    base = __shfl(base, 0, 64);
+    if (listed) dlist[base + (int)__popcll(lead & ((1ull << lane) - 1ull))] = cells[c0 + lane];
   }
-  // the listed cells of the wavefront (its eight cells' first lanes) take
-  // consecutive places after one atomic increment
-  const bool listed = active && !(lo == hi);
-  const uint64_t lead = __ballot(listed && orth == 0);
-  const int lane = (int)(threadIdx.x & 63);
-  int base = 0;
-  if (lane == 0 && lead != 0) base = atomicAdd(dcount, (int)__popcll(lead));
-  base = __shfl(base, 0, 64);
-  if (listed && orth == 0) dlist[base + (int)__popcll(lead & ((1ull << lane) - 1ull))] = cells[ci];
-  if (!active || listed) return;
+  const int lc = lane / 3, yx = lane - 3 * lc;
+  if (lc >= ncw || nonuni[lc] != 0) return;
   const int Vx = cc[3 * lc] + (orth & 1), Vy = cc[3 * lc + 1] + ((orth >> 1) & 1),
             Vz = cc[3 * lc + 2] + ((orth >> 2) & 1);
   const int sx = (orth & 1) ? -1 : 1, sy = (orth & 2) ? -1 : 1, sz = (orth & 4) ? -1 : 1;
   if (!interior(Lc, Vx, Vy, Vz)) {
-    zero_boundary_orthant<3>(Lf, Pw, Vx, Vy, Vz, sx, sy, sz);
+    zero_boundary_orthant<3>(Lf, Pw, Vx, Vy, Vz, sx, sy, sz, yx);
     return;
   }
   write_orthant<3>(Lf, Lc, Pw, cref, Vx, Vy, Vz, sx, sy, sz,
-                   [](int yx, int yy, int yz) { return dlin_ref(yx) * dlin_ref(yy) * dlin_ref(yz); });
+                   [](int ax, int ay, int az) { return dlin_ref(ax) * dlin_ref(ay) * dlin_ref(az); }, nullptr,
+                   yx);
 }
 
 // pass (3D, listed cells): 0 solves every cell; 2 solves the *dcount cells
@@ -1497,7 +1498,7 @@ bool launch_boxmg(const Lat& Lf, const Lat& Lc, const double* Afine, const doubl
       int32_t* dcount = (int32_t*)scratch;
       int32_t* dlist = dcount + 16;
       hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, dcount, (int64_t)1, 0);
-      hipLaunchKernelGGL(k_boxmg_uniform3, dim3(blocks_for(n_cells, kBoxCells)), dim3(8 * kBoxCells), 0, s, Lf, Lc,
+      hipLaunchKernelGGL(k_boxmg_uniform3, dim3(blocks_for(n_cells, kBoxCells)), dim3(512), 0, s, Lf, Lc,
                          epsf, Pw, cref_coarse, cells, n_cells, dlist, dcount);
       hipLaunchKernelGGL((k_boxmg<3, 2>), g, dim3(64), 0, s, Lf, Lc, F, Pw, cref_coarse, (const int32_t*)dlist,
                          n_cells, (const int32_t*)dcount, 2, dirty);

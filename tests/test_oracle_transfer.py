@@ -285,3 +285,35 @@ def test_boxmg_3d_layered_eps_is_harmonic_times_linear(axis):
                 got = W[kap[0] + 2 * kap[1] + 4 * kap[2], f[2], f[1], f[0]]
                 worst = max(worst, abs(got - want))
     assert worst < 1e-13
+
+
+@pytest.mark.parametrize("seed,contrast", [(3, 10.0), (3, 1e4), (4, 1e4)])
+def test_boxmg_3d_eps_constant_along_z_is_2d_weight_times_linear(seed, contrast):
+    """eps varying along x and y only, two-valued at the given contrast: collapsing
+    the 3D Q1 stencil along z gives h times the 2D Q1 stencil of the
+    cross-section, and a Q1 z-stiffness annihilates linear functions, so every
+    3D BoxMG weight (line, face and interior points) is the 2D BoxMG weight of
+    the cross-section (itself pinned to the printed C(s) system and the 1D
+    harmonic formula) times the linear weight along z.  Both sides solve
+    their patch systems in floating point, so they agree to the rounding
+    amplified by the contrast kappa: held to 16 kappa 2^-52, the shared-entry
+    bound (measured at most 5 kappa 2^-52).  A dropped mass term or an axis
+    mix-up in the 3D face or volume systems moves weights by 1e-2 or more."""
+    Lf = 2
+    n = 3 ** Lf
+    rng = np.random.default_rng(seed)
+    e2 = np.where(rng.random((n, n)) < 0.5, 1.0, contrast)      # (y, x)
+    eps = np.broadcast_to(e2[None, :, :], (n, n, n)).copy()   # (z, y, x)
+    W3 = O.P_to_parent_weights(O.boxmg_P(O.geometric_stencil(eps, 3, Lf), 3, Lf), 3, Lf)
+    W2 = O.P_to_parent_weights(O.boxmg_P(O.geometric_stencil(e2, 2, Lf), 2, Lf), 2, Lf)
+    nc = n // 3
+    worst = 0.0
+    for V in itertools.product(range(1, nc), repeat=3):            # (Vx, Vy, Vz)
+        for s in itertools.product((1, -1), repeat=3):
+            for t in itertools.product(range(3), repeat=3):
+                f = [3 * V[a] + s[a] * t[a] for a in range(3)]
+                kap = [0 if f[a] // 3 == V[a] else 1 for a in range(3)]
+                want = W2[kap[0] + 2 * kap[1], f[1], f[0]] * (1.0 - t[2] / 3.0)
+                got = W3[kap[0] + 2 * kap[1] + 4 * kap[2], f[2], f[1], f[0]]
+                worst = max(worst, abs(got - want))
+    assert worst < 16 * contrast * 2.0 ** -52, worst / (contrast * 2.0 ** -52)

@@ -24,7 +24,11 @@ jumping-coefficient workload (729^2 cells, solves to 1e-8) with its store
 variants, a roofline sweep on regular grids larger than the Infinity Cache,
 the other single-grid workloads, the served request stream, and the CPU
 baselines: the oracle (test infrastructure) timed on a bounded sample of the
-headline workload, on one thread and on every host core.
+headline workload, on one thread and on every host core.  In the same leg,
+after every timed region, the oracle checks the other results: it recomputes
+the relative residual of every regular-grid solution (sweep, store variants,
+each served request), the four-ball workload's composite rows at sampled
+unknowns, and the checkerboard solutions' distance to its own solve.
 """
 from __future__ import annotations
 
@@ -208,6 +212,7 @@ def other_workloads(qmg, n):
     epsa = torch.from_numpy(epsa).cuda()
     fa = torch.from_numpy(fa).cuda()
     r = time_solves(g, epsa, fa, 1e-8, n, warmup=1)
+    r["_check"] = (P, xyz, lev, g.solution(), np.linalg.norm(fa.cpu().numpy() * (3.0 ** -lev.astype(float)) ** 3))
     out["adaptive3d_balls"] = dict(r, unknowns=g.n_unknowns, leaf_cells=g.n_cells,
                                    build_ms=time_build(g, epsa, fa, 5),
                                    workload="3D adaptive: level 3 everywhere, level 5 within 0.2 of 4 "
@@ -219,16 +224,21 @@ def other_workloads(qmg, n):
     return out
 
 
-def serve_stream(qmg, n_requests=256, seed=0, slots=16, budget=8 << 30):
+def serve_stream(qmg, n_requests=256, seed=0, slots=16, budget=8 << 30, oracle_check=False):
     """Served stream of mixed 2D/3D checkerboard solves (FP16 deltas, FP32
     cycles under FP64 refinement to 1e-8): first closed loop (all requests at
-    t = 0) for the saturated throughput, then Poisson arrivals at 0.9 of it."""
+    t = 0) for the saturated throughput, then Poisson arrivals at 0.9 of it.
+    With ``oracle_check``, after the timed runs the oracle recomputes every
+    served solution's relative residual, and the Poisson run's solutions are
+    compared bit for bit with the closed loop's."""
     import workloads as W
     mixed = qmg.make_opts("boxmg", "hier16")
     stream = W.request_stream(seed=seed, n_requests=n_requests)
     out = {"requests": n_requests, "store": "hier16", "slots": slots, "hbm_budget_bytes": budget}
 
-    def run(arrivals, opts):
+    sols = {}
+
+    def run(arrivals, opts, key):
         srv = qmg.Server(budget, max_slots=slots)
         t0 = time.perf_counter()
         tickets = []
@@ -240,31 +250,67 @@ def serve_stream(qmg, n_requests=256, seed=0, slots=16, budget=8 << 30):
         srv.drain()
         wall = time.perf_counter() - t0
         lat, upd, bad = [], 0, 0
+        us = []
         for t in tickets:
             done, status, u, rep, l = srv.poll(t)
             bad += status != "QMG_OK"
+            us.append(u)
             lat.append(l)
             upd += rep["vertex_updates"]
         st = srv.stats()
         srv.close()
+        if oracle_check:
+            sols[key] = us
         lat = np.array(lat)
         return {"wall_s": wall, "solves_per_s": len(tickets) / wall, "vertex_updates_per_s": upd / wall,
                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
                 "failed": int(bad), "hbm_peak_bytes": int(st["hbm_peak"])}
 
-    closed = run([0.0] * n_requests, mixed)
+    closed = run([0.0] * n_requests, mixed, "mixed")
     rate = 0.9 * closed["solves_per_s"]
     rng = np.random.default_rng(seed + 1)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
-    opened = run(list(arrivals), mixed)
+    opened = run(list(arrivals), mixed, "poisson")
     out["closed_loop"] = closed
     out["poisson_0.9"] = dict(opened, rate_per_s=rate)
     # the same stream served in plain FP64 (full stencils, FP64 cycles) to the
     # same tolerance, for the mixed-precision ratio
-    plain = run([0.0] * n_requests, qmg.make_opts("boxmg", "plain64"))
+    plain = run([0.0] * n_requests, qmg.make_opts("boxmg", "plain64"), "plain64")
     out["plain64_closed_loop"] = plain
     out["mixed_over_plain64"] = closed["solves_per_s"] / plain["solves_per_s"]
+    if oracle_check:
+        worst = {"mixed": 0.0, "plain64": 0.0}
+        for k, req in enumerate(stream):
+            S = None
+            for key in worst:
+                rr, S = oracle_relres(req.problem, sols[key][k], S)
+                worst[key] = max(worst[key], rr)
+        out["closed_loop"]["max_relres_by_oracle"] = worst["mixed"]
+        out["plain64_closed_loop"]["max_relres_by_oracle"] = worst["plain64"]
+        out["poisson_0.9"]["bitwise_equal_to_closed_loop"] = all(
+            np.array_equal(a, b) for a, b in zip(sols["mixed"], sols["poisson"]))
     return out
+
+
+def oracle_relres(problem, u, S=None):
+    """||b - A u|| / ||b|| of a regular-grid solution, recomputed in FP64 by
+    the oracle from the problem's own eps and f (its rediscretised finest
+    stencils applied on the lattice).  Returns (relres, S) so that several
+    solutions of one problem share the stencil array."""
+    import oracle as O
+    from oracle.fem import offsets, shifted
+    d, L = problem.dim, problem.level
+    n = 3 ** L
+    if S is None:
+        S = O.geometric_stencil(problem.eps, d, L)
+    inner = (slice(1, n),) * d
+    U = np.zeros((n + 1,) * d)
+    U[inner] = np.asarray(u, dtype=np.float64).reshape((n - 1,) * d)
+    AU = np.zeros_like(U)
+    for k, o in enumerate(offsets(d)):
+        AU += S[k] * shifted(U, o)
+    b = O.rhs_from_f(problem.f, d, L)
+    return float(np.linalg.norm(b - AU[inner].ravel()) / np.linalg.norm(b)), S
 
 
 def cpu_baseline(problem):
@@ -481,17 +527,16 @@ def band_step_runs(qmg, P, store, steps, warmup, inputs=None, profile=0, cycles=
     return g, inputs, out
 
 
-def band_residual_rows(g, inputs, P, n_samples=160, seed=11):
-    """Composite residual rows (FP64 iterates) of the library against the
-    oracle's rows assembled one by one at sampled unknowns from the same
-    iterate; rows needing a hanging value (a BoxMG interpolant) are left to
-    the mid-size parity tests."""
+def sampled_rows(P, xyz, lev, u, n_samples, seed):
+    """The oracle's composite residual rows at sampled unknowns of an adaptive
+    grid, assembled one by one from its spacetree decided cell by cell and
+    the library's iterate u (at the library's unknown positions xyz, lev);
+    rows that need a hanging value (a BoxMG interpolant) come back NaN.
+    Returns (sample indices, rows, row scales sum |K||u|)."""
     import oracle.adaptive as AD
-    u = g.solution()
-    r = g.residual()
-    lev = inputs.lev.astype(np.int64)
+    lev = np.asarray(lev, dtype=np.int64)
     n = 3 ** lev
-    ijk = np.rint(inputs.xyz * n[:, None]).astype(np.int64)
+    ijk = np.rint(xyz * n[:, None]).astype(np.int64)
     key = (lev << 40) | (ijk[:, 0] + 1024 * (ijk[:, 1] + 1024 * ijk[:, 2]))
     order = np.argsort(key)
     skey = key[order]
@@ -508,12 +553,33 @@ def band_residual_rows(g, inputs, P, n_samples=160, seed=11):
     T = AD.LocalSpacetree(3, P.base, P.level, P.mark)
     samples = [(int(lev[k]), tuple(int(x) for x in ijk[k])) for k in pick]
     rows, scale = AD.local_composite_rows(T, P.eps_at, P.f_at, u_of, samples)
+    return pick, rows, scale
+
+
+def band_residual_rows(g, inputs, P, n_samples=160, seed=11):
+    """Composite residual rows (FP64 iterates) of the library against the
+    oracle's rows assembled one by one at sampled unknowns from the same
+    iterate; rows needing a hanging value (a BoxMG interpolant) are left to
+    the mid-size parity tests."""
+    r = g.residual()
+    pick, rows, scale = sampled_rows(P, inputs.xyz, inputs.lev, g.solution(), n_samples, seed)
     ok = ~np.isnan(rows)
     diff = np.abs(rows[ok] - r[pick][ok]) / np.maximum(scale[ok], 1e-300)
     return {"sampled": int(n_samples), "checked": int(ok.sum()),
             "max_rel_diff": float(diff.max()) if ok.any() else None,
             "note": "|r_gpu - r_oracle| / sum |K||u| per row after the timed steps; "
                     "rows touching a hanging vertex are skipped"}
+
+
+def balls_rows_check(P, xyz, lev, u, norm_b, n_samples=300, seed=21):
+    """The four-ball solution's composite residual at sampled unknowns,
+    recomputed by the oracle row by row, relative to ||b||."""
+    _, rows, _ = sampled_rows(P, xyz, lev, u, n_samples, seed)
+    ok = ~np.isnan(rows)
+    return {"sampled": int(n_samples), "checked": int(ok.sum()),
+            "max_abs_row_over_norm_b": float(np.abs(rows[ok]).max() / norm_b) if ok.any() else None,
+            "note": "max |b - A u| over the checked rows / ||b||, rows touching a hanging vertex "
+                    "skipped; the solve stops at ||b - A u|| <= 1e-8 ||b||"}
 
 
 CPU_SAMPLE_REPS = 6
@@ -626,23 +692,27 @@ def checkerboard_block(qmg, W, args):
         variants[v] = {"solves_per_s": len(r["lat"]) / r["elapsed"],
                        "vertex_updates_per_s": r["updates"] / r["elapsed"],
                        "cycles_per_solve": r["reps"][-1]["cycles"], "relres": r["reps"][-1]["relres"],
-                       "p50_ms": float(np.percentile(r["lat"], 50) * 1e3)}
+                       "p50_ms": float(np.percentile(r["lat"], 50) * 1e3), "_u": r["u"]}
     if args.variants:
         r = run_variant(qmg, p, "boxmg", store, max(3, args.cb_steps // 2), 1, smoother="block", bj_sweeps=3)
         variants[f"{store}_block_jacobi3"] = {
             "solves_per_s": len(r["lat"]) / r["elapsed"],
             "vertex_updates_per_s": r["updates"] / r["elapsed"],
             "cycles_per_solve": r["reps"][-1]["cycles"], "relres": r["reps"][-1]["relres"],
-            "p50_ms": float(np.percentile(r["lat"], 50) * 1e3)}
+            "p50_ms": float(np.percentile(r["lat"], 50) * 1e3), "_u": r["u"]}
     out["variants"] = variants
     return out, res["u"], p
 
 
-def roofline_sweep(qmg, W, spec, profile_every, ceiling):
+def roofline_sweep(qmg, W, spec, profile_every, ceiling, oracle_check=False):
+    """Regular jumping-coefficient grids, one solve per store, each timed on
+    its finest-level kernel; with ``oracle_check`` the oracle recomputes each
+    solution's relative residual after the timing."""
     sweep = []
     for item in [s for s in spec.split(",") if s]:
         dim, level = (int(x) for x in item.split(":"))
         q = W.random_checkerboard(dim, level, 0, name=f"jump{dim}d-L{level}")
+        S = None
         for store in ("hier64", "plain64", "bf16"):
             try:
                 r = run_variant(qmg, q, "boxmg", store, 2, 1, profile=profile_every or 8)
@@ -667,10 +737,13 @@ def roofline_sweep(qmg, W, spec, profile_every, ceiling):
                           "frac_of_copy": gbs / ceiling if gbs and ceiling else None,
                           "effective_gbs": op_b / avg / 1e9 if avg > 0 else None,
                           "traffic": measured_traffic(f"{kern}:jump{dim}d_L{level}:{store}")})
+            if oracle_check:
+                sweep[-1]["relres_by_oracle"], S = oracle_relres(q, r["u"], S)
+            del r
             print(f"sweep {dim}D L{level} {store}: {sweep[-1]['solves_per_s']:.2f} solves/s, "
                   f"{sweep[-1]['avg_launch_us']:.1f} us/launch, {gbs or 0:.0f} GB/s", file=sys.stderr,
                   flush=True)
-        del q
+        del q, S
     return sweep
 
 
@@ -806,13 +879,14 @@ def main():
     ucb = pcb = None
     if not args.no_checkerboard:
         out["checkerboard2d"], ucb, pcb = checkerboard_block(qmg, W, args)
-    sweep = roofline_sweep(qmg, W, args.sweep, args.profile_every, ceiling)
+    sweep = roofline_sweep(qmg, W, args.sweep, args.profile_every, ceiling,
+                           oracle_check=not args.no_cpu_baseline)
     if sweep:
         out["roofline_sweep"] = sweep
     if args.others:
         out["other_workloads"] = other_workloads(qmg, args.others)
     if not args.no_serving:
-        out["serving"] = serve_stream(qmg)
+        out["serving"] = serve_stream(qmg, oracle_check=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         one, allc = cpu_baselines()
         out["cpu_baseline"] = one
@@ -823,12 +897,24 @@ def main():
             out["checkerboard2d"]["cpu_baseline"] = cb
             out["checkerboard2d"]["u_rel_diff_vs_oracle"] = float(np.linalg.norm(ucb - ucpu) /
                                                                    np.linalg.norm(ucpu))
+            S = None
+            for v in out["checkerboard2d"]["variants"].values():
+                uv = v.pop("_u")
+                v["relres_by_oracle"], S = oracle_relres(pcb, uv, S)
+                v["u_rel_diff_vs_oracle"] = float(np.linalg.norm(uv - ucpu) / np.linalg.norm(ucpu))
+    if "checkerboard2d" in out:
+        for v in out["checkerboard2d"]["variants"].values():
+            v.pop("_u", None)
     if args.others:
         ow = out["other_workloads"]["poisson2d_L4"]
         u1 = ow.pop("u")
         if not args.no_cpu_baseline:
             ucpu = cpu_solution_poisson()
             ow["u_rel_diff_vs_oracle"] = float(np.linalg.norm(u1 - ucpu) / np.linalg.norm(ucpu))
+        ob = out["other_workloads"]["adaptive3d_balls"]
+        Pb, xyz, lev, ub, nb = ob.pop("_check")
+        if not args.no_cpu_baseline:
+            ob["rows_by_oracle"] = balls_rows_check(Pb, xyz, lev, ub, nb)
     print(json.dumps(out))
 
 

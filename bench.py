@@ -292,6 +292,11 @@ def serve_stream(qmg, n_requests=256, seed=0, slots=16, budget=8 << 30, oracle_c
     return out
 
 
+# the oracle's stencil array takes 3^d doubles per lattice vertex on the host
+# (3.1 GB at 2D level 8 or 3D level 5, about 30 GB and 84 GB one level up)
+ORACLE_RELRES_MAX_UNKNOWNS = 50_000_000
+
+
 def oracle_relres(problem, u, S=None):
     """||b - A u|| / ||b|| of a regular-grid solution, recomputed in FP64 by
     the oracle from the problem's own eps and f (its rediscretised finest
@@ -737,8 +742,10 @@ def roofline_sweep(qmg, W, spec, profile_every, ceiling, oracle_check=False):
                           "frac_of_copy": gbs / ceiling if gbs and ceiling else None,
                           "effective_gbs": op_b / avg / 1e9 if avg > 0 else None,
                           "traffic": measured_traffic(f"{kern}:jump{dim}d_L{level}:{store}")})
-            if oracle_check:
+            if oracle_check and q.n_unknowns <= ORACLE_RELRES_MAX_UNKNOWNS:
                 sweep[-1]["relres_by_oracle"], S = oracle_relres(q, r["u"], S)
+            elif oracle_check:
+                sweep[-1]["relres_by_oracle"] = None     # host stencil array too large
             del r
             print(f"sweep {dim}D L{level} {store}: {sweep[-1]['solves_per_s']:.2f} solves/s, "
                   f"{sweep[-1]['avg_launch_us']:.1f} us/launch, {gbs or 0:.0f} GB/s", file=sys.stderr,

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from boxmg_equations import worst_defining_equation
 from oracle import fem, transfer
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -319,44 +320,6 @@ def test_boxmg_3d_eps_constant_along_z_is_2d_weight_times_linear(seed, contrast)
     assert worst < 16 * contrast * 2.0 ** -52, worst / (contrast * 2.0 ** -52)
 
 
-def _worst_defining_equation(S, P, d, Lf, columns):
-    """The largest relative residual of BoxMG's defining equations (Sect. 4.4)
-    over the given coarse hat columns w = P e_V on the fine lattice: at a fine
-    vertex that lies on the coarse planes of the axes in a set K (but not on
-    all of them), the fine stencil collapsed along K (offsets along K set to
-    zero, entries summed) annihilates w; interior points (K empty) take the
-    stencil whole.  Each residual is relative to the sum of its terms'
-    magnitudes."""
-    from oracle.fem import shifted
-    nf = 3 ** Lf
-    inner = (slice(1, nf),) * d
-    ax = np.meshgrid(*[np.arange(nf + 1)] * d, indexing="ij")        # lattice axes (z, y, x)
-    onplane = [ax[d - 1 - i] % 3 == 0 for i in range(d)]             # per axis, x first
-    interior = np.zeros((nf + 1,) * d, dtype=bool)
-    interior[inner] = True
-    Pc = P.tocsc()
-    worst = 0.0
-    for j in columns:
-        w = np.zeros((nf + 1,) * d)
-        w[inner] = Pc[:, j].toarray().reshape((nf - 1,) * d)
-        for K in itertools.product((False, True), repeat=d):
-            if all(K):
-                continue                                             # c-points: unit rows
-            sel = interior.copy()
-            for i in range(d):
-                sel &= onplane[i] if K[i] else ~onplane[i]
-            eq = np.zeros_like(w)
-            mag = np.zeros_like(w)
-            for k, o in enumerate(fem.offsets(d)):
-                t = S[k] * shifted(w, tuple(0 if K[i] else o[i] for i in range(d)))
-                eq += t
-                mag += np.abs(t)
-            sel &= mag > 0
-            if sel.any():
-                worst = max(worst, float((np.abs(eq[sel]) / mag[sel]).max()))
-    return worst
-
-
 @pytest.mark.parametrize("d,Lf,contrast,field", [(2, 3, 1e2, "smooth"), (2, 3, 1e4, "checker"),
                                                  (3, 2, 1e4, "smooth"), (3, 2, 1e4, "checker"),
                                                  (3, 3, 1e4, "checker")])
@@ -379,5 +342,5 @@ def test_boxmg_columns_satisfy_the_collapsed_fine_equations(d, Lf, contrast, fie
     ncol = P.shape[1]
     cols = range(ncol) if ncol <= 64 else np.random.default_rng(5).choice(ncol, 24, replace=False)
     bound = 16 * contrast * 2.0 ** -52
-    assert _worst_defining_equation(S, P, d, Lf, cols) < bound
-    assert _worst_defining_equation(S, O.dlinear_P(d, Lf), d, Lf, cols) > 0.1
+    assert worst_defining_equation(S, P, d, Lf, cols) < bound
+    assert worst_defining_equation(S, O.dlinear_P(d, Lf), d, Lf, cols) > 0.1

@@ -389,3 +389,30 @@ def test_adaptive_boxmg_columns_satisfy_the_collapsed_fine_equations(d, base, L,
         assert worst_defining_equation(S, H.P[l], d, l, cols, region) < 16 * contrast * 2.0 ** -52
         assert worst_defining_equation(S, O.dlinear_P(d, l), d, l, cols, region) > 0.1
 
+
+
+def _asymptotic_rate(hist):
+    return (hist[-1] / hist[-5]) ** 0.25
+
+
+@pytest.mark.parametrize("d,base,L", [(2, 2, 4), (3, 1, 3)])
+def test_adaptive_fas_converges_at_the_regular_rate(d, base, L):
+    """With constant eps and d-linear transfers, the FAS cycle on a spacetree
+    refined around two balls (hanging vertices present) contracts the
+    composite residual per cycle at the rate of the regular V(2,2) cycle on
+    the finest level, within 15 % (measured 1.07x in 2D, 0.96x in 3D).
+    Planted on the CPU: a halved coarse correction, a missing FAS coarse term
+    A u, hanging values left stale after the correction (2D) or one
+    pre-smoothing step instead of two each push the rate past it."""
+    P = W.adaptive_balls(dim=d, base=base, level=L, n_balls=2, radius=0.25, seed=0,
+                         contrast_field=False)
+    G = AD.AdaptiveGrid(d, base, L, P.flags)
+    assert (G.vtype[L] == AD.HANGING).any()
+    H = AD.build_adaptive(G, np.ones(len(G.leaf_cells())), transfer="galerkin")
+    n = sum(int((G.vtype[l] == AD.LEAF).sum()) for l in range(base, L + 1))
+    f = np.random.default_rng(0).uniform(-1.0, 1.0, n)
+    _, hist_ad = AD.solve_adaptive(H, f, cycles=12)
+    p = W.random_checkerboard(d, L, 0, values=(1.0, 1.0))
+    Hr = O.build_hierarchy(p.eps, d, L, transfer="galerkin")
+    _, hist_reg = O.solve(Hr, O.rhs_from_f(p.f, d, L), cycles=12)
+    assert _asymptotic_rate(hist_ad) <= 1.15 * _asymptotic_rate(hist_reg)

@@ -395,11 +395,13 @@ def _asymptotic_rate(hist):
     return (hist[-1] / hist[-5]) ** 0.25
 
 
+@pytest.mark.parametrize("transfer", ["galerkin", "boxmg"])
 @pytest.mark.parametrize("d,base,L", [(2, 2, 4), (3, 1, 3)])
-def test_adaptive_fas_converges_at_the_regular_rate(d, base, L):
-    """With constant eps and d-linear transfers, the FAS cycle on a spacetree
-    refined around two balls (hanging vertices present) contracts the
-    composite residual per cycle at the rate of the regular V(2,2) cycle on
+def test_adaptive_fas_converges_at_the_regular_rate(d, base, L, transfer):
+    """With constant eps and d-linear transfers (or BoxMG, whose weights are
+    d-linear for constant eps), the FAS cycle on a spacetree refined around
+    two balls (hanging vertices present) contracts the composite residual
+    per cycle at the rate of the regular V(2,2) cycle on
     the finest level, within 15 % (measured 1.07x in 2D, 0.96x in 3D).
     Planted on the CPU: a halved coarse correction, a missing FAS coarse term
     A u, hanging values left stale after the correction (2D) or one
@@ -408,7 +410,7 @@ def test_adaptive_fas_converges_at_the_regular_rate(d, base, L):
                          contrast_field=False)
     G = AD.AdaptiveGrid(d, base, L, P.flags)
     assert (G.vtype[L] == AD.HANGING).any()
-    H = AD.build_adaptive(G, np.ones(len(G.leaf_cells())), transfer="galerkin")
+    H = AD.build_adaptive(G, np.ones(len(G.leaf_cells())), transfer=transfer)
     n = sum(int((G.vtype[l] == AD.LEAF).sum()) for l in range(base, L + 1))
     f = np.random.default_rng(0).uniform(-1.0, 1.0, n)
     _, hist_ad = AD.solve_adaptive(H, f, cycles=12)
